@@ -1,0 +1,241 @@
+/*
+ * fepic.h - C ABI of the MI355X (gfx950) charge-conserving finite-element PIC hot path.
+ *
+ * Method: O'Connor, Crawford, Ramachandran, Luginsland, Shanker, "Time Integrator
+ * Agnostic Charge Conserving Finite Element PIC" (arXiv:2102.06248).  Each step:
+ *   gather E from edge (Whitney-1) and B from face (Whitney-2) unknowns at every
+ *   particle (Sec. II-A), push with a relativistic Boris step (Sec. III-B), follow the
+ *   straight path through the tetrahedra splitting it at every face (Sec. III-C, Alg. 1),
+ *   integrate the Whitney-1 forms along each piece to get the time-integrated current G
+ *   (Sec. III-A, eqs. (gaussredo)-(G)), then advance the edge field with the Newmark-beta
+ *   wave-equation update whose source is the second difference of G (Sec. II-B, III-A),
+ *   solved by Jacobi-preconditioned CG, and the face flux with Faraday's law.
+ *
+ * Conventions for every entry point:
+ *   - Return value: FEPIC_OK (0) or a negative FEPIC_E_* code.  fepic_error_string(code)
+ *     names the code; fepic_last_error(ctx) gives the message of the last failure.
+ *   - Ownership: the caller owns every buffer it passes; the library copies what it needs
+ *     during the call and keeps no caller pointer.  The context owns all device memory it
+ *     allocates (hipMalloc) and frees it in fepic_destroy.  Pointer arguments are host
+ *     pointers unless the name says device.
+ *   - Threading: one context per host thread; calls on one context must not overlap.
+ *   - Units: SI.  Edge unknowns e_i are volts (line integrals of E), face unknowns b_f are
+ *     webers (fluxes of B), currents are time-integrated (coulombs).
+ *   - Numbering (canonical, independent of the input order of vertices): each tet's node
+ *     ids are sorted ascending (local vertex k = k-th smallest); edges are the unique
+ *     sorted node pairs in lexicographic order, oriented low -> high id; faces are the
+ *     unique sorted node triples in lexicographic order, oriented by the right-hand normal
+ *     (r_j - r_i) x (r_k - r_i), i < j < k; local face k of a tet is opposite vertex k.
+ *   - Every boundary face is a perfect electric conductor (eq. (dirichlet) with
+ *     Psi_D = 0): boundary edge unknowns are held at zero and particles reaching the wall
+ *     are absorbed after depositing their current up to it.
+ */
+#ifndef FEPIC_H
+#define FEPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FEPIC_ABI_VERSION 1
+
+enum {
+    FEPIC_OK = 0,
+    FEPIC_E_ARG = -1,               /* null pointer, bad size or enum value            */
+    FEPIC_E_MESH = -2,              /* degenerate tet, non-conforming face, bad id      */
+    FEPIC_E_STATE = -3,             /* call order (e.g. step before mesh upload)        */
+    FEPIC_E_OOM = -4,               /* device or host allocation failed                 */
+    FEPIC_E_HIP = -5,               /* HIP runtime error (message in fepic_last_error)  */
+    FEPIC_E_CG_NOT_CONVERGED = -6,  /* stats filled, nothing committed                  */
+    FEPIC_E_CROSSING_CAP = -7,      /* a path crossed more faces than allowed; nothing  */
+                                    /* committed                                        */
+    FEPIC_E_IO = -8,                /* checkpoint file error                            */
+    FEPIC_E_NO_DEVICE = -9          /* the call needs a device context                  */
+};
+
+enum { FEPIC_FP32_PUSH_FP64_ACC = 0, FEPIC_ALL_FP64 = 1 };
+
+/* Warm start of the Newmark solve: previous field, linear or quadratic extrapolation in
+ * time, or the per-edge learned predictor (fepic_ws_*). */
+enum { FEPIC_WS_PREV = 0, FEPIC_WS_EXTRAP1 = 1, FEPIC_WS_EXTRAP2 = 2, FEPIC_WS_MLP = 3 };
+
+typedef struct fepic_ctx fepic_ctx;
+
+typedef struct {
+    int device;        /* HIP device ordinal; -1 = host-only context: mesh topology and
+                          matrix assembly only (no device calls), for inspection/tests   */
+    int precision;     /* FEPIC_FP32_PUSH_FP64_ACC: gather/push/path split in FP32 with
+                          per-tet barycentric positions, current and charge in FP64;
+                          FEPIC_ALL_FP64: everything FP64                               */
+    double cg_tol;     /* stop when ||b - A x||_2 <= cg_tol ||b||_2 (default 1e-10)      */
+    int cg_max_iters;  /* default 10000                                                  */
+    int cg_check_every;/* iterations between convergence reads on the host (default 8)   */
+    int sort_period;   /* re-bin particles by tet every this many steps (default 1)      */
+    int crossing_cap;  /* faces one path may cross in one step (default 64)              */
+    int warm_start;    /* FEPIC_WS_* (default FEPIC_WS_PREV)                             */
+    int diagnostics;   /* 1: charge continuity, Gauss and div b residuals every step      */
+    int timing;        /* 1: per-phase HIP-event times in fepic_step_stats                */
+} fepic_options;
+
+typedef struct {
+    int64_t step;                 /* steps committed so far                               */
+    double t;                     /* simulated time after the step                        */
+    int cg_iters;                 /* PCG iterations of this step's Newmark solve          */
+    double cg_rel_resid;          /* true ||b - A e^{n+1}||_2 / ||b||_2 at exit           */
+    double cg_rel_resid0;         /* ||b - A x0||_2 / ||b||_2 (quality of the warm start) */
+    double cont_resid_rel;        /* max |rho^{n+1} - rho^n - D^T dG| / scale, interior   */
+    double gauss_resid_rel;       /* max |-D^T M e - rho| / scale, interior nodes         */
+    double gauss_drift_check_rel; /* max |Delta^2 r_Gauss - D^T r_cg| / scale (Sec. III-A */
+                                  /* solver-tolerance caveat); -1 until 3 levels exist    */
+    double divb_max;              /* max over tets of |sum of signed face fluxes|         */
+    double field_energy;          /* 1/2 e^T M e (electric part), joules                  */
+    int64_t n_particles;          /* live particles after the step (all species)          */
+    int64_t n_absorbed;           /* absorbed at the wall this step                       */
+    int64_t n_crossings;          /* face crossings this step                             */
+    int max_crossings;            /* most crossings of one path this step                 */
+    int n_cap_exceeded;           /* paths stopped by the crossing cap                    */
+    float ms_sort, ms_stage, ms_particles, ms_rhs, ms_warm, ms_cg, ms_faraday, ms_diag;
+} fepic_step_stats;
+
+/* ---------------------------------------------------------------- lifecycle */
+int fepic_abi_version(void);
+void fepic_default_options(fepic_options* opts);
+const char* fepic_error_string(int code);
+const char* fepic_last_error(const fepic_ctx* ctx);
+/* Creates a context on opts->device (NULL opts = defaults).  *out receives it. */
+int fepic_create(const fepic_options* opts, fepic_ctx** out);
+int fepic_destroy(fepic_ctx* ctx);
+/* Runs all later device work of this context on the given hipStream_t (NULL = the
+ * context's own stream).  The caller keeps the stream alive while the context uses it. */
+int fepic_set_stream(fepic_ctx* ctx, void* hip_stream);
+
+/* ---------------------------------------------------------------- mesh (Sec. II-A)
+ * xyz: [n_nodes][3] float64 node coordinates.  tets: [n_tets][4] int32 0-based node ids,
+ * any vertex order.  Builds the canonical edges/faces, incidence, neighbours, per-tet
+ * barycentric gradients, the edge mass matrix M = [*eps0] and the curl-curl matrix
+ * S = [curl]^T [*mu0^-1] [curl] (Sec. II-A) over interior edges, and uploads them.
+ * Errors: FEPIC_E_MESH for a degenerate tet, an out-of-range id or a face shared by
+ * more than two tets.  May be called once per context. */
+int fepic_upload_mesh(fepic_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets);
+/* Entity counts after upload; any output pointer may be NULL.  euler = V - E + F - T. */
+int fepic_get_topology_sizes(fepic_ctx* ctx, int64_t* n_edges, int64_t* n_faces, int64_t* n_int_edges,
+                             int64_t* n_int_nodes, int64_t* euler);
+/* Canonical topology; any output may be NULL.  tets_sorted [n_tets][4], edges
+ * [n_edges][2], faces [n_faces][3], tet_edges [n_tets][6] (local edge order (0,1),(0,2),
+ * (0,3),(1,2),(1,3),(2,3)), tet_faces [n_tets][4], nbr [n_tets][4] (tet across local
+ * face k, -1 on the wall). */
+int fepic_get_topology(fepic_ctx* ctx, int32_t* tets_sorted, int32_t* edges, int32_t* faces, int32_t* tet_edges,
+                       int32_t* tet_faces, int32_t* nbr);
+/* Assembled matrix which = 0 (M) or 1 (S) restricted to interior edges, as COO over
+ * global edge ids.  With row == NULL only *nnz is returned.  cap = capacity of the arrays. */
+int fepic_get_matrix(fepic_ctx* ctx, int which, int64_t cap, int64_t* nnz, int64_t* row, int64_t* col, double* val);
+
+/* ---------------------------------------------------------------- fields
+ * e, e_prev: [n_edges] edge unknowns at t_n and t_{n-1} (boundary entries ignored, held
+ * at 0); b: [n_faces] face fluxes at t_n.  Any may be NULL (left unchanged). */
+int fepic_set_fields(fepic_ctx* ctx, const double* e, const double* e_prev, const double* b);
+/* b_f = B0 . (area vector of f): the exact Whitney-2 interpolant of a uniform field. */
+int fepic_set_uniform_B(fepic_ctx* ctx, const double B0[3]);
+/* Electrostatic start (Gauss at t_0 and t_{-1}): solves -D^T M (-D phi) = rho^0 on
+ * interior nodes by CG to tol, sets e^0 = e^{-1} = -D phi.  *iters may be NULL. */
+int fepic_init_electrostatic(fepic_ctx* ctx, double tol, int* iters);
+
+/* ---------------------------------------------------------------- particles
+ * A species has charge q (C), mass m (kg) and macro-particle weight w (physical particles
+ * per macro-particle, Sec. II-A point shapes). */
+int fepic_add_species(fepic_ctx* ctx, double q, double m, double w, int* species_out);
+/* Appends n particles: id [n] (caller-chosen, kept through sorting; NULL = running
+ * index), x [n][3] Cartesian positions at t_n, u [n][3] = gamma v at t_{n-1/2} (m/s).
+ * Each is located in its tet on the device; points outside the mesh or with non-finite
+ * values are dropped and counted in *n_rejected (may be NULL). */
+int fepic_upload_particles(fepic_ctx* ctx, int species, int64_t n, const int64_t* id, const double* x,
+                           const double* u, int64_t* n_rejected);
+int fepic_num_particles(fepic_ctx* ctx, int species, int64_t* n);
+/* Copies live particles out (order = current device order): id, x [n][3] (Cartesian,
+ * reconstructed as sum lambda_k r_k), u [n][3], tet [n], lambda [n][4] (local vertex
+ * order of the sorted tet).  Any output may be NULL.  *n = count written (<= cap). */
+int fepic_get_particles(fepic_ctx* ctx, int species, int64_t cap, int64_t* n, int64_t* id, double* x, double* u,
+                        int32_t* tet, double* lambda);
+
+/* ---------------------------------------------------------------- the step
+ * One PIC step (Sec. II-A cycle): stage fields per tet, gather + relativistic Boris +
+ * path tracking + Whitney-1 deposit of dG^{n+1} = G^{n+1} - G^n for every particle,
+ * Newmark right-hand side
+ *   b = (2M - (1/2 - 2beta + gamma) dt^2 S) e^n - (M + (1/2 + beta - gamma) dt^2 S) e^{n-1}
+ *       - (dG^{n+1} - dG^n),
+ * PCG solve (M + beta dt^2 S) e^{n+1} = b from the configured warm start, Faraday
+ * b^{n+1} = b^n - dt C (gamma e^{n+1} + (1 - gamma) e^n).  Atomic: on
+ * FEPIC_E_CG_NOT_CONVERGED or FEPIC_E_CROSSING_CAP nothing is committed.  out may be
+ * NULL. */
+int fepic_step(fepic_ctx* ctx, double dt, double beta, double gamma, fepic_step_stats* out);
+/* Particle half only (fields frozen): stage, gather, push, track, deposit; commits the
+ * particles and dG^{n+1} (the field history is left as is).  out may be NULL. */
+int fepic_push_particles(fepic_ctx* ctx, double dt, fepic_step_stats* out);
+
+/* ---------------------------------------------------------------- read-out
+ * Host copies; sizes from fepic_get_topology_sizes.  Any output may be NULL. */
+int fepic_get_fields(fepic_ctx* ctx, double* e, double* e_prev, double* b);
+/* dG: [n_edges] current deposited by the last step (G^n - G^{n-1}); G: [n_edges]
+ * time-integrated current G^n = sum of all deposits (eq. (G)). */
+int fepic_get_current(fepic_ctx* ctx, double* dG, double* G);
+/* rho: [n_nodes] nodal charge sum_p q w lambda_k(x_p) of the live particles. */
+int fepic_get_rho(fepic_ctx* ctx, double* rho);
+/* Recomputes the residuals of fepic_step_stats for the current state on demand. */
+int fepic_diagnostics(fepic_ctx* ctx, fepic_step_stats* out);
+
+/* ---------------------------------------------------------------- profiling
+ * Brackets every launch of the named kernel family ("push", "stage", "sort", "rhs",
+ * "cg_spmv", "cg_update", "faraday", "mlp_fwd") with HIP events on the context's stream
+ * while enabled; fepic_kernel_time returns the summed duration and launch count since
+ * enabling (synchronizes the stream). */
+int fepic_kernel_timing(fepic_ctx* ctx, const char* family, int enable);
+int fepic_kernel_time(fepic_ctx* ctx, const char* family, double* total_ms, int64_t* launches);
+
+/* ---------------------------------------------------------------- learned warm start
+ * Per-edge network 4 -> 64 -> 64 -> 1 (ReLU), BF16 matrix-core arithmetic with FP32
+ * accumulation.  Inputs per interior edge: [e^n, e^{n-1}, e^{n-2}] / s_e and dG^{n+1} / s_g
+ * with s_e, s_g the RMS over interior edges (1 if zero); prediction x0 = e^n + s_e y.
+ * Flat FP32 weight layout: W1[64][4], b1[64], W2[64][64], b2[64], W3[1][64], b3[1]
+ * (4481 values).  The PCG always runs to cg_tol from whatever start, so the network only
+ * changes the iteration count, never the accuracy; a non-finite prediction or one whose
+ * residual exceeds ||b|| falls back to e^n. */
+#define FEPIC_MLP_N_PARAMS 4481
+typedef struct {
+    int epochs;          /* passes over the recorded samples                       */
+    int64_t batch;       /* rows per minibatch (multiple of 64)                    */
+    double lr, beta1, beta2, eps;  /* Adam                                         */
+    uint64_t seed;       /* initialization and minibatch order                    */
+    double val_fraction; /* share of recorded snapshots held out for validation   */
+} fepic_train_opts;
+typedef struct {
+    double train_loss, val_loss;   /* final mean squared error (normalized units)  */
+    int64_t n_train_rows, n_val_rows, n_steps;
+    float ms_total;
+} fepic_train_stats;
+/* on != 0: each later fepic_step appends (features, target) of its interior edges to a
+ * device buffer holding up to max_snapshots steps (oldest dropped first). */
+int fepic_ws_record(fepic_ctx* ctx, int on, int64_t max_snapshots);
+int fepic_ws_num_snapshots(fepic_ctx* ctx, int64_t* n);
+int fepic_ws_train(fepic_ctx* ctx, const fepic_train_opts* opts, fepic_train_stats* out);
+int fepic_ws_get_weights(fepic_ctx* ctx, float* w, int64_t cap, int64_t* n);
+int fepic_ws_set_weights(fepic_ctx* ctx, const float* w, int64_t n);
+int fepic_set_warm_start(fepic_ctx* ctx, int mode);
+/* Test entries on host batches: X [n][4] FP32 -> y [n]; gradient of the mean squared
+ * error against t [n] -> grad [4481] and *loss, computed by the device kernels. */
+int fepic_mlp_forward(fepic_ctx* ctx, int64_t n, const float* X, float* y);
+int fepic_mlp_grad(fepic_ctx* ctx, int64_t n, const float* X, const float* t, float* grad, double* loss);
+
+/* ---------------------------------------------------------------- checkpoint
+ * Versioned binary file: fields and their history, current history, particles of every
+ * species, step counter and time, warm-start weights.  Load requires a context with the
+ * same mesh uploaded and the same species added. */
+int fepic_save(fepic_ctx* ctx, const char* path);
+int fepic_load(fepic_ctx* ctx, const char* path);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEPIC_H */

@@ -1,0 +1,1068 @@
+// libfepic C ABI: context, device state, the step, read-out (see include/fepic.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace fepic;
+
+namespace fepic {
+
+const char* kFamilies[] = {"push", "stage", "sort", "rhs", "cg_spmv", "cg_update", "faraday", "mlp_fwd"};
+
+int hip_fail(fepic_ctx* c, hipError_t e, const char* what) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return FEPIC_E_HIP;
+}
+
+int fail(fepic_ctx* c, int code, const std::string& msg) {
+    c->err = msg;
+    return code;
+}
+
+void* dmalloc(fepic_ctx* c, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    c->allocs.push_back(p);
+    return p;
+}
+
+void dfree(fepic_ctx* c, void* p) {
+    if (!p) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+hipEvent_t* timer_pair(fepic_ctx* c, int fam) {
+    if (fam < 0 || !c->timers[fam].on) return nullptr;
+    KernelTimer& k = c->timers[fam];
+    if (k.used + 2 > (int64_t)k.ev.size()) {
+        for (int i = 0; i < 256; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            k.ev.push_back(e);
+        }
+    }
+    hipEvent_t* p = &k.ev[k.used];
+    k.used += 2;
+    return p;
+}
+
+}  // namespace fepic
+
+#define HIPCHK(c, expr)                                            \
+    do {                                                           \
+        hipError_t e_ = (expr);                                    \
+        if (e_ != hipSuccess) return fepic::hip_fail(c, e_, #expr); \
+    } while (0)
+
+#define NEED_DEV(c)                                                                                   \
+    do {                                                                                              \
+        if (!(c)) return FEPIC_E_ARG;                                                                 \
+        if ((c)->host_only) return fepic::fail(c, FEPIC_E_NO_DEVICE, "host-only context");           \
+        if (!(c)->have_mesh) return fepic::fail(c, FEPIC_E_STATE, "no mesh uploaded");               \
+    } while (0)
+
+namespace {
+
+template <typename T>
+T* dalloc(fepic_ctx* c, int64_t n) {
+    return (T*)dmalloc(c, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+}
+
+template <typename T>
+int upload(fepic_ctx* c, T** dst, const std::vector<T>& src) {
+    *dst = dalloc<T>(c, (int64_t)src.size());
+    if (!*dst) return fail(c, FEPIC_E_OOM, "device allocation failed");
+    if (!src.empty()) HIPCHK(c, hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return FEPIC_OK;
+}
+
+template <typename T>
+PArrays<T> parr(Species& s, int which) {
+    PArrays<T> p;
+    p.tet = (int32_t*)s.buf[which][0];
+    p.l1 = (T*)s.buf[which][1];
+    p.l2 = (T*)s.buf[which][2];
+    p.l3 = (T*)s.buf[which][3];
+    p.u0 = (T*)s.buf[which][4];
+    p.u1 = (T*)s.buf[which][5];
+    p.u2 = (T*)s.buf[which][6];
+    p.id = (int64_t*)s.buf[which][7];
+    return p;
+}
+
+size_t field_size(const fepic_ctx* c) { return c->opt.precision == FEPIC_ALL_FP64 ? 8 : 4; }
+
+size_t array_bytes(const fepic_ctx* c, int a, int64_t n) {
+    if (a == 0) return 4 * (size_t)n;
+    if (a == 7) return 8 * (size_t)n;
+    return field_size(c) * (size_t)n;
+}
+
+int ensure_capacity(fepic_ctx* c, Species& s, int64_t need) {
+    if (need <= s.cap) return FEPIC_OK;
+    const int64_t cap = std::max<int64_t>({need, s.cap + s.cap / 4, 1024});
+    void* nb[2][8] = {};
+    for (int w = 0; w < 2; ++w)
+        for (int a = 0; a < 8; ++a) {
+            nb[w][a] = dmalloc(c, array_bytes(c, a, cap));
+            if (!nb[w][a]) return fail(c, FEPIC_E_OOM, "particle buffer allocation failed");
+        }
+    for (int a = 0; a < 8; ++a)
+        if (s.n > 0) HIPCHK(c, hipMemcpyAsync(nb[0][a], s.buf[s.cur][a], array_bytes(c, a, s.n), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int w = 0; w < 2; ++w)
+        for (int a = 0; a < 8; ++a) {
+            dfree(c, s.buf[w][a]);
+            s.buf[w][a] = nb[w][a];
+        }
+    s.cur = 0;
+    s.cap = cap;
+    return FEPIC_OK;
+}
+
+template <typename T>
+void sort_species(fepic_ctx* c, Species& s) {
+    hipEvent_t* ev = timer_pair(c, FAM_SORT);
+    if (ev) (void)hipEventRecord(ev[0], c->stream);
+    launch_sort<T>(c->stream, parr<T>(s, s.cur), parr<T>(s, 1 - s.cur), s.n, c->mesh.n_tets, c->d_count, c->d_offset,
+                   c->d_bsums, s.d_nlive);
+    if (ev) (void)hipEventRecord(ev[1], c->stream);
+    s.cur = 1 - s.cur;
+    s.sorted_pending = true;
+}
+
+void sort_all(fepic_ctx* c) {
+    for (auto& s : c->species) {
+        if (c->opt.precision == FEPIC_ALL_FP64) sort_species<double>(c, s);
+        else sort_species<float>(c, s);
+    }
+}
+
+// Reads the live counts written by the last sorts (stream must be synchronized).
+void settle_counts(fepic_ctx* c) {
+    for (auto& s : c->species)
+        if (s.sorted_pending) {
+            s.n = *s.h_nlive;
+            s.sorted_pending = false;
+        }
+}
+
+int sync_counts(fepic_ctx* c) {
+    for (auto& s : c->species)
+        if (s.sorted_pending) HIPCHK(c, hipMemcpyAsync(s.h_nlive, s.d_nlive, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    settle_counts(c);
+    return FEPIC_OK;
+}
+
+template <typename T>
+void compute_rho_T(fepic_ctx* c, double* rho) {
+    launch_fill(c->stream, rho, c->mesh.n_nodes, 0.0);
+    for (auto& s : c->species) launch_rho<T>(c->stream, parr<T>(s, s.cur), s.n, c->d_tets, s.q * s.w, rho);
+}
+
+void compute_rho(fepic_ctx* c, double* rho) {
+    if (c->opt.precision == FEPIC_ALL_FP64) compute_rho_T<double>(c, rho);
+    else compute_rho_T<float>(c, rho);
+}
+
+void ev_mark(fepic_ctx* c, int i) {
+    if (c->opt.timing) (void)hipEventRecord(c->phase_ev[i], c->stream);
+}
+
+// Particle half: optional sort, staging, gather/push/track/deposit into d_dgn and the
+// alternate particle buffers.  Nothing is committed here.
+template <typename T>
+void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
+    ev_mark(c, 0);
+    if (do_sort) sort_all(c);
+    ev_mark(c, 1);
+    {
+        hipEvent_t* ev = timer_pair(c, FAM_STAGE);
+        if (ev) (void)hipEventRecord(ev[0], c->stream);
+        launch_stage<T>(c->stream, c->mesh.n_tets, (TetBlock<T>*)c->d_blk, c->d_e, c->d_b, c->d_grad64,
+                        c->d_tet_edges, c->d_tet_faces);
+        if (ev) (void)hipEventRecord(ev[1], c->stream);
+    }
+    ev_mark(c, 2);
+    launch_fill(c->stream, c->d_dgn, c->mesh.n_edges, 0.0);
+    if (hipMemsetAsync(c->d_cnt, 0, sizeof(PushCounters), c->stream) != hipSuccess) c->deferred_err = FEPIC_E_HIP;
+    for (auto& s : c->species) {
+        if (s.n == 0) continue;
+        PushParams pp;
+        pp.dt = dt;
+        pp.qm_half_dt = s.q * dt / (2.0 * s.m);
+        pp.qw = s.q * s.w;
+        pp.cap = c->opt.crossing_cap;
+        hipEvent_t* ev = timer_pair(c, FAM_PUSH);
+        if (ev) (void)hipEventRecord(ev[0], c->stream);
+        launch_push<T>(c->stream, parr<T>(s, s.cur), parr<T>(s, 1 - s.cur), s.n, (const TetBlock<T>*)c->d_blk,
+                       c->d_dgn, pp, c->d_cnt, s.sorted_pending ? s.d_nlive : nullptr);
+        if (ev) (void)hipEventRecord(ev[1], c->stream);
+    }
+    ev_mark(c, 3);
+}
+
+void particle_phase(fepic_ctx* c, double dt, bool do_sort) {
+    if (c->opt.precision == FEPIC_ALL_FP64) particle_phase_T<double>(c, dt, do_sort);
+    else particle_phase_T<float>(c, dt, do_sort);
+}
+
+void ensure_operator(fepic_ctx* c, double dt, double beta) {
+    const double cA = beta * dt * dt;
+    if (c->A_scale == cA && c->A_valid) return;
+    launch_scale_A(c->stream, c->mesh.mat, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_A, c->d_dinv, c->d_bedge, cA);
+    c->A_scale = cA;
+    c->A_valid = true;
+}
+
+// Field half: RHS, warm start, PCG, true residual, Faraday into d_bn.  Returns the
+// iteration count via the host scalars (stream synchronized at return).
+int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
+    const int64_t ne = c->mesh.n_edges;
+    ensure_operator(c, dt, beta);
+    ev_mark(c, 4);
+    {
+        hipEvent_t* ev = timer_pair(c, FAM_RHS);
+        if (ev) (void)hipEventRecord(ev[0], c->stream);
+        launch_rhs(c->stream, ne, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_e, c->d_ep, c->d_dgn, c->d_dg, c->d_bedge,
+                   dt * dt, 0.5 - 2.0 * beta + gamma, 0.5 + beta - gamma, c->d_rhs, c->d_partial, c->d_sc,
+                   c->opt.cg_tol);
+        if (ev) (void)hipEventRecord(ev[1], c->stream);
+    }
+    ev_mark(c, 5);
+    int mode = c->opt.warm_start;
+    if (mode == FEPIC_WS_MLP && !c->mlp_ready) mode = FEPIC_WS_PREV;
+    if (mode == FEPIC_WS_MLP) {
+        int rc = mlp_warm_start(c);
+        if (rc != FEPIC_OK) return rc;
+    } else {
+        launch_warm(c->stream, mode, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
+    }
+    if (c->recording) {
+        int rc = mlp_record_features(c);
+        if (rc != FEPIC_OK) return rc;
+    }
+    ev_mark(c, 6);
+    launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, c->d_r, c->d_z, c->d_p[0],
+                   c->d_partial, c->d_sc);
+    if (mode == FEPIC_WS_MLP) {
+        // guard: a start worse than x0 = 0 (or non-finite) falls back to e^n
+        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (!(std::isfinite(c->h_sc->rr0)) || c->h_sc->rr0 > c->h_sc->bb) {
+            c->mlp_fallbacks++;
+            launch_warm(c->stream, FEPIC_WS_PREV, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
+            launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, c->d_r, c->d_z,
+                           c->d_p[0], c->d_partial, c->d_sc);
+        }
+    }
+    int it = 0, pb = 0;
+    const int maxit = c->opt.cg_max_iters;
+    int batch = std::max(1, c->opt.cg_check_every);
+    for (;;) {
+        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->h_sc->converged || c->h_sc->iters >= maxit) break;
+        // estimate the remaining iterations from the observed contraction of ||r||^2
+        int todo = batch;
+        const double rr = c->h_sc->rr, rr0 = c->h_sc->rr0, tgt = c->h_sc->tol2_bb;
+        const int done = c->h_sc->iters;
+        if (done >= 4 && rr > 0 && rr0 > rr && tgt > 0) {
+            const double rate = std::log(rr / rr0) / done;  // per iteration, < 0
+            const double need = std::log(tgt / rr) / rate;
+            if (std::isfinite(need)) todo = std::max(batch, (int)std::ceil(0.9 * need));
+        }
+        todo = std::min(todo, maxit - done);
+        for (int k = 0; k < todo; ++k) {
+            hipEvent_t* e1 = timer_pair(c, FAM_CG_SPMV);
+            hipEvent_t* e2 = timer_pair(c, FAM_CG_UPDATE);
+            launch_cg_iter(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, c->d_r, c->d_z, c->d_p[pb],
+                           c->d_p[1 - pb], c->d_q, c->d_partial, c->d_sc, e1, e2);
+            pb ^= 1;
+        }
+        it += todo;
+    }
+    ev_mark(c, 7);
+    launch_cg_resid(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_rhs, c->d_x, c->d_rt, c->d_partial, c->d_sc);
+    {
+        hipEvent_t* ev = timer_pair(c, FAM_FARADAY);
+        if (ev) (void)hipEventRecord(ev[0], c->stream);
+        launch_faraday(c->stream, c->mesh.n_faces, c->d_face_edges, c->d_b, c->d_x, c->d_e, dt, gamma, c->d_bn);
+        if (ev) (void)hipEventRecord(ev[1], c->stream);
+    }
+    ev_mark(c, 8);
+    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+    return FEPIC_OK;
+}
+
+void fill_phase_times(fepic_ctx* c, fepic_step_stats* st, bool field) {
+    if (!c->opt.timing || !st) return;
+    float ms[8] = {0};
+    const int last = field ? 8 : 3;
+    for (int i = 0; i < last; ++i) (void)hipEventElapsedTime(&ms[i], c->phase_ev[i], c->phase_ev[i + 1]);
+    st->ms_sort = ms[0];
+    st->ms_stage = ms[1];
+    st->ms_particles = ms[2];
+    if (field) {
+        st->ms_rhs = ms[4];
+        st->ms_warm = ms[5];
+        st->ms_cg = ms[6];
+        st->ms_faraday = ms[7];
+    }
+}
+
+double max_abs_qw(const fepic_ctx* c) {
+    double q = 0.0;
+    for (const auto& s : c->species) q = std::max(q, std::fabs(s.q * s.w));
+    return q > 0 ? q : 1.0;
+}
+
+// Conservation diagnostics after a committed step.  have_step: continuity/drift apply.
+int run_diagnostics(fepic_ctx* c, fepic_step_stats* st, bool have_step, bool have_solve) {
+    const int64_t nn = c->mesh.n_nodes, ne = c->mesh.n_edges;
+    const hipStream_t s = c->stream;
+    HIPCHK(c, hipMemsetAsync(c->d_acc, 0, sizeof(DiagAcc), s));
+    compute_rho(c, c->d_rho_new);
+    launch_fill(s, c->d_n1, nn, 0.0);
+    launch_DT(s, ne, c->d_edges, c->d_dg, c->d_n1);                   // D^T dG
+    launch_sell_spmv(s, ne, c->d_sp, c->d_col, c->d_M, c->d_e, c->d_Me);
+    launch_fill(s, c->d_n2, nn, 0.0);
+    launch_DT(s, ne, c->d_edges, c->d_Me, c->d_n2);                   // D^T M e
+    launch_fill(s, c->d_n3, nn, 0.0);
+    if (have_solve) launch_DT(s, ne, c->d_edges, c->d_rt, c->d_n3);   // D^T r_cg
+    const int have_hist = (have_step && have_solve && c->rG_levels >= 2) ? 1 : 0;
+    double* rG_new = c->d_rG[c->rG_head];
+    const double* rG1 = c->d_rG[(c->rG_head + 2) % 3];
+    const double* rG2 = c->d_rG[(c->rG_head + 1) % 3];
+    launch_diag_nodes(s, nn, c->d_inode, c->d_rho_new, c->rho_valid ? c->d_rho : c->d_rho_new, c->d_n1, c->d_n2, rG1,
+                      rG2, c->d_n3, have_hist, rG_new, c->d_acc);
+    launch_divb(s, c->mesh.n_tets, c->d_tet_faces, c->d_b, c->d_acc);
+    HIPCHK(c, hipMemsetAsync(c->d_dotc, 0, sizeof(unsigned int), s));
+    launch_dot(s, ne, c->d_e, c->d_Me, c->d_partial, &c->d_acc->energy, c->d_dotc);
+    HIPCHK(c, hipMemcpyAsync(c->h_acc, c->d_acc, sizeof(DiagAcc), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    auto dbl = [](unsigned long long v) {
+        double d;
+        std::memcpy(&d, &v, 8);
+        return d;
+    };
+    const double scale = std::max(dbl(c->h_acc->rho_max), max_abs_qw(c));
+    if (st) {
+        st->cont_resid_rel = (have_step && c->rho_valid) ? dbl(c->h_acc->cont_max) / scale : -1.0;
+        st->gauss_resid_rel = dbl(c->h_acc->gauss_max) / scale;
+        st->gauss_drift_check_rel = have_hist ? dbl(c->h_acc->drift_max) / scale : -1.0;
+        st->divb_max = dbl(c->h_acc->divb_max);
+        st->field_energy = 0.5 * c->h_acc->energy;
+    }
+    // rotate: the new charge becomes the current one; Gauss residual history
+    std::swap(c->d_rho, c->d_rho_new);
+    c->rho_valid = true;
+    if (have_step && have_solve) {
+        c->rG_head = (c->rG_head + 1) % 3;
+        c->rG_levels = std::min(c->rG_levels + 1, 3);
+    } else {
+        c->rG_levels = 0;
+    }
+    return FEPIC_OK;
+}
+
+int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats* out, bool solve) {
+    NEED_DEV(c);
+    if (!(dt > 0) || !std::isfinite(dt) || !std::isfinite(beta) || !std::isfinite(gamma))
+        return fail(c, FEPIC_E_ARG, "bad step parameters");
+    fepic_step_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.gauss_drift_check_rel = st.cont_resid_rel = st.gauss_resid_rel = -1.0;
+    if (c->opt.diagnostics && !c->rho_valid) {
+        compute_rho(c, c->d_rho);
+        c->rho_valid = true;
+    }
+    const bool do_sort = (c->opt.sort_period > 0) && (c->step_count % c->opt.sort_period == 0);
+    particle_phase(c, dt, do_sort);
+    if (c->deferred_err) {
+        int rc = c->deferred_err;
+        c->deferred_err = 0;
+        return rc;
+    }
+    if (solve) {
+        int rc = field_phase(c, dt, beta, gamma);
+        if (rc != FEPIC_OK) return rc;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(PushCounters), hipMemcpyDeviceToHost, c->stream));
+    int rc = sync_counts(c);
+    if (rc != FEPIC_OK) return rc;
+    HIPCHK(c, hipGetLastError());
+    st.n_crossings = (int64_t)c->h_cnt->n_crossings;
+    st.max_crossings = (int)c->h_cnt->max_crossings;
+    st.n_absorbed = c->h_cnt->n_absorbed;
+    st.n_cap_exceeded = (int)c->h_cnt->n_cap;
+    if (solve) {
+        const CgScalars& sc = *c->h_sc;
+        st.cg_iters = sc.iters;
+        st.cg_rel_resid = sc.bb > 0 ? std::sqrt(sc.rr_true / sc.bb) : 0.0;
+        st.cg_rel_resid0 = sc.bb > 0 ? std::sqrt(sc.rr0 / sc.bb) : 0.0;
+    }
+    fill_phase_times(c, &st, solve);
+    // failure: leave the state as it was before the call (the sort is a pure reorder)
+    if (st.n_cap_exceeded) {
+        if (out) *out = st;
+        return fail(c, FEPIC_E_CROSSING_CAP, "a particle path exceeded the crossing cap; step not committed");
+    }
+    if (solve && !c->h_sc->converged) {
+        if (out) *out = st;
+        return fail(c, FEPIC_E_CG_NOT_CONVERGED, "PCG did not reach the tolerance; step not committed");
+    }
+    if (solve && c->recording) {
+        rc = mlp_record_target(c);
+        if (rc != FEPIC_OK) return rc;
+    }
+    // commit
+    for (auto& s : c->species) s.cur = 1 - s.cur;
+    std::swap(c->d_dg, c->d_dgn);
+    launch_axpby(c->stream, c->d_G, c->d_G, 1.0, c->d_dg, 1.0, c->mesh.n_edges);
+    if (solve) {
+        double* old_ep2 = c->d_ep2;
+        c->d_ep2 = c->d_ep;
+        c->d_ep = c->d_e;
+        c->d_e = c->d_x;
+        c->d_x = old_ep2;
+        std::swap(c->d_b, c->d_bn);
+    }
+    c->step_count++;
+    c->time += dt;
+    // one more sort bookkeeping: dead particles are compacted at the next sort
+    int64_t live = 0;
+    for (auto& s : c->species) live += s.n;
+    st.n_particles = live - st.n_absorbed;
+    if (c->opt.diagnostics) {
+        rc = run_diagnostics(c, &st, true, solve);
+        if (rc != FEPIC_OK) return rc;
+    } else {
+        c->rho_valid = false;
+    }
+    st.step = c->step_count;
+    st.t = c->time;
+    if (out) *out = st;
+    return FEPIC_OK;
+}
+
+}  // namespace
+
+namespace fepic {
+
+// Electrostatic start: -D^T M (-D phi) = rho on interior nodes.  D^T M D is the P1
+// (Whitney-0) stiffness eps0 int grad l_i . grad l_j, assembled here in closed form and
+// solved by Jacobi-PCG on the host (set-up only), then e^0 = e^{-1} = -D phi.
+int init_electrostatic(fepic_ctx* c, double tol, int* iters) {
+    NEED_DEV(c);
+    if (!(tol > 0)) return fail(c, FEPIC_E_ARG, "bad tolerance");
+    int rc = sync_counts(c);
+    if (rc) return rc;
+    const HostMesh& m = c->mesh;
+    const int64_t nn = m.n_nodes;
+    compute_rho(c, c->d_n1);
+    std::vector<double> rho(nn);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(rho.data(), c->d_n1, 8 * nn, hipMemcpyDeviceToHost));
+    std::vector<int64_t> idx(nn, -1);
+    int64_t ni = 0;
+    for (int64_t v = 0; v < nn; ++v)
+        if (!m.bnode[v]) idx[v] = ni++;
+    std::vector<double> bvec(ni);
+    double bn = 0.0;
+    for (int64_t v = 0; v < nn; ++v)
+        if (idx[v] >= 0) {
+            bvec[idx[v]] = rho[v];
+            bn += rho[v] * rho[v];
+        }
+    bn = std::sqrt(bn);
+    std::vector<double> phi(ni, 0.0);
+    int it = 0;
+    if (bn > 0) {
+        struct Trip { int64_t r, c; double v; };
+        std::vector<Trip> tr;
+        tr.reserve(16 * m.n_tets);
+        for (int64_t t = 0; t < m.n_tets; ++t) {
+            double g[4][3];
+            for (int k = 1; k < 4; ++k)
+                for (int d = 0; d < 3; ++d) g[k][d] = m.grad[9 * t + 3 * (k - 1) + d];
+            for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+            for (int a = 0; a < 4; ++a) {
+                const int64_t ra = idx[m.tets[4 * t + a]];
+                if (ra < 0) continue;
+                for (int b = 0; b < 4; ++b) {
+                    const int64_t rb = idx[m.tets[4 * t + b]];
+                    if (rb < 0) continue;
+                    tr.push_back({ra, rb, kEps0 * m.vol[t] * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2])});
+                }
+            }
+        }
+        std::sort(tr.begin(), tr.end(), [](const Trip& x, const Trip& y) { return x.r != y.r ? x.r < y.r : x.c < y.c; });
+        std::vector<int64_t> rp(ni + 1, 0), ci;
+        std::vector<double> vv;
+        for (size_t k = 0; k < tr.size(); ++k) {
+            if (k > 0 && tr[k].r == tr[k - 1].r && tr[k].c == tr[k - 1].c) {
+                vv.back() += tr[k].v;
+                continue;
+            }
+            ci.push_back(tr[k].c);
+            vv.push_back(tr[k].v);
+            rp[tr[k].r + 1]++;
+        }
+        for (int64_t r = 0; r < ni; ++r) rp[r + 1] += rp[r];
+        std::vector<double> dinv(ni), r(bvec), z(ni), p(ni), q(ni);
+        for (int64_t i = 0; i < ni; ++i)
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+                if (ci[k] == i) dinv[i] = 1.0 / vv[k];
+        auto spmv = [&](const std::vector<double>& x, std::vector<double>& y) {
+            for (int64_t i = 0; i < ni; ++i) {
+                double a = 0.0;
+                for (int64_t k = rp[i]; k < rp[i + 1]; ++k) a += vv[k] * x[ci[k]];
+                y[i] = a;
+            }
+        };
+        double rz = 0.0;
+        for (int64_t i = 0; i < ni; ++i) {
+            z[i] = dinv[i] * r[i];
+            p[i] = z[i];
+            rz += r[i] * z[i];
+        }
+        for (it = 0; it < 100000; ++it) {
+            spmv(p, q);
+            double pq = 0.0;
+            for (int64_t i = 0; i < ni; ++i) pq += p[i] * q[i];
+            const double al = rz / pq;
+            double rr = 0.0, rzn = 0.0;
+            for (int64_t i = 0; i < ni; ++i) {
+                phi[i] += al * p[i];
+                r[i] -= al * q[i];
+                rr += r[i] * r[i];
+            }
+            if (std::sqrt(rr) <= tol * bn) {
+                ++it;
+                break;
+            }
+            for (int64_t i = 0; i < ni; ++i) {
+                z[i] = dinv[i] * r[i];
+                rzn += r[i] * z[i];
+            }
+            const double be = rzn / rz;
+            rz = rzn;
+            for (int64_t i = 0; i < ni; ++i) p[i] = z[i] + be * p[i];
+        }
+    }
+    std::vector<double> e(m.n_edges, 0.0);
+    for (int64_t k = 0; k < m.n_edges; ++k) {
+        const int64_t a = idx[m.edges[2 * k]], b = idx[m.edges[2 * k + 1]];
+        const double pa = a >= 0 ? phi[a] : 0.0, pb = b >= 0 ? phi[b] : 0.0;
+        e[k] = m.bedge[k] ? 0.0 : -(pb - pa);
+    }
+    for (double* d : {c->d_e, c->d_ep, c->d_ep2}) HIPCHK(c, hipMemcpy(d, e.data(), 8 * m.n_edges, hipMemcpyHostToDevice));
+    c->rG_levels = 0;
+    if (iters) *iters = it;
+    return FEPIC_OK;
+}
+
+}  // namespace fepic
+
+// =============================================================================== C ABI
+extern "C" {
+
+int fepic_abi_version(void) { return FEPIC_ABI_VERSION; }
+
+void fepic_default_options(fepic_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->device = 0;
+    o->precision = FEPIC_FP32_PUSH_FP64_ACC;
+    o->cg_tol = 1e-10;
+    o->cg_max_iters = 10000;
+    o->cg_check_every = 8;
+    o->sort_period = 1;
+    o->crossing_cap = 64;
+    o->warm_start = FEPIC_WS_PREV;
+    o->diagnostics = 0;
+    o->timing = 0;
+}
+
+const char* fepic_error_string(int code) {
+    switch (code) {
+        case FEPIC_OK: return "ok";
+        case FEPIC_E_ARG: return "bad argument";
+        case FEPIC_E_MESH: return "bad mesh";
+        case FEPIC_E_STATE: return "bad call order";
+        case FEPIC_E_OOM: return "out of memory";
+        case FEPIC_E_HIP: return "HIP error";
+        case FEPIC_E_CG_NOT_CONVERGED: return "PCG did not converge";
+        case FEPIC_E_CROSSING_CAP: return "crossing cap exceeded";
+        case FEPIC_E_IO: return "I/O error";
+        case FEPIC_E_NO_DEVICE: return "no device in this context";
+        default: return "unknown error";
+    }
+}
+
+const char* fepic_last_error(const fepic_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int fepic_create(const fepic_options* opts, fepic_ctx** out) {
+    if (!out) return FEPIC_E_ARG;
+    *out = nullptr;
+    fepic_options o;
+    fepic_default_options(&o);
+    if (opts) o = *opts;
+    if (o.precision != FEPIC_FP32_PUSH_FP64_ACC && o.precision != FEPIC_ALL_FP64) return FEPIC_E_ARG;
+    if (!(o.cg_tol > 0) || o.cg_max_iters < 1 || o.crossing_cap < 1 || o.sort_period < 0) return FEPIC_E_ARG;
+    if (o.warm_start < FEPIC_WS_PREV || o.warm_start > FEPIC_WS_MLP) return FEPIC_E_ARG;
+    if (o.cg_check_every < 1) o.cg_check_every = 8;
+    fepic_ctx* c = new fepic_ctx();
+    c->opt = o;
+    c->host_only = (o.device < 0);
+    if (!c->host_only) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) {
+            delete c;
+            return FEPIC_E_NO_DEVICE;
+        }
+        if (hipSetDevice(o.device) != hipSuccess || hipStreamCreate(&c->own_stream) != hipSuccess) {
+            delete c;
+            return FEPIC_E_HIP;
+        }
+        c->stream = c->own_stream;
+        if (hipHostMalloc((void**)&c->h_sc, sizeof(CgScalars)) != hipSuccess ||
+            hipHostMalloc((void**)&c->h_cnt, sizeof(PushCounters)) != hipSuccess ||
+            hipHostMalloc((void**)&c->h_acc, sizeof(DiagAcc)) != hipSuccess) {
+            delete c;
+            return FEPIC_E_OOM;
+        }
+        for (auto& e : c->phase_ev) (void)hipEventCreate(&e);
+    }
+    *out = c;
+    return FEPIC_OK;
+}
+
+int fepic_destroy(fepic_ctx* c) {
+    if (!c) return FEPIC_E_ARG;
+    if (!c->host_only) {
+        (void)hipSetDevice(c->opt.device);
+        (void)hipStreamSynchronize(c->stream);
+        for (void* p : c->allocs) (void)hipFree(p);
+        for (auto& s : c->species) {
+            if (s.h_nlive) (void)hipHostFree(s.h_nlive);
+        }
+        for (auto& t : c->timers)
+            for (auto e : t.ev) (void)hipEventDestroy(e);
+        for (auto e : c->phase_ev) (void)hipEventDestroy(e);
+        if (c->h_sc) (void)hipHostFree(c->h_sc);
+        if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+        if (c->h_acc) (void)hipHostFree(c->h_acc);
+        if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    }
+    mlp_destroy(c);
+    delete c;
+    return FEPIC_OK;
+}
+
+int fepic_set_stream(fepic_ctx* c, void* stream) {
+    if (!c) return FEPIC_E_ARG;
+    if (c->host_only) return fail(c, FEPIC_E_NO_DEVICE, "host-only context");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->stream = stream ? (hipStream_t)stream : c->own_stream;
+    return FEPIC_OK;
+}
+
+int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets) {
+    if (!c) return FEPIC_E_ARG;
+    if (c->have_mesh) return fail(c, FEPIC_E_STATE, "mesh already uploaded");
+    int rc = build_host_mesh(c->mesh, n_nodes, xyz, n_tets, tets, c->err);
+    if (rc != FEPIC_OK) return rc;
+    c->have_mesh = true;
+    if (c->host_only) return FEPIC_OK;
+    HostMesh& m = c->mesh;
+    const int64_t ne = m.n_edges, nf = m.n_faces, nn = m.n_nodes, nt = m.n_tets;
+    std::vector<uint8_t> inode(nn);
+    for (int64_t v = 0; v < nn; ++v) inode[v] = !m.bnode[v];
+    std::vector<double> r0(3 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int d = 0; d < 3; ++d) r0[3 * t + d] = m.xyz[3 * m.tets[4 * t] + d];
+    if ((rc = upload(c, &c->d_tets, m.tets)) || (rc = upload(c, &c->d_edges, m.edges)) ||
+        (rc = upload(c, &c->d_tet_edges, m.tet_edges)) || (rc = upload(c, &c->d_tet_faces, m.tet_faces)) ||
+        (rc = upload(c, &c->d_face_edges, m.face_edges)) || (rc = upload(c, &c->d_bedge, m.bedge)) ||
+        (rc = upload(c, &c->d_inode, inode)) || (rc = upload(c, &c->d_grad64, m.grad)) ||
+        (rc = upload(c, &c->d_r0, r0)) || (rc = upload(c, &c->d_sp, m.mat.slice_ptr)) ||
+        (rc = upload(c, &c->d_col, m.mat.col)) || (rc = upload(c, &c->d_M, m.mat.M)) ||
+        (rc = upload(c, &c->d_S, m.mat.S)) || (rc = upload(c, &c->d_cell_start, m.cell_start)) ||
+        (rc = upload(c, &c->d_cell_tets, m.cell_tets)) || (rc = upload(c, &c->d_int_edges, m.int_edges)))
+        return rc;
+    std::vector<double> g3 = {m.grid_lo[0], m.grid_lo[1], m.grid_lo[2], m.grid_inv_h[0], m.grid_inv_h[1], m.grid_inv_h[2]};
+    std::vector<int32_t> gn = {m.grid_n[0], m.grid_n[1], m.grid_n[2]};
+    if ((rc = upload(c, &c->d_grid, g3)) || (rc = upload(c, &c->d_grid_n, gn))) return rc;
+    // per-tet records with the static geometry filled in
+    const bool f64 = c->opt.precision == FEPIC_ALL_FP64;
+    const size_t bsz = f64 ? sizeof(TetBlock<double>) : sizeof(TetBlock<float>);
+    std::vector<unsigned char> blk(bsz * nt, 0);
+    for (int64_t t = 0; t < nt; ++t) {
+        int32_t nbr[4], ed[6];
+        for (int k = 0; k < 4; ++k) nbr[k] = m.nbr[4 * t + k] < 0 ? -1 : (m.nbr[4 * t + k] << 2) | m.nbr_far[4 * t + k];
+        for (int i = 0; i < 6; ++i) ed[i] = m.tet_edges[6 * t + i];
+        if (f64) {
+            auto* b = (TetBlock<double>*)(blk.data() + bsz * t);
+            for (int i = 0; i < 9; ++i) b->gl[i] = m.grad[9 * t + i];
+            std::memcpy(b->nbr, nbr, sizeof(nbr));
+            std::memcpy(b->edge, ed, sizeof(ed));
+        } else {
+            auto* b = (TetBlock<float>*)(blk.data() + bsz * t);
+            for (int i = 0; i < 9; ++i) b->gl[i] = (float)m.grad[9 * t + i];
+            std::memcpy(b->nbr, nbr, sizeof(nbr));
+            std::memcpy(b->edge, ed, sizeof(ed));
+        }
+    }
+    if ((rc = upload(c, (unsigned char**)&c->d_blk, blk))) return rc;
+    const int64_t nnz = m.mat.slice_ptr.back();
+    c->d_A = dalloc<double>(c, nnz);
+    c->d_dinv = dalloc<double>(c, ne);
+    double** ev[] = {&c->d_e, &c->d_ep, &c->d_ep2, &c->d_x, &c->d_dg, &c->d_dgn, &c->d_G, &c->d_rhs, &c->d_r,
+                     &c->d_z, &c->d_p[0], &c->d_p[1], &c->d_q, &c->d_rt, &c->d_Me};
+    for (double** p : ev) {
+        *p = dalloc<double>(c, ne);
+        if (!*p) return fail(c, FEPIC_E_OOM, "device allocation failed");
+        HIPCHK(c, hipMemset(*p, 0, sizeof(double) * ne));
+    }
+    double** fv[] = {&c->d_b, &c->d_bn};
+    for (double** p : fv) {
+        *p = dalloc<double>(c, nf);
+        if (!*p) return fail(c, FEPIC_E_OOM, "device allocation failed");
+        HIPCHK(c, hipMemset(*p, 0, sizeof(double) * nf));
+    }
+    double** nv[] = {&c->d_rho, &c->d_rho_new, &c->d_n1, &c->d_n2, &c->d_n3, &c->d_rG[0], &c->d_rG[1], &c->d_rG[2]};
+    for (double** p : nv) {
+        *p = dalloc<double>(c, nn);
+        if (!*p) return fail(c, FEPIC_E_OOM, "device allocation failed");
+        HIPCHK(c, hipMemset(*p, 0, sizeof(double) * nn));
+    }
+    const int64_t max_blocks = ((std::max(ne, nt) + 255) / 256 + 8) * 2 + 64;
+    c->d_partial = dalloc<double>(c, 2 * max_blocks);
+    c->d_sc = dalloc<CgScalars>(c, 1);
+    c->d_cnt = dalloc<PushCounters>(c, 1);
+    c->d_acc = dalloc<DiagAcc>(c, 1);
+    c->d_dotc = dalloc<unsigned int>(c, 1);
+    c->d_count = dalloc<int32_t>(c, nt);
+    c->d_offset = dalloc<int32_t>(c, nt);
+    c->d_bsums = dalloc<int32_t>(c, nt / 1024 + 2);
+    if (!c->d_A || !c->d_dinv || !c->d_partial || !c->d_sc || !c->d_cnt || !c->d_acc || !c->d_count ||
+        !c->d_offset || !c->d_bsums || !c->d_dotc)
+        return fail(c, FEPIC_E_OOM, "device allocation failed");
+    HIPCHK(c, hipMemset(c->d_sc, 0, sizeof(CgScalars)));
+    HIPCHK(c, hipMemset(c->d_dotc, 0, sizeof(unsigned int)));
+    HIPCHK(c, hipDeviceSynchronize());
+    return FEPIC_OK;
+}
+
+int fepic_get_topology_sizes(fepic_ctx* c, int64_t* n_edges, int64_t* n_faces, int64_t* n_int_edges,
+                             int64_t* n_int_nodes, int64_t* euler) {
+    if (!c) return FEPIC_E_ARG;
+    if (!c->have_mesh) return fail(c, FEPIC_E_STATE, "no mesh uploaded");
+    const HostMesh& m = c->mesh;
+    if (n_edges) *n_edges = m.n_edges;
+    if (n_faces) *n_faces = m.n_faces;
+    if (n_int_edges) *n_int_edges = m.n_int_edges;
+    if (n_int_nodes) *n_int_nodes = m.n_int_nodes;
+    if (euler) *euler = m.n_nodes - m.n_edges + m.n_faces - m.n_tets;
+    return FEPIC_OK;
+}
+
+int fepic_get_topology(fepic_ctx* c, int32_t* tets_sorted, int32_t* edges, int32_t* faces, int32_t* tet_edges,
+                       int32_t* tet_faces, int32_t* nbr) {
+    if (!c) return FEPIC_E_ARG;
+    if (!c->have_mesh) return fail(c, FEPIC_E_STATE, "no mesh uploaded");
+    const HostMesh& m = c->mesh;
+    if (tets_sorted) std::copy(m.tets.begin(), m.tets.end(), tets_sorted);
+    if (edges) std::copy(m.edges.begin(), m.edges.end(), edges);
+    if (faces) std::copy(m.faces.begin(), m.faces.end(), faces);
+    if (tet_edges) std::copy(m.tet_edges.begin(), m.tet_edges.end(), tet_edges);
+    if (tet_faces) std::copy(m.tet_faces.begin(), m.tet_faces.end(), tet_faces);
+    if (nbr) std::copy(m.nbr.begin(), m.nbr.end(), nbr);
+    return FEPIC_OK;
+}
+
+int fepic_get_matrix(fepic_ctx* c, int which, int64_t cap, int64_t* nnz, int64_t* row, int64_t* col, double* val) {
+    if (!c || !nnz || (which != 0 && which != 1)) return FEPIC_E_ARG;
+    if (!c->have_mesh) return fail(c, FEPIC_E_STATE, "no mesh uploaded");
+    const HostMesh& m = c->mesh;
+    const SellMatrix& A = m.mat;
+    const std::vector<double>& v = which == 0 ? A.M : A.S;
+    int64_t n = 0;
+    for (int64_t s = 0; s < A.n_slices; ++s) {
+        const int64_t w = (A.slice_ptr[s + 1] - A.slice_ptr[s]) / kSell;
+        for (int l = 0; l < kSell; ++l) {
+            const int64_t r = s * kSell + l;
+            if (r >= A.n_rows || m.bedge[r]) continue;
+            for (int64_t k = 0; k < w; ++k) {
+                const int64_t p = A.slice_ptr[s] + k * kSell + l;
+                if (k > 0 && A.col[p] == r) continue;  // padding
+                if (row && n < cap) {
+                    row[n] = r;
+                    col[n] = A.col[p];
+                    val[n] = v[p];
+                }
+                ++n;
+            }
+        }
+    }
+    *nnz = n;
+    return (row && n > cap) ? FEPIC_E_ARG : FEPIC_OK;
+}
+
+int fepic_set_fields(fepic_ctx* c, const double* e, const double* e_prev, const double* b) {
+    NEED_DEV(c);
+    const HostMesh& m = c->mesh;
+    auto put_e = [&](double* dst, const double* src) -> int {
+        std::vector<double> v(src, src + m.n_edges);
+        for (int64_t i = 0; i < m.n_edges; ++i)
+            if (m.bedge[i]) v[i] = 0.0;
+        HIPCHK(c, hipMemcpy(dst, v.data(), sizeof(double) * m.n_edges, hipMemcpyHostToDevice));
+        return FEPIC_OK;
+    };
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int rc;
+    if (e && (rc = put_e(c->d_e, e))) return rc;
+    if (e_prev && (rc = put_e(c->d_ep, e_prev))) return rc;
+    if (e_prev && (rc = put_e(c->d_ep2, e_prev))) return rc;
+    if (b) HIPCHK(c, hipMemcpy(c->d_b, b, sizeof(double) * m.n_faces, hipMemcpyHostToDevice));
+    c->rG_levels = 0;
+    return FEPIC_OK;
+}
+
+int fepic_set_uniform_B(fepic_ctx* c, const double B0[3]) {
+    NEED_DEV(c);
+    if (!B0) return FEPIC_E_ARG;
+    std::vector<double> av;
+    face_area_vectors(c->mesh, av);
+    std::vector<double> b(c->mesh.n_faces);
+    for (int64_t f = 0; f < c->mesh.n_faces; ++f) b[f] = B0[0] * av[3 * f] + B0[1] * av[3 * f + 1] + B0[2] * av[3 * f + 2];
+    return fepic_set_fields(c, nullptr, nullptr, b.data());
+}
+
+int fepic_add_species(fepic_ctx* c, double q, double m, double w, int* out) {
+    NEED_DEV(c);
+    if (!(m > 0) || !std::isfinite(q) || !std::isfinite(w)) return fail(c, FEPIC_E_ARG, "bad species parameters");
+    Species s;
+    s.q = q;
+    s.m = m;
+    s.w = w;
+    s.d_nlive = dalloc<int32_t>(c, 1);
+    if (!s.d_nlive || hipHostMalloc((void**)&s.h_nlive, sizeof(int32_t)) != hipSuccess)
+        return fail(c, FEPIC_E_OOM, "allocation failed");
+    c->species.push_back(s);
+    if (out) *out = (int)c->species.size() - 1;
+    return FEPIC_OK;
+}
+
+int fepic_upload_particles(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
+                           const double* u, int64_t* n_rejected) {
+    NEED_DEV(c);
+    if (species < 0 || species >= (int)c->species.size() || n < 0 || (n > 0 && (!x || !u)))
+        return fail(c, FEPIC_E_ARG, "bad particle upload arguments");
+    if (n_rejected) *n_rejected = 0;
+    if (n == 0) return FEPIC_OK;
+    Species& s = c->species[species];
+    int rc = sync_counts(c);
+    if (rc) return rc;
+    if (s.n + n >= ((int64_t)1 << 31)) return fail(c, FEPIC_E_ARG, "too many particles for one species");
+    if ((rc = ensure_capacity(c, s, s.n + n))) return rc;
+    double* dx = dalloc<double>(c, 3 * n);
+    double* du = dalloc<double>(c, 3 * n);
+    int64_t* did = id ? dalloc<int64_t>(c, n) : nullptr;
+    if (!dx || !du || (id && !did)) return fail(c, FEPIC_E_OOM, "device allocation failed");
+    HIPCHK(c, hipMemcpyAsync(dx, x, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(du, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+    if (id) HIPCHK(c, hipMemcpyAsync(did, id, sizeof(int64_t) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_cnt, 0, sizeof(PushCounters), c->stream));
+    const double* g = c->d_grid;
+    if (c->opt.precision == FEPIC_ALL_FP64)
+        launch_locate<double>(c->stream, n, dx, du, did, s.next_id, parr<double>(s, s.cur), s.n, c->d_grad64, c->d_r0,
+                              c->d_cell_start, c->d_cell_tets, g, g + 3, c->d_grid_n, c->d_cnt);
+    else
+        launch_locate<float>(c->stream, n, dx, du, did, s.next_id, parr<float>(s, s.cur), s.n, c->d_grad64, c->d_r0,
+                             c->d_cell_start, c->d_cell_tets, g, g + 3, c->d_grid_n, c->d_cnt);
+    s.next_id += n;
+    s.n += n;
+    if (c->opt.precision == FEPIC_ALL_FP64) sort_species<double>(c, s);
+    else sort_species<float>(c, s);
+    HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(PushCounters), hipMemcpyDeviceToHost, c->stream));
+    if ((rc = sync_counts(c))) return rc;
+    HIPCHK(c, hipGetLastError());
+    dfree(c, dx);
+    dfree(c, du);
+    dfree(c, did);
+    if (n_rejected) *n_rejected = c->h_cnt->n_rejected;
+    c->rho_valid = false;
+    c->rG_levels = 0;
+    return FEPIC_OK;
+}
+
+int fepic_num_particles(fepic_ctx* c, int species, int64_t* n) {
+    NEED_DEV(c);
+    if (species < 0 || species >= (int)c->species.size() || !n) return FEPIC_E_ARG;
+    int rc = sync_counts(c);
+    if (rc) return rc;
+    // count live entries (dead ones stay until the next sort)
+    Species& s = c->species[species];
+    std::vector<int32_t> tet(s.n);
+    if (s.n) HIPCHK(c, hipMemcpy(tet.data(), s.buf[s.cur][0], sizeof(int32_t) * s.n, hipMemcpyDeviceToHost));
+    *n = std::count_if(tet.begin(), tet.end(), [](int32_t t) { return t >= 0; });
+    return FEPIC_OK;
+}
+
+int fepic_get_particles(fepic_ctx* c, int species, int64_t cap, int64_t* n, int64_t* id, double* x, double* u,
+                        int32_t* tet, double* lambda) {
+    NEED_DEV(c);
+    if (species < 0 || species >= (int)c->species.size() || !n) return FEPIC_E_ARG;
+    int rc = sync_counts(c);
+    if (rc) return rc;
+    Species& s = c->species[species];
+    const int64_t N = s.n;
+    std::vector<int32_t> ht(N);
+    std::vector<int64_t> hid(N);
+    std::vector<double> hv[6];
+    for (auto& v : hv) v.resize(N);
+    if (N) {
+        HIPCHK(c, hipMemcpy(ht.data(), s.buf[s.cur][0], 4 * N, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(hid.data(), s.buf[s.cur][7], 8 * N, hipMemcpyDeviceToHost));
+        for (int a = 1; a < 7; ++a) {
+            if (c->opt.precision == FEPIC_ALL_FP64) {
+                HIPCHK(c, hipMemcpy(hv[a - 1].data(), s.buf[s.cur][a], 8 * N, hipMemcpyDeviceToHost));
+            } else {
+                std::vector<float> f(N);
+                HIPCHK(c, hipMemcpy(f.data(), s.buf[s.cur][a], 4 * N, hipMemcpyDeviceToHost));
+                for (int64_t i = 0; i < N; ++i) hv[a - 1][i] = f[i];
+            }
+        }
+    }
+    const HostMesh& m = c->mesh;
+    int64_t k = 0;
+    for (int64_t i = 0; i < N && k < cap; ++i) {
+        const int t = ht[i];
+        if (t < 0) continue;
+        const double l[4] = {1.0 - hv[0][i] - hv[1][i] - hv[2][i], hv[0][i], hv[1][i], hv[2][i]};
+        if (id) id[k] = hid[i];
+        if (tet) tet[k] = t;
+        if (lambda)
+            for (int j = 0; j < 4; ++j) lambda[4 * k + j] = l[j];
+        if (u)
+            for (int d = 0; d < 3; ++d) u[3 * k + d] = hv[3 + d][i];
+        if (x)
+            for (int d = 0; d < 3; ++d) {
+                double v = 0.0;
+                for (int j = 0; j < 4; ++j) v += l[j] * m.xyz[3 * m.tets[4 * t + j] + d];
+                x[3 * k + d] = v;
+            }
+        ++k;
+    }
+    *n = k;
+    return FEPIC_OK;
+}
+
+int fepic_init_electrostatic(fepic_ctx* c, double tol, int* iters) { return fepic::init_electrostatic(c, tol, iters); }
+
+int fepic_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats* out) {
+    return do_step(c, dt, beta, gamma, out, true);
+}
+
+int fepic_push_particles(fepic_ctx* c, double dt, fepic_step_stats* out) { return do_step(c, dt, 0.25, 0.5, out, false); }
+
+int fepic_get_fields(fepic_ctx* c, double* e, double* e_prev, double* b) {
+    NEED_DEV(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (e) HIPCHK(c, hipMemcpy(e, c->d_e, 8 * c->mesh.n_edges, hipMemcpyDeviceToHost));
+    if (e_prev) HIPCHK(c, hipMemcpy(e_prev, c->d_ep, 8 * c->mesh.n_edges, hipMemcpyDeviceToHost));
+    if (b) HIPCHK(c, hipMemcpy(b, c->d_b, 8 * c->mesh.n_faces, hipMemcpyDeviceToHost));
+    return FEPIC_OK;
+}
+
+int fepic_get_current(fepic_ctx* c, double* dG, double* G) {
+    NEED_DEV(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (dG) HIPCHK(c, hipMemcpy(dG, c->d_dg, 8 * c->mesh.n_edges, hipMemcpyDeviceToHost));
+    if (G) HIPCHK(c, hipMemcpy(G, c->d_G, 8 * c->mesh.n_edges, hipMemcpyDeviceToHost));
+    return FEPIC_OK;
+}
+
+int fepic_get_rho(fepic_ctx* c, double* rho) {
+    NEED_DEV(c);
+    if (!rho) return FEPIC_E_ARG;
+    int rc = sync_counts(c);
+    if (rc) return rc;
+    compute_rho(c, c->d_n1);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(rho, c->d_n1, 8 * c->mesh.n_nodes, hipMemcpyDeviceToHost));
+    return FEPIC_OK;
+}
+
+int fepic_diagnostics(fepic_ctx* c, fepic_step_stats* out) {
+    NEED_DEV(c);
+    int rc = sync_counts(c);
+    if (rc) return rc;
+    fepic_step_stats st;
+    std::memset(&st, 0, sizeof(st));
+    const bool keep = c->rho_valid;
+    c->rho_valid = false;
+    rc = run_diagnostics(c, &st, false, false);
+    c->rho_valid = keep || c->rho_valid;
+    st.step = c->step_count;
+    st.t = c->time;
+    if (out) *out = st;
+    return rc;
+}
+
+int fepic_kernel_timing(fepic_ctx* c, const char* family, int enable) {
+    if (!c || !family) return FEPIC_E_ARG;
+    if (c->host_only) return fail(c, FEPIC_E_NO_DEVICE, "host-only context");
+    for (int f = 0; f < FAM_COUNT; ++f)
+        if (!std::strcmp(family, kFamilies[f])) {
+            KernelTimer& k = c->timers[f];
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            k.on = enable != 0;
+            k.used = 0;
+            // pre-create events so the timed region does not create them
+            while ((int64_t)k.ev.size() < 2 * (int64_t)std::max(enable, 0)) {
+                hipEvent_t e;
+                HIPCHK(c, hipEventCreate(&e));
+                k.ev.push_back(e);
+            }
+            return FEPIC_OK;
+        }
+    return fail(c, FEPIC_E_ARG, std::string("unknown kernel family ") + family);
+}
+
+int fepic_kernel_time(fepic_ctx* c, const char* family, double* total_ms, int64_t* launches) {
+    if (!c || !family) return FEPIC_E_ARG;
+    if (c->host_only) return fail(c, FEPIC_E_NO_DEVICE, "host-only context");
+    for (int f = 0; f < FAM_COUNT; ++f)
+        if (!std::strcmp(family, kFamilies[f])) {
+            KernelTimer& k = c->timers[f];
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            double tot = 0.0;
+            for (int64_t i = 0; i + 1 < k.used; i += 2) {
+                float ms = 0.f;
+                HIPCHK(c, hipEventElapsedTime(&ms, k.ev[i], k.ev[i + 1]));
+                tot += ms;
+            }
+            if (total_ms) *total_ms = tot;
+            if (launches) *launches = k.used / 2;
+            return FEPIC_OK;
+        }
+    return fail(c, FEPIC_E_ARG, std::string("unknown kernel family ") + family);
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// The libfepic context: host mesh, device state and bookkeeping shared by the API files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "fepic_internal.h"
+#include "host_mesh.h"
+
+namespace fepic {
+
+enum { FAM_PUSH, FAM_STAGE, FAM_SORT, FAM_RHS, FAM_CG_SPMV, FAM_CG_UPDATE, FAM_FARADAY, FAM_MLP_FWD, FAM_COUNT };
+extern const char* kFamilies[];
+
+struct KernelTimer {
+    bool on = false;
+    int64_t used = 0;
+    std::vector<hipEvent_t> ev;
+};
+
+struct Species {
+    double q = 0, m = 1, w = 1;
+    int64_t n = 0;        // slots in use in buffer cur (dead entries have tet -1)
+    int64_t cap = 0;
+    int cur = 0;
+    int64_t next_id = 0;  // default ids
+    void* buf[2][8] = {}; // tet, l1, l2, l3, u0, u1, u2, id
+    int32_t* d_nlive = nullptr;
+    int32_t* h_nlive = nullptr;
+    bool sorted_pending = false;  // d_nlive holds a count not yet read back
+};
+
+struct MlpState;
+
+}  // namespace fepic
+
+struct fepic_ctx {
+    fepic_options opt{};
+    std::string err;
+    bool host_only = false;
+    hipStream_t stream = nullptr, own_stream = nullptr;
+    std::vector<void*> allocs;
+
+    fepic::HostMesh mesh;
+    bool have_mesh = false;
+
+    // device mesh
+    int32_t *d_tets = nullptr, *d_edges = nullptr, *d_tet_edges = nullptr, *d_tet_faces = nullptr,
+            *d_face_edges = nullptr, *d_int_edges = nullptr;
+    uint8_t *d_bedge = nullptr, *d_inode = nullptr;
+    double *d_grad64 = nullptr, *d_r0 = nullptr;
+    void* d_blk = nullptr;
+    int64_t* d_sp = nullptr;
+    int32_t* d_col = nullptr;
+    double *d_M = nullptr, *d_S = nullptr, *d_A = nullptr, *d_dinv = nullptr;
+    int32_t *d_cell_start = nullptr, *d_cell_tets = nullptr, *d_grid_n = nullptr;
+    double* d_grid = nullptr;  // lo[3], inv_h[3]
+    double A_scale = -1.0;
+    bool A_valid = false;
+
+    // fields (edge vectors length n_edges, face vectors length n_faces)
+    double *d_e = nullptr, *d_ep = nullptr, *d_ep2 = nullptr, *d_x = nullptr;
+    double *d_dg = nullptr, *d_dgn = nullptr, *d_G = nullptr;
+    double *d_b = nullptr, *d_bn = nullptr;
+    double *d_rhs = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p[2] = {nullptr, nullptr}, *d_q = nullptr,
+           *d_rt = nullptr, *d_Me = nullptr;
+    double* d_partial = nullptr;
+    fepic::CgScalars* d_sc = nullptr;
+    fepic::CgScalars* h_sc = nullptr;
+    fepic::PushCounters* d_cnt = nullptr;
+    fepic::PushCounters* h_cnt = nullptr;
+    int deferred_err = 0;
+
+    // sort scratch
+    int32_t *d_count = nullptr, *d_offset = nullptr, *d_bsums = nullptr;
+
+    // diagnostics
+    double *d_rho = nullptr, *d_rho_new = nullptr, *d_n1 = nullptr, *d_n2 = nullptr, *d_n3 = nullptr;
+    double* d_rG[3] = {nullptr, nullptr, nullptr};
+    int rG_head = 0, rG_levels = 0;
+    bool rho_valid = false;
+    fepic::DiagAcc* d_acc = nullptr;
+    fepic::DiagAcc* h_acc = nullptr;
+    unsigned int* d_dotc = nullptr;
+
+    std::vector<fepic::Species> species;
+    int64_t step_count = 0;
+    double time = 0.0;
+
+    fepic::KernelTimer timers[fepic::FAM_COUNT];
+    hipEvent_t phase_ev[9] = {};
+
+    // learned warm start
+    fepic::MlpState* mlp = nullptr;
+    bool mlp_ready = false;
+    bool recording = false;
+    int64_t mlp_fallbacks = 0;
+};
+
+namespace fepic {
+int hip_fail(fepic_ctx* c, hipError_t e, const char* what);
+int fail(fepic_ctx* c, int code, const std::string& msg);
+void* dmalloc(fepic_ctx* c, size_t bytes);
+void dfree(fepic_ctx* c, void* p);
+hipEvent_t* timer_pair(fepic_ctx* c, int fam);
+
+int init_electrostatic(fepic_ctx* c, double tol, int* iters);
+int mlp_warm_start(fepic_ctx* c);
+int mlp_record_features(fepic_ctx* c);
+int mlp_record_target(fepic_ctx* c);
+void mlp_destroy(fepic_ctx* c);
+}  // namespace fepic

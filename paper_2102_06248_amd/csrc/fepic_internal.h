@@ -1,0 +1,169 @@
+// Internal declarations shared by the host side and the HIP kernels of libfepic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fepic.h"
+
+namespace fepic {
+
+// SI constants (CODATA 2018).
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kMu0 = 1.25663706212e-6;
+constexpr double kC = 299792458.0;
+
+// Sliced-ELLPACK slice height: one 64-lane wavefront per slice of 64 consecutive rows,
+// each of the slice's columns stored contiguously so a wave's loads coalesce.
+constexpr int kSell = 64;
+
+// Per-tet record read by the particle kernel: the staged field (edge DoFs, constant B)
+// and the static geometry/topology, padded to a whole number of 64-byte lines.
+template <typename T>
+struct TetBlock {
+    T e[6];           // edge unknowns of local edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)
+    T B[3];           // B inside the tet (Whitney-2 field of a div-free flux is constant)
+    T gl[9];          // grad lambda_1..3 (grad lambda_0 = -sum)
+    int32_t nbr[4];   // (neighbour tet << 2) | neighbour's local index of its far vertex;
+                      // -1 = wall
+    int32_t edge[6];  // global edge ids of the 6 local edges
+    int32_t pad[sizeof(T) == 4 ? 4 : 2];
+};
+static_assert(sizeof(TetBlock<float>) == 128, "TetBlock<float> layout");
+static_assert(sizeof(TetBlock<double>) == 192, "TetBlock<double> layout");
+
+// Structure-of-arrays particle storage for one species (one buffer of a double buffer).
+template <typename T>
+struct PArrays {
+    int32_t* tet;     // -1 = dead (absorbed or rejected)
+    T* l1;
+    T* l2;
+    T* l3;            // barycentric coordinates 1..3 in the sorted tet (lambda_0 = 1 - sum)
+    T* u0;
+    T* u1;
+    T* u2;            // gamma v
+    int64_t* id;
+};
+
+struct PushParams {
+    double dt;
+    double qm_half_dt;   // q dt / (2 m)
+    double qw;           // q w (deposit scale)
+    int cap;             // crossing cap
+};
+
+struct PushCounters {
+    unsigned long long n_crossings;
+    unsigned int max_crossings;
+    unsigned int n_absorbed;
+    unsigned int n_cap;
+    unsigned int n_rejected;
+    unsigned int pad[2];
+};
+
+// Scalars of the PCG recurrence, kept on the device between kernels.
+struct CgScalars {
+    double bb;        // ||b||^2
+    double rz;        // r . z of the current iterate
+    double pq;        // p . q
+    double rr;        // r . r
+    double alpha, beta;
+    double rr0;       // ||b - A x0||^2
+    double rr_true;   // ||b - A x||^2 at exit
+    double tol2_bb;   // tol^2 ||b||^2
+    int converged;
+    int iters;
+    unsigned int counter[4];  // last-block-done tickets (one per reducing kernel kind)
+};
+
+// Device-side diagnostics accumulators (max-abs values stored as ordered bit patterns).
+struct DiagAcc {
+    unsigned long long cont_max, gauss_max, drift_max, rho_max, divb_max;
+    double energy;
+    unsigned int counter;
+    unsigned int pad;
+};
+
+struct SellMatrix {
+    int64_t n_rows = 0;
+    int64_t n_slices = 0;
+    std::vector<int64_t> slice_ptr;  // [n_slices + 1], element offsets
+    std::vector<int32_t> col;        // padded entries point at the row itself, value 0
+    std::vector<double> M, S;        // edge mass and curl-curl values
+};
+
+// ----------------------------------------------------------------------------- launchers
+// Particle kernels (kernels_particles.hip).
+template <typename T>
+void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double* e, const double* b,
+                  const double* grad64, const int32_t* tet_edges, const int32_t* tet_faces);
+template <typename T>
+void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const TetBlock<T>* blk, double* dg,
+                 PushParams pp, PushCounters* cnt, const int32_t* n_live);
+template <typename T>
+void launch_locate(hipStream_t s, int64_t n, const double* x, const double* u, const int64_t* id, int64_t id_base,
+                   PArrays<T> out, int64_t out_off, const double* grad64, const double* r0, const int32_t* cell_start,
+                   const int32_t* cell_tets, const double* grid_lo, const double* grid_inv_h, const int32_t* grid_n,
+                   PushCounters* cnt);
+template <typename T>
+void launch_sort(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, int64_t n_tets, int32_t* count,
+                 int32_t* offset, int32_t* block_sums, int32_t* n_live_dev);
+template <typename T>
+void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, double qw, double* rho);
+
+// Field kernels (kernels_fields.hip).
+void launch_fill(hipStream_t s, double* x, int64_t n, double v);
+void launch_axpby(hipStream_t s, double* y, const double* a, double alpha, const double* b, double beta, int64_t n);
+void launch_scale_A(hipStream_t s, const SellMatrix& shape, const int64_t* slice_ptr, const int32_t* col,
+                    const double* M, const double* S, double* A, double* dinv, const uint8_t* bmask, double c);
+void launch_sell_spmv(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
+                      const double* val, const double* x, double* y);
+void launch_rhs(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* M,
+                const double* S, const double* e, const double* ep, const double* dg_new, const double* dg_old,
+                const uint8_t* bmask, double dt2, double c1, double c2, double* b, double* partial,
+                CgScalars* sc, double tol);
+void launch_warm(hipStream_t s, int mode, int64_t n, const double* e, const double* ep, const double* ep2, double* x);
+void launch_cg_init(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* A,
+                    const double* dinv, const double* b, const double* x, double* r, double* z, double* p,
+                    double* partial, CgScalars* sc);
+void launch_cg_iter(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* A,
+                    const double* dinv, double* x, double* r, double* z, const double* p_old, double* p_new,
+                    double* q, double* partial, CgScalars* sc, hipEvent_t* ev_spmv, hipEvent_t* ev_upd);
+void launch_cg_resid(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
+                     const double* A, const double* b, double* x, double* r_true, double* partial,
+                     CgScalars* sc);
+void launch_faraday(hipStream_t s, int64_t n_faces, const int32_t* face_edges, const double* b_old,
+                    const double* e_new, const double* e_old, double dt, double gamma, double* b_new);
+void launch_DT(hipStream_t s, int64_t n_edges, const int32_t* edges, const double* v, double* out_nodes);
+void launch_diag_nodes(hipStream_t s, int64_t n_nodes, const uint8_t* interior_node, const double* rho_new,
+                       const double* rho_old, const double* dtdg, const double* dtMe, const double* rG1,
+                       const double* rG2, const double* dtrcg, int have_hist, double* rG_out, DiagAcc* acc);
+void launch_divb(hipStream_t s, int64_t n_tets, const int32_t* tet_faces, const double* b, DiagAcc* acc);
+void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial, double* out,
+                unsigned int* counter);
+
+// Learned warm start (kernels_mlp.hip).
+struct MlpDevice;
+void mlp_launch_features(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e,
+                         const double* ep, const double* ep2, const double* dg, const double* scales,
+                         float* X);
+void mlp_launch_rms(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e, const double* dg,
+                    double* partial, double* scales, unsigned int* counter);
+void mlp_launch_forward(hipStream_t s, int64_t n, const float* X, const float* params_f32, float* y);
+void mlp_launch_apply(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e, const float* y,
+                      const double* scales, double* x);
+void mlp_launch_grad(hipStream_t s, int64_t n, const float* X, const float* target, const float* params_f32,
+                     float* grad, double* loss_acc);
+void mlp_launch_adam(hipStream_t s, int64_t n, float* params, const float* grad, float* m, float* v, float lr,
+                     float b1, float b2, float eps, float bc1, float bc2);
+void mlp_launch_target(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e_new,
+                       const double* e, const double* scales, float* t);
+void mlp_launch_gather_rows(hipStream_t s, int64_t n, const int64_t* rows, const float* Xall, const float* Tall,
+                            float* X, float* T);
+
+int grid_1d(int64_t n, int block);
+
+}  // namespace fepic

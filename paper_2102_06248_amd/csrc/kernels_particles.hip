@@ -1,0 +1,528 @@
+// Particle-side kernels for gfx950: per-tet field staging, the fused particle step
+// (gather -> relativistic Boris -> straight-path tracking -> Whitney-1 deposit), point
+// location, counting sort by tet, nodal charge.
+//
+// Wave64 throughout; particles are kept sorted by tet so that lanes of a wave read the
+// same 128-byte tet record and the current of their first path piece can be summed
+// across the wave before the FP64 atomics.
+#include "fepic_internal.h"
+
+namespace fepic {
+
+int grid_1d(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int LE_A[6] = {0, 0, 0, 1, 1, 2};
+constexpr int LE_B[6] = {1, 2, 3, 2, 3, 3};
+
+template <typename T>
+__device__ __forceinline__ T tsqrt(T x);
+template <>
+__device__ __forceinline__ float tsqrt<float>(float x) { return __builtin_sqrtf(x); }
+template <>
+__device__ __forceinline__ double tsqrt<double>(double x) { return __builtin_sqrt(x); }
+
+__device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// ------------------------------------------------------------------------- staging
+// B in a tet from its four face fluxes: sum_k b_k W2_k evaluated at the centroid
+// (lambda = 1/4), i.e. sum_k b_k * 1/2 (g_j x g_l + g_l x g_i + g_i x g_j) for face
+// k = (i,j,l).  For a divergence-free flux the Whitney-2 field is constant in the tet.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_stage(int64_t n_tets, TetBlock<T>* __restrict__ blk,
+                                                   const double* __restrict__ e, const double* __restrict__ b,
+                                                   const double* __restrict__ grad64,
+                                                   const int32_t* __restrict__ tet_edges,
+                                                   const int32_t* __restrict__ tet_faces) {
+    int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_tets) return;
+    TetBlock<T>* B = blk + t;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) B->e[i] = (T)e[tet_edges[6 * t + i]];
+    double g[4][3];
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[k][d] = grad64[9 * t + 3 * (k - 1) + d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+    constexpr int F[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    double Bv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double* gi = g[F[k][0]];
+        const double* gj = g[F[k][1]];
+        const double* gl = g[F[k][2]];
+        double bf = 0.5 * b[tet_faces[4 * t + k]];
+        Bv[0] += bf * ((gj[1] * gl[2] - gj[2] * gl[1]) + (gl[1] * gi[2] - gl[2] * gi[1]) + (gi[1] * gj[2] - gi[2] * gj[1]));
+        Bv[1] += bf * ((gj[2] * gl[0] - gj[0] * gl[2]) + (gl[2] * gi[0] - gl[0] * gi[2]) + (gi[2] * gj[0] - gi[0] * gj[2]));
+        Bv[2] += bf * ((gj[0] * gl[1] - gj[1] * gl[0]) + (gl[0] * gi[1] - gl[1] * gi[0]) + (gi[0] * gj[1] - gi[1] * gj[0]));
+    }
+    B->B[0] = (T)Bv[0];
+    B->B[1] = (T)Bv[1];
+    B->B[2] = (T)Bv[2];
+}
+
+// ------------------------------------------------------------------------- particle step
+template <typename T>
+__device__ __forceinline__ void load_grads(const TetBlock<T>* bp, T g[4][3]) {
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[k][d] = bp->gl[3 * (k - 1) + d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+}
+
+// Whitney-1 path integral of one straight piece from barycentric point s to e inside a
+// tet: for edge (a,b), int (lambda_a d lambda_b - lambda_b d lambda_a) = s_a e_b - e_a s_b
+// (the integrand is constant along a line).
+__device__ __forceinline__ void piece_current(double qw, const double s[4], const double e[4], double out[6]) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) out[i] = qw * (s[LE_A[i]] * e[LE_B[i]] - e[LE_A[i]] * s[LE_B[i]]);
+}
+
+__device__ __forceinline__ double pick4(int idx, const double v[4]) {
+    double r = v[3];
+    r = (idx == 2) ? v[2] : r;
+    r = (idx == 1) ? v[1] : r;
+    r = (idx == 0) ? v[0] : r;
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, int64_t n,
+                                                  const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
+                                                  PushParams pp, PushCounters* __restrict__ cnt,
+                                                  const int32_t* __restrict__ n_live) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    if (n_live) n = min(n, (int64_t)*n_live);
+    int t0 = -1;
+    if (i < n) t0 = in.tet[i];
+    double first[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    unsigned int ncross = 0;
+    int status = 0;
+    if (t0 >= 0) {
+        const TetBlock<T>* bp = blk + t0;
+        const T l1 = in.l1[i], l2 = in.l2[i], l3 = in.l3[i];
+        T u[3] = {in.u0[i], in.u1[i], in.u2[i]};
+        T g[4][3];
+        load_grads(bp, g);
+        // gather: E = sum over edges e_ab (lambda_a grad l_b - lambda_b grad l_a)
+        const T lam[4] = {T(1) - l1 - l2 - l3, l1, l2, l3};
+        T E[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const T ek = bp->e[k];
+            const int a = LE_A[k], b = LE_B[k];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) E[d] += ek * (lam[a] * g[b][d] - lam[b] * g[a][d]);
+        }
+        const T Bv[3] = {bp->B[0], bp->B[1], bp->B[2]};
+        // relativistic Boris: half kick, rotation, half kick
+        const T h = (T)pp.qm_half_dt;
+        const T ic2 = (T)(1.0 / (kC * kC));
+        T um[3] = {u[0] + h * E[0], u[1] + h * E[1], u[2] + h * E[2]};
+        const T gm = tsqrt<T>(T(1) + (um[0] * um[0] + um[1] * um[1] + um[2] * um[2]) * ic2);
+        const T hg = h / gm;
+        const T tv[3] = {hg * Bv[0], hg * Bv[1], hg * Bv[2]};
+        const T s2 = T(2) / (T(1) + tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
+        const T up[3] = {um[0] + (um[1] * tv[2] - um[2] * tv[1]), um[1] + (um[2] * tv[0] - um[0] * tv[2]),
+                         um[2] + (um[0] * tv[1] - um[1] * tv[0])};
+        u[0] = um[0] + s2 * (up[1] * tv[2] - up[2] * tv[1]) + h * E[0];
+        u[1] = um[1] + s2 * (up[2] * tv[0] - up[0] * tv[2]) + h * E[1];
+        u[2] = um[2] + s2 * (up[0] * tv[1] - up[1] * tv[0]) + h * E[2];
+        const T ginv = T(1) / tsqrt<T>(T(1) + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic2);
+        const T dtt = (T)pp.dt;
+        const T dx[3] = {dtt * u[0] * ginv, dtt * u[1] * ginv, dtt * u[2] * ginv};
+
+        // path in barycentric coordinates of the current tet; exit points kept in FP64
+        double ls[4] = {1.0 - (double)l1 - (double)l2 - (double)l3, (double)l1, (double)l2, (double)l3};
+        double dl[4];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) dl[k] = (double)(g[k][0] * dx[0] + g[k][1] * dx[1] + g[k][2] * dx[2]);
+        dl[0] = -(dl[1] + dl[2] + dl[3]);
+        int t = t0, entry = -1;
+        double frac = 1.0;
+        for (int seg = 0;; ++seg) {
+            double best = 1.0;
+            int kb = -1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k != entry && dl[k] < 0.0) {
+                    const double tk = ls[k] / (-dl[k]);
+                    if (tk < best) {
+                        best = tk;
+                        kb = k;
+                    }
+                }
+            }
+            double le[4];
+            double cur[6];
+            if (kb < 0) {
+                // the rest of the path stays in t: store the end point rounded to storage
+                // precision and deposit up to exactly that stored point
+                const T r1 = (T)fmax(ls[1] + dl[1], 0.0);
+                const T r2 = (T)fmax(ls[2] + dl[2], 0.0);
+                const T r3 = (T)fmax(ls[3] + dl[3], 0.0);
+                le[1] = (double)r1;
+                le[2] = (double)r2;
+                le[3] = (double)r3;
+                le[0] = 1.0 - le[1] - le[2] - le[3];
+                piece_current(pp.qw, ls, le, cur);
+                if (seg == 0) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) first[c] = cur[c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) atomic_add_f64(dg + bp->edge[c], cur[c]);
+                }
+                out.tet[i] = t;
+                out.l1[i] = r1;
+                out.l2[i] = r2;
+                out.l3[i] = r3;
+                out.u0[i] = u[0];
+                out.u1[i] = u[1];
+                out.u2[i] = u[2];
+                out.id[i] = in.id[i];
+                break;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) le[k] = (k == kb) ? 0.0 : ls[k] + best * dl[k];
+            piece_current(pp.qw, ls, le, cur);
+            if (seg == 0) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) first[c] = cur[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) atomic_add_f64(dg + bp->edge[c], cur[c]);
+            }
+            const int nb = bp->nbr[kb];
+            if (nb < 0) {  // wall: absorbed after depositing up to it
+                status = 1;
+                out.tet[i] = -1;
+                break;
+            }
+            if (++ncross > (unsigned)pp.cap) {
+                status = 2;
+                out.tet[i] = -1;
+                break;
+            }
+            const int tn = nb >> 2, q = nb & 3;
+            // shared vertices keep their relative order (both tets are sorted by node id):
+            // new local k != q takes old local index r + (r >= kb), r = k - (k > q)
+            double ln[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int r = k - (k > q ? 1 : 0);
+                ln[k] = (k == q) ? 0.0 : pick4(r + (r >= kb ? 1 : 0), le);
+            }
+            frac *= (1.0 - best);
+            t = tn;
+            bp = blk + tn;
+            load_grads(bp, g);
+#pragma unroll
+            for (int k = 1; k < 4; ++k)
+                dl[k] = frac * (double)(g[k][0] * dx[0] + g[k][1] * dx[1] + g[k][2] * dx[2]);
+            dl[0] = -(dl[1] + dl[2] + dl[3]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ls[k] = ln[k];
+            entry = q;
+        }
+    } else if (i < n) {
+        out.tet[i] = -1;
+    }
+
+    // Sum the first-piece currents of lanes that share a start tet (runs of equal keys
+    // in the sorted order) with a segmented scan across the wave; the last lane of each
+    // run issues the six FP64 atomics for the whole run.
+    const int key = t0;
+    const int prev_key = __shfl_up(key, 1);
+    int f = (lane == 0) || (key != prev_key);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        double o[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] = __shfl_up(first[c], off);
+        const int fo = __shfl_up(f, off);
+        if (lane >= off) {
+            if (!f) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) first[c] += o[c];
+            }
+            f |= fo;
+        }
+    }
+    const int next_key = __shfl_down(key, 1);
+    if (key >= 0 && (lane == 63 || next_key != key)) {
+        const TetBlock<T>* bk = blk + key;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) atomic_add_f64(dg + bk->edge[c], first[c]);
+    }
+
+    // per-wave counters
+    unsigned int sc = ncross, mc = ncross, na = (status == 1), ncap = (status == 2);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sc += __shfl_xor(sc, off);
+        mc = max(mc, (unsigned int)__shfl_xor(mc, off));
+        na += __shfl_xor(na, off);
+        ncap += __shfl_xor(ncap, off);
+    }
+    if (lane == 0) {
+        if (sc) atomicAdd(&cnt->n_crossings, (unsigned long long)sc);
+        if (mc) atomicMax(&cnt->max_crossings, mc);
+        if (na) atomicAdd(&cnt->n_absorbed, na);
+        if (ncap) atomicAdd(&cnt->n_cap, ncap);
+    }
+}
+
+// ------------------------------------------------------------------------- locate
+// Point location through a uniform bucket grid: the tet among the bucket's candidates
+// whose smallest barycentric coordinate is largest, accepted if >= -1e-12.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_locate(int64_t n, const double* __restrict__ x,
+                                                    const double* __restrict__ u, const int64_t* __restrict__ id,
+                                                    int64_t id_base, PArrays<T> out, int64_t out_off,
+                                                    const double* __restrict__ grad64, const double* __restrict__ r0,
+                                                    const int32_t* __restrict__ cell_start,
+                                                    const int32_t* __restrict__ cell_tets,
+                                                    const double* __restrict__ lo, const double* __restrict__ inv_h,
+                                                    const int32_t* __restrict__ gn, PushCounters* cnt) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double px = x[3 * i], py = x[3 * i + 1], pz = x[3 * i + 2];
+    const double ux = u[3 * i], uy = u[3 * i + 1], uz = u[3 * i + 2];
+    int best_t = -1;
+    double best_s = -1e300, bl[3] = {0.0, 0.0, 0.0};
+    const bool finite = isfinite(px) && isfinite(py) && isfinite(pz) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+    if (finite) {
+        int c[3];
+        const double p[3] = {px, py, pz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double f = (p[d] - lo[d]) * inv_h[d];
+            int ci = (int)floor(f);
+            c[d] = ci < 0 ? 0 : (ci >= gn[d] ? gn[d] - 1 : ci);
+        }
+        const int cell = c[0] + gn[0] * (c[1] + gn[1] * c[2]);
+        for (int j = cell_start[cell]; j < cell_start[cell + 1]; ++j) {
+            const int t = cell_tets[j];
+            const double* g = grad64 + 9 * t;
+            const double dxv = px - r0[3 * t], dyv = py - r0[3 * t + 1], dzv = pz - r0[3 * t + 2];
+            const double a1 = g[0] * dxv + g[1] * dyv + g[2] * dzv;
+            const double a2 = g[3] * dxv + g[4] * dyv + g[5] * dzv;
+            const double a3 = g[6] * dxv + g[7] * dyv + g[8] * dzv;
+            const double a0 = 1.0 - a1 - a2 - a3;
+            const double s = fmin(fmin(a0, a1), fmin(a2, a3));
+            if (s > best_s) {
+                best_s = s;
+                best_t = t;
+                bl[0] = a1;
+                bl[1] = a2;
+                bl[2] = a3;
+            }
+        }
+    }
+    const int64_t o = out_off + i;
+    if (best_t < 0 || best_s < -1e-12) {
+        out.tet[o] = -1;
+        atomicAdd(&cnt->n_rejected, 1u);
+        return;
+    }
+    out.tet[o] = best_t;
+    out.l1[o] = (T)fmax(bl[0], 0.0);
+    out.l2[o] = (T)fmax(bl[1], 0.0);
+    out.l3[o] = (T)fmax(bl[2], 0.0);
+    out.u0[o] = (T)ux;
+    out.u1[o] = (T)uy;
+    out.u2[o] = (T)uz;
+    out.id[o] = id ? id[i] : id_base + i;
+}
+
+// ------------------------------------------------------------------------- counting sort
+__global__ __launch_bounds__(kBlock) void k_zero_i32(int32_t* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hist(const int32_t* __restrict__ tet, int64_t n, int32_t* count) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int t = tet[i];
+    if (t >= 0) atomicAdd(count + t, 1);
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads = 4 waves).
+__device__ __forceinline__ int block_excl_scan(int v, int* s_w, int& total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    int base = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) base += (k < w) ? s_w[k] : 0;
+    total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    __syncthreads();
+    return x - v + base;
+}
+
+constexpr int kScanItems = 4;  // per thread; 1024 per block
+
+__global__ __launch_bounds__(kBlock) void k_scan_blocks(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                         int64_t n, int32_t* __restrict__ block_sums) {
+    __shared__ int s_w[4];
+    const int64_t base = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kScanItems;
+    int v[kScanItems];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        sum += v[k];
+    }
+    int total;
+    int run = block_excl_scan(sum, s_w, total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the block sums in place; total -> *n_total.
+__global__ __launch_bounds__(kBlock) void k_scan_top(int32_t* block_sums, int64_t nb, int32_t* n_total) {
+    __shared__ int s_w[4];
+    const int64_t per = (nb + kBlock - 1) / kBlock;
+    const int64_t b0 = threadIdx.x * per;
+    int sum = 0;
+    for (int64_t k = 0; k < per; ++k)
+        if (b0 + k < nb) sum += block_sums[b0 + k];
+    int total;
+    int run = block_excl_scan(sum, s_w, total);
+    for (int64_t k = 0; k < per; ++k) {
+        if (b0 + k < nb) {
+            const int v = block_sums[b0 + k];
+            block_sums[b0 + k] = run;
+            run += v;
+        }
+    }
+    if (threadIdx.x == 0) *n_total = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(int32_t* __restrict__ out, int64_t n,
+                                                      const int32_t* __restrict__ block_sums) {
+    const int64_t base = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kScanItems;
+    const int add = block_sums[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) out[base + k] += add;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scatter(PArrays<T> in, PArrays<T> out, int64_t n,
+                                                     int32_t* __restrict__ offset) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int t = in.tet[i];
+    if (t < 0) return;
+    const int pos = atomicAdd(offset + t, 1);
+    out.tet[pos] = t;
+    out.l1[pos] = in.l1[i];
+    out.l2[pos] = in.l2[i];
+    out.l3[pos] = in.l3[i];
+    out.u0[pos] = in.u0[i];
+    out.u1[pos] = in.u1[i];
+    out.u2[pos] = in.u2[i];
+    out.id[pos] = in.id[i];
+}
+
+// ------------------------------------------------------------------------- charge
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rho(PArrays<T> p, int64_t n, const int32_t* __restrict__ tets,
+                                                 double qw, double* __restrict__ rho) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int t = p.tet[i];
+    if (t < 0) return;
+    const double l1 = (double)p.l1[i], l2 = (double)p.l2[i], l3 = (double)p.l3[i];
+    const double l0 = 1.0 - l1 - l2 - l3;
+    atomic_add_f64(rho + tets[4 * t + 0], qw * l0);
+    atomic_add_f64(rho + tets[4 * t + 1], qw * l1);
+    atomic_add_f64(rho + tets[4 * t + 2], qw * l2);
+    atomic_add_f64(rho + tets[4 * t + 3], qw * l3);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------- launchers
+template <typename T>
+void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double* e, const double* b,
+                  const double* grad64, const int32_t* tet_edges, const int32_t* tet_faces) {
+    if (n_tets <= 0) return;
+    hipLaunchKernelGGL(k_stage<T>, dim3(grid_1d(n_tets, kBlock)), dim3(kBlock), 0, s, n_tets, blk, e, b, grad64,
+                       tet_edges, tet_faces);
+}
+
+template <typename T>
+void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const TetBlock<T>* blk, double* dg,
+                 PushParams pp, PushCounters* cnt, const int32_t* n_live) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_push<T>, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live);
+}
+
+template <typename T>
+void launch_locate(hipStream_t s, int64_t n, const double* x, const double* u, const int64_t* id, int64_t id_base,
+                   PArrays<T> out, int64_t out_off, const double* grad64, const double* r0, const int32_t* cell_start,
+                   const int32_t* cell_tets, const double* grid_lo, const double* grid_inv_h, const int32_t* grid_n,
+                   PushCounters* cnt) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_locate<T>, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, n, x, u, id, id_base, out,
+                       out_off, grad64, r0, cell_start, cell_tets, grid_lo, grid_inv_h, grid_n, cnt);
+}
+
+template <typename T>
+void launch_sort(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, int64_t n_tets, int32_t* count,
+                 int32_t* offset, int32_t* block_sums, int32_t* n_live_dev) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_1d(n_tets, kBlock)), dim3(kBlock), 0, s, count, n_tets);
+    if (n > 0)
+        hipLaunchKernelGGL(k_hist, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, in.tet, n, count);
+    const int64_t per_block = (int64_t)kBlock * kScanItems;
+    const int64_t nb = (n_tets + per_block - 1) / per_block;
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kBlock), 0, s, count, offset, n_tets, block_sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, block_sums, nb, n_live_dev);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, s, offset, n_tets, block_sums);
+    if (n > 0)
+        hipLaunchKernelGGL(k_scatter<T>, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, in, out, n, offset);
+}
+
+template <typename T>
+void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, double qw, double* rho) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_rho<T>, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, p, n, tets, qw, rho);
+}
+
+#define FEPIC_INSTANTIATE(T)                                                                                      \
+    template void launch_stage<T>(hipStream_t, int64_t, TetBlock<T>*, const double*, const double*,             \
+                                  const double*, const int32_t*, const int32_t*);                                \
+    template void launch_push<T>(hipStream_t, PArrays<T>, PArrays<T>, int64_t, const TetBlock<T>*, double*,      \
+                                 PushParams, PushCounters*, const int32_t*);                                     \
+    template void launch_locate<T>(hipStream_t, int64_t, const double*, const double*, const int64_t*, int64_t,  \
+                                   PArrays<T>, int64_t, const double*, const double*, const int32_t*,            \
+                                   const int32_t*, const double*, const double*, const int32_t*, PushCounters*); \
+    template void launch_sort<T>(hipStream_t, PArrays<T>, PArrays<T>, int64_t, int64_t, int32_t*, int32_t*,      \
+                                 int32_t*, int32_t*);                                                            \
+    template void launch_rho<T>(hipStream_t, PArrays<T>, int64_t, const int32_t*, double, double*);
+
+FEPIC_INSTANTIATE(float)
+FEPIC_INSTANTIATE(double)
+
+}  // namespace fepic

@@ -1,0 +1,294 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the same
+seeded inputs.  Tolerances (from the precision each mode computes in):
+
+* ALL_FP64: positions and momenta to 1e-10 relative; deposits to 1e-10 of their max.
+* FP32 push / FP64 deposit: positions within 1e-5 of the element size (FP32 barycentric
+  storage is ~6e-8 h); momenta 1e-5 relative; deposits within 1e-5 of their max (FP32
+  displacement, ~1e-7, accumulated over a step's crossings).
+* Fields after a Newmark step: 1e-6 relative (both solves stop at ||r|| <= 1e-10 ||b||;
+  the FP32 push perturbs the source at ~1e-7).
+* Charge continuity from the library's own diagnostics: 1e-12 relative, every step.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import (announce, compare_particles, divfree_fields, have_gpu, jittered_kuhn, require_lib)
+from oracle.constants import C_LIGHT, M_E, Q_E
+from oracle.pic import OracleSim
+from paper_2102_06248_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not have_gpu():
+        pytest.fail("GPU tests need an MI355X")
+    return require_lib()
+
+
+def _lib_sim(F, xyz, tets, **opts):
+    return F.Simulation(xyz, tets, **opts)
+
+
+# ----------------------------------------------------------------------------- one push
+@pytest.mark.parametrize("precision,n", [(1, 4099), (0, 4099), (0, 70001)])
+def test_particle_step_vs_oracle(F, precision, n):
+    announce(f"particle step precision={precision} n={n}")
+    xyz, tets, h = jittered_kuhn(6)
+    osim = OracleSim(xyz, tets)
+    e, b = divfree_fields(osim, 50.0, 1e-4, [0.0, 0.0, 0.002], seed=1)
+    x, u = inputs.uniform_box_particles(n, [0.02] * 3, [0.98] * 3, 3e6, seed=2)
+    qw = -Q_E * 1e3
+    s = osim.add_species(-Q_E, M_E, 1e3)
+    assert osim.upload_particles(s, x, u, ids=np.arange(n)) == 0
+    osim.e, osim.b = e.copy(), b.copy()
+    dt = 2e-8
+    with _lib_sim(F, xyz, tets, precision=precision) as L:
+        F.fepic_set_fields(L.ctx, e=e, e_prev=e, b=b)
+        sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 1e3)
+        assert F.fepic_upload_particles(L.ctx, sp, x, u, ids=np.arange(n)) == 0
+        g0 = F.fepic_get_particles(L.ctx, sp)
+        # upload locates every particle in the same tet as the oracle
+        o0 = osim.particles(s)
+        oi = np.argsort(o0["id"])
+        gi = np.argsort(g0["id"])
+        assert np.array_equal(g0["tet"][gi], o0["tet"][oi])
+        st = F.fepic_push_particles(L.ctx, dt)
+        gp = F.fepic_get_particles(L.ctx, sp)
+        dg_gpu, _ = F.fepic_get_current(L.ctx)
+    ost = osim.step(dt, solve=False)
+    op = osim.particles(s)
+    tol = (1e-10, 1e-10) if precision == 1 else (1e-5, 1e-5)
+    ncommon, nodd = compare_particles(gp, op, h, *tol)
+    assert nodd <= max(1, n // 2000)
+    assert ncommon > 0.9 * n
+    assert st.n_crossings == pytest.approx(ost["n_crossings"], rel=0.01, abs=3)
+    assert st.n_absorbed == pytest.approx(ost["n_absorbed"], abs=max(1, n // 2000))
+    dg_orc = osim.dG
+    scale = np.abs(dg_orc).max()
+    dtol = 1e-10 if precision == 1 else 1e-5
+    if nodd == 0:
+        assert np.max(np.abs(dg_gpu - dg_orc)) <= dtol * scale
+    # particles come back sorted by tet (the sort runs at upload)
+    assert np.all(np.diff(g0["tet"]) >= 0)
+
+
+def test_gather_uniform_fields_exact(F):
+    """A uniform E0 is reproduced exactly by the Whitney-1 interpolant, so one push from
+    rest with B = 0 gives the closed-form Boris update u = (q dt / m) E0."""
+    announce("uniform-field gather")
+    xyz, tets, h = jittered_kuhn(4)
+    osim = OracleSim(xyz, tets)
+    E0 = np.array([3e3, -1e3, 2e3])
+    e = osim.mesh.edge_dofs_of_uniform_field(E0)
+    e[osim.mesh.boundary_edge] = 0.0
+    x, _ = inputs.uniform_box_particles(500, [0.2] * 3, [0.8] * 3, 0.0, seed=5)
+    u = np.zeros_like(x)
+    dt = 1e-12
+    with _lib_sim(F, xyz, tets, precision=1) as L:
+        # interior tets only see interior edges; boundary edges are zeroed by the library,
+        # so keep particles in tets with no wall edge
+        F.fepic_set_fields(L.ctx, e=e, e_prev=e)
+        sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 1.0)
+        F.fepic_upload_particles(L.ctx, sp, x, u)
+        F.fepic_push_particles(L.ctx, dt)
+        gp = F.fepic_get_particles(L.ctx, sp)
+    m = osim.mesh
+    wall_tet = np.any(m.boundary_edge[m.tet_edges], axis=1)
+    inner = ~wall_tet[m.locate(x)]
+    ids = np.arange(len(x))[inner]
+    sel = np.isin(gp["id"], ids)
+    expect = -Q_E * dt / M_E * E0
+    assert np.allclose(gp["u"][sel], expect, rtol=1e-12, atol=1e-12 * np.abs(expect).max())
+
+
+# ----------------------------------------------------------------------------- C1
+def test_c1_single_electron_2000_steps_fp64(F):
+    announce("C1: single electron, Kuhn 6x6x6, 2000 steps, all FP64")
+    xyz, tets = inputs.kuhn_cube(6)
+    B0, v0 = 0.1, 1e5
+    gam = 1 / math.sqrt(1 - (v0 / C_LIGHT) ** 2)
+    om = Q_E * B0 / (gam * M_E)
+    dt = 2 * math.pi / om / 50
+    rL = gam * M_E * v0 / (Q_E * B0)
+    c = np.full(3, 5 / 12)
+    x0, u0 = [c + [rL, 0, 0]], [[0, gam * v0, 0]]
+    osim = OracleSim(xyz, tets)
+    osim.set_uniform_B([0, 0, B0])
+    s = osim.add_species(-Q_E, M_E, 1.0)
+    osim.upload_particles(s, x0, u0)
+    osim.init_electrostatic()
+    with _lib_sim(F, xyz, tets, precision=1, diagnostics=1) as L:
+        F.fepic_set_uniform_B(L.ctx, [0, 0, B0])
+        sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 1.0)
+        F.fepic_upload_particles(L.ctx, sp, x0, u0)
+        F.fepic_init_electrostatic(L.ctx, 1e-14)
+        e0, _, _ = F.fepic_get_fields(L.ctx)
+        assert np.allclose(e0, osim.e, rtol=0, atol=1e-9 * np.abs(osim.e).max())
+        worst = 0.0
+        cont, drift, ncross = 0.0, 0.0, 0
+        for n in range(2000):
+            st = F.fepic_step(L.ctx, dt, 0.25, 0.5)
+            ost = osim.step(dt, 0.25, 0.5)
+            ncross += st.n_crossings
+            cont = max(cont, st.cont_resid_rel)
+            if st.gauss_drift_check_rel >= 0:
+                drift = max(drift, st.gauss_drift_check_rel)
+            if n % 50 == 0 or n == 1999:
+                gp = F.fepic_get_particles(L.ctx, sp)
+                worst = max(worst, np.max(np.abs(gp["x"][0] - osim.species[0].x[0])) / rL)
+        e, _, b = F.fepic_get_fields(L.ctx)
+    assert worst < 1e-7
+    assert ncross > 200
+    assert cont < 1e-12
+    assert drift < 1e-12
+    assert np.linalg.norm(e - osim.e) <= 1e-6 * np.linalg.norm(osim.e)
+    assert np.max(np.abs(b - osim.b)) <= 1e-12 * np.abs(osim.b).max()
+
+
+# ----------------------------------------------------------------------------- full steps
+@pytest.mark.parametrize("precision", [1, 0])
+def test_beam_steps_fields_and_conservation(F, precision):
+    announce(f"tiny beam, 12 full steps, precision={precision}")
+    xyz, tets, h = jittered_kuhn(4, lo=(-0.02, -0.02, 0.0), hi=(0.02, 0.02, 0.04), seed=5)
+    x, u = inputs.beam_particles(700, 0.008, 0.004, 0.03, 1000.0, 1.0, M_E, 5)
+    osim = OracleSim(xyz, tets)
+    s = osim.add_species(-Q_E, M_E, 5e4)
+    osim.upload_particles(s, x, u, ids=np.arange(len(x)))
+    osim.init_electrostatic()
+    dt = 1e-10
+    with _lib_sim(F, xyz, tets, precision=precision, diagnostics=1) as L:
+        sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 5e4)
+        F.fepic_upload_particles(L.ctx, sp, x, u, ids=np.arange(len(x)))
+        F.fepic_init_electrostatic(L.ctx, 1e-14)
+        for n in range(12):
+            st = F.fepic_step(L.ctx, dt, 0.25, 0.5)
+            osim.step(dt, 0.25, 0.5)
+            assert st.cont_resid_rel < 1e-12
+            if st.gauss_drift_check_rel >= 0:
+                assert st.gauss_drift_check_rel < 1e-12
+            assert st.cg_rel_resid <= 1e-10 * 1.01
+        e, ep, b = F.fepic_get_fields(L.ctx)
+        dg, G = F.fepic_get_current(L.ctx)
+        gp = F.fepic_get_particles(L.ctx, sp)
+    assert np.linalg.norm(e - osim.e) <= 1e-6 * np.linalg.norm(osim.e)
+    assert np.linalg.norm(b - osim.b) <= 1e-6 * np.linalg.norm(osim.b) + 1e-30
+    assert np.linalg.norm(G - osim.G) <= 1e-6 * np.linalg.norm(osim.G)
+    tol = (1e-9, 1e-9) if precision == 1 else (1e-5, 1e-5)
+    compare_particles(gp, osim.particles(s), h, *tol)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_newmark_solve_vs_oracle(F, mode):
+    """No particles: the step is the Newmark update alone, from random e^n, e^{n-1}."""
+    announce(f"Newmark solve, warm start {mode}")
+    xyz, tets, h = jittered_kuhn(7, seed=9)
+    osim = OracleSim(xyz, tets)
+    rng = np.random.default_rng(4)
+    e = rng.normal(size=osim.mesh.n_edges)
+    ep = e + 0.01 * rng.normal(size=osim.mesh.n_edges)
+    e[osim.mesh.boundary_edge] = ep[osim.mesh.boundary_edge] = 0.0
+    b = osim.mesh.face_dofs_of_uniform_field([0.1, 0.0, 0.0])
+    osim.e, osim.e_prev, osim.b = e.copy(), ep.copy(), b.copy()
+    dt = 3e-10
+    with _lib_sim(F, xyz, tets, precision=0, warm_start=mode) as L:
+        F.fepic_set_fields(L.ctx, e=e, e_prev=ep, b=b)
+        for _ in range(3):
+            st = F.fepic_step(L.ctx, dt, 0.25, 0.5)
+            osim.step(dt, 0.25, 0.5)
+        eg, epg, bg = F.fepic_get_fields(L.ctx)
+    assert st.cg_iters > 0
+    assert np.linalg.norm(eg - osim.e) <= 1e-6 * np.linalg.norm(osim.e)
+    assert np.linalg.norm(bg - osim.b) <= 1e-6 * np.linalg.norm(osim.b)
+
+
+def test_general_beta_gamma(F):
+    announce("Newmark beta=0.3 gamma=0.6")
+    xyz, tets, h = jittered_kuhn(5, seed=10)
+    osim = OracleSim(xyz, tets)
+    rng = np.random.default_rng(6)
+    e = rng.normal(size=osim.mesh.n_edges)
+    e[osim.mesh.boundary_edge] = 0.0
+    osim.e, osim.e_prev = e.copy(), 0.9 * e
+    with _lib_sim(F, xyz, tets) as L:
+        F.fepic_set_fields(L.ctx, e=e, e_prev=0.9 * e)
+        for _ in range(2):
+            F.fepic_step(L.ctx, 5e-10, 0.3, 0.6)
+            osim.step(5e-10, 0.3, 0.6)
+        eg, _, bg = F.fepic_get_fields(L.ctx)
+    assert np.linalg.norm(eg - osim.e) <= 1e-7 * np.linalg.norm(osim.e)
+    assert np.linalg.norm(bg - osim.b) <= 1e-7 * np.linalg.norm(osim.b)
+
+
+# ----------------------------------------------------------------------------- edge cases
+def test_empty_and_degenerate_inputs(F):
+    announce("edge cases: no particles, single tet, rejected uploads")
+    # a single tet: every edge is on the wall, the system is empty
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    tets = np.array([[0, 1, 2, 3]], np.int32)
+    with _lib_sim(F, xyz, tets) as L:
+        st = F.fepic_step(L.ctx, 1e-9)
+        assert st.cg_iters == 0
+        sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 1.0)
+        x = np.array([[0.1, 0.1, 0.1], [2.0, 0, 0], [np.nan, 0, 0]])
+        assert F.fepic_upload_particles(L.ctx, sp, x, np.zeros((3, 3))) == 2
+        assert F.fepic_num_particles(L.ctx, sp) == 1
+        # at rest it stays; one pushed out through the wall x = 0 is absorbed
+        st = F.fepic_push_particles(L.ctx, 1e-9)
+        assert st.n_absorbed == 0
+        F.fepic_upload_particles(L.ctx, sp, np.array([[0.2, 0.2, 0.2]]), np.array([[-5e8, 0, 0]]))
+        st = F.fepic_push_particles(L.ctx, 1e-9)
+        assert st.n_absorbed == 1
+        assert F.fepic_num_particles(L.ctx, sp) == 1
+    # bad meshes are refused
+    with pytest.raises(F.FepicError):
+        F.Simulation(xyz, np.array([[0, 1, 2, 2]], np.int32))
+    with pytest.raises(F.FepicError):
+        F.Simulation(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], float), tets)
+
+
+def test_failed_step_commits_nothing(F):
+    announce("atomic step: crossing cap and CG failure")
+    xyz, tets, h = jittered_kuhn(4, seed=2)
+    x, u = inputs.uniform_box_particles(200, [0.1] * 3, [0.9] * 3, 4e7, seed=3)
+    with _lib_sim(F, xyz, tets, precision=1, crossing_cap=1) as L:
+        sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 1e3)
+        F.fepic_upload_particles(L.ctx, sp, x, u, ids=np.arange(200))
+        before = F.fepic_get_particles(L.ctx, sp)
+        rc, st = F.fepic_step(L.ctx, 1e-8, check=False)
+        assert rc == F.FEPIC_E_CROSSING_CAP
+        after = F.fepic_get_particles(L.ctx, sp)
+        assert np.array_equal(np.sort(before["id"]), np.sort(after["id"]))
+        o1, o2 = np.argsort(before["id"]), np.argsort(after["id"])
+        assert np.array_equal(before["x"][o1], after["x"][o2])
+    with _lib_sim(F, xyz, tets, precision=1, cg_max_iters=1) as L:
+        rng = np.random.default_rng(0)
+        e = rng.normal(size=L.sizes["n_edges"])
+        F.fepic_set_fields(L.ctx, e=e, e_prev=0.5 * e)
+        e_before = F.fepic_get_fields(L.ctx)[0]
+        rc, st = F.fepic_step(L.ctx, 1e-9, check=False)
+        assert rc == F.FEPIC_E_CG_NOT_CONVERGED
+        assert np.array_equal(F.fepic_get_fields(L.ctx)[0], e_before)
+
+
+def test_sort_period_and_many_waves(F):
+    """Ragged counts over many waves, sorting every 3rd step: conservation still exact."""
+    announce("sort period 3, 64*300+37 particles")
+    xyz, tets, h = jittered_kuhn(6, seed=12)
+    n = 64 * 300 + 37
+    x, u = inputs.uniform_box_particles(n, [0.05] * 3, [0.95] * 3, 2e6, seed=8)
+    with _lib_sim(F, xyz, tets, sort_period=3, diagnostics=1) as L:
+        sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 1e2)
+        sp2 = F.fepic_add_species(L.ctx, Q_E, 1836 * M_E, 1e2)
+        F.fepic_upload_particles(L.ctx, sp, x, u)
+        F.fepic_upload_particles(L.ctx, sp2, x, u / 40)
+        F.fepic_init_electrostatic(L.ctx, 1e-14)
+        for k in range(7):
+            st = F.fepic_step(L.ctx, 3e-9, 0.25, 0.5)
+            assert st.cont_resid_rel < 1e-12
+            if st.gauss_drift_check_rel >= 0:
+                assert st.gauss_drift_check_rel < 1e-12
+        assert st.n_crossings > 0
