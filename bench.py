@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark of the FE-PIC hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2_beam]
+
+One step = the whole per-step path through the C ABI (fepic_step): sort by tet, field
+staging, gather + relativistic Boris + path tracking + Whitney-1 deposit, Newmark
+right-hand side, warm start, Jacobi-PCG to ||r|| <= 1e-10 ||b||, Faraday.  Inputs are
+resident on the device before the timed region.  Prints one JSON line.
+
+value = particle-steps per second of whole steps (particles alive at the start of each
+timed step, summed, over the wall time of the K steps).  The JSON also carries the
+particle kernel's own rate, the Newmark step time and CG iterations, the roofline of the
+dominant kernel (HIP-event timed inside the timed region) and the CPU oracle on a
+bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (gather+push+deposit) + Newmark step time at CG resid 1e-10"
+HBM_PEAK_GBS = 8000.0
+FAMILIES = ["push", "stage", "sort", "rhs", "cg_iter", "faraday"]
+KERNEL_NAMES = {"push": "k_push", "stage": "k_stage", "sort": "k_hist/k_scan/k_scatter", "rhs": "k_rhs",
+                "cg_iter": "k_cg_iter", "faraday": "k_faraday"}
+KERNEL_SOURCES = {"push": "kernels_particles.hip", "stage": "kernels_particles.hip", "sort": "kernels_particles.hip",
+                  "rhs": "kernels_fields.hip", "cg_iter": "kernels_fields.hip", "faraday": "kernels_fields.hip"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(fam, geo, st):
+    """Bytes the method must move per launch (each HBM word once), by kernel family."""
+    n_rows, nnz, ne, nf, nt = geo["n_rows"], geo["nnz"], geo["n_edges"], geo["n_faces"], geo["n_tets"]
+    npart, occ, cross = st["particles"], st["occupied_tets"], st["crossings"]
+    if fam == "cg_iter":      # A values + columns once; r, w, s, p, x, dinv read; r, w, s, p, x written
+        return 12 * nnz + 88 * n_rows
+    if fam == "rhs":          # M, S values + columns; e, e_prev, dG_new, dG_old read; b written
+        return 20 * nnz + 40 * n_rows
+    if fam == "push":         # particle state read + written (tet, 3 lambda, 3 u at 4 B);
+        # per occupied tet and per crossing: its 128 B record and 6 FP64 read-modify-writes
+        return 56 * npart + (128 + 96) * (occ + cross)
+    if fam == "stage":        # per tet record write (9 x 4 B); e, b once; grad 72 B + 10 ids
+        return nt * (36 + 72 + 40) + 8 * (ne + nf)
+    if fam == "faraday":      # 3 edge ids + b read/write per face; e^{n+1}, e^n once
+        return nf * (12 + 16) + 16 * ne
+    if fam == "sort":         # histogram read of tet; scatter read + write of 36 B payload
+        return npart * (4 + 72) + 12 * nt
+    return 0
+
+
+def source_hash(fam):
+    p = os.path.join(ROOT, "paper_2102_06248_amd", "csrc", KERNEL_SOURCES[fam])
+    return hashlib.sha1(open(p, "rb").read()).hexdigest()[:12]
+
+
+def traffic_from_profile(fam, workload, launches_bytes_per):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; None otherwise."""
+    p = os.path.join(ROOT, "profiles", f"{fam}_{workload}_counters.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("source_sha1") != source_hash(fam):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, n_sample=None):
+    """The oracle, single-threaded, on one full step of the same workload (all particles,
+    from its own electrostatic start): particle push + Newmark solve."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.pic import OracleSim
+
+    with threadpool_limits(limits=1):
+        osim = OracleSim(wl["xyz"], wl["tets"])
+        n_total = 0
+        for sp in wl["species"]:
+            s = osim.add_species(sp["q"], sp["m"], sp["w"])
+            k = len(sp["x"]) if n_sample is None else min(n_sample, len(sp["x"]))
+            osim.upload_particles(s, sp["x"][:k], sp["u"][:k])
+            n_total += k
+        if wl.get("B0") is not None:
+            osim.set_uniform_B(wl["B0"])
+        osim.init_electrostatic(tol=1e-12)
+        t0 = time.perf_counter()
+        dG, _ = osim.push_particles(wl["dt"])
+        t_push = time.perf_counter() - t0
+        ie = osim.ie
+        A, B1, B2 = osim.operators(wl["dt"], wl["beta"], wl["gamma"])
+        rhs = B1 @ osim.e[ie] + B2 @ osim.e_prev[ie] - (dG - osim.dG)[ie]
+        from oracle.newmark import pcg_jacobi
+        t0 = time.perf_counter()
+        _, iters, _ = pcg_jacobi(A, rhs, osim.e[ie], 1e-10, 10000)
+        t_solve = time.perf_counter() - t0
+    return {"value": n_total / (t_push + t_solve), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one full step of the same workload ({n_total} particles) from the oracle's own "
+                       f"electrostatic start: push {t_push:.2f} s + Newmark Jacobi-PCG {iters} iters "
+                       f"{t_solve:.2f} s; single thread"),
+            "push_particle_steps_per_s": n_total / t_push, "newmark_ms": 1e3 * t_solve, "cg_iters": iters}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2_beam", choices=["c2_beam", "c3_plasma"])
+    ap.add_argument("--particles", type=int, default=None, help="override the particle count (pairs for c3)")
+    ap.add_argument("--warm-start", default="prev", choices=["prev", "extrap1", "extrap2"])
+    ap.add_argument("--sort-period", type=int, default=1)
+    ap.add_argument("--inject", type=int, default=1, help="inject the beam's per-step batch (c2)")
+    ap.add_argument("--cpu-sample", type=int, default=None, help="limit the oracle's particle count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
+              "'How the path would shard')", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2102_06248_amd import fepic as F
+    from paper_2102_06248_amd import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    kw = {}
+    if args.particles:
+        kw = {"n_particles": args.particles} if args.workload == "c2_beam" else {"n_pairs": args.particles}
+    t0 = time.perf_counter()
+    wl = workloads.WORKLOADS[args.workload](**kw)
+    log(f"[bench] workload {wl['name']} built in {time.perf_counter() - t0:.1f}s: "
+        f"{len(wl['tets'])} tets, {sum(len(s['x']) for s in wl['species'])} particles")
+    ws = {"prev": F.FEPIC_WS_PREV, "extrap1": F.FEPIC_WS_EXTRAP1, "extrap2": F.FEPIC_WS_EXTRAP2}[args.warm_start]
+    sim = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=wl["precision"], warm_start=ws,
+                       sort_period=args.sort_period, timing=1)
+    ctx = sim.ctx
+    species = []
+    for sp in wl["species"]:
+        s = F.fepic_add_species(ctx, sp["q"], sp["m"], sp["w"])
+        rej = F.fepic_upload_particles(ctx, s, sp["x"], sp["u"])
+        species.append(s)
+        log(f"[bench] species {s}: {len(sp['x'])} uploaded, {rej} rejected")
+    if wl.get("B0") is not None:
+        F.fepic_set_uniform_B(ctx, wl["B0"])
+    it = F.fepic_init_electrostatic(ctx, 1e-12)
+    log(f"[bench] electrostatic start: {it} CG iterations")
+    inject = args.inject and wl.get("inject_per_step")
+    batches = [workloads.c2_injection_batch(k) for k in range(args.warmup + args.steps)] if inject else []
+    next_id = [10 ** 9]
+
+    def one_step(k):
+        if inject:
+            x, u = batches[k]
+            ids = np.arange(next_id[0], next_id[0] + len(x))
+            next_id[0] += len(x)
+            F.fepic_inject_particles(ctx, species[0], x, u, ids=ids)
+        return F.fepic_step(ctx, wl["dt"], wl["beta"], wl["gamma"])
+
+    for k in range(args.warmup):
+        st = one_step(k)
+        log(f"[bench] warmup {k}: cg {st.cg_iters} iters, {st.n_particles} particles, {st.n_crossings} crossings")
+    # geometry of the work, for algorithmic bytes
+    sizes = F.fepic_get_topology_sizes(ctx)
+    r, c, v = F.fepic_get_matrix(ctx, 0)
+    geo = {"n_rows": sizes["n_edges"], "nnz": len(v) + (sizes["n_edges"] - sizes["n_int_edges"]),
+           "n_edges": sizes["n_edges"], "n_faces": sizes["n_faces"], "n_tets": len(wl["tets"])}
+    occ = 0
+    for s in species:
+        occ += len(np.unique(F.fepic_get_particles(ctx, s)["tet"]))
+    for fam in FAMILIES:
+        F.fepic_kernel_timing(ctx, fam, 1 + args.steps * (1200 if fam.startswith("cg") else 4))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psteps, cg_iters, cross, newmark_ms, push_ms, stats = 0, [], 0, [], [], []
+    for k in range(args.steps):
+        n_before = sum(F.fepic_num_particles(ctx, s) for s in species) if k == 0 else stats[-1].n_particles
+        if inject:
+            n_before += len(batches[args.warmup + k][0])
+        st = one_step(args.warmup + k)
+        psteps += n_before
+        cg_iters.append(st.cg_iters)
+        cross += st.n_crossings
+        newmark_ms.append(st.ms_rhs + st.ms_warm + st.ms_cg + st.ms_faraday)
+        push_ms.append(st.ms_stage + st.ms_particles)
+        stats.append(st)
+        log(f"[bench] step {k}: cg {st.cg_iters} iters, {st.n_particles} particles, {st.n_crossings} crossings, "
+            f"push {push_ms[-1]:.3f} ms, newmark {newmark_ms[-1]:.3f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    fam_time = {}
+    for fam in FAMILIES:
+        ms, n = F.fepic_kernel_time(ctx, fam)
+        fam_time[fam] = (ms, n)
+    dominant = max(fam_time, key=lambda f: fam_time[f][0])
+    ms_tot, nl = fam_time[dominant]
+    mean_particles = psteps / args.steps
+    wst = {"particles": mean_particles, "occupied_tets": occ, "crossings": cross / args.steps}
+    per_launch_bytes = algorithmic_bytes(dominant, geo, wst)
+    if dominant == "push":
+        per_launch_bytes = algorithmic_bytes(dominant, geo, wst) / len(species)
+    avg_s = ms_tot / nl / 1e3
+    achieved = per_launch_bytes / avg_s / 1e9
+    traffic = traffic_from_profile(dominant, wl["name"], per_launch_bytes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": KERNEL_NAMES[dominant], "avg_launch_us": round(avg_s * 1e6, 3), "launches": nl,
+                "algorithmic_bytes_per_launch": int(per_launch_bytes)}
+    # the particle kernel's own rate and roofline, for reference
+    pms, pn = fam_time["push"]
+    push_bytes = algorithmic_bytes("push", geo, wst)
+    push_info = {"particle_steps_per_s": mean_particles * args.steps / (pms / 1e3) if pms > 0 else None,
+                 "avg_launch_us": round(pms / max(pn, 1) * 1e3, 3),
+                 "achieved_GBs": round(push_bytes * args.steps / (pms / 1e3) / 1e9, 1) if pms > 0 else None}
+    breakdown = {f: {"ms_per_step": round(fam_time[f][0] / args.steps, 4), "launches_per_step": fam_time[f][1] / args.steps}
+                 for f in FAMILIES}
+    if args.copy_calibration:
+        a = torch.empty(256 * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(wl, args.cpu_sample)
+    n_total = sum(len(s["x"]) for s in wl["species"])
+    out = {
+        "metric": METRIC, "value": psteps / elapsed, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "tets": len(wl["tets"]), "particles": n_total,
+                   "mean_live_particles": round(mean_particles), "dt": wl["dt"], "beta": wl["beta"],
+                   "gamma": wl["gamma"], "cg_tol": 1e-10, "warm_start": args.warm_start,
+                   "sort_period": args.sort_period, "inject_per_step": int(wl.get("inject_per_step") or 0) if inject else 0,
+                   "precision": "fp32 push / fp64 deposit+solve", "parallelism": "single GPU"},
+        "newmark_ms_per_step": round(float(np.mean(newmark_ms)), 4),
+        "cg_iters_mean": round(float(np.mean(cg_iters)), 2),
+        "push": push_info,
+        "crossings_per_particle_step": round(cross / psteps, 4),
+        "kernel_breakdown": breakdown,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,12 @@ int fepic_add_species(fepic_ctx* ctx, double q, double m, double w, int* species
  * values are dropped and counted in *n_rejected (may be NULL). */
 int fepic_upload_particles(fepic_ctx* ctx, int species, int64_t n, const int64_t* id, const double* x,
                            const double* u, int64_t* n_rejected);
+/* Injection during a run (e.g. a beam source): appends n particles like
+ * fepic_upload_particles but without re-sorting or waiting for the device; the next
+ * step's sort orders them, and points outside the mesh are dropped there (not counted).
+ * The counts of live particles are exact again after the next fepic_step. */
+int fepic_inject_particles(fepic_ctx* ctx, int species, int64_t n, const int64_t* id, const double* x,
+                           const double* u);
 int fepic_num_particles(fepic_ctx* ctx, int species, int64_t* n);
 /* Copies live particles out (order = current device order): id, x [n][3] (Cartesian,
  * reconstructed as sum lambda_k r_k), u [n][3], tet [n], lambda [n][4] (local vertex
@@ -188,7 +194,7 @@ int fepic_diagnostics(fepic_ctx* ctx, fepic_step_stats* out);
 
 /* ---------------------------------------------------------------- profiling
  * Brackets every launch of the named kernel family ("push", "stage", "sort", "rhs",
- * "cg_spmv", "cg_update", "faraday", "mlp_fwd") with HIP events on the context's stream
+ * "cg_iter", "faraday", "mlp_fwd") with HIP events on the context's stream
  * while enabled; fepic_kernel_time returns the summed duration and launch count since
  * enabling (synchronizes the stream). */
 int fepic_kernel_timing(fepic_ctx* ctx, const char* family, int enable);

@@ -158,6 +158,9 @@ class Mesh:
         whose smallest barycentric coordinate is largest, accepted if >= -1e-12.
         Returns int64 tet ids (-1 if outside the mesh)."""
         x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+        if len(x) > 65536:
+            return np.concatenate([self.locate(x[i:i + 65536], n_candidates)
+                                   for i in range(0, len(x), 65536)])
         if not hasattr(self, "_kdtree"):
             self._centroid = self.xyz[self.tets].mean(axis=1)
             self._kdtree = cKDTree(self._centroid)

@@ -15,7 +15,7 @@ using namespace fepic;
 
 namespace fepic {
 
-const char* kFamilies[] = {"push", "stage", "sort", "rhs", "cg_spmv", "cg_update", "faraday", "mlp_fwd"};
+const char* kFamilies[] = {"push", "stage", "sort", "rhs", "cg_iter", "faraday", "mlp_fwd"};
 
 int hip_fail(fepic_ctx* c, hipError_t e, const char* what) {
     c->err = std::string(what) + ": " + hipGetErrorString(e);
@@ -159,8 +159,13 @@ void settle_counts(fepic_ctx* c) {
 }
 
 int sync_counts(fepic_ctx* c) {
+    bool any = false;
     for (auto& s : c->species)
-        if (s.sorted_pending) HIPCHK(c, hipMemcpyAsync(s.h_nlive, s.d_nlive, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        if (s.sorted_pending) {
+            HIPCHK(c, hipMemcpyAsync(s.h_nlive, s.d_nlive, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+            any = true;
+        }
+    if (!any) return FEPIC_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     settle_counts(c);
     return FEPIC_OK;
@@ -237,8 +242,7 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
         hipEvent_t* ev = timer_pair(c, FAM_RHS);
         if (ev) (void)hipEventRecord(ev[0], c->stream);
         launch_rhs(c->stream, ne, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_e, c->d_ep, c->d_dgn, c->d_dg, c->d_bedge,
-                   dt * dt, 0.5 - 2.0 * beta + gamma, 0.5 + beta - gamma, c->d_rhs, c->d_partial, c->d_sc,
-                   c->opt.cg_tol);
+                   dt * dt, 0.5 - 2.0 * beta + gamma, 0.5 + beta - gamma, c->d_rhs, c->d_partial);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
     ev_mark(c, 5);
@@ -255,47 +259,77 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
         if (rc != FEPIC_OK) return rc;
     }
     ev_mark(c, 6);
-    launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, c->d_r, c->d_z, c->d_p[0],
-                   c->d_partial, c->d_sc);
-    if (mode == FEPIC_WS_MLP) {
-        // guard: a start worse than x0 = 0 (or non-finite) falls back to e^n
-        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (!(std::isfinite(c->h_sc->rr0)) || c->h_sc->rr0 > c->h_sc->bb) {
-            c->mlp_fallbacks++;
-            launch_warm(c->stream, FEPIC_WS_PREV, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
-            launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, c->d_r, c->d_z,
-                           c->d_p[0], c->d_partial, c->d_sc);
-        }
-    }
-    int it = 0, pb = 0;
+    double* const R[2] = {c->d_r, c->d_z};
+    double* const W[2] = {c->d_q, c->d_w2};
+    double* const SV[2] = {c->d_p[1], c->d_s2};
+    double* const P = c->d_p[0];
     const int maxit = c->opt.cg_max_iters;
-    int batch = std::max(1, c->opt.cg_check_every);
-    for (;;) {
+    const int batch = std::max(1, c->opt.cg_check_every);
+    int total = 0;
+    double rr0_first = -1.0;
+    c->cg_restarts = 0;
+    for (int restart = 0;; ++restart) {
+        launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, R[0], W[0], P, SV[0],
+                       c->d_partial, c->d_sc, c->opt.cg_tol);
+        if (restart == 0 && mode == FEPIC_WS_MLP) {
+            // guard: a start worse than x0 = 0 (or non-finite) falls back to e^n
+            launch_cg_rr0(c->stream, ne, c->d_partial, c->d_sc);
+            HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (!(std::isfinite(c->h_sc->rr0)) || c->h_sc->rr0 > c->h_sc->bb) {
+                c->mlp_fallbacks++;
+                launch_warm(c->stream, FEPIC_WS_PREV, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
+                launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, R[0], W[0], P,
+                               SV[0], c->d_partial, c->d_sc, c->opt.cg_tol);
+            }
+        }
+        // Iterations are launched in batches; between batches the host reads the device's
+        // convergence flag and sizes the next batch from the recent contraction of ||r||
+        // (never more than doubling what has been launched).
+        int launched = 0, last_done = -1;
+        double last_rr = 0.0;
+        const int budget = maxit - total;
+        for (;;) {
+            HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            const CgScalars& h = *c->h_sc;
+            if (h.converged || launched > budget) break;
+            int todo = batch;
+            if (launched > 0) {
+                const int done = h.iters;
+                if (last_done >= 0 && done > last_done && h.rr > 0 && last_rr > h.rr && h.tol2_bb > 0) {
+                    const double rate = std::log(h.rr / last_rr) / (done - last_done);
+                    const double need = std::log(h.tol2_bb / h.rr) / rate;
+                    if (std::isfinite(need)) todo = (int)std::ceil(0.85 * need) - (launched - 1 - done);
+                } else {
+                    todo = launched;
+                }
+                todo = std::max(batch, std::min(todo, launched));
+                last_done = done;
+                last_rr = h.rr;
+            }
+            // the launch after the budget only checks (and is discarded on failure)
+            todo = std::min(todo, budget + 1 - launched);
+            for (int k = 0; k < todo; ++k)
+                launch_cg_iter(c->stream, launched + k, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, P, R, W, SV,
+                               c->d_partial, c->d_sc, timer_pair(c, FAM_CG_ITER));
+            launched += todo;
+        }
+        if (restart == 0) rr0_first = c->h_sc->rr0;
+        total += c->h_sc->iters;
+        // the stopping rule is on the true residual: if the recurrence drifted, restart
+        // from the current iterate
+        launch_cg_resid(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_rhs, c->d_x, c->d_rt, c->d_partial, c->d_sc);
         HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->h_sc->converged || c->h_sc->iters >= maxit) break;
-        // estimate the remaining iterations from the observed contraction of ||r||^2
-        int todo = batch;
-        const double rr = c->h_sc->rr, rr0 = c->h_sc->rr0, tgt = c->h_sc->tol2_bb;
-        const int done = c->h_sc->iters;
-        if (done >= 4 && rr > 0 && rr0 > rr && tgt > 0) {
-            const double rate = std::log(rr / rr0) / done;  // per iteration, < 0
-            const double need = std::log(tgt / rr) / rate;
-            if (std::isfinite(need)) todo = std::max(batch, (int)std::ceil(0.9 * need));
-        }
-        todo = std::min(todo, maxit - done);
-        for (int k = 0; k < todo; ++k) {
-            hipEvent_t* e1 = timer_pair(c, FAM_CG_SPMV);
-            hipEvent_t* e2 = timer_pair(c, FAM_CG_UPDATE);
-            launch_cg_iter(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, c->d_r, c->d_z, c->d_p[pb],
-                           c->d_p[1 - pb], c->d_q, c->d_partial, c->d_sc, e1, e2);
-            pb ^= 1;
-        }
-        it += todo;
+        const CgScalars& h = *c->h_sc;
+        if (h.converged != 1 || h.rr_true <= h.tol2_bb || restart >= 3 || total >= maxit) break;
+        c->cg_restarts++;
     }
+    c->h_sc->iters = total;
+    c->h_sc->rr0 = rr0_first;
+    if (c->h_sc->converged == 1 && !(c->h_sc->rr_true <= c->h_sc->tol2_bb)) c->h_sc->converged = 0;
     ev_mark(c, 7);
-    launch_cg_resid(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_rhs, c->d_x, c->d_rt, c->d_partial, c->d_sc);
     {
         hipEvent_t* ev = timer_pair(c, FAM_FARADAY);
         if (ev) (void)hipEventRecord(ev[0], c->stream);
@@ -303,7 +337,6 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
     ev_mark(c, 8);
-    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
     return FEPIC_OK;
 }
 
@@ -349,8 +382,7 @@ int run_diagnostics(fepic_ctx* c, fepic_step_stats* st, bool have_step, bool hav
     launch_diag_nodes(s, nn, c->d_inode, c->d_rho_new, c->rho_valid ? c->d_rho : c->d_rho_new, c->d_n1, c->d_n2, rG1,
                       rG2, c->d_n3, have_hist, rG_new, c->d_acc);
     launch_divb(s, c->mesh.n_tets, c->d_tet_faces, c->d_b, c->d_acc);
-    HIPCHK(c, hipMemsetAsync(c->d_dotc, 0, sizeof(unsigned int), s));
-    launch_dot(s, ne, c->d_e, c->d_Me, c->d_partial, &c->d_acc->energy, c->d_dotc);
+    launch_dot(s, ne, c->d_e, c->d_Me, c->d_partial, &c->d_acc->energy);
     HIPCHK(c, hipMemcpyAsync(c->h_acc, c->d_acc, sizeof(DiagAcc), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     auto dbl = [](unsigned long long v) {
@@ -403,6 +435,7 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
     HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(PushCounters), hipMemcpyDeviceToHost, c->stream));
     int rc = sync_counts(c);
     if (rc != FEPIC_OK) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipGetLastError());
     st.n_crossings = (int64_t)c->h_cnt->n_crossings;
     st.max_crossings = (int)c->h_cnt->max_crossings;
@@ -666,6 +699,8 @@ int fepic_destroy(fepic_ctx* c) {
         if (c->h_sc) (void)hipHostFree(c->h_sc);
         if (c->h_cnt) (void)hipHostFree(c->h_cnt);
         if (c->h_acc) (void)hipHostFree(c->h_acc);
+        if (c->h_stage) (void)hipHostFree(c->h_stage);
+        if (c->stage_event_valid) (void)hipEventDestroy(c->stage_event);
         if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     }
     mlp_destroy(c);
@@ -732,7 +767,7 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
     c->d_A = dalloc<double>(c, nnz);
     c->d_dinv = dalloc<double>(c, ne);
     double** ev[] = {&c->d_e, &c->d_ep, &c->d_ep2, &c->d_x, &c->d_dg, &c->d_dgn, &c->d_G, &c->d_rhs, &c->d_r,
-                     &c->d_z, &c->d_p[0], &c->d_p[1], &c->d_q, &c->d_rt, &c->d_Me};
+                     &c->d_z, &c->d_p[0], &c->d_p[1], &c->d_q, &c->d_rt, &c->d_Me, &c->d_w2, &c->d_s2};
     for (double** p : ev) {
         *p = dalloc<double>(c, ne);
         if (!*p) return fail(c, FEPIC_E_OOM, "device allocation failed");
@@ -750,8 +785,7 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
         if (!*p) return fail(c, FEPIC_E_OOM, "device allocation failed");
         HIPCHK(c, hipMemset(*p, 0, sizeof(double) * nn));
     }
-    const int64_t max_blocks = ((std::max(ne, nt) + 255) / 256 + 8) * 2 + 64;
-    c->d_partial = dalloc<double>(c, 2 * max_blocks);
+    c->d_partial = dalloc<double>(c, (int64_t)partial_buffer_doubles());
     c->d_sc = dalloc<CgScalars>(c, 1);
     c->d_cnt = dalloc<PushCounters>(c, 1);
     c->d_acc = dalloc<DiagAcc>(c, 1);
@@ -901,11 +935,65 @@ int fepic_upload_particles(fepic_ctx* c, int species, int64_t n, const int64_t* 
     else sort_species<float>(c, s);
     HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(PushCounters), hipMemcpyDeviceToHost, c->stream));
     if ((rc = sync_counts(c))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipGetLastError());
     dfree(c, dx);
     dfree(c, du);
     dfree(c, did);
     if (n_rejected) *n_rejected = c->h_cnt->n_rejected;
+    c->rho_valid = false;
+    c->rG_levels = 0;
+    return FEPIC_OK;
+}
+
+int fepic_inject_particles(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
+                           const double* u) {
+    NEED_DEV(c);
+    if (species < 0 || species >= (int)c->species.size() || n < 0 || (n > 0 && (!x || !u)))
+        return fail(c, FEPIC_E_ARG, "bad injection arguments");
+    if (n == 0) return FEPIC_OK;
+    Species& s = c->species[species];
+    int rc = sync_counts(c);
+    if (rc) return rc;
+    if (s.n + n >= ((int64_t)1 << 31)) return fail(c, FEPIC_E_ARG, "too many particles for one species");
+    if ((rc = ensure_capacity(c, s, s.n + n))) return rc;
+    const size_t per = 7 * sizeof(double);  // x[3], u[3], id
+    if (n > c->stage_cap) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->h_stage) (void)hipHostFree(c->h_stage);
+        dfree(c, c->d_stage);
+        const int64_t cap = std::max<int64_t>(n, 4096);
+        if (hipHostMalloc(&c->h_stage, per * cap) != hipSuccess) return fail(c, FEPIC_E_OOM, "pinned allocation");
+        c->d_stage = dmalloc(c, per * cap);
+        if (!c->d_stage) return fail(c, FEPIC_E_OOM, "device allocation failed");
+        c->stage_cap = cap;
+    }
+    // the previous injection's copy must be done before the pinned buffer is reused
+    if (c->stage_event_valid) HIPCHK(c, hipEventSynchronize(c->stage_event));
+    double* hx = (double*)c->h_stage;
+    double* hu = hx + 3 * n;
+    int64_t* hid = (int64_t*)(hu + 3 * n);
+    std::memcpy(hx, x, 24 * n);
+    std::memcpy(hu, u, 24 * n);
+    if (id) std::memcpy(hid, id, 8 * n);
+    HIPCHK(c, hipMemcpyAsync(c->d_stage, c->h_stage, (id ? 7 : 6) * 8 * n, hipMemcpyHostToDevice, c->stream));
+    if (!c->stage_event_valid) {
+        HIPCHK(c, hipEventCreateWithFlags(&c->stage_event, hipEventDisableTiming));
+        c->stage_event_valid = true;
+    }
+    HIPCHK(c, hipEventRecord(c->stage_event, c->stream));
+    const double* dx = (const double*)c->d_stage;
+    const double* du = dx + 3 * n;
+    const int64_t* did = id ? (const int64_t*)(du + 3 * n) : nullptr;
+    const double* g = c->d_grid;
+    if (c->opt.precision == FEPIC_ALL_FP64)
+        launch_locate<double>(c->stream, n, dx, du, did, s.next_id, parr<double>(s, s.cur), s.n, c->d_grad64, c->d_r0,
+                              c->d_cell_start, c->d_cell_tets, g, g + 3, c->d_grid_n, c->d_cnt);
+    else
+        launch_locate<float>(c->stream, n, dx, du, did, s.next_id, parr<float>(s, s.cur), s.n, c->d_grad64, c->d_r0,
+                             c->d_cell_start, c->d_cell_tets, g, g + 3, c->d_grid_n, c->d_cnt);
+    s.next_id += n;
+    s.n += n;
     c->rho_valid = false;
     c->rG_levels = 0;
     return FEPIC_OK;
@@ -917,6 +1005,7 @@ int fepic_num_particles(fepic_ctx* c, int species, int64_t* n) {
     int rc = sync_counts(c);
     if (rc) return rc;
     // count live entries (dead ones stay until the next sort)
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     Species& s = c->species[species];
     std::vector<int32_t> tet(s.n);
     if (s.n) HIPCHK(c, hipMemcpy(tet.data(), s.buf[s.cur][0], sizeof(int32_t) * s.n, hipMemcpyDeviceToHost));
@@ -930,6 +1019,7 @@ int fepic_get_particles(fepic_ctx* c, int species, int64_t cap, int64_t* n, int6
     if (species < 0 || species >= (int)c->species.size() || !n) return FEPIC_E_ARG;
     int rc = sync_counts(c);
     if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     Species& s = c->species[species];
     const int64_t N = s.n;
     std::vector<int32_t> ht(N);

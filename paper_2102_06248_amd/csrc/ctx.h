@@ -11,7 +11,7 @@
 
 namespace fepic {
 
-enum { FAM_PUSH, FAM_STAGE, FAM_SORT, FAM_RHS, FAM_CG_SPMV, FAM_CG_UPDATE, FAM_FARADAY, FAM_MLP_FWD, FAM_COUNT };
+enum { FAM_PUSH, FAM_STAGE, FAM_SORT, FAM_RHS, FAM_CG_ITER, FAM_FARADAY, FAM_MLP_FWD, FAM_COUNT };
 extern const char* kFamilies[];
 
 struct KernelTimer {
@@ -65,13 +65,19 @@ struct fepic_ctx {
     double *d_dg = nullptr, *d_dgn = nullptr, *d_G = nullptr;
     double *d_b = nullptr, *d_bn = nullptr;
     double *d_rhs = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p[2] = {nullptr, nullptr}, *d_q = nullptr,
-           *d_rt = nullptr, *d_Me = nullptr;
+           *d_rt = nullptr, *d_Me = nullptr, *d_w2 = nullptr, *d_s2 = nullptr;
     double* d_partial = nullptr;
     fepic::CgScalars* d_sc = nullptr;
     fepic::CgScalars* h_sc = nullptr;
     fepic::PushCounters* d_cnt = nullptr;
     fepic::PushCounters* h_cnt = nullptr;
     int deferred_err = 0;
+    // injection staging: pinned host buffer and its device mirror (x, u, id)
+    void* h_stage = nullptr;
+    void* d_stage = nullptr;
+    int64_t stage_cap = 0;
+    hipEvent_t stage_event{};
+    bool stage_event_valid = false;
 
     // sort scratch
     int32_t *d_count = nullptr, *d_offset = nullptr, *d_bsums = nullptr;
@@ -95,6 +101,7 @@ struct fepic_ctx {
     // learned warm start
     fepic::MlpState* mlp = nullptr;
     bool mlp_ready = false;
+    int cg_restarts = 0;
     bool recording = false;
     int64_t mlp_fallbacks = 0;
 };

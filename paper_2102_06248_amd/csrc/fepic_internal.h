@@ -67,16 +67,14 @@ struct PushCounters {
 // Scalars of the PCG recurrence, kept on the device between kernels.
 struct CgScalars {
     double bb;        // ||b||^2
-    double rz;        // r . z of the current iterate
-    double pq;        // p . q
-    double rr;        // r . r
-    double alpha, beta;
+    double tol2_bb;   // tol^2 ||b||^2
+    double gam[2];    // (r,u) of iteration i (slot i & 1)
+    double alpha[2];  // step length of iteration i
+    double rr;        // r . r of the current iterate
     double rr0;       // ||b - A x0||^2
     double rr_true;   // ||b - A x||^2 at exit
-    double tol2_bb;   // tol^2 ||b||^2
-    int converged;
+    int converged;    // 1 = tolerance met, 2 = breakdown
     int iters;
-    unsigned int counter[4];  // last-block-done tickets (one per reducing kernel kind)
 };
 
 // Device-side diagnostics accumulators (max-abs values stored as ordered bit patterns).
@@ -123,15 +121,15 @@ void launch_sell_spmv(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, c
                       const double* val, const double* x, double* y);
 void launch_rhs(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* M,
                 const double* S, const double* e, const double* ep, const double* dg_new, const double* dg_old,
-                const uint8_t* bmask, double dt2, double c1, double c2, double* b, double* partial,
-                CgScalars* sc, double tol);
+                const uint8_t* bmask, double dt2, double c1, double c2, double* b, double* partial);
 void launch_warm(hipStream_t s, int mode, int64_t n, const double* e, const double* ep, const double* ep2, double* x);
 void launch_cg_init(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* A,
-                    const double* dinv, const double* b, const double* x, double* r, double* z, double* p,
-                    double* partial, CgScalars* sc);
-void launch_cg_iter(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* A,
-                    const double* dinv, double* x, double* r, double* z, const double* p_old, double* p_new,
-                    double* q, double* partial, CgScalars* sc, hipEvent_t* ev_spmv, hipEvent_t* ev_upd);
+                    const double* dinv, const double* b, const double* x, double* r, double* w, double* p, double* sv,
+                    double* partial, CgScalars* sc, double tol);
+void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
+                    const double* A, const double* dinv, double* x, double* p, double* const r[2], double* const w[2],
+                    double* const sv[2], double* partial, CgScalars* sc, hipEvent_t* ev);
+void launch_cg_rr0(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc);
 void launch_cg_resid(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
                      const double* A, const double* b, double* x, double* r_true, double* partial,
                      CgScalars* sc);
@@ -142,8 +140,8 @@ void launch_diag_nodes(hipStream_t s, int64_t n_nodes, const uint8_t* interior_n
                        const double* rho_old, const double* dtdg, const double* dtMe, const double* rG1,
                        const double* rG2, const double* dtrcg, int have_hist, double* rG_out, DiagAcc* acc);
 void launch_divb(hipStream_t s, int64_t n_tets, const int32_t* tet_faces, const double* b, DiagAcc* acc);
-void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial, double* out,
-                unsigned int* counter);
+void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial, double* out);
+size_t partial_buffer_doubles();
 
 // Learned warm start (kernels_mlp.hip).
 struct MlpDevice;

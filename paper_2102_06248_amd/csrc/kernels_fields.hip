@@ -2,26 +2,49 @@
 // matrix (slice height 64 = one wavefront, coalesced column loads), Faraday update and
 // the conservation diagnostics.  All arithmetic FP64.
 //
-// Row blocks are mapped XCD-contiguously: the hardware hands workgroup b to XCD b % 8,
-// so logical block (b % 8) * ceil(nb / 8) + b / 8 gives each XCD's L2 one contiguous
-// stretch of rows (and of the vector entries their columns mostly touch).
+// Grids are bounded (at most kMaxGrid workgroups) and XCD-contiguous: the hardware hands
+// workgroup b to XCD b % 8, so workgroup b walks the row blocks of the b % 8-th eighth of
+// the rows, giving each XCD's L2 one contiguous stretch of rows and of the vector entries
+// their columns mostly touch.
 //
-// Global reductions use per-block partials plus a last-block-done ticket: the block that
-// arrives last sums the partials in index order (deterministic) and publishes the
-// scalar, so a PCG iteration is two kernels and no host round trip.
+// Global dot products never communicate between workgroups inside a kernel: each kernel
+// writes one partial per workgroup, and the next kernel (every workgroup, redundantly, in
+// the same fixed order, so all reach the same bits) sums them.  Kernel boundaries give
+// the visibility; no device-scope fences are issued.  A PCG iteration is two kernels.
+#include <algorithm>
+
 #include "fepic_internal.h"
 
 namespace fepic {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kMaxGrid = 1024;  // 4 workgroups per CU on 256 CUs
 
-__device__ __forceinline__ int64_t xcd_block(int64_t nb_real) {
-    const int64_t per = (nb_real + 7) / 8;
-    return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+struct RowGrid {
+    int64_t nb;      // row blocks of kBlock rows
+    int64_t per;     // row blocks per XCD
+    int g;           // workgroups per XCD
+    unsigned grid;   // 8 * g
+};
+
+inline RowGrid row_grid(int64_t n_rows) {
+    RowGrid r;
+    r.nb = (n_rows + kBlock - 1) / kBlock;
+    r.per = (r.nb + 7) / 8;
+    r.g = (int)std::min<int64_t>(r.per, kMaxGrid / 8);
+    if (r.g < 1) r.g = 1;
+    r.grid = 8u * (unsigned)r.g;
+    return r;
 }
 
-inline unsigned xcd_grid(int64_t nb_real) { return (unsigned)(((nb_real + 7) / 8) * 8); }
+__device__ __forceinline__ int64_t rg_first(const RowGrid& rg) {
+    return (int64_t)(blockIdx.x % 8) * rg.per + blockIdx.x / 8;
+}
+__device__ __forceinline__ int64_t rg_end(const RowGrid& rg) {
+    const int64_t e = (int64_t)(blockIdx.x % 8 + 1) * rg.per;
+    return e < rg.nb ? e : rg.nb;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -29,10 +52,12 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sums NV values over the block; thread 0 gets the totals in out[].
-template <int NV>
-__device__ __forceinline__ void block_sum(const double v[NV], double out[NV]) {
-    __shared__ double s[NV][kBlock / 64];
+// Block-wide sums of NV values over a block of BS threads; every thread receives the
+// totals (summed in a fixed order).
+template <int NV, int BS = kBlock>
+__device__ __forceinline__ void block_sum_all(double v[NV]) {
+    constexpr int NW = BS / 64;
+    __shared__ double s[NV][NW];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
@@ -40,47 +65,59 @@ __device__ __forceinline__ void block_sum(const double v[NV], double out[NV]) {
         if (lane == 0) s[j][w] = x;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) out[j] = s[j][0] + s[j][1] + s[j][2] + s[j][3];
-    }
-    __syncthreads();
-}
-
-// Writes this block's partials, then returns true in the block that arrived last, which
-// then sees every partial.  The ticket counter is reset by that block.
-template <int NV>
-__device__ __forceinline__ bool publish_partials(const double v[NV], double* partial, unsigned int* counter) {
-    double tot[NV];
-    block_sum<NV>(v, tot);
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) partial[(size_t)j * gridDim.x + blockIdx.x] = tot[j];
-        __threadfence();
-        const unsigned int ticket = atomicAdd(counter, 1u);
-        last = (ticket == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
-
-// In the last block: totals[j] = sum of partial[j][*] in a fixed order.
-template <int NV>
-__device__ __forceinline__ void reduce_partials(const double* partial, double tot[NV]) {
-    double v[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
         double a = 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += kBlock)
-            a += __builtin_nontemporal_load(partial + (size_t)j * gridDim.x + b);
+#pragma unroll
+        for (int q = 0; q < NW; ++q) a += s[j][q];
         v[j] = a;
     }
-    block_sum<NV>(v, tot);
+    __syncthreads();
 }
 
-// Row r of a sliced-ELLPACK matrix times x.
+// Workgroup totals -> partial[j * gridDim.x + blockIdx.x].
+template <int NV, int BS = kBlock>
+__device__ __forceinline__ void write_partials(double v[NV], double* partial) {
+    block_sum_all<NV, BS>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) partial[(size_t)j * gridDim.x + blockIdx.x] = v[j];
+    }
+}
+
+// Sum of the partials a previous kernel of n_src workgroups wrote (fixed order).
+template <int NV, int BS = kBlock>
+__device__ __forceinline__ void read_partials(const double* partial, int n_src, double tot[NV]) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < n_src; b += BS) a += partial[(size_t)j * n_src + b];
+        tot[j] = a;
+    }
+    block_sum_all<NV, BS>(tot);
+}
+
+// Sum over the row's slots of A(j,c) * f(c), four slots in flight at a time so the column
+// and gather loads of a wavefront overlap (one thread per row, one wave per slice).
+template <typename GatherFn>
+__device__ __forceinline__ double sell_row(const int64_t* __restrict__ sp, const int32_t* __restrict__ col,
+                                           const double* __restrict__ A, int64_t row, GatherFn f) {
+    const int64_t sl = row >> 6;
+    const int lane = (int)(row & 63);
+    const int64_t k1 = sp[sl + 1];
+    int64_t k = sp[sl] + lane;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (; k + 3 * 64 < k1; k += 4 * 64) {
+        const int c0 = col[k], c1 = col[k + 64], c2 = col[k + 128], c3 = col[k + 192];
+        const double a0 = A[k], a1 = A[k + 64], a2 = A[k + 128], a3 = A[k + 192];
+        const double u0 = f(c0), u1 = f(c1), u2 = f(c2), u3 = f(c3);
+        acc0 += a0 * u0 + a2 * u2;
+        acc1 += a1 * u1 + a3 * u3;
+    }
+    for (; k < k1; k += 64) acc0 += A[k] * f(col[k]);
+    return acc0 + acc1;
+}
+
 __device__ __forceinline__ double sell_dot(const int64_t* __restrict__ sp, const int32_t* __restrict__ col,
                                            const double* __restrict__ val, const double* __restrict__ x,
                                            int64_t r) {
@@ -135,18 +172,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n_rows, const int64_t* 
     if (r < n_rows) y[r] = v;
 }
 
-// b = M (2 e - ep) - dt^2 S (c1 e + c2 ep) - (dg_new - dg_old), zero on boundary rows.
-__global__ __launch_bounds__(kBlock) void k_rhs(int64_t n_rows, int64_t nb_real, const int64_t* __restrict__ sp,
+// b = M (2 e - ep) - dt^2 S (c1 e + c2 ep) - (dg_new - dg_old), zero on boundary rows;
+// partials of ||b||^2.
+__global__ __launch_bounds__(kBlock) void k_rhs(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
                                                  const int32_t* __restrict__ col, const double* __restrict__ M,
                                                  const double* __restrict__ S, const double* __restrict__ e,
                                                  const double* __restrict__ ep, const double* __restrict__ dgn,
                                                  const double* __restrict__ dgo, const uint8_t* __restrict__ bmask,
                                                  double dt2, double c1, double c2, double* __restrict__ bvec,
-                                                 double* partial, CgScalars* sc, double tol) {
-    const int64_t lb = xcd_block(nb_real);
-    const int64_t r = lb * kBlock + threadIdx.x;
-    double bb = 0.0;
-    if (lb < nb_real && ((r >> 6) << 6) < n_rows) {
+                                                 double* __restrict__ partial) {
+    double bb[1] = {0.0};
+    for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
+        const int64_t r = lb * kBlock + threadIdx.x;
+        if (((r >> 6) << 6) >= n_rows) continue;
         const int64_t s = r >> 6;
         const int lane = (int)(r & 63);
         const int64_t k0 = sp[s], k1 = sp[s + 1];
@@ -161,19 +199,10 @@ __global__ __launch_bounds__(kBlock) void k_rhs(int64_t n_rows, int64_t nb_real,
             double v = am - dt2 * as - (dgn[r] - dgo[r]);
             if (bmask[r]) v = 0.0;
             bvec[r] = v;
-            bb = v * v;
+            bb[0] += v * v;
         }
     }
-    const double pv[1] = {bb};
-    if (publish_partials<1>(pv, partial, &sc->counter[0])) {
-        double tot[1];
-        reduce_partials<1>(partial, tot);
-        if (threadIdx.x == 0) {
-            sc->bb = tot[0];
-            sc->tol2_bb = tol * tol * tot[0];
-            sc->counter[0] = 0;
-        }
-    }
+    write_partials<1>(bb, partial);
 }
 
 __global__ __launch_bounds__(kBlock) void k_warm(int mode, int64_t n, const double* __restrict__ e,
@@ -187,122 +216,119 @@ __global__ __launch_bounds__(kBlock) void k_warm(int mode, int64_t n, const doub
     x[i] = v;
 }
 
-// r = b - A x, z = D^-1 r, p_old = 0; rz, rr.
-__global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n_rows, int64_t nb_real, const int64_t* __restrict__ sp,
-                                                     const int32_t* __restrict__ col, const double* __restrict__ A,
-                                                     const double* __restrict__ dinv, const double* __restrict__ b,
-                                                     const double* __restrict__ x, double* __restrict__ r,
-                                                     double* __restrict__ z, double* __restrict__ p,
-                                                     double* partial, CgScalars* sc) {
-    const int64_t lb = xcd_block(nb_real);
-    const int64_t row = lb * kBlock + threadIdx.x;
-    double rz = 0.0, rr = 0.0;
-    if (lb < nb_real && ((row >> 6) << 6) < n_rows) {
-        const double ax = sell_dot(sp, col, A, x, row);
+// Jacobi-preconditioned CG in the single-reduction form of Chronopoulos and Gear (1989):
+// with u = D^-1 r and w = A u kept by recurrence, one iteration needs the three dots
+// (r,u), (u,w), (r,r) of the previous iterate only, so it is one kernel:
+//   beta_i  = g_i / g_{i-1},   alpha_i = g_i / (d_i - beta_i g_i / alpha_{i-1})
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r' = r - alpha s,  u' = D^-1 r',
+//   w' = A u' (the neighbours' u' formed on the fly from the previous r, w, s),
+//   g_{i+1} = (r',u'), d_{i+1} = (u',w'), ||r'||^2.
+// The kernel keeps r, w and s scaled by D^-1 (R = D^-1 r, W = D^-1 w, S = D^-1 s, D =
+// diag A) so a neighbour's u' = R - alpha (W + beta S) costs three gathers.  R, W and S
+// are double buffered (neighbours read the previous values); p and x are touched by
+// their own row only.
+
+// ||b||^2 from the right-hand side's partials; R = D^-1 (b - A x); p = S = 0.
+__global__ __launch_bounds__(kBlock) void k_cg_init_a(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
+                                                       const int32_t* __restrict__ col, const double* __restrict__ A,
+                                                       const double* __restrict__ dinv, const double* __restrict__ b,
+                                                       const double* __restrict__ x, double* __restrict__ R,
+                                                       double* __restrict__ p, double* __restrict__ S,
+                                                       const double* __restrict__ part_rhs, CgScalars* sc, double tol) {
+    double bb[1];
+    read_partials<1>(part_rhs, gridDim.x, bb);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->bb = bb[0];
+        sc->tol2_bb = tol * tol * bb[0];
+        sc->converged = 0;
+    }
+    for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
+        const int64_t row = lb * kBlock + threadIdx.x;
+        if (((row >> 6) << 6) >= n_rows) continue;
+        const double ax = sell_row(sp, col, A, row, [&](int c) { return x[c]; });
         if (row < n_rows) {
-            const double rv = b[row] - ax;
-            const double zv = dinv[row] * rv;
-            r[row] = rv;
-            z[row] = zv;
+            R[row] = dinv[row] * (b[row] - ax);
             p[row] = 0.0;
-            rz = rv * zv;
-            rr = rv * rv;
-        }
-    }
-    const double pv[2] = {rz, rr};
-    if (publish_partials<2>(pv, partial, &sc->counter[1])) {
-        double tot[2];
-        reduce_partials<2>(partial, tot);
-        if (threadIdx.x == 0) {
-            sc->rz = tot[0];
-            sc->rr = tot[1];
-            sc->rr0 = tot[1];
-            sc->beta = 0.0;
-            sc->iters = 0;
-            sc->converged = (tot[1] <= sc->tol2_bb) ? 1 : 0;
-            sc->counter[1] = 0;
+            S[row] = 0.0;
         }
     }
 }
 
-// p_new = z + beta p_old (formed on the fly for the neighbours as well), q = A p_new,
-// p.q; the last block sets alpha = rz / pq.
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t n_rows, int64_t nb_real, const int64_t* __restrict__ sp,
-                                                     const int32_t* __restrict__ col, const double* __restrict__ A,
-                                                     const double* __restrict__ z, const double* __restrict__ p_old,
-                                                     double* __restrict__ p_new, double* __restrict__ q,
-                                                     double* partial, CgScalars* sc) {
-    if (sc->converged) return;
-    const double beta = sc->beta;
-    const int64_t lb = xcd_block(nb_real);
-    const int64_t row = lb * kBlock + threadIdx.x;
-    double pq = 0.0;
-    if (lb < nb_real && ((row >> 6) << 6) < n_rows) {
-        const int64_t s = row >> 6;
-        const int lane = (int)(row & 63);
-        const int64_t k0 = sp[s], k1 = sp[s + 1];
-        double acc = 0.0;
-        for (int64_t k = k0 + lane; k < k1; k += 64) {
-            const int c = col[k];
-            acc += A[k] * (z[c] + beta * p_old[c]);
-        }
+// W = D^-1 A u with u = R; partials of (r,u), (u,w), (r,r).
+__global__ __launch_bounds__(kBlock) void k_cg_init_b(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
+                                                       const int32_t* __restrict__ col, const double* __restrict__ A,
+                                                       const double* __restrict__ dinv, const double* __restrict__ R,
+                                                       double* __restrict__ W, double* __restrict__ partial) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
+        const int64_t row = lb * kBlock + threadIdx.x;
+        if (((row >> 6) << 6) >= n_rows) continue;
+        const double acc = sell_row(sp, col, A, row, [&](int c) { return R[c]; });
         if (row < n_rows) {
-            const double pn = z[row] + beta * p_old[row];
-            p_new[row] = pn;
-            q[row] = acc;
-            pq = pn * acc;
+            const double dj = dinv[row], uv = R[row], rv = uv / dj;
+            W[row] = dj * acc;
+            v[0] += rv * uv;
+            v[1] += uv * acc;
+            v[2] += rv * rv;
         }
     }
-    const double pv[1] = {pq};
-    if (publish_partials<1>(pv, partial, &sc->counter[2])) {
-        double tot[1];
-        reduce_partials<1>(partial, tot);
-        if (threadIdx.x == 0) {
-            if (tot[0] > 0.0) {
-                sc->alpha = sc->rz / tot[0];
-            } else {
-                sc->alpha = 0.0;
-                sc->converged = 2;  // breakdown: p = 0
-            }
-            sc->pq = tot[0];
-            sc->counter[2] = 0;
-        }
-    }
+    write_partials<3>(v, partial);
 }
 
-// x += alpha p, r -= alpha q, z = D^-1 r; rz, rr; the last block sets beta and tests
-// ||r||^2 <= tol^2 ||b||^2.
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n_rows, int64_t nb_real, const double* __restrict__ dinv,
-                                                       double* __restrict__ x, double* __restrict__ r,
-                                                       double* __restrict__ z, const double* __restrict__ p,
-                                                       const double* __restrict__ q, double* partial, CgScalars* sc) {
-    if (sc->converged) return;
-    const double alpha = sc->alpha;
-    const int64_t lb = xcd_block(nb_real);
-    const int64_t row = lb * kBlock + threadIdx.x;
-    double rz = 0.0, rr = 0.0;
-    if (lb < nb_real && row < n_rows) {
-        x[row] += alpha * p[row];
-        const double rv = r[row] - alpha * q[row];
-        const double zv = dinv[row] * rv;
-        r[row] = rv;
-        z[row] = zv;
-        rz = rv * zv;
-        rr = rv * rv;
+__global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, int i, const int64_t* __restrict__ sp,
+                                                     const int32_t* __restrict__ col, const double* __restrict__ A,
+                                                     const double* __restrict__ dinv, double* __restrict__ x,
+                                                     double* __restrict__ p, const double* __restrict__ R,
+                                                     const double* __restrict__ W, const double* __restrict__ S,
+                                                     double* __restrict__ R_new, double* __restrict__ W_new,
+                                                     double* __restrict__ S_new, const double* __restrict__ part_in,
+                                                     double* __restrict__ part_out, CgScalars* sc) {
+    // one read of the flag per workgroup, so all of its waves take the same branch
+    __shared__ int s_conv;
+    if (threadIdx.x == 0) s_conv = sc->converged;
+    __syncthreads();
+    if (s_conv) return;
+    double t[3];
+    read_partials<3>(part_in, gridDim.x, t);
+    const double g = t[0], d = t[1], rr = t[2];
+    const bool done = !(rr > sc->tol2_bb) || sc->bb == 0.0;
+    const double beta = (i == 0) ? 0.0 : g / sc->gam[(i - 1) & 1];
+    const double alpha = (i == 0) ? g / d : g / (d - beta * g / sc->alpha[(i - 1) & 1]);
+    const bool bad = !done && !(alpha > 0.0 && alpha < INFINITY && beta >= 0.0 && beta < INFINITY);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->gam[i & 1] = g;
+        sc->alpha[i & 1] = alpha;
+        sc->rr = rr;
+        sc->iters = i;
+        if (i == 0) sc->rr0 = rr;
+        if (done) sc->converged = 1;
+        if (bad) sc->converged = 2;
     }
-    const double pv[2] = {rz, rr};
-    if (publish_partials<2>(pv, partial, &sc->counter[3])) {
-        double tot[2];
-        reduce_partials<2>(partial, tot);
-        if (threadIdx.x == 0) {
-            sc->beta = tot[0] / sc->rz;
-            sc->rz = tot[0];
-            sc->rr = tot[1];
-            sc->iters += 1;
-            if (tot[1] <= sc->tol2_bb) sc->converged = 1;
-            sc->counter[3] = 0;
+    if (done || bad) return;
+    const double ab = alpha * beta;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
+        const int64_t row = lb * kBlock + threadIdx.x;
+        if (((row >> 6) << 6) >= n_rows) continue;
+        const double acc = sell_row(sp, col, A, row, [&](int c) { return R[c] - alpha * W[c] - ab * S[c]; });
+        if (row < n_rows) {
+            const double dj = dinv[row];
+            const double uj = R[row];
+            const double pj = uj + beta * p[row];
+            const double sj = W[row] + beta * S[row];   // D^-1 s
+            x[row] += alpha * pj;
+            const double un = uj - alpha * sj;          // D^-1 r' = u'
+            const double rn = un / dj;
+            p[row] = pj;
+            S_new[row] = sj;
+            R_new[row] = un;
+            W_new[row] = dj * acc;
+            v[0] += rn * un;
+            v[1] += un * acc;
+            v[2] += rn * rn;
         }
     }
+    write_partials<3>(v, part_out);
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero_if_b_zero(double* x, int64_t n, const CgScalars* sc) {
@@ -310,30 +336,29 @@ __global__ __launch_bounds__(kBlock) void k_zero_if_b_zero(double* x, int64_t n,
     if (i < n && sc->bb == 0.0) x[i] = 0.0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_resid(int64_t n_rows, int64_t nb_real, const int64_t* __restrict__ sp,
+__global__ __launch_bounds__(kBlock) void k_cg_resid(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
                                                       const int32_t* __restrict__ col, const double* __restrict__ A,
                                                       const double* __restrict__ b, const double* __restrict__ x,
-                                                      double* __restrict__ rt, double* partial, CgScalars* sc) {
-    const int64_t lb = xcd_block(nb_real);
-    const int64_t row = lb * kBlock + threadIdx.x;
-    double rr = 0.0;
-    if (lb < nb_real && ((row >> 6) << 6) < n_rows) {
-        const double ax = sell_dot(sp, col, A, x, row);
+                                                      double* __restrict__ rt, double* __restrict__ partial) {
+    double v[1] = {0.0};
+    for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
+        const int64_t row = lb * kBlock + threadIdx.x;
+        if (((row >> 6) << 6) >= n_rows) continue;
+        const double ax = sell_row(sp, col, A, row, [&](int c) { return x[c]; });
         if (row < n_rows) {
-            const double v = b[row] - ax;
-            rt[row] = v;
-            rr = v * v;
+            const double d = b[row] - ax;
+            rt[row] = d;
+            v[0] += d * d;
         }
     }
-    const double pv[1] = {rr};
-    if (publish_partials<1>(pv, partial, &sc->counter[0])) {
-        double tot[1];
-        reduce_partials<1>(partial, tot);
-        if (threadIdx.x == 0) {
-            sc->rr_true = tot[0];
-            sc->counter[0] = 0;
-        }
-    }
+    write_partials<1>(v, partial);
+}
+
+// One workgroup: sum n_src partials into *out.
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partial, int n_src, double* out) {
+    double t[1];
+    read_partials<1>(partial, n_src, t);
+    if (threadIdx.x == 0) *out = t[0];
 }
 
 // b_new = b_old - dt C (gamma e_new + (1 - gamma) e_old); face (i,j,k) has edges
@@ -399,21 +424,23 @@ __global__ __launch_bounds__(kBlock) void k_divb(int64_t n_tets, const int32_t* 
     atomic_max_abs(&acc->divb_max, d);
 }
 
-__global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
-                                                 double* partial, double* out, unsigned int* counter) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const double pv[1] = {i < n ? a[i] * b[i] : 0.0};
-    if (publish_partials<1>(pv, partial, counter)) {
-        double tot[1];
-        reduce_partials<1>(partial, tot);
-        if (threadIdx.x == 0) {
-            *out = tot[0];
-            *counter = 0;
-        }
+__global__ __launch_bounds__(kBlock) void k_dot(int64_t n, RowGrid rg, const double* __restrict__ a,
+                                                 const double* __restrict__ b, double* __restrict__ partial) {
+    double v[1] = {0.0};
+    for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
+        const int64_t i = lb * kBlock + threadIdx.x;
+        if (i < n) v[0] += a[i] * b[i];
     }
+    write_partials<1>(v, partial);
 }
 
+// Partial-buffer slots (each holds up to 3 values per workgroup of the largest grid).
+constexpr size_t kSlot = 4 * kMaxGrid;
+enum { SLOT_RHS = 0, SLOT_INIT, SLOT_SPMV, SLOT_UPD, SLOT_RESID, SLOT_DOT, SLOT_COUNT };
+
 }  // namespace
+
+size_t partial_buffer_doubles() { return SLOT_COUNT * kSlot; }
 
 // ------------------------------------------------------------------------- launchers
 void launch_fill(hipStream_t s, double* x, int64_t n, double v) {
@@ -426,26 +453,24 @@ void launch_axpby(hipStream_t s, double* y, const double* a, double alpha, const
     hipLaunchKernelGGL(k_axpby, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, y, a, alpha, b, beta, n);
 }
 
-static int64_t row_blocks(int64_t n_rows) { return (n_rows + kBlock - 1) / kBlock; }
-
 void launch_scale_A(hipStream_t s, const SellMatrix& shape, const int64_t* sp, const int32_t* col, const double* M,
                     const double* S, double* A, double* dinv, const uint8_t* bmask, double c) {
-    hipLaunchKernelGGL(k_scale_A, dim3((unsigned)row_blocks(shape.n_slices * kSell)), dim3(kBlock), 0, s,
-                       shape.n_rows, sp, col, M, S, A, dinv, bmask, c);
+    const int64_t rows = shape.n_slices * kSell;
+    hipLaunchKernelGGL(k_scale_A, dim3(grid_1d(rows, kBlock)), dim3(kBlock), 0, s, shape.n_rows, sp, col, M, S, A,
+                       dinv, bmask, c);
 }
 
 void launch_sell_spmv(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* val,
                       const double* x, double* y) {
-    hipLaunchKernelGGL(k_spmv, dim3((unsigned)row_blocks(n_rows)), dim3(kBlock), 0, s, n_rows, sp, col, val, x, y);
+    hipLaunchKernelGGL(k_spmv, dim3(grid_1d(n_rows, kBlock)), dim3(kBlock), 0, s, n_rows, sp, col, val, x, y);
 }
 
 void launch_rhs(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* M,
                 const double* S, const double* e, const double* ep, const double* dg_new, const double* dg_old,
-                const uint8_t* bmask, double dt2, double c1, double c2, double* b, double* partial, CgScalars* sc,
-                double tol) {
-    const int64_t nb = row_blocks(n_rows);
-    hipLaunchKernelGGL(k_rhs, dim3(xcd_grid(nb)), dim3(kBlock), 0, s, n_rows, nb, sp, col, M, S, e, ep, dg_new,
-                       dg_old, bmask, dt2, c1, c2, b, partial, sc, tol);
+                const uint8_t* bmask, double dt2, double c1, double c2, double* b, double* partial) {
+    const RowGrid rg = row_grid(n_rows);
+    hipLaunchKernelGGL(k_rhs, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, M, S, e, ep, dg_new, dg_old,
+                       bmask, dt2, c1, c2, b, partial + SLOT_RHS * kSlot);
 }
 
 void launch_warm(hipStream_t s, int mode, int64_t n, const double* e, const double* ep, const double* ep2, double* x) {
@@ -453,33 +478,43 @@ void launch_warm(hipStream_t s, int mode, int64_t n, const double* e, const doub
 }
 
 void launch_cg_init(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
-                    const double* dinv, const double* b, const double* x, double* r, double* z, double* p,
-                    double* partial, CgScalars* sc) {
-    const int64_t nb = row_blocks(n_rows);
-    hipLaunchKernelGGL(k_cg_init, dim3(xcd_grid(nb)), dim3(kBlock), 0, s, n_rows, nb, sp, col, A, dinv, b, x, r, z,
-                       p, partial, sc);
+                    const double* dinv, const double* b, const double* x, double* r, double* w, double* p, double* sv,
+                    double* partial, CgScalars* sc, double tol) {
+    const RowGrid rg = row_grid(n_rows);
+    hipLaunchKernelGGL(k_cg_init_a, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, dinv, b, x, r, p, sv,
+                       partial + SLOT_RHS * kSlot, sc, tol);
+    hipLaunchKernelGGL(k_cg_init_b, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, dinv, r, w,
+                       partial + SLOT_INIT * kSlot);
 }
 
-void launch_cg_iter(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
-                    const double* dinv, double* x, double* r, double* z, const double* p_old, double* p_new,
-                    double* q, double* partial, CgScalars* sc, hipEvent_t* ev_spmv, hipEvent_t* ev_upd) {
-    const int64_t nb = row_blocks(n_rows);
-    if (ev_spmv) (void)hipEventRecord(ev_spmv[0], s);
-    hipLaunchKernelGGL(k_cg_spmv, dim3(xcd_grid(nb)), dim3(kBlock), 0, s, n_rows, nb, sp, col, A, z, p_old, p_new, q,
-                       partial, sc);
-    if (ev_spmv) (void)hipEventRecord(ev_spmv[1], s);
-    if (ev_upd) (void)hipEventRecord(ev_upd[0], s);
-    hipLaunchKernelGGL(k_cg_update, dim3(xcd_grid(nb)), dim3(kBlock), 0, s, n_rows, nb, dinv, x, r, z, p_new, q,
-                       partial, sc);
-    if (ev_upd) (void)hipEventRecord(ev_upd[1], s);
+// Iteration i reads r, w, s from buffer i & 1 and writes buffer (i + 1) & 1.
+void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
+                    const double* dinv, double* x, double* p, double* const r[2], double* const w[2],
+                    double* const sv[2], double* partial, CgScalars* sc, hipEvent_t* ev) {
+    const RowGrid rg = row_grid(n_rows);
+    const int a = i & 1, b = 1 - a;
+    const double* part_in = partial + (i == 0 ? SLOT_INIT : (a ? SLOT_UPD : SLOT_SPMV)) * kSlot;
+    double* part_out = partial + (b ? SLOT_UPD : SLOT_SPMV) * kSlot;
+    if (ev) (void)hipEventRecord(ev[0], s);
+    hipLaunchKernelGGL(k_cg_iter, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, dinv, x, p, r[a],
+                       w[a], sv[a], r[b], w[b], sv[b], part_in, part_out, sc);
+    if (ev) (void)hipEventRecord(ev[1], s);
+}
+
+void launch_cg_rr0(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc) {
+    const RowGrid rg = row_grid(n_rows);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partial + SLOT_INIT * kSlot + 2 * rg.grid,
+                       (int)rg.grid, &sc->rr0);
 }
 
 void launch_cg_resid(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
                      const double* b, double* x, double* r_true, double* partial, CgScalars* sc) {
     hipLaunchKernelGGL(k_zero_if_b_zero, dim3(grid_1d(n_rows, kBlock)), dim3(kBlock), 0, s, x, n_rows, sc);
-    const int64_t nb = row_blocks(n_rows);
-    hipLaunchKernelGGL(k_cg_resid, dim3(xcd_grid(nb)), dim3(kBlock), 0, s, n_rows, nb, sp, col, A, b, x, r_true,
-                       partial, sc);
+    const RowGrid rg = row_grid(n_rows);
+    hipLaunchKernelGGL(k_cg_resid, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, b, x, r_true,
+                       partial + SLOT_RESID * kSlot);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partial + SLOT_RESID * kSlot, (int)rg.grid,
+                       &sc->rr_true);
 }
 
 void launch_faraday(hipStream_t s, int64_t n_faces, const int32_t* face_edges, const double* b_old,
@@ -504,9 +539,10 @@ void launch_divb(hipStream_t s, int64_t n_tets, const int32_t* tet_faces, const 
     hipLaunchKernelGGL(k_divb, dim3(grid_1d(n_tets, kBlock)), dim3(kBlock), 0, s, n_tets, tet_faces, b, acc);
 }
 
-void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial, double* out,
-                unsigned int* counter) {
-    hipLaunchKernelGGL(k_dot, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, n, a, b, partial, out, counter);
+void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial, double* out) {
+    const RowGrid rg = row_grid(n);
+    hipLaunchKernelGGL(k_dot, dim3(rg.grid), dim3(kBlock), 0, s, n, rg, a, b, partial + SLOT_DOT * kSlot);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partial + SLOT_DOT * kSlot, (int)rg.grid, out);
 }
 
 }  // namespace fepic

@@ -86,6 +86,7 @@ _SIGS = {
     "fepic_init_electrostatic": [_P, _D, ctypes.POINTER(_INT)],
     "fepic_add_species": [_P, _D, _D, _D, ctypes.POINTER(_INT)],
     "fepic_upload_particles": [_P, _INT, _I64, _P, _P, _P, _PI64],
+    "fepic_inject_particles": [_P, _INT, _I64, _P, _P, _P],
     "fepic_num_particles": [_P, _INT, _PI64],
     "fepic_get_particles": [_P, _INT, _I64, _PI64, _P, _P, _P, _P, _P],
     "fepic_step": [_P, _D, _D, _D, ctypes.POINTER(fepic_step_stats)],
@@ -243,6 +244,13 @@ def fepic_upload_particles(ctx, species, x, u, ids=None):
     rej = ctypes.c_int64()
     _check(ctx, lib().fepic_upload_particles(ctx, species, len(x), _ptr(ids), _ptr(x), _ptr(u), ctypes.byref(rej)))
     return rej.value
+
+
+def fepic_inject_particles(ctx, species, x, u, ids=None):
+    x = _arr(x, np.float64, (-1, 3))
+    u = _arr(u, np.float64, (-1, 3))
+    ids = None if ids is None else _arr(ids, np.int64)
+    _check(ctx, lib().fepic_inject_particles(ctx, species, len(x), _ptr(ids), _ptr(x), _ptr(u)))
 
 
 def fepic_num_particles(ctx, species):
