@@ -205,10 +205,10 @@ int fepic_kernel_time(fepic_ctx* ctx, const char* family, double* total_ms, int6
  * accumulation.  Inputs per interior edge: [e^n, e^{n-1}, e^{n-2}] / s_e and dG^{n+1} / s_g
  * with s_e, s_g the RMS over interior edges (1 if zero); prediction x0 = e^n + s_e y.
  * Flat FP32 weight layout: W1[64][4], b1[64], W2[64][64], b2[64], W3[1][64], b3[1]
- * (4481 values).  The PCG always runs to cg_tol from whatever start, so the network only
+ * (4545 values).  The PCG always runs to cg_tol from whatever start, so the network only
  * changes the iteration count, never the accuracy; a non-finite prediction or one whose
  * residual exceeds ||b|| falls back to e^n. */
-#define FEPIC_MLP_N_PARAMS 4481
+#define FEPIC_MLP_N_PARAMS 4545
 typedef struct {
     int epochs;          /* passes over the recorded samples                       */
     int64_t batch;       /* rows per minibatch (multiple of 64)                    */
@@ -230,7 +230,7 @@ int fepic_ws_get_weights(fepic_ctx* ctx, float* w, int64_t cap, int64_t* n);
 int fepic_ws_set_weights(fepic_ctx* ctx, const float* w, int64_t n);
 int fepic_set_warm_start(fepic_ctx* ctx, int mode);
 /* Test entries on host batches: X [n][4] FP32 -> y [n]; gradient of the mean squared
- * error against t [n] -> grad [4481] and *loss, computed by the device kernels. */
+ * error against t [n] -> grad [4545] and *loss, computed by the device kernels. */
 int fepic_mlp_forward(fepic_ctx* ctx, int64_t n, const float* X, float* y);
 int fepic_mlp_grad(fepic_ctx* ctx, int64_t n, const float* X, const float* t, float* grad, double* loss);
 

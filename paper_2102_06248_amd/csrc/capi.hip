@@ -1115,6 +1115,113 @@ int fepic_diagnostics(fepic_ctx* c, fepic_step_stats* out) {
     return rc;
 }
 
+// Checkpoint: "FEPICCK1", sizes, step/time, fields and histories, species and their
+// particles (buffer in use, live entries only), then the warm-start network.
+int fepic_save(fepic_ctx* c, const char* path) {
+    NEED_DEV(c);
+    if (!path) return FEPIC_E_ARG;
+    int rc = sync_counts(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(c, FEPIC_E_IO, std::string("cannot open ") + path);
+    const HostMesh& m = c->mesh;
+    bool ok = true;
+    auto W = [&](const void* p, size_t n) { ok = ok && std::fwrite(p, 1, n, f) == n; };
+    W("FEPICCK1", 8);
+    const int64_t hdr[6] = {m.n_nodes, m.n_tets, m.n_edges, m.n_faces, (int64_t)c->species.size(),
+                            c->opt.precision};
+    W(hdr, sizeof(hdr));
+    W(&c->step_count, 8);
+    W(&c->time, 8);
+    std::vector<double> buf(std::max(m.n_edges, m.n_faces));
+    auto dump = [&](const double* d, int64_t n) {
+        if (hipMemcpy(buf.data(), d, 8 * n, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+        W(buf.data(), 8 * n);
+    };
+    for (const double* d : {c->d_e, c->d_ep, c->d_ep2, c->d_dg, c->d_G}) dump(d, m.n_edges);
+    dump(c->d_b, m.n_faces);
+    for (auto& s : c->species) {
+        W(&s.q, 8);
+        W(&s.m, 8);
+        W(&s.w, 8);
+        W(&s.n, 8);
+        W(&s.next_id, 8);
+        for (int a = 0; a < 8; ++a) {
+            const size_t nb = array_bytes(c, a, s.n);
+            std::vector<unsigned char> tmp(nb);
+            if (nb && hipMemcpy(tmp.data(), s.buf[s.cur][a], nb, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+            W(tmp.data(), nb);
+        }
+    }
+    if (ok) ok = mlp_save(c, f) == FEPIC_OK;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? FEPIC_OK : fail(c, FEPIC_E_IO, std::string("write failed: ") + path);
+}
+
+int fepic_load(fepic_ctx* c, const char* path) {
+    NEED_DEV(c);
+    if (!path) return FEPIC_E_ARG;
+    int rc = sync_counts(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(c, FEPIC_E_IO, std::string("cannot open ") + path);
+    const HostMesh& m = c->mesh;
+    bool ok = true;
+    auto R = [&](void* p, size_t n) { ok = ok && std::fread(p, 1, n, f) == n; };
+    char magic[8];
+    R(magic, 8);
+    int64_t hdr[6];
+    R(hdr, sizeof(hdr));
+    if (!ok || std::memcmp(magic, "FEPICCK1", 8) || hdr[0] != m.n_nodes || hdr[1] != m.n_tets ||
+        hdr[2] != m.n_edges || hdr[3] != m.n_faces || hdr[4] != (int64_t)c->species.size() ||
+        hdr[5] != c->opt.precision) {
+        std::fclose(f);
+        return fail(c, FEPIC_E_IO, "checkpoint does not match this context (mesh, species or precision)");
+    }
+    R(&c->step_count, 8);
+    R(&c->time, 8);
+    std::vector<double> buf(std::max(m.n_edges, m.n_faces));
+    auto fill = [&](double* d, int64_t n) {
+        R(buf.data(), 8 * n);
+        if (ok && hipMemcpy(d, buf.data(), 8 * n, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    };
+    for (double* d : {c->d_e, c->d_ep, c->d_ep2, c->d_dg, c->d_G}) fill(d, m.n_edges);
+    fill(c->d_b, m.n_faces);
+    for (auto& s : c->species) {
+        double q, mm, w;
+        int64_t n, next_id;
+        R(&q, 8);
+        R(&mm, 8);
+        R(&w, 8);
+        R(&n, 8);
+        R(&next_id, 8);
+        if (!ok || q != s.q || mm != s.m || w != s.w || n < 0) {
+            std::fclose(f);
+            return fail(c, FEPIC_E_IO, "checkpoint species differ from this context's");
+        }
+        if ((rc = ensure_capacity(c, s, n))) {
+            std::fclose(f);
+            return rc;
+        }
+        for (int a = 0; a < 8; ++a) {
+            const size_t nb = array_bytes(c, a, n);
+            std::vector<unsigned char> tmp(nb);
+            R(tmp.data(), nb);
+            if (ok && nb && hipMemcpy(s.buf[s.cur][a], tmp.data(), nb, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+        }
+        s.n = n;
+        s.next_id = next_id;
+        s.sorted_pending = false;
+    }
+    if (ok) ok = mlp_load(c, f) == FEPIC_OK;
+    std::fclose(f);
+    c->rho_valid = false;
+    c->rG_levels = 0;
+    return ok ? FEPIC_OK : fail(c, FEPIC_E_IO, std::string("read failed: ") + path);
+}
+
 int fepic_kernel_timing(fepic_ctx* c, const char* family, int enable) {
     if (!c || !family) return FEPIC_E_ARG;
     if (c->host_only) return fail(c, FEPIC_E_NO_DEVICE, "host-only context");

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -106,6 +107,12 @@ struct fepic_ctx {
     int64_t mlp_fallbacks = 0;
 };
 
+#define HIPCHK_RET(c, expr)                                          \
+    do {                                                             \
+        hipError_t e_ = (expr);                                      \
+        if (e_ != hipSuccess) return fepic::hip_fail(c, e_, #expr); \
+    } while (0)
+
 namespace fepic {
 int hip_fail(fepic_ctx* c, hipError_t e, const char* what);
 int fail(fepic_ctx* c, int code, const std::string& msg);
@@ -118,4 +125,6 @@ int mlp_warm_start(fepic_ctx* c);
 int mlp_record_features(fepic_ctx* c);
 int mlp_record_target(fepic_ctx* c);
 void mlp_destroy(fepic_ctx* c);
+int mlp_save(fepic_ctx* c, std::FILE* f);
+int mlp_load(fepic_ctx* c, std::FILE* f);
 }  // namespace fepic

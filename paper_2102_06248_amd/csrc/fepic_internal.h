@@ -142,25 +142,19 @@ void launch_diag_nodes(hipStream_t s, int64_t n_nodes, const uint8_t* interior_n
 void launch_divb(hipStream_t s, int64_t n_tets, const int32_t* tet_faces, const double* b, DiagAcc* acc);
 void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial, double* out);
 size_t partial_buffer_doubles();
+void launch_line_start(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* A,
+                       const double* b, const double* e, const double* d, double* partial, double* theta, double* x);
 
 // Learned warm start (kernels_mlp.hip).
-struct MlpDevice;
-void mlp_launch_features(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e,
-                         const double* ep, const double* ep2, const double* dg, const double* scales,
-                         float* X);
 void mlp_launch_rms(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e, const double* dg,
-                    double* partial, double* scales, unsigned int* counter);
+                    double* scales);
+void mlp_launch_features(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e,
+                         const double* ep, const double* ep2, const double* dg, const double* scales, float* X);
 void mlp_launch_forward(hipStream_t s, int64_t n, const float* X, const float* params_f32, float* y);
-void mlp_launch_apply(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e, const float* y,
-                      const double* scales, double* x);
-void mlp_launch_grad(hipStream_t s, int64_t n, const float* X, const float* target, const float* params_f32,
-                     float* grad, double* loss_acc);
-void mlp_launch_adam(hipStream_t s, int64_t n, float* params, const float* grad, float* m, float* v, float lr,
-                     float b1, float b2, float eps, float bc1, float bc2);
+void mlp_launch_direction(hipStream_t s, int64_t n_int, const int32_t* int_edges, const float* y,
+                          const double* scales, double* d);
 void mlp_launch_target(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e_new,
                        const double* e, const double* scales, float* t);
-void mlp_launch_gather_rows(hipStream_t s, int64_t n, const int64_t* rows, const float* Xall, const float* Tall,
-                            float* X, float* T);
 
 int grid_1d(int64_t n, int block);
 

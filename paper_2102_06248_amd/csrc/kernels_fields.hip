@@ -434,6 +434,41 @@ __global__ __launch_bounds__(kBlock) void k_dot(int64_t n, RowGrid rg, const dou
     write_partials<1>(v, partial);
 }
 
+// Energy-norm step along a given direction d from e: x = e + theta d with
+// theta = d.(b - A e) / d.A d = (b.d - e.(A d)) / (d.A d) (A symmetric), the minimiser of
+// the A-norm error over the line, so x is never farther from the solution than e.
+__global__ __launch_bounds__(kBlock) void k_line_dots(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
+                                                       const int32_t* __restrict__ col, const double* __restrict__ A,
+                                                       const double* __restrict__ b, const double* __restrict__ e,
+                                                       const double* __restrict__ d, double* __restrict__ partial) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
+        const int64_t row = lb * kBlock + threadIdx.x;
+        if (((row >> 6) << 6) >= n_rows) continue;
+        const double ad = sell_row(sp, col, A, row, [&](int c) { return d[c]; });
+        if (row < n_rows) {
+            v[0] += b[row] * d[row];
+            v[1] += e[row] * ad;
+            v[2] += d[row] * ad;
+        }
+    }
+    write_partials<3>(v, partial);
+}
+
+__global__ __launch_bounds__(kBlock) void k_line_theta(const double* __restrict__ partial, int n_src,
+                                                        double* __restrict__ theta) {
+    double t[3];
+    read_partials<3>(partial, n_src, t);
+    if (threadIdx.x == 0) theta[0] = (t[2] > 0.0 && isfinite(t[0] - t[1])) ? (t[0] - t[1]) / t[2] : 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_line_apply(int64_t n, const double* __restrict__ e,
+                                                        const double* __restrict__ d,
+                                                        const double* __restrict__ theta, double* __restrict__ x) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] = e[i] + theta[0] * d[i];
+}
+
 // Partial-buffer slots (each holds up to 3 values per workgroup of the largest grid).
 constexpr size_t kSlot = 4 * kMaxGrid;
 enum { SLOT_RHS = 0, SLOT_INIT, SLOT_SPMV, SLOT_UPD, SLOT_RESID, SLOT_DOT, SLOT_COUNT };
@@ -537,6 +572,15 @@ void launch_diag_nodes(hipStream_t s, int64_t n_nodes, const uint8_t* interior_n
 
 void launch_divb(hipStream_t s, int64_t n_tets, const int32_t* tet_faces, const double* b, DiagAcc* acc) {
     hipLaunchKernelGGL(k_divb, dim3(grid_1d(n_tets, kBlock)), dim3(kBlock), 0, s, n_tets, tet_faces, b, acc);
+}
+
+void launch_line_start(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
+                       const double* b, const double* e, const double* d, double* partial, double* theta, double* x) {
+    const RowGrid rg = row_grid(n_rows);
+    hipLaunchKernelGGL(k_line_dots, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, b, e, d,
+                       partial + SLOT_DOT * kSlot);
+    hipLaunchKernelGGL(k_line_theta, dim3(1), dim3(kBlock), 0, s, partial + SLOT_DOT * kSlot, (int)rg.grid, theta);
+    hipLaunchKernelGGL(k_line_apply, dim3(grid_1d(n_rows, kBlock)), dim3(kBlock), 0, s, n_rows, e, d, theta, x);
 }
 
 void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial, double* out) {

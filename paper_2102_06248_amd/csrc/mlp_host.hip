@@ -1,26 +1,386 @@
-// Learned warm start: host side (placeholder until the MFMA kernels land).
+// Learned warm start (host side) and checkpoint files.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <vector>
+
 #include "ctx.h"
 
 namespace fepic {
-int mlp_warm_start(fepic_ctx* c) { return fail(c, FEPIC_E_STATE, "learned warm start not built"); }
-int mlp_record_features(fepic_ctx* c) { return fail(c, FEPIC_E_STATE, "recording not built"); }
-int mlp_record_target(fepic_ctx* c) { return fail(c, FEPIC_E_STATE, "recording not built"); }
-void mlp_destroy(fepic_ctx*) {}
+
+int mlp_grad_blocks(int64_t n);
+void mlp_launch_grad(hipStream_t s, const float* X, const float* T, int64_t n, int64_t n_all, uint64_t seed,
+                     const float* P, float* part, double* loss_part, int blocks);
+void mlp_launch_reduce_adam(hipStream_t s, const float* part, int blocks, float* grad, float* P, float* m, float* v,
+                            int adam, float lr, float b1, float b2, float eps, float bc1, float bc2);
+
+constexpr int kNP = FEPIC_MLP_N_PARAMS;
+constexpr int kMaxGradBlocks = 512;
+
+struct MlpState {
+    float* P = nullptr;      // FP32 master weights
+    float* m = nullptr;      // Adam moments
+    float* v = nullptr;
+    float* grad = nullptr;
+    float* part = nullptr;   // [kMaxGradBlocks][kNP]
+    double* loss_part = nullptr;
+    double* scales = nullptr;  // s_e, s_g of the current step
+    float* Xcur = nullptr;   // features of the current step [n_int][4]
+    float* ycur = nullptr;
+    // recording ring
+    float* Xrec = nullptr;   // [cap][n_int][4]
+    float* Trec = nullptr;   // [cap][n_int]
+    int64_t cap = 0, count = 0, head = 0;
+    int64_t adam_t = 0;
+    bool have_weights = false;
+    // scratch for host batches
+    float* Xh = nullptr;
+    float* Th = nullptr;
+    int64_t h_cap = 0;
+};
+
+static int ensure_mlp(fepic_ctx* c) {
+    if (c->host_only) return fail(c, FEPIC_E_NO_DEVICE, "host-only context");
+    if (!c->have_mesh) return fail(c, FEPIC_E_STATE, "no mesh uploaded");
+    if (c->mlp) return FEPIC_OK;
+    MlpState* s = new MlpState();
+    const int64_t ni = std::max<int64_t>(c->mesh.n_int_edges, 1);
+    s->P = (float*)dmalloc(c, sizeof(float) * kNP);
+    s->m = (float*)dmalloc(c, sizeof(float) * kNP);
+    s->v = (float*)dmalloc(c, sizeof(float) * kNP);
+    s->grad = (float*)dmalloc(c, sizeof(float) * kNP);
+    s->part = (float*)dmalloc(c, sizeof(float) * kNP * kMaxGradBlocks);
+    s->loss_part = (double*)dmalloc(c, sizeof(double) * kMaxGradBlocks);
+    s->scales = (double*)dmalloc(c, sizeof(double) * 3);  // s_e, s_g, line step
+    s->Xcur = (float*)dmalloc(c, sizeof(float) * 4 * ni);
+    s->ycur = (float*)dmalloc(c, sizeof(float) * ni);
+    c->mlp = s;
+    if (!s->P || !s->m || !s->v || !s->grad || !s->part || !s->loss_part || !s->scales || !s->Xcur || !s->ycur)
+        return fail(c, FEPIC_E_OOM, "device allocation failed");
+    return FEPIC_OK;
+}
+
+// He-uniform weights (scaled output layer), zero biases; Adam state cleared.
+static int init_weights(fepic_ctx* c, uint64_t seed) {
+    std::vector<float> w(kNP, 0.f);
+    std::mt19937_64 gen(seed);
+    auto fill = [&](int off, int n, int fan_in, float scale) {
+        std::uniform_real_distribution<float> U(-std::sqrt(6.f / fan_in), std::sqrt(6.f / fan_in));
+        for (int i = 0; i < n; ++i) w[off + i] = scale * U(gen);
+    };
+    fill(0, 256, 4, 1.f);
+    fill(320, 4096, 64, 1.f);
+    fill(4480, 64, 64, 0.1f);
+    MlpState* s = c->mlp;
+    if (hipMemcpy(s->P, w.data(), sizeof(float) * kNP, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(s->m, 0, sizeof(float) * kNP) != hipSuccess || hipMemset(s->v, 0, sizeof(float) * kNP) != hipSuccess)
+        return fail(c, FEPIC_E_HIP, "weight upload failed");
+    s->adam_t = 0;
+    s->have_weights = true;
+    return FEPIC_OK;
+}
+
+// Scales and features of the current step (e^n, e^{n-1}, e^{n-2}, dG^{n+1}) into dst.
+static void features_into(fepic_ctx* c, float* dst) {
+    MlpState* s = c->mlp;
+    const int64_t ni = c->mesh.n_int_edges;
+    mlp_launch_rms(c->stream, ni, c->d_int_edges, c->d_e, c->d_dgn, s->scales);
+    mlp_launch_features(c->stream, ni, c->d_int_edges, c->d_e, c->d_ep, c->d_ep2, c->d_dgn, s->scales, dst);
+}
+
+int mlp_warm_start(fepic_ctx* c) {
+    int rc = ensure_mlp(c);
+    if (rc) return rc;
+    MlpState* s = c->mlp;
+    const int64_t ni = c->mesh.n_int_edges;
+    features_into(c, s->Xcur);
+    hipEvent_t* ev = timer_pair(c, FAM_MLP_FWD);
+    if (ev) (void)hipEventRecord(ev[0], c->stream);
+    mlp_launch_forward(c->stream, ni, s->Xcur, s->P, s->ycur);
+    if (ev) (void)hipEventRecord(ev[1], c->stream);
+    // the prediction is used as a search direction: x0 = e^n + theta d with the
+    // energy-norm-optimal theta (never worse than x0 = e^n in the A-norm)
+    double* d = c->d_Me;  // work vector, free during the solve
+    launch_fill(c->stream, d, c->mesh.n_edges, 0.0);
+    mlp_launch_direction(c->stream, ni, c->d_int_edges, s->ycur, s->scales, d);
+    launch_line_start(c->stream, c->mesh.n_edges, c->d_sp, c->d_col, c->d_A, c->d_rhs, c->d_e, d, c->d_partial,
+                      s->scales + 2, c->d_x);
+    return FEPIC_OK;
+}
+
+int mlp_record_features(fepic_ctx* c) {
+    int rc = ensure_mlp(c);
+    if (rc) return rc;
+    MlpState* s = c->mlp;
+    if (s->cap == 0) return FEPIC_OK;
+    const int64_t ni = c->mesh.n_int_edges;
+    float* dst = s->Xrec + (size_t)s->head * ni * 4;
+    if (c->opt.warm_start == FEPIC_WS_MLP && c->mlp_ready)
+        HIPCHK_RET(c, hipMemcpyAsync(dst, s->Xcur, sizeof(float) * 4 * ni, hipMemcpyDeviceToDevice, c->stream));
+    else
+        features_into(c, dst);
+    return FEPIC_OK;
+}
+
+int mlp_record_target(fepic_ctx* c) {
+    MlpState* s = c->mlp;
+    if (!s || s->cap == 0) return FEPIC_OK;
+    const int64_t ni = c->mesh.n_int_edges;
+    mlp_launch_target(c->stream, ni, c->d_int_edges, c->d_x, c->d_e, s->scales, s->Trec + (size_t)s->head * ni);
+    s->head = (s->head + 1) % s->cap;
+    s->count = std::min(s->count + 1, s->cap);
+    return FEPIC_OK;
+}
+
+// Device buffers of the state are owned by the context's allocation list.
+void mlp_destroy(fepic_ctx* c) {
+    delete c->mlp;
+    c->mlp = nullptr;
+}
+
+int mlp_save(fepic_ctx* c, std::FILE* f) {
+    const int32_t have = (c->mlp && c->mlp->have_weights) ? 1 : 0;
+    if (std::fwrite(&have, 4, 1, f) != 1) return FEPIC_E_IO;
+    if (!have) return FEPIC_OK;
+    std::vector<float> w(3 * kNP);
+    HIPCHK_RET(c, hipStreamSynchronize(c->stream));
+    HIPCHK_RET(c, hipMemcpy(w.data(), c->mlp->P, sizeof(float) * kNP, hipMemcpyDeviceToHost));
+    HIPCHK_RET(c, hipMemcpy(w.data() + kNP, c->mlp->m, sizeof(float) * kNP, hipMemcpyDeviceToHost));
+    HIPCHK_RET(c, hipMemcpy(w.data() + 2 * kNP, c->mlp->v, sizeof(float) * kNP, hipMemcpyDeviceToHost));
+    const int64_t t = c->mlp->adam_t;
+    const int32_t ready = c->mlp_ready ? 1 : 0;
+    if (std::fwrite(w.data(), sizeof(float), w.size(), f) != w.size() || std::fwrite(&t, 8, 1, f) != 1 ||
+        std::fwrite(&ready, 4, 1, f) != 1)
+        return FEPIC_E_IO;
+    return FEPIC_OK;
+}
+
+int mlp_load(fepic_ctx* c, std::FILE* f) {
+    int32_t have = 0;
+    if (std::fread(&have, 4, 1, f) != 1) return FEPIC_E_IO;
+    if (!have) return FEPIC_OK;
+    int rc = ensure_mlp(c);
+    if (rc) return rc;
+    std::vector<float> w(3 * kNP);
+    int64_t t = 0;
+    int32_t ready = 0;
+    if (std::fread(w.data(), sizeof(float), w.size(), f) != w.size() || std::fread(&t, 8, 1, f) != 1 ||
+        std::fread(&ready, 4, 1, f) != 1)
+        return FEPIC_E_IO;
+    HIPCHK_RET(c, hipMemcpy(c->mlp->P, w.data(), sizeof(float) * kNP, hipMemcpyHostToDevice));
+    HIPCHK_RET(c, hipMemcpy(c->mlp->m, w.data() + kNP, sizeof(float) * kNP, hipMemcpyHostToDevice));
+    HIPCHK_RET(c, hipMemcpy(c->mlp->v, w.data() + 2 * kNP, sizeof(float) * kNP, hipMemcpyHostToDevice));
+    c->mlp->adam_t = t;
+    c->mlp->have_weights = true;
+    c->mlp_ready = ready != 0;
+    return FEPIC_OK;
+}
+
+// Loss of the current weights on explicit device rows (mean squared error).
+static int eval_loss(fepic_ctx* c, const float* X, const float* T, int64_t n, double* loss) {
+    MlpState* s = c->mlp;
+    if (n <= 0) {
+        *loss = 0.0;
+        return FEPIC_OK;
+    }
+    const int blocks = std::min(mlp_grad_blocks(n), kMaxGradBlocks);
+    mlp_launch_grad(c->stream, X, T, n, 0, 0, s->P, s->part, s->loss_part, blocks);
+    std::vector<double> lp(blocks);
+    HIPCHK_RET(c, hipMemcpyAsync(lp.data(), s->loss_part, sizeof(double) * blocks, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK_RET(c, hipStreamSynchronize(c->stream));
+    double a = 0.0;
+    for (double v : lp) a += v;
+    *loss = a / (double)n;
+    return FEPIC_OK;
+}
+
+static int host_batch(fepic_ctx* c, int64_t n, const float* X, const float* T) {
+    MlpState* s = c->mlp;
+    if (n > s->h_cap) {
+        dfree(c, s->Xh);
+        dfree(c, s->Th);
+        s->Xh = (float*)dmalloc(c, sizeof(float) * 4 * n);
+        s->Th = (float*)dmalloc(c, sizeof(float) * n);
+        if (!s->Xh || !s->Th) return fail(c, FEPIC_E_OOM, "device allocation failed");
+        s->h_cap = n;
+    }
+    HIPCHK_RET(c, hipMemcpy(s->Xh, X, sizeof(float) * 4 * n, hipMemcpyHostToDevice));
+    if (T) HIPCHK_RET(c, hipMemcpy(s->Th, T, sizeof(float) * n, hipMemcpyHostToDevice));
+    return FEPIC_OK;
+}
+
 }  // namespace fepic
 
+using namespace fepic;
+
 extern "C" {
-int fepic_ws_record(fepic_ctx* c, int, int64_t) { return c ? fepic::fail(c, FEPIC_E_STATE, "not built") : FEPIC_E_ARG; }
-int fepic_ws_num_snapshots(fepic_ctx* c, int64_t* n) { if (n) *n = 0; return c ? FEPIC_OK : FEPIC_E_ARG; }
-int fepic_ws_train(fepic_ctx* c, const fepic_train_opts*, fepic_train_stats*) { return c ? fepic::fail(c, FEPIC_E_STATE, "not built") : FEPIC_E_ARG; }
-int fepic_ws_get_weights(fepic_ctx* c, float*, int64_t, int64_t*) { return c ? fepic::fail(c, FEPIC_E_STATE, "not built") : FEPIC_E_ARG; }
-int fepic_ws_set_weights(fepic_ctx* c, const float*, int64_t) { return c ? fepic::fail(c, FEPIC_E_STATE, "not built") : FEPIC_E_ARG; }
+
+int fepic_ws_record(fepic_ctx* c, int on, int64_t max_snapshots) {
+    if (!c) return FEPIC_E_ARG;
+    int rc = ensure_mlp(c);
+    if (rc) return rc;
+    MlpState* s = c->mlp;
+    if (on && max_snapshots > 0 && max_snapshots != s->cap) {
+        const int64_t ni = c->mesh.n_int_edges;
+        dfree(c, s->Xrec);
+        dfree(c, s->Trec);
+        s->Xrec = (float*)dmalloc(c, sizeof(float) * 4 * ni * max_snapshots);
+        s->Trec = (float*)dmalloc(c, sizeof(float) * ni * max_snapshots);
+        if (!s->Xrec || !s->Trec) {
+            s->cap = 0;
+            return fail(c, FEPIC_E_OOM, "recording buffer allocation failed");
+        }
+        s->cap = max_snapshots;
+        s->count = s->head = 0;
+    }
+    if (on && s->cap == 0) return fail(c, FEPIC_E_ARG, "recording needs max_snapshots > 0");
+    c->recording = on != 0;
+    return FEPIC_OK;
+}
+
+int fepic_ws_num_snapshots(fepic_ctx* c, int64_t* n) {
+    if (!c || !n) return FEPIC_E_ARG;
+    *n = c->mlp ? c->mlp->count : 0;
+    return FEPIC_OK;
+}
+
+int fepic_ws_train(fepic_ctx* c, const fepic_train_opts* o, fepic_train_stats* out) {
+    if (!c || !o) return FEPIC_E_ARG;
+    int rc = ensure_mlp(c);
+    if (rc) return rc;
+    MlpState* s = c->mlp;
+    const int64_t ni = c->mesh.n_int_edges;
+    if (s->count < 1 || ni == 0) return fail(c, FEPIC_E_STATE, "no recorded snapshots");
+    if (o->epochs < 1 || o->batch < 64 || !(o->lr > 0)) return fail(c, FEPIC_E_ARG, "bad training options");
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!s->have_weights && (rc = init_weights(c, o->seed))) return rc;
+    // the ring's oldest snapshots train, the newest val_fraction validate
+    int64_t n_val_snap = (int64_t)std::floor(o->val_fraction * (double)s->count);
+    if (s->count > 1) n_val_snap = std::max<int64_t>(std::min(n_val_snap, s->count - 1), o->val_fraction > 0 ? 1 : 0);
+    else n_val_snap = 0;
+    const int64_t n_tr_snap = s->count - n_val_snap;
+    // make the ring contiguous in time order: rotate so the oldest snapshot is first
+    if (s->count == s->cap && s->head != 0) {
+        std::vector<float> tmpX((size_t)4 * ni * s->cap), tmpT((size_t)ni * s->cap);
+        HIPCHK_RET(c, hipStreamSynchronize(c->stream));
+        HIPCHK_RET(c, hipMemcpy(tmpX.data(), s->Xrec, sizeof(float) * tmpX.size(), hipMemcpyDeviceToHost));
+        HIPCHK_RET(c, hipMemcpy(tmpT.data(), s->Trec, sizeof(float) * tmpT.size(), hipMemcpyDeviceToHost));
+        std::rotate(tmpX.begin(), tmpX.begin() + (size_t)4 * ni * s->head, tmpX.end());
+        std::rotate(tmpT.begin(), tmpT.begin() + (size_t)ni * s->head, tmpT.end());
+        HIPCHK_RET(c, hipMemcpy(s->Xrec, tmpX.data(), sizeof(float) * tmpX.size(), hipMemcpyHostToDevice));
+        HIPCHK_RET(c, hipMemcpy(s->Trec, tmpT.data(), sizeof(float) * tmpT.size(), hipMemcpyHostToDevice));
+        s->head = 0;
+    }
+    const int64_t n_tr = n_tr_snap * ni, n_val = n_val_snap * ni;
+    const float* Xtr = s->Xrec;
+    const float* Ttr = s->Trec;
+    const float* Xva = s->Xrec + (size_t)4 * n_tr;
+    const float* Tva = s->Trec + (size_t)n_tr;
+    const int64_t batch = (o->batch / 64) * 64;
+    const int64_t steps_per_epoch = std::max<int64_t>(1, n_tr / batch);
+    const int blocks = std::min(mlp_grad_blocks(batch), kMaxGradBlocks);
+    const float b1 = (float)(o->beta1 > 0 ? o->beta1 : 0.9), b2 = (float)(o->beta2 > 0 ? o->beta2 : 0.999);
+    const float eps = (float)(o->eps > 0 ? o->eps : 1e-8);
+    int64_t steps = 0;
+    for (int ep = 0; ep < o->epochs; ++ep) {
+        for (int64_t k = 0; k < steps_per_epoch; ++k) {
+            s->adam_t++;
+            const uint64_t seed = o->seed * 0x9E3779B97F4A7C15ull + (uint64_t)s->adam_t * 0xBF58476D1CE4E5B9ull;
+            mlp_launch_grad(c->stream, Xtr, Ttr, batch, n_tr, seed, s->P, s->part, s->loss_part, blocks);
+            const float bc1 = 1.f - std::pow(b1, (float)s->adam_t), bc2 = 1.f - std::pow(b2, (float)s->adam_t);
+            mlp_launch_reduce_adam(c->stream, s->part, blocks, nullptr, s->P, s->m, s->v, 1, (float)o->lr, b1, b2, eps,
+                                   bc1, bc2);
+            ++steps;
+        }
+    }
+    HIPCHK_RET(c, hipStreamSynchronize(c->stream));
+    HIPCHK_RET(c, hipGetLastError());
+    double tl = 0.0, vl = 0.0;
+    // training loss on (at most) the first 1M training rows, validation on all held-out rows
+    if ((rc = eval_loss(c, Xtr, Ttr, std::min<int64_t>(n_tr, 1 << 20), &tl))) return rc;
+    if ((rc = eval_loss(c, Xva, Tva, n_val, &vl))) return rc;
+    c->mlp_ready = true;
+    if (out) {
+        out->train_loss = tl;
+        out->val_loss = n_val ? vl : -1.0;
+        out->n_train_rows = n_tr;
+        out->n_val_rows = n_val;
+        out->n_steps = steps;
+        out->ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return FEPIC_OK;
+}
+
+int fepic_ws_get_weights(fepic_ctx* c, float* w, int64_t cap, int64_t* n) {
+    if (!c || !w || !n) return FEPIC_E_ARG;
+    if (!c->mlp || !c->mlp->have_weights) return fail(c, FEPIC_E_STATE, "no weights");
+    if (cap < kNP) return fail(c, FEPIC_E_ARG, "buffer too small");
+    HIPCHK_RET(c, hipStreamSynchronize(c->stream));
+    HIPCHK_RET(c, hipMemcpy(w, c->mlp->P, sizeof(float) * kNP, hipMemcpyDeviceToHost));
+    *n = kNP;
+    return FEPIC_OK;
+}
+
+int fepic_ws_set_weights(fepic_ctx* c, const float* w, int64_t n) {
+    if (!c || !w || n != kNP) return FEPIC_E_ARG;
+    int rc = ensure_mlp(c);
+    if (rc) return rc;
+    HIPCHK_RET(c, hipStreamSynchronize(c->stream));
+    HIPCHK_RET(c, hipMemcpy(c->mlp->P, w, sizeof(float) * kNP, hipMemcpyHostToDevice));
+    HIPCHK_RET(c, hipMemset(c->mlp->m, 0, sizeof(float) * kNP));
+    HIPCHK_RET(c, hipMemset(c->mlp->v, 0, sizeof(float) * kNP));
+    c->mlp->adam_t = 0;
+    c->mlp->have_weights = true;
+    c->mlp_ready = true;
+    return FEPIC_OK;
+}
+
 int fepic_set_warm_start(fepic_ctx* c, int mode) {
     if (!c || mode < FEPIC_WS_PREV || mode > FEPIC_WS_MLP) return FEPIC_E_ARG;
     c->opt.warm_start = mode;
     return FEPIC_OK;
 }
-int fepic_mlp_forward(fepic_ctx* c, int64_t, const float*, float*) { return c ? fepic::fail(c, FEPIC_E_STATE, "not built") : FEPIC_E_ARG; }
-int fepic_mlp_grad(fepic_ctx* c, int64_t, const float*, const float*, float*, double*) { return c ? fepic::fail(c, FEPIC_E_STATE, "not built") : FEPIC_E_ARG; }
-int fepic_save(fepic_ctx* c, const char*) { return c ? fepic::fail(c, FEPIC_E_STATE, "not built") : FEPIC_E_ARG; }
-int fepic_load(fepic_ctx* c, const char*) { return c ? fepic::fail(c, FEPIC_E_STATE, "not built") : FEPIC_E_ARG; }
+
+int fepic_mlp_forward(fepic_ctx* c, int64_t n, const float* X, float* y) {
+    if (!c || n < 0 || (n > 0 && (!X || !y))) return FEPIC_E_ARG;
+    int rc = ensure_mlp(c);
+    if (rc) return rc;
+    if (!c->mlp->have_weights) return fail(c, FEPIC_E_STATE, "no weights");
+    if (n == 0) return FEPIC_OK;
+    if ((rc = host_batch(c, n, X, nullptr))) return rc;
+    float* dy = (float*)dmalloc(c, sizeof(float) * n);
+    if (!dy) return fail(c, FEPIC_E_OOM, "device allocation failed");
+    mlp_launch_forward(c->stream, n, c->mlp->Xh, c->mlp->P, dy);
+    HIPCHK_RET(c, hipStreamSynchronize(c->stream));
+    HIPCHK_RET(c, hipMemcpy(y, dy, sizeof(float) * n, hipMemcpyDeviceToHost));
+    dfree(c, dy);
+    return FEPIC_OK;
 }
+
+int fepic_mlp_grad(fepic_ctx* c, int64_t n, const float* X, const float* t, float* grad, double* loss) {
+    if (!c || n <= 0 || !X || !t || !grad) return FEPIC_E_ARG;
+    int rc = ensure_mlp(c);
+    if (rc) return rc;
+    if (!c->mlp->have_weights) return fail(c, FEPIC_E_STATE, "no weights");
+    if ((rc = host_batch(c, n, X, t))) return rc;
+    MlpState* s = c->mlp;
+    const int blocks = std::min(mlp_grad_blocks(n), kMaxGradBlocks);
+    mlp_launch_grad(c->stream, s->Xh, s->Th, n, 0, 0, s->P, s->part, s->loss_part, blocks);
+    mlp_launch_reduce_adam(c->stream, s->part, blocks, s->grad, s->P, s->m, s->v, 0, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f);
+    std::vector<double> lp(blocks);
+    HIPCHK_RET(c, hipStreamSynchronize(c->stream));
+    HIPCHK_RET(c, hipMemcpy(grad, s->grad, sizeof(float) * kNP, hipMemcpyDeviceToHost));
+    HIPCHK_RET(c, hipMemcpy(lp.data(), s->loss_part, sizeof(double) * blocks, hipMemcpyDeviceToHost));
+    if (loss) {
+        double a = 0.0;
+        for (double v : lp) a += v;
+        *loss = a / (double)n;
+    }
+    return FEPIC_OK;
+}
+
+}  // extern "C"

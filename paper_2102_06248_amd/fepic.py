@@ -20,7 +20,7 @@ FEPIC_FP32_PUSH_FP64_ACC, FEPIC_ALL_FP64 = 0, 1
 FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP = 0, 1, 2, 3
 FEPIC_E_CG_NOT_CONVERGED = -6
 FEPIC_E_CROSSING_CAP = -7
-FEPIC_MLP_N_PARAMS = 4481
+FEPIC_MLP_N_PARAMS = 4545
 
 ERROR_NAMES = {-1: "FEPIC_E_ARG", -2: "FEPIC_E_MESH", -3: "FEPIC_E_STATE", -4: "FEPIC_E_OOM", -5: "FEPIC_E_HIP",
                -6: "FEPIC_E_CG_NOT_CONVERGED", -7: "FEPIC_E_CROSSING_CAP", -8: "FEPIC_E_IO", -9: "FEPIC_E_NO_DEVICE"}
