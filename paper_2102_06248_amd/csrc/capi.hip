@@ -596,11 +596,11 @@ int init_electrostatic(fepic_ctx* c, double tol, int* iters) {
             for (int64_t i = 0; i < ni; ++i) p[i] = z[i] + be * p[i];
         }
     }
-    std::vector<double> e(m.n_edges, 0.0);
+    std::vector<double> e(m.n_edges, 0.0);  // device order
     for (int64_t k = 0; k < m.n_edges; ++k) {
         const int64_t a = idx[m.edges[2 * k]], b = idx[m.edges[2 * k + 1]];
         const double pa = a >= 0 ? phi[a] : 0.0, pb = b >= 0 ? phi[b] : 0.0;
-        e[k] = m.bedge[k] ? 0.0 : -(pb - pa);
+        e[m.eperm[k]] = m.bedge[k] ? 0.0 : -(pb - pa);
     }
     for (double* d : {c->d_e, c->d_ep, c->d_ep2}) HIPCHK(c, hipMemcpy(d, e.data(), 8 * m.n_edges, hipMemcpyHostToDevice));
     c->rG_levels = 0;
@@ -730,14 +730,14 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
     std::vector<double> r0(3 * nt);
     for (int64_t t = 0; t < nt; ++t)
         for (int d = 0; d < 3; ++d) r0[3 * t + d] = m.xyz[3 * m.tets[4 * t] + d];
-    if ((rc = upload(c, &c->d_tets, m.tets)) || (rc = upload(c, &c->d_edges, m.edges)) ||
-        (rc = upload(c, &c->d_tet_edges, m.tet_edges)) || (rc = upload(c, &c->d_tet_faces, m.tet_faces)) ||
-        (rc = upload(c, &c->d_face_edges, m.face_edges)) || (rc = upload(c, &c->d_bedge, m.bedge)) ||
+    if ((rc = upload(c, &c->d_tets, m.tets)) || (rc = upload(c, &c->d_edges, m.dev_edges)) ||
+        (rc = upload(c, &c->d_tet_edges, m.dev_tet_edges)) || (rc = upload(c, &c->d_tet_faces, m.tet_faces)) ||
+        (rc = upload(c, &c->d_face_edges, m.dev_face_edges)) || (rc = upload(c, &c->d_bedge, m.dev_bedge)) ||
         (rc = upload(c, &c->d_inode, inode)) || (rc = upload(c, &c->d_grad64, m.grad)) ||
         (rc = upload(c, &c->d_r0, r0)) || (rc = upload(c, &c->d_sp, m.mat.slice_ptr)) ||
         (rc = upload(c, &c->d_col, m.mat.col)) || (rc = upload(c, &c->d_M, m.mat.M)) ||
         (rc = upload(c, &c->d_S, m.mat.S)) || (rc = upload(c, &c->d_cell_start, m.cell_start)) ||
-        (rc = upload(c, &c->d_cell_tets, m.cell_tets)) || (rc = upload(c, &c->d_int_edges, m.int_edges)))
+        (rc = upload(c, &c->d_cell_tets, m.cell_tets)) || (rc = upload(c, &c->d_int_edges, m.dev_int_edges)))
         return rc;
     std::vector<double> g3 = {m.grid_lo[0], m.grid_lo[1], m.grid_lo[2], m.grid_inv_h[0], m.grid_inv_h[1], m.grid_inv_h[2]};
     std::vector<int32_t> gn = {m.grid_n[0], m.grid_n[1], m.grid_n[2]};
@@ -749,7 +749,7 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
     for (int64_t t = 0; t < nt; ++t) {
         int32_t nbr[4], ed[6];
         for (int k = 0; k < 4; ++k) nbr[k] = m.nbr[4 * t + k] < 0 ? -1 : (m.nbr[4 * t + k] << 2) | m.nbr_far[4 * t + k];
-        for (int i = 0; i < 6; ++i) ed[i] = m.tet_edges[6 * t + i];
+        for (int i = 0; i < 6; ++i) ed[i] = m.dev_tet_edges[6 * t + i];
         if (f64) {
             auto* b = (TetBlock<double>*)(blk.data() + bsz * t);
             for (int i = 0; i < 9; ++i) b->gl[i] = m.grad[9 * t + i];
@@ -840,13 +840,13 @@ int fepic_get_matrix(fepic_ctx* c, int which, int64_t cap, int64_t* nnz, int64_t
         const int64_t w = (A.slice_ptr[s + 1] - A.slice_ptr[s]) / kSell;
         for (int l = 0; l < kSell; ++l) {
             const int64_t r = s * kSell + l;
-            if (r >= A.n_rows || m.bedge[r]) continue;
+            if (r >= A.n_rows || m.dev_bedge[r]) continue;
             for (int64_t k = 0; k < w; ++k) {
                 const int64_t p = A.slice_ptr[s] + k * kSell + l;
                 if (k > 0 && A.col[p] == r) continue;  // padding
                 if (row && n < cap) {
-                    row[n] = r;
-                    col[n] = A.col[p];
+                    row[n] = m.eiperm[r];
+                    col[n] = m.eiperm[A.col[p]];
                     val[n] = v[p];
                 }
                 ++n;
@@ -861,9 +861,8 @@ int fepic_set_fields(fepic_ctx* c, const double* e, const double* e_prev, const 
     NEED_DEV(c);
     const HostMesh& m = c->mesh;
     auto put_e = [&](double* dst, const double* src) -> int {
-        std::vector<double> v(src, src + m.n_edges);
-        for (int64_t i = 0; i < m.n_edges; ++i)
-            if (m.bedge[i]) v[i] = 0.0;
+        std::vector<double> v(m.n_edges);
+        for (int64_t i = 0; i < m.n_edges; ++i) v[m.eperm[i]] = m.bedge[i] ? 0.0 : src[i];
         HIPCHK(c, hipMemcpy(dst, v.data(), sizeof(double) * m.n_edges, hipMemcpyHostToDevice));
         return FEPIC_OK;
     };
@@ -1071,11 +1070,21 @@ int fepic_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_st
 
 int fepic_push_particles(fepic_ctx* c, double dt, fepic_step_stats* out) { return do_step(c, dt, 0.25, 0.5, out, false); }
 
+// Device edge vector -> caller's array in canonical edge order.
+static int edge_out(fepic_ctx* c, const double* d, double* out) {
+    const HostMesh& m = c->mesh;
+    std::vector<double> v(m.n_edges);
+    HIPCHK(c, hipMemcpy(v.data(), d, 8 * m.n_edges, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m.n_edges; ++i) out[i] = v[m.eperm[i]];
+    return FEPIC_OK;
+}
+
 int fepic_get_fields(fepic_ctx* c, double* e, double* e_prev, double* b) {
     NEED_DEV(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (e) HIPCHK(c, hipMemcpy(e, c->d_e, 8 * c->mesh.n_edges, hipMemcpyDeviceToHost));
-    if (e_prev) HIPCHK(c, hipMemcpy(e_prev, c->d_ep, 8 * c->mesh.n_edges, hipMemcpyDeviceToHost));
+    int rc;
+    if (e && (rc = edge_out(c, c->d_e, e))) return rc;
+    if (e_prev && (rc = edge_out(c, c->d_ep, e_prev))) return rc;
     if (b) HIPCHK(c, hipMemcpy(b, c->d_b, 8 * c->mesh.n_faces, hipMemcpyDeviceToHost));
     return FEPIC_OK;
 }
@@ -1083,8 +1092,9 @@ int fepic_get_fields(fepic_ctx* c, double* e, double* e_prev, double* b) {
 int fepic_get_current(fepic_ctx* c, double* dG, double* G) {
     NEED_DEV(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (dG) HIPCHK(c, hipMemcpy(dG, c->d_dg, 8 * c->mesh.n_edges, hipMemcpyDeviceToHost));
-    if (G) HIPCHK(c, hipMemcpy(G, c->d_G, 8 * c->mesh.n_edges, hipMemcpyDeviceToHost));
+    int rc;
+    if (dG && (rc = edge_out(c, c->d_dg, dG))) return rc;
+    if (G && (rc = edge_out(c, c->d_G, G))) return rc;
     return FEPIC_OK;
 }
 

@@ -181,15 +181,69 @@ int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_t
     m.n_int_nodes = 0;
     for (int64_t v = 0; v < n_nodes; ++v) m.n_int_nodes += !m.bnode[v];
 
-    // ---- assembly pattern: row e couples to the interior edges of every tet holding e
+    // ---- device edge numbering: Morton order of edge midpoints
+    {
+        const int64_t ne0 = m.n_edges;
+        double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
+        for (int64_t v = 0; v < n_nodes; ++v)
+            for (int d = 0; d < 3; ++d) {
+                lo3[d] = std::min(lo3[d], m.xyz[3 * v + d]);
+                hi3[d] = std::max(hi3[d], m.xyz[3 * v + d]);
+            }
+        auto spread = [](uint64_t v) {  // 21 bits -> every third bit
+            v &= 0x1fffff;
+            v = (v | v << 32) & 0x1f00000000ffffull;
+            v = (v | v << 16) & 0x1f0000ff0000ffull;
+            v = (v | v << 8) & 0x100f00f00f00f00full;
+            v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+            v = (v | v << 2) & 0x1249249249249249ull;
+            return v;
+        };
+        std::vector<uint64_t> key(ne0);
+        for (int64_t e = 0; e < ne0; ++e) {
+            uint64_t q[3];
+            for (int d = 0; d < 3; ++d) {
+                const double mid = 0.5 * (m.xyz[3 * m.edges[2 * e] + d] + m.xyz[3 * m.edges[2 * e + 1] + d]);
+                const double ext = hi3[d] - lo3[d];
+                const double f = ext > 0 ? (mid - lo3[d]) / ext : 0.0;
+                q[d] = (uint64_t)std::min(2097151.0, std::max(0.0, f * 2097151.0));
+            }
+            key[e] = spread(q[0]) | spread(q[1]) << 1 | spread(q[2]) << 2;
+        }
+        m.eiperm.resize(ne0);
+        std::iota(m.eiperm.begin(), m.eiperm.end(), 0);
+        std::stable_sort(m.eiperm.begin(), m.eiperm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+        m.eperm.resize(ne0);
+        for (int64_t d = 0; d < ne0; ++d) m.eperm[m.eiperm[d]] = (int32_t)d;
+        m.dev_edges.resize(2 * ne0);
+        m.dev_bedge.resize(ne0);
+        for (int64_t d = 0; d < ne0; ++d) {
+            const int32_t e = m.eiperm[d];
+            m.dev_edges[2 * d] = m.edges[2 * e];
+            m.dev_edges[2 * d + 1] = m.edges[2 * e + 1];
+            m.dev_bedge[d] = m.bedge[e];
+        }
+        m.dev_tet_edges.resize(m.tet_edges.size());
+        for (size_t j = 0; j < m.tet_edges.size(); ++j) m.dev_tet_edges[j] = m.eperm[m.tet_edges[j]];
+        m.dev_face_edges.resize(m.face_edges.size());
+        for (size_t j = 0; j < m.face_edges.size(); ++j) m.dev_face_edges[j] = m.eperm[m.face_edges[j]];
+        m.dev_int_edges.clear();
+        for (int64_t d = 0; d < ne0; ++d)
+            if (!m.dev_bedge[d]) m.dev_int_edges.push_back((int32_t)d);
+    }
+    const std::vector<int32_t>& TE = m.dev_tet_edges;
+    const std::vector<uint8_t>& BE = m.dev_bedge;
+
+    // ---- assembly pattern (device order): row e couples to the interior edges of every
+    // tet holding e
     const int64_t ne = m.n_edges;
     std::vector<int64_t> et_start(ne + 1, 0);
-    for (int64_t j = 0; j < 6 * n_tets; ++j) et_start[m.tet_edges[j] + 1]++;
+    for (int64_t j = 0; j < 6 * n_tets; ++j) et_start[TE[j] + 1]++;
     for (int64_t e = 0; e < ne; ++e) et_start[e + 1] += et_start[e];
     std::vector<int32_t> et(6 * n_tets);
     {
         std::vector<int64_t> pos(et_start.begin(), et_start.end() - 1);
-        for (int64_t j = 0; j < 6 * n_tets; ++j) et[pos[m.tet_edges[j]]++] = (int32_t)(j / 6);
+        for (int64_t j = 0; j < 6 * n_tets; ++j) et[pos[TE[j]]++] = (int32_t)(j / 6);
     }
     SellMatrix& A = m.mat;
     A.n_rows = ne;
@@ -202,13 +256,13 @@ int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_t
     for (int64_t e = 0; e < ne; ++e) {
         rstart[e] = (int64_t)rcols.size();
         rcols.push_back((int32_t)e);  // diagonal first
-        if (!m.bedge[e]) {
+        if (!BE[e]) {
             tmp.clear();
             for (int64_t j = et_start[e]; j < et_start[e + 1]; ++j) {
                 const int t = et[j];
                 for (int i = 0; i < 6; ++i) {
-                    const int32_t c = m.tet_edges[6 * t + i];
-                    if (c != e && !m.bedge[c]) tmp.push_back(c);
+                    const int32_t c = TE[6 * t + i];
+                    if (c != e && !BE[c]) tmp.push_back(c);
                 }
             }
             std::sort(tmp.begin(), tmp.end());
@@ -267,12 +321,12 @@ int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_t
         const double V = m.vol[t];
         const double mc = kEps0 * V / 20.0, sc = 4.0 * V / kMu0;
         for (int i = 0; i < 6; ++i) {
-            const int32_t ei = m.tet_edges[6 * t + i];
-            if (m.bedge[ei]) continue;
+            const int32_t ei = TE[6 * t + i];
+            if (BE[ei]) continue;
             const int a = kLE[i][0], b = kLE[i][1];
             for (int j = 0; j < 6; ++j) {
-                const int32_t ej = m.tet_edges[6 * t + j];
-                if (m.bedge[ej]) continue;
+                const int32_t ej = TE[6 * t + j];
+                if (BE[ej]) continue;
                 const int c = kLE[j][0], d = kLE[j][1];
                 const double Mv = mc * ((1 + (a == c)) * gg[b][d] - (1 + (a == d)) * gg[b][c] -
                                         (1 + (b == c)) * gg[a][d] + (1 + (b == d)) * gg[a][c]);
@@ -289,7 +343,7 @@ int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_t
     }
     // boundary rows: keep a unit mass on the diagonal (identity rows after scaling)
     for (int64_t e = 0; e < ne; ++e)
-        if (m.bedge[e]) A.M[slot(e, (int32_t)e)] = 1.0;
+        if (BE[e]) A.M[slot(e, (int32_t)e)] = 1.0;
 
     // ---- point-location grid
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};

@@ -25,9 +25,20 @@ struct HostMesh {
     std::vector<int32_t> face_edges;  // [n_faces][3]: (i,j), (j,k), (i,k)
     std::vector<uint8_t> bedge, bnode;
     std::vector<int32_t> int_edges;   // interior edge ids, ascending
+    // Device numbering of edges: canonical edges re-ordered along a Morton curve of their
+    // midpoints, so consecutive matrix rows (and the columns they gather) are close in
+    // space and in memory.  All device arrays use it; the C ABI converts at its boundary.
+    std::vector<int32_t> eperm;        // canonical edge id -> device edge id
+    std::vector<int32_t> eiperm;       // device edge id -> canonical edge id
+    std::vector<int32_t> dev_edges;       // [n_edges][2] node pairs, device order
+    std::vector<int32_t> dev_tet_edges;   // [n_tets][6] device edge ids
+    std::vector<int32_t> dev_face_edges;  // [n_faces][3] device edge ids
+    std::vector<uint8_t> dev_bedge;       // wall flag, device order
+    std::vector<int32_t> dev_int_edges;   // interior edges, device ids ascending
     std::vector<double> grad;         // [n_tets][9] grad lambda_1..3
     std::vector<double> vol;          // [n_tets]
-    SellMatrix mat;                   // M and S over all edge rows (boundary rows: diagonal only)
+    SellMatrix mat;                   // M and S over all edge rows in device order (boundary rows:
+                                      // diagonal only)
     // point-location grid
     double grid_lo[3] = {0, 0, 0}, grid_inv_h[3] = {1, 1, 1};
     int32_t grid_n[3] = {1, 1, 1};

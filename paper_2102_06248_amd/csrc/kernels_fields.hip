@@ -275,6 +275,44 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_b(int64_t n_rows, RowGrid rg
     write_partials<3>(v, partial);
 }
 
+// Loads of one row that do not depend on the iteration's scalars: its slots (up to
+// kRowW, clamped into the row so no branch guards them), and its own vector entries.
+constexpr int kRowW = 20;
+
+struct RowLoads {
+    int c[kRowW];
+    double a[kRowW];
+    int64_t k_end, k_next;   // remaining slots (rows wider than kRowW)
+    double R, W, S, p, x, dinv;
+};
+
+__device__ __forceinline__ void row_loads(RowLoads& L, const int64_t* __restrict__ sp, const int32_t* __restrict__ col,
+                                          const double* __restrict__ A, const double* __restrict__ R,
+                                          const double* __restrict__ W, const double* __restrict__ S,
+                                          const double* __restrict__ p, const double* __restrict__ x,
+                                          const double* __restrict__ dinv, int64_t row, bool real) {
+    const int64_t sl = row >> 6;
+    const int lane = (int)(row & 63);
+    const int64_t k0 = sp[sl] + lane, k1 = sp[sl + 1];
+    const int64_t k_last = k1 - 64;  // this lane's last slot
+#pragma unroll
+    for (int q = 0; q < kRowW; ++q) {
+        const int64_t k = k0 + 64 * q;
+        const int64_t kk = k < k1 ? k : k_last;
+        L.c[q] = col[kk];
+        L.a[q] = k < k1 ? A[kk] : 0.0;
+    }
+    L.k_next = k0 + 64 * kRowW;
+    L.k_end = k1;
+    const int64_t r = real ? row : 0;
+    L.R = R[r];
+    L.W = W[r];
+    L.S = S[r];
+    L.p = p[r];
+    L.x = x[r];
+    L.dinv = dinv[r];
+}
+
 __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, int i, const int64_t* __restrict__ sp,
                                                      const int32_t* __restrict__ col, const double* __restrict__ A,
                                                      const double* __restrict__ dinv, double* __restrict__ x,
@@ -288,8 +326,25 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
     if (threadIdx.x == 0) s_conv = sc->converged;
     __syncthreads();
     if (s_conv) return;
-    double t[3];
-    read_partials<3>(part_in, gridDim.x, t);
+    // issue the previous kernel's partials and this workgroup's first row together
+    const int n_src = gridDim.x;
+    double t[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < kMaxGrid / kBlock; ++q) {
+        const int b = threadIdx.x + q * kBlock;
+        if (b < n_src) {
+            t[0] += part_in[b];
+            t[1] += part_in[n_src + b];
+            t[2] += part_in[2 * n_src + b];
+        }
+    }
+    int64_t lb = rg_first(rg);
+    const int64_t le = rg_end(rg);
+    RowLoads L;
+    int64_t row = lb * kBlock + threadIdx.x;
+    bool active = lb < le && ((row >> 6) << 6) < n_rows;
+    if (active) row_loads(L, sp, col, A, R, W, S, p, x, dinv, row, row < n_rows);
+    block_sum_all<3>(t);
     const double g = t[0], d = t[1], rr = t[2];
     const bool done = !(rr > sc->tol2_bb) || sc->bb == 0.0;
     const double beta = (i == 0) ? 0.0 : g / sc->gam[(i - 1) & 1];
@@ -307,26 +362,39 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
     if (done || bad) return;
     const double ab = alpha * beta;
     double v[3] = {0.0, 0.0, 0.0};
-    for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
-        const int64_t row = lb * kBlock + threadIdx.x;
-        if (((row >> 6) << 6) >= n_rows) continue;
-        const double acc = sell_row(sp, col, A, row, [&](int c) { return R[c] - alpha * W[c] - ab * S[c]; });
-        if (row < n_rows) {
-            const double dj = dinv[row];
-            const double uj = R[row];
-            const double pj = uj + beta * p[row];
-            const double sj = W[row] + beta * S[row];   // D^-1 s
-            x[row] += alpha * pj;
-            const double un = uj - alpha * sj;          // D^-1 r' = u'
-            const double rn = un / dj;
-            p[row] = pj;
-            S_new[row] = sj;
-            R_new[row] = un;
-            W_new[row] = dj * acc;
-            v[0] += rn * un;
-            v[1] += un * acc;
-            v[2] += rn * rn;
+    while (lb < le) {
+        if (active) {
+            double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < kRowW; q += 2) {
+                const int c0 = L.c[q], c1 = L.c[q + 1];
+                acc0 += L.a[q] * (R[c0] - alpha * W[c0] - ab * S[c0]);
+                acc1 += L.a[q + 1] * (R[c1] - alpha * W[c1] - ab * S[c1]);
+            }
+            for (int64_t k = L.k_next; k < L.k_end; k += 64) {
+                const int c = col[k];
+                acc0 += A[k] * (R[c] - alpha * W[c] - ab * S[c]);
+            }
+            const double acc = acc0 + acc1;
+            if (row < n_rows) {
+                const double pj = L.R + beta * L.p;
+                const double sj = L.W + beta * L.S;   // D^-1 s
+                x[row] = L.x + alpha * pj;
+                const double un = L.R - alpha * sj;   // D^-1 r' = u'
+                const double rn = un / L.dinv;
+                p[row] = pj;
+                S_new[row] = sj;
+                R_new[row] = un;
+                W_new[row] = L.dinv * acc;
+                v[0] += rn * un;
+                v[1] += un * acc;
+                v[2] += rn * rn;
+            }
         }
+        lb += rg.g;
+        row = lb * kBlock + threadIdx.x;
+        active = lb < le && ((row >> 6) << 6) < n_rows;
+        if (active) row_loads(L, sp, col, A, R, W, S, p, x, dinv, row, row < n_rows);
     }
     write_partials<3>(v, part_out);
 }
