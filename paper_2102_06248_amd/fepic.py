@@ -135,6 +135,14 @@ class FepicError(RuntimeError):
         self.code = code
 
 
+def fepic_error_string(code):
+    return lib().fepic_error_string(code).decode()
+
+
+def fepic_last_error(ctx):
+    return lib().fepic_last_error(ctx).decode()
+
+
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
