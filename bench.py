@@ -129,8 +129,8 @@ def main():
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
-              "'How the path would shard')", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; a mesh-partition "
+              "sharding is described in the design notes but not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -20,5 +20,5 @@ states the method:
 * ``pic``         one whole PIC step in the paper's cycle order (Sec. II-A)
 * ``mlp``         the per-edge warm-start network, forward/backward/Adam in float64
 
-Readings of the paper where it is silent or garbled are listed in the design doc.
+Where the paper is silent or garbled, each module states the reading it takes.
 """

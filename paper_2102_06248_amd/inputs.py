@@ -6,7 +6,7 @@ coordinates, no Whitney forms, no assembly, no push.  Both the HIP library and t
 oracle consume what it produces, each through its own code.
 
 Meshes stand in for the paper's (its beam cylinder and plasma ball meshes are not
-published, Sec. IV-B/IV-C); shapes and sizes follow the workloads named in the design doc.
+published, Sec. IV-B/IV-C); shapes and sizes follow the workloads in ``workloads``.
 
 All random draws use numpy's PCG64 with an explicit seed.
 """

@@ -2,7 +2,7 @@
 
 Stand-ins for the paper's test problems (Sec. IV), whose meshes and data are not
 published: an electron beam in a PEC cylinder (Sec. IV-B) and an expanding neutral plasma
-(Sec. IV-C), at the sizes named in the design doc.  Only input construction lives here.
+(Sec. IV-C), at the sizes given below.  Only input construction lives here.
 """
 from __future__ import annotations
 
