@@ -259,18 +259,15 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
         if (rc != FEPIC_OK) return rc;
     }
     ev_mark(c, 6);
-    double* const R[2] = {c->d_r, c->d_z};
-    double* const W[2] = {c->d_q, c->d_w2};
-    double* const SV[2] = {c->d_p[1], c->d_s2};
-    double* const P = c->d_p[0];
+    CgVec* const V[2] = {c->d_cgv[0], c->d_cgv[1]};
     const int maxit = c->opt.cg_max_iters;
     const int batch = std::max(1, c->opt.cg_check_every);
     int total = 0;
     double rr0_first = -1.0;
     c->cg_restarts = 0;
     for (int restart = 0;; ++restart) {
-        launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, R[0], W[0], P, SV[0],
-                       c->d_partial, c->d_sc, c->opt.cg_tol);
+        launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, V[0], c->d_partial,
+                       c->d_sc, c->opt.cg_tol);
         if (restart == 0 && mode == FEPIC_WS_MLP) {
             // guard: a start worse than x0 = 0 (or non-finite) falls back to e^n
             launch_cg_rr0(c->stream, ne, c->d_partial, c->d_sc);
@@ -279,8 +276,8 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
             if (!(std::isfinite(c->h_sc->rr0)) || c->h_sc->rr0 > c->h_sc->bb) {
                 c->mlp_fallbacks++;
                 launch_warm(c->stream, FEPIC_WS_PREV, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
-                launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, R[0], W[0], P,
-                               SV[0], c->d_partial, c->d_sc, c->opt.cg_tol);
+                launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, V[0],
+                               c->d_partial, c->d_sc, c->opt.cg_tol);
             }
         }
         // Iterations are launched in batches; between batches the host reads the device's
@@ -311,7 +308,7 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
             // the launch after the budget only checks (and is discarded on failure)
             todo = std::min(todo, budget + 1 - launched);
             for (int k = 0; k < todo; ++k)
-                launch_cg_iter(c->stream, launched + k, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, P, R, W, SV,
+                launch_cg_iter(c->stream, launched + k, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, V,
                                c->d_partial, c->d_sc, timer_pair(c, FAM_CG_ITER));
             launched += todo;
         }
@@ -766,12 +763,17 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
     const int64_t nnz = m.mat.slice_ptr.back();
     c->d_A = dalloc<double>(c, nnz);
     c->d_dinv = dalloc<double>(c, ne);
-    double** ev[] = {&c->d_e, &c->d_ep, &c->d_ep2, &c->d_x, &c->d_dg, &c->d_dgn, &c->d_G, &c->d_rhs, &c->d_r,
-                     &c->d_z, &c->d_p[0], &c->d_p[1], &c->d_q, &c->d_rt, &c->d_Me, &c->d_w2, &c->d_s2};
+    double** ev[] = {&c->d_e, &c->d_ep, &c->d_ep2, &c->d_x, &c->d_dg, &c->d_dgn, &c->d_G, &c->d_rhs, &c->d_rt,
+                     &c->d_Me};
     for (double** p : ev) {
         *p = dalloc<double>(c, ne);
         if (!*p) return fail(c, FEPIC_E_OOM, "device allocation failed");
         HIPCHK(c, hipMemset(*p, 0, sizeof(double) * ne));
+    }
+    for (CgVec*& p : c->d_cgv) {
+        p = dalloc<CgVec>(c, ne);
+        if (!p) return fail(c, FEPIC_E_OOM, "device allocation failed");
+        HIPCHK(c, hipMemset(p, 0, sizeof(CgVec) * ne));
     }
     double** fv[] = {&c->d_b, &c->d_bn};
     for (double** p : fv) {

@@ -65,8 +65,8 @@ struct fepic_ctx {
     double *d_e = nullptr, *d_ep = nullptr, *d_ep2 = nullptr, *d_x = nullptr;
     double *d_dg = nullptr, *d_dgn = nullptr, *d_G = nullptr;
     double *d_b = nullptr, *d_bn = nullptr;
-    double *d_rhs = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p[2] = {nullptr, nullptr}, *d_q = nullptr,
-           *d_rt = nullptr, *d_Me = nullptr, *d_w2 = nullptr, *d_s2 = nullptr;
+    double *d_rhs = nullptr, *d_rt = nullptr, *d_Me = nullptr;
+    fepic::CgVec* d_cgv[2] = {nullptr, nullptr};   // PCG state, double buffered
     double* d_partial = nullptr;
     fepic::CgScalars* d_sc = nullptr;
     fepic::CgScalars* h_sc = nullptr;

@@ -77,6 +77,13 @@ struct CgScalars {
     int iters;
 };
 
+// Per-row state of the PCG iteration, interleaved so that a neighbour's three gathered
+// values (R, W, S) share one 32-byte sector: R = D^-1 r, W = D^-1 w, S = D^-1 s, and the
+// row's own search direction P.
+struct alignas(32) CgVec {
+    double R, W, S, P;
+};
+
 // Device-side diagnostics accumulators (max-abs values stored as ordered bit patterns).
 struct DiagAcc {
     unsigned long long cont_max, gauss_max, drift_max, rho_max, divb_max;
@@ -124,11 +131,11 @@ void launch_rhs(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const i
                 const uint8_t* bmask, double dt2, double c1, double c2, double* b, double* partial);
 void launch_warm(hipStream_t s, int mode, int64_t n, const double* e, const double* ep, const double* ep2, double* x);
 void launch_cg_init(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* A,
-                    const double* dinv, const double* b, const double* x, double* r, double* w, double* p, double* sv,
-                    double* partial, CgScalars* sc, double tol);
+                    const double* dinv, const double* b, const double* x, CgVec* v, double* partial, CgScalars* sc,
+                    double tol);
 void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
-                    const double* A, const double* dinv, double* x, double* p, double* const r[2], double* const w[2],
-                    double* const sv[2], double* partial, CgScalars* sc, hipEvent_t* ev);
+                    const double* A, const double* dinv, double* x, CgVec* const v[2], double* partial,
+                    CgScalars* sc, hipEvent_t* ev);
 void launch_cg_rr0(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc);
 void launch_cg_resid(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
                      const double* A, const double* b, double* x, double* r_true, double* partial,

@@ -224,16 +224,16 @@ __global__ __launch_bounds__(kBlock) void k_warm(int mode, int64_t n, const doub
 //   w' = A u' (the neighbours' u' formed on the fly from the previous r, w, s),
 //   g_{i+1} = (r',u'), d_{i+1} = (u',w'), ||r'||^2.
 // The kernel keeps r, w and s scaled by D^-1 (R = D^-1 r, W = D^-1 w, S = D^-1 s, D =
-// diag A) so a neighbour's u' = R - alpha (W + beta S) costs three gathers.  R, W and S
-// are double buffered (neighbours read the previous values); p and x are touched by
-// their own row only.
+// diag A) so a neighbour's u' = R - alpha (W + beta S) needs three of its values; they
+// are stored interleaved with the row's own p (CgVec, 32 bytes per row) so the three
+// come from one sector.  The interleaved state is double buffered (neighbours read the
+// previous values); x is touched by its own row only.
 
-// ||b||^2 from the right-hand side's partials; R = D^-1 (b - A x); p = S = 0.
+// ||b||^2 from the right-hand side's partials; R = D^-1 (b - A x); W = S = P = 0.
 __global__ __launch_bounds__(kBlock) void k_cg_init_a(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
                                                        const int32_t* __restrict__ col, const double* __restrict__ A,
                                                        const double* __restrict__ dinv, const double* __restrict__ b,
-                                                       const double* __restrict__ x, double* __restrict__ R,
-                                                       double* __restrict__ p, double* __restrict__ S,
+                                                       const double* __restrict__ x, CgVec* __restrict__ V,
                                                        const double* __restrict__ part_rhs, CgScalars* sc, double tol) {
     double bb[1];
     read_partials<1>(part_rhs, gridDim.x, bb);
@@ -247,26 +247,26 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_a(int64_t n_rows, RowGrid rg
         if (((row >> 6) << 6) >= n_rows) continue;
         const double ax = sell_row(sp, col, A, row, [&](int c) { return x[c]; });
         if (row < n_rows) {
-            R[row] = dinv[row] * (b[row] - ax);
-            p[row] = 0.0;
-            S[row] = 0.0;
+            double2* o = reinterpret_cast<double2*>(V + row);
+            o[0] = make_double2(dinv[row] * (b[row] - ax), 0.0);
+            o[1] = make_double2(0.0, 0.0);
         }
     }
 }
 
-// W = D^-1 A u with u = R; partials of (r,u), (u,w), (r,r).
+// W = D^-1 A u with u = R (only R is gathered); partials of (r,u), (u,w), (r,r).
 __global__ __launch_bounds__(kBlock) void k_cg_init_b(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
                                                        const int32_t* __restrict__ col, const double* __restrict__ A,
-                                                       const double* __restrict__ dinv, const double* __restrict__ R,
-                                                       double* __restrict__ W, double* __restrict__ partial) {
+                                                       const double* __restrict__ dinv, CgVec* __restrict__ V,
+                                                       double* __restrict__ partial) {
     double v[3] = {0.0, 0.0, 0.0};
     for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
         const int64_t row = lb * kBlock + threadIdx.x;
         if (((row >> 6) << 6) >= n_rows) continue;
-        const double acc = sell_row(sp, col, A, row, [&](int c) { return R[c]; });
+        const double acc = sell_row(sp, col, A, row, [&](int c) { return V[c].R; });
         if (row < n_rows) {
-            const double dj = dinv[row], uv = R[row], rv = uv / dj;
-            W[row] = dj * acc;
+            const double dj = dinv[row], uv = V[row].R, rv = uv / dj;
+            V[row].W = dj * acc;
             v[0] += rv * uv;
             v[1] += uv * acc;
             v[2] += rv * rv;
@@ -275,58 +275,81 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_b(int64_t n_rows, RowGrid rg
     write_partials<3>(v, partial);
 }
 
-// Loads of one row that do not depend on the iteration's scalars: its slots (up to
-// kRowW, clamped into the row so no branch guards them), and its own vector entries.
-constexpr int kRowW = 20;
-
-struct RowLoads {
-    int c[kRowW];
-    double a[kRowW];
-    int64_t k_end, k_next;   // remaining slots (rows wider than kRowW)
-    double R, W, S, p, x, dinv;
+// The part of row j's product that does not depend on the iteration's scalars: the three
+// sums sum_k A_jk R_k, sum_k A_jk W_k, sum_k A_jk S_k over the row's stored entries, and
+// the row's own entries.  A_j u' = sR - alpha sW - alpha beta sS, so the gathers of a row
+// can be issued before the scalars of this iteration are known.
+struct RowPart {
+    double sR, sW, sS;
+    double2 RW, SP;   // own R, W and S, P
+    double x, dinv;
 };
 
-__device__ __forceinline__ void row_loads(RowLoads& L, const int64_t* __restrict__ sp, const int32_t* __restrict__ col,
-                                          const double* __restrict__ A, const double* __restrict__ R,
-                                          const double* __restrict__ W, const double* __restrict__ S,
-                                          const double* __restrict__ p, const double* __restrict__ x,
-                                          const double* __restrict__ dinv, int64_t row, bool real) {
+__device__ __forceinline__ void row_part(RowPart& P, const int64_t* __restrict__ sp, const int32_t* __restrict__ col,
+                                         const double* __restrict__ A, const CgVec* __restrict__ V,
+                                         const double* __restrict__ x, const double* __restrict__ dinv, int64_t row,
+                                         bool real) {
     const int64_t sl = row >> 6;
     const int lane = (int)(row & 63);
-    const int64_t k0 = sp[sl] + lane, k1 = sp[sl + 1];
-    const int64_t k_last = k1 - 64;  // this lane's last slot
-#pragma unroll
-    for (int q = 0; q < kRowW; ++q) {
-        const int64_t k = k0 + 64 * q;
-        const int64_t kk = k < k1 ? k : k_last;
-        L.c[q] = col[kk];
-        L.a[q] = k < k1 ? A[kk] : 0.0;
-    }
-    L.k_next = k0 + 64 * kRowW;
-    L.k_end = k1;
+    const int64_t k1 = sp[sl + 1];
+    int64_t k = sp[sl] + lane;
     const int64_t r = real ? row : 0;
-    L.R = R[r];
-    L.W = W[r];
-    L.S = S[r];
-    L.p = p[r];
-    L.x = x[r];
-    L.dinv = dinv[r];
+    const double2* own = reinterpret_cast<const double2*>(V + r);
+    P.RW = own[0];
+    P.SP = own[1];
+    P.x = x[r];
+    P.dinv = dinv[r];
+    double r0 = 0.0, w0 = 0.0, s0 = 0.0, r1 = 0.0, w1 = 0.0, s1 = 0.0;
+    for (; k + 3 * 64 < k1; k += 4 * 64) {
+        int c[4];
+        double a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = col[k + 64 * q];
+            a[q] = A[k + 64 * q];
+        }
+        double2 rw[4];
+        double sv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            rw[q] = *reinterpret_cast<const double2*>(V + c[q]);
+            sv[q] = V[c[q]].S;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q += 2) {
+            r0 += a[q] * rw[q].x;
+            w0 += a[q] * rw[q].y;
+            s0 += a[q] * sv[q];
+            r1 += a[q + 1] * rw[q + 1].x;
+            w1 += a[q + 1] * rw[q + 1].y;
+            s1 += a[q + 1] * sv[q + 1];
+        }
+    }
+    for (; k < k1; k += 64) {
+        const int c = col[k];
+        const double a = A[k];
+        const double2 rw = *reinterpret_cast<const double2*>(V + c);
+        r0 += a * rw.x;
+        w0 += a * rw.y;
+        s0 += a * V[c].S;
+    }
+    P.sR = r0 + r1;
+    P.sW = w0 + w1;
+    P.sS = s0 + s1;
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, int i, const int64_t* __restrict__ sp,
                                                      const int32_t* __restrict__ col, const double* __restrict__ A,
                                                      const double* __restrict__ dinv, double* __restrict__ x,
-                                                     double* __restrict__ p, const double* __restrict__ R,
-                                                     const double* __restrict__ W, const double* __restrict__ S,
-                                                     double* __restrict__ R_new, double* __restrict__ W_new,
-                                                     double* __restrict__ S_new, const double* __restrict__ part_in,
+                                                     const CgVec* __restrict__ V, CgVec* __restrict__ V_new,
+                                                     const double* __restrict__ part_in,
                                                      double* __restrict__ part_out, CgScalars* sc) {
     // one read of the flag per workgroup, so all of its waves take the same branch
     __shared__ int s_conv;
     if (threadIdx.x == 0) s_conv = sc->converged;
     __syncthreads();
     if (s_conv) return;
-    // issue the previous kernel's partials and this workgroup's first row together
+    // the previous kernel's partials and this workgroup's first rows are in flight together
     const int n_src = gridDim.x;
     double t[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -340,10 +363,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
     }
     int64_t lb = rg_first(rg);
     const int64_t le = rg_end(rg);
-    RowLoads L;
+    RowPart P;
     int64_t row = lb * kBlock + threadIdx.x;
     bool active = lb < le && ((row >> 6) << 6) < n_rows;
-    if (active) row_loads(L, sp, col, A, R, W, S, p, x, dinv, row, row < n_rows);
+    if (active) row_part(P, sp, col, A, V, x, dinv, row, row < n_rows);
     block_sum_all<3>(t);
     const double g = t[0], d = t[1], rr = t[2];
     const bool done = !(rr > sc->tol2_bb) || sc->bb == 0.0;
@@ -363,38 +386,25 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
     const double ab = alpha * beta;
     double v[3] = {0.0, 0.0, 0.0};
     while (lb < le) {
-        if (active) {
-            double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll
-            for (int q = 0; q < kRowW; q += 2) {
-                const int c0 = L.c[q], c1 = L.c[q + 1];
-                acc0 += L.a[q] * (R[c0] - alpha * W[c0] - ab * S[c0]);
-                acc1 += L.a[q + 1] * (R[c1] - alpha * W[c1] - ab * S[c1]);
-            }
-            for (int64_t k = L.k_next; k < L.k_end; k += 64) {
-                const int c = col[k];
-                acc0 += A[k] * (R[c] - alpha * W[c] - ab * S[c]);
-            }
-            const double acc = acc0 + acc1;
-            if (row < n_rows) {
-                const double pj = L.R + beta * L.p;
-                const double sj = L.W + beta * L.S;   // D^-1 s
-                x[row] = L.x + alpha * pj;
-                const double un = L.R - alpha * sj;   // D^-1 r' = u'
-                const double rn = un / L.dinv;
-                p[row] = pj;
-                S_new[row] = sj;
-                R_new[row] = un;
-                W_new[row] = L.dinv * acc;
-                v[0] += rn * un;
-                v[1] += un * acc;
-                v[2] += rn * rn;
-            }
+        if (active && row < n_rows) {
+            const double acc = P.sR - alpha * P.sW - ab * P.sS;   // (A u')_j
+            const double pj = P.RW.x + beta * P.SP.y;
+            const double sj = P.RW.y + beta * P.SP.x;   // D^-1 s
+            x[row] = P.x + alpha * pj;
+            const double un = P.RW.x - alpha * sj;      // D^-1 r' = u'
+            const double rn = un / P.dinv;
+            const double wn = P.dinv * acc;
+            double2* o = reinterpret_cast<double2*>(V_new + row);
+            o[0] = make_double2(un, wn);
+            o[1] = make_double2(sj, pj);
+            v[0] += rn * un;
+            v[1] += un * acc;
+            v[2] += rn * rn;
         }
         lb += rg.g;
         row = lb * kBlock + threadIdx.x;
         active = lb < le && ((row >> 6) << 6) < n_rows;
-        if (active) row_loads(L, sp, col, A, R, W, S, p, x, dinv, row, row < n_rows);
+        if (active) row_part(P, sp, col, A, V, x, dinv, row, row < n_rows);
     }
     write_partials<3>(v, part_out);
 }
@@ -581,26 +591,26 @@ void launch_warm(hipStream_t s, int mode, int64_t n, const double* e, const doub
 }
 
 void launch_cg_init(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
-                    const double* dinv, const double* b, const double* x, double* r, double* w, double* p, double* sv,
-                    double* partial, CgScalars* sc, double tol) {
+                    const double* dinv, const double* b, const double* x, CgVec* v, double* partial, CgScalars* sc,
+                    double tol) {
     const RowGrid rg = row_grid(n_rows);
-    hipLaunchKernelGGL(k_cg_init_a, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, dinv, b, x, r, p, sv,
+    hipLaunchKernelGGL(k_cg_init_a, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, dinv, b, x, v,
                        partial + SLOT_RHS * kSlot, sc, tol);
-    hipLaunchKernelGGL(k_cg_init_b, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, dinv, r, w,
+    hipLaunchKernelGGL(k_cg_init_b, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, dinv, v,
                        partial + SLOT_INIT * kSlot);
 }
 
-// Iteration i reads r, w, s from buffer i & 1 and writes buffer (i + 1) & 1.
+// Iteration i reads the interleaved state from buffer i & 1 and writes buffer (i + 1) & 1.
 void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
-                    const double* dinv, double* x, double* p, double* const r[2], double* const w[2],
-                    double* const sv[2], double* partial, CgScalars* sc, hipEvent_t* ev) {
+                    const double* dinv, double* x, CgVec* const v[2], double* partial, CgScalars* sc,
+                    hipEvent_t* ev) {
     const RowGrid rg = row_grid(n_rows);
     const int a = i & 1, b = 1 - a;
     const double* part_in = partial + (i == 0 ? SLOT_INIT : (a ? SLOT_UPD : SLOT_SPMV)) * kSlot;
     double* part_out = partial + (b ? SLOT_UPD : SLOT_SPMV) * kSlot;
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL(k_cg_iter, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, dinv, x, p, r[a],
-                       w[a], sv[a], r[b], w[b], sv[b], part_in, part_out, sc);
+    hipLaunchKernelGGL(k_cg_iter, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, dinv, x, v[a], v[b],
+                       part_in, part_out, sc);
     if (ev) (void)hipEventRecord(ev[1], s);
 }
 
