@@ -181,7 +181,9 @@ int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_t
     m.n_int_nodes = 0;
     for (int64_t v = 0; v < n_nodes; ++v) m.n_int_nodes += !m.bnode[v];
 
-    // ---- device edge numbering: Morton order of edge midpoints
+    // ---- device edge numbering: Morton order of edge midpoints, rows of equal length
+    // grouped within windows of kSortWindow rows
+    constexpr int64_t kSortWindow = 8 * kSell;
     {
         const int64_t ne0 = m.n_edges;
         double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
@@ -213,6 +215,34 @@ int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_t
         m.eiperm.resize(ne0);
         std::iota(m.eiperm.begin(), m.eiperm.end(), 0);
         std::stable_sort(m.eiperm.begin(), m.eiperm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+        // Within windows of kSortWindow consecutive rows, order rows by their stored length
+        // (stable, so Morton order is kept among equal lengths): slices of 64 rows then
+        // hold rows of one length and carry little padding.
+        {
+            std::vector<int64_t> ets(ne0 + 1, 0);
+            for (int64_t j = 0; j < 6 * n_tets; ++j) ets[m.tet_edges[j] + 1]++;
+            for (int64_t e = 0; e < ne0; ++e) ets[e + 1] += ets[e];
+            std::vector<int32_t> etl(6 * n_tets);
+            std::vector<int64_t> pos(ets.begin(), ets.end() - 1);
+            for (int64_t j = 0; j < 6 * n_tets; ++j) etl[pos[m.tet_edges[j]]++] = (int32_t)(j / 6);
+            std::vector<int32_t> len(ne0, 1), nb;
+            for (int64_t e = 0; e < ne0; ++e) {
+                if (m.bedge[e]) continue;
+                nb.clear();
+                for (int64_t j = ets[e]; j < ets[e + 1]; ++j)
+                    for (int i = 0; i < 6; ++i) {
+                        const int32_t c = m.tet_edges[6 * etl[j] + i];
+                        if (c != e && !m.bedge[c]) nb.push_back(c);
+                    }
+                std::sort(nb.begin(), nb.end());
+                len[e] = 1 + (int32_t)(std::unique(nb.begin(), nb.end()) - nb.begin());
+            }
+            for (int64_t w0 = 0; w0 < ne0; w0 += kSortWindow) {
+                const int64_t w1 = std::min<int64_t>(ne0, w0 + kSortWindow);
+                std::stable_sort(m.eiperm.begin() + w0, m.eiperm.begin() + w1,
+                                 [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+            }
+        }
         m.eperm.resize(ne0);
         for (int64_t d = 0; d < ne0; ++d) m.eperm[m.eiperm[d]] = (int32_t)d;
         m.dev_edges.resize(2 * ne0);

@@ -277,13 +277,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_b(int64_t n_rows, RowGrid rg
 
 // The part of row j's product that does not depend on the iteration's scalars: the three
 // sums sum_k A_jk R_k, sum_k A_jk W_k, sum_k A_jk S_k over the row's stored entries, and
-// the row's own entries.  A_j u' = sR - alpha sW - alpha beta sS, so the gathers of a row
-// can be issued before the scalars of this iteration are known.
+// the row's own entries (1 / A_jj from the row's first slot).  A_j u' = sR - alpha sW
+// - alpha beta sS, so the gathers of a row can be issued before the scalars of this
+// iteration are known.
 struct RowPart {
     double sR, sW, sS;
     double2 RW, SP;   // own R, W and S, P
     double x, dinv;
 };
+
+constexpr int kUnroll = 6;   // slots per batch of gathers (rows hold up to ~20 slots)
 
 __device__ __forceinline__ void row_part(RowPart& P, const int64_t* __restrict__ sp, const int32_t* __restrict__ col,
                                          const double* __restrict__ A, const CgVec* __restrict__ V,
@@ -298,25 +301,25 @@ __device__ __forceinline__ void row_part(RowPart& P, const int64_t* __restrict__
     P.RW = own[0];
     P.SP = own[1];
     P.x = x[r];
-    P.dinv = dinv[r];
+    P.dinv = real ? 1.0 / A[sp[sl] + lane] : 1.0;   // the diagonal is slot 0 of the row
     double r0 = 0.0, w0 = 0.0, s0 = 0.0, r1 = 0.0, w1 = 0.0, s1 = 0.0;
-    for (; k + 3 * 64 < k1; k += 4 * 64) {
-        int c[4];
-        double a[4];
+    for (; k + (kUnroll - 1) * 64 < k1; k += kUnroll * 64) {
+        int c[kUnroll];
+        double a[kUnroll];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kUnroll; ++q) {
             c[q] = col[k + 64 * q];
             a[q] = A[k + 64 * q];
         }
-        double2 rw[4];
-        double sv[4];
+        double2 rw[kUnroll];
+        double sv[kUnroll];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kUnroll; ++q) {
             rw[q] = *reinterpret_cast<const double2*>(V + c[q]);
             sv[q] = V[c[q]].S;
         }
 #pragma unroll
-        for (int q = 0; q < 4; q += 2) {
+        for (int q = 0; q < kUnroll; q += 2) {
             r0 += a[q] * rw[q].x;
             w0 += a[q] * rw[q].y;
             s0 += a[q] * sv[q];
@@ -344,12 +347,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
                                                      const CgVec* __restrict__ V, CgVec* __restrict__ V_new,
                                                      const double* __restrict__ part_in,
                                                      double* __restrict__ part_out, CgScalars* sc) {
-    // one read of the flag per workgroup, so all of its waves take the same branch
-    __shared__ int s_conv;
-    if (threadIdx.x == 0) s_conv = sc->converged;
-    __syncthreads();
-    if (s_conv) return;
-    // the previous kernel's partials and this workgroup's first rows are in flight together
+    // The converged flag, the previous kernel's partials and this workgroup's first rows
+    // are all in flight together; the flag (the same for every thread) is checked before
+    // any write, so a launch after convergence changes nothing.
+    const int conv = sc->converged;
     const int n_src = gridDim.x;
     double t[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -367,6 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
     int64_t row = lb * kBlock + threadIdx.x;
     bool active = lb < le && ((row >> 6) << 6) < n_rows;
     if (active) row_part(P, sp, col, A, V, x, dinv, row, row < n_rows);
+    if (conv) return;
     block_sum_all<3>(t);
     const double g = t[0], d = t[1], rr = t[2];
     const bool done = !(rr > sc->tol2_bb) || sc->bb == 0.0;
