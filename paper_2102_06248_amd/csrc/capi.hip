@@ -186,6 +186,45 @@ void ev_mark(fepic_ctx* c, int i) {
     if (c->opt.timing) (void)hipEventRecord(c->phase_ev[i], c->stream);
 }
 
+// Crossing queue of the particle step: room for one slot per particle of the largest
+// species (rounded up to whole 256-particle workgroups), carved into the CrossQueue arrays.
+constexpr int64_t kQueueSlotBytes = 5 * 8 + 3 * 8 + 3 * 4;   // l0..l3, frac; dx (as FP64 at most); ids
+
+int ensure_queue(fepic_ctx* c) {
+    int64_t need = 0;
+    for (const auto& s : c->species) need = std::max(need, (s.n + 255) / 256 * 256);
+    if (need <= c->cq_cap) return FEPIC_OK;
+    const int64_t cap = std::max<int64_t>(need, (c->cq_cap + c->cq_cap / 4 + 255) / 256 * 256);
+    unsigned char* p = (unsigned char*)dmalloc(c, (size_t)cap * kQueueSlotBytes + (size_t)(cap / 256) * 4 + 256);
+    if (!p) return fail(c, FEPIC_E_OOM, "crossing queue allocation failed");
+    dfree(c, c->d_cq);
+    c->d_cq = p;
+    c->cq_cap = cap;
+    return FEPIC_OK;
+}
+
+template <typename T>
+CrossQueue<T> cqueue(fepic_ctx* c) {
+    CrossQueue<T> q;
+    const int64_t n = c->cq_cap;
+    double* d = (double*)c->d_cq;
+    q.l0 = d;
+    q.l1 = d + n;
+    q.l2 = d + 2 * n;
+    q.l3 = d + 3 * n;
+    q.frac = d + 4 * n;
+    T* t = (T*)(d + 5 * n);
+    q.dx0 = t;
+    q.dx1 = t + n;
+    q.dx2 = t + 2 * n;
+    int32_t* i = (int32_t*)(d + 8 * n);
+    q.idx = i;
+    q.tet = i + n;
+    q.entry = i + 2 * n;
+    q.wg_count = i + 3 * n;
+    return q;
+}
+
 // Particle half: optional sort, staging, gather/push/track/deposit into d_dgn and the
 // alternate particle buffers.  Nothing is committed here.
 template <typename T>
@@ -202,7 +241,10 @@ void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
     }
     ev_mark(c, 2);
     launch_fill(c->stream, c->d_dgn, c->mesh.n_edges, 0.0);
-    if (hipMemsetAsync(c->d_cnt, 0, sizeof(PushCounters), c->stream) != hipSuccess) c->deferred_err = FEPIC_E_HIP;
+    if (ensure_queue(c) != FEPIC_OK) {
+        c->deferred_err = FEPIC_E_OOM;
+        return;
+    }
     for (auto& s : c->species) {
         if (s.n == 0) continue;
         PushParams pp;
@@ -213,9 +255,10 @@ void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
         hipEvent_t* ev = timer_pair(c, FAM_PUSH);
         if (ev) (void)hipEventRecord(ev[0], c->stream);
         launch_push<T>(c->stream, parr<T>(s, s.cur), parr<T>(s, 1 - s.cur), s.n, (const TetBlock<T>*)c->d_blk,
-                       c->d_dgn, pp, c->d_cnt, s.sorted_pending ? s.d_nlive : nullptr);
+                       c->d_dgn, pp, c->d_cnt_slots, s.sorted_pending ? s.d_nlive : nullptr, cqueue<T>(c));
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
+    launch_cnt_finish(c->stream, c->d_cnt_slots, c->d_cnt);
     ev_mark(c, 3);
 }
 
@@ -790,12 +833,14 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
     c->d_partial = dalloc<double>(c, (int64_t)partial_buffer_doubles());
     c->d_sc = dalloc<CgScalars>(c, 1);
     c->d_cnt = dalloc<PushCounters>(c, 1);
+    c->d_cnt_slots = dalloc<PushCounters>(c, kCntSlots);
+    if (c->d_cnt_slots) HIPCHK(c, hipMemset(c->d_cnt_slots, 0, sizeof(PushCounters) * kCntSlots));
     c->d_acc = dalloc<DiagAcc>(c, 1);
     c->d_dotc = dalloc<unsigned int>(c, 1);
     c->d_count = dalloc<int32_t>(c, nt);
     c->d_offset = dalloc<int32_t>(c, nt);
     c->d_bsums = dalloc<int32_t>(c, nt / 1024 + 2);
-    if (!c->d_A || !c->d_dinv || !c->d_partial || !c->d_sc || !c->d_cnt || !c->d_acc || !c->d_count ||
+    if (!c->d_A || !c->d_dinv || !c->d_partial || !c->d_sc || !c->d_cnt || !c->d_cnt_slots || !c->d_acc || !c->d_count ||
         !c->d_offset || !c->d_bsums || !c->d_dotc)
         return fail(c, FEPIC_E_OOM, "device allocation failed");
     HIPCHK(c, hipMemset(c->d_sc, 0, sizeof(CgScalars)));

@@ -48,12 +48,31 @@ struct PArrays {
     int64_t* id;
 };
 
+// Particles whose path crosses a face in the first kernel of the particle step, queued
+// for the second: SoA, slot blockIdx * 256 + rank within the first kernel's workgroup
+// (capacity = its grid * 256), with the per-workgroup counts in wg_count.
+template <typename T>
+struct CrossQueue {
+    double *l0, *l1, *l2, *l3;  // barycentric start in the entered tet
+    double* frac;               // fraction of the step's displacement still to go
+    T *dx0, *dx1, *dx2;         // the step's displacement
+    int32_t *idx, *tet, *entry; // particle slot, entered tet, its local index of the entry face
+    int32_t* wg_count;
+};
+// A workgroup of the second kernel takes the queue regions of up to this many
+// consecutive first-kernel workgroups.
+constexpr int kCrossGroupMax = 32;
+
 struct PushParams {
     double dt;
     double qm_half_dt;   // q dt / (2 m)
     double qw;           // q w (deposit scale)
     int cap;             // crossing cap
 };
+
+// The particle kernel adds its per-workgroup counts into kCntSlots copies of the counters
+// (workgroup b -> slot b mod kCntSlots); launch_cnt_finish folds them into one.
+constexpr int kCntSlots = 256;
 
 struct PushCounters {
     unsigned long long n_crossings;
@@ -107,7 +126,8 @@ void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double*
                   const double* grad64, const int32_t* tet_edges, const int32_t* tet_faces);
 template <typename T>
 void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const TetBlock<T>* blk, double* dg,
-                 PushParams pp, PushCounters* cnt, const int32_t* n_live);
+                 PushParams pp, PushCounters* cnt, const int32_t* n_live, CrossQueue<T> cq);
+void launch_cnt_finish(hipStream_t s, PushCounters* slots, PushCounters* out);
 template <typename T>
 void launch_locate(hipStream_t s, int64_t n, const double* x, const double* u, const int64_t* id, int64_t id_base,
                    PArrays<T> out, int64_t out_off, const double* grad64, const double* r0, const int32_t* cell_start,

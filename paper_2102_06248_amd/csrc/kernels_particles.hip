@@ -5,6 +5,8 @@
 // Wave64 throughout; particles are kept sorted by tet so that lanes of a wave read the
 // same 128-byte tet record and the current of their first path piece can be summed
 // across the wave before the FP64 atomics.
+#include <algorithm>
+
 #include "fepic_internal.h"
 
 namespace fepic {
@@ -92,19 +94,116 @@ __device__ __forceinline__ double pick4(int idx, const double v[4]) {
     return r;
 }
 
+// First exit of a straight piece from barycentric point ls along dl (d lambda over the
+// rest of the step): the smallest ls_k / (-dl_k) over faces with dl_k < 0, other than the
+// entry face; kb = -1 if the piece ends inside (t* >= 1).  Ties go to the smallest k.
+__device__ __forceinline__ void exit_search(const double ls[4], const double dl[4], int entry, double& best,
+                                            int& kb) {
+    best = 1.0;
+    kb = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k != entry && dl[k] < 0.0) {
+            const double tk = ls[k] / (-dl[k]);
+            if (tk < best) {
+                best = tk;
+                kb = k;
+            }
+        }
+    }
+}
+
+// Barycentric coordinates in the neighbour across the face opposite local kb, whose far
+// vertex is its local q: shared vertices keep their relative order (both tets are sorted
+// by node id), so new local k != q takes old local index r + (r >= kb), r = k - (k > q).
+__device__ __forceinline__ void enter_neighbour(const double le[4], int kb, int q, double ln[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int r = k - (k > q ? 1 : 0);
+        ln[k] = (k == q) ? 0.0 : pick4(r + (r >= kb ? 1 : 0), le);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void path_step(const T g[4][3], const T dx[3], double frac, double dl[4]) {
+#pragma unroll
+    for (int k = 1; k < 4; ++k) dl[k] = frac * (double)(g[k][0] * dx[0] + g[k][1] * dx[1] + g[k][2] * dx[2]);
+    dl[0] = -(dl[1] + dl[2] + dl[3]);
+}
+
+// End point of the last piece, rounded to storage precision (clamped at 0) before the
+// piece's current is formed, so the stored state and the deposit agree exactly.
+template <typename T>
+__device__ __forceinline__ void end_point(const double ls[4], const double dl[4], T r[3], double le[4]) {
+    r[0] = (T)fmax(ls[1] + dl[1], 0.0);
+    r[1] = (T)fmax(ls[2] + dl[2], 0.0);
+    r[2] = (T)fmax(ls[3] + dl[3], 0.0);
+    le[1] = (double)r[0];
+    le[2] = (double)r[1];
+    le[3] = (double)r[2];
+    le[0] = 1.0 - le[1] - le[2] - le[3];
+}
+
+// Counters: summed across the wave, then across the workgroup in LDS; one thread adds the
+// workgroup's totals into one of kCntSlots slots (so no single address takes an atomic
+// from every wave); k_cnt_finish folds the slots afterwards.  Every thread must call it.
+__device__ __forceinline__ void add_counters(unsigned int sc, unsigned int mc, unsigned int na, unsigned int ncap,
+                                             PushCounters* __restrict__ cnt) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sc += __shfl_xor(sc, off);
+        mc = max(mc, (unsigned int)__shfl_xor(mc, off));
+        na += __shfl_xor(na, off);
+        ncap += __shfl_xor(ncap, off);
+    }
+    __shared__ unsigned int s_cnt[kBlock / 64][4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_cnt[w][0] = sc;
+        s_cnt[w][1] = mc;
+        s_cnt[w][2] = na;
+        s_cnt[w][3] = ncap;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int tc = 0, tm = 0, ta = 0, tp = 0;
+#pragma unroll
+        for (int k = 0; k < kBlock / 64; ++k) {
+            tc += s_cnt[k][0];
+            tm = max(tm, s_cnt[k][1]);
+            ta += s_cnt[k][2];
+            tp += s_cnt[k][3];
+        }
+        PushCounters* slot = cnt + (blockIdx.x & (kCntSlots - 1));
+        if (tc) atomicAdd(&slot->n_crossings, (unsigned long long)tc);
+        if (tm) atomicMax(&slot->max_crossings, tm);
+        if (ta) atomicAdd(&slot->n_absorbed, ta);
+        if (tp) atomicAdd(&slot->n_cap, tp);
+    }
+}
+
+// The particle step, first piece: gather E and B in the particle's tet, relativistic
+// Boris, and the straight path up to its first face crossing (or its end).  Particles
+// whose path continues into a neighbour are compacted, per workgroup, into the crossing
+// queue (slots blockIdx * kBlock + rank, count in wg_count) and finished by k_cross; their
+// u and id are final here.  First-piece currents are summed over runs of lanes that share
+// a tet (the particles are sorted by tet) before the FP64 atomics.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, int64_t n,
                                                   const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
                                                   PushParams pp, PushCounters* __restrict__ cnt,
-                                                  const int32_t* __restrict__ n_live) {
+                                                  const int32_t* __restrict__ n_live, CrossQueue<T> cq) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     if (n_live) n = min(n, (int64_t)*n_live);
     int t0 = -1;
     if (i < n) t0 = in.tet[i];
     double first[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    unsigned int ncross = 0;
-    int status = 0;
+    int status = 0;       // 1 absorbed, 2 crossing cap
+    bool cross = false;   // continues in k_cross
+    double ln[4] = {0.0, 0.0, 0.0, 0.0}, frac = 0.0;
+    T dx[3] = {T(0), T(0), T(0)};
+    int tn = 0, q = 0;
     if (t0 >= 0) {
         const TetBlock<T>* bp = blk + t0;
         const T l1 = in.l1[i], l2 = in.l2[i], l3 = in.l3[i];
@@ -137,146 +236,264 @@ __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, 
         u[2] = um[2] + s2 * (up[0] * tv[1] - up[1] * tv[0]) + h * E[2];
         const T ginv = T(1) / tsqrt<T>(T(1) + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic2);
         const T dtt = (T)pp.dt;
-        const T dx[3] = {dtt * u[0] * ginv, dtt * u[1] * ginv, dtt * u[2] * ginv};
+        dx[0] = dtt * u[0] * ginv;
+        dx[1] = dtt * u[1] * ginv;
+        dx[2] = dtt * u[2] * ginv;
 
-        // path in barycentric coordinates of the current tet; exit points kept in FP64
-        double ls[4] = {1.0 - (double)l1 - (double)l2 - (double)l3, (double)l1, (double)l2, (double)l3};
+        // path in barycentric coordinates of the tet; exit points kept in FP64
+        const double ls[4] = {1.0 - (double)l1 - (double)l2 - (double)l3, (double)l1, (double)l2, (double)l3};
         double dl[4];
-#pragma unroll
-        for (int k = 1; k < 4; ++k) dl[k] = (double)(g[k][0] * dx[0] + g[k][1] * dx[1] + g[k][2] * dx[2]);
-        dl[0] = -(dl[1] + dl[2] + dl[3]);
-        int t = t0, entry = -1;
-        double frac = 1.0;
-        for (int seg = 0;; ++seg) {
-            double best = 1.0;
-            int kb = -1;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (k != entry && dl[k] < 0.0) {
-                    const double tk = ls[k] / (-dl[k]);
-                    if (tk < best) {
-                        best = tk;
-                        kb = k;
-                    }
-                }
-            }
-            double le[4];
-            double cur[6];
-            if (kb < 0) {
-                // the rest of the path stays in t: store the end point rounded to storage
-                // precision and deposit up to exactly that stored point
-                const T r1 = (T)fmax(ls[1] + dl[1], 0.0);
-                const T r2 = (T)fmax(ls[2] + dl[2], 0.0);
-                const T r3 = (T)fmax(ls[3] + dl[3], 0.0);
-                le[1] = (double)r1;
-                le[2] = (double)r2;
-                le[3] = (double)r3;
-                le[0] = 1.0 - le[1] - le[2] - le[3];
-                piece_current(pp.qw, ls, le, cur);
-                if (seg == 0) {
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) first[c] = cur[c];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) atomic_add_f64(dg + bp->edge[c], cur[c]);
-                }
-                out.tet[i] = t;
-                out.l1[i] = r1;
-                out.l2[i] = r2;
-                out.l3[i] = r3;
-                out.u0[i] = u[0];
-                out.u1[i] = u[1];
-                out.u2[i] = u[2];
-                out.id[i] = in.id[i];
-                break;
-            }
+        path_step(g, dx, 1.0, dl);
+        double best;
+        int kb;
+        exit_search(ls, dl, -1, best, kb);
+        double le[4];
+        if (kb < 0) {
+            T r[3];
+            end_point(ls, dl, r, le);
+            piece_current(pp.qw, ls, le, first);
+            out.tet[i] = t0;
+            out.l1[i] = r[0];
+            out.l2[i] = r[1];
+            out.l3[i] = r[2];
+        } else {
 #pragma unroll
             for (int k = 0; k < 4; ++k) le[k] = (k == kb) ? 0.0 : ls[k] + best * dl[k];
-            piece_current(pp.qw, ls, le, cur);
-            if (seg == 0) {
-#pragma unroll
-                for (int c = 0; c < 6; ++c) first[c] = cur[c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < 6; ++c) atomic_add_f64(dg + bp->edge[c], cur[c]);
-            }
+            piece_current(pp.qw, ls, le, first);
             const int nb = bp->nbr[kb];
-            if (nb < 0) {  // wall: absorbed after depositing up to it
+            if (nb < 0) {           // wall: absorbed after depositing up to it
                 status = 1;
                 out.tet[i] = -1;
-                break;
-            }
-            if (++ncross > (unsigned)pp.cap) {
+            } else if (pp.cap < 1) {
                 status = 2;
                 out.tet[i] = -1;
-                break;
+            } else {
+                cross = true;
+                tn = nb >> 2;
+                q = nb & 3;
+                enter_neighbour(le, kb, q, ln);
+                frac = 1.0 - best;
             }
-            const int tn = nb >> 2, q = nb & 3;
-            // shared vertices keep their relative order (both tets are sorted by node id):
-            // new local k != q takes old local index r + (r >= kb), r = k - (k > q)
-            double ln[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int r = k - (k > q ? 1 : 0);
-                ln[k] = (k == q) ? 0.0 : pick4(r + (r >= kb ? 1 : 0), le);
-            }
-            frac *= (1.0 - best);
-            t = tn;
-            bp = blk + tn;
-            load_grads(bp, g);
-#pragma unroll
-            for (int k = 1; k < 4; ++k)
-                dl[k] = frac * (double)(g[k][0] * dx[0] + g[k][1] * dx[1] + g[k][2] * dx[2]);
-            dl[0] = -(dl[1] + dl[2] + dl[3]);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) ls[k] = ln[k];
-            entry = q;
+        }
+        if (status == 0) {
+            out.u0[i] = u[0];
+            out.u1[i] = u[1];
+            out.u2[i] = u[2];
+            out.id[i] = in.id[i];
         }
     } else if (i < n) {
         out.tet[i] = -1;
     }
 
-    // Sum the first-piece currents of lanes that share a start tet (runs of equal keys
-    // in the sorted order) with a segmented scan across the wave; the last lane of each
-    // run issues the six FP64 atomics for the whole run.
-    const int key = t0;
-    const int prev_key = __shfl_up(key, 1);
-    int f = (lane == 0) || (key != prev_key);
+    // first-piece currents: one sum and six atomics per run of lanes sharing a tet
+    {
+        const int key = t0;
+        const int prev_key = __shfl_up(key, 1);
+        int f = (lane == 0) || (key != prev_key);
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        double o[6];
+        for (int off = 1; off < 64; off <<= 1) {
+            double o[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) o[c] = __shfl_up(first[c], off);
-        const int fo = __shfl_up(f, off);
-        if (lane >= off) {
-            if (!f) {
+            for (int c = 0; c < 6; ++c) o[c] = __shfl_up(first[c], off);
+            const int fo = __shfl_up(f, off);
+            if (lane >= off) {
+                if (!f) {
 #pragma unroll
-                for (int c = 0; c < 6; ++c) first[c] += o[c];
+                    for (int c = 0; c < 6; ++c) first[c] += o[c];
+                }
+                f |= fo;
             }
-            f |= fo;
+        }
+        const int next_key = __shfl_down(key, 1);
+        if (key >= 0 && (lane == 63 || next_key != key)) {
+            const TetBlock<T>* bk = blk + key;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) atomic_add_f64(dg + bk->edge[c], first[c]);
         }
     }
-    const int next_key = __shfl_down(key, 1);
-    if (key >= 0 && (lane == 63 || next_key != key)) {
-        const TetBlock<T>* bk = blk + key;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) atomic_add_f64(dg + bk->edge[c], first[c]);
-    }
 
-    // per-wave counters
-    unsigned int sc = ncross, mc = ncross, na = (status == 1), ncap = (status == 2);
+    // compact the crossing lanes of the workgroup into its queue region
+    {
+        __shared__ int s_wc[kBlock / 64];
+        const int w = threadIdx.x >> 6;
+        const unsigned long long m = __ballot(cross);
+        if (lane == 0) s_wc[w] = (int)__popcll(m);
+        __syncthreads();
+        int base = 0, total = 0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        sc += __shfl_xor(sc, off);
-        mc = max(mc, (unsigned int)__shfl_xor(mc, off));
-        na += __shfl_xor(na, off);
-        ncap += __shfl_xor(ncap, off);
+        for (int k = 0; k < kBlock / 64; ++k) {
+            base += (k < w) ? s_wc[k] : 0;
+            total += s_wc[k];
+        }
+        if (cross) {
+            const int64_t slot =
+                (int64_t)blockIdx.x * kBlock + base + (int)__popcll(m & ((1ull << lane) - 1ull));
+            cq.l0[slot] = ln[0];
+            cq.l1[slot] = ln[1];
+            cq.l2[slot] = ln[2];
+            cq.l3[slot] = ln[3];
+            cq.frac[slot] = frac;
+            cq.dx0[slot] = dx[0];
+            cq.dx1[slot] = dx[1];
+            cq.dx2[slot] = dx[2];
+            cq.idx[slot] = (int32_t)i;
+            cq.tet[slot] = tn;
+            cq.entry[slot] = q;
+        }
+        if (threadIdx.x == 0) cq.wg_count[blockIdx.x] = total;
     }
-    if (lane == 0) {
-        if (sc) atomicAdd(&cnt->n_crossings, (unsigned long long)sc);
-        if (mc) atomicMax(&cnt->max_crossings, mc);
-        if (na) atomicAdd(&cnt->n_absorbed, na);
-        if (ncap) atomicAdd(&cnt->n_cap, ncap);
+    const unsigned int c1 = (cross || status == 2) ? 1u : 0u;   // a refused crossing counts, as in k_cross
+    add_counters(c1, c1, status == 1, status == 2, cnt);
+}
+
+// Per-workgroup accumulation of edge currents in LDS: an open-addressed table keyed by
+// edge id (linear probing, insertion by compare-and-swap), flushed with one FP64 global
+// atomic per distinct edge.  An insert that finds no slot within kProbe steps goes to
+// global memory directly.
+constexpr int kHashBits = 11;
+constexpr int kHashSlots = 1 << kHashBits;
+constexpr int kProbe = 16;
+
+__device__ __forceinline__ void lds_add(int* s_key, double* s_val, double* __restrict__ dg, int e, double v) {
+    if (v == 0.0) return;
+    unsigned int h = ((unsigned int)e * 2654435761u) >> (32 - kHashBits);
+    for (int p = 0; p < kProbe; ++p) {
+        const int k = atomicCAS(s_key + h, -1, e);
+        if (k == -1 || k == e) {
+            __hip_atomic_fetch_add(s_val + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
+        h = (h + 1) & (kHashSlots - 1);
+    }
+    atomic_add_f64(dg + e, v);
+}
+
+// The rest of the paths that crossed a face in k_push: each thread takes queued particles
+// of a group of `per` consecutive k_push workgroups (their queue regions concatenated) and
+// walks them tet by tet, up to the end point or a wall.  Piece currents are summed per
+// edge in the workgroup's LDS table, then added to global memory once per edge.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cross(PArrays<T> out, CrossQueue<T> cq, int64_t n_wg, int per,
+                                                   const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
+                                                   PushParams pp, PushCounters* __restrict__ cnt) {
+    __shared__ int s_pre[kCrossGroupMax + 1];
+    __shared__ int s_key[kHashSlots];
+    __shared__ double s_val[kHashSlots];
+    for (int k = threadIdx.x; k < kHashSlots; k += kBlock) {
+        s_key[k] = -1;
+        s_val[k] = 0.0;
+    }
+    const int64_t g0 = (int64_t)blockIdx.x * per;
+    const int nr = (int)min((int64_t)per, n_wg - g0);
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int r = 0; r < nr; ++r) {
+            s_pre[r] = acc;
+            acc += cq.wg_count[g0 + r];
+        }
+        s_pre[nr] = acc;
+    }
+    __syncthreads();
+    const int total = s_pre[nr];
+    unsigned int sc = 0, mc = 0, na = 0, ncap = 0;
+    for (int j = threadIdx.x; j < total; j += kBlock) {
+        int r = 0;
+        while (r + 1 < nr && s_pre[r + 1] <= j) ++r;
+        const int64_t slot = (g0 + r) * kBlock + (j - s_pre[r]);
+        const int64_t i = cq.idx[slot];
+        int t = cq.tet[slot], entry = cq.entry[slot];
+        double ls[4] = {cq.l0[slot], cq.l1[slot], cq.l2[slot], cq.l3[slot]};
+        double frac = cq.frac[slot];
+        const T dx[3] = {cq.dx0[slot], cq.dx1[slot], cq.dx2[slot]};
+        const TetBlock<T>* bp = blk + t;
+        T g[4][3];
+        load_grads(bp, g);
+        double dl[4];
+        path_step(g, dx, frac, dl);
+        unsigned int nc = 1;   // crossings of this particle in this step
+        for (;;) {
+            double best;
+            int kb;
+            exit_search(ls, dl, entry, best, kb);
+            double le[4], cur[6];
+            if (kb < 0) {
+                T rr[3];
+                end_point(ls, dl, rr, le);
+                piece_current(pp.qw, ls, le, cur);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) lds_add(s_key, s_val, dg, bp->edge[c], cur[c]);
+                out.tet[i] = t;
+                out.l1[i] = rr[0];
+                out.l2[i] = rr[1];
+                out.l3[i] = rr[2];
+                break;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) le[k] = (k == kb) ? 0.0 : ls[k] + best * dl[k];
+            piece_current(pp.qw, ls, le, cur);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) lds_add(s_key, s_val, dg, bp->edge[c], cur[c]);
+            const int nb = bp->nbr[kb];
+            if (nb < 0) {
+                ++na;
+                out.tet[i] = -1;
+                break;
+            }
+            if (++nc > (unsigned)pp.cap) {
+                ++ncap;
+                out.tet[i] = -1;
+                break;
+            }
+            const int q = nb & 3;
+            double ln[4];
+            enter_neighbour(le, kb, q, ln);
+            frac *= (1.0 - best);
+            t = nb >> 2;
+            bp = blk + t;
+            load_grads(bp, g);
+            path_step(g, dx, frac, dl);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ls[k] = ln[k];
+            entry = q;
+        }
+        sc += nc - 1;
+        mc = max(mc, nc);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kHashSlots; k += kBlock)
+        if (s_key[k] >= 0) atomic_add_f64(dg + s_key[k], s_val[k]);
+    add_counters(sc, mc, na, ncap, cnt);
+}
+
+// Folds the per-slot push counters into *out and clears the slots for the next step.
+__global__ __launch_bounds__(kCntSlots) void k_cnt_finish(PushCounters* __restrict__ slots,
+                                                          PushCounters* __restrict__ out) {
+    __shared__ unsigned long long s_c[kCntSlots];
+    __shared__ unsigned int s_m[kCntSlots], s_a[kCntSlots], s_p[kCntSlots];
+    const int t = threadIdx.x;
+    PushCounters v = slots[t];
+    s_c[t] = v.n_crossings;
+    s_m[t] = v.max_crossings;
+    s_a[t] = v.n_absorbed;
+    s_p[t] = v.n_cap;
+    slots[t] = PushCounters{};
+    __syncthreads();
+    for (int h = kCntSlots / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            s_c[t] += s_c[t + h];
+            s_m[t] = max(s_m[t], s_m[t + h]);
+            s_a[t] += s_a[t + h];
+            s_p[t] += s_p[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        PushCounters r{};
+        r.n_crossings = s_c[0];
+        r.max_crossings = s_m[0];
+        r.n_absorbed = s_a[0];
+        r.n_cap = s_p[0];
+        *out = r;
     }
 }
 
@@ -349,11 +566,26 @@ __global__ __launch_bounds__(kBlock) void k_zero_i32(int32_t* p, int64_t n) {
     if (i < n) p[i] = 0;
 }
 
+// Runs of equal keys in a wave (the particles are nearly sorted by tet between sorts):
+// for each lane the first lane of its run and the run's length, from a ballot of the
+// run starts.
+__device__ __forceinline__ void key_run(int key, int lane, int& start, int& len) {
+    const int prev = __shfl_up(key, 1);
+    const unsigned long long starts = __ballot(lane == 0 || key != prev);
+    const unsigned long long upto = (2ull << lane) - 1ull;   // lanes 0..lane (all for 63)
+    start = 63 - __clzll(starts & upto);
+    const unsigned long long after = starts & ~upto;
+    len = (after ? __ffsll((long long)after) - 1 : 64) - start;
+}
+
+// count[t] += number of particles in t; one atomic per run of equal tets in a wave.
 __global__ __launch_bounds__(kBlock) void k_hist(const int32_t* __restrict__ tet, int64_t n, int32_t* count) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int t = tet[i];
-    if (t >= 0) atomicAdd(count + t, 1);
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int t = i < n ? tet[i] : -1;
+    int start, len;
+    key_run(t, lane, start, len);
+    if (t >= 0 && lane == start) atomicAdd(count + t, len);
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads = 4 waves).
@@ -430,11 +662,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(int32_t* __restrict__ out, 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scatter(PArrays<T> in, PArrays<T> out, int64_t n,
                                                      int32_t* __restrict__ offset) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int t = in.tet[i];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int t = i < n ? in.tet[i] : -1;
+    int start, len;
+    key_run(t, lane, start, len);
+    // the run's first lane reserves len places in t's range; lanes keep their order
+    int base = 0;
+    if (t >= 0 && lane == start) base = atomicAdd(offset + t, len);
+    base = __shfl(base, start);
     if (t < 0) return;
-    const int pos = atomicAdd(offset + t, 1);
+    const int pos = base + (lane - start);
     out.tet[pos] = t;
     out.l1[pos] = in.l1[i];
     out.l2[pos] = in.l2[i];
@@ -464,6 +702,10 @@ __global__ __launch_bounds__(kBlock) void k_rho(PArrays<T> p, int64_t n, const i
 }  // namespace
 
 // ------------------------------------------------------------------------- launchers
+void launch_cnt_finish(hipStream_t s, PushCounters* slots, PushCounters* out) {
+    hipLaunchKernelGGL(k_cnt_finish, dim3(1), dim3(kCntSlots), 0, s, slots, out);
+}
+
 template <typename T>
 void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double* e, const double* b,
                   const double* grad64, const int32_t* tet_edges, const int32_t* tet_faces) {
@@ -474,9 +716,15 @@ void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double*
 
 template <typename T>
 void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const TetBlock<T>* blk, double* dg,
-                 PushParams pp, PushCounters* cnt, const int32_t* n_live) {
+                 PushParams pp, PushCounters* cnt, const int32_t* n_live, CrossQueue<T> cq) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_push<T>, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live);
+    const int64_t n_wg = grid_1d(n, kBlock);
+    hipLaunchKernelGGL(k_push<T>, dim3((unsigned)n_wg), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live,
+                       cq);
+    // enough groups to fill the chip; each concatenates up to kCrossGroupMax queue regions
+    const int per = (int)std::min<int64_t>(kCrossGroupMax, std::max<int64_t>(1, n_wg / 2048));
+    hipLaunchKernelGGL(k_cross<T>, dim3((unsigned)((n_wg + per - 1) / per)), dim3(kBlock), 0, s, out, cq, n_wg, per,
+                       blk, dg, pp, cnt);
 }
 
 template <typename T>
@@ -514,7 +762,7 @@ void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, dou
     template void launch_stage<T>(hipStream_t, int64_t, TetBlock<T>*, const double*, const double*,             \
                                   const double*, const int32_t*, const int32_t*);                                \
     template void launch_push<T>(hipStream_t, PArrays<T>, PArrays<T>, int64_t, const TetBlock<T>*, double*,      \
-                                 PushParams, PushCounters*, const int32_t*);                                     \
+                                 PushParams, PushCounters*, const int32_t*, CrossQueue<T>);                      \
     template void launch_locate<T>(hipStream_t, int64_t, const double*, const double*, const int64_t*, int64_t,  \
                                    PArrays<T>, int64_t, const double*, const double*, const int32_t*,            \
                                    const int32_t*, const double*, const double*, const int32_t*, PushCounters*); \
