@@ -721,8 +721,9 @@ void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const 
     const int64_t n_wg = grid_1d(n, kBlock);
     hipLaunchKernelGGL(k_push<T>, dim3((unsigned)n_wg), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live,
                        cq);
-    // enough groups to fill the chip; each concatenates up to kCrossGroupMax queue regions
-    const int per = (int)std::min<int64_t>(kCrossGroupMax, std::max<int64_t>(1, n_wg / 2048));
+    // about one resident round of k_cross workgroups (256 CUs x 6, as its LDS table allows);
+    // each concatenates up to kCrossGroupMax queue regions
+    const int per = (int)std::min<int64_t>(kCrossGroupMax, std::max<int64_t>(1, (n_wg + 1535) / 1536));
     hipLaunchKernelGGL(k_cross<T>, dim3((unsigned)((n_wg + per - 1) / per)), dim3(kBlock), 0, s, out, cq, n_wg, per,
                        blk, dg, pp, cnt);
 }

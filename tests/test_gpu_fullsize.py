@@ -92,3 +92,64 @@ def test_beam_full_size_two_steps(F):
             assert np.linalg.norm(b - osim.b) <= 1e-6 * np.linalg.norm(osim.b) + 1e-30
     finally:
         L.close()
+
+
+def test_plasma_full_size_sampled(F):
+    """Plasma ball at full size (998,250 tets, 8M electron/proton pairs, FP32 push): the first
+    step starts from zero fields (co-located pairs carry no charge; the library's start
+    differs from zero by the round-off of the cancelling pairs only), so the particles of a
+    seeded sample move independently of the rest and the oracle pushes them one by one.
+    Continuity (every interior node) and the Newmark solve's true residual are checked at
+    full size with the oracle's incidence matrix and operator."""
+    announce("full-size plasma ball: 998,250 tets, 16M particles, sampled step vs oracle")
+    wl = workloads.c3_plasma()
+    dt, beta, gamma = wl["dt"], wl["beta"], wl["gamma"]
+    n = len(wl["species"][0]["x"])
+    sample = np.random.default_rng(12).choice(n, 100_000, replace=False)
+
+    osim = OracleSim(wl["xyz"], wl["tets"])
+    m = osim.mesh
+    h = np.linalg.norm(m.xyz[m.edges[:, 1]] - m.xyz[m.edges[:, 0]], axis=1).min()
+    L = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=wl["precision"], warm_start=F.FEPIC_WS_PREV,
+                     sort_period=1)
+    try:
+        sps, sos = [], []
+        for sp in wl["species"]:
+            s = F.fepic_add_species(L.ctx, sp["q"], sp["m"], sp["w"])
+            assert F.fepic_upload_particles(L.ctx, s, sp["x"], sp["u"], ids=np.arange(n)) == 0
+            sps.append(s)
+            so = osim.add_species(sp["q"], sp["m"], sp["w"])
+            assert osim.upload_particles(so, sp["x"][sample], sp["u"][sample], ids=sample) == 0
+            sos.append(so)
+        F.fepic_init_electrostatic(L.ctx, 1e-12)
+        e0, ep0, b0 = F.fepic_get_fields(L.ctx)       # round-off of the cancelling pairs only
+        rho0 = F.fepic_get_rho(L.ctx, m.n_nodes)
+        st = F.fepic_step(L.ctx, dt, beta, gamma)
+        print(f"\n[full] plasma step: cg {st.cg_iters} iters, {st.n_crossings} crossings, "
+              f"{st.n_absorbed} absorbed")
+        ost = osim.step(dt, beta, gamma, solve=False)
+        for s, so in zip(sps, sos):
+            gp = F.fepic_get_particles(L.ctx, s)
+            keep = np.isin(gp["id"], sample)
+            sub = {k: v[keep] for k, v in gp.items()}
+            ncommon, nodd = compare_particles(sub, osim.particles(so), h, 1e-5, 1e-5)
+            assert ncommon >= len(sample) - 2 and nodd <= 2
+        # continuity on interior nodes and the solve's residual, at full size
+        e, _, _ = F.fepic_get_fields(L.ctx)
+        dG, G = F.fepic_get_current(L.ctx)
+        rho = F.fepic_get_rho(L.ctx, m.n_nodes)
+        interior = ~m.boundary_node
+        cont = (rho - rho0) - odiag.divergence_T(osim.D, dG)
+        # the pairs' charges cancel, so the round-off scale is the gross nodal charge
+        gross = np.zeros(m.n_nodes)
+        for s, sp in zip(sps, wl["species"]):
+            gp = F.fepic_get_particles(L.ctx, s)
+            np.add.at(gross, m.tets[gp["tet"]].ravel(), (abs(sp["q"] * sp["w"]) * gp["lam"]).ravel())
+        assert np.abs(cont[interior]).max() <= 1e-12 * gross[interior].max()
+        ie = osim.ie
+        A, B1, B2 = osim.operators(dt, beta, gamma)
+        rhs = B1 @ e0[ie] + B2 @ ep0[ie] - dG[ie]          # G^0 = G^{-1} = 0
+        r = rhs - A @ e[ie]
+        assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(rhs)
+    finally:
+        L.close()
