@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/s (gather+push+deposit) + Newmark step time at CG resid 1e-10"
 HBM_PEAK_GBS = 8000.0
 FAMILIES = ["push", "stage", "sort", "rhs", "cg_iter", "faraday"]
-KERNEL_NAMES = {"push": "k_push", "stage": "k_stage", "sort": "k_hist/k_scan/k_scatter", "rhs": "k_rhs",
+KERNEL_NAMES = {"push": "k_push+k_cross", "stage": "k_stage", "sort": "k_hist/k_scan/k_scatter", "rhs": "k_rhs",
                 "cg_iter": "k_cg_iter", "faraday": "k_faraday"}
 KERNEL_SOURCES = {"push": "kernels_particles.hip", "stage": "kernels_particles.hip", "sort": "kernels_particles.hip",
                   "rhs": "kernels_fields.hip", "cg_iter": "kernels_fields.hip", "faraday": "kernels_fields.hip"}
@@ -45,8 +45,8 @@ def algorithmic_bytes(fam, geo, st):
     """Bytes the method must move per launch (each HBM word once), by kernel family."""
     n_rows, nnz, ne, nf, nt = geo["n_rows"], geo["nnz"], geo["n_edges"], geo["n_faces"], geo["n_tets"]
     npart, occ, cross = st["particles"], st["occupied_tets"], st["crossings"]
-    if fam == "cg_iter":      # A values + columns once; r, w, s, p, x, dinv read; r, w, s, p, x written
-        return 12 * nnz + 88 * n_rows
+    if fam == "cg_iter":      # A values + columns once; per row R, W, S, P and x read and written
+        return 12 * nnz + 80 * n_rows
     if fam == "rhs":          # M, S values + columns; e, e_prev, dG_new, dG_old read; b written
         return 20 * nnz + 40 * n_rows
     if fam == "push":         # particle state read + written (tet, 3 lambda, 3 u at 4 B);
@@ -79,18 +79,23 @@ def traffic_from_profile(fam, workload, launches_bytes_per):
 
 
 def cpu_baseline(wl, n_sample=None):
-    """The oracle, single-threaded, on one full step of the same workload (all particles,
-    from its own electrostatic start): particle push + Newmark solve."""
+    """The oracle, single-threaded, on the same workload from its own electrostatic start.
+    Beam: one full step over all particles (particle push + Newmark solve).  Plasma balls
+    (whose field solve takes thousands of iterations on the full mesh): the particle push
+    of a seeded sample of particles only."""
     from threadpoolctl import threadpool_limits
 
     from oracle.pic import OracleSim
 
+    plasma = "plasma" in wl["name"]
+    if plasma and n_sample is None:
+        n_sample = 1_000_000
     with threadpool_limits(limits=1):
         osim = OracleSim(wl["xyz"], wl["tets"])
         n_total = 0
         for sp in wl["species"]:
             s = osim.add_species(sp["q"], sp["m"], sp["w"])
-            k = len(sp["x"]) if n_sample is None else min(n_sample, len(sp["x"]))
+            k = len(sp["x"]) if n_sample is None else min(n_sample // len(wl["species"]), len(sp["x"]))
             osim.upload_particles(s, sp["x"][:k], sp["u"][:k])
             n_total += k
         if wl.get("B0") is not None:
@@ -99,6 +104,11 @@ def cpu_baseline(wl, n_sample=None):
         t0 = time.perf_counter()
         dG, _ = osim.push_particles(wl["dt"])
         t_push = time.perf_counter() - t0
+        if plasma:
+            return {"value": n_total / t_push, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+                    "sample": (f"particle push of the first {n_total} particles of the workload's seeded draw "
+                               f"({t_push:.2f} s), field solve not timed; single thread"),
+                    "push_particle_steps_per_s": n_total / t_push}
         ie = osim.ie
         A, B1, B2 = osim.operators(wl["dt"], wl["beta"], wl["gamma"])
         rhs = B1 @ osim.e[ie] + B2 @ osim.e_prev[ie] - (dG - osim.dG)[ie]
@@ -118,9 +128,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2_beam", choices=["c2_beam", "c3_plasma"])
-    ap.add_argument("--particles", type=int, default=None, help="override the particle count (pairs for c3)")
-    ap.add_argument("--warm-start", default="prev", choices=["prev", "extrap1", "extrap2"])
+    ap.add_argument("--workload", default="c2_beam", choices=["c2_beam", "c3_plasma", "c5_plasma"])
+    ap.add_argument("--particles", type=int, default=None, help="override the particle count (pairs for plasmas)")
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "fp64"],
+                    help="particle path precision (auto: the workload's; fp64 = all-FP64 path)")
+    ap.add_argument("--warm-start", default="prev", choices=["prev", "extrap1", "extrap2", "mlp"])
+    ap.add_argument("--train-steps", type=int, default=40,
+                    help="mlp: plain steps recorded for training before the warm-up steps")
+    ap.add_argument("--diagnostics", action="store_true",
+                    help="run the conservation diagnostics every step (continuity, Gauss drift)")
     ap.add_argument("--sort-period", type=int, default=1)
     ap.add_argument("--inject", type=int, default=1, help="inject the beam's per-step batch (c2)")
     ap.add_argument("--cpu-sample", type=int, default=None, help="limit the oracle's particle count")
@@ -147,9 +163,11 @@ def main():
     wl = workloads.WORKLOADS[args.workload](**kw)
     log(f"[bench] workload {wl['name']} built in {time.perf_counter() - t0:.1f}s: "
         f"{len(wl['tets'])} tets, {sum(len(s['x']) for s in wl['species'])} particles")
-    ws = {"prev": F.FEPIC_WS_PREV, "extrap1": F.FEPIC_WS_EXTRAP1, "extrap2": F.FEPIC_WS_EXTRAP2}[args.warm_start]
-    sim = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=wl["precision"], warm_start=ws,
-                       sort_period=args.sort_period, timing=1)
+    ws = {"prev": F.FEPIC_WS_PREV, "extrap1": F.FEPIC_WS_EXTRAP1, "extrap2": F.FEPIC_WS_EXTRAP2,
+          "mlp": F.FEPIC_WS_PREV}[args.warm_start]
+    precision = {"auto": wl["precision"], "fp32": 0, "fp64": 1}[args.precision]
+    sim = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=precision, warm_start=ws,
+                       sort_period=args.sort_period, timing=1, diagnostics=1 if args.diagnostics else 0)
     ctx = sim.ctx
     species = []
     for sp in wl["species"]:
@@ -162,7 +180,9 @@ def main():
     it = F.fepic_init_electrostatic(ctx, 1e-12)
     log(f"[bench] electrostatic start: {it} CG iterations")
     inject = args.inject and wl.get("inject_per_step")
-    batches = [workloads.c2_injection_batch(k) for k in range(args.warmup + args.steps)] if inject else []
+    n_train = args.train_steps if args.warm_start == "mlp" else 0
+    batches = ([workloads.c2_injection_batch(k) for k in range(n_train + args.warmup + args.steps)]
+               if inject else [])
     next_id = [10 ** 9]
 
     def one_step(k):
@@ -173,8 +193,22 @@ def main():
             F.fepic_inject_particles(ctx, species[0], x, u, ids=ids)
         return F.fepic_step(ctx, wl["dt"], wl["beta"], wl["gamma"])
 
+    learned = None
+    if n_train:
+        # learned warm start: record plain solves, train on the GPU, then solve from the network
+        F.fepic_ws_record(ctx, 1, n_train)
+        plain_iters = []
+        for k in range(n_train):
+            st = one_step(k)
+            plain_iters.append(st.cg_iters)
+        F.fepic_ws_record(ctx, 0)
+        tst = F.fepic_ws_train(ctx, epochs=6, batch=8192, lr=2e-3, seed=1, val_fraction=0.25)
+        F.fepic_set_warm_start(ctx, F.FEPIC_WS_MLP)
+        learned = {"train_steps": n_train, "plain_cg_iters_mean_while_recording": round(float(np.mean(plain_iters)), 2),
+                   "train": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in tst.as_dict().items()}}
+        log(f"[bench] trained the warm-start network on {n_train} solves: {learned['train']}")
     for k in range(args.warmup):
-        st = one_step(k)
+        st = one_step(n_train + k)
         log(f"[bench] warmup {k}: cg {st.cg_iters} iters, {st.n_particles} particles, {st.n_crossings} crossings")
     # geometry of the work, for algorithmic bytes
     sizes = F.fepic_get_topology_sizes(ctx)
@@ -193,16 +227,18 @@ def main():
     for k in range(args.steps):
         n_before = sum(F.fepic_num_particles(ctx, s) for s in species) if k == 0 else stats[-1].n_particles
         if inject:
-            n_before += len(batches[args.warmup + k][0])
-        st = one_step(args.warmup + k)
+            n_before += len(batches[n_train + args.warmup + k][0])
+        st = one_step(n_train + args.warmup + k)
         psteps += n_before
         cg_iters.append(st.cg_iters)
         cross += st.n_crossings
         newmark_ms.append(st.ms_rhs + st.ms_warm + st.ms_cg + st.ms_faraday)
         push_ms.append(st.ms_stage + st.ms_particles)
         stats.append(st)
+        diag = (f", continuity {st.cont_resid_rel:.2e}, gauss drift {st.gauss_drift_check_rel:.2e}"
+                if args.diagnostics else "")
         log(f"[bench] step {k}: cg {st.cg_iters} iters, {st.n_particles} particles, {st.n_crossings} crossings, "
-            f"push {push_ms[-1]:.3f} ms, newmark {newmark_ms[-1]:.3f} ms")
+            f"push {push_ms[-1]:.3f} ms, newmark {newmark_ms[-1]:.3f} ms{diag}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -246,13 +282,14 @@ def main():
     out = {
         "metric": METRIC, "value": psteps / elapsed, "unit": "particle-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if precision == 0 else "f64",
         "data": "synthetic",
         "config": {"workload": wl["name"], "tets": len(wl["tets"]), "particles": n_total,
                    "mean_live_particles": round(mean_particles), "dt": wl["dt"], "beta": wl["beta"],
                    "gamma": wl["gamma"], "cg_tol": 1e-10, "warm_start": args.warm_start,
                    "sort_period": args.sort_period, "inject_per_step": int(wl.get("inject_per_step") or 0) if inject else 0,
-                   "precision": "fp32 push / fp64 deposit+solve", "parallelism": "single GPU"},
+                   "precision": ("fp32 push / fp64 deposit+solve" if precision == 0 else "all fp64"),
+                   "diagnostics_in_timed_steps": bool(args.diagnostics), "parallelism": "single GPU"},
         "newmark_ms_per_step": round(float(np.mean(newmark_ms)), 4),
         "cg_iters_mean": round(float(np.mean(cg_iters)), 2),
         "push": push_info,
@@ -261,6 +298,14 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if learned is not None:
+        learned["mlp_cg_iters_mean"] = out["cg_iters_mean"]
+        out["learned_warm_start"] = learned
+    if args.diagnostics:
+        out["conservation"] = {
+            "cont_resid_rel_max": max(st.cont_resid_rel for st in stats),
+            "gauss_drift_check_rel_max": max(st.gauss_drift_check_rel for st in stats),
+            "gauss_resid_rel_max": max(st.gauss_resid_rel for st in stats)}
     print(json.dumps(out), flush=True)
     sim.close()
 
