@@ -193,10 +193,12 @@ int fepic_get_rho(fepic_ctx* ctx, double* rho);
 int fepic_diagnostics(fepic_ctx* ctx, fepic_step_stats* out);
 
 /* ---------------------------------------------------------------- profiling
- * Brackets every launch of the named kernel family ("push", "stage", "sort", "rhs",
- * "cg_iter", "faraday", "mlp_fwd") with HIP events on the context's stream
- * while enabled; fepic_kernel_time returns the summed duration and launch count since
- * enabling (synchronizes the stream). */
+ * Brackets the launches of the named kernel family ("push", "stage", "sort", "rhs",
+ * "cg_iter", "faraday", "mlp_fwd") with HIP events on the context's stream while
+ * enabled: one pair per launch, except "cg_iter", whose pair spans each batch of
+ * back-to-back iteration launches (so its per-launch average includes the dispatch gap
+ * between iterations, and events do not separate them).  fepic_kernel_time returns the
+ * summed duration and the launch count since enabling (synchronizes the stream). */
 int fepic_kernel_timing(fepic_ctx* ctx, const char* family, int enable);
 int fepic_kernel_time(fepic_ctx* ctx, const char* family, double* total_ms, int64_t* launches);
 

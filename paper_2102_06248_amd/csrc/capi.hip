@@ -42,9 +42,10 @@ void dfree(fepic_ctx* c, void* p) {
     (void)hipFree(p);
 }
 
-hipEvent_t* timer_pair(fepic_ctx* c, int fam) {
+hipEvent_t* timer_pair(fepic_ctx* c, int fam, int64_t n_launches) {
     if (fam < 0 || !c->timers[fam].on) return nullptr;
     KernelTimer& k = c->timers[fam];
+    k.launches += n_launches;
     if (k.used + 2 > (int64_t)k.ev.size()) {
         for (int i = 0; i < 256; ++i) {
             hipEvent_t e;
@@ -350,9 +351,12 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
             }
             // the launch after the budget only checks (and is discarded on failure)
             todo = std::min(todo, budget + 1 - launched);
+            hipEvent_t* ev = timer_pair(c, FAM_CG_ITER, todo);
+            if (ev) (void)hipEventRecord(ev[0], c->stream);
             for (int k = 0; k < todo; ++k)
                 launch_cg_iter(c->stream, launched + k, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, V,
-                               c->d_partial, c->d_sc, timer_pair(c, FAM_CG_ITER));
+                               c->d_partial, c->d_sc);
+            if (ev) (void)hipEventRecord(ev[1], c->stream);
             launched += todo;
         }
         if (restart == 0) rr0_first = c->h_sc->rr0;
@@ -1288,6 +1292,7 @@ int fepic_kernel_timing(fepic_ctx* c, const char* family, int enable) {
             HIPCHK(c, hipStreamSynchronize(c->stream));
             k.on = enable != 0;
             k.used = 0;
+            k.launches = 0;
             // pre-create events so the timed region does not create them
             while ((int64_t)k.ev.size() < 2 * (int64_t)std::max(enable, 0)) {
                 hipEvent_t e;
@@ -1313,7 +1318,7 @@ int fepic_kernel_time(fepic_ctx* c, const char* family, double* total_ms, int64_
                 tot += ms;
             }
             if (total_ms) *total_ms = tot;
-            if (launches) *launches = k.used / 2;
+            if (launches) *launches = k.launches;
             return FEPIC_OK;
         }
     return fail(c, FEPIC_E_ARG, std::string("unknown kernel family ") + family);

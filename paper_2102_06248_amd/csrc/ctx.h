@@ -17,7 +17,8 @@ extern const char* kFamilies[];
 
 struct KernelTimer {
     bool on = false;
-    int64_t used = 0;
+    int64_t used = 0;       // events recorded (pairs * 2)
+    int64_t launches = 0;   // kernel launches the pairs span
     std::vector<hipEvent_t> ev;
 };
 
@@ -121,7 +122,7 @@ int hip_fail(fepic_ctx* c, hipError_t e, const char* what);
 int fail(fepic_ctx* c, int code, const std::string& msg);
 void* dmalloc(fepic_ctx* c, size_t bytes);
 void dfree(fepic_ctx* c, void* p);
-hipEvent_t* timer_pair(fepic_ctx* c, int fam);
+hipEvent_t* timer_pair(fepic_ctx* c, int fam, int64_t n_launches = 1);
 
 int init_electrostatic(fepic_ctx* c, double tol, int* iters);
 int mlp_warm_start(fepic_ctx* c);

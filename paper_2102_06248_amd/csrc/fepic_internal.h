@@ -155,7 +155,7 @@ void launch_cg_init(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, con
                     double tol);
 void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
                     const double* A, const double* dinv, double* x, CgVec* const v[2], double* partial,
-                    CgScalars* sc, hipEvent_t* ev);
+                    CgScalars* sc);
 void launch_cg_rr0(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc);
 void launch_cg_resid(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
                      const double* A, const double* b, double* x, double* r_true, double* partial,

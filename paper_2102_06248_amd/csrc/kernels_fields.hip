@@ -604,16 +604,13 @@ void launch_cg_init(hipStream_t s, int64_t n_rows, const int64_t* sp, const int3
 
 // Iteration i reads the interleaved state from buffer i & 1 and writes buffer (i + 1) & 1.
 void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
-                    const double* dinv, double* x, CgVec* const v[2], double* partial, CgScalars* sc,
-                    hipEvent_t* ev) {
+                    const double* dinv, double* x, CgVec* const v[2], double* partial, CgScalars* sc) {
     const RowGrid rg = row_grid(n_rows);
     const int a = i & 1, b = 1 - a;
     const double* part_in = partial + (i == 0 ? SLOT_INIT : (a ? SLOT_UPD : SLOT_SPMV)) * kSlot;
     double* part_out = partial + (b ? SLOT_UPD : SLOT_SPMV) * kSlot;
-    if (ev) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(k_cg_iter, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, dinv, x, v[a], v[b],
                        part_in, part_out, sc);
-    if (ev) (void)hipEventRecord(ev[1], s);
 }
 
 void launch_cg_rr0(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc) {
