@@ -256,7 +256,8 @@ void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
         hipEvent_t* ev = timer_pair(c, FAM_PUSH);
         if (ev) (void)hipEventRecord(ev[0], c->stream);
         launch_push<T>(c->stream, parr<T>(s, s.cur), parr<T>(s, 1 - s.cur), s.n, (const TetBlock<T>*)c->d_blk,
-                       c->d_dgn, pp, c->d_cnt_slots, s.sorted_pending ? s.d_nlive : nullptr, cqueue<T>(c));
+                       c->d_dgn, pp, c->d_cnt_slots, s.sorted_pending ? s.d_nlive : nullptr, cqueue<T>(c),
+                       c->cross_share);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
     launch_cnt_finish(c->stream, c->d_cnt_slots, c->d_cnt);
@@ -482,6 +483,11 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipGetLastError());
     st.n_crossings = (int64_t)c->h_cnt->n_crossings;
+    {
+        int64_t n_all = 0;
+        for (const auto& sp : c->species) n_all += sp.n;
+        c->cross_share = n_all > 0 ? (double)st.n_crossings / (double)n_all : 1.0;
+    }
     st.max_crossings = (int)c->h_cnt->max_crossings;
     st.n_absorbed = c->h_cnt->n_absorbed;
     st.n_cap_exceeded = (int)c->h_cnt->n_cap;

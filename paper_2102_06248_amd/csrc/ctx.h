@@ -75,6 +75,7 @@ struct fepic_ctx {
     fepic::PushCounters* d_cnt_slots = nullptr;   // [kCntSlots], zero between steps
     unsigned char* d_cq = nullptr;                 // crossing queue storage (CrossQueue arrays)
     int64_t cq_cap = 0;                            // its capacity in slots (multiple of 256)
+    double cross_share = 1.0;                      // face crossings per particle, last step
     fepic::PushCounters* h_cnt = nullptr;
     int deferred_err = 0;
     // injection staging: pinned host buffer and its device mirror (x, u, id)

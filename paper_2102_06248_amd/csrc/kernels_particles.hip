@@ -147,6 +147,7 @@ __device__ __forceinline__ void end_point(const double ls[4], const double dl[4]
 // Counters: summed across the wave, then across the workgroup in LDS; one thread adds the
 // workgroup's totals into one of kCntSlots slots (so no single address takes an atomic
 // from every wave); k_cnt_finish folds the slots afterwards.  Every thread must call it.
+template <int kB = kBlock>
 __device__ __forceinline__ void add_counters(unsigned int sc, unsigned int mc, unsigned int na, unsigned int ncap,
                                              PushCounters* __restrict__ cnt) {
 #pragma unroll
@@ -156,7 +157,7 @@ __device__ __forceinline__ void add_counters(unsigned int sc, unsigned int mc, u
         na += __shfl_xor(na, off);
         ncap += __shfl_xor(ncap, off);
     }
-    __shared__ unsigned int s_cnt[kBlock / 64][4];
+    __shared__ unsigned int s_cnt[kB / 64][4];
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         s_cnt[w][0] = sc;
@@ -168,7 +169,7 @@ __device__ __forceinline__ void add_counters(unsigned int sc, unsigned int mc, u
     if (threadIdx.x == 0) {
         unsigned int tc = 0, tm = 0, ta = 0, tp = 0;
 #pragma unroll
-        for (int k = 0; k < kBlock / 64; ++k) {
+        for (int k = 0; k < kB / 64; ++k) {
             tc += s_cnt[k][0];
             tm = max(tm, s_cnt[k][1]);
             ta += s_cnt[k][2];
@@ -346,60 +347,51 @@ __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, 
     add_counters(c1, c1, status == 1, status == 2, cnt);
 }
 
-// Per-workgroup accumulation of edge currents in LDS: an open-addressed table keyed by
-// edge id (linear probing, insertion by compare-and-swap), flushed with one FP64 global
-// atomic per distinct edge.  An insert that finds no slot within kProbe steps goes to
-// global memory directly.
-constexpr int kHashBits = 11;
-constexpr int kHashSlots = 1 << kHashBits;
+// Per-workgroup accumulation of edge currents in LDS: an open-addressed table of 2^kBits
+// slots keyed by edge id (linear probing, insertion by compare-and-swap), flushed with one
+// FP64 global atomic per distinct edge.  An insert that finds no slot within kProbe steps
+// goes to global memory directly.
 constexpr int kProbe = 16;
 
+template <int kBits>
 __device__ __forceinline__ void lds_add(int* s_key, double* s_val, double* __restrict__ dg, int e, double v) {
     if (v == 0.0) return;
-    unsigned int h = ((unsigned int)e * 2654435761u) >> (32 - kHashBits);
+    unsigned int h = ((unsigned int)e * 2654435761u) >> (32 - kBits);
     for (int p = 0; p < kProbe; ++p) {
         const int k = atomicCAS(s_key + h, -1, e);
         if (k == -1 || k == e) {
             __hip_atomic_fetch_add(s_val + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             return;
         }
-        h = (h + 1) & (kHashSlots - 1);
+        h = (h + 1) & ((1u << kBits) - 1u);
     }
     atomic_add_f64(dg + e, v);
 }
 
-// The rest of the paths that crossed a face in k_push: each thread takes queued particles
-// of a group of `per` consecutive k_push workgroups (their queue regions concatenated) and
-// walks them tet by tet, up to the end point or a wall.  Piece currents are summed per
-// edge in the workgroup's LDS table, then added to global memory once per edge.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cross(PArrays<T> out, CrossQueue<T> cq, int64_t n_wg, int per,
-                                                   const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
-                                                   PushParams pp, PushCounters* __restrict__ cnt) {
-    __shared__ int s_pre[kCrossGroupMax + 1];
-    __shared__ int s_key[kHashSlots];
-    __shared__ double s_val[kHashSlots];
-    for (int k = threadIdx.x; k < kHashSlots; k += kBlock) {
+constexpr int log2_const(int v) { return v <= 1 ? 0 : 1 + log2_const(v / 2); }
+
+// The rest of the paths that crossed a face in k_push: workgroup b takes the queue region
+// of k_push workgroup b (up to 256 particles) with kB threads and walks each particle tet
+// by tet, up to the end point or a wall.  Piece currents are summed per edge in an LDS
+// table of 8 kB slots, then added to global memory once per edge.  kB is chosen from the
+// expected share of crossing particles, so most threads have one particle.
+template <typename T, int kB>
+__global__ __launch_bounds__(kB) void k_cross(PArrays<T> out, CrossQueue<T> cq, const TetBlock<T>* __restrict__ blk,
+                                              double* __restrict__ dg, PushParams pp,
+                                              PushCounters* __restrict__ cnt) {
+    constexpr int kBits = log2_const(8 * kB);
+    constexpr int kSlots = 1 << kBits;
+    __shared__ int s_key[kSlots];
+    __shared__ double s_val[kSlots];
+    for (int k = threadIdx.x; k < kSlots; k += kB) {
         s_key[k] = -1;
         s_val[k] = 0.0;
     }
-    const int64_t g0 = (int64_t)blockIdx.x * per;
-    const int nr = (int)min((int64_t)per, n_wg - g0);
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int r = 0; r < nr; ++r) {
-            s_pre[r] = acc;
-            acc += cq.wg_count[g0 + r];
-        }
-        s_pre[nr] = acc;
-    }
+    const int total = cq.wg_count[blockIdx.x];
     __syncthreads();
-    const int total = s_pre[nr];
     unsigned int sc = 0, mc = 0, na = 0, ncap = 0;
-    for (int j = threadIdx.x; j < total; j += kBlock) {
-        int r = 0;
-        while (r + 1 < nr && s_pre[r + 1] <= j) ++r;
-        const int64_t slot = (g0 + r) * kBlock + (j - s_pre[r]);
+    for (int j = threadIdx.x; j < total; j += kB) {
+        const int64_t slot = (int64_t)blockIdx.x * kBlock + j;
         const int64_t i = cq.idx[slot];
         int t = cq.tet[slot], entry = cq.entry[slot];
         double ls[4] = {cq.l0[slot], cq.l1[slot], cq.l2[slot], cq.l3[slot]};
@@ -421,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_cross(PArrays<T> out, CrossQueue<T> 
                 end_point(ls, dl, rr, le);
                 piece_current(pp.qw, ls, le, cur);
 #pragma unroll
-                for (int c = 0; c < 6; ++c) lds_add(s_key, s_val, dg, bp->edge[c], cur[c]);
+                for (int c = 0; c < 6; ++c) lds_add<kBits>(s_key, s_val, dg, bp->edge[c], cur[c]);
                 out.tet[i] = t;
                 out.l1[i] = rr[0];
                 out.l2[i] = rr[1];
@@ -432,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_cross(PArrays<T> out, CrossQueue<T> 
             for (int k = 0; k < 4; ++k) le[k] = (k == kb) ? 0.0 : ls[k] + best * dl[k];
             piece_current(pp.qw, ls, le, cur);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) lds_add(s_key, s_val, dg, bp->edge[c], cur[c]);
+            for (int c = 0; c < 6; ++c) lds_add<kBits>(s_key, s_val, dg, bp->edge[c], cur[c]);
             const int nb = bp->nbr[kb];
             if (nb < 0) {
                 ++na;
@@ -460,9 +452,9 @@ __global__ __launch_bounds__(kBlock) void k_cross(PArrays<T> out, CrossQueue<T> 
         mc = max(mc, nc);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kHashSlots; k += kBlock)
+    for (int k = threadIdx.x; k < kSlots; k += kB)
         if (s_key[k] >= 0) atomic_add_f64(dg + s_key[k], s_val[k]);
-    add_counters(sc, mc, na, ncap, cnt);
+    add_counters<kB>(sc, mc, na, ncap, cnt);
 }
 
 // Folds the per-slot push counters into *out and clears the slots for the next step.
@@ -716,16 +708,17 @@ void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double*
 
 template <typename T>
 void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const TetBlock<T>* blk, double* dg,
-                 PushParams pp, PushCounters* cnt, const int32_t* n_live, CrossQueue<T> cq) {
+                 PushParams pp, PushCounters* cnt, const int32_t* n_live, CrossQueue<T> cq, double cross_share) {
     if (n <= 0) return;
-    const int64_t n_wg = grid_1d(n, kBlock);
-    hipLaunchKernelGGL(k_push<T>, dim3((unsigned)n_wg), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live,
-                       cq);
-    // about one resident round of k_cross workgroups (256 CUs x 6, as its LDS table allows);
-    // each concatenates up to kCrossGroupMax queue regions
-    const int per = (int)std::min<int64_t>(kCrossGroupMax, std::max<int64_t>(1, (n_wg + 1535) / 1536));
-    hipLaunchKernelGGL(k_cross<T>, dim3((unsigned)((n_wg + per - 1) / per)), dim3(kBlock), 0, s, out, cq, n_wg, per,
-                       blk, dg, pp, cnt);
+    const unsigned n_wg = (unsigned)grid_1d(n, kBlock);
+    hipLaunchKernelGGL(k_push<T>, dim3(n_wg), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live, cq);
+    // one k_cross workgroup per k_push workgroup, sized for its expected queue length
+    if (cross_share <= 0.25)
+        hipLaunchKernelGGL((k_cross<T, 64>), dim3(n_wg), dim3(64), 0, s, out, cq, blk, dg, pp, cnt);
+    else if (cross_share <= 0.5)
+        hipLaunchKernelGGL((k_cross<T, 128>), dim3(n_wg), dim3(128), 0, s, out, cq, blk, dg, pp, cnt);
+    else
+        hipLaunchKernelGGL((k_cross<T, 256>), dim3(n_wg), dim3(256), 0, s, out, cq, blk, dg, pp, cnt);
 }
 
 template <typename T>
@@ -763,7 +756,7 @@ void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, dou
     template void launch_stage<T>(hipStream_t, int64_t, TetBlock<T>*, const double*, const double*,             \
                                   const double*, const int32_t*, const int32_t*);                                \
     template void launch_push<T>(hipStream_t, PArrays<T>, PArrays<T>, int64_t, const TetBlock<T>*, double*,      \
-                                 PushParams, PushCounters*, const int32_t*, CrossQueue<T>);                      \
+                                 PushParams, PushCounters*, const int32_t*, CrossQueue<T>, double);              \
     template void launch_locate<T>(hipStream_t, int64_t, const double*, const double*, const int64_t*, int64_t,  \
                                    PArrays<T>, int64_t, const double*, const double*, const int32_t*,            \
                                    const int32_t*, const double*, const double*, const int32_t*, PushCounters*); \
