@@ -159,6 +159,12 @@ int fepic_upload_particles(fepic_ctx* ctx, int species, int64_t n, const int64_t
  * The counts of live particles are exact again after the next fepic_step. */
 int fepic_inject_particles(fepic_ctx* ctx, int species, int64_t n, const int64_t* id, const double* x,
                            const double* u);
+/* The same with x, u ([n][3] FP64) and id ([n] int64, or NULL for default ids) in device
+ * memory of the context's device (e.g. torch tensors): read by kernels enqueued on the
+ * context's stream, with no host copy; the caller keeps them valid and unchanged until the
+ * stream has passed this call (e.g. until the next fepic_step returns). */
+int fepic_inject_particles_device(fepic_ctx* ctx, int species, int64_t n, const int64_t* id, const double* x,
+                                  const double* u);
 int fepic_num_particles(fepic_ctx* ctx, int species, int64_t* n);
 /* Copies live particles out (order = current device order): id, x [n][3] (Cartesian,
  * reconstructed as sum lambda_k r_k), u [n][3], tet [n], lambda [n][4] (local vertex

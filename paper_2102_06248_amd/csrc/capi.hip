@@ -1002,6 +1002,9 @@ int fepic_upload_particles(fepic_ctx* c, int species, int64_t n, const int64_t* 
     return FEPIC_OK;
 }
 
+static int inject_located(fepic_ctx* c, Species& s, int64_t n, const int64_t* did, const double* dx,
+                          const double* du);
+
 int fepic_inject_particles(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
                            const double* u) {
     NEED_DEV(c);
@@ -1041,6 +1044,13 @@ int fepic_inject_particles(fepic_ctx* c, int species, int64_t n, const int64_t* 
     const double* dx = (const double*)c->d_stage;
     const double* du = dx + 3 * n;
     const int64_t* did = id ? (const int64_t*)(du + 3 * n) : nullptr;
+    return inject_located(c, s, n, did, dx, du);
+}
+
+// Appends n particles read from device memory (x, u [n][3] FP64, id [n] or null) to
+// species s: located on the device in stream order, sorted by the next step.
+static int inject_located(fepic_ctx* c, Species& s, int64_t n, const int64_t* did, const double* dx,
+                          const double* du) {
     const double* g = c->d_grid;
     if (c->opt.precision == FEPIC_ALL_FP64)
         launch_locate<double>(c->stream, n, dx, du, did, s.next_id, parr<double>(s, s.cur), s.n, c->d_grad64, c->d_r0,
@@ -1053,6 +1063,20 @@ int fepic_inject_particles(fepic_ctx* c, int species, int64_t n, const int64_t* 
     c->rho_valid = false;
     c->rG_levels = 0;
     return FEPIC_OK;
+}
+
+int fepic_inject_particles_device(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
+                                  const double* u) {
+    NEED_DEV(c);
+    if (species < 0 || species >= (int)c->species.size() || n < 0 || (n > 0 && (!x || !u)))
+        return fail(c, FEPIC_E_ARG, "bad injection arguments");
+    if (n == 0) return FEPIC_OK;
+    Species& s = c->species[species];
+    int rc = sync_counts(c);
+    if (rc) return rc;
+    if (s.n + n >= ((int64_t)1 << 31)) return fail(c, FEPIC_E_ARG, "too many particles for one species");
+    if ((rc = ensure_capacity(c, s, s.n + n))) return rc;
+    return inject_located(c, s, n, id, x, u);
 }
 
 int fepic_num_particles(fepic_ctx* c, int species, int64_t* n) {

@@ -87,6 +87,7 @@ _SIGS = {
     "fepic_add_species": [_P, _D, _D, _D, ctypes.POINTER(_INT)],
     "fepic_upload_particles": [_P, _INT, _I64, _P, _P, _P, _PI64],
     "fepic_inject_particles": [_P, _INT, _I64, _P, _P, _P],
+    "fepic_inject_particles_device": [_P, _INT, _I64, _P, _P, _P],
     "fepic_num_particles": [_P, _INT, _PI64],
     "fepic_get_particles": [_P, _INT, _I64, _PI64, _P, _P, _P, _P, _P],
     "fepic_step": [_P, _D, _D, _D, ctypes.POINTER(fepic_step_stats)],
@@ -259,6 +260,12 @@ def fepic_inject_particles(ctx, species, x, u, ids=None):
     u = _arr(u, np.float64, (-1, 3))
     ids = None if ids is None else _arr(ids, np.int64)
     _check(ctx, lib().fepic_inject_particles(ctx, species, len(x), _ptr(ids), _ptr(x), _ptr(u)))
+
+
+def fepic_inject_particles_device(ctx, species, n, x_ptr, u_ptr, id_ptr=None):
+    """x_ptr, u_ptr: device addresses of [n][3] float64 arrays (e.g. tensor.data_ptr());
+    id_ptr: device address of [n] int64 ids, or None."""
+    _check(ctx, lib().fepic_inject_particles_device(ctx, species, n, id_ptr, x_ptr, u_ptr))
 
 
 def fepic_num_particles(ctx, species):

@@ -150,14 +150,16 @@ def test_checkpoint_round_trip(F, tmp_path):
 
 
 def test_injection_matches_upload(F):
-    """Particles injected between steps (no sort, no host wait) give the same state as
-    the same particles uploaded with the synchronous path."""
+    """Particles injected between steps (no sort, no host wait), from host arrays or from
+    device memory, give the same state as the same particles uploaded with the synchronous
+    path, and as the oracle."""
     announce("injection vs upload")
+    import torch
     from oracle.pic import OracleSim
     xyz, tets = inputs.prism_cylinder(0.05, 0.5, 6, 20)
     osim = OracleSim(xyz, tets)
     so = osim.add_species(-Q_E, M_E, 2e5)
-    sims = [F.Simulation(xyz, tets, device=0, precision=1) for _ in range(2)]
+    sims = [F.Simulation(xyz, tets, device=0, precision=1) for _ in range(3)]
     sps = [F.fepic_add_species(s.ctx, -Q_E, M_E, 2e5) for s in sims]
     nid = 0
     for k in range(4):
@@ -166,9 +168,14 @@ def test_injection_matches_upload(F):
         nid += len(x)
         F.fepic_upload_particles(sims[0].ctx, sps[0], x, u, ids=ids)
         F.fepic_inject_particles(sims[1].ctx, sps[1], x, u, ids=ids)
+        dev = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0") for a in (x, u, ids)]
+        torch.cuda.synchronize()
+        F.fepic_inject_particles_device(sims[2].ctx, sps[2], len(x), dev[0].data_ptr(), dev[1].data_ptr(),
+                                        dev[2].data_ptr())
         osim.upload_particles(so, x, u, ids=ids)
         for s in sims:
             F.fepic_step(s.ctx, 1e-10)
+        del dev                       # the steps above have consumed the device arrays
         osim.step(1e-10)
     ps = [F.fepic_get_particles(s.ctx, sp) for s, sp in zip(sims, sps)]
     po = osim.particles(so)
