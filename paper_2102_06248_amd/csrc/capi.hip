@@ -277,6 +277,8 @@ void ensure_operator(fepic_ctx* c, double dt, double beta) {
     c->A_valid = true;
 }
 
+constexpr int kMaxRestarts = 3;
+
 // Field half: RHS, warm start, PCG, true residual, Faraday into d_bn.  Returns the
 // iteration count via the host scalars (stream synchronized at return).
 int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
@@ -362,18 +364,20 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
         }
         if (restart == 0) rr0_first = c->h_sc->rr0;
         total += c->h_sc->iters;
-        // the stopping rule is on the true residual: if the recurrence drifted, restart
-        // from the current iterate
+        // The stopping rule is on the true residual.  If the recurrences drifted from it, or
+        // broke down (converged == 2: a non-positive or non-finite step), restart from the
+        // current iterate, up to kMaxRestarts times within the iteration budget.
         launch_cg_resid(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_rhs, c->d_x, c->d_rt, c->d_partial, c->d_sc);
         HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         const CgScalars& h = *c->h_sc;
-        if (h.converged != 1 || h.rr_true <= h.tol2_bb || restart >= 3 || total >= maxit) break;
+        if (h.rr_true <= h.tol2_bb || restart >= kMaxRestarts || total >= maxit || h.converged == 0) break;
         c->cg_restarts++;
     }
     c->h_sc->iters = total;
     c->h_sc->rr0 = rr0_first;
-    if (c->h_sc->converged == 1 && !(c->h_sc->rr_true <= c->h_sc->tol2_bb)) c->h_sc->converged = 0;
+    // success only when the true residual meets the tolerance
+    c->h_sc->converged = (c->h_sc->rr_true <= c->h_sc->tol2_bb) ? 1 : 0;
     ev_mark(c, 7);
     {
         hipEvent_t* ev = timer_pair(c, FAM_FARADAY);
