@@ -88,6 +88,9 @@ int upload(fepic_ctx* c, T** dst, const std::vector<T>& src) {
     return FEPIC_OK;
 }
 
+// Array a (0..7) of the species' current state.
+void* cur_arr(Species& s, int a) { return s.buf[a == 7 ? s.idcur : s.cur][a]; }
+
 template <typename T>
 PArrays<T> parr(Species& s, int which) {
     PArrays<T> p;
@@ -98,7 +101,7 @@ PArrays<T> parr(Species& s, int which) {
     p.u0 = (T*)s.buf[which][4];
     p.u1 = (T*)s.buf[which][5];
     p.u2 = (T*)s.buf[which][6];
-    p.id = (int64_t*)s.buf[which][7];
+    p.id = (int64_t*)s.buf[which == s.cur ? s.idcur : 1 - s.idcur][7];
     return p;
 }
 
@@ -120,7 +123,7 @@ int ensure_capacity(fepic_ctx* c, Species& s, int64_t need) {
             if (!nb[w][a]) return fail(c, FEPIC_E_OOM, "particle buffer allocation failed");
         }
     for (int a = 0; a < 8; ++a)
-        if (s.n > 0) HIPCHK(c, hipMemcpyAsync(nb[0][a], s.buf[s.cur][a], array_bytes(c, a, s.n), hipMemcpyDeviceToDevice, c->stream));
+        if (s.n > 0) HIPCHK(c, hipMemcpyAsync(nb[0][a], cur_arr(s, a), array_bytes(c, a, s.n), hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int w = 0; w < 2; ++w)
         for (int a = 0; a < 8; ++a) {
@@ -128,6 +131,7 @@ int ensure_capacity(fepic_ctx* c, Species& s, int64_t need) {
             s.buf[w][a] = nb[w][a];
         }
     s.cur = 0;
+    s.idcur = 0;
     s.cap = cap;
     return FEPIC_OK;
 }
@@ -140,6 +144,7 @@ void sort_species(fepic_ctx* c, Species& s) {
                    c->d_bsums, s.d_nlive);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
     s.cur = 1 - s.cur;
+    s.idcur = 1 - s.idcur;
     s.sorted_pending = true;
 }
 
@@ -1112,7 +1117,7 @@ int fepic_get_particles(fepic_ctx* c, int species, int64_t cap, int64_t* n, int6
     for (auto& v : hv) v.resize(N);
     if (N) {
         HIPCHK(c, hipMemcpy(ht.data(), s.buf[s.cur][0], 4 * N, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(hid.data(), s.buf[s.cur][7], 8 * N, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(hid.data(), cur_arr(s, 7), 8 * N, hipMemcpyDeviceToHost));
         for (int a = 1; a < 7; ++a) {
             if (c->opt.precision == FEPIC_ALL_FP64) {
                 HIPCHK(c, hipMemcpy(hv[a - 1].data(), s.buf[s.cur][a], 8 * N, hipMemcpyDeviceToHost));
@@ -1245,7 +1250,7 @@ int fepic_save(fepic_ctx* c, const char* path) {
         for (int a = 0; a < 8; ++a) {
             const size_t nb = array_bytes(c, a, s.n);
             std::vector<unsigned char> tmp(nb);
-            if (nb && hipMemcpy(tmp.data(), s.buf[s.cur][a], nb, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+            if (nb && hipMemcpy(tmp.data(), cur_arr(s, a), nb, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
             W(tmp.data(), nb);
         }
     }
@@ -1304,7 +1309,7 @@ int fepic_load(fepic_ctx* c, const char* path) {
             const size_t nb = array_bytes(c, a, n);
             std::vector<unsigned char> tmp(nb);
             R(tmp.data(), nb);
-            if (ok && nb && hipMemcpy(s.buf[s.cur][a], tmp.data(), nb, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+            if (ok && nb && hipMemcpy(cur_arr(s, a), tmp.data(), nb, hipMemcpyHostToDevice) != hipSuccess) ok = false;
         }
         s.n = n;
         s.next_id = next_id;

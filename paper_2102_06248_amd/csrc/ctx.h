@@ -29,6 +29,9 @@ struct Species {
     int cur = 0;
     int64_t next_id = 0;  // default ids
     void* buf[2][8] = {}; // tet, l1, l2, l3, u0, u1, u2, id
+    // The particle step keeps each particle's slot, so ids are not copied by it: the id
+    // arrays have their own current index, flipped only by the sort.
+    int idcur = 0;
     int32_t* d_nlive = nullptr;
     int32_t* h_nlive = nullptr;
     bool sorted_pending = false;  // d_nlive holds a count not yet read back

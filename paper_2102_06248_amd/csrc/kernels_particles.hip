@@ -279,8 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, 
         if (status == 0) {
             out.u0[i] = u[0];
             out.u1[i] = u[1];
-            out.u2[i] = u[2];
-            out.id[i] = in.id[i];
+            out.u2[i] = u[2];   // the slot (and its id) is kept: ids are not copied
         }
     } else if (i < n) {
         out.tet[i] = -1;
