@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define FEPIC_ABI_VERSION 1
+#define FEPIC_ABI_VERSION 2
 
 enum {
     FEPIC_OK = 0,
@@ -98,6 +98,8 @@ typedef struct {
     int max_crossings;            /* most crossings of one path this step                 */
     int n_cap_exceeded;           /* paths stopped by the crossing cap                    */
     float ms_sort, ms_stage, ms_particles, ms_rhs, ms_warm, ms_cg, ms_faraday, ms_diag;
+    double magnetic_energy;       /* 1/(2 mu0) int |B|^2 = 1/2 b^T [*mu0^-1] b, joules    */
+    double kinetic_energy;        /* sum over live particles of w m c^2 (gamma - 1), J    */
 } fepic_step_stats;
 
 /* ---------------------------------------------------------------- lifecycle */

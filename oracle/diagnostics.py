@@ -37,3 +37,16 @@ def continuity_residual(D, rho_new, rho_old, dG, interior_nodes):
 def gauss_residual(D, M, e, rho, interior_nodes):
     r = -(D.T @ (M @ e)) - rho
     return r[interior_nodes]
+
+
+def kinetic_energy(u, w, m, c):
+    """Sum over particles of w m c^2 (gamma - 1), gamma = sqrt(1 + |u|^2/c^2), u = gamma v
+    (relativistic kinetic energy of macro-particles of weight w), written with
+    gamma - 1 = (|u|^2/c^2) / (gamma + 1) to avoid cancellation at low speed."""
+    q = np.sum(np.asarray(u, dtype=np.float64) ** 2, axis=1) / c ** 2
+    return float(w * m * c ** 2 * np.sum(q / (np.sqrt(1.0 + q) + 1.0)))
+
+
+def magnetic_energy(Mf, b):
+    """1/2 b^T [*mu0^-1] b = 1/(2 mu0) int |B|^2 for the Whitney-2 field of the face fluxes b."""
+    return 0.5 * float(b @ (Mf @ b))

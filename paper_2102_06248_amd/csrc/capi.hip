@@ -437,6 +437,14 @@ int run_diagnostics(fepic_ctx* c, fepic_step_stats* st, bool have_step, bool hav
                       rG2, c->d_n3, have_hist, rG_new, c->d_acc);
     launch_divb(s, c->mesh.n_tets, c->d_tet_faces, c->d_b, c->d_acc);
     launch_dot(s, ne, c->d_e, c->d_Me, c->d_partial, &c->d_acc->energy);
+    launch_magnetic(s, c->mesh.n_tets, c->d_b, c->d_grad64, c->d_tet_faces, &c->d_acc->magnetic);
+    for (auto& sp : c->species) {
+        const double wmc2 = sp.w * sp.m * kC * kC;
+        if (c->opt.precision == FEPIC_ALL_FP64)
+            launch_kinetic<double>(s, parr<double>(sp, sp.cur), sp.n, wmc2, &c->d_acc->kinetic);
+        else
+            launch_kinetic<float>(s, parr<float>(sp, sp.cur), sp.n, wmc2, &c->d_acc->kinetic);
+    }
     HIPCHK(c, hipMemcpyAsync(c->h_acc, c->d_acc, sizeof(DiagAcc), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     auto dbl = [](unsigned long long v) {
@@ -451,6 +459,8 @@ int run_diagnostics(fepic_ctx* c, fepic_step_stats* st, bool have_step, bool hav
         st->gauss_drift_check_rel = have_hist ? dbl(c->h_acc->drift_max) / scale : -1.0;
         st->divb_max = dbl(c->h_acc->divb_max);
         st->field_energy = 0.5 * c->h_acc->energy;
+        st->magnetic_energy = c->h_acc->magnetic;
+        st->kinetic_energy = c->h_acc->kinetic;
     }
     // rotate: the new charge becomes the current one; Gauss residual history
     std::swap(c->d_rho, c->d_rho_new);

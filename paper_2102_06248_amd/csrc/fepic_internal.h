@@ -103,7 +103,8 @@ struct alignas(32) CgVec {
 // Device-side diagnostics accumulators (max-abs values stored as ordered bit patterns).
 struct DiagAcc {
     unsigned long long cont_max, gauss_max, drift_max, rho_max, divb_max;
-    double energy;
+    double energy;            // e^T M e
+    double magnetic, kinetic; // joules
     unsigned int counter;
     unsigned int pad;
 };
@@ -135,6 +136,10 @@ void launch_sort(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, int64_
                  int32_t* offset, int32_t* block_sums, int32_t* n_live_dev);
 template <typename T>
 void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, double qw, double* rho);
+void launch_magnetic(hipStream_t s, int64_t n_tets, const double* b, const double* grad64, const int32_t* tet_faces,
+                     double* out);
+template <typename T>
+void launch_kinetic(hipStream_t s, PArrays<T> p, int64_t n, double wmc2, double* out);
 
 // Field kernels (kernels_fields.hip).
 void launch_fill(hipStream_t s, double* x, int64_t n, double v);

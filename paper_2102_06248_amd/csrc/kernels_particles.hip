@@ -692,7 +692,90 @@ __global__ __launch_bounds__(kBlock) void k_rho(PArrays<T> p, int64_t n, const i
 
 }  // namespace
 
+// ------------------------------------------------------------------------- energies
+// Sum of v over the workgroup, then one atomic add into *out (diagnostics only).
+__device__ __forceinline__ void block_add(double v, double* out) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __shared__ double s_w[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < kBlock / 64; ++k) t += s_w[k];
+        atomic_add_f64(out, t);
+    }
+}
+
+// Magnetic energy 1/(2 mu0) int |B|^2: the Whitney-2 field of a divergence-free flux is
+// constant in each tet, B = sum_k b_k W2_k, so each tet adds V |B|^2 / (2 mu0), with
+// V = 1 / (6 |det(grad l1, grad l2, grad l3)|).
+__global__ __launch_bounds__(kBlock) void k_magnetic(int64_t n_tets, const double* __restrict__ b,
+                                                      const double* __restrict__ grad64,
+                                                      const int32_t* __restrict__ tet_faces, double* out) {
+    double acc = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n_tets; t += (int64_t)gridDim.x * kBlock) {
+        double g[4][3];
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) g[k][d] = grad64[9 * t + 3 * (k - 1) + d];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+        constexpr int F[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+        double Bv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double* gi = g[F[k][0]];
+            const double* gj = g[F[k][1]];
+            const double* gl = g[F[k][2]];
+            const double bf = 0.5 * b[tet_faces[4 * t + k]];
+            Bv[0] += bf * ((gj[1] * gl[2] - gj[2] * gl[1]) + (gl[1] * gi[2] - gl[2] * gi[1]) +
+                           (gi[1] * gj[2] - gi[2] * gj[1]));
+            Bv[1] += bf * ((gj[2] * gl[0] - gj[0] * gl[2]) + (gl[2] * gi[0] - gl[0] * gi[2]) +
+                           (gi[2] * gj[0] - gi[0] * gj[2]));
+            Bv[2] += bf * ((gj[0] * gl[1] - gj[1] * gl[0]) + (gl[0] * gi[1] - gl[1] * gi[0]) +
+                           (gi[0] * gj[1] - gi[1] * gj[0]));
+        }
+        const double det = g[1][0] * (g[2][1] * g[3][2] - g[2][2] * g[3][1]) -
+                           g[1][1] * (g[2][0] * g[3][2] - g[2][2] * g[3][0]) +
+                           g[1][2] * (g[2][0] * g[3][1] - g[2][1] * g[3][0]);
+        const double vol = 1.0 / (6.0 * fabs(det));
+        acc += vol * (Bv[0] * Bv[0] + Bv[1] * Bv[1] + Bv[2] * Bv[2]) / (2.0 * kMu0);
+    }
+    block_add(acc, out);
+}
+
+// Kinetic energy sum_p w m c^2 (gamma - 1), with gamma - 1 = (u^2/c^2) / (gamma + 1).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_kinetic(PArrays<T> p, int64_t n, double wmc2, double* out) {
+    double acc = 0.0;
+    const double ic2 = 1.0 / (kC * kC);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        if (p.tet[i] < 0) continue;
+        const double u0 = p.u0[i], u1 = p.u1[i], u2 = p.u2[i];
+        const double q = (u0 * u0 + u1 * u1 + u2 * u2) * ic2;
+        acc += wmc2 * q / (sqrt(1.0 + q) + 1.0);
+    }
+    block_add(acc, out);
+}
+
 // ------------------------------------------------------------------------- launchers
+void launch_magnetic(hipStream_t s, int64_t n_tets, const double* b, const double* grad64, const int32_t* tet_faces,
+                     double* out) {
+    if (n_tets <= 0) return;
+    hipLaunchKernelGGL(k_magnetic, dim3((unsigned)std::min<int64_t>(1024, grid_1d(n_tets, kBlock))), dim3(kBlock), 0,
+                       s, n_tets, b, grad64, tet_faces, out);
+}
+
+template <typename T>
+void launch_kinetic(hipStream_t s, PArrays<T> p, int64_t n, double wmc2, double* out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_kinetic<T>, dim3((unsigned)std::min<int64_t>(1024, grid_1d(n, kBlock))), dim3(kBlock), 0, s,
+                       p, n, wmc2, out);
+}
+
 void launch_cnt_finish(hipStream_t s, PushCounters* slots, PushCounters* out) {
     hipLaunchKernelGGL(k_cnt_finish, dim3(1), dim3(kCntSlots), 0, s, slots, out);
 }
@@ -761,7 +844,8 @@ void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, dou
                                    const int32_t*, const double*, const double*, const int32_t*, PushCounters*); \
     template void launch_sort<T>(hipStream_t, PArrays<T>, PArrays<T>, int64_t, int64_t, int32_t*, int32_t*,      \
                                  int32_t*, int32_t*);                                                            \
-    template void launch_rho<T>(hipStream_t, PArrays<T>, int64_t, const int32_t*, double, double*);
+    template void launch_rho<T>(hipStream_t, PArrays<T>, int64_t, const int32_t*, double, double*);               \
+    template void launch_kinetic<T>(hipStream_t, PArrays<T>, int64_t, double, double*);
 
 FEPIC_INSTANTIATE(float)
 FEPIC_INSTANTIATE(double)

@@ -15,6 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfepic.so")
 
+ABI_VERSION = 2   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
 FEPIC_OK = 0
 FEPIC_FP32_PUSH_FP64_ACC, FEPIC_ALL_FP64 = 0, 1
 FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP = 0, 1, 2, 3
@@ -42,7 +43,8 @@ class fepic_step_stats(ctypes.Structure):
                 ("n_crossings", ctypes.c_int64), ("max_crossings", ctypes.c_int), ("n_cap_exceeded", ctypes.c_int),
                 ("ms_sort", ctypes.c_float), ("ms_stage", ctypes.c_float), ("ms_particles", ctypes.c_float),
                 ("ms_rhs", ctypes.c_float), ("ms_warm", ctypes.c_float), ("ms_cg", ctypes.c_float),
-                ("ms_faraday", ctypes.c_float), ("ms_diag", ctypes.c_float)]
+                ("ms_faraday", ctypes.c_float), ("ms_diag", ctypes.c_float),
+                ("magnetic_energy", ctypes.c_double), ("kinetic_energy", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -126,6 +128,9 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = _RESTYPES.get(name, ctypes.c_int)
+        if L.fepic_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"libfepic.so has ABI version {L.fepic_abi_version()}, this binding expects "
+                               f"{ABI_VERSION}; rebuild with `python -m paper_2102_06248_amd.build`")
         _lib = L
     return _lib
 

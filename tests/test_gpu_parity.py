@@ -174,6 +174,16 @@ def test_beam_steps_fields_and_conservation(F, precision):
         e, ep, b = F.fepic_get_fields(L.ctx)
         dg, G = F.fepic_get_current(L.ctx)
         gp = F.fepic_get_particles(L.ctx, sp)
+    # energies of the last step's diagnostics against the oracle's state (quadratic in the
+    # fields, which agree to 1e-6)
+    from oracle import diagnostics as odiag, fem
+    o = osim.particles(s)
+    w_e = 0.5 * float(osim.e @ (osim.M @ osim.e))
+    w_b = odiag.magnetic_energy(fem.face_mass_matrix(osim.mesh), osim.b)
+    w_k = odiag.kinetic_energy(o["u"], 5e4, M_E, C_LIGHT)
+    assert st.field_energy == pytest.approx(w_e, rel=5e-6)
+    assert st.magnetic_energy == pytest.approx(w_b, rel=5e-6, abs=1e-12 * w_e)
+    assert st.kinetic_energy == pytest.approx(w_k, rel=5e-6)
     assert np.linalg.norm(e - osim.e) <= 1e-6 * np.linalg.norm(osim.e)
     assert np.linalg.norm(b - osim.b) <= 1e-6 * np.linalg.norm(osim.b) + 1e-30
     assert np.linalg.norm(G - osim.G) <= 1e-6 * np.linalg.norm(osim.G)

@@ -168,6 +168,28 @@ def test_mass_uniform_field_energy(kuhn2_jittered):
     assert np.isclose(e @ (M @ e), EPS0 * (E0 @ E0) * m.vol.sum(), rtol=1e-13)
 
 
+def test_magnetic_energy_of_uniform_field(kuhn2_jittered):
+    """Face fluxes of a uniform B0 carry the energy |B0|^2 Vol / (2 mu0)."""
+    from oracle import diagnostics
+    m = Mesh(*kuhn2_jittered)
+    B0 = np.array([-0.7, 0.25, 1.3])
+    b = m.face_dofs_of_uniform_field(B0)
+    W = diagnostics.magnetic_energy(fem.face_mass_matrix(m), b)
+    assert np.isclose(W, (B0 @ B0) * m.vol.sum() / (2 * MU0), rtol=1e-13)
+
+
+def test_kinetic_energy_closed_forms():
+    from oracle import diagnostics
+    from oracle.constants import C_LIGHT, M_E
+    # gamma v for v = 0.6 c: gamma = 1.25, kinetic energy 0.25 m c^2 per unit weight
+    u = np.array([[0.0, 0.75 * C_LIGHT, 0.0]])
+    assert np.isclose(diagnostics.kinetic_energy(u, 3.0, M_E, C_LIGHT), 3.0 * 0.25 * M_E * C_LIGHT ** 2, rtol=1e-14)
+    # slow particles: 1/2 m v^2 to O(v^2/c^2)
+    v = np.array([[1e3, -2e3, 5e2], [0.0, 0.0, 0.0]])
+    ke = diagnostics.kinetic_energy(v, 2.0, M_E, C_LIGHT)
+    assert np.isclose(ke, 2.0 * 0.5 * M_E * np.sum(v ** 2), rtol=1e-10)
+
+
 def test_mass_on_gradients_is_p1_stiffness(kuhn2_jittered):
     m = Mesh(*kuhn2_jittered)
     M, D = fem.mass_matrix(m), m.D()
