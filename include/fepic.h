@@ -110,6 +110,14 @@ const char* fepic_last_error(const fepic_ctx* ctx);
 /* Creates a context on opts->device (NULL opts = defaults).  *out receives it. */
 int fepic_create(const fepic_options* opts, fepic_ctx** out);
 int fepic_destroy(fepic_ctx* ctx);
+/* Device memory of the context from the caller's allocator instead of hipMalloc/hipFree
+ * (e.g. a framework's caching allocator): alloc(bytes, user) returns device memory of the
+ * context's device or NULL (then the calling entry point fails with FEPIC_E_OOM);
+ * free_(ptr, user) takes back a pointer alloc returned, after the context's stream has
+ * drained.  Both NULL restores hipMalloc.  Only before fepic_upload_mesh
+ * (FEPIC_E_STATE after).  The functions and user must outlive the context. */
+int fepic_set_allocator(fepic_ctx* ctx, void* (*alloc)(size_t bytes, void* user), void (*free_)(void* ptr, void* user),
+                        void* user);
 /* Runs all later device work of this context on the given hipStream_t (NULL = the
  * context's own stream).  The caller keeps the stream alive while the context uses it. */
 int fepic_set_stream(fepic_ctx* ctx, void* hip_stream);
@@ -155,6 +163,11 @@ int fepic_add_species(fepic_ctx* ctx, double q, double m, double w, int* species
  * values are dropped and counted in *n_rejected (may be NULL). */
 int fepic_upload_particles(fepic_ctx* ctx, int species, int64_t n, const int64_t* id, const double* x,
                            const double* u, int64_t* n_rejected);
+/* The same with x, u ([n][3] FP64) and id ([n] int64, or NULL) in device memory of the
+ * context's device (e.g. torch tensors), read on the context's stream; synchronous like
+ * fepic_upload_particles (the arrays may be freed when it returns). */
+int fepic_upload_particles_device(fepic_ctx* ctx, int species, int64_t n, const int64_t* id, const double* x,
+                                  const double* u, int64_t* n_rejected);
 /* Injection during a run (e.g. a beam source): appends n particles like
  * fepic_upload_particles but without re-sorting or waiting for the device; the next
  * step's sort orders them, and points outside the mesh are dropped there (not counted).

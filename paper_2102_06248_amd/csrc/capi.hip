@@ -30,16 +30,32 @@ int fail(fepic_ctx* c, int code, const std::string& msg) {
 void* dmalloc(fepic_ctx* c, size_t bytes) {
     if (bytes == 0) bytes = 8;
     void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    if (c->ualloc) {
+        p = c->ualloc(bytes, c->uarg);
+        if (!p) return nullptr;
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        return nullptr;
+    }
     c->allocs.push_back(p);
     return p;
+}
+
+// Returns one device allocation to whichever allocator made it.  A caller's allocator may
+// hand the memory to other work at once, so the context's stream is drained first.
+static void release(fepic_ctx* c, void* p) {
+    if (c->ufree) {
+        (void)hipStreamSynchronize(c->stream);
+        c->ufree(p, c->uarg);
+    } else {
+        (void)hipFree(p);
+    }
 }
 
 void dfree(fepic_ctx* c, void* p) {
     if (!p) return;
     auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
     if (it != c->allocs.end()) c->allocs.erase(it);
-    (void)hipFree(p);
+    release(c, p);
 }
 
 hipEvent_t* timer_pair(fepic_ctx* c, int fam, int64_t n_launches) {
@@ -758,7 +774,7 @@ int fepic_destroy(fepic_ctx* c) {
     if (!c->host_only) {
         (void)hipSetDevice(c->opt.device);
         (void)hipStreamSynchronize(c->stream);
-        for (void* p : c->allocs) (void)hipFree(p);
+        for (void* p : c->allocs) release(c, p);
         for (auto& s : c->species) {
             if (s.h_nlive) (void)hipHostFree(s.h_nlive);
         }
@@ -774,6 +790,18 @@ int fepic_destroy(fepic_ctx* c) {
     }
     mlp_destroy(c);
     delete c;
+    return FEPIC_OK;
+}
+
+int fepic_set_allocator(fepic_ctx* c, void* (*alloc)(size_t bytes, void* user), void (*free_)(void* ptr, void* user),
+                        void* user) {
+    if (!c) return FEPIC_E_ARG;
+    if (c->host_only) return fail(c, FEPIC_E_NO_DEVICE, "host-only context");
+    if (c->have_mesh || !c->allocs.empty()) return fail(c, FEPIC_E_STATE, "set the allocator before the mesh upload");
+    if ((alloc == nullptr) != (free_ == nullptr)) return fail(c, FEPIC_E_ARG, "give both functions or neither");
+    c->ualloc = alloc;
+    c->ufree = free_;
+    c->uarg = user;
     return FEPIC_OK;
 }
 
@@ -977,25 +1005,10 @@ int fepic_add_species(fepic_ctx* c, double q, double m, double w, int* out) {
     return FEPIC_OK;
 }
 
-int fepic_upload_particles(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
-                           const double* u, int64_t* n_rejected) {
-    NEED_DEV(c);
-    if (species < 0 || species >= (int)c->species.size() || n < 0 || (n > 0 && (!x || !u)))
-        return fail(c, FEPIC_E_ARG, "bad particle upload arguments");
-    if (n_rejected) *n_rejected = 0;
-    if (n == 0) return FEPIC_OK;
-    Species& s = c->species[species];
-    int rc = sync_counts(c);
-    if (rc) return rc;
-    if (s.n + n >= ((int64_t)1 << 31)) return fail(c, FEPIC_E_ARG, "too many particles for one species");
-    if ((rc = ensure_capacity(c, s, s.n + n))) return rc;
-    double* dx = dalloc<double>(c, 3 * n);
-    double* du = dalloc<double>(c, 3 * n);
-    int64_t* did = id ? dalloc<int64_t>(c, n) : nullptr;
-    if (!dx || !du || (id && !did)) return fail(c, FEPIC_E_OOM, "device allocation failed");
-    HIPCHK(c, hipMemcpyAsync(dx, x, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(du, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
-    if (id) HIPCHK(c, hipMemcpyAsync(did, id, sizeof(int64_t) * n, hipMemcpyHostToDevice, c->stream));
+// Locates n particles read from device memory, appends them to species s, sorts the
+// species and reads back the rejected count (synchronizes the stream).
+static int upload_located(fepic_ctx* c, Species& s, int64_t n, const int64_t* did, const double* dx,
+                          const double* du, int64_t* n_rejected) {
     HIPCHK(c, hipMemsetAsync(c->d_cnt, 0, sizeof(PushCounters), c->stream));
     const double* g = c->d_grid;
     if (c->opt.precision == FEPIC_ALL_FP64)
@@ -1009,16 +1022,61 @@ int fepic_upload_particles(fepic_ctx* c, int species, int64_t n, const int64_t* 
     if (c->opt.precision == FEPIC_ALL_FP64) sort_species<double>(c, s);
     else sort_species<float>(c, s);
     HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(PushCounters), hipMemcpyDeviceToHost, c->stream));
-    if ((rc = sync_counts(c))) return rc;
+    int rc = sync_counts(c);
+    if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipGetLastError());
-    dfree(c, dx);
-    dfree(c, du);
-    dfree(c, did);
     if (n_rejected) *n_rejected = c->h_cnt->n_rejected;
     c->rho_valid = false;
     c->rG_levels = 0;
     return FEPIC_OK;
+}
+
+static int check_upload(fepic_ctx* c, int species, int64_t n, const double* x, const double* u) {
+    if (species < 0 || species >= (int)c->species.size() || n < 0 || (n > 0 && (!x || !u)))
+        return fail(c, FEPIC_E_ARG, "bad particle upload arguments");
+    if (n == 0) return FEPIC_OK;
+    Species& s = c->species[species];
+    int rc = sync_counts(c);
+    if (rc) return rc;
+    if (s.n + n >= ((int64_t)1 << 31)) return fail(c, FEPIC_E_ARG, "too many particles for one species");
+    return ensure_capacity(c, s, s.n + n);
+}
+
+int fepic_upload_particles(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
+                           const double* u, int64_t* n_rejected) {
+    NEED_DEV(c);
+    if (n_rejected) *n_rejected = 0;
+    int rc = check_upload(c, species, n, x, u);
+    if (rc || n == 0) return rc;
+    Species& s = c->species[species];
+    double* dx = dalloc<double>(c, 3 * n);
+    double* du = dalloc<double>(c, 3 * n);
+    int64_t* did = id ? dalloc<int64_t>(c, n) : nullptr;
+    if (!dx || !du || (id && !did)) {
+        dfree(c, dx);
+        dfree(c, du);
+        dfree(c, did);
+        return fail(c, FEPIC_E_OOM, "device allocation failed");
+    }
+    hipError_t e = hipMemcpyAsync(dx, x, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(du, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && id) e = hipMemcpyAsync(did, id, sizeof(int64_t) * n, hipMemcpyHostToDevice, c->stream);
+    rc = (e == hipSuccess) ? upload_located(c, s, n, did, dx, du, n_rejected) : hip_fail(c, e, "particle upload copy");
+    (void)hipStreamSynchronize(c->stream);
+    dfree(c, dx);
+    dfree(c, du);
+    dfree(c, did);
+    return rc;
+}
+
+int fepic_upload_particles_device(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
+                                  const double* u, int64_t* n_rejected) {
+    NEED_DEV(c);
+    if (n_rejected) *n_rejected = 0;
+    int rc = check_upload(c, species, n, x, u);
+    if (rc || n == 0) return rc;
+    return upload_located(c, c->species[species], n, id, x, u, n_rejected);
 }
 
 static int inject_located(fepic_ctx* c, Species& s, int64_t n, const int64_t* did, const double* dx,

@@ -47,6 +47,10 @@ struct fepic_ctx {
     bool host_only = false;
     hipStream_t stream = nullptr, own_stream = nullptr;
     std::vector<void*> allocs;
+    // caller's device allocator (fepic_set_allocator), or hipMalloc/hipFree when null
+    void* (*ualloc)(size_t, void*) = nullptr;
+    void (*ufree)(void*, void*) = nullptr;
+    void* uarg = nullptr;
 
     fepic::HostMesh mesh;
     bool have_mesh = false;

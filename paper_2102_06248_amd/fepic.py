@@ -79,6 +79,7 @@ _SIGS = {
     "fepic_create": [ctypes.POINTER(fepic_options), ctypes.POINTER(_P)],
     "fepic_destroy": [_P],
     "fepic_set_stream": [_P, _P],
+    "fepic_set_allocator": [_P, _P, _P, _P],
     "fepic_upload_mesh": [_P, _I64, _P, _I64, _P],
     "fepic_get_topology_sizes": [_P, _PI64, _PI64, _PI64, _PI64, _PI64],
     "fepic_get_topology": [_P, _P, _P, _P, _P, _P, _P],
@@ -90,6 +91,7 @@ _SIGS = {
     "fepic_upload_particles": [_P, _INT, _I64, _P, _P, _P, _PI64],
     "fepic_inject_particles": [_P, _INT, _I64, _P, _P, _P],
     "fepic_inject_particles_device": [_P, _INT, _I64, _P, _P, _P],
+    "fepic_upload_particles_device": [_P, _INT, _I64, _P, _P, _P, _PI64],
     "fepic_num_particles": [_P, _INT, _PI64],
     "fepic_get_particles": [_P, _INT, _I64, _PI64, _P, _P, _P, _P, _P],
     "fepic_step": [_P, _D, _D, _D, ctypes.POINTER(fepic_step_stats)],
@@ -195,6 +197,43 @@ def fepic_set_stream(ctx, stream_handle):
     _check(ctx, lib().fepic_set_stream(ctx, ctypes.c_void_p(stream_handle)))
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def fepic_set_allocator(ctx, alloc_fn, free_fn):
+    """alloc_fn(nbytes) -> device address (int) or None; free_fn(address).  Returns the
+    ctypes callbacks, which the caller must keep alive as long as the context."""
+    def _a(n, user):
+        p = alloc_fn(n)
+        return p if p else None
+
+    def _f(p, user):
+        free_fn(p)
+
+    cbs = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(ctx, lib().fepic_set_allocator(ctx, ctypes.cast(cbs[0], ctypes.c_void_p),
+                                          ctypes.cast(cbs[1], ctypes.c_void_p), None))
+    return cbs
+
+
+def torch_allocator(device=0):
+    """(alloc_fn, free_fn) routing the library's device memory through torch's caching
+    allocator on the given device."""
+    import torch
+
+    def alloc_fn(n):
+        try:
+            return torch.cuda.caching_allocator_alloc(n, device)
+        except RuntimeError:
+            return None
+
+    def free_fn(p):
+        torch.cuda.caching_allocator_delete(p)
+
+    return alloc_fn, free_fn
+
+
 def fepic_upload_mesh(ctx, xyz, tets):
     xyz = _arr(xyz, np.float64, (-1, 3))
     tets = _arr(tets, np.int32, (-1, 4))
@@ -265,6 +304,13 @@ def fepic_inject_particles(ctx, species, x, u, ids=None):
     u = _arr(u, np.float64, (-1, 3))
     ids = None if ids is None else _arr(ids, np.int64)
     _check(ctx, lib().fepic_inject_particles(ctx, species, len(x), _ptr(ids), _ptr(x), _ptr(u)))
+
+
+def fepic_upload_particles_device(ctx, species, n, x_ptr, u_ptr, id_ptr=None):
+    """Device addresses as for fepic_inject_particles_device; returns the rejected count."""
+    rej = ctypes.c_int64()
+    _check(ctx, lib().fepic_upload_particles_device(ctx, species, n, id_ptr, x_ptr, u_ptr, ctypes.byref(rej)))
+    return rej.value
 
 
 def fepic_inject_particles_device(ctx, species, n, x_ptr, u_ptr, id_ptr=None):
@@ -406,11 +452,17 @@ def fepic_load(ctx, path):
 class Simulation:
     """Owns one context; thin sugar over the functions above."""
 
-    def __init__(self, xyz, tets, **opts):
+    def __init__(self, xyz, tets, allocator=None, **opts):
+        """allocator: None (hipMalloc) or "torch" (torch's caching allocator)."""
         self.ctx = fepic_create(**opts)
         self.n_nodes = len(xyz)
         self.n_tets = len(tets)
+        self._alloc_cbs = None
         try:
+            if allocator == "torch":
+                self._alloc_cbs = fepic_set_allocator(self.ctx, *torch_allocator(opts.get("device", 0)))
+            elif allocator is not None:
+                raise ValueError(f"unknown allocator {allocator!r}")
             fepic_upload_mesh(self.ctx, xyz, tets)
         except Exception:
             self.close()

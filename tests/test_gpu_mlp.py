@@ -150,16 +150,16 @@ def test_checkpoint_round_trip(F, tmp_path):
 
 
 def test_injection_matches_upload(F):
-    """Particles injected between steps (no sort, no host wait), from host arrays or from
-    device memory, give the same state as the same particles uploaded with the synchronous
-    path, and as the oracle."""
+    """Particles injected between steps (no sort, no host wait) from host arrays or device
+    memory, and particles uploaded from device memory, give the same state as the same
+    particles uploaded from host arrays, and as the oracle."""
     announce("injection vs upload")
     import torch
     from oracle.pic import OracleSim
     xyz, tets = inputs.prism_cylinder(0.05, 0.5, 6, 20)
     osim = OracleSim(xyz, tets)
     so = osim.add_species(-Q_E, M_E, 2e5)
-    sims = [F.Simulation(xyz, tets, device=0, precision=1) for _ in range(3)]
+    sims = [F.Simulation(xyz, tets, device=0, precision=1) for _ in range(4)]
     sps = [F.fepic_add_species(s.ctx, -Q_E, M_E, 2e5) for s in sims]
     nid = 0
     for k in range(4):
@@ -172,6 +172,8 @@ def test_injection_matches_upload(F):
         torch.cuda.synchronize()
         F.fepic_inject_particles_device(sims[2].ctx, sps[2], len(x), dev[0].data_ptr(), dev[1].data_ptr(),
                                         dev[2].data_ptr())
+        assert F.fepic_upload_particles_device(sims[3].ctx, sps[3], len(x), dev[0].data_ptr(), dev[1].data_ptr(),
+                                               dev[2].data_ptr()) == 0
         osim.upload_particles(so, x, u, ids=ids)
         for s in sims:
             F.fepic_step(s.ctx, 1e-10)
