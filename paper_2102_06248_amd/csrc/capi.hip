@@ -348,31 +348,16 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
                                c->d_partial, c->d_sc, c->opt.cg_tol);
             }
         }
-        // Iterations are launched in batches; between batches the host reads the device's
+        // Iterations are launched in batches; after each batch the host reads the device's
         // convergence flag and sizes the next batch from the recent contraction of ||r||
-        // (never more than doubling what has been launched).
+        // (never more than doubling what has been launched).  The first batch is most of
+        // the previous solve's count: counts vary little from step to step, and launches
+        // after convergence change nothing.
         int launched = 0, last_done = -1;
         double last_rr = 0.0;
         const int budget = maxit - total;
+        int todo = (restart == 0 && c->last_cg_iters > 0) ? std::max(batch, (int)(0.9 * c->last_cg_iters)) : batch;
         for (;;) {
-            HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            const CgScalars& h = *c->h_sc;
-            if (h.converged || launched > budget) break;
-            int todo = batch;
-            if (launched > 0) {
-                const int done = h.iters;
-                if (last_done >= 0 && done > last_done && h.rr > 0 && last_rr > h.rr && h.tol2_bb > 0) {
-                    const double rate = std::log(h.rr / last_rr) / (done - last_done);
-                    const double need = std::log(h.tol2_bb / h.rr) / rate;
-                    if (std::isfinite(need)) todo = (int)std::ceil(0.85 * need) - (launched - 1 - done);
-                } else {
-                    todo = launched;
-                }
-                todo = std::max(batch, std::min(todo, launched));
-                last_done = done;
-                last_rr = h.rr;
-            }
             // the launch after the budget only checks (and is discarded on failure)
             todo = std::min(todo, budget + 1 - launched);
             hipEvent_t* ev = timer_pair(c, FAM_CG_ITER, todo);
@@ -382,6 +367,24 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
                                c->d_partial, c->d_sc);
             if (ev) (void)hipEventRecord(ev[1], c->stream);
             launched += todo;
+            HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            const CgScalars& h = *c->h_sc;
+            if (h.converged || launched > budget) break;
+            const int done = h.iters;
+            if (last_done < 0 && done > 0 && h.rr0 > 0) {   // contraction since the start
+                last_done = 0;
+                last_rr = h.rr0;
+            }
+            todo = launched;
+            if (last_done >= 0 && done > last_done && h.rr > 0 && last_rr > h.rr && h.tol2_bb > 0) {
+                const double rate = std::log(h.rr / last_rr) / (done - last_done);
+                const double need = std::log(h.tol2_bb / h.rr) / rate;
+                if (std::isfinite(need)) todo = (int)std::ceil(0.85 * need) - (launched - 1 - done);
+            }
+            todo = std::max(batch, std::min(todo, launched));
+            last_done = done;
+            last_rr = h.rr;
         }
         if (restart == 0) rr0_first = c->h_sc->rr0;
         total += c->h_sc->iters;
@@ -399,6 +402,7 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
     c->h_sc->rr0 = rr0_first;
     // success only when the true residual meets the tolerance
     c->h_sc->converged = (c->h_sc->rr_true <= c->h_sc->tol2_bb) ? 1 : 0;
+    if (c->h_sc->converged) c->last_cg_iters = total;
     ev_mark(c, 7);
     {
         hipEvent_t* ev = timer_pair(c, FAM_FARADAY);

@@ -83,6 +83,7 @@ struct fepic_ctx {
     unsigned char* d_cq = nullptr;                 // crossing queue storage (CrossQueue arrays)
     int64_t cq_cap = 0;                            // its capacity in slots (multiple of 256)
     double cross_share = 1.0;                      // face crossings per particle, last step
+    int last_cg_iters = 0;                         // iterations of the last successful solve
     fepic::PushCounters* h_cnt = nullptr;
     int deferred_err = 0;
     // injection staging: pinned host buffer and its device mirror (x, u, id)
