@@ -264,15 +264,23 @@ def main():
     mean_particles = psteps / args.steps
     wst = {"particles": mean_particles, "occupied_tets": occ, "crossings": cross / args.steps}
     per_launch_bytes = algorithmic_bytes(dominant, geo, wst)
+    work_share = 1.0
     if dominant == "push":
         per_launch_bytes = algorithmic_bytes(dominant, geo, wst) / len(species)
+    if dominant == "cg_iter":
+        # launches that find the solve converged move nothing: average the algorithmic
+        # bytes over all launches (iterations / launches of a full iteration's bytes)
+        work_share = min(1.0, sum(cg_iters) / nl)
     avg_s = ms_tot / nl / 1e3
-    achieved = per_launch_bytes / avg_s / 1e9
+    achieved = per_launch_bytes * work_share / avg_s / 1e9
     traffic = traffic_from_profile(dominant, wl["name"], per_launch_bytes)
+    if traffic is not None:
+        traffic = int(traffic * work_share)   # counters are per working launch (median)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": KERNEL_NAMES[dominant], "avg_launch_us": round(avg_s * 1e6, 3), "launches": nl,
-                "algorithmic_bytes_per_launch": int(per_launch_bytes)}
+                "working_launch_share": round(work_share, 4),
+                "algorithmic_bytes_per_launch": int(per_launch_bytes * work_share)}
     # the particle kernel's own rate and roofline, for reference
     pms, pn = fam_time["push"]
     push_bytes = algorithmic_bytes("push", geo, wst)
