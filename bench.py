@@ -284,9 +284,15 @@ def main():
     # the particle kernel's own rate and roofline, for reference
     pms, pn = fam_time["push"]
     push_bytes = algorithmic_bytes("push", geo, wst)
-    push_info = {"particle_steps_per_s": mean_particles * args.steps / (pms / 1e3) if pms > 0 else None,
+    sms, tms = fam_time["stage"][0], fam_time["sort"][0]
+    psteps_all = mean_particles * args.steps
+    push_info = {"particle_steps_per_s": psteps_all / (pms / 1e3) if pms > 0 else None,
+                 "with_staging": psteps_all / ((pms + sms) / 1e3) if pms > 0 else None,
+                 "with_staging_and_sort": psteps_all / ((pms + sms + tms) / 1e3) if pms > 0 else None,
                  "avg_launch_us": round(pms / max(pn, 1) * 1e3, 3),
-                 "achieved_GBs": round(push_bytes * args.steps / (pms / 1e3) / 1e9, 1) if pms > 0 else None}
+                 "achieved_GBs": round(push_bytes * args.steps / (pms / 1e3) / 1e9, 1) if pms > 0 else None,
+                 "frac_of_hbm_peak": round(push_bytes * args.steps / (pms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                 if pms > 0 else None}
     breakdown = {f: {"ms_per_step": round(fam_time[f][0] / args.steps, 4), "launches_per_step": fam_time[f][1] / args.steps}
                  for f in FAMILIES}
     if args.copy_calibration:
