@@ -352,19 +352,41 @@ __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, 
 // goes to global memory directly.
 constexpr int kProbe = 16;
 
+// The six edge currents of one piece: the first probe of all six keys is issued at once
+// (independent compare-and-swaps), so one LDS round trip serves the common case; keys
+// whose first slot holds another edge continue with lds_add's probing.
 template <int kBits>
-__device__ __forceinline__ void lds_add(int* s_key, double* s_val, double* __restrict__ dg, int e, double v) {
-    if (v == 0.0) return;
-    unsigned int h = ((unsigned int)e * 2654435761u) >> (32 - kBits);
-    for (int p = 0; p < kProbe; ++p) {
-        const int k = atomicCAS(s_key + h, -1, e);
-        if (k == -1 || k == e) {
-            __hip_atomic_fetch_add(s_val + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            return;
-        }
-        h = (h + 1) & ((1u << kBits) - 1u);
+__device__ __forceinline__ void lds_add6(int* s_key, double* s_val, double* __restrict__ dg, const int32_t* e,
+                                         const double v[6]) {
+    int key[6], got[6];
+    unsigned int h[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        key[c] = e[c];
+        h[c] = ((unsigned int)key[c] * 2654435761u) >> (32 - kBits);
     }
-    atomic_add_f64(dg + e, v);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) got[c] = (v[c] != 0.0) ? atomicCAS(s_key + h[c], -1, key[c]) : key[c];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        if (v[c] == 0.0) continue;
+        if (got[c] == -1 || got[c] == key[c]) {
+            __hip_atomic_fetch_add(s_val + h[c], v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            // probe on from the next slot
+            unsigned int hh = (h[c] + 1) & ((1u << kBits) - 1u);
+            bool placed = false;
+            for (int p = 1; p < kProbe && !placed; ++p) {
+                const int k = atomicCAS(s_key + hh, -1, key[c]);
+                if (k == -1 || k == key[c]) {
+                    __hip_atomic_fetch_add(s_val + hh, v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    placed = true;
+                }
+                hh = (hh + 1) & ((1u << kBits) - 1u);
+            }
+            if (!placed) atomic_add_f64(dg + key[c], v[c]);
+        }
+    }
 }
 
 constexpr int log2_const(int v) { return v <= 1 ? 0 : 1 + log2_const(v / 2); }
@@ -411,8 +433,7 @@ __global__ __launch_bounds__(kB) void k_cross(PArrays<T> out, CrossQueue<T> cq, 
                 T rr[3];
                 end_point(ls, dl, rr, le);
                 piece_current(pp.qw, ls, le, cur);
-#pragma unroll
-                for (int c = 0; c < 6; ++c) lds_add<kBits>(s_key, s_val, dg, bp->edge[c], cur[c]);
+                lds_add6<kBits>(s_key, s_val, dg, bp->edge, cur);
                 out.tet[i] = t;
                 out.l1[i] = rr[0];
                 out.l2[i] = rr[1];
@@ -422,8 +443,7 @@ __global__ __launch_bounds__(kB) void k_cross(PArrays<T> out, CrossQueue<T> cq, 
 #pragma unroll
             for (int k = 0; k < 4; ++k) le[k] = (k == kb) ? 0.0 : ls[k] + best * dl[k];
             piece_current(pp.qw, ls, le, cur);
-#pragma unroll
-            for (int c = 0; c < 6; ++c) lds_add<kBits>(s_key, s_val, dg, bp->edge[c], cur[c]);
+            lds_add6<kBits>(s_key, s_val, dg, bp->edge, cur);
             const int nb = bp->nbr[kb];
             if (nb < 0) {
                 ++na;
