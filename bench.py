@@ -78,11 +78,11 @@ def traffic_from_profile(fam, workload, launches_bytes_per):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, n_sample=None):
+def cpu_baseline(wl, n_sample=None, n_steps=12):
     """The oracle, single-threaded, on the same workload from its own electrostatic start.
-    Beam: one full step over all particles (particle push + Newmark solve).  Plasma balls
-    (whose field solve takes thousands of iterations on the full mesh): the particle push
-    of a seeded sample of particles only."""
+    Beam: n_steps full steps over all particles (particle push + Newmark solve; about 10 s
+    of CPU work).  Plasma balls (whose field solve takes thousands of iterations on the full
+    mesh): the particle push of a seeded sample of particles only."""
     from threadpoolctl import threadpool_limits
 
     from oracle.pic import OracleSim
@@ -101,26 +101,27 @@ def cpu_baseline(wl, n_sample=None):
         if wl.get("B0") is not None:
             osim.set_uniform_B(wl["B0"])
         osim.init_electrostatic(tol=1e-12)
-        t0 = time.perf_counter()
-        dG, _ = osim.push_particles(wl["dt"])
-        t_push = time.perf_counter() - t0
         if plasma:
+            t0 = time.perf_counter()
+            osim.push_particles(wl["dt"])
+            t_push = time.perf_counter() - t0
             return {"value": n_total / t_push, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
                     "sample": (f"particle push of the first {n_total} particles of the workload's seeded draw "
                                f"({t_push:.2f} s), field solve not timed; single thread"),
                     "push_particle_steps_per_s": n_total / t_push}
-        ie = osim.ie
-        A, B1, B2 = osim.operators(wl["dt"], wl["beta"], wl["gamma"])
-        rhs = B1 @ osim.e[ie] + B2 @ osim.e_prev[ie] - (dG - osim.dG)[ie]
-        from oracle.newmark import pcg_jacobi
-        t0 = time.perf_counter()
-        _, iters, _ = pcg_jacobi(A, rhs, osim.e[ie], 1e-10, 10000)
-        t_solve = time.perf_counter() - t0
-    return {"value": n_total / (t_push + t_solve), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one full step of the same workload ({n_total} particles) from the oracle's own "
-                       f"electrostatic start: push {t_push:.2f} s + Newmark Jacobi-PCG {iters} iters "
-                       f"{t_solve:.2f} s; single thread"),
-            "push_particle_steps_per_s": n_total / t_push, "newmark_ms": 1e3 * t_solve, "cg_iters": iters}
+        t_all, iters, psteps = 0.0, [], 0
+        for _ in range(n_steps):
+            n_live = sum(int(sp_.alive.sum()) for sp_ in osim.species)
+            t0 = time.perf_counter()
+            st = osim.step(wl["dt"], wl["beta"], wl["gamma"])
+            t_all += time.perf_counter() - t0
+            iters.append(st["cg_iters"])
+            psteps += n_live
+    return {"value": psteps / t_all, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{n_steps} full steps of the same workload ({n_total} particles, no injection) from the "
+                       f"oracle's own electrostatic start: {t_all:.1f} s, Newmark Jacobi-PCG "
+                       f"{np.mean(iters):.0f} iterations per step; single thread"),
+            "newmark_cg_iters_mean": float(np.mean(iters)), "seconds": round(t_all, 2)}
 
 
 def main():
