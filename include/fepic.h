@@ -15,9 +15,11 @@
  *   - Return value: FEPIC_OK (0) or a negative FEPIC_E_* code.  fepic_error_string(code)
  *     names the code; fepic_last_error(ctx) gives the message of the last failure.
  *   - Ownership: the caller owns every buffer it passes; the library copies what it needs
- *     during the call and keeps no caller pointer.  The context owns all device memory it
- *     allocates (hipMalloc) and frees it in fepic_destroy.  Pointer arguments are host
- *     pointers unless the name says device.
+ *     during the call and keeps no caller pointer (fepic_inject_particles_device reads its
+ *     device arrays in stream order, see there).  The context owns all device memory it
+ *     allocates (hipMalloc, or the caller's allocator from fepic_set_allocator) and frees it
+ *     in fepic_destroy.  Pointer arguments are host pointers unless the function's name
+ *     says device.
  *   - Threading: one context per host thread; calls on one context must not overlap.
  *   - Units: SI.  Edge unknowns e_i are volts (line integrals of E), face unknowns b_f are
  *     webers (fluxes of B), currents are time-integrated (coulombs).

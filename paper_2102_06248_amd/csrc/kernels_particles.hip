@@ -1,6 +1,7 @@
-// Particle-side kernels for gfx950: per-tet field staging, the fused particle step
-// (gather -> relativistic Boris -> straight-path tracking -> Whitney-1 deposit), point
-// location, counting sort by tet, nodal charge.
+// Particle-side kernels for gfx950: per-tet field staging, the particle step (gather ->
+// relativistic Boris -> straight-path tracking -> Whitney-1 deposit) as a first-piece
+// kernel for every particle plus a kernel for the compacted face-crossing paths, point
+// location, counting sort by tet, nodal charge, energies.
 //
 // Wave64 throughout; particles are kept sorted by tet so that lanes of a wave read the
 // same 128-byte tet record and the current of their first path piece can be summed
