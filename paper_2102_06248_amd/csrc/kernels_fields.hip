@@ -229,18 +229,41 @@ __global__ __launch_bounds__(kBlock) void k_warm(int mode, int64_t n, const doub
 // come from one sector.  The interleaved state is double buffered (neighbours read the
 // previous values); x is touched by its own row only.
 
-// ||b||^2 from the right-hand side's partials; R = D^-1 (b - A x); W = S = P = 0.
+// Iteration partials: the three dots of each iteration are added with FP64 atomics into
+// kCgSlots slots per value (workgroup b -> slot b mod kCgSlots), in three rotating
+// buffers: iteration i reads buffer i mod 3 (filled by the previous kernel), adds into
+// buffer (i + 1) mod 3 (cleared by the previous kernel) and clears buffer (i + 2) mod 3
+// (read by the previous kernel).  Reading 3 x 64 values instead of one partial per
+// workgroup lets the iteration kernel run one workgroup per row block at any size.
+constexpr int kCgSlots = 64;
+__device__ __forceinline__ double* cg_buf(double* base, int k) { return base + (size_t)(k % 3) * 3 * kCgSlots; }
+
+// Workgroup totals v (already summed over the block) added into buffer slots.
+__device__ __forceinline__ void cg_add(double* buf, const double v[3]) {
+    if (threadIdx.x == 0) {
+        const int s = blockIdx.x & (kCgSlots - 1);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) unsafeAtomicAdd(buf + j * kCgSlots + s, v[j]);
+    }
+}
+
+// ||b||^2 from the right-hand side's partials; R = D^-1 (b - A x); W = S = P = 0; clears
+// iteration buffers 0 and 1.
 __global__ __launch_bounds__(kBlock) void k_cg_init_a(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
                                                        const int32_t* __restrict__ col, const double* __restrict__ A,
                                                        const double* __restrict__ dinv, const double* __restrict__ b,
                                                        const double* __restrict__ x, CgVec* __restrict__ V,
-                                                       const double* __restrict__ part_rhs, CgScalars* sc, double tol) {
+                                                       const double* __restrict__ part_rhs, double* cg_slots,
+                                                       CgScalars* sc, double tol) {
     double bb[1];
     read_partials<1>(part_rhs, gridDim.x, bb);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->bb = bb[0];
-        sc->tol2_bb = tol * tol * bb[0];
-        sc->converged = 0;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            sc->bb = bb[0];
+            sc->tol2_bb = tol * tol * bb[0];
+            sc->converged = 0;
+        }
+        for (int k = threadIdx.x; k < 2 * 3 * kCgSlots; k += kBlock) cg_slots[k] = 0.0;
     }
     for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
         const int64_t row = lb * kBlock + threadIdx.x;
@@ -258,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_a(int64_t n_rows, RowGrid rg
 __global__ __launch_bounds__(kBlock) void k_cg_init_b(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
                                                        const int32_t* __restrict__ col, const double* __restrict__ A,
                                                        const double* __restrict__ dinv, CgVec* __restrict__ V,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ cg_slots) {
     double v[3] = {0.0, 0.0, 0.0};
     for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
         const int64_t row = lb * kBlock + threadIdx.x;
@@ -272,7 +295,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_b(int64_t n_rows, RowGrid rg
             v[2] += rv * rv;
         }
     }
-    write_partials<3>(v, partial);
+    block_sum_all<3>(v);
+    cg_add(cg_buf(cg_slots, 0), v);
 }
 
 // The part of row j's product that does not depend on the iteration's scalars: the three
@@ -345,21 +369,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
                                                      const int32_t* __restrict__ col, const double* __restrict__ A,
                                                      const double* __restrict__ dinv, double* __restrict__ x,
                                                      const CgVec* __restrict__ V, CgVec* __restrict__ V_new,
-                                                     const double* __restrict__ part_in,
-                                                     double* __restrict__ part_out, CgScalars* sc) {
-    // The converged flag, the previous kernel's partials and this workgroup's first rows
+                                                     double* __restrict__ cg_slots, CgScalars* sc) {
+    // The converged flag, the previous kernel's dot slots and this workgroup's first rows
     // are all in flight together; the flag (the same for every thread) is checked before
     // any write, so a launch after convergence changes nothing.
     const int conv = sc->converged;
-    const int n_src = gridDim.x;
     double t[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < kMaxGrid / kBlock; ++q) {
-        const int b = threadIdx.x + q * kBlock;
-        if (b < n_src) {
-            t[0] += part_in[b];
-            t[1] += part_in[n_src + b];
-            t[2] += part_in[2 * n_src + b];
+    {
+        const double* in = cg_buf(cg_slots, i);
+        if (threadIdx.x < kCgSlots) {
+            t[0] = in[threadIdx.x];
+            t[1] = in[kCgSlots + threadIdx.x];
+            t[2] = in[2 * kCgSlots + threadIdx.x];
         }
     }
     int64_t lb = rg_first(rg);
@@ -385,6 +406,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
         if (bad) sc->converged = 2;
     }
     if (done || bad) return;
+    if (blockIdx.x == 0)   // read by the previous kernel; the next one adds into it
+        for (int k = threadIdx.x; k < 3 * kCgSlots; k += kBlock) cg_buf(cg_slots, i + 2)[k] = 0.0;
     const double ab = alpha * beta;
     double v[3] = {0.0, 0.0, 0.0};
     while (lb < le) {
@@ -408,7 +431,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
         active = lb < le && ((row >> 6) << 6) < n_rows;
         if (active) row_part(P, sp, col, A, V, x, dinv, row, row < n_rows);
     }
-    write_partials<3>(v, part_out);
+    block_sum_all<3>(v);
+    cg_add(cg_buf(cg_slots, i + 1), v);
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero_if_b_zero(double* x, int64_t n, const CgScalars* sc) {
@@ -551,7 +575,8 @@ __global__ __launch_bounds__(kBlock) void k_line_apply(int64_t n, const double* 
 
 // Partial-buffer slots (each holds up to 3 values per workgroup of the largest grid).
 constexpr size_t kSlot = 4 * kMaxGrid;
-enum { SLOT_RHS = 0, SLOT_INIT, SLOT_SPMV, SLOT_UPD, SLOT_RESID, SLOT_DOT, SLOT_COUNT };
+enum { SLOT_RHS = 0, SLOT_CG, SLOT_RESID, SLOT_DOT, SLOT_COUNT };
+static_assert(3 * 3 * kCgSlots <= kSlot, "iteration slots fit one partial region");
 
 }  // namespace
 
@@ -597,26 +622,35 @@ void launch_cg_init(hipStream_t s, int64_t n_rows, const int64_t* sp, const int3
                     double tol) {
     const RowGrid rg = row_grid(n_rows);
     hipLaunchKernelGGL(k_cg_init_a, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, dinv, b, x, v,
-                       partial + SLOT_RHS * kSlot, sc, tol);
+                       partial + SLOT_RHS * kSlot, partial + SLOT_CG * kSlot, sc, tol);
     hipLaunchKernelGGL(k_cg_init_b, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, dinv, v,
-                       partial + SLOT_INIT * kSlot);
+                       partial + SLOT_CG * kSlot);
+}
+
+// One workgroup per block of kBlock rows (the iteration's partials do not grow with the
+// grid), consecutive blocks on the same XCD.
+inline RowGrid row_grid_full(int64_t n_rows) {
+    RowGrid r;
+    r.nb = (n_rows + kBlock - 1) / kBlock;
+    r.per = (r.nb + 7) / 8;
+    r.g = (int)std::max<int64_t>(1, r.per);
+    r.grid = 8u * (unsigned)r.g;
+    return r;
 }
 
 // Iteration i reads the interleaved state from buffer i & 1 and writes buffer (i + 1) & 1.
 void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
                     const double* dinv, double* x, CgVec* const v[2], double* partial, CgScalars* sc) {
-    const RowGrid rg = row_grid(n_rows);
+    const RowGrid rg = row_grid_full(n_rows);
     const int a = i & 1, b = 1 - a;
-    const double* part_in = partial + (i == 0 ? SLOT_INIT : (a ? SLOT_UPD : SLOT_SPMV)) * kSlot;
-    double* part_out = partial + (b ? SLOT_UPD : SLOT_SPMV) * kSlot;
     hipLaunchKernelGGL(k_cg_iter, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, dinv, x, v[a], v[b],
-                       part_in, part_out, sc);
+                       partial + SLOT_CG * kSlot, sc);
 }
 
 void launch_cg_rr0(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc) {
-    const RowGrid rg = row_grid(n_rows);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partial + SLOT_INIT * kSlot + 2 * rg.grid,
-                       (int)rg.grid, &sc->rr0);
+    (void)n_rows;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partial + SLOT_CG * kSlot + 2 * kCgSlots, kCgSlots,
+                       &sc->rr0);
 }
 
 void launch_cg_resid(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
