@@ -16,6 +16,8 @@ states the method:
                   Alg. 1, eqs. (chargeDef)-(G))
 * ``newmark``     Newmark-beta 3-level update of the wave equation with the
                   time-integrated current as source, Jacobi-PCG, Faraday (Sec. II-B, III-A)
+* ``auxspace``    nodal auxiliary-space preconditioner for the Newmark system and PCG
+                  with it (the paper leaves the solver open; Hiptmair and Xu 2007)
 * ``diagnostics`` nodal charge, continuity and Gauss residuals (Sec. III-A)
 * ``pic``         one whole PIC step in the paper's cycle order (Sec. II-A)
 * ``mlp``         the per-edge warm-start network, forward/backward/Adam in float64

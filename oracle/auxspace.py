@@ -1,0 +1,106 @@
+"""Oracle: nodal auxiliary-space preconditioner for the Newmark system, and PCG with it.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The paper fixes the Newmark system (M + beta dt^2 S) e^{n+1} = ... (Sec. II-B, III-A) but
+not how it is solved.  Jacobi-PCG needs many iterations once dt is well beyond the
+explicit limit: the error components that converge slowly are the discrete gradients
+(the kernel of S, where only M acts) and the smooth curl fields.  The nodal auxiliary-space
+preconditioner of Hiptmair and Xu (SIAM J. Numer. Anal. 45 (2007) 2483-2509) adds a
+correction from two nodal spaces to the edge smoother; here every space gets one Jacobi
+step, in additive form:
+
+    B = diag(A)^-1 + G diag(G^T A G)^-1 G^T + Pi diag(Pi^T A Pi)^-1 Pi^T,
+
+with, on interior edges (rows) and interior nodes (columns; PEC walls hold the boundary
+unknowns at zero):
+
+* G  the discrete gradient: -1 at the tail and +1 at the head of each edge, i.e. the
+  incidence matrix D of the mesh restricted to those rows and columns (de Rham: S G = 0);
+* Pi the nodal interpolation of piecewise-linear vector fields into Whitney-1 unknowns.
+  For a linear field F the edge unknown is its line integral along the edge, which the
+  trapezoid rule gives exactly: (r_b - r_a) . (F(r_a) + F(r_b)) / 2, so the entry of Pi
+  for edge (a, b) and node n in {a, b}, component d, is (r_b - r_a)_d / 2.
+
+B is symmetric positive definite (a sum of an SPD matrix and two symmetric positive
+semi-definite ones), so PCG with it converges to the same solution as any other PCG; it
+only changes how many iterations that takes.  The stopping rule is the one of
+``newmark.pcg_jacobi``: ||r||_2 <= tol ||b||_2 on the updated residual.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def gradient_matrix(mesh, rows, cols):
+    """Discrete gradient G = D[rows][:, cols] (edges x nodes, -1 tail, +1 head)."""
+    return mesh.D().tocsr()[rows][:, cols].tocsr()
+
+
+def vector_interpolation_matrix(mesh, rows, nodes):
+    """Pi: values of a vector field at `nodes` (3 per node, x y z) -> line integrals of its
+    linear interpolant along the edges `rows` (trapezoid rule, exact for linear fields).
+    A node outside `nodes` contributes nothing (its field value is taken as zero)."""
+    rows = np.asarray(rows)
+    nodes = np.asarray(nodes)
+    where = -np.ones(mesh.n_nodes, dtype=np.int64)
+    where[nodes] = np.arange(len(nodes))
+    ends = mesh.edges[rows]
+    t = mesh.xyz[ends[:, 1]] - mesh.xyz[ends[:, 0]]
+    r_idx, c_idx, vals = [], [], []
+    for end in (0, 1):
+        k = where[ends[:, end]]
+        ok = k >= 0
+        for d in range(3):
+            r_idx.append(np.nonzero(ok)[0])
+            c_idx.append(3 * k[ok] + d)
+            vals.append(0.5 * t[ok, d])
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(r_idx), np.concatenate(c_idx))),
+                         shape=(len(rows), 3 * len(nodes)))
+
+
+def aux_space_preconditioner(A, mesh, edges=None, nodes=None):
+    """The additive preconditioner B as a function r -> B r on the unknowns `edges`
+    (default: interior edges, the rows of A) with nodal spaces on `nodes` (default:
+    interior nodes).  Returns (apply, G, Pi, dG, dPi) with the diagonals used."""
+    edges = mesh.interior_edges if edges is None else edges
+    nodes = mesh.interior_nodes if nodes is None else nodes
+    G = gradient_matrix(mesh, edges, nodes)
+    Pi = vector_interpolation_matrix(mesh, edges, nodes)
+    dA = A.diagonal()
+    dG = (G.T @ (A @ G)).diagonal()
+    dPi = (Pi.T @ (A @ Pi)).diagonal()
+
+    def apply(r):
+        return r / dA + G @ ((G.T @ r) / dG) + Pi @ ((Pi.T @ r) / dPi)
+
+    return apply, G, Pi, dG, dPi
+
+
+def pcg(A, b, x0, apply_B, tol=1e-10, maxit=10000):
+    """Preconditioned CG (Hestenes-Stiefel recurrences), stopping when the updated residual
+    satisfies ||r||_2 <= tol ||b||_2.  Returns (x, iterations, true relative residual)."""
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return np.zeros_like(b), 0, 0.0
+    x = np.array(x0, dtype=np.float64, copy=True)
+    r = b - A @ x
+    it = 0
+    if np.linalg.norm(r) > tol * bnorm:
+        z = apply_B(r)
+        p = z.copy()
+        rz = r @ z
+        while it < maxit:
+            q = A @ p
+            alpha = rz / (p @ q)
+            x += alpha * p
+            r -= alpha * q
+            it += 1
+            if np.linalg.norm(r) <= tol * bnorm:
+                break
+            z = apply_B(r)
+            rz_new = r @ z
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+    return x, it, np.linalg.norm(b - A @ x) / bnorm

@@ -1,0 +1,110 @@
+"""Pins for the oracle's nodal auxiliary-space preconditioner and its PCG.
+
+Each check compares against something other than the preconditioner's own formula: the
+de Rham identity S G = 0 of the Whitney complex, line integrals of linear fields by an
+independent two-point Gauss-Legendre quadrature, symmetry and positivity, and the direct
+sparse solve of the Newmark system.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import auxspace, fem, newmark
+from oracle.constants import C_LIGHT
+from oracle.mesh import Mesh
+from oracle.pic import OracleSim
+from paper_2102_06248_amd import inputs
+
+
+def _jittered_kuhn(n, seed, amp=0.15):
+    xyz, tets = inputs.kuhn_cube(n)
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    inner = np.all((xyz > 1e-12) & (xyz < 1 - 1e-12), axis=1)
+    xyz = xyz.copy()
+    xyz[inner] += amp * h * rng.uniform(-1, 1, size=(inner.sum(), 3))
+    return xyz, tets
+
+
+@pytest.fixture(scope="module")
+def mesh():
+    return Mesh(*_jittered_kuhn(5, 1))
+
+
+def test_gradients_are_in_the_kernel_of_curl_curl(mesh):
+    S = fem.curlcurl_matrix(mesh)
+    G = auxspace.gradient_matrix(mesh, np.arange(mesh.n_edges), np.arange(mesh.n_nodes))
+    assert abs(S @ G).max() <= 1e-12 * abs(S).max()
+    # a planted orientation error (one edge entered with the wrong sign at one node)
+    # breaks the identity
+    Gb = G.tolil()
+    e = G[:, 7].nonzero()[0][0]
+    Gb[e, 7] = -Gb[e, 7]
+    assert abs(S @ Gb.tocsr()).max() > 1e-3 * abs(S).max()
+
+
+def test_vector_interpolation_is_exact_on_linear_fields(mesh):
+    rng = np.random.default_rng(2)
+    c, L = rng.normal(size=3), rng.normal(size=(3, 3))
+    field = lambda x: c + x @ L.T
+    Pi = auxspace.vector_interpolation_matrix(mesh, np.arange(mesh.n_edges), np.arange(mesh.n_nodes))
+    got = Pi @ field(mesh.xyz).ravel()
+    # two-point Gauss-Legendre along each edge (exact for the linear integrand)
+    a, b = mesh.xyz[mesh.edges[:, 0]], mesh.xyz[mesh.edges[:, 1]]
+    t = b - a
+    g = 0.5 / np.sqrt(3.0)
+    want = 0.5 * np.sum(t * (field(a + (0.5 - g) * t) + field(a + (0.5 + g) * t)), axis=1)
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-13 * np.abs(want).max())
+    # uniform fields: the line integral the mesh module gives
+    u = rng.normal(size=3)
+    assert np.allclose(Pi @ np.tile(u, mesh.n_nodes), mesh.edge_dofs_of_uniform_field(u), rtol=1e-13, atol=1e-15)
+
+
+def test_restricted_interpolation_drops_wall_nodes(mesh):
+    ie, inode = mesh.interior_edges, mesh.interior_nodes
+    full = auxspace.vector_interpolation_matrix(mesh, ie, np.arange(mesh.n_nodes))
+    cols = np.stack([3 * inode, 3 * inode + 1, 3 * inode + 2], 1).ravel()
+    part = auxspace.vector_interpolation_matrix(mesh, ie, inode)
+    assert abs(part - full[:, cols]).max() == 0.0
+
+
+def _newmark_A(m, cfl_ratio):
+    sim = OracleSim(m.xyz, m.tets)
+    h = np.linalg.norm(m.xyz[m.edges[:, 1]] - m.xyz[m.edges[:, 0]], axis=1).min()
+    dt = cfl_ratio * h / C_LIGHT
+    A, _, _ = sim.operators(dt, 0.25, 0.5)
+    return A
+
+
+def test_preconditioner_is_symmetric_positive_definite(mesh):
+    A = _newmark_A(mesh, 10.0)
+    apply, G, Pi, dG, dPi = auxspace.aux_space_preconditioner(A, mesh)
+    assert np.all(dG > 0) and np.all(dPi > 0)
+    rng = np.random.default_rng(3)
+    x, y = rng.normal(size=(2, A.shape[0]))
+    bx, by = apply(x), apply(y)
+    assert abs(x @ by - y @ bx) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(by)
+    assert x @ bx > 0 and y @ by > 0
+    # G^T A G has no curl-curl part: its diagonal is that of G^T M G
+    M = newmark.restrict(fem.mass_matrix(mesh), mesh.interior_edges)
+    assert np.allclose(dG, (G.T @ (M @ G)).diagonal(), rtol=1e-9)
+
+
+@pytest.mark.parametrize("cfl_ratio", [5.0, 20.0])
+def test_pcg_matches_the_direct_solve_in_fewer_iterations(mesh, cfl_ratio):
+    A = _newmark_A(mesh, cfl_ratio)
+    rng = np.random.default_rng(4)
+    b = rng.normal(size=A.shape[0])
+    x_direct = spla.spsolve(A.tocsc(), b)
+    apply = auxspace.aux_space_preconditioner(A, mesh)[0]
+    x, it, res = auxspace.pcg(A, b, np.zeros_like(b), apply, tol=1e-10)
+    assert res <= 1e-10
+    assert np.linalg.norm(x - x_direct) <= 1e-8 * np.linalg.norm(x_direct)
+    _, it_j, _ = newmark.pcg_jacobi(A, b, np.zeros_like(b), 1e-10)
+    assert it < it_j
+    # the same PCG with the Jacobi part alone is the Jacobi PCG of the Newmark module (up
+    # to the rounding of r / d against d^-1 r, which moves late iterations a little)
+    dA = A.diagonal()
+    _, it_same, _ = auxspace.pcg(A, b, np.zeros_like(b), lambda r: r / dA, tol=1e-10)
+    assert abs(it_same - it_j) <= max(2, 0.02 * it_j)
+    print(f"cfl ratio {cfl_ratio}: aux-space PCG {it} iterations, Jacobi PCG {it_j}")
