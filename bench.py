@@ -32,7 +32,8 @@ METRIC = "particle-steps/s (gather+push+deposit) + Newmark step time at CG resid
 HBM_PEAK_GBS = 8000.0
 FAMILIES = ["push", "stage", "sort", "rhs", "cg_iter", "faraday"]
 KERNEL_NAMES = {"push": "k_push+k_cross", "stage": "k_stage", "sort": "k_hist/k_scan/k_scatter", "rhs": "k_rhs",
-                "cg_iter": "k_cg_iter", "faraday": "k_faraday"}
+                "cg_iter": "k_pcg_q+k_pcg_nodes+k_pcg_update", "faraday": "k_faraday"}
+JACOBI_ITER_KERNEL = "k_cg_iter"
 KERNEL_SOURCES = {"push": "kernels_particles.hip", "stage": "kernels_particles.hip", "sort": "kernels_particles.hip",
                   "rhs": "kernels_fields.hip", "cg_iter": "kernels_fields.hip", "faraday": "kernels_fields.hip"}
 
@@ -41,12 +42,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(fam, geo, st):
-    """Bytes the method must move per launch (each HBM word once), by kernel family."""
+def algorithmic_bytes(fam, geo, st, pc="aux"):
+    """Bytes the method must move per launch (each HBM word once), by kernel family.  A
+    "cg_iter" launch is one PCG iteration: one kernel with Jacobi, three with the nodal
+    auxiliary-space preconditioner."""
     n_rows, nnz, ne, nf, nt = geo["n_rows"], geo["nnz"], geo["n_edges"], geo["n_faces"], geo["n_tets"]
     npart, occ, cross = st["particles"], st["occupied_tets"], st["crossings"]
-    if fam == "cg_iter":      # A values + columns once; per row R, W, S, P and x read and written
-        return 12 * nnz + 80 * n_rows
+    if fam == "cg_iter" and pc == "jacobi":   # A values + columns once; per row R, W, S, P and x read
+        return 12 * nnz + 80 * n_rows          # and written
+    if fam == "cg_iter":
+        # q = A p: A values + columns, (z, p) read, p and q written: 12 nnz + 32 per row;
+        # nodes: one 4 B incidence per interior edge end, (r, q) and the half edge vector
+        # per row (32), scale read and Y written per node (64);
+        # update: r, q, z, p, x, 1/A_jj, edge vector, ends read (72) and r, z, p, x written
+        # (32) per row, Y read per node (32)
+        return 12 * nnz + (32 + 32 + 104) * n_rows + 8 * geo["n_int_edges"] + 96 * geo["n_aux"]
     if fam == "rhs":          # M, S values + columns; e, e_prev, dG_new, dG_old read; b written
         return 20 * nnz + 40 * n_rows
     if fam == "push":         # particle state read + written (tet, 3 lambda, 3 u at 4 B);
@@ -66,10 +76,15 @@ def source_hash(fam):
     return hashlib.sha1(open(p, "rb").read()).hexdigest()[:12]
 
 
-def traffic_from_profile(fam, workload, launches_bytes_per):
+def profile_key(fam, pc):
+    """Name stem of a family's counter summary under profiles/."""
+    return "cg_iter_jacobi" if (fam == "cg_iter" and pc == "jacobi") else fam
+
+
+def traffic_from_profile(fam, workload, launches_bytes_per, pc="aux"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
     on the current kernel source; None otherwise."""
-    p = os.path.join(ROOT, "profiles", f"{fam}_{workload}_counters.json")
+    p = os.path.join(ROOT, "profiles", f"{profile_key(fam, pc)}_{workload}_counters.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -139,6 +154,8 @@ def main():
     ap.add_argument("--diagnostics", action="store_true",
                     help="run the conservation diagnostics every step (continuity, Gauss drift)")
     ap.add_argument("--sort-period", type=int, default=1)
+    ap.add_argument("--preconditioner", default="aux", choices=["aux", "jacobi"],
+                    help="Newmark PCG preconditioner: nodal auxiliary space (default) or Jacobi")
     ap.add_argument("--inject", type=int, default=1, help="inject the beam's per-step batch (c2)")
     ap.add_argument("--inject-from", default="device", choices=["device", "host"],
                     help="device: batches staged in HBM before the timed region; host: copied per step")
@@ -169,8 +186,10 @@ def main():
     ws = {"prev": F.FEPIC_WS_PREV, "extrap1": F.FEPIC_WS_EXTRAP1, "extrap2": F.FEPIC_WS_EXTRAP2,
           "mlp": F.FEPIC_WS_PREV}[args.warm_start]
     precision = {"auto": wl["precision"], "fp32": 0, "fp64": 1}[args.precision]
+    pc = args.preconditioner
     sim = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=precision, warm_start=ws,
-                       sort_period=args.sort_period, timing=1, diagnostics=1 if args.diagnostics else 0)
+                       sort_period=args.sort_period, timing=1, diagnostics=1 if args.diagnostics else 0,
+                       preconditioner=F.FEPIC_PC_AUX if pc == "aux" else F.FEPIC_PC_JACOBI)
     ctx = sim.ctx
     species = []
     for sp in wl["species"]:
@@ -228,7 +247,8 @@ def main():
     sizes = F.fepic_get_topology_sizes(ctx)
     r, c, v = F.fepic_get_matrix(ctx, 0)
     geo = {"n_rows": sizes["n_edges"], "nnz": len(v) + (sizes["n_edges"] - sizes["n_int_edges"]),
-           "n_edges": sizes["n_edges"], "n_faces": sizes["n_faces"], "n_tets": len(wl["tets"])}
+           "n_edges": sizes["n_edges"], "n_faces": sizes["n_faces"], "n_tets": len(wl["tets"]),
+           "n_int_edges": sizes["n_int_edges"], "n_aux": sizes["n_int_nodes"]}
     occ = 0
     for s in species:
         occ += len(np.unique(F.fepic_get_particles(ctx, s)["tet"]))
@@ -264,7 +284,7 @@ def main():
     ms_tot, nl = fam_time[dominant]
     mean_particles = psteps / args.steps
     wst = {"particles": mean_particles, "occupied_tets": occ, "crossings": cross / args.steps}
-    per_launch_bytes = algorithmic_bytes(dominant, geo, wst)
+    per_launch_bytes = algorithmic_bytes(dominant, geo, wst, pc)
     work_share = 1.0
     if dominant == "push":
         per_launch_bytes = algorithmic_bytes(dominant, geo, wst) / len(species)
@@ -274,12 +294,13 @@ def main():
         work_share = min(1.0, sum(cg_iters) / nl)
     avg_s = ms_tot / nl / 1e3
     achieved = per_launch_bytes * work_share / avg_s / 1e9
-    traffic = traffic_from_profile(dominant, wl["name"], per_launch_bytes)
+    traffic = traffic_from_profile(dominant, wl["name"], per_launch_bytes, pc)
     if traffic is not None:
         traffic = int(traffic * work_share)   # counters are per working launch (median)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": KERNEL_NAMES[dominant], "avg_launch_us": round(avg_s * 1e6, 3), "launches": nl,
+                "kernel": JACOBI_ITER_KERNEL if (dominant == "cg_iter" and pc == "jacobi") else KERNEL_NAMES[dominant],
+                "avg_launch_us": round(avg_s * 1e6, 3), "launches": nl,
                 "working_launch_share": round(work_share, 4),
                 "algorithmic_bytes_per_launch": int(per_launch_bytes * work_share)}
     # the particle kernel's own rate and roofline, for reference
@@ -314,7 +335,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "tets": len(wl["tets"]), "particles": n_total,
                    "mean_live_particles": round(mean_particles), "dt": wl["dt"], "beta": wl["beta"],
-                   "gamma": wl["gamma"], "cg_tol": 1e-10, "warm_start": args.warm_start,
+                   "gamma": wl["gamma"], "cg_tol": 1e-10, "preconditioner": pc, "warm_start": args.warm_start,
                    "sort_period": args.sort_period, "inject_per_step": int(wl.get("inject_per_step") or 0) if inject else 0,
                    "inject_from": args.inject_from if inject else None,
                    "precision": ("fp32 push / fp64 deposit+solve" if precision == 0 else "all fp64"),

@@ -294,6 +294,7 @@ void ensure_operator(fepic_ctx* c, double dt, double beta) {
     const double cA = beta * dt * dt;
     if (c->A_scale == cA && c->A_valid) return;
     launch_scale_A(c->stream, c->mesh.mat, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_A, c->d_dinv, c->d_bedge, cA);
+    launch_aux_scale(c->stream, c->aux, c->d_sp, c->d_col, c->d_A);
     c->A_scale = cA;
     c->A_valid = true;
 }
@@ -328,24 +329,33 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
     }
     ev_mark(c, 6);
     CgVec* const V[2] = {c->d_cgv[0], c->d_cgv[1]};
+    double2* const ZP[2] = {c->d_zp[0], c->d_zp[1]};
+    const bool aux = c->opt.preconditioner == FEPIC_PC_AUX;
+    auto cg_init = [&]() {
+        if (aux)
+            launch_pcg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, c->aux, ZP[0],
+                            c->d_rq, c->d_partial, c->d_sc, c->opt.cg_tol);
+        else
+            launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, V[0], c->d_partial,
+                           c->d_sc, c->opt.cg_tol);
+    };
     const int maxit = c->opt.cg_max_iters;
     const int batch = std::max(1, c->opt.cg_check_every);
     int total = 0;
     double rr0_first = -1.0;
     c->cg_restarts = 0;
     for (int restart = 0;; ++restart) {
-        launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, V[0], c->d_partial,
-                       c->d_sc, c->opt.cg_tol);
+        cg_init();
         if (restart == 0 && mode == FEPIC_WS_MLP) {
             // guard: a start worse than x0 = 0 (or non-finite) falls back to e^n
-            launch_cg_rr0(c->stream, ne, c->d_partial, c->d_sc);
+            if (aux) launch_pcg_rr0(c->stream, c->d_partial, c->d_sc);
+            else launch_cg_rr0(c->stream, ne, c->d_partial, c->d_sc);
             HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
             if (!(std::isfinite(c->h_sc->rr0)) || c->h_sc->rr0 > c->h_sc->bb) {
                 c->mlp_fallbacks++;
                 launch_warm(c->stream, FEPIC_WS_PREV, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
-                launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, V[0],
-                               c->d_partial, c->d_sc, c->opt.cg_tol);
+                cg_init();
             }
         }
         // Iterations are launched in batches; after each batch the host reads the device's
@@ -362,9 +372,14 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
             todo = std::min(todo, budget + 1 - launched);
             hipEvent_t* ev = timer_pair(c, FAM_CG_ITER, todo);
             if (ev) (void)hipEventRecord(ev[0], c->stream);
-            for (int k = 0; k < todo; ++k)
-                launch_cg_iter(c->stream, launched + k, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, V,
-                               c->d_partial, c->d_sc);
+            for (int k = 0; k < todo; ++k) {
+                if (aux)
+                    launch_pcg_iter(c->stream, launched + k, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, c->aux,
+                                    ZP, c->d_rq, c->d_partial, c->d_sc);
+                else
+                    launch_cg_iter(c->stream, launched + k, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, V,
+                                   c->d_partial, c->d_sc);
+            }
             if (ev) (void)hipEventRecord(ev[1], c->stream);
             launched += todo;
             HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
@@ -717,6 +732,7 @@ void fepic_default_options(fepic_options* o) {
     o->warm_start = FEPIC_WS_PREV;
     o->diagnostics = 0;
     o->timing = 0;
+    o->preconditioner = FEPIC_PC_AUX;
 }
 
 const char* fepic_error_string(int code) {
@@ -746,6 +762,7 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
     if (o.precision != FEPIC_FP32_PUSH_FP64_ACC && o.precision != FEPIC_ALL_FP64) return FEPIC_E_ARG;
     if (!(o.cg_tol > 0) || o.cg_max_iters < 1 || o.crossing_cap < 1 || o.sort_period < 0) return FEPIC_E_ARG;
     if (o.warm_start < FEPIC_WS_PREV || o.warm_start > FEPIC_WS_MLP) return FEPIC_E_ARG;
+    if (o.preconditioner != FEPIC_PC_JACOBI && o.preconditioner != FEPIC_PC_AUX) return FEPIC_E_ARG;
     if (o.cg_check_every < 1) o.cg_check_every = 8;
     fepic_ctx* c = new fepic_ctx();
     c->opt = o;
@@ -806,6 +823,13 @@ int fepic_set_allocator(fepic_ctx* c, void* (*alloc)(size_t bytes, void* user), 
     c->ualloc = alloc;
     c->ufree = free_;
     c->uarg = user;
+    return FEPIC_OK;
+}
+
+int fepic_set_preconditioner(fepic_ctx* c, int pc) {
+    if (!c || (pc != FEPIC_PC_JACOBI && pc != FEPIC_PC_AUX)) return FEPIC_E_ARG;
+    if (c->opt.preconditioner != pc) c->last_cg_iters = 0;   // batch sizing starts afresh
+    c->opt.preconditioner = pc;
     return FEPIC_OK;
 }
 
@@ -878,6 +902,30 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
         p = dalloc<CgVec>(c, ne);
         if (!p) return fail(c, FEPIC_E_OOM, "device allocation failed");
         HIPCHK(c, hipMemset(p, 0, sizeof(CgVec) * ne));
+    }
+    // nodal auxiliary space of the preconditioner
+    {
+        int64_t *asp = nullptr;
+        int32_t *ainc = nullptr, *aends = nullptr;
+        float* ath = nullptr;
+        if ((rc = upload(c, &asp, m.aux_sp)) || (rc = upload(c, &ainc, m.aux_inc)) ||
+            (rc = upload(c, &ath, m.aux_th)) || (rc = upload(c, &aends, m.aux_ends)))
+            return rc;
+        c->aux.n_aux = m.n_aux;
+        c->aux.sp = asp;
+        c->aux.inc = ainc;
+        c->aux.th = reinterpret_cast<const float4*>(ath);
+        c->aux.ends = reinterpret_cast<const int2*>(aends);
+        c->aux.scale = dalloc<double4>(c, m.n_aux);
+        c->aux.Y = dalloc<double4>(c, m.n_aux + 1);
+        c->d_rq = dalloc<double2>(c, ne);
+        for (double2*& p : c->d_zp) p = dalloc<double2>(c, ne);
+        if (!c->aux.scale || !c->aux.Y || !c->d_rq || !c->d_zp[0] || !c->d_zp[1])
+            return fail(c, FEPIC_E_OOM, "device allocation failed");
+        HIPCHK(c, hipMemset(c->aux.Y, 0, sizeof(double4) * (m.n_aux + 1)));   // entry n_aux stays zero
+        HIPCHK(c, hipMemset(c->aux.scale, 0, sizeof(double4) * std::max<int64_t>(m.n_aux, 1)));
+        HIPCHK(c, hipMemset(c->d_rq, 0, sizeof(double2) * ne));
+        for (double2* p : c->d_zp) HIPCHK(c, hipMemset(p, 0, sizeof(double2) * ne));
     }
     double** fv[] = {&c->d_b, &c->d_bn};
     for (double** p : fv) {

@@ -74,7 +74,11 @@ struct fepic_ctx {
     double *d_dg = nullptr, *d_dgn = nullptr, *d_G = nullptr;
     double *d_b = nullptr, *d_bn = nullptr;
     double *d_rhs = nullptr, *d_rt = nullptr, *d_Me = nullptr;
-    fepic::CgVec* d_cgv[2] = {nullptr, nullptr};   // PCG state, double buffered
+    fepic::CgVec* d_cgv[2] = {nullptr, nullptr};   // Jacobi-PCG state, double buffered
+    // auxiliary-space PCG: (z, p) pairs double buffered, (r, q) pairs, nodal arrays
+    double2* d_zp[2] = {nullptr, nullptr};
+    double2* d_rq = nullptr;
+    fepic::AuxSpace aux;
     double* d_partial = nullptr;
     fepic::CgScalars* d_sc = nullptr;
     fepic::CgScalars* h_sc = nullptr;

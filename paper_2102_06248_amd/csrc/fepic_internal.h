@@ -100,6 +100,22 @@ struct alignas(32) CgVec {
     double R, W, S, P;
 };
 
+// Padding entry of the auxiliary space's node incidence lists (no edge).
+constexpr int32_t kAuxPad = INT32_MIN;
+
+// Device arrays of the nodal auxiliary space of the Newmark preconditioner
+// B = diag(A)^-1 + G diag(G^T A G)^-1 G^T + Pi diag(Pi^T A Pi)^-1 Pi^T, with G the discrete
+// gradient and Pi the vector nodal interpolation, both on interior edges and nodes.
+struct AuxSpace {
+    int64_t n_aux = 0;            // interior nodes
+    const int64_t* sp = nullptr;  // SELL-64 slice offsets of the node incidence lists
+    const int32_t* inc = nullptr; // device edge id (node is its head) or ~id (tail); kAuxPad
+    const float4* th = nullptr;   // [n_edges] (r_head - r_tail) / 2, w unused; zero on wall edges
+    const int2* ends = nullptr;   // [n_edges] auxiliary index of tail, head (n_aux: zero entry)
+    double4* scale = nullptr;     // [n_aux] 1/diag(G^T A G), 1/diag(Pi^T A Pi) for x, y, z
+    double4* Y = nullptr;         // [n_aux + 1] nodal corrections of the residual; Y[n_aux] = 0
+};
+
 // Device-side diagnostics accumulators (max-abs values stored as ordered bit patterns).
 struct DiagAcc {
     unsigned long long cont_max, gauss_max, drift_max, rho_max, divb_max;
@@ -159,6 +175,17 @@ void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* slice_p
                     const double* A, const double* dinv, double* x, CgVec* const v[2], double* partial,
                     CgScalars* sc);
 void launch_cg_rr0(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc);
+// PCG with the nodal auxiliary-space preconditioner: per row z = B r with the previous
+// search direction p (zp, double buffered) and r with q = A p (rq).
+void launch_aux_scale(hipStream_t s, const AuxSpace& g, const int64_t* slice_ptr, const int32_t* col,
+                      const double* A);
+void launch_pcg_init(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* A,
+                     const double* dinv, const double* b, const double* x, const AuxSpace& g, double2* zp0,
+                     double2* rq, double* partial, CgScalars* sc, double tol);
+void launch_pcg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
+                     const double* A, const double* dinv, double* x, const AuxSpace& g, double2* const zp[2],
+                     double2* rq, double* partial, CgScalars* sc);
+void launch_pcg_rr0(hipStream_t s, double* partial, CgScalars* sc);
 void launch_cg_resid(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
                      const double* A, const double* b, double* x, double* r_true, double* partial,
                      CgScalars* sc);

@@ -26,7 +26,99 @@ inline void cross(const double* a, const double* b, double* c) {
 }
 inline double dot(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
+// Morton code of a point of the box [lo, hi]: 21 bits per axis, interleaved x y z.
+uint64_t morton_key(const double* p, const double* lo, const double* hi) {
+    auto spread = [](uint64_t v) {  // 21 bits -> every third bit
+        v &= 0x1fffff;
+        v = (v | v << 32) & 0x1f00000000ffffull;
+        v = (v | v << 16) & 0x1f0000ff0000ffull;
+        v = (v | v << 8) & 0x100f00f00f00f00full;
+        v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+        v = (v | v << 2) & 0x1249249249249249ull;
+        return v;
+    };
+    uint64_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        const double ext = hi[d] - lo[d];
+        const double f = ext > 0 ? (p[d] - lo[d]) / ext : 0.0;
+        q[d] = (uint64_t)std::min(2097151.0, std::max(0.0, f * 2097151.0));
+    }
+    return spread(q[0]) | spread(q[1]) << 1 | spread(q[2]) << 2;
+}
+
 }  // namespace
+
+// Nodal auxiliary space of the Newmark preconditioner: the interior nodes in Morton order
+// of their positions (rows of equal degree grouped within windows of kAuxWindow), each
+// with the list of its interior edges in SELL-64 layout, and per edge the half edge
+// vector and the auxiliary indices of its ends.
+void build_aux_space(HostMesh& m) {
+    constexpr int64_t kAuxWindow = 8 * kSell;
+    const int64_t nn = m.n_nodes, ne = m.n_edges;
+    double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < nn; ++v)
+        for (int d = 0; d < 3; ++d) {
+            lo3[d] = std::min(lo3[d], m.xyz[3 * v + d]);
+            hi3[d] = std::max(hi3[d], m.xyz[3 * v + d]);
+        }
+    // interior edges of every node, device edge ids ascending
+    std::vector<int64_t> start(nn + 1, 0);
+    for (int64_t d = 0; d < ne; ++d)
+        if (!m.dev_bedge[d]) {
+            start[m.dev_edges[2 * d] + 1]++;
+            start[m.dev_edges[2 * d + 1] + 1]++;
+        }
+    for (int64_t v = 0; v < nn; ++v) start[v + 1] += start[v];
+    std::vector<int32_t> code(start[nn]);
+    {
+        std::vector<int64_t> pos(start.begin(), start.end() - 1);
+        for (int64_t d = 0; d < ne; ++d)
+            if (!m.dev_bedge[d]) {
+                code[pos[m.dev_edges[2 * d]]++] = ~(int32_t)d;   // tail: -1 in the gradient
+                code[pos[m.dev_edges[2 * d + 1]]++] = (int32_t)d;  // head: +1
+            }
+    }
+    std::vector<int32_t> order;
+    std::vector<uint64_t> key(nn, 0);
+    for (int64_t v = 0; v < nn; ++v)
+        if (!m.bnode[v]) {
+            order.push_back((int32_t)v);
+            key[v] = morton_key(&m.xyz[3 * v], lo3, hi3);
+        }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    auto deg = [&](int32_t v) { return start[v + 1] - start[v]; };
+    for (size_t w0 = 0; w0 < order.size(); w0 += kAuxWindow) {
+        const size_t w1 = std::min(order.size(), w0 + (size_t)kAuxWindow);
+        std::stable_sort(order.begin() + w0, order.begin() + w1, [&](int32_t a, int32_t b) { return deg(a) > deg(b); });
+    }
+    const int64_t na = (int64_t)order.size();
+    m.n_aux = na;
+    m.aux_node = order;
+    std::vector<int32_t> aux_of(nn, (int32_t)na);   // wall nodes -> the zero entry
+    for (int64_t a = 0; a < na; ++a) aux_of[order[a]] = (int32_t)a;
+    const int64_t nsl = (na + kSell - 1) / kSell;
+    m.aux_sp.assign(nsl + 1, 0);
+    for (int64_t s = 0; s < nsl; ++s) {
+        int64_t w = 0;
+        for (int l = 0; l < kSell && s * kSell + l < na; ++l) w = std::max(w, deg(order[s * kSell + l]));
+        m.aux_sp[s + 1] = m.aux_sp[s] + w * kSell;
+    }
+    m.aux_inc.assign(m.aux_sp[nsl], kAuxPad);
+    for (int64_t a = 0; a < na; ++a) {
+        const int32_t v = order[a];
+        const int64_t s = a / kSell, l = a % kSell;
+        for (int64_t k = 0; k < deg(v); ++k) m.aux_inc[m.aux_sp[s] + k * kSell + l] = code[start[v] + k];
+    }
+    m.aux_th.assign(4 * ne, 0.0f);
+    m.aux_ends.assign(2 * ne, (int32_t)na);
+    for (int64_t d = 0; d < ne; ++d) {
+        if (m.dev_bedge[d]) continue;
+        const int32_t a = m.dev_edges[2 * d], b = m.dev_edges[2 * d + 1];
+        for (int k = 0; k < 3; ++k) m.aux_th[4 * d + k] = (float)(0.5 * (m.xyz[3 * b + k] - m.xyz[3 * a + k]));
+        m.aux_ends[2 * d] = aux_of[a];
+        m.aux_ends[2 * d + 1] = aux_of[b];
+    }
+}
 
 int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets_in,
                     std::string& err) {
@@ -192,25 +284,12 @@ int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_t
                 lo3[d] = std::min(lo3[d], m.xyz[3 * v + d]);
                 hi3[d] = std::max(hi3[d], m.xyz[3 * v + d]);
             }
-        auto spread = [](uint64_t v) {  // 21 bits -> every third bit
-            v &= 0x1fffff;
-            v = (v | v << 32) & 0x1f00000000ffffull;
-            v = (v | v << 16) & 0x1f0000ff0000ffull;
-            v = (v | v << 8) & 0x100f00f00f00f00full;
-            v = (v | v << 4) & 0x10c30c30c30c30c3ull;
-            v = (v | v << 2) & 0x1249249249249249ull;
-            return v;
-        };
         std::vector<uint64_t> key(ne0);
         for (int64_t e = 0; e < ne0; ++e) {
-            uint64_t q[3];
-            for (int d = 0; d < 3; ++d) {
-                const double mid = 0.5 * (m.xyz[3 * m.edges[2 * e] + d] + m.xyz[3 * m.edges[2 * e + 1] + d]);
-                const double ext = hi3[d] - lo3[d];
-                const double f = ext > 0 ? (mid - lo3[d]) / ext : 0.0;
-                q[d] = (uint64_t)std::min(2097151.0, std::max(0.0, f * 2097151.0));
-            }
-            key[e] = spread(q[0]) | spread(q[1]) << 1 | spread(q[2]) << 2;
+            double mid[3];
+            for (int d = 0; d < 3; ++d)
+                mid[d] = 0.5 * (m.xyz[3 * m.edges[2 * e] + d] + m.xyz[3 * m.edges[2 * e + 1] + d]);
+            key[e] = morton_key(mid, lo3, hi3);
         }
         m.eiperm.resize(ne0);
         std::iota(m.eiperm.begin(), m.eiperm.end(), 0);
@@ -374,6 +453,8 @@ int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_t
     // boundary rows: keep a unit mass on the diagonal (identity rows after scaling)
     for (int64_t e = 0; e < ne; ++e)
         if (BE[e]) A.M[slot(e, (int32_t)e)] = 1.0;
+
+    build_aux_space(m);
 
     // ---- point-location grid
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};

@@ -39,6 +39,15 @@ struct HostMesh {
     std::vector<double> vol;          // [n_tets]
     SellMatrix mat;                   // M and S over all edge rows in device order (boundary rows:
                                       // diagonal only)
+    // Nodal auxiliary space of the Newmark preconditioner: interior nodes in Morton order.
+    int64_t n_aux = 0;
+    std::vector<int32_t> aux_node;    // auxiliary index -> node id
+    std::vector<int64_t> aux_sp;      // SELL-64 slice offsets of the node incidence lists
+    std::vector<int32_t> aux_inc;     // device edge id (node is its head) or ~id (its tail);
+                                      // kAuxPad in padding
+    std::vector<float> aux_th;        // [n_edges][4] (r_head - r_tail) / 2; zero on wall edges
+    std::vector<int32_t> aux_ends;    // [n_edges][2] auxiliary index of tail, head; n_aux for
+                                      // wall nodes (and both ends of wall edges)
     // point-location grid
     double grid_lo[3] = {0, 0, 0}, grid_inv_h[3] = {1, 1, 1};
     int32_t grid_n[3] = {1, 1, 1};

@@ -435,6 +435,356 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
     cg_add(cg_buf(cg_slots, i + 1), v);
 }
 
+// ------------------------------------------------------------------------------------
+// PCG with the nodal auxiliary-space preconditioner of Hiptmair and Xu (2007), additive,
+// one Jacobi step in each space:  B r = D^-1 r + G D_G^-1 G^T r + Pi D_Pi^-1 Pi^T r,
+// D = diag A, D_G = diag G^T A G, D_Pi = diag Pi^T A Pi, G the discrete gradient and Pi the
+// vector nodal interpolation on interior edges and nodes.  The slow components of
+// Jacobi-PCG on the Newmark system are gradients (the kernel of S) and smooth curl
+// fields; the two nodal spaces reach both.  Plain (Hestenes-Stiefel) recurrences; an
+// iteration is three kernels, because z = B r needs the nodal sums of the new residual
+// before any edge can form it:
+//   k_pcg_q(i):      beta = g_i / g_{i-1};  p = z + beta p;  q = A p (the neighbours' p
+//                    formed on the fly from their gathered (z, p) pair);  dot (p, q)
+//   k_pcg_nodes(i):  alpha = g_i / (p, q);  per interior node, G^T r' and Pi^T r' over its
+//                    edges, r' = r - alpha q, scaled by D_G^-1 and D_Pi^-1
+//   k_pcg_update(i): x += alpha p;  r = r';  z = D^-1 r + G y + Pi v;  dots (r, z), (r, r)
+// Every kernel issues its loads before it sums the previous kernel's slots.  Reductions
+// use the iteration slots in four rotating buffers: reduction k goes to buffer k mod 4;
+// iteration i adds (p, q) as reduction 2i and (r, z), (r, r) as reduction 2i + 1; the
+// start's dots are reduction -1.  k_pcg_nodes(i) clears buffer 2i + 1 and
+// k_pcg_update(i) buffer 2i + 2, each after that buffer's last reader and before its next
+// writer.
+__device__ __forceinline__ double* red_buf(double* base, int k) {
+    return base + (size_t)(((k % 4) + 4) % 4) * 3 * kCgSlots;
+}
+
+template <int NV>
+__device__ __forceinline__ void slot_load(const double* buf, double t[NV]) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) t[j] = threadIdx.x < kCgSlots ? buf[j * kCgSlots + threadIdx.x] : 0.0;
+}
+
+template <int NV>
+__device__ __forceinline__ void slot_add(double* buf, const double v[NV]) {
+    if (threadIdx.x == 0) {
+        const int s = blockIdx.x & (kCgSlots - 1);
+#pragma unroll
+        for (int j = 0; j < NV; ++j) unsafeAtomicAdd(buf + j * kCgSlots + s, v[j]);
+    }
+}
+
+__device__ __forceinline__ void clear_buf(double* buf) {
+    for (int k = threadIdx.x; k < 3 * kCgSlots; k += kBlock) buf[k] = 0.0;
+}
+
+// Per node: D_G^-1 and D_Pi^-1 from the rows of A.  The pair (e, f) of the node's edges
+// contributes s_e A_ef s_f to diag G^T A G (s = +1 at an edge's head, -1 at its tail) and
+// th_e,d A_ef th_f,d to component d of diag Pi^T A Pi; f runs over row e's stored columns
+// and counts when the node is one of its ends.
+__global__ __launch_bounds__(kBlock) void k_aux_scale(AuxSpace g, const int64_t* __restrict__ sp,
+                                                       const int32_t* __restrict__ col, const double* __restrict__ A) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.n_aux) return;
+    const int64_t sl = n >> 6;
+    const int lane = (int)(n & 63);
+    double dg = 0.0, dp0 = 0.0, dp1 = 0.0, dp2 = 0.0;
+    for (int64_t k = g.sp[sl] + lane; k < g.sp[sl + 1]; k += 64) {
+        const int32_t c = g.inc[k];
+        if (c == kAuxPad) continue;
+        const int32_t e = c >= 0 ? c : ~c;
+        const double se = c >= 0 ? 1.0 : -1.0;
+        const float4 te = g.th[e];
+        const int64_t esl = e >> 6;
+        const int el = e & 63;
+        for (int64_t kk = sp[esl] + el; kk < sp[esl + 1]; kk += 64) {
+            const int32_t f = col[kk];
+            const int2 ef = g.ends[f];
+            const double sf = ef.y == n ? 1.0 : (ef.x == n ? -1.0 : 0.0);
+            if (sf == 0.0) continue;
+            const double a = A[kk];
+            const float4 tf = g.th[f];
+            dg += se * a * sf;
+            dp0 += (double)te.x * a * (double)tf.x;
+            dp1 += (double)te.y * a * (double)tf.y;
+            dp2 += (double)te.z * a * (double)tf.z;
+        }
+    }
+    g.scale[n] = make_double4(dg > 0.0 ? 1.0 / dg : 0.0, dp0 > 0.0 ? 1.0 / dp0 : 0.0, dp1 > 0.0 ? 1.0 / dp1 : 0.0,
+                              dp2 > 0.0 ? 1.0 / dp2 : 0.0);
+}
+
+// ||b||^2 from the right-hand side's partials; r = b - A x, q = 0; clears the four
+// reduction buffers.
+__global__ __launch_bounds__(kBlock) void k_pcg_init(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
+                                                      const int32_t* __restrict__ col, const double* __restrict__ A,
+                                                      const double* __restrict__ b, const double* __restrict__ x,
+                                                      double2* __restrict__ RQ, const double* __restrict__ part_rhs,
+                                                      double* cg_slots, CgScalars* sc, double tol) {
+    double bb[1];
+    read_partials<1>(part_rhs, gridDim.x, bb);
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            sc->bb = bb[0];
+            sc->tol2_bb = tol * tol * bb[0];
+            sc->converged = 0;
+        }
+        for (int k = threadIdx.x; k < 4 * 3 * kCgSlots; k += kBlock) cg_slots[k] = 0.0;
+    }
+    for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
+        const int64_t row = lb * kBlock + threadIdx.x;
+        if (((row >> 6) << 6) >= n_rows) continue;
+        const double ax = sell_row(sp, col, A, row, [&](int c) { return x[c]; });
+        if (row < n_rows) RQ[row] = make_double2(b[row] - ax, 0.0);
+    }
+}
+
+// Row j of A p split by the iteration's scalar: sum_k A_jk z_k and sum_k A_jk p_k over
+// the stored entries, so the gathers are issued before beta is known; own (z, p).
+struct QPart {
+    double sZ, sP;
+    double2 own;
+};
+
+__device__ __forceinline__ void q_part(QPart& P, const int64_t* __restrict__ sp, const int32_t* __restrict__ col,
+                                       const double* __restrict__ A, const double2* __restrict__ ZP, int64_t row,
+                                       bool real) {
+    const int64_t sl = row >> 6;
+    const int lane = (int)(row & 63);
+    const int64_t k1 = sp[sl + 1];
+    int64_t k = sp[sl] + lane;
+    P.own = ZP[real ? row : 0];
+    double z0 = 0.0, p0 = 0.0, z1 = 0.0, p1 = 0.0;
+    for (; k + (kUnroll - 1) * 64 < k1; k += kUnroll * 64) {
+        int c[kUnroll];
+        double a[kUnroll];
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) {
+            c[q] = col[k + 64 * q];
+            a[q] = A[k + 64 * q];
+        }
+        double2 zp[kUnroll];
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) zp[q] = ZP[c[q]];
+#pragma unroll
+        for (int q = 0; q < kUnroll; q += 2) {
+            z0 += a[q] * zp[q].x;
+            p0 += a[q] * zp[q].y;
+            z1 += a[q + 1] * zp[q + 1].x;
+            p1 += a[q + 1] * zp[q + 1].y;
+        }
+    }
+    for (; k < k1; k += 64) {
+        const double a = A[k];
+        const double2 zp = ZP[col[k]];
+        z0 += a * zp.x;
+        p0 += a * zp.y;
+    }
+    P.sZ = z0 + z1;
+    P.sP = p0 + p1;
+}
+
+// The convergence test of iterate i (its (r, r) from reduction 2i - 1), beta, the new
+// direction p (into ZPn, the other buffer) and q = A p; (p, q) into reduction 2i.
+__global__ __launch_bounds__(kBlock) void k_pcg_q(int64_t n_rows, RowGrid rg, int i, const int64_t* __restrict__ sp,
+                                                   const int32_t* __restrict__ col, const double* __restrict__ A,
+                                                   const double2* __restrict__ ZP, double2* __restrict__ ZPn,
+                                                   double2* __restrict__ RQ, double* __restrict__ cg_slots,
+                                                   CgScalars* sc) {
+    const int conv = sc->converged;
+    double t[2];
+    slot_load<2>(red_buf(cg_slots, 2 * i - 1), t);
+    int64_t lb = rg_first(rg);
+    const int64_t le = rg_end(rg);
+    QPart P;
+    int64_t row = lb * kBlock + threadIdx.x;
+    bool active = lb < le && ((row >> 6) << 6) < n_rows;
+    if (active) q_part(P, sp, col, A, ZP, row, row < n_rows);
+    if (conv) return;
+    block_sum_all<2>(t);
+    const double g = t[0], rr = t[1];
+    const bool done = !(rr > sc->tol2_bb) || sc->bb == 0.0;
+    const double beta = (i == 0) ? 0.0 : g / sc->gam[(i - 1) & 1];
+    const bool bad = !done && !(g > 0.0 && g < INFINITY && beta >= 0.0 && beta < INFINITY);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->gam[i & 1] = g;
+        sc->rr = rr;
+        sc->iters = i;
+        if (i == 0) sc->rr0 = rr;
+        if (done) sc->converged = 1;
+        if (bad) sc->converged = 2;
+    }
+    if (done || bad) return;
+    double v[1] = {0.0};
+    double* pn = reinterpret_cast<double*>(ZPn);
+    double* qn = reinterpret_cast<double*>(RQ);
+    while (lb < le) {
+        if (active && row < n_rows) {
+            const double p = P.own.x + beta * P.own.y;
+            const double q = P.sZ + beta * P.sP;
+            pn[2 * row + 1] = p;
+            qn[2 * row + 1] = q;
+            v[0] += p * q;
+        }
+        lb += rg.g;
+        row = lb * kBlock + threadIdx.x;
+        active = lb < le && ((row >> 6) << 6) < n_rows;
+        if (active) q_part(P, sp, col, A, ZP, row, row < n_rows);
+    }
+    block_sum_all<1>(v);
+    slot_add<1>(red_buf(cg_slots, 2 * i), v);
+}
+
+// Sums over a node's edges of s_e r_e, s_e q_e, th_e r_e and th_e q_e (r' = r - alpha q is
+// formed once alpha is known).  Padding entries read edge 0 and count zero.
+struct NodePart {
+    double yr, yq, vr[3], vq[3];
+    double4 scale;
+};
+
+constexpr int kNodeUnroll = 4;
+
+__device__ __forceinline__ void node_part(NodePart& P, const AuxSpace& g, const double2* __restrict__ RQ,
+                                          int64_t node) {
+    const int64_t sl = node >> 6;
+    const int lane = (int)(node & 63);
+    const int64_t k1 = g.sp[sl + 1];
+    P.yr = P.yq = 0.0;
+    for (int d = 0; d < 3; ++d) P.vr[d] = P.vq[d] = 0.0;
+    P.scale = g.scale[node < g.n_aux ? node : 0];
+    for (int64_t k = g.sp[sl] + lane; k < k1; k += kNodeUnroll * 64) {
+        int32_t c[kNodeUnroll];
+#pragma unroll
+        for (int q = 0; q < kNodeUnroll; ++q) c[q] = (k + 64 * q < k1) ? g.inc[k + 64 * q] : kAuxPad;
+        double2 rq[kNodeUnroll];
+        float4 th[kNodeUnroll];
+        double s[kNodeUnroll];
+#pragma unroll
+        for (int q = 0; q < kNodeUnroll; ++q) {
+            const bool ok = c[q] != kAuxPad;
+            const int32_t e = ok ? (c[q] >= 0 ? c[q] : ~c[q]) : 0;
+            s[q] = ok ? (c[q] >= 0 ? 1.0 : -1.0) : 0.0;
+            rq[q] = RQ[e];
+            th[q] = g.th[e];
+        }
+#pragma unroll
+        for (int q = 0; q < kNodeUnroll; ++q) {
+            const double r = s[q] != 0.0 ? rq[q].x : 0.0, qq = s[q] != 0.0 ? rq[q].y : 0.0;
+            P.yr += s[q] * r;
+            P.yq += s[q] * qq;
+            P.vr[0] += (double)th[q].x * r;
+            P.vr[1] += (double)th[q].y * r;
+            P.vr[2] += (double)th[q].z * r;
+            P.vq[0] += (double)th[q].x * qq;
+            P.vq[1] += (double)th[q].y * qq;
+            P.vq[2] += (double)th[q].z * qq;
+        }
+    }
+}
+
+// alpha from reduction 2i (i = -1: the start, alpha = 0); Y = (D_G^-1 G^T r', D_Pi^-1 Pi^T r').
+__global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpace g, const double2* __restrict__ RQ,
+                                                       double* __restrict__ cg_slots, CgScalars* sc) {
+    const int conv = sc->converged;
+    double t[1] = {0.0};
+    if (i >= 0) slot_load<1>(red_buf(cg_slots, 2 * i), t);
+    int64_t lb = rg_first(rg);
+    const int64_t le = rg_end(rg);
+    NodePart P;
+    int64_t node = lb * kBlock + threadIdx.x;
+    bool active = lb < le && ((node >> 6) << 6) < g.n_aux;
+    if (active) node_part(P, g, RQ, node);
+    if (conv) return;
+    double alpha = 0.0;
+    if (i >= 0) {
+        block_sum_all<1>(t);
+        alpha = sc->gam[i & 1] / t[0];
+        if (!(alpha > 0.0 && alpha < INFINITY)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) sc->converged = 2;
+            return;
+        }
+    }
+    if (blockIdx.x == 0) clear_buf(red_buf(cg_slots, 2 * i + 1));
+    while (lb < le) {
+        if (active && node < g.n_aux) {
+            g.Y[node] = make_double4((P.yr - alpha * P.yq) * P.scale.x, (P.vr[0] - alpha * P.vq[0]) * P.scale.y,
+                                     (P.vr[1] - alpha * P.vq[1]) * P.scale.z,
+                                     (P.vr[2] - alpha * P.vq[2]) * P.scale.w);
+        }
+        lb += rg.g;
+        node = lb * kBlock + threadIdx.x;
+        active = lb < le && ((node >> 6) << 6) < g.n_aux;
+        if (active) node_part(P, g, RQ, node);
+    }
+}
+
+// A row's own values for the update.
+struct UPart {
+    double2 rq, zp;
+    double x, dinv;
+    float4 th;
+    double4 ya, yb;
+};
+
+__device__ __forceinline__ void u_part(UPart& P, const AuxSpace& g, const double* __restrict__ dinv,
+                                       const double* __restrict__ x, const double2* __restrict__ ZP,
+                                       const double2* __restrict__ RQ, int64_t row) {
+    P.rq = RQ[row];
+    P.zp = ZP[row];
+    P.x = x[row];
+    P.dinv = dinv[row];
+    P.th = g.th[row];
+    const int2 en = g.ends[row];
+    P.ya = g.Y[en.x];
+    P.yb = g.Y[en.y];
+}
+
+// x += alpha p (not at the start), r' = r - alpha q, z = D^-1 r' + G y + Pi v; (r', z) and
+// (r', r') into reduction 2i + 1.  ZP here is the buffer k_pcg_q(i) wrote p into.
+__global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n_rows, RowGrid rg, int i, AuxSpace g,
+                                                        const double* __restrict__ dinv, double* __restrict__ x,
+                                                        double2* __restrict__ ZP, double2* __restrict__ RQ,
+                                                        double* __restrict__ cg_slots, CgScalars* sc) {
+    const int conv = sc->converged;
+    double t[1] = {0.0};
+    if (i >= 0) slot_load<1>(red_buf(cg_slots, 2 * i), t);
+    int64_t lb = rg_first(rg);
+    const int64_t le = rg_end(rg);
+    UPart P;
+    int64_t row = lb * kBlock + threadIdx.x;
+    bool active = lb < le && row < n_rows;
+    if (active) u_part(P, g, dinv, x, ZP, RQ, row);
+    if (conv) return;
+    double alpha = 0.0;
+    if (i >= 0) {
+        block_sum_all<1>(t);
+        alpha = sc->gam[i & 1] / t[0];
+        if (!(alpha > 0.0 && alpha < INFINITY)) return;
+    }
+    if (blockIdx.x == 0) clear_buf(red_buf(cg_slots, 2 * i + 2));
+    double v[2] = {0.0, 0.0};
+    double* rn = reinterpret_cast<double*>(RQ);
+    while (lb < le) {
+        if (active) {
+            const double r = P.rq.x - alpha * P.rq.y;
+            const double p = i >= 0 ? P.zp.y : 0.0;
+            if (i >= 0) x[row] = P.x + alpha * p;
+            const double z = P.dinv * r + (P.yb.x - P.ya.x) + (double)P.th.x * (P.ya.y + P.yb.y) +
+                             (double)P.th.y * (P.ya.z + P.yb.z) + (double)P.th.z * (P.ya.w + P.yb.w);
+            rn[2 * row] = r;
+            ZP[row] = make_double2(z, p);
+            v[0] += r * z;
+            v[1] += r * r;
+        }
+        lb += rg.g;
+        row = lb * kBlock + threadIdx.x;
+        active = lb < le && row < n_rows;
+        if (active) u_part(P, g, dinv, x, ZP, RQ, row);
+    }
+    block_sum_all<2>(v);
+    slot_add<2>(red_buf(cg_slots, 2 * i + 1), v);
+}
+
 __global__ __launch_bounds__(kBlock) void k_zero_if_b_zero(double* x, int64_t n, const CgScalars* sc) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n && sc->bb == 0.0) x[i] = 0.0;
@@ -576,7 +926,7 @@ __global__ __launch_bounds__(kBlock) void k_line_apply(int64_t n, const double* 
 // Partial-buffer slots (each holds up to 3 values per workgroup of the largest grid).
 constexpr size_t kSlot = 4 * kMaxGrid;
 enum { SLOT_RHS = 0, SLOT_CG, SLOT_RESID, SLOT_DOT, SLOT_COUNT };
-static_assert(3 * 3 * kCgSlots <= kSlot, "iteration slots fit one partial region");
+static_assert(4 * 3 * kCgSlots <= kSlot, "iteration slots fit one partial region");
 
 }  // namespace
 
@@ -645,6 +995,46 @@ void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, con
     const int a = i & 1, b = 1 - a;
     hipLaunchKernelGGL(k_cg_iter, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, dinv, x, v[a], v[b],
                        partial + SLOT_CG * kSlot, sc);
+}
+
+void launch_aux_scale(hipStream_t s, const AuxSpace& g, const int64_t* sp, const int32_t* col, const double* A) {
+    if (g.n_aux <= 0) return;
+    hipLaunchKernelGGL(k_aux_scale, dim3(grid_1d(g.n_aux, kBlock)), dim3(kBlock), 0, s, g, sp, col, A);
+}
+
+// The start: r = b - A x, then z = B r and the dots (r, z), (r, r) as reduction -1.
+void launch_pcg_init(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
+                     const double* dinv, const double* b, const double* x, const AuxSpace& g, double2* zp0,
+                     double2* rq, double* partial, CgScalars* sc, double tol) {
+    const RowGrid rg = row_grid(n_rows);
+    double* slots = partial + SLOT_CG * kSlot;
+    hipLaunchKernelGGL(k_pcg_init, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, b, x, rq,
+                       partial + SLOT_RHS * kSlot, slots, sc, tol);
+    const RowGrid ng = row_grid_full(g.n_aux);
+    hipLaunchKernelGGL(k_pcg_nodes, dim3(ng.grid), dim3(kBlock), 0, s, ng, -1, g, rq, slots, sc);
+    const RowGrid ug = row_grid_full(n_rows);
+    hipLaunchKernelGGL(k_pcg_update, dim3(ug.grid), dim3(kBlock), 0, s, n_rows, ug, -1, g, dinv, const_cast<double*>(x),
+                       zp0, rq, slots, sc);
+}
+
+// Iteration i: (z, p) pairs read from buffer i & 1, p and then z written to (i + 1) & 1.
+void launch_pcg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
+                     const double* dinv, double* x, const AuxSpace& g, double2* const zp[2], double2* rq,
+                     double* partial, CgScalars* sc) {
+    const RowGrid rg = row_grid_full(n_rows);
+    const RowGrid ng = row_grid_full(g.n_aux);
+    double* slots = partial + SLOT_CG * kSlot;
+    const int a = i & 1, b = 1 - a;
+    hipLaunchKernelGGL(k_pcg_q, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, zp[a], zp[b], rq, slots,
+                       sc);
+    hipLaunchKernelGGL(k_pcg_nodes, dim3(ng.grid), dim3(kBlock), 0, s, ng, i, g, rq, slots, sc);
+    hipLaunchKernelGGL(k_pcg_update, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, g, dinv, x, zp[b], rq, slots,
+                       sc);
+}
+
+void launch_pcg_rr0(hipStream_t s, double* partial, CgScalars* sc) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partial + SLOT_CG * kSlot + 3 * 3 * kCgSlots + kCgSlots,
+                       kCgSlots, &sc->rr0);
 }
 
 void launch_cg_rr0(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc) {

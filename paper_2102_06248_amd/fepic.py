@@ -15,10 +15,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfepic.so")
 
-ABI_VERSION = 2   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
+ABI_VERSION = 3   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
 FEPIC_OK = 0
 FEPIC_FP32_PUSH_FP64_ACC, FEPIC_ALL_FP64 = 0, 1
 FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP = 0, 1, 2, 3
+FEPIC_PC_JACOBI, FEPIC_PC_AUX = 0, 1
 FEPIC_E_CG_NOT_CONVERGED = -6
 FEPIC_E_CROSSING_CAP = -7
 FEPIC_MLP_N_PARAMS = 4545
@@ -31,7 +32,7 @@ class fepic_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("precision", ctypes.c_int), ("cg_tol", ctypes.c_double),
                 ("cg_max_iters", ctypes.c_int), ("cg_check_every", ctypes.c_int), ("sort_period", ctypes.c_int),
                 ("crossing_cap", ctypes.c_int), ("warm_start", ctypes.c_int), ("diagnostics", ctypes.c_int),
-                ("timing", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("preconditioner", ctypes.c_int)]
 
 
 class fepic_step_stats(ctypes.Structure):
@@ -108,6 +109,7 @@ _SIGS = {
     "fepic_ws_get_weights": [_P, _P, _I64, _PI64],
     "fepic_ws_set_weights": [_P, _P, _I64],
     "fepic_set_warm_start": [_P, _INT],
+    "fepic_set_preconditioner": [_P, _INT],
     "fepic_mlp_forward": [_P, _I64, _P, _P],
     "fepic_mlp_grad": [_P, _I64, _P, _P, _P, ctypes.POINTER(_D)],
     "fepic_save": [_P, ctypes.c_char_p],
@@ -421,6 +423,10 @@ def fepic_ws_set_weights(ctx, w):
 
 def fepic_set_warm_start(ctx, mode):
     _check(ctx, lib().fepic_set_warm_start(ctx, int(mode)))
+
+
+def fepic_set_preconditioner(ctx, pc):
+    _check(ctx, lib().fepic_set_preconditioner(ctx, int(pc)))
 
 
 def fepic_mlp_forward(ctx, X):

@@ -116,12 +116,15 @@ def test_c1_single_electron_2000_steps_fp64(F):
     rL = gam * M_E * v0 / (Q_E * B0)
     c = np.full(3, 5 / 12)
     x0, u0 = [c + [rL, 0, 0]], [[0, gam * v0, 0]]
-    osim = OracleSim(xyz, tets)
+    # Both solves stop at 1e-13: the library's preconditioner differs from the oracle's
+    # Jacobi, so each step's solution differs within the stopping tolerance, and over 2000
+    # steps a 1e-10 tolerance adds up to a few 1e-6 of this small field.
+    osim = OracleSim(xyz, tets, cg_tol=1e-13)
     osim.set_uniform_B([0, 0, B0])
     s = osim.add_species(-Q_E, M_E, 1.0)
     osim.upload_particles(s, x0, u0)
     osim.init_electrostatic()
-    with _lib_sim(F, xyz, tets, precision=1, diagnostics=1) as L:
+    with _lib_sim(F, xyz, tets, precision=1, diagnostics=1, cg_tol=1e-13) as L:
         F.fepic_set_uniform_B(L.ctx, [0, 0, B0])
         sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 1.0)
         F.fepic_upload_particles(L.ctx, sp, x0, u0)
@@ -213,6 +216,49 @@ def test_newmark_solve_vs_oracle(F, mode):
     assert st.cg_iters > 0
     assert np.linalg.norm(eg - osim.e) <= 1e-6 * np.linalg.norm(osim.e)
     assert np.linalg.norm(bg - osim.b) <= 1e-6 * np.linalg.norm(osim.b)
+
+
+@pytest.mark.parametrize("n,cfl_ratio", [(7, 4.0), (16, 20.0)])
+@pytest.mark.parametrize("pc", ["jacobi", "aux"])
+def test_preconditioned_cg_vs_oracle_pcg(F, pc, n, cfl_ratio):
+    """One field-only step with each preconditioner: the library's iteration count matches
+    the oracle's PCG with the same preconditioner on the same right-hand side and start
+    (within the spread that summation order gives), and the fields match the direct solve.
+    An auxiliary-space preconditioner with a wrong sign, scale or asymmetry still converges,
+    but not in the oracle's number of iterations."""
+    from oracle import auxspace, newmark
+    import scipy.sparse.linalg as spla
+    announce(f"PCG {pc} on a {n}^3 Kuhn mesh, dt = {cfl_ratio} x the explicit limit")
+    xyz, tets, h = jittered_kuhn(n, seed=11)
+    osim = OracleSim(xyz, tets)
+    m = osim.mesh
+    rng = np.random.default_rng(8)
+    e = rng.normal(size=m.n_edges)
+    ep = e + 0.05 * rng.normal(size=m.n_edges)
+    e[m.boundary_edge] = ep[m.boundary_edge] = 0.0
+    hmin = np.linalg.norm(m.xyz[m.edges[:, 1]] - m.xyz[m.edges[:, 0]], axis=1).min()
+    dt = cfl_ratio * hmin / C_LIGHT
+    ie = osim.ie
+    A, B1, B2 = osim.operators(dt, 0.25, 0.5)
+    rhs = newmark.newmark_rhs(B1, B2, e[ie], ep[ie], np.zeros(len(ie)))
+    if pc == "aux":
+        x_o, it_o, _ = auxspace.pcg(A, rhs, e[ie], auxspace.aux_space_preconditioner(A, m)[0], tol=1e-10)
+    else:
+        x_o, it_o, _ = newmark.pcg_jacobi(A, rhs, e[ie], 1e-10)
+    x_direct = spla.spsolve(A.tocsc(), rhs)
+    # a residual of 1e-10 leaves an error of up to cond(A) 1e-10: the oracle's own PCG sets
+    # the scale
+    err_o = np.linalg.norm(x_o - x_direct)
+    code = F.FEPIC_PC_AUX if pc == "aux" else F.FEPIC_PC_JACOBI
+    with _lib_sim(F, xyz, tets, precision=0, preconditioner=code, cg_check_every=4) as L:
+        F.fepic_set_fields(L.ctx, e=e, e_prev=ep)
+        st = F.fepic_step(L.ctx, dt, 0.25, 0.5)
+        eg, _, _ = F.fepic_get_fields(L.ctx)
+    print(f"\n[pcg] {pc} n={n}: library {st.cg_iters} iterations, oracle {it_o}")
+    assert abs(st.cg_iters - it_o) <= max(2, 0.03 * it_o)
+    assert st.cg_rel_resid <= 1e-10
+    assert np.linalg.norm(eg[ie] - x_direct) <= 10 * err_o + 1e-12 * np.linalg.norm(x_direct)
+    assert np.abs(eg[m.boundary_edge]).max() == 0.0
 
 
 def test_general_beta_gamma(F):

@@ -89,9 +89,11 @@ def test_plasma_weight_and_step():
 def test_bench_byte_model_and_profile_bookkeeping(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
-    geo = {"n_rows": 100, "nnz": 1500, "n_edges": 100, "n_faces": 180, "n_tets": 60}
+    geo = {"n_rows": 100, "nnz": 1500, "n_edges": 100, "n_faces": 180, "n_tets": 60, "n_int_edges": 70,
+           "n_aux": 12}
     st = {"particles": 1000, "occupied_tets": 40, "crossings": 300}
-    assert bench.algorithmic_bytes("cg_iter", geo, st) == 12 * 1500 + 80 * 100
+    assert bench.algorithmic_bytes("cg_iter", geo, st, "jacobi") == 12 * 1500 + 80 * 100
+    assert bench.algorithmic_bytes("cg_iter", geo, st, "aux") == 12 * 1500 + 168 * 100 + 8 * 70 + 96 * 12
     assert bench.algorithmic_bytes("push", geo, st) == 56 * 1000 + 224 * 340
     # counter summaries are used only while the kernel source is unchanged
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
@@ -102,6 +104,7 @@ def test_bench_byte_model_and_profile_bookkeeping(tmp_path, monkeypatch):
     rec = {"source_sha1": bench.source_hash("cg_iter"), "hbm_bytes_per_launch": 123456}
     (tmp_path / "profiles" / "cg_iter_c2_beam_counters.json").write_text(json.dumps(rec))
     assert bench.traffic_from_profile("cg_iter", "c2_beam", 0) == 123456
+    assert bench.traffic_from_profile("cg_iter", "c2_beam", 0, "jacobi") is None   # its own summary
     (src_dir / "kernels_fields.hip").write_text("kernel v2")
     assert bench.traffic_from_profile("cg_iter", "c2_beam", 0) is None
     assert bench.traffic_from_profile("cg_iter", "c3_plasma", 0) is None
