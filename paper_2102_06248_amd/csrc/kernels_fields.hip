@@ -636,31 +636,29 @@ __global__ __launch_bounds__(kBlock) void k_pcg_q(int64_t n_rows, RowGrid rg, in
 }
 
 // Sums over a node's edges of s_e r_e, s_e q_e, th_e r_e and th_e q_e (r' = r - alpha q is
-// formed once alpha is known).  Padding entries read edge 0 and count zero.
-struct NodePart {
-    double yr, yq, vr[3], vq[3];
-    double4 scale;
-};
+// formed once alpha is known).  A workgroup takes one slice of 64 nodes: wave j sums
+// slots j, j + 4, j + 8, ... of every node (coalesced loads of the slice's columns), and
+// the four partial sums meet in LDS.  Padding entries read edge 0 and count zero.
+constexpr int kNodePhases = kBlock / 64;
 
-constexpr int kNodeUnroll = 4;
-
-__device__ __forceinline__ void node_part(NodePart& P, const AuxSpace& g, const double2* __restrict__ RQ,
-                                          int64_t node) {
-    const int64_t sl = node >> 6;
-    const int lane = (int)(node & 63);
-    const int64_t k1 = g.sp[sl + 1];
-    P.yr = P.yq = 0.0;
-    for (int d = 0; d < 3; ++d) P.vr[d] = P.vq[d] = 0.0;
-    P.scale = g.scale[node < g.n_aux ? node : 0];
-    for (int64_t k = g.sp[sl] + lane; k < k1; k += kNodeUnroll * 64) {
-        int32_t c[kNodeUnroll];
+__device__ __forceinline__ void node_part(double P[8], const AuxSpace& g, const double2* __restrict__ RQ, int64_t sl,
+                                          int lane, int j) {
+    const int64_t k0 = g.sp[sl] + lane, k1 = g.sp[sl + 1];
 #pragma unroll
-        for (int q = 0; q < kNodeUnroll; ++q) c[q] = (k + 64 * q < k1) ? g.inc[k + 64 * q] : kAuxPad;
-        double2 rq[kNodeUnroll];
-        float4 th[kNodeUnroll];
-        double s[kNodeUnroll];
+    for (int v = 0; v < 8; ++v) P[v] = 0.0;
+    constexpr int U = 2;
+    for (int64_t k = k0 + 64 * j; k < k1; k += U * kNodePhases * 64) {
+        int32_t c[U];
 #pragma unroll
-        for (int q = 0; q < kNodeUnroll; ++q) {
+        for (int q = 0; q < U; ++q) {
+            const int64_t kk = k + (int64_t)q * kNodePhases * 64;
+            c[q] = kk < k1 ? g.inc[kk] : kAuxPad;
+        }
+        double2 rq[U];
+        float4 th[U];
+        double s[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
             const bool ok = c[q] != kAuxPad;
             const int32_t e = ok ? (c[q] >= 0 ? c[q] : ~c[q]) : 0;
             s[q] = ok ? (c[q] >= 0 ? 1.0 : -1.0) : 0.0;
@@ -668,32 +666,34 @@ __device__ __forceinline__ void node_part(NodePart& P, const AuxSpace& g, const 
             th[q] = g.th[e];
         }
 #pragma unroll
-        for (int q = 0; q < kNodeUnroll; ++q) {
+        for (int q = 0; q < U; ++q) {
             const double r = s[q] != 0.0 ? rq[q].x : 0.0, qq = s[q] != 0.0 ? rq[q].y : 0.0;
-            P.yr += s[q] * r;
-            P.yq += s[q] * qq;
-            P.vr[0] += (double)th[q].x * r;
-            P.vr[1] += (double)th[q].y * r;
-            P.vr[2] += (double)th[q].z * r;
-            P.vq[0] += (double)th[q].x * qq;
-            P.vq[1] += (double)th[q].y * qq;
-            P.vq[2] += (double)th[q].z * qq;
+            P[0] += s[q] * r;
+            P[1] += s[q] * qq;
+            P[2] += (double)th[q].x * r;
+            P[3] += (double)th[q].y * r;
+            P[4] += (double)th[q].z * r;
+            P[5] += (double)th[q].x * qq;
+            P[6] += (double)th[q].y * qq;
+            P[7] += (double)th[q].z * qq;
         }
     }
 }
 
 // alpha from reduction 2i (i = -1: the start, alpha = 0); Y = (D_G^-1 G^T r', D_Pi^-1 Pi^T r').
+// rg runs over slices of 64 nodes.
 __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpace g, const double2* __restrict__ RQ,
                                                        double* __restrict__ cg_slots, CgScalars* sc) {
+    __shared__ double part[8][kNodePhases][64];
     const int conv = sc->converged;
     double t[1] = {0.0};
     if (i >= 0) slot_load<1>(red_buf(cg_slots, 2 * i), t);
-    int64_t lb = rg_first(rg);
+    const int lane = threadIdx.x & 63, j = threadIdx.x >> 6;
+    const int nl = threadIdx.x >> 2, comp = threadIdx.x & 3;   // output: node of the slice, component
+    int64_t sl = rg_first(rg);
     const int64_t le = rg_end(rg);
-    NodePart P;
-    int64_t node = lb * kBlock + threadIdx.x;
-    bool active = lb < le && ((node >> 6) << 6) < g.n_aux;
-    if (active) node_part(P, g, RQ, node);
+    double P[8];
+    if (sl < le) node_part(P, g, RQ, sl, lane, j);
     if (conv) return;
     double alpha = 0.0;
     if (i >= 0) {
@@ -705,16 +705,27 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
         }
     }
     if (blockIdx.x == 0) clear_buf(red_buf(cg_slots, 2 * i + 1));
-    while (lb < le) {
-        if (active && node < g.n_aux) {
-            g.Y[node] = make_double4((P.yr - alpha * P.yq) * P.scale.x, (P.vr[0] - alpha * P.vq[0]) * P.scale.y,
-                                     (P.vr[1] - alpha * P.vq[1]) * P.scale.z,
-                                     (P.vr[2] - alpha * P.vq[2]) * P.scale.w);
+    const double* scale = reinterpret_cast<const double*>(g.scale);
+    double* Y = reinterpret_cast<double*>(g.Y);
+    // component comp of Y: (sum of value a) - alpha (sum of value b)
+    const int va = comp == 0 ? 0 : 1 + comp, vb = comp == 0 ? 1 : 4 + comp;
+    while (sl < le) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) part[v][j][lane] = P[v];
+        __syncthreads();
+        const int64_t node = sl * 64 + nl;
+        if (node < g.n_aux) {
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int q = 0; q < kNodePhases; ++q) {
+                a += part[va][q][nl];
+                b += part[vb][q][nl];
+            }
+            Y[4 * node + comp] = (a - alpha * b) * scale[4 * node + comp];
         }
-        lb += rg.g;
-        node = lb * kBlock + threadIdx.x;
-        active = lb < le && ((node >> 6) << 6) < g.n_aux;
-        if (active) node_part(P, g, RQ, node);
+        __syncthreads();
+        sl += rg.g;
+        if (sl < le) node_part(P, g, RQ, sl, lane, j);
     }
 }
 
@@ -997,6 +1008,16 @@ void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, con
                        partial + SLOT_CG * kSlot, sc);
 }
 
+// One workgroup per slice of 64 auxiliary nodes, consecutive slices on the same XCD.
+inline RowGrid node_grid(int64_t n_aux) {
+    RowGrid r;
+    r.nb = (n_aux + 63) / 64;
+    r.per = (r.nb + 7) / 8;
+    r.g = (int)std::max<int64_t>(1, r.per);
+    r.grid = 8u * (unsigned)r.g;
+    return r;
+}
+
 void launch_aux_scale(hipStream_t s, const AuxSpace& g, const int64_t* sp, const int32_t* col, const double* A) {
     if (g.n_aux <= 0) return;
     hipLaunchKernelGGL(k_aux_scale, dim3(grid_1d(g.n_aux, kBlock)), dim3(kBlock), 0, s, g, sp, col, A);
@@ -1010,7 +1031,7 @@ void launch_pcg_init(hipStream_t s, int64_t n_rows, const int64_t* sp, const int
     double* slots = partial + SLOT_CG * kSlot;
     hipLaunchKernelGGL(k_pcg_init, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, b, x, rq,
                        partial + SLOT_RHS * kSlot, slots, sc, tol);
-    const RowGrid ng = row_grid_full(g.n_aux);
+    const RowGrid ng = node_grid(g.n_aux);
     hipLaunchKernelGGL(k_pcg_nodes, dim3(ng.grid), dim3(kBlock), 0, s, ng, -1, g, rq, slots, sc);
     const RowGrid ug = row_grid_full(n_rows);
     hipLaunchKernelGGL(k_pcg_update, dim3(ug.grid), dim3(kBlock), 0, s, n_rows, ug, -1, g, dinv, const_cast<double*>(x),
@@ -1022,7 +1043,7 @@ void launch_pcg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, co
                      const double* dinv, double* x, const AuxSpace& g, double2* const zp[2], double2* rq,
                      double* partial, CgScalars* sc) {
     const RowGrid rg = row_grid_full(n_rows);
-    const RowGrid ng = row_grid_full(g.n_aux);
+    const RowGrid ng = node_grid(g.n_aux);
     double* slots = partial + SLOT_CG * kSlot;
     const int a = i & 1, b = 1 - a;
     hipLaunchKernelGGL(k_pcg_q, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, zp[a], zp[b], rq, slots,
