@@ -22,7 +22,18 @@ unknowns at zero):
   trapezoid rule gives exactly: (r_b - r_a) . (F(r_a) + F(r_b)) / 2, so the entry of Pi
   for edge (a, b) and node n in {a, b}, component d, is (r_b - r_a)_d / 2.
 
-B is symmetric positive definite (a sum of an SPD matrix and two symmetric positive
+Coarser levels (optional, ``levels``): the one-level form leaves the smooth components of
+the two nodal spaces slow.  Each level groups the interior nodes into aggregates of
+consecutive nodes in Morton order of their positions (sizes 8, 64, ...), and adds the
+same two corrections for the piecewise-constant nodal fields of each aggregate (the
+aggregate's summed hat functions for G, and a constant vector over it for Pi), again with
+one Jacobi step:  B += sum over levels of Q diag(Q^T A Q)^-1 Q^T, Q = [G P, Pi P3], P the
+aggregation (node -> aggregate) matrix.  This is an additive multilevel (BPX-type) scheme
+on the auxiliary spaces.  Morton order: each coordinate scaled to [0, 1] over the bounding
+box of all nodes, truncated to 21 bits, bits interleaved x, y, z from the lowest; ties
+keep node order.
+
+B is symmetric positive definite (a sum of an SPD matrix and symmetric positive
 semi-definite ones), so PCG with it converges to the same solution as any other PCG; it
 only changes how many iterations that takes.  The stopping rule is the one of
 ``newmark.pcg_jacobi``: ||r||_2 <= tol ||b||_2 on the updated residual.
@@ -60,20 +71,49 @@ def vector_interpolation_matrix(mesh, rows, nodes):
                          shape=(len(rows), 3 * len(nodes)))
 
 
-def aux_space_preconditioner(A, mesh, edges=None, nodes=None):
+def morton_order(mesh, nodes):
+    """`nodes` sorted by the Morton code of their positions (module docstring)."""
+    lo, hi = mesh.xyz.min(axis=0), mesh.xyz.max(axis=0)
+    ext = hi - lo
+    f = np.where(ext > 0, (mesh.xyz[nodes] - lo) / np.where(ext > 0, ext, 1.0), 0.0)
+    q = np.minimum(2097151.0, np.maximum(0.0, f * 2097151.0)).astype(np.uint64)
+    code = np.zeros(len(nodes), dtype=np.uint64)
+    for bit in range(21):
+        for d in range(3):
+            code |= ((q[:, d] >> np.uint64(bit)) & np.uint64(1)) << np.uint64(3 * bit + d)
+    return np.asarray(nodes)[np.argsort(code, kind="stable")]
+
+
+def aggregation_matrix(n, size):
+    """n x ceil(n / size): node k (in Morton order) -> aggregate k // size."""
+    k = np.arange(n)
+    return sp.csr_matrix((np.ones(n), (k, k // size)), shape=(n, (n + size - 1) // size))
+
+
+def aux_space_preconditioner(A, mesh, edges=None, nodes=None, levels=()):
     """The additive preconditioner B as a function r -> B r on the unknowns `edges`
     (default: interior edges, the rows of A) with nodal spaces on `nodes` (default:
-    interior nodes).  Returns (apply, G, Pi, dG, dPi) with the diagonals used."""
+    interior nodes, taken in Morton order) and aggregation levels of the given sizes.
+    Returns (apply, G, Pi, dG, dPi) with the fine-level matrices and diagonals."""
     edges = mesh.interior_edges if edges is None else edges
-    nodes = mesh.interior_nodes if nodes is None else nodes
+    nodes = morton_order(mesh, mesh.interior_nodes if nodes is None else nodes)
     G = gradient_matrix(mesh, edges, nodes)
     Pi = vector_interpolation_matrix(mesh, edges, nodes)
     dA = A.diagonal()
     dG = (G.T @ (A @ G)).diagonal()
     dPi = (Pi.T @ (A @ Pi)).diagonal()
+    coarse = []
+    for size in levels:
+        P = aggregation_matrix(len(nodes), size)
+        P3 = sp.kron(P, sp.identity(3)).tocsr()   # (node, d) -> (aggregate, d)
+        for Q in ((G @ P).tocsr(), (Pi @ P3).tocsr()):
+            coarse.append((Q, (Q.T @ (A @ Q)).diagonal()))
 
     def apply(r):
-        return r / dA + G @ ((G.T @ r) / dG) + Pi @ ((Pi.T @ r) / dPi)
+        z = r / dA + G @ ((G.T @ r) / dG) + Pi @ ((Pi.T @ r) / dPi)
+        for Q, d in coarse:
+            z = z + Q @ ((Q.T @ r) / d)
+        return z
 
     return apply, G, Pi, dG, dPi
 

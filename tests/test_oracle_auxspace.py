@@ -7,6 +7,7 @@ sparse solve of the Newmark system.
 """
 import numpy as np
 import pytest
+import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from oracle import auxspace, fem, newmark
@@ -108,3 +109,58 @@ def test_pcg_matches_the_direct_solve_in_fewer_iterations(mesh, cfl_ratio):
     _, it_same, _ = auxspace.pcg(A, b, np.zeros_like(b), lambda r: r / dA, tol=1e-10)
     assert abs(it_same - it_j) <= max(2, 0.02 * it_j)
     print(f"cfl ratio {cfl_ratio}: aux-space PCG {it} iterations, Jacobi PCG {it_j}")
+
+
+def _morton_brute(mesh, nodes):
+    """Morton order by string interleaving of the 21-bit quantized coordinates."""
+    lo, hi = mesh.xyz.min(axis=0), mesh.xyz.max(axis=0)
+    keys = []
+    for v in nodes:
+        q = [int(min(2097151.0, max(0.0, (mesh.xyz[v, d] - lo[d]) / (hi[d] - lo[d]) * 2097151.0)))
+             for d in range(3)]
+        bits = [format(x, "021b") for x in q]            # most significant bit first
+        keys.append("".join(bits[2][i] + bits[1][i] + bits[0][i] for i in range(21)))   # z y x per level
+    return [v for _, v in sorted(zip(keys, nodes), key=lambda kv: kv[0])]
+
+
+def test_morton_order_and_aggregate_locality():
+    m = Mesh(*_jittered_kuhn(9, 5, amp=0.02))
+    order = auxspace.morton_order(m, m.interior_nodes)
+    assert list(order) == _morton_brute(m, m.interior_nodes)
+    # a space-filling curve: runs of 8 consecutive nodes of the 8^3 interior lattice are
+    # compact (each lies within a small box of lattice cells)
+    h = 1.0 / 9
+    ext = [np.ptp(m.xyz[order[k:k + 8]], axis=0).max() for k in range(0, len(order), 8)]
+    assert np.median(ext) <= 1.2 * h and max(ext) <= 4.2 * h
+
+
+def test_coarse_vector_level_interpolates_uniform_fields(mesh):
+    """One aggregate holding every interior node: its Pi-level basis for component d is
+    the field that is e_d at interior nodes (zero at the wall), whose unknowns on edges
+    with both ends interior are the line integrals of the uniform field e_d."""
+    ie, inode = mesh.interior_edges, auxspace.morton_order(mesh, mesh.interior_nodes)
+    Pi = auxspace.vector_interpolation_matrix(mesh, ie, inode)
+    P = auxspace.aggregation_matrix(len(inode), len(inode))
+    Q = (Pi @ sp.kron(P, sp.identity(3))).toarray()
+    both = ~mesh.boundary_node[mesh.edges[ie]].any(axis=1)
+    for d in range(3):
+        u = np.eye(3)[d]
+        assert np.allclose(Q[both, d], mesh.edge_dofs_of_uniform_field(u)[ie][both], rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("levels", [(8,), (8, 64)])
+def test_multilevel_preconditioner(mesh, levels):
+    A = _newmark_A(mesh, 20.0)
+    apply1 = auxspace.aux_space_preconditioner(A, mesh)[0]
+    apply = auxspace.aux_space_preconditioner(A, mesh, levels=levels)[0]
+    rng = np.random.default_rng(6)
+    x, y = rng.normal(size=(2, A.shape[0]))
+    assert abs(x @ apply(y) - y @ apply(x)) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(apply(y))
+    assert x @ apply(x) > x @ apply1(x) > 0        # the levels add positive semi-definite terms
+    b = rng.normal(size=A.shape[0])
+    x_direct = spla.spsolve(A.tocsc(), b)
+    xs, it, res = auxspace.pcg(A, b, np.zeros_like(b), apply, tol=1e-10)
+    _, it1, _ = auxspace.pcg(A, b, np.zeros_like(b), apply1, tol=1e-10)
+    assert res <= 1e-10 and np.linalg.norm(xs - x_direct) <= 1e-8 * np.linalg.norm(x_direct)
+    assert it < it1
+    print(f"levels {levels}: {it} iterations, one level {it1}")
