@@ -917,10 +917,13 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
         c->aux.th = reinterpret_cast<const float4*>(ath);
         c->aux.ends = reinterpret_cast<const int2*>(aends);
         c->aux.scale = dalloc<double4>(c, m.n_aux);
+        c->aux.scale8 = dalloc<double4>(c, (m.n_aux + 7) / 8);
+        c->aux.scale64 = dalloc<double4>(c, (m.n_aux + 63) / 64);
         c->aux.Y = dalloc<double4>(c, m.n_aux + 1);
         c->d_rq = dalloc<double2>(c, ne);
         for (double2*& p : c->d_zp) p = dalloc<double2>(c, ne);
-        if (!c->aux.scale || !c->aux.Y || !c->d_rq || !c->d_zp[0] || !c->d_zp[1])
+        if (!c->aux.scale || !c->aux.scale8 || !c->aux.scale64 || !c->aux.Y || !c->d_rq || !c->d_zp[0] ||
+            !c->d_zp[1])
             return fail(c, FEPIC_E_OOM, "device allocation failed");
         HIPCHK(c, hipMemset(c->aux.Y, 0, sizeof(double4) * (m.n_aux + 1)));   // entry n_aux stays zero
         HIPCHK(c, hipMemset(c->aux.scale, 0, sizeof(double4) * std::max<int64_t>(m.n_aux, 1)));

@@ -113,7 +113,12 @@ struct AuxSpace {
     const float4* th = nullptr;   // [n_edges] (r_head - r_tail) / 2, w unused; zero on wall edges
     const int2* ends = nullptr;   // [n_edges] auxiliary index of tail, head (n_aux: zero entry)
     double4* scale = nullptr;     // [n_aux] 1/diag(G^T A G), 1/diag(Pi^T A Pi) for x, y, z
-    double4* Y = nullptr;         // [n_aux + 1] nodal corrections of the residual; Y[n_aux] = 0
+    // the same for the aggregates of 8 and of 64 consecutive auxiliary nodes (the coarser
+    // levels: summed hat functions for G, constant vectors for Pi)
+    double4* scale8 = nullptr;    // [ceil(n_aux / 8)]
+    double4* scale64 = nullptr;   // [ceil(n_aux / 64)]
+    double4* Y = nullptr;         // [n_aux + 1] nodal corrections of the residual, all levels;
+                                  // Y[n_aux] = 0
 };
 
 // Device-side diagnostics accumulators (max-abs values stored as ordered bit patterns).

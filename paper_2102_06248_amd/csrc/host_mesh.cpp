@@ -49,11 +49,10 @@ uint64_t morton_key(const double* p, const double* lo, const double* hi) {
 }  // namespace
 
 // Nodal auxiliary space of the Newmark preconditioner: the interior nodes in Morton order
-// of their positions (rows of equal degree grouped within windows of kAuxWindow), each
-// with the list of its interior edges in SELL-64 layout, and per edge the half edge
-// vector and the auxiliary indices of its ends.
+// of their positions (ties in node order; runs of 8 and 64 consecutive nodes are the
+// aggregates of the coarser levels), each with the list of its interior edges in SELL-64
+// layout, and per edge the half edge vector and the auxiliary indices of its ends.
 void build_aux_space(HostMesh& m) {
-    constexpr int64_t kAuxWindow = 8 * kSell;
     const int64_t nn = m.n_nodes, ne = m.n_edges;
     double lo3[3] = {1e300, 1e300, 1e300}, hi3[3] = {-1e300, -1e300, -1e300};
     for (int64_t v = 0; v < nn; ++v)
@@ -87,10 +86,6 @@ void build_aux_space(HostMesh& m) {
         }
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
     auto deg = [&](int32_t v) { return start[v + 1] - start[v]; };
-    for (size_t w0 = 0; w0 < order.size(); w0 += kAuxWindow) {
-        const size_t w1 = std::min(order.size(), w0 + (size_t)kAuxWindow);
-        std::stable_sort(order.begin() + w0, order.begin() + w1, [&](int32_t a, int32_t b) { return deg(a) > deg(b); });
-    }
     const int64_t na = (int64_t)order.size();
     m.n_aux = na;
     m.aux_node = order;

@@ -514,6 +514,73 @@ __global__ __launch_bounds__(kBlock) void k_aux_scale(AuxSpace g, const int64_t*
                               dp2 > 0.0 ? 1.0 / dp2 : 0.0);
 }
 
+// Diagonals of the aggregate levels: for aggregate a (aux nodes [a L, (a + 1) L)) the
+// G-level basis vector is phi_e = (head of e in a) - (tail of e in a) and the Pi-level one
+// psi_e = th_e ((tail in a) + (head in a)); diag = phi^T A phi and psi_d^T A psi_d.  Each
+// node adds the terms of its incident edges, an edge with both ends in the aggregate from
+// its tail only, into the aggregate's accumulator (zeroed before).
+template <int kLog>
+__device__ __forceinline__ void coarse_terms(const AuxSpace& g, const int64_t* __restrict__ sp,
+                                             const int32_t* __restrict__ col, const double* __restrict__ A,
+                                             int64_t n, double4* __restrict__ acc) {
+    const int64_t agg = n >> kLog;
+    auto in_agg = [&](int32_t k) { return k < g.n_aux && ((int64_t)k >> kLog) == agg; };
+    const int64_t sl = n >> 6;
+    const int lane = (int)(n & 63);
+    double dg = 0.0, dp0 = 0.0, dp1 = 0.0, dp2 = 0.0;
+    for (int64_t k = g.sp[sl] + lane; k < g.sp[sl + 1]; k += 64) {
+        const int32_t c = g.inc[k];
+        if (c == kAuxPad) continue;
+        const int32_t e = c >= 0 ? c : ~c;
+        const int2 ee = g.ends[e];
+        const bool t_in = in_agg(ee.x), h_in = in_agg(ee.y);
+        if (c >= 0 && t_in) continue;   // head end of an edge inside the aggregate: its tail counts it
+        const double phe = (h_in ? 1.0 : 0.0) - (t_in ? 1.0 : 0.0);
+        const double pse = (t_in ? 1.0 : 0.0) + (h_in ? 1.0 : 0.0);
+        const float4 te = g.th[e];
+        const int64_t esl = e >> 6;
+        const int el = e & 63;
+        double rg = 0.0, r0 = 0.0, r1 = 0.0, r2 = 0.0;   // (A phi)_e, (A psi_d)_e
+        for (int64_t kk = sp[esl] + el; kk < sp[esl + 1]; kk += 64) {
+            const int32_t f = col[kk];
+            const int2 ef = g.ends[f];
+            const bool ft = in_agg(ef.x), fh = in_agg(ef.y);
+            if (!ft && !fh) continue;
+            const double a = A[kk];
+            const float4 tf = g.th[f];
+            const double phf = (fh ? 1.0 : 0.0) - (ft ? 1.0 : 0.0);
+            const double psf = (ft ? 1.0 : 0.0) + (fh ? 1.0 : 0.0);
+            rg += a * phf;
+            r0 += a * psf * (double)tf.x;
+            r1 += a * psf * (double)tf.y;
+            r2 += a * psf * (double)tf.z;
+        }
+        dg += phe * rg;
+        dp0 += pse * (double)te.x * r0;
+        dp1 += pse * (double)te.y * r1;
+        dp2 += pse * (double)te.z * r2;
+    }
+    double* out = reinterpret_cast<double*>(acc + agg);
+    unsafeAtomicAdd(out, dg);
+    unsafeAtomicAdd(out + 1, dp0);
+    unsafeAtomicAdd(out + 2, dp1);
+    unsafeAtomicAdd(out + 3, dp2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_aux_coarse(AuxSpace g, const int64_t* __restrict__ sp,
+                                                        const int32_t* __restrict__ col, const double* __restrict__ A) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.n_aux) return;
+    coarse_terms<3>(g, sp, col, A, n, g.scale8);
+    coarse_terms<6>(g, sp, col, A, n, g.scale64);
+}
+
+// diag -> 1 / diag in place (0 where the diagonal is not positive).
+__global__ __launch_bounds__(kBlock) void k_invert_pos(double* v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) v[i] = v[i] > 0.0 ? 1.0 / v[i] : 0.0;
+}
+
 // ||b||^2 from the right-hand side's partials; r = b - A x, q = 0; clears the four
 // reduction buffers.
 __global__ __launch_bounds__(kBlock) void k_pcg_init(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
@@ -706,23 +773,39 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
     }
     if (blockIdx.x == 0) clear_buf(red_buf(cg_slots, 2 * i + 1));
     const double* scale = reinterpret_cast<const double*>(g.scale);
+    const double* scale8 = reinterpret_cast<const double*>(g.scale8);
+    const double* scale64 = reinterpret_cast<const double*>(g.scale64);
     double* Y = reinterpret_cast<double*>(g.Y);
-    // component comp of Y: (sum of value a) - alpha (sum of value b)
+    __shared__ double wsum[kNodePhases][4];
+    // component comp of P^T r' at node nl: (sum of value va) - alpha (sum of value vb)
     const int va = comp == 0 ? 0 : 1 + comp, vb = comp == 0 ? 1 : 4 + comp;
     while (sl < le) {
 #pragma unroll
         for (int v = 0; v < 8; ++v) part[v][j][lane] = P[v];
         __syncthreads();
         const int64_t node = sl * 64 + nl;
-        if (node < g.n_aux) {
-            double a = 0.0, b = 0.0;
+        double a = 0.0, b = 0.0;
 #pragma unroll
-            for (int q = 0; q < kNodePhases; ++q) {
-                a += part[va][q][nl];
-                b += part[vb][q][nl];
-            }
-            Y[4 * node + comp] = (a - alpha * b) * scale[4 * node + comp];
+        for (int q = 0; q < kNodePhases; ++q) {
+            a += part[va][q][nl];
+            b += part[vb][q][nl];
         }
+        const double u = a - alpha * b;   // zero for the padding nodes of the last slice
+        // the aggregate of 8 nodes: lanes 4 nl + comp with the same comp and nl >> 3
+        double s8 = u;
+        s8 += __shfl_xor(s8, 4);
+        s8 += __shfl_xor(s8, 8);
+        s8 += __shfl_xor(s8, 16);
+        // the aggregate of 64 nodes (the slice): the wave's two groups, then the four waves
+        double s16 = s8 + __shfl_xor(s8, 32);
+        if (lane < 4) wsum[j][lane] = s16;
+        __syncthreads();
+        double s64 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kNodePhases; ++q) s64 += wsum[q][comp];
+        if (node < g.n_aux)
+            Y[4 * node + comp] = u * scale[4 * node + comp] + s8 * scale8[4 * (node >> 3) + comp] +
+                                 s64 * scale64[4 * sl + comp];
         __syncthreads();
         sl += rg.g;
         if (sl < le) node_part(P, g, RQ, sl, lane, j);
@@ -1020,7 +1103,17 @@ inline RowGrid node_grid(int64_t n_aux) {
 
 void launch_aux_scale(hipStream_t s, const AuxSpace& g, const int64_t* sp, const int32_t* col, const double* A) {
     if (g.n_aux <= 0) return;
+    const int64_t n8 = 4 * ((g.n_aux + 7) / 8), n64 = 4 * ((g.n_aux + 63) / 64);
     hipLaunchKernelGGL(k_aux_scale, dim3(grid_1d(g.n_aux, kBlock)), dim3(kBlock), 0, s, g, sp, col, A);
+    hipLaunchKernelGGL(k_fill, dim3(grid_1d(n8, kBlock)), dim3(kBlock), 0, s, reinterpret_cast<double*>(g.scale8), n8,
+                       0.0);
+    hipLaunchKernelGGL(k_fill, dim3(grid_1d(n64, kBlock)), dim3(kBlock), 0, s, reinterpret_cast<double*>(g.scale64),
+                       n64, 0.0);
+    hipLaunchKernelGGL(k_aux_coarse, dim3(grid_1d(g.n_aux, kBlock)), dim3(kBlock), 0, s, g, sp, col, A);
+    hipLaunchKernelGGL(k_invert_pos, dim3(grid_1d(n8, kBlock)), dim3(kBlock), 0, s, reinterpret_cast<double*>(g.scale8),
+                       n8);
+    hipLaunchKernelGGL(k_invert_pos, dim3(grid_1d(n64, kBlock)), dim3(kBlock), 0, s,
+                       reinterpret_cast<double*>(g.scale64), n64);
 }
 
 // The start: r = b - A x, then z = B r and the dots (r, z), (r, r) as reduction -1.

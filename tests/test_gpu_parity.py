@@ -242,7 +242,8 @@ def test_preconditioned_cg_vs_oracle_pcg(F, pc, n, cfl_ratio):
     A, B1, B2 = osim.operators(dt, 0.25, 0.5)
     rhs = newmark.newmark_rhs(B1, B2, e[ie], ep[ie], np.zeros(len(ie)))
     if pc == "aux":
-        x_o, it_o, _ = auxspace.pcg(A, rhs, e[ie], auxspace.aux_space_preconditioner(A, m)[0], tol=1e-10)
+        x_o, it_o, _ = auxspace.pcg(A, rhs, e[ie], auxspace.aux_space_preconditioner(A, m, levels=(8, 64))[0],
+                                    tol=1e-10)
     else:
         x_o, it_o, _ = newmark.pcg_jacobi(A, rhs, e[ie], 1e-10)
     x_direct = spla.spsolve(A.tocsc(), rhs)
