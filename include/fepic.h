@@ -69,10 +69,13 @@ enum { FEPIC_WS_PREV = 0, FEPIC_WS_EXTRAP1 = 1, FEPIC_WS_EXTRAP2 = 2, FEPIC_WS_M
 /* Preconditioner of the Newmark solve.  FEPIC_PC_JACOBI: diag(A)^-1.  FEPIC_PC_AUX: the
  * nodal auxiliary-space preconditioner (Hiptmair and Xu, SIAM J. Numer. Anal. 45, 2007),
  * additive with one Jacobi step per space:
- *   B = diag(A)^-1 + G diag(G^T A G)^-1 G^T + Pi diag(Pi^T A Pi)^-1 Pi^T,
+ *   B = diag(A)^-1 + G diag(G^T A G)^-1 G^T + Pi diag(Pi^T A Pi)^-1 Pi^T + coarse levels,
  * G the discrete gradient (edge-node incidence, Sec. II-A) and Pi the interpolation of
  * nodal vector fields into edge unknowns ((r_b - r_a) . (v_a + v_b) / 2), both on interior
- * edges and nodes.  Either one converges to the same tolerance; the auxiliary space needs
+ * edges and nodes.  The coarse levels add the same two corrections, again with one Jacobi
+ * step, for piecewise-constant nodal fields on aggregates of 8, 64 (always) and 512,
+ * 4096 (aux_far_levels) interior nodes consecutive in Morton order of their positions.
+ * Either preconditioner converges to the same tolerance; the auxiliary spaces need
  * several times fewer iterations once dt is well beyond the explicit limit. */
 enum { FEPIC_PC_JACOBI = 0, FEPIC_PC_AUX = 1 };
 
@@ -93,6 +96,9 @@ typedef struct {
     int diagnostics;   /* 1: charge continuity, Gauss and div b residuals every step      */
     int timing;        /* 1: per-phase HIP-event times in fepic_step_stats                */
     int preconditioner;/* FEPIC_PC_* (default FEPIC_PC_AUX)                               */
+    int aux_far_levels;/* FEPIC_PC_AUX aggregate levels beyond 64 nodes (512, 4096 nodes):
+                          -1 (default) from dt: with tau^2 = mean beta dt^2 S_jj / M_jj,
+                          the level of 2^k nodes when tau >= 2 * 2^(k/3); or 0, 1, 2       */
 } fepic_options;
 
 typedef struct {
@@ -115,6 +121,8 @@ typedef struct {
     float ms_sort, ms_stage, ms_particles, ms_rhs, ms_warm, ms_cg, ms_faraday, ms_diag;
     double magnetic_energy;       /* 1/(2 mu0) int |B|^2 = 1/2 b^T [*mu0^-1] b, joules    */
     double kinetic_energy;        /* sum over live particles of w m c^2 (gamma - 1), J    */
+    int pc_far_levels;            /* aggregate levels beyond 64 nodes the solve used (-1:  */
+                                  /* Jacobi preconditioner or no solve)                   */
 } fepic_step_stats;
 
 /* ---------------------------------------------------------------- lifecycle */

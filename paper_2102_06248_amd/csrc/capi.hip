@@ -292,6 +292,8 @@ void particle_phase(fepic_ctx* c, double dt, bool do_sort) {
 
 void ensure_operator(fepic_ctx* c, double dt, double beta) {
     const double cA = beta * dt * dt;
+    c->aux.n_far = c->opt.aux_far_levels >= 0 ? std::min(c->opt.aux_far_levels, kAuxFarLevels)
+                                              : aux_far_auto(cA * c->s_over_m);
     if (c->A_scale == cA && c->A_valid) return;
     launch_scale_A(c->stream, c->mesh.mat, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_A, c->d_dinv, c->d_bedge, cA);
     launch_aux_scale(c->stream, c->aux, c->d_sp, c->d_col, c->d_A);
@@ -516,6 +518,7 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
     fepic_step_stats st;
     std::memset(&st, 0, sizeof(st));
     st.gauss_drift_check_rel = st.cont_resid_rel = st.gauss_resid_rel = -1.0;
+    st.pc_far_levels = -1;
     if (c->opt.diagnostics && !c->rho_valid) {
         compute_rho(c, c->d_rho);
         c->rho_valid = true;
@@ -550,6 +553,7 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
         st.cg_iters = sc.iters;
         st.cg_rel_resid = sc.bb > 0 ? std::sqrt(sc.rr_true / sc.bb) : 0.0;
         st.cg_rel_resid0 = sc.bb > 0 ? std::sqrt(sc.rr0 / sc.bb) : 0.0;
+        st.pc_far_levels = c->opt.preconditioner == FEPIC_PC_AUX ? c->aux.n_far : -1;
     }
     fill_phase_times(c, &st, solve);
     // failure: leave the state as it was before the call (the sort is a pure reorder)
@@ -733,6 +737,7 @@ void fepic_default_options(fepic_options* o) {
     o->diagnostics = 0;
     o->timing = 0;
     o->preconditioner = FEPIC_PC_AUX;
+    o->aux_far_levels = -1;
 }
 
 const char* fepic_error_string(int code) {
@@ -763,6 +768,7 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
     if (!(o.cg_tol > 0) || o.cg_max_iters < 1 || o.crossing_cap < 1 || o.sort_period < 0) return FEPIC_E_ARG;
     if (o.warm_start < FEPIC_WS_PREV || o.warm_start > FEPIC_WS_MLP) return FEPIC_E_ARG;
     if (o.preconditioner != FEPIC_PC_JACOBI && o.preconditioner != FEPIC_PC_AUX) return FEPIC_E_ARG;
+    if (o.aux_far_levels < -1 || o.aux_far_levels > 2) return FEPIC_E_ARG;
     if (o.cg_check_every < 1) o.cg_check_every = 8;
     fepic_ctx* c = new fepic_ctx();
     c->opt = o;
@@ -905,6 +911,17 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
     }
     // nodal auxiliary space of the preconditioner
     {
+        double sum = 0.0;
+        int64_t cnt = 0;
+        for (int64_t r = 0; r < ne; ++r) {
+            if (m.dev_bedge[r]) continue;
+            const int64_t k = m.mat.slice_ptr[r / kSell] + r % kSell;   // the diagonal slot
+            if (m.mat.M[k] > 0) {
+                sum += m.mat.S[k] / m.mat.M[k];
+                ++cnt;
+            }
+        }
+        c->s_over_m = cnt ? sum / (double)cnt : 0.0;
         int64_t *asp = nullptr;
         int32_t *ainc = nullptr, *aends = nullptr;
         float* ath = nullptr;
@@ -920,6 +937,13 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
         c->aux.scale8 = dalloc<double4>(c, (m.n_aux + 7) / 8);
         c->aux.scale64 = dalloc<double4>(c, (m.n_aux + 63) / 64);
         c->aux.Y = dalloc<double4>(c, m.n_aux + 1);
+        for (int L = 0; L < kAuxFarLevels; ++L) {
+            const int64_t nf = aux_far_count(m.n_aux, L);
+            c->aux.far_scale[L] = dalloc<double4>(c, nf);
+            c->aux.far_acc[L] = dalloc<double4>(c, 8 * nf);
+            if (!c->aux.far_scale[L] || !c->aux.far_acc[L]) return fail(c, FEPIC_E_OOM, "device allocation failed");
+            HIPCHK(c, hipMemset(c->aux.far_acc[L], 0, sizeof(double4) * std::max<int64_t>(8 * nf, 1)));
+        }
         c->d_rq = dalloc<double2>(c, ne);
         for (double2*& p : c->d_zp) p = dalloc<double2>(c, ne);
         if (!c->aux.scale || !c->aux.scale8 || !c->aux.scale64 || !c->aux.Y || !c->d_rq || !c->d_zp[0] ||

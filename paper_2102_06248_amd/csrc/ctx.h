@@ -67,6 +67,7 @@ struct fepic_ctx {
     int32_t *d_cell_start = nullptr, *d_cell_tets = nullptr, *d_grid_n = nullptr;
     double* d_grid = nullptr;  // lo[3], inv_h[3]
     double A_scale = -1.0;
+    double s_over_m = 0.0;   // mean of S_jj / M_jj over interior rows (chooses the far levels)
     bool A_valid = false;
 
     // fields (edge vectors length n_edges, face vectors length n_faces)

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -102,6 +103,18 @@ struct alignas(32) CgVec {
 
 // Padding entry of the auxiliary space's node incidence lists (no edge).
 constexpr int32_t kAuxPad = INT32_MIN;
+// log2 of the aggregate sizes of the auxiliary space's levels beyond one node slice.
+constexpr int kAuxFarLevels = 2;
+__host__ __device__ constexpr int aux_far_log(int L) { return L == 0 ? 9 : 12; }
+inline int64_t aux_far_count(int64_t n_aux, int L) { return (n_aux + (1ll << aux_far_log(L)) - 1) >> aux_far_log(L); }
+// Far levels chosen from tau^2 = mean over interior rows of beta dt^2 S_jj / M_jj (how many
+// cells a wave crosses in a step, squared): the level of 2^k nodes (about 2^(k/3) cells
+// across) is used when tau >= 2 * 2^(k/3).
+inline int aux_far_auto(double tau2) {
+    int n = 0;
+    while (n < kAuxFarLevels && tau2 >= 4.0 * std::exp2(2.0 * aux_far_log(n) / 3.0)) ++n;
+    return n;
+}
 
 // Device arrays of the nodal auxiliary space of the Newmark preconditioner
 // B = diag(A)^-1 + G diag(G^T A G)^-1 G^T + Pi diag(Pi^T A Pi)^-1 Pi^T, with G the discrete
@@ -117,6 +130,13 @@ struct AuxSpace {
     // levels: summed hat functions for G, constant vectors for Pi)
     double4* scale8 = nullptr;    // [ceil(n_aux / 8)]
     double4* scale64 = nullptr;   // [ceil(n_aux / 64)]
+    // levels of 2^aux_far_log(L) nodes, which span several workgroups of the node pass: the
+    // residual's sums per aggregate are accumulated with atomics (far_acc: a 64-byte line
+    // per aggregate and component, the sum in its first double; zeroed by the product
+    // kernel of each iteration) and applied by the update kernel
+    double4* far_scale[2] = {nullptr, nullptr};
+    double4* far_acc[2] = {nullptr, nullptr};   // [8 * count] double4
+    int n_far = 0;                              // far levels in use (0 .. kAuxFarLevels)
     double4* Y = nullptr;         // [n_aux + 1] nodal corrections of the residual, all levels;
                                   // Y[n_aux] = 0
 };

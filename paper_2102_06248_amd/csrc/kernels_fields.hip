@@ -522,7 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_aux_scale(AuxSpace g, const int64_t*
 template <int kLog>
 __device__ __forceinline__ void coarse_terms(const AuxSpace& g, const int64_t* __restrict__ sp,
                                              const int32_t* __restrict__ col, const double* __restrict__ A,
-                                             int64_t n, double4* __restrict__ acc) {
+                                             int64_t n, double out[4]) {
     const int64_t agg = n >> kLog;
     auto in_agg = [&](int32_t k) { return k < g.n_aux && ((int64_t)k >> kLog) == agg; };
     const int64_t sl = n >> 6;
@@ -560,19 +560,43 @@ __device__ __forceinline__ void coarse_terms(const AuxSpace& g, const int64_t* _
         dp1 += pse * (double)te.y * r1;
         dp2 += pse * (double)te.z * r2;
     }
-    double* out = reinterpret_cast<double*>(acc + agg);
-    unsafeAtomicAdd(out, dg);
-    unsafeAtomicAdd(out + 1, dp0);
-    unsafeAtomicAdd(out + 2, dp1);
-    unsafeAtomicAdd(out + 3, dp2);
+    out[0] = dg;
+    out[1] = dp0;
+    out[2] = dp1;
+    out[3] = dp2;
 }
 
+__device__ __forceinline__ void add4(double4* acc, const double v[4]) {
+    double* o = reinterpret_cast<double*>(acc);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) unsafeAtomicAdd(o + k, v[k]);
+}
+
+// Aggregates of 8 and 64 nodes take one atomic per node; the far levels (whole
+// workgroups of consecutive nodes per aggregate) one per workgroup.
 __global__ __launch_bounds__(kBlock) void k_aux_coarse(AuxSpace g, const int64_t* __restrict__ sp,
                                                         const int32_t* __restrict__ col, const double* __restrict__ A) {
+    static_assert(aux_far_log(0) >= 8, "a far aggregate holds whole workgroups");
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (n >= g.n_aux) return;
-    coarse_terms<3>(g, sp, col, A, n, g.scale8);
-    coarse_terms<6>(g, sp, col, A, n, g.scale64);
+    const bool real = n < g.n_aux;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (real) {
+        coarse_terms<3>(g, sp, col, A, n, v);
+        add4(g.scale8 + (n >> 3), v);
+        coarse_terms<6>(g, sp, col, A, n, v);
+        add4(g.scale64 + (n >> 6), v);
+    }
+#pragma unroll
+    for (int L = 0; L < kAuxFarLevels; ++L) {
+        if (real) {
+            if (L == 0) coarse_terms<aux_far_log(0)>(g, sp, col, A, n, v);
+            else coarse_terms<aux_far_log(1)>(g, sp, col, A, n, v);
+        } else {
+            v[0] = v[1] = v[2] = v[3] = 0.0;
+        }
+        block_sum_all<4>(v);
+        if (threadIdx.x == 0) add4(g.far_scale[L] + (((int64_t)blockIdx.x * kBlock) >> aux_far_log(L)), v);
+    }
 }
 
 // diag -> 1 / diag in place (0 where the diagonal is not positive).
@@ -581,13 +605,29 @@ __global__ __launch_bounds__(kBlock) void k_invert_pos(double* v, int64_t n) {
     if (i < n) v[i] = v[i] > 0.0 ? 1.0 / v[i] : 0.0;
 }
 
+// Zeroes the far levels' accumulators (one workgroup).
+__device__ __forceinline__ void clear_far(const AuxSpace& g) {
+#pragma unroll
+    for (int L = 0; L < kAuxFarLevels; ++L) {
+        if (L >= g.n_far) break;
+        const int64_t nf = (g.n_aux + (1ll << aux_far_log(L)) - 1) >> aux_far_log(L);
+        double* a = reinterpret_cast<double*>(g.far_acc[L]);
+        for (int64_t k = threadIdx.x; k < 4 * nf; k += kBlock) a[8 * k] = 0.0;
+    }
+}
+
+// The accumulator of component comp of far-level L aggregate a: one 64-byte line each.
+__device__ __forceinline__ double* far_line(const AuxSpace& g, int L, int64_t a, int comp) {
+    return reinterpret_cast<double*>(g.far_acc[L]) + 8 * (4 * a + comp);
+}
+
 // ||b||^2 from the right-hand side's partials; r = b - A x, q = 0; clears the four
-// reduction buffers.
+// reduction buffers and the far levels' accumulators.
 __global__ __launch_bounds__(kBlock) void k_pcg_init(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
                                                       const int32_t* __restrict__ col, const double* __restrict__ A,
                                                       const double* __restrict__ b, const double* __restrict__ x,
                                                       double2* __restrict__ RQ, const double* __restrict__ part_rhs,
-                                                      double* cg_slots, CgScalars* sc, double tol) {
+                                                      double* cg_slots, CgScalars* sc, double tol, AuxSpace g) {
     double bb[1];
     read_partials<1>(part_rhs, gridDim.x, bb);
     if (blockIdx.x == 0) {
@@ -597,6 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(int64_t n_rows, RowGrid rg,
             sc->converged = 0;
         }
         for (int k = threadIdx.x; k < 4 * 3 * kCgSlots; k += kBlock) cg_slots[k] = 0.0;
+        clear_far(g);
     }
     for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
         const int64_t row = lb * kBlock + threadIdx.x;
@@ -657,7 +698,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_q(int64_t n_rows, RowGrid rg, in
                                                    const int32_t* __restrict__ col, const double* __restrict__ A,
                                                    const double2* __restrict__ ZP, double2* __restrict__ ZPn,
                                                    double2* __restrict__ RQ, double* __restrict__ cg_slots,
-                                                   CgScalars* sc) {
+                                                   CgScalars* sc, AuxSpace aux) {
     const int conv = sc->converged;
     double t[2];
     slot_load<2>(red_buf(cg_slots, 2 * i - 1), t);
@@ -682,6 +723,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_q(int64_t n_rows, RowGrid rg, in
         if (bad) sc->converged = 2;
     }
     if (done || bad) return;
+    if (blockIdx.x == 0) clear_far(aux);   // read by the previous update, added to by the next node pass
     double v[1] = {0.0};
     double* pn = reinterpret_cast<double*>(ZPn);
     double* qn = reinterpret_cast<double*>(RQ);
@@ -806,6 +848,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
         if (node < g.n_aux)
             Y[4 * node + comp] = u * scale[4 * node + comp] + s8 * scale8[4 * (node >> 3) + comp] +
                                  s64 * scale64[4 * sl + comp];
+        // Far levels: the slice's sums added into its aggregates; each component of an
+        // aggregate has its own 64-byte line, so at most 2^(log - 6) workgroups add into one
+        // line.
+        if (threadIdx.x < 4) {   // comp = threadIdx.x
+#pragma unroll
+            for (int L = 0; L < kAuxFarLevels; ++L)
+                if (L < g.n_far) unsafeAtomicAdd(far_line(g, L, (sl * 64) >> aux_far_log(L), comp), s64);
+        }
         __syncthreads();
         sl += rg.g;
         if (sl < le) node_part(P, g, RQ, sl, lane, j);
@@ -831,6 +881,26 @@ __device__ __forceinline__ void u_part(UPart& P, const AuxSpace& g, const double
     const int2 en = g.ends[row];
     P.ya = g.Y[en.x];
     P.yb = g.Y[en.y];
+#pragma unroll
+    for (int L = 0; L < kAuxFarLevels; ++L) {
+        if (L >= g.n_far) break;
+        if (en.x < g.n_aux) {
+            const int64_t a = (int64_t)en.x >> aux_far_log(L);
+            const double4 d = g.far_scale[L][a];
+            P.ya.x += *far_line(g, L, a, 0) * d.x;
+            P.ya.y += *far_line(g, L, a, 1) * d.y;
+            P.ya.z += *far_line(g, L, a, 2) * d.z;
+            P.ya.w += *far_line(g, L, a, 3) * d.w;
+        }
+        if (en.y < g.n_aux) {
+            const int64_t b = (int64_t)en.y >> aux_far_log(L);
+            const double4 d = g.far_scale[L][b];
+            P.yb.x += *far_line(g, L, b, 0) * d.x;
+            P.yb.y += *far_line(g, L, b, 1) * d.y;
+            P.yb.z += *far_line(g, L, b, 2) * d.z;
+            P.yb.w += *far_line(g, L, b, 3) * d.w;
+        }
+    }
 }
 
 // x += alpha p (not at the start), r' = r - alpha q, z = D^-1 r' + G y + Pi v; (r', z) and
@@ -1109,11 +1179,21 @@ void launch_aux_scale(hipStream_t s, const AuxSpace& g, const int64_t* sp, const
                        0.0);
     hipLaunchKernelGGL(k_fill, dim3(grid_1d(n64, kBlock)), dim3(kBlock), 0, s, reinterpret_cast<double*>(g.scale64),
                        n64, 0.0);
+    for (int L = 0; L < kAuxFarLevels; ++L) {
+        const int64_t nf = 4 * aux_far_count(g.n_aux, L);
+        hipLaunchKernelGGL(k_fill, dim3(grid_1d(nf, kBlock)), dim3(kBlock), 0, s,
+                           reinterpret_cast<double*>(g.far_scale[L]), nf, 0.0);
+    }
     hipLaunchKernelGGL(k_aux_coarse, dim3(grid_1d(g.n_aux, kBlock)), dim3(kBlock), 0, s, g, sp, col, A);
     hipLaunchKernelGGL(k_invert_pos, dim3(grid_1d(n8, kBlock)), dim3(kBlock), 0, s, reinterpret_cast<double*>(g.scale8),
                        n8);
     hipLaunchKernelGGL(k_invert_pos, dim3(grid_1d(n64, kBlock)), dim3(kBlock), 0, s,
                        reinterpret_cast<double*>(g.scale64), n64);
+    for (int L = 0; L < kAuxFarLevels; ++L) {
+        const int64_t nf = 4 * aux_far_count(g.n_aux, L);
+        hipLaunchKernelGGL(k_invert_pos, dim3(grid_1d(nf, kBlock)), dim3(kBlock), 0, s,
+                           reinterpret_cast<double*>(g.far_scale[L]), nf);
+    }
 }
 
 // The start: r = b - A x, then z = B r and the dots (r, z), (r, r) as reduction -1.
@@ -1123,7 +1203,7 @@ void launch_pcg_init(hipStream_t s, int64_t n_rows, const int64_t* sp, const int
     const RowGrid rg = row_grid(n_rows);
     double* slots = partial + SLOT_CG * kSlot;
     hipLaunchKernelGGL(k_pcg_init, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, b, x, rq,
-                       partial + SLOT_RHS * kSlot, slots, sc, tol);
+                       partial + SLOT_RHS * kSlot, slots, sc, tol, g);
     const RowGrid ng = node_grid(g.n_aux);
     hipLaunchKernelGGL(k_pcg_nodes, dim3(ng.grid), dim3(kBlock), 0, s, ng, -1, g, rq, slots, sc);
     const RowGrid ug = row_grid_full(n_rows);
@@ -1140,7 +1220,7 @@ void launch_pcg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, co
     double* slots = partial + SLOT_CG * kSlot;
     const int a = i & 1, b = 1 - a;
     hipLaunchKernelGGL(k_pcg_q, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, zp[a], zp[b], rq, slots,
-                       sc);
+                       sc, g);
     hipLaunchKernelGGL(k_pcg_nodes, dim3(ng.grid), dim3(kBlock), 0, s, ng, i, g, rq, slots, sc);
     hipLaunchKernelGGL(k_pcg_update, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, g, dinv, x, zp[b], rq, slots,
                        sc);

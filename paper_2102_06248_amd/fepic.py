@@ -32,7 +32,7 @@ class fepic_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("precision", ctypes.c_int), ("cg_tol", ctypes.c_double),
                 ("cg_max_iters", ctypes.c_int), ("cg_check_every", ctypes.c_int), ("sort_period", ctypes.c_int),
                 ("crossing_cap", ctypes.c_int), ("warm_start", ctypes.c_int), ("diagnostics", ctypes.c_int),
-                ("timing", ctypes.c_int), ("preconditioner", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("preconditioner", ctypes.c_int), ("aux_far_levels", ctypes.c_int)]
 
 
 class fepic_step_stats(ctypes.Structure):
@@ -45,7 +45,8 @@ class fepic_step_stats(ctypes.Structure):
                 ("ms_sort", ctypes.c_float), ("ms_stage", ctypes.c_float), ("ms_particles", ctypes.c_float),
                 ("ms_rhs", ctypes.c_float), ("ms_warm", ctypes.c_float), ("ms_cg", ctypes.c_float),
                 ("ms_faraday", ctypes.c_float), ("ms_diag", ctypes.c_float),
-                ("magnetic_energy", ctypes.c_double), ("kinetic_energy", ctypes.c_double)]
+                ("magnetic_energy", ctypes.c_double), ("kinetic_energy", ctypes.c_double),
+                ("pc_far_levels", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

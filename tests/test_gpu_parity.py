@@ -218,17 +218,20 @@ def test_newmark_solve_vs_oracle(F, mode):
     assert np.linalg.norm(bg - osim.b) <= 1e-6 * np.linalg.norm(osim.b)
 
 
-@pytest.mark.parametrize("n,cfl_ratio", [(7, 4.0), (16, 20.0)])
-@pytest.mark.parametrize("pc", ["jacobi", "aux"])
-def test_preconditioned_cg_vs_oracle_pcg(F, pc, n, cfl_ratio):
+@pytest.mark.parametrize("pc,n,cfl_ratio,far", [("jacobi", 7, 4.0, -1), ("jacobi", 16, 20.0, -1), ("aux", 7, 4.0, -1),
+                                                ("aux", 16, 8.0, -1), ("aux", 16, 20.0, -1), ("aux", 16, 20.0, 1)])
+def test_preconditioned_cg_vs_oracle_pcg(F, pc, n, cfl_ratio, far):
     """One field-only step with each preconditioner: the library's iteration count matches
-    the oracle's PCG with the same preconditioner on the same right-hand side and start
-    (within the spread that summation order gives), and the fields match the direct solve.
-    An auxiliary-space preconditioner with a wrong sign, scale or asymmetry still converges,
-    but not in the oracle's number of iterations."""
+    the oracle's PCG with the same preconditioner (for the auxiliary space: the same
+    aggregate levels, 8 and 64 nodes and as many of 512, 4096 as the library used) on the
+    same right-hand side and start, within the spread that summation order gives, and the
+    fields match the direct solve.  An auxiliary-space preconditioner with a wrong sign,
+    scale, aggregate or asymmetry still converges, but not in the oracle's number of
+    iterations.  far = -1 lets the library choose the far levels from dt; the choice is
+    checked against the rule computed from the oracle's matrices."""
     from oracle import auxspace, newmark
     import scipy.sparse.linalg as spla
-    announce(f"PCG {pc} on a {n}^3 Kuhn mesh, dt = {cfl_ratio} x the explicit limit")
+    announce(f"PCG {pc} on a {n}^3 Kuhn mesh, dt = {cfl_ratio} x the explicit limit, far levels {far}")
     xyz, tets, h = jittered_kuhn(n, seed=11)
     osim = OracleSim(xyz, tets)
     m = osim.mesh
@@ -241,21 +244,26 @@ def test_preconditioned_cg_vs_oracle_pcg(F, pc, n, cfl_ratio):
     ie = osim.ie
     A, B1, B2 = osim.operators(dt, 0.25, 0.5)
     rhs = newmark.newmark_rhs(B1, B2, e[ie], ep[ie], np.zeros(len(ie)))
+    code = F.FEPIC_PC_AUX if pc == "aux" else F.FEPIC_PC_JACOBI
+    with _lib_sim(F, xyz, tets, precision=0, preconditioner=code, cg_check_every=4, aux_far_levels=far) as L:
+        F.fepic_set_fields(L.ctx, e=e, e_prev=ep)
+        st = F.fepic_step(L.ctx, dt, 0.25, 0.5)
+        eg, _, _ = F.fepic_get_fields(L.ctx)
     if pc == "aux":
-        x_o, it_o, _ = auxspace.pcg(A, rhs, e[ie], auxspace.aux_space_preconditioner(A, m, levels=(8, 64))[0],
-                                    tol=1e-10)
+        tau2 = np.mean(0.25 * dt * dt * osim.Si.diagonal() / osim.Mi.diagonal())
+        rule = int(tau2 >= 4 * 2.0 ** 6) + int(tau2 >= 4 * 2.0 ** 8)
+        assert st.pc_far_levels == (rule if far < 0 else far)
+        levels = (8, 64, 512, 4096)[:2 + st.pc_far_levels]
+        x_o, it_o, _ = auxspace.pcg(A, rhs, e[ie], auxspace.aux_space_preconditioner(A, m, levels=levels)[0], tol=1e-10)
     else:
+        assert st.pc_far_levels == -1
+        levels = None
         x_o, it_o, _ = newmark.pcg_jacobi(A, rhs, e[ie], 1e-10)
     x_direct = spla.spsolve(A.tocsc(), rhs)
     # a residual of 1e-10 leaves an error of up to cond(A) 1e-10: the oracle's own PCG sets
     # the scale
     err_o = np.linalg.norm(x_o - x_direct)
-    code = F.FEPIC_PC_AUX if pc == "aux" else F.FEPIC_PC_JACOBI
-    with _lib_sim(F, xyz, tets, precision=0, preconditioner=code, cg_check_every=4) as L:
-        F.fepic_set_fields(L.ctx, e=e, e_prev=ep)
-        st = F.fepic_step(L.ctx, dt, 0.25, 0.5)
-        eg, _, _ = F.fepic_get_fields(L.ctx)
-    print(f"\n[pcg] {pc} n={n}: library {st.cg_iters} iterations, oracle {it_o}")
+    print(f"\n[pcg] {pc} n={n} levels {levels}: library {st.cg_iters} iterations, oracle {it_o}")
     assert abs(st.cg_iters - it_o) <= max(2, 0.03 * it_o)
     assert st.cg_rel_resid <= 1e-10
     assert np.linalg.norm(eg[ie] - x_direct) <= 10 * err_o + 1e-12 * np.linalg.norm(x_direct)
