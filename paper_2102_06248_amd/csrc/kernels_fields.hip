@@ -1,16 +1,17 @@
-// Field-side kernels for gfx950: Newmark right-hand side, Jacobi-PCG on a sliced-ELLPACK
-// matrix (slice height 64 = one wavefront, coalesced column loads), Faraday update and
-// the conservation diagnostics.  All arithmetic FP64.
+// Field-side kernels for gfx950: Newmark right-hand side, PCG on a sliced-ELLPACK matrix
+// (slice height 64 = one wavefront, coalesced column loads) with the nodal auxiliary-space
+// preconditioner or with Jacobi, Faraday update and the conservation diagnostics.  All
+// arithmetic FP64.
 //
-// Grids are bounded (at most kMaxGrid workgroups) and XCD-contiguous: the hardware hands
-// workgroup b to XCD b % 8, so workgroup b walks the row blocks of the b % 8-th eighth of
-// the rows, giving each XCD's L2 one contiguous stretch of rows and of the vector entries
-// their columns mostly touch.
+// Grids are XCD-contiguous: the hardware hands workgroup b to XCD b % 8, so workgroup b
+// walks the row blocks of the b % 8-th eighth of the rows, giving each XCD's L2 one
+// contiguous stretch of rows and of the vector entries their columns mostly touch.
 //
-// Global dot products never communicate between workgroups inside a kernel: each kernel
-// writes one partial per workgroup, and the next kernel (every workgroup, redundantly, in
-// the same fixed order, so all reach the same bits) sums them.  Kernel boundaries give
-// the visibility; no device-scope fences are issued.  A PCG iteration is two kernels.
+// Global dot products never communicate between workgroups inside a kernel: the
+// once-per-solve reductions write one partial per workgroup that the next kernel sums
+// (every workgroup, redundantly, in the same fixed order, so all reach the same bits);
+// the iteration dots go through FP64-atomic slots that the next kernel sums the same way.
+// Kernel boundaries give the visibility; no device-scope fences are issued.
 #include <algorithm>
 
 #include "fepic_internal.h"
