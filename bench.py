@@ -154,6 +154,8 @@ def main():
     ap.add_argument("--diagnostics", action="store_true",
                     help="run the conservation diagnostics every step (continuity, Gauss drift)")
     ap.add_argument("--sort-period", type=int, default=1)
+    ap.add_argument("--walk", default="auto", choices=["auto", "queue", "fused"],
+                    help="crossing paths: chosen from the last step's crossings, queue + second kernel, or in place")
     ap.add_argument("--preconditioner", default="aux", choices=["aux", "jacobi"],
                     help="Newmark PCG preconditioner: nodal auxiliary space (default) or Jacobi")
     ap.add_argument("--inject", type=int, default=1, help="inject the beam's per-step batch (c2)")
@@ -189,7 +191,8 @@ def main():
     pc = args.preconditioner
     sim = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=precision, warm_start=ws,
                        sort_period=args.sort_period, timing=1, diagnostics=1 if args.diagnostics else 0,
-                       preconditioner=F.FEPIC_PC_AUX if pc == "aux" else F.FEPIC_PC_JACOBI)
+                       preconditioner=F.FEPIC_PC_AUX if pc == "aux" else F.FEPIC_PC_JACOBI,
+                       walk={"auto": F.FEPIC_WALK_AUTO, "queue": F.FEPIC_WALK_QUEUE, "fused": F.FEPIC_WALK_FUSED}[args.walk])
     ctx = sim.ctx
     species = []
     for sp in wl["species"]:
@@ -335,7 +338,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "tets": len(wl["tets"]), "particles": n_total,
                    "mean_live_particles": round(mean_particles), "dt": wl["dt"], "beta": wl["beta"],
-                   "gamma": wl["gamma"], "cg_tol": 1e-10, "preconditioner": pc, "warm_start": args.warm_start,
+                   "gamma": wl["gamma"], "cg_tol": 1e-10, "preconditioner": pc, "walk": args.walk,
+                   "warm_start": args.warm_start,
                    "sort_period": args.sort_period, "inject_per_step": int(wl.get("inject_per_step") or 0) if inject else 0,
                    "inject_from": args.inject_from if inject else None,
                    "precision": ("fp32 push / fp64 deposit+solve" if precision == 0 else "all fp64"),

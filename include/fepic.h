@@ -79,6 +79,13 @@ enum { FEPIC_WS_PREV = 0, FEPIC_WS_EXTRAP1 = 1, FEPIC_WS_EXTRAP2 = 2, FEPIC_WS_M
  * several times fewer iterations once dt is well beyond the explicit limit. */
 enum { FEPIC_PC_JACOBI = 0, FEPIC_PC_AUX = 1 };
 
+/* How the particle step finishes paths that cross a face (Sec. III-C, Alg. 1): in a second
+ * kernel from a compacted queue of the crossing particles (FEPIC_WALK_QUEUE), or in place
+ * in the first kernel (FEPIC_WALK_FUSED: no queue traffic, idle lanes while others walk).
+ * FEPIC_WALK_AUTO takes the fused form when the last step had more than 0.5 crossings per
+ * particle.  Results agree to the rounding order of the current sums either way. */
+enum { FEPIC_WALK_AUTO = 0, FEPIC_WALK_QUEUE = 1, FEPIC_WALK_FUSED = 2 };
+
 typedef struct fepic_ctx fepic_ctx;
 
 typedef struct {
@@ -99,6 +106,7 @@ typedef struct {
     int aux_far_levels;/* FEPIC_PC_AUX aggregate levels beyond 64 nodes (512, 4096 nodes):
                           -1 (default) from dt: with tau^2 = mean beta dt^2 S_jj / M_jj,
                           the level of 2^k nodes when tau >= 2 * 2^(k/3); or 0, 1, 2       */
+    int walk;          /* FEPIC_WALK_* (default FEPIC_WALK_AUTO)                          */
 } fepic_options;
 
 typedef struct {

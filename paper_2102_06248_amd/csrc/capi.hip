@@ -278,7 +278,7 @@ void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
         if (ev) (void)hipEventRecord(ev[0], c->stream);
         launch_push<T>(c->stream, parr<T>(s, s.cur), parr<T>(s, 1 - s.cur), s.n, (const TetBlock<T>*)c->d_blk,
                        c->d_dgn, pp, c->d_cnt_slots, s.sorted_pending ? s.d_nlive : nullptr, cqueue<T>(c),
-                       c->cross_share);
+                       c->cross_share, c->opt.walk);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
     launch_cnt_finish(c->stream, c->d_cnt_slots, c->d_cnt);
@@ -738,6 +738,7 @@ void fepic_default_options(fepic_options* o) {
     o->timing = 0;
     o->preconditioner = FEPIC_PC_AUX;
     o->aux_far_levels = -1;
+    o->walk = FEPIC_WALK_AUTO;
 }
 
 const char* fepic_error_string(int code) {
@@ -769,6 +770,7 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
     if (o.warm_start < FEPIC_WS_PREV || o.warm_start > FEPIC_WS_MLP) return FEPIC_E_ARG;
     if (o.preconditioner != FEPIC_PC_JACOBI && o.preconditioner != FEPIC_PC_AUX) return FEPIC_E_ARG;
     if (o.aux_far_levels < -1 || o.aux_far_levels > 2) return FEPIC_E_ARG;
+    if (o.walk < FEPIC_WALK_AUTO || o.walk > FEPIC_WALK_FUSED) return FEPIC_E_ARG;
     if (o.cg_check_every < 1) o.cg_check_every = 8;
     fepic_ctx* c = new fepic_ctx();
     c->opt = o;

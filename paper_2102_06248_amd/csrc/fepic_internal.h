@@ -165,7 +165,8 @@ void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double*
                   const double* grad64, const int32_t* tet_edges, const int32_t* tet_faces);
 template <typename T>
 void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const TetBlock<T>* blk, double* dg,
-                 PushParams pp, PushCounters* cnt, const int32_t* n_live, CrossQueue<T> cq, double cross_share);
+                 PushParams pp, PushCounters* cnt, const int32_t* n_live, CrossQueue<T> cq, double cross_share,
+                 int walk);
 void launch_cnt_finish(hipStream_t s, PushCounters* slots, PushCounters* out);
 template <typename T>
 void launch_locate(hipStream_t s, int64_t n, const double* x, const double* u, const int64_t* id, int64_t id_base,

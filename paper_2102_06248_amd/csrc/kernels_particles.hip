@@ -184,17 +184,134 @@ __device__ __forceinline__ void add_counters(unsigned int sc, unsigned int mc, u
     }
 }
 
+// Per-workgroup accumulation of edge currents in LDS: an open-addressed table of 2^kBits
+// slots keyed by edge id (linear probing, insertion by compare-and-swap), flushed with one
+// FP64 global atomic per distinct edge.  An insert that finds no slot within kProbe steps
+// goes to global memory directly.
+constexpr int kProbe = 16;
+
+// The six edge currents of one piece: the first probe of all six keys is issued at once
+// (independent compare-and-swaps), so one LDS round trip serves the common case; keys
+// whose first slot holds another edge continue with lds_add's probing.
+template <int kBits>
+__device__ __forceinline__ void lds_add6(int* s_key, double* s_val, double* __restrict__ dg, const int32_t* e,
+                                         const double v[6]) {
+    int key[6], got[6];
+    unsigned int h[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        key[c] = e[c];
+        h[c] = ((unsigned int)key[c] * 2654435761u) >> (32 - kBits);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) got[c] = (v[c] != 0.0) ? atomicCAS(s_key + h[c], -1, key[c]) : key[c];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        if (v[c] == 0.0) continue;
+        if (got[c] == -1 || got[c] == key[c]) {
+            __hip_atomic_fetch_add(s_val + h[c], v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            // probe on from the next slot
+            unsigned int hh = (h[c] + 1) & ((1u << kBits) - 1u);
+            bool placed = false;
+            for (int p = 1; p < kProbe && !placed; ++p) {
+                const int k = atomicCAS(s_key + hh, -1, key[c]);
+                if (k == -1 || k == key[c]) {
+                    __hip_atomic_fetch_add(s_val + hh, v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    placed = true;
+                }
+                hh = (hh + 1) & ((1u << kBits) - 1u);
+            }
+            if (!placed) atomic_add_f64(dg + key[c], v[c]);
+        }
+    }
+}
+
+constexpr int log2_const(int v) { return v <= 1 ? 0 : 1 + log2_const(v / 2); }
+
+// The rest of one particle's path after its first face crossing: from barycentric ls in
+// tet t (entered through local face `entry`) with the remaining fraction frac of the
+// displacement dx, tet by tet up to the end point or a wall, each piece's current into the
+// workgroup's LDS table.  nc counts the particle's crossings (1 on entry); na and ncap
+// count an absorption and a stop at the crossing cap.
+template <typename T, int kBits>
+__device__ __forceinline__ void walk_rest(PArrays<T>& out, int64_t i, int t, int entry, double ls[4], double frac,
+                                          const T dx[3], const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
+                                          const PushParams& pp, int* s_key, double* s_val, unsigned int& nc,
+                                          unsigned int& na, unsigned int& ncap) {
+    const TetBlock<T>* bp = blk + t;
+    T g[4][3];
+    load_grads(bp, g);
+    double dl[4];
+    path_step(g, dx, frac, dl);
+    nc = 1;
+    for (;;) {
+        double best;
+        int kb;
+        exit_search(ls, dl, entry, best, kb);
+        double le[4], cur[6];
+        if (kb < 0) {
+            T rr[3];
+            end_point(ls, dl, rr, le);
+            piece_current(pp.qw, ls, le, cur);
+            lds_add6<kBits>(s_key, s_val, dg, bp->edge, cur);
+            out.tet[i] = t;
+            out.l1[i] = rr[0];
+            out.l2[i] = rr[1];
+            out.l3[i] = rr[2];
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) le[k] = (k == kb) ? 0.0 : ls[k] + best * dl[k];
+        piece_current(pp.qw, ls, le, cur);
+        lds_add6<kBits>(s_key, s_val, dg, bp->edge, cur);
+        const int nb = bp->nbr[kb];
+        if (nb < 0) {
+            ++na;
+            out.tet[i] = -1;
+            return;
+        }
+        if (++nc > (unsigned)pp.cap) {
+            ++ncap;
+            out.tet[i] = -1;
+            return;
+        }
+        const int q = nb & 3;
+        double ln[4];
+        enter_neighbour(le, kb, q, ln);
+        frac *= (1.0 - best);
+        t = nb >> 2;
+        bp = blk + t;
+        load_grads(bp, g);
+        path_step(g, dx, frac, dl);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ls[k] = ln[k];
+        entry = q;
+    }
+}
+
 // The particle step, first piece: gather E and B in the particle's tet, relativistic
 // Boris, and the straight path up to its first face crossing (or its end).  Particles
 // whose path continues into a neighbour are compacted, per workgroup, into the crossing
 // queue (slots blockIdx * kBlock + rank, count in wg_count) and finished by k_cross; their
 // u and id are final here.  First-piece currents are summed over runs of lanes that share
 // a tet (the particles are sorted by tet) before the FP64 atomics.
-template <typename T>
+template <typename T, bool kFused>
 __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, int64_t n,
                                                   const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
                                                   PushParams pp, PushCounters* __restrict__ cnt,
                                                   const int32_t* __restrict__ n_live, CrossQueue<T> cq) {
+    constexpr int kBits = log2_const(8 * kBlock);
+    constexpr int kSlots = kFused ? (1 << kBits) : 1;
+    __shared__ int s_key[kSlots];
+    __shared__ double s_val[kSlots];
+    if (kFused) {
+        for (int k = threadIdx.x; k < kSlots; k += kBlock) {
+            s_key[k] = -1;
+            s_val[k] = 0.0;
+        }
+        __syncthreads();
+    }
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     if (n_live) n = min(n, (int64_t)*n_live);
@@ -313,6 +430,18 @@ __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, 
         }
     }
 
+    if (kFused) {
+        // the rest of every crossing path here, currents through the LDS table
+        unsigned int nc = 0, na = 0, ncap = 0;
+        if (cross) walk_rest<T, kBits>(out, i, tn, q, ln, frac, dx, blk, dg, pp, s_key, s_val, nc, na, ncap);
+        __syncthreads();
+        for (int k = threadIdx.x; k < kSlots; k += kBlock)
+            if (s_key[k] >= 0) atomic_add_f64(dg + s_key[k], s_val[k]);
+        const unsigned int c1 = (cross || status == 2) ? 1u : 0u;
+        const unsigned int sc = cross ? nc : c1;
+        add_counters(sc, sc, (status == 1) + na, (status == 2) + ncap, cnt);
+        return;
+    }
     // compact the crossing lanes of the workgroup into its queue region
     {
         __shared__ int s_wc[kBlock / 64];
@@ -347,50 +476,6 @@ __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, 
     add_counters(c1, c1, status == 1, status == 2, cnt);
 }
 
-// Per-workgroup accumulation of edge currents in LDS: an open-addressed table of 2^kBits
-// slots keyed by edge id (linear probing, insertion by compare-and-swap), flushed with one
-// FP64 global atomic per distinct edge.  An insert that finds no slot within kProbe steps
-// goes to global memory directly.
-constexpr int kProbe = 16;
-
-// The six edge currents of one piece: the first probe of all six keys is issued at once
-// (independent compare-and-swaps), so one LDS round trip serves the common case; keys
-// whose first slot holds another edge continue with lds_add's probing.
-template <int kBits>
-__device__ __forceinline__ void lds_add6(int* s_key, double* s_val, double* __restrict__ dg, const int32_t* e,
-                                         const double v[6]) {
-    int key[6], got[6];
-    unsigned int h[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        key[c] = e[c];
-        h[c] = ((unsigned int)key[c] * 2654435761u) >> (32 - kBits);
-    }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) got[c] = (v[c] != 0.0) ? atomicCAS(s_key + h[c], -1, key[c]) : key[c];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        if (v[c] == 0.0) continue;
-        if (got[c] == -1 || got[c] == key[c]) {
-            __hip_atomic_fetch_add(s_val + h[c], v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        } else {
-            // probe on from the next slot
-            unsigned int hh = (h[c] + 1) & ((1u << kBits) - 1u);
-            bool placed = false;
-            for (int p = 1; p < kProbe && !placed; ++p) {
-                const int k = atomicCAS(s_key + hh, -1, key[c]);
-                if (k == -1 || k == key[c]) {
-                    __hip_atomic_fetch_add(s_val + hh, v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    placed = true;
-                }
-                hh = (hh + 1) & ((1u << kBits) - 1u);
-            }
-            if (!placed) atomic_add_f64(dg + key[c], v[c]);
-        }
-    }
-}
-
-constexpr int log2_const(int v) { return v <= 1 ? 0 : 1 + log2_const(v / 2); }
 
 // The rest of the paths that crossed a face in k_push: workgroup b takes the queue region
 // of k_push workgroup b (up to 256 particles) with kB threads and walks each particle tet
@@ -415,59 +500,11 @@ __global__ __launch_bounds__(kB) void k_cross(PArrays<T> out, CrossQueue<T> cq, 
     for (int j = threadIdx.x; j < total; j += kB) {
         const int64_t slot = (int64_t)blockIdx.x * kBlock + j;
         const int64_t i = cq.idx[slot];
-        int t = cq.tet[slot], entry = cq.entry[slot];
         double ls[4] = {cq.l0[slot], cq.l1[slot], cq.l2[slot], cq.l3[slot]};
-        double frac = cq.frac[slot];
         const T dx[3] = {cq.dx0[slot], cq.dx1[slot], cq.dx2[slot]};
-        const TetBlock<T>* bp = blk + t;
-        T g[4][3];
-        load_grads(bp, g);
-        double dl[4];
-        path_step(g, dx, frac, dl);
-        unsigned int nc = 1;   // crossings of this particle in this step
-        for (;;) {
-            double best;
-            int kb;
-            exit_search(ls, dl, entry, best, kb);
-            double le[4], cur[6];
-            if (kb < 0) {
-                T rr[3];
-                end_point(ls, dl, rr, le);
-                piece_current(pp.qw, ls, le, cur);
-                lds_add6<kBits>(s_key, s_val, dg, bp->edge, cur);
-                out.tet[i] = t;
-                out.l1[i] = rr[0];
-                out.l2[i] = rr[1];
-                out.l3[i] = rr[2];
-                break;
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) le[k] = (k == kb) ? 0.0 : ls[k] + best * dl[k];
-            piece_current(pp.qw, ls, le, cur);
-            lds_add6<kBits>(s_key, s_val, dg, bp->edge, cur);
-            const int nb = bp->nbr[kb];
-            if (nb < 0) {
-                ++na;
-                out.tet[i] = -1;
-                break;
-            }
-            if (++nc > (unsigned)pp.cap) {
-                ++ncap;
-                out.tet[i] = -1;
-                break;
-            }
-            const int q = nb & 3;
-            double ln[4];
-            enter_neighbour(le, kb, q, ln);
-            frac *= (1.0 - best);
-            t = nb >> 2;
-            bp = blk + t;
-            load_grads(bp, g);
-            path_step(g, dx, frac, dl);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) ls[k] = ln[k];
-            entry = q;
-        }
+        unsigned int nc = 0;
+        walk_rest<T, kBits>(out, i, cq.tet[slot], cq.entry[slot], ls, cq.frac[slot], dx, blk, dg, pp, s_key, s_val, nc,
+                            na, ncap);
         sc += nc - 1;
         mc = max(mc, nc);
     }
@@ -809,12 +846,22 @@ void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double*
                        tet_edges, tet_faces);
 }
 
+// Crossings per particle (last step) above which the particle step is one kernel.
+constexpr double kFuseShare = 0.5;
+
 template <typename T>
 void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const TetBlock<T>* blk, double* dg,
-                 PushParams pp, PushCounters* cnt, const int32_t* n_live, CrossQueue<T> cq, double cross_share) {
+                 PushParams pp, PushCounters* cnt, const int32_t* n_live, CrossQueue<T> cq, double cross_share,
+                 int walk) {
     if (n <= 0) return;
     const unsigned n_wg = (unsigned)grid_1d(n, kBlock);
-    hipLaunchKernelGGL(k_push<T>, dim3(n_wg), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live, cq);
+    if (walk == FEPIC_WALK_FUSED || (walk == FEPIC_WALK_AUTO && cross_share > kFuseShare)) {
+        // most paths cross: finishing them in place costs less idle lanes than the queue
+        // costs bytes (64 B written and read back per crossing particle)
+        hipLaunchKernelGGL((k_push<T, true>), dim3(n_wg), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live, cq);
+        return;
+    }
+    hipLaunchKernelGGL((k_push<T, false>), dim3(n_wg), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live, cq);
     // one k_cross workgroup per k_push workgroup, sized for its expected queue length
     if (cross_share <= 0.25)
         hipLaunchKernelGGL((k_cross<T, 64>), dim3(n_wg), dim3(64), 0, s, out, cq, blk, dg, pp, cnt);
@@ -859,7 +906,7 @@ void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, dou
     template void launch_stage<T>(hipStream_t, int64_t, TetBlock<T>*, const double*, const double*,             \
                                   const double*, const int32_t*, const int32_t*);                                \
     template void launch_push<T>(hipStream_t, PArrays<T>, PArrays<T>, int64_t, const TetBlock<T>*, double*,      \
-                                 PushParams, PushCounters*, const int32_t*, CrossQueue<T>, double);              \
+                                 PushParams, PushCounters*, const int32_t*, CrossQueue<T>, double, int);         \
     template void launch_locate<T>(hipStream_t, int64_t, const double*, const double*, const int64_t*, int64_t,  \
                                    PArrays<T>, int64_t, const double*, const double*, const int32_t*,            \
                                    const int32_t*, const double*, const double*, const int32_t*, PushCounters*); \

@@ -20,6 +20,7 @@ FEPIC_OK = 0
 FEPIC_FP32_PUSH_FP64_ACC, FEPIC_ALL_FP64 = 0, 1
 FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP = 0, 1, 2, 3
 FEPIC_PC_JACOBI, FEPIC_PC_AUX = 0, 1
+FEPIC_WALK_AUTO, FEPIC_WALK_QUEUE, FEPIC_WALK_FUSED = 0, 1, 2
 FEPIC_E_CG_NOT_CONVERGED = -6
 FEPIC_E_CROSSING_CAP = -7
 FEPIC_MLP_N_PARAMS = 4545
@@ -32,7 +33,8 @@ class fepic_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("precision", ctypes.c_int), ("cg_tol", ctypes.c_double),
                 ("cg_max_iters", ctypes.c_int), ("cg_check_every", ctypes.c_int), ("sort_period", ctypes.c_int),
                 ("crossing_cap", ctypes.c_int), ("warm_start", ctypes.c_int), ("diagnostics", ctypes.c_int),
-                ("timing", ctypes.c_int), ("preconditioner", ctypes.c_int), ("aux_far_levels", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("preconditioner", ctypes.c_int), ("aux_far_levels", ctypes.c_int),
+                ("walk", ctypes.c_int)]
 
 
 class fepic_step_stats(ctypes.Structure):

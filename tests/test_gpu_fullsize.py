@@ -110,8 +110,10 @@ def test_plasma_full_size_sampled(F):
     osim = OracleSim(wl["xyz"], wl["tets"])
     m = osim.mesh
     h = np.linalg.norm(m.xyz[m.edges[:, 1]] - m.xyz[m.edges[:, 0]], axis=1).min()
+    # the first step has no crossing history: take the queue form the plasma's 15 % share
+    # of crossing particles selects from the second step on
     L = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=wl["precision"], warm_start=F.FEPIC_WS_PREV,
-                     sort_period=1)
+                     sort_period=1, walk=F.FEPIC_WALK_QUEUE)
     try:
         sps, sos = [], []
         for sp in wl["species"]:

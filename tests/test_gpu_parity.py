@@ -34,9 +34,12 @@ def _lib_sim(F, xyz, tets, **opts):
 
 
 # ----------------------------------------------------------------------------- one push
-@pytest.mark.parametrize("precision,n", [(1, 4099), (0, 4099), (0, 70001)])
-def test_particle_step_vs_oracle(F, precision, n):
-    announce(f"particle step precision={precision} n={n}")
+@pytest.mark.parametrize("precision,n,walk", [(1, 4099, "queue"), (1, 4099, "fused"), (0, 4099, "queue"),
+                                              (0, 4099, "fused"), (0, 70001, "queue"), (0, 70001, "fused")])
+def test_particle_step_vs_oracle(F, precision, n, walk):
+    """One particle step against the oracle, with the crossing paths finished from the
+    queue by a second kernel or in place by the first."""
+    announce(f"particle step precision={precision} n={n} walk={walk}")
     xyz, tets, h = jittered_kuhn(6)
     osim = OracleSim(xyz, tets)
     e, b = divfree_fields(osim, 50.0, 1e-4, [0.0, 0.0, 0.002], seed=1)
@@ -46,7 +49,8 @@ def test_particle_step_vs_oracle(F, precision, n):
     assert osim.upload_particles(s, x, u, ids=np.arange(n)) == 0
     osim.e, osim.b = e.copy(), b.copy()
     dt = 2e-8
-    with _lib_sim(F, xyz, tets, precision=precision) as L:
+    mode = F.FEPIC_WALK_QUEUE if walk == "queue" else F.FEPIC_WALK_FUSED
+    with _lib_sim(F, xyz, tets, precision=precision, walk=mode) as L:
         F.fepic_set_fields(L.ctx, e=e, e_prev=e, b=b)
         sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 1e3)
         assert F.fepic_upload_particles(L.ctx, sp, x, u, ids=np.arange(n)) == 0
