@@ -1,11 +1,13 @@
 // Particle-side kernels for gfx950: per-tet field staging, the particle step (gather ->
-// relativistic Boris -> straight-path tracking -> Whitney-1 deposit) as a first-piece
-// kernel for every particle plus a kernel for the compacted face-crossing paths, point
-// location, counting sort by tet, nodal charge, energies.
+// relativistic Boris -> straight-path tracking -> Whitney-1 deposit) as one kernel, or as a
+// first-piece kernel for every particle plus a kernel for the compacted face-crossing
+// paths when few particles cross, point location, counting sort by tet, nodal charge,
+// energies.
 //
 // Wave64 throughout; particles are kept sorted by tet so that lanes of a wave read the
 // same 128-byte tet record and the current of their first path piece can be summed
-// across the wave before the FP64 atomics.
+// across the wave; per-workgroup LDS tables then merge the currents per edge before the
+// FP64 atomics.
 #include <algorithm>
 
 #include "fepic_internal.h"
@@ -229,6 +231,13 @@ __device__ __forceinline__ void lds_add6(int* s_key, double* s_val, double* __re
 
 constexpr int log2_const(int v) { return v <= 1 ? 0 : 1 + log2_const(v / 2); }
 
+// One FP64 atomic per occupied slot of the table (after a barrier).
+template <int kSlots, int kB>
+__device__ __forceinline__ void flush_table(const int* s_key, const double* s_val, double* __restrict__ dg) {
+    for (int k = threadIdx.x; k < kSlots; k += kB)
+        if (s_key[k] >= 0) atomic_add_f64(dg + s_key[k], s_val[k]);
+}
+
 // The rest of one particle's path after its first face crossing: from barycentric ls in
 // tet t (entered through local face `entry`) with the remaining fraction frac of the
 // displacement dx, tet by tet up to the end point or a wall, each piece's current into the
@@ -290,17 +299,21 @@ __device__ __forceinline__ void walk_rest(PArrays<T>& out, int64_t i, int t, int
     }
 }
 
-// The particle step, first piece: gather E and B in the particle's tet, relativistic
-// Boris, and the straight path up to its first face crossing (or its end).  Particles
-// whose path continues into a neighbour are compacted, per workgroup, into the crossing
-// queue (slots blockIdx * kBlock + rank, count in wg_count) and finished by k_cross; their
-// u and id are final here.  First-piece currents are summed over runs of lanes that share
-// a tet (the particles are sorted by tet) before the FP64 atomics.
+// The particle step: gather E and B in the particle's tet, relativistic Boris, and the
+// straight path up to its first face crossing (or its end).  With kFused the crossing
+// paths are walked to their end here; otherwise they are compacted, per workgroup, into
+// the crossing queue (slots blockIdx * kBlock + rank, count in wg_count) and finished by
+// k_cross, their u and id being final here.  First-piece currents are summed over runs of
+// lanes that share a tet (the particles are sorted by tet); in the fused form the run sums
+// and walk pieces go through the workgroup's LDS table, flushed with one FP64 atomic per
+// edge, in the queue form each run adds its six sums with FP64 atomics.
 template <typename T, bool kFused>
 __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, int64_t n,
                                                   const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
                                                   PushParams pp, PushCounters* __restrict__ cnt,
                                                   const int32_t* __restrict__ n_live, CrossQueue<T> cq) {
+    // the LDS table of the fused form (the queue form leaves it to k_cross: its 24 KB
+    // would cost the first kernel occupancy)
     constexpr int kBits = log2_const(8 * kBlock);
     constexpr int kSlots = kFused ? (1 << kBits) : 1;
     __shared__ int s_key[kSlots];
@@ -403,7 +416,9 @@ __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, 
         out.tet[i] = -1;
     }
 
-    // first-piece currents: one sum and six atomics per run of lanes sharing a tet
+    // first-piece currents: one sum per run of lanes sharing a tet, added by the run's last
+    // lane (fused form: into the workgroup's LDS table, where runs of neighbouring tets and
+    // the walks share edges; queue form: six FP64 atomics)
     {
         const int key = t0;
         const int prev_key = __shfl_up(key, 1);
@@ -424,9 +439,13 @@ __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, 
         }
         const int next_key = __shfl_down(key, 1);
         if (key >= 0 && (lane == 63 || next_key != key)) {
-            const TetBlock<T>* bk = blk + key;
+            if (kFused) {
+                lds_add6<kBits>(s_key, s_val, dg, blk[key].edge, first);
+            } else {
+                const TetBlock<T>* bk = blk + key;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) atomic_add_f64(dg + bk->edge[c], first[c]);
+                for (int c = 0; c < 6; ++c) atomic_add_f64(dg + bk->edge[c], first[c]);
+            }
         }
     }
 
@@ -435,8 +454,7 @@ __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, 
         unsigned int nc = 0, na = 0, ncap = 0;
         if (cross) walk_rest<T, kBits>(out, i, tn, q, ln, frac, dx, blk, dg, pp, s_key, s_val, nc, na, ncap);
         __syncthreads();
-        for (int k = threadIdx.x; k < kSlots; k += kBlock)
-            if (s_key[k] >= 0) atomic_add_f64(dg + s_key[k], s_val[k]);
+        flush_table<kSlots, kBlock>(s_key, s_val, dg);
         const unsigned int c1 = (cross || status == 2) ? 1u : 0u;
         const unsigned int sc = cross ? nc : c1;
         add_counters(sc, sc, (status == 1) + na, (status == 2) + ncap, cnt);
@@ -509,8 +527,7 @@ __global__ __launch_bounds__(kB) void k_cross(PArrays<T> out, CrossQueue<T> cq, 
         mc = max(mc, nc);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kSlots; k += kB)
-        if (s_key[k] >= 0) atomic_add_f64(dg + s_key[k], s_val[k]);
+    flush_table<kSlots, kB>(s_key, s_val, dg);
     add_counters<kB>(sc, mc, na, ncap, cnt);
 }
 
