@@ -153,7 +153,8 @@ def main():
                     help="mlp: plain steps recorded for training before the warm-up steps")
     ap.add_argument("--diagnostics", action="store_true",
                     help="run the conservation diagnostics every step (continuity, Gauss drift)")
-    ap.add_argument("--sort-period", type=int, default=1)
+    ap.add_argument("--sort-period", type=int, default=None,
+                    help="re-sort particles by tet every this many steps (default: the workload's)")
     ap.add_argument("--walk", default="auto", choices=["auto", "queue", "fused"],
                     help="crossing paths: chosen from the last step's crossings, queue + second kernel, or in place")
     ap.add_argument("--preconditioner", default="aux", choices=["aux", "jacobi"],
@@ -189,8 +190,9 @@ def main():
           "mlp": F.FEPIC_WS_PREV}[args.warm_start]
     precision = {"auto": wl["precision"], "fp32": 0, "fp64": 1}[args.precision]
     pc = args.preconditioner
+    sort_period = args.sort_period if args.sort_period is not None else wl.get("sort_period", 1)
     sim = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=precision, warm_start=ws,
-                       sort_period=args.sort_period, timing=1, diagnostics=1 if args.diagnostics else 0,
+                       sort_period=sort_period, timing=1, diagnostics=1 if args.diagnostics else 0,
                        preconditioner=F.FEPIC_PC_AUX if pc == "aux" else F.FEPIC_PC_JACOBI,
                        walk={"auto": F.FEPIC_WALK_AUTO, "queue": F.FEPIC_WALK_QUEUE, "fused": F.FEPIC_WALK_FUSED}[args.walk])
     ctx = sim.ctx
@@ -340,7 +342,7 @@ def main():
                    "mean_live_particles": round(mean_particles), "dt": wl["dt"], "beta": wl["beta"],
                    "gamma": wl["gamma"], "cg_tol": 1e-10, "preconditioner": pc, "walk": args.walk,
                    "warm_start": args.warm_start,
-                   "sort_period": args.sort_period, "inject_per_step": int(wl.get("inject_per_step") or 0) if inject else 0,
+                   "sort_period": sort_period, "inject_per_step": int(wl.get("inject_per_step") or 0) if inject else 0,
                    "inject_from": args.inject_from if inject else None,
                    "precision": ("fp32 push / fp64 deposit+solve" if precision == 0 else "all fp64"),
                    "diagnostics_in_timed_steps": bool(args.diagnostics), "parallelism": "single GPU"},

@@ -36,7 +36,8 @@ def c2_beam(n_particles=1_000_000, seed=0, n_rings=12, n_layers=78):
     12 rings x 78 layers = 202,176 tets); macro-particles uniform on the disk r <= 0.01 m,
     filling z in [0, 0.5) (the steady state of a 0.25 A beam injected at z = 0), 1 keV drift
     along z with a 1 eV Gaussian thermal spread; dt = 1e-10 s; weight from the injection
-    rate of 3,750 macro-particles per step carrying 0.25 A."""
+    rate of 3,750 macro-particles per step carrying 0.25 A.  The beam drifts as a whole,
+    so particles sorted by tet stay nearly sorted: re-sorting every 4th step is enough."""
     xyz, tets = inputs.prism_cylinder(0.05, 0.5, n_rings, n_layers)
     dt = 1e-10
     per_step = 3750
@@ -44,7 +45,7 @@ def c2_beam(n_particles=1_000_000, seed=0, n_rings=12, n_layers=78):
     x, u = inputs.beam_particles(n_particles, 0.01, 0.0, 0.5, 1000.0, 1.0, M_E, seed)
     return dict(name="c2_beam", xyz=xyz, tets=tets, B0=None,
                 species=[dict(q=-E_CHARGE, m=M_E, w=w, x=x, u=u)], dt=dt, beta=0.25, gamma=0.5,
-                inject_per_step=per_step, precision=0)
+                inject_per_step=per_step, precision=0, sort_period=4)
 
 
 def c2_injection_batch(step, seed=0, per_step=3750):

@@ -1,7 +1,9 @@
 """GPU parity at full size: the electron-beam workload (202,176-tet PEC cylinder, 1M
 macro-particles, 3,750 injected per step, dt = 1e-10 s) in the launch configuration the
-benchmark times (FP32 push / FP64 deposit, sort every step, warm start from e^n), against
-the FP64 oracle fed the same seeded inputs.
+benchmark times (FP32 push / FP64 deposit, the workload's sort period of 4 steps, so one
+step from sorted and one from unsorted particles, crossing paths finished in the first
+kernel, auxiliary-space PCG, warm start from e^n), against the FP64 oracle fed the same
+seeded inputs.
 
 The oracle finishes a whole step of this size in seconds, so every particle, every edge
 and face DoF is compared, with the tolerances of the small parity tests (positions within
@@ -44,7 +46,7 @@ def test_beam_full_size_two_steps(F):
     osim.init_electrostatic(tol=1e-13)
 
     L = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=wl["precision"], warm_start=F.FEPIC_WS_PREV,
-                     sort_period=1)
+                     sort_period=wl["sort_period"])
     try:
         s = F.fepic_add_species(L.ctx, sp["q"], sp["m"], sp["w"])
         assert F.fepic_upload_particles(L.ctx, s, sp["x"], sp["u"], ids=ids) == 0
