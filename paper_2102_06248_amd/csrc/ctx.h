@@ -76,7 +76,7 @@ struct fepic_ctx {
     double *d_b = nullptr, *d_bn = nullptr;
     double *d_rhs = nullptr, *d_rt = nullptr, *d_Me = nullptr;
     fepic::CgVec* d_cgv[2] = {nullptr, nullptr};   // Jacobi-PCG state, double buffered
-    // auxiliary-space PCG: (z, p) pairs double buffered, (r, q) pairs, nodal arrays
+    // auxiliary-space PCG: (z, p) pairs double buffered, r and q (n_edges each), nodal arrays
     double2* d_zp[2] = {nullptr, nullptr};
     double2* d_rq = nullptr;
     fepic::AuxSpace aux;

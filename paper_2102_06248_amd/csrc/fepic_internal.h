@@ -202,7 +202,8 @@ void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* slice_p
                     CgScalars* sc);
 void launch_cg_rr0(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc);
 // PCG with the nodal auxiliary-space preconditioner: per row z = B r with the previous
-// search direction p (zp, double buffered) and r with q = A p (rq).
+// search direction p (zp, double buffered), and r and q = A p as two arrays of n_rows
+// doubles in rq (r first; each written whole by one kernel).
 void launch_aux_scale(hipStream_t s, const AuxSpace& g, const int64_t* slice_ptr, const int32_t* col,
                       const double* A);
 void launch_pcg_init(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* A,

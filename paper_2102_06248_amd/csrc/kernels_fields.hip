@@ -627,7 +627,8 @@ __device__ __forceinline__ double* far_line(const AuxSpace& g, int L, int64_t a,
 __global__ __launch_bounds__(kBlock) void k_pcg_init(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
                                                       const int32_t* __restrict__ col, const double* __restrict__ A,
                                                       const double* __restrict__ b, const double* __restrict__ x,
-                                                      double2* __restrict__ RQ, const double* __restrict__ part_rhs,
+                                                      double* __restrict__ R, double* __restrict__ Q,
+                                                      const double* __restrict__ part_rhs,
                                                       double* cg_slots, CgScalars* sc, double tol, AuxSpace g) {
     double bb[1];
     read_partials<1>(part_rhs, gridDim.x, bb);
@@ -644,7 +645,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(int64_t n_rows, RowGrid rg,
         const int64_t row = lb * kBlock + threadIdx.x;
         if (((row >> 6) << 6) >= n_rows) continue;
         const double ax = sell_row(sp, col, A, row, [&](int c) { return x[c]; });
-        if (row < n_rows) RQ[row] = make_double2(b[row] - ax, 0.0);
+        if (row < n_rows) {
+            R[row] = b[row] - ax;
+            Q[row] = 0.0;
+        }
     }
 }
 
@@ -694,12 +698,12 @@ __device__ __forceinline__ void q_part(QPart& P, const int64_t* __restrict__ sp,
 }
 
 // The convergence test of iterate i (its (r, r) from reduction 2i - 1), beta, the new
-// direction p (into ZPn, the other buffer) and q = A p; (p, q) into reduction 2i.
+// direction p = z + beta p and q = A p (only q is stored: the update kernel forms the same
+// p from the same operands); (p, q) into reduction 2i.
 __global__ __launch_bounds__(kBlock) void k_pcg_q(int64_t n_rows, RowGrid rg, int i, const int64_t* __restrict__ sp,
                                                    const int32_t* __restrict__ col, const double* __restrict__ A,
-                                                   const double2* __restrict__ ZP, double2* __restrict__ ZPn,
-                                                   double2* __restrict__ RQ, double* __restrict__ cg_slots,
-                                                   CgScalars* sc, AuxSpace aux) {
+                                                   const double2* __restrict__ ZP, double* __restrict__ Q,
+                                                   double* __restrict__ cg_slots, CgScalars* sc, AuxSpace aux) {
     const int conv = sc->converged;
     double t[2];
     slot_load<2>(red_buf(cg_slots, 2 * i - 1), t);
@@ -726,14 +730,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_q(int64_t n_rows, RowGrid rg, in
     if (done || bad) return;
     if (blockIdx.x == 0) clear_far(aux);   // read by the previous update, added to by the next node pass
     double v[1] = {0.0};
-    double* pn = reinterpret_cast<double*>(ZPn);
-    double* qn = reinterpret_cast<double*>(RQ);
     while (lb < le) {
         if (active && row < n_rows) {
             const double p = P.own.x + beta * P.own.y;
             const double q = P.sZ + beta * P.sP;
-            pn[2 * row + 1] = p;
-            qn[2 * row + 1] = q;
+            Q[row] = q;
             v[0] += p * q;
         }
         lb += rg.g;
@@ -751,7 +752,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_q(int64_t n_rows, RowGrid rg, in
 // the four partial sums meet in LDS.  Padding entries read edge 0 and count zero.
 constexpr int kNodePhases = kBlock / 64;
 
-__device__ __forceinline__ void node_part(double P[8], const AuxSpace& g, const double2* __restrict__ RQ, int64_t sl,
+__device__ __forceinline__ void node_part(double P[8], const AuxSpace& g, const double* __restrict__ R,
+                                          const double* __restrict__ Q, int64_t sl,
                                           int lane, int j) {
     const int64_t k0 = g.sp[sl] + lane, k1 = g.sp[sl + 1];
 #pragma unroll
@@ -764,7 +766,7 @@ __device__ __forceinline__ void node_part(double P[8], const AuxSpace& g, const 
             const int64_t kk = k + (int64_t)q * kNodePhases * 64;
             c[q] = kk < k1 ? g.inc[kk] : kAuxPad;
         }
-        double2 rq[U];
+        double rv[U], qv[U];
         float4 th[U];
         double s[U];
 #pragma unroll
@@ -772,12 +774,13 @@ __device__ __forceinline__ void node_part(double P[8], const AuxSpace& g, const 
             const bool ok = c[q] != kAuxPad;
             const int32_t e = ok ? (c[q] >= 0 ? c[q] : ~c[q]) : 0;
             s[q] = ok ? (c[q] >= 0 ? 1.0 : -1.0) : 0.0;
-            rq[q] = RQ[e];
+            rv[q] = R[e];
+            qv[q] = Q[e];
             th[q] = g.th[e];
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            const double r = s[q] != 0.0 ? rq[q].x : 0.0, qq = s[q] != 0.0 ? rq[q].y : 0.0;
+            const double r = s[q] != 0.0 ? rv[q] : 0.0, qq = s[q] != 0.0 ? qv[q] : 0.0;
             P[0] += s[q] * r;
             P[1] += s[q] * qq;
             P[2] += (double)th[q].x * r;
@@ -792,7 +795,8 @@ __device__ __forceinline__ void node_part(double P[8], const AuxSpace& g, const 
 
 // alpha from reduction 2i (i = -1: the start, alpha = 0); Y = (D_G^-1 G^T r', D_Pi^-1 Pi^T r').
 // rg runs over slices of 64 nodes.
-__global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpace g, const double2* __restrict__ RQ,
+__global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpace g, const double* __restrict__ R,
+                                                       const double* __restrict__ Q,
                                                        double* __restrict__ cg_slots, CgScalars* sc) {
     __shared__ double part[8][kNodePhases][64];
     const int conv = sc->converged;
@@ -803,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
     int64_t sl = rg_first(rg);
     const int64_t le = rg_end(rg);
     double P[8];
-    if (sl < le) node_part(P, g, RQ, sl, lane, j);
+    if (sl < le) node_part(P, g, R, Q, sl, lane, j);
     if (conv) return;
     double alpha = 0.0;
     if (i >= 0) {
@@ -859,13 +863,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
         }
         __syncthreads();
         sl += rg.g;
-        if (sl < le) node_part(P, g, RQ, sl, lane, j);
+        if (sl < le) node_part(P, g, R, Q, sl, lane, j);
     }
 }
 
 // A row's own values for the update.
 struct UPart {
-    double2 rq, zp;
+    double r, q;
+    double2 zp;
     double x, dinv;
     float4 th;
     double4 ya, yb;
@@ -873,8 +878,9 @@ struct UPart {
 
 __device__ __forceinline__ void u_part(UPart& P, const AuxSpace& g, const double* __restrict__ dinv,
                                        const double* __restrict__ x, const double2* __restrict__ ZP,
-                                       const double2* __restrict__ RQ, int64_t row) {
-    P.rq = RQ[row];
+                                       const double* __restrict__ R, const double* __restrict__ Q, int64_t row) {
+    P.r = R[row];
+    P.q = Q[row];
     P.zp = ZP[row];
     P.x = x[row];
     P.dinv = dinv[row];
@@ -904,11 +910,13 @@ __device__ __forceinline__ void u_part(UPart& P, const AuxSpace& g, const double
     }
 }
 
-// x += alpha p (not at the start), r' = r - alpha q, z = D^-1 r' + G y + Pi v; (r', z) and
-// (r', r') into reduction 2i + 1.  ZP here is the buffer k_pcg_q(i) wrote p into.
+// x += alpha p with p = z + beta p from the pair k_pcg_q(i) read (not at the start),
+// r' = r - alpha q, z' = D^-1 r' + G y + Pi v; the pair (z', p) into the other buffer;
+// (r', z') and (r', r') into reduction 2i + 1.
 __global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n_rows, RowGrid rg, int i, AuxSpace g,
                                                         const double* __restrict__ dinv, double* __restrict__ x,
-                                                        double2* __restrict__ ZP, double2* __restrict__ RQ,
+                                                        const double2* __restrict__ ZP, double2* __restrict__ ZPn,
+                                                        double* __restrict__ R, const double* __restrict__ Q,
                                                         double* __restrict__ cg_slots, CgScalars* sc) {
     const int conv = sc->converged;
     double t[1] = {0.0};
@@ -918,7 +926,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n_rows, RowGrid r
     UPart P;
     int64_t row = lb * kBlock + threadIdx.x;
     bool active = lb < le && row < n_rows;
-    if (active) u_part(P, g, dinv, x, ZP, RQ, row);
+    if (active) u_part(P, g, dinv, x, ZP, R, Q, row);
     if (conv) return;
     double alpha = 0.0;
     if (i >= 0) {
@@ -926,25 +934,26 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n_rows, RowGrid r
         alpha = sc->gam[i & 1] / t[0];
         if (!(alpha > 0.0 && alpha < INFINITY)) return;
     }
+    // beta of this iteration, from the same operands as in k_pcg_q (the same bits)
+    const double beta = (i <= 0) ? 0.0 : sc->gam[i & 1] / sc->gam[(i - 1) & 1];
     if (blockIdx.x == 0) clear_buf(red_buf(cg_slots, 2 * i + 2));
     double v[2] = {0.0, 0.0};
-    double* rn = reinterpret_cast<double*>(RQ);
     while (lb < le) {
         if (active) {
-            const double r = P.rq.x - alpha * P.rq.y;
-            const double p = i >= 0 ? P.zp.y : 0.0;
+            const double r = P.r - alpha * P.q;
+            const double p = i >= 0 ? P.zp.x + beta * P.zp.y : 0.0;
             if (i >= 0) x[row] = P.x + alpha * p;
             const double z = P.dinv * r + (P.yb.x - P.ya.x) + (double)P.th.x * (P.ya.y + P.yb.y) +
                              (double)P.th.y * (P.ya.z + P.yb.z) + (double)P.th.z * (P.ya.w + P.yb.w);
-            rn[2 * row] = r;
-            ZP[row] = make_double2(z, p);
+            R[row] = r;
+            ZPn[row] = make_double2(z, p);
             v[0] += r * z;
             v[1] += r * r;
         }
         lb += rg.g;
         row = lb * kBlock + threadIdx.x;
         active = lb < le && row < n_rows;
-        if (active) u_part(P, g, dinv, x, ZP, RQ, row);
+        if (active) u_part(P, g, dinv, x, ZP, R, Q, row);
     }
     block_sum_all<2>(v);
     slot_add<2>(red_buf(cg_slots, 2 * i + 1), v);
@@ -1203,16 +1212,19 @@ void launch_pcg_init(hipStream_t s, int64_t n_rows, const int64_t* sp, const int
                      double2* rq, double* partial, CgScalars* sc, double tol) {
     const RowGrid rg = row_grid(n_rows);
     double* slots = partial + SLOT_CG * kSlot;
-    hipLaunchKernelGGL(k_pcg_init, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, b, x, rq,
+    double* R = reinterpret_cast<double*>(rq);
+    double* Q = R + n_rows;
+    hipLaunchKernelGGL(k_pcg_init, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, b, x, R, Q,
                        partial + SLOT_RHS * kSlot, slots, sc, tol, g);
     const RowGrid ng = node_grid(g.n_aux);
-    hipLaunchKernelGGL(k_pcg_nodes, dim3(ng.grid), dim3(kBlock), 0, s, ng, -1, g, rq, slots, sc);
+    hipLaunchKernelGGL(k_pcg_nodes, dim3(ng.grid), dim3(kBlock), 0, s, ng, -1, g, R, Q, slots, sc);
     const RowGrid ug = row_grid_full(n_rows);
     hipLaunchKernelGGL(k_pcg_update, dim3(ug.grid), dim3(kBlock), 0, s, n_rows, ug, -1, g, dinv, const_cast<double*>(x),
-                       zp0, rq, slots, sc);
+                       zp0, zp0, R, Q, slots, sc);
 }
 
-// Iteration i: (z, p) pairs read from buffer i & 1, p and then z written to (i + 1) & 1.
+// Iteration i: (z, p) pairs read from buffer i & 1, the new pair written to (i + 1) & 1;
+// r in the first n_rows doubles of rq, q in the next n_rows.
 void launch_pcg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
                      const double* dinv, double* x, const AuxSpace& g, double2* const zp[2], double2* rq,
                      double* partial, CgScalars* sc) {
@@ -1220,11 +1232,12 @@ void launch_pcg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, co
     const RowGrid ng = node_grid(g.n_aux);
     double* slots = partial + SLOT_CG * kSlot;
     const int a = i & 1, b = 1 - a;
-    hipLaunchKernelGGL(k_pcg_q, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, zp[a], zp[b], rq, slots,
-                       sc, g);
-    hipLaunchKernelGGL(k_pcg_nodes, dim3(ng.grid), dim3(kBlock), 0, s, ng, i, g, rq, slots, sc);
-    hipLaunchKernelGGL(k_pcg_update, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, g, dinv, x, zp[b], rq, slots,
-                       sc);
+    double* R = reinterpret_cast<double*>(rq);
+    double* Q = R + n_rows;
+    hipLaunchKernelGGL(k_pcg_q, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, zp[a], Q, slots, sc, g);
+    hipLaunchKernelGGL(k_pcg_nodes, dim3(ng.grid), dim3(kBlock), 0, s, ng, i, g, R, Q, slots, sc);
+    hipLaunchKernelGGL(k_pcg_update, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, g, dinv, x, zp[a], zp[b], R, Q,
+                       slots, sc);
 }
 
 void launch_pcg_rr0(hipStream_t s, double* partial, CgScalars* sc) {
