@@ -52,11 +52,11 @@ def algorithmic_bytes(fam, geo, st, pc="aux"):
         return 12 * nnz + 80 * n_rows          # and written
     if fam == "cg_iter":
         # q = A p: A values + columns, (z, p) read, q written: 12 nnz + 24 per row;
-        # nodes: one 4 B incidence per interior edge end, r, q and the half edge vector per
-        # row (32), scale read and Y written per node (64);
-        # update: r, q, z, p, x, 1/A_jj, edge vector, ends read (72) and r, z, p, x written
+        # nodes: one 4 B incidence per interior edge end, r, q and the FP16 edge vector per
+        # row (24), scale read and Y written per node (64);
+        # update: r, q, z, p, x, 1/A_jj, edge vector, ends read (64) and r, z, p, x written
         # (32) per row, Y read per node (32)
-        return 12 * nnz + (24 + 32 + 104) * n_rows + 8 * geo["n_int_edges"] + 96 * geo["n_aux"]
+        return 12 * nnz + (24 + 24 + 96) * n_rows + 8 * geo["n_int_edges"] + 96 * geo["n_aux"]
     if fam == "rhs":          # M, S values + columns; e, e_prev, dG_new, dG_old read; b written
         return 20 * nnz + 40 * n_rows
     if fam == "push":         # particle state read + written (tet, 3 lambda, 3 u at 4 B);

@@ -926,14 +926,14 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
         c->s_over_m = cnt ? sum / (double)cnt : 0.0;
         int64_t *asp = nullptr;
         int32_t *ainc = nullptr, *aends = nullptr;
-        float* ath = nullptr;
+        EdgeVec* ath = nullptr;
         if ((rc = upload(c, &asp, m.aux_sp)) || (rc = upload(c, &ainc, m.aux_inc)) ||
             (rc = upload(c, &ath, m.aux_th)) || (rc = upload(c, &aends, m.aux_ends)))
             return rc;
         c->aux.n_aux = m.n_aux;
         c->aux.sp = asp;
         c->aux.inc = ainc;
-        c->aux.th = reinterpret_cast<const float4*>(ath);
+        c->aux.th = ath;
         c->aux.ends = reinterpret_cast<const int2*>(aends);
         c->aux.scale = dalloc<double4>(c, m.n_aux);
         c->aux.scale8 = dalloc<double4>(c, (m.n_aux + 7) / 8);

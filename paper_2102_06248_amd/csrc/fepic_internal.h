@@ -101,6 +101,13 @@ struct alignas(32) CgVec {
     double R, W, S, P;
 };
 
+// Half edge vector (r_head - r_tail) / 2 of the auxiliary space, divided by the mesh's
+// largest such component and rounded to FP16 (a constant factor on Pi cancels in
+// Pi diag(Pi^T A Pi)^-1 Pi^T, and every kernel uses the same rounded values).
+struct alignas(8) EdgeVec {
+    _Float16 x, y, z, w;
+};
+
 // Padding entry of the auxiliary space's node incidence lists (no edge).
 constexpr int32_t kAuxPad = INT32_MIN;
 // log2 of the aggregate sizes of the auxiliary space's levels beyond one node slice.
@@ -123,7 +130,7 @@ struct AuxSpace {
     int64_t n_aux = 0;            // interior nodes
     const int64_t* sp = nullptr;  // SELL-64 slice offsets of the node incidence lists
     const int32_t* inc = nullptr; // device edge id (node is its head) or ~id (tail); kAuxPad
-    const float4* th = nullptr;   // [n_edges] (r_head - r_tail) / 2, w unused; zero on wall edges
+    const EdgeVec* th = nullptr;  // [n_edges] scaled (r_head - r_tail) / 2; zero on wall edges
     const int2* ends = nullptr;   // [n_edges] auxiliary index of tail, head (n_aux: zero entry)
     double4* scale = nullptr;     // [n_aux] 1/diag(G^T A G), 1/diag(Pi^T A Pi) for x, y, z
     // the same for the aggregates of 8 and of 64 consecutive auxiliary nodes (the coarser

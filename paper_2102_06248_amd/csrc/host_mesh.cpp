@@ -104,12 +104,22 @@ void build_aux_space(HostMesh& m) {
         const int64_t s = a / kSell, l = a % kSell;
         for (int64_t k = 0; k < deg(v); ++k) m.aux_inc[m.aux_sp[s] + k * kSell + l] = code[start[v] + k];
     }
-    m.aux_th.assign(4 * ne, 0.0f);
+    double scale = 0.0;
+    for (int64_t d = 0; d < ne; ++d) {
+        if (m.dev_bedge[d]) continue;
+        const int32_t a = m.dev_edges[2 * d], b = m.dev_edges[2 * d + 1];
+        for (int k = 0; k < 3; ++k) scale = std::max(scale, std::fabs(0.5 * (m.xyz[3 * b + k] - m.xyz[3 * a + k])));
+    }
+    const double inv = scale > 0 ? 1.0 / scale : 1.0;
+    m.aux_th.assign(ne, EdgeVec{});
     m.aux_ends.assign(2 * ne, (int32_t)na);
     for (int64_t d = 0; d < ne; ++d) {
         if (m.dev_bedge[d]) continue;
         const int32_t a = m.dev_edges[2 * d], b = m.dev_edges[2 * d + 1];
-        for (int k = 0; k < 3; ++k) m.aux_th[4 * d + k] = (float)(0.5 * (m.xyz[3 * b + k] - m.xyz[3 * a + k]));
+        EdgeVec& t = m.aux_th[d];
+        t.x = (_Float16)(0.5 * (m.xyz[3 * b] - m.xyz[3 * a]) * inv);
+        t.y = (_Float16)(0.5 * (m.xyz[3 * b + 1] - m.xyz[3 * a + 1]) * inv);
+        t.z = (_Float16)(0.5 * (m.xyz[3 * b + 2] - m.xyz[3 * a + 2]) * inv);
         m.aux_ends[2 * d] = aux_of[a];
         m.aux_ends[2 * d + 1] = aux_of[b];
     }

@@ -45,7 +45,8 @@ struct HostMesh {
     std::vector<int64_t> aux_sp;      // SELL-64 slice offsets of the node incidence lists
     std::vector<int32_t> aux_inc;     // device edge id (node is its head) or ~id (its tail);
                                       // kAuxPad in padding
-    std::vector<float> aux_th;        // [n_edges][4] (r_head - r_tail) / 2; zero on wall edges
+    std::vector<EdgeVec> aux_th;      // [n_edges] (r_head - r_tail) / 2 over the largest
+                                      // component, FP16; zero on wall edges
     std::vector<int32_t> aux_ends;    // [n_edges][2] auxiliary index of tail, head; n_aux for
                                       // wall nodes (and both ends of wall edges)
     // point-location grid

@@ -479,6 +479,11 @@ __device__ __forceinline__ void clear_buf(double* buf) {
     for (int k = threadIdx.x; k < 3 * kCgSlots; k += kBlock) buf[k] = 0.0;
 }
 
+__device__ __forceinline__ double3 edge_vec(const AuxSpace& g, int64_t e) {
+    const EdgeVec t = g.th[e];
+    return make_double3((double)(float)t.x, (double)(float)t.y, (double)(float)t.z);
+}
+
 // Per node: D_G^-1 and D_Pi^-1 from the rows of A.  The pair (e, f) of the node's edges
 // contributes s_e A_ef s_f to diag G^T A G (s = +1 at an edge's head, -1 at its tail) and
 // th_e,d A_ef th_f,d to component d of diag Pi^T A Pi; f runs over row e's stored columns
@@ -495,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_aux_scale(AuxSpace g, const int64_t*
         if (c == kAuxPad) continue;
         const int32_t e = c >= 0 ? c : ~c;
         const double se = c >= 0 ? 1.0 : -1.0;
-        const float4 te = g.th[e];
+        const double3 te = edge_vec(g, e);
         const int64_t esl = e >> 6;
         const int el = e & 63;
         for (int64_t kk = sp[esl] + el; kk < sp[esl + 1]; kk += 64) {
@@ -504,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_aux_scale(AuxSpace g, const int64_t*
             const double sf = ef.y == n ? 1.0 : (ef.x == n ? -1.0 : 0.0);
             if (sf == 0.0) continue;
             const double a = A[kk];
-            const float4 tf = g.th[f];
+            const double3 tf = edge_vec(g, f);
             dg += se * a * sf;
             dp0 += (double)te.x * a * (double)tf.x;
             dp1 += (double)te.y * a * (double)tf.y;
@@ -538,7 +543,7 @@ __device__ __forceinline__ void coarse_terms(const AuxSpace& g, const int64_t* _
         if (c >= 0 && t_in) continue;   // head end of an edge inside the aggregate: its tail counts it
         const double phe = (h_in ? 1.0 : 0.0) - (t_in ? 1.0 : 0.0);
         const double pse = (t_in ? 1.0 : 0.0) + (h_in ? 1.0 : 0.0);
-        const float4 te = g.th[e];
+        const double3 te = edge_vec(g, e);
         const int64_t esl = e >> 6;
         const int el = e & 63;
         double rg = 0.0, r0 = 0.0, r1 = 0.0, r2 = 0.0;   // (A phi)_e, (A psi_d)_e
@@ -548,7 +553,7 @@ __device__ __forceinline__ void coarse_terms(const AuxSpace& g, const int64_t* _
             const bool ft = in_agg(ef.x), fh = in_agg(ef.y);
             if (!ft && !fh) continue;
             const double a = A[kk];
-            const float4 tf = g.th[f];
+            const double3 tf = edge_vec(g, f);
             const double phf = (fh ? 1.0 : 0.0) - (ft ? 1.0 : 0.0);
             const double psf = (ft ? 1.0 : 0.0) + (fh ? 1.0 : 0.0);
             rg += a * phf;
@@ -767,7 +772,7 @@ __device__ __forceinline__ void node_part(double P[8], const AuxSpace& g, const 
             c[q] = kk < k1 ? g.inc[kk] : kAuxPad;
         }
         double rv[U], qv[U];
-        float4 th[U];
+        double3 th[U];
         double s[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
@@ -776,7 +781,7 @@ __device__ __forceinline__ void node_part(double P[8], const AuxSpace& g, const 
             s[q] = ok ? (c[q] >= 0 ? 1.0 : -1.0) : 0.0;
             rv[q] = R[e];
             qv[q] = Q[e];
-            th[q] = g.th[e];
+            th[q] = edge_vec(g, e);
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
@@ -872,7 +877,7 @@ struct UPart {
     double r, q;
     double2 zp;
     double x, dinv;
-    float4 th;
+    double3 th;
     double4 ya, yb;
 };
 
@@ -884,7 +889,7 @@ __device__ __forceinline__ void u_part(UPart& P, const AuxSpace& g, const double
     P.zp = ZP[row];
     P.x = x[row];
     P.dinv = dinv[row];
-    P.th = g.th[row];
+    P.th = edge_vec(g, row);
     const int2 en = g.ends[row];
     P.ya = g.Y[en.x];
     P.yb = g.Y[en.y];

@@ -93,7 +93,7 @@ def test_bench_byte_model_and_profile_bookkeeping(tmp_path, monkeypatch):
            "n_aux": 12}
     st = {"particles": 1000, "occupied_tets": 40, "crossings": 300}
     assert bench.algorithmic_bytes("cg_iter", geo, st, "jacobi") == 12 * 1500 + 80 * 100
-    assert bench.algorithmic_bytes("cg_iter", geo, st, "aux") == 12 * 1500 + 160 * 100 + 8 * 70 + 96 * 12
+    assert bench.algorithmic_bytes("cg_iter", geo, st, "aux") == 12 * 1500 + 144 * 100 + 8 * 70 + 96 * 12
     assert bench.algorithmic_bytes("push", geo, st) == 56 * 1000 + 224 * 340
     # counter summaries are used only while the kernel source is unchanged
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
