@@ -1022,8 +1022,31 @@ __global__ __launch_bounds__(kBlock) void k_DT(int64_t n_edges, const int32_t* _
     }
 }
 
-__device__ __forceinline__ void atomic_max_abs(unsigned long long* p, double v) {
-    atomicMax(p, (unsigned long long)__double_as_longlong(fabs(v)));
+// Largest |v| over the workgroup (values as ordered bit patterns), then one atomicMax by
+// thread 0: same-address atomics from every thread would serialize at the memory side.
+template <int NV>
+__device__ __forceinline__ void block_max_abs(const double v[NV], unsigned long long* const out[NV]) {
+    __shared__ unsigned long long s[NV][kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        unsigned long long m = (unsigned long long)__double_as_longlong(fabs(v[j]));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(m, off);
+            m = o > m ? o : m;
+        }
+        if (lane == 0) s[j][w] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            unsigned long long m = 0;
+            for (int q = 0; q < kBlock / 64; ++q) m = s[j][q] > m ? s[j][q] : m;
+            if (m) atomicMax(out[j], m);
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_diag_nodes(int64_t n_nodes, const uint8_t* __restrict__ interior,
@@ -1034,27 +1057,32 @@ __global__ __launch_bounds__(kBlock) void k_diag_nodes(int64_t n_nodes, const ui
                                                         const double* __restrict__ rG1, const double* __restrict__ rG2,
                                                         const double* __restrict__ dtrcg, int have_hist,
                                                         double* __restrict__ rG_out, DiagAcc* acc) {
-    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= n_nodes) return;
-    if (!interior[k]) {
-        rG_out[k] = 0.0;
-        return;
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};   // continuity, Gauss, rho, drift
+    if (k < n_nodes) {
+        if (!interior[k]) {
+            rG_out[k] = 0.0;
+        } else {
+            const double rc = (rho_new[k] - rho_old[k]) - dtdg[k];
+            const double rg = -dtMe[k] - rho_new[k];
+            rG_out[k] = rg;
+            v[0] = rc;
+            v[1] = rg;
+            v[2] = rho_new[k];
+            if (have_hist) v[3] = (rg - 2.0 * rG1[k] + rG2[k]) - dtrcg[k];
+        }
     }
-    const double rc = (rho_new[k] - rho_old[k]) - dtdg[k];
-    const double rg = -dtMe[k] - rho_new[k];
-    rG_out[k] = rg;
-    atomic_max_abs(&acc->cont_max, rc);
-    atomic_max_abs(&acc->gauss_max, rg);
-    atomic_max_abs(&acc->rho_max, rho_new[k]);
-    if (have_hist) atomic_max_abs(&acc->drift_max, (rg - 2.0 * rG1[k] + rG2[k]) - dtrcg[k]);
+    unsigned long long* const out[4] = {&acc->cont_max, &acc->gauss_max, &acc->rho_max, &acc->drift_max};
+    block_max_abs<4>(v, out);
 }
 
 __global__ __launch_bounds__(kBlock) void k_divb(int64_t n_tets, const int32_t* __restrict__ tf,
                                                   const double* __restrict__ b, DiagAcc* acc) {
-    int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= n_tets) return;
-    const double d = b[tf[4 * t]] - b[tf[4 * t + 1]] + b[tf[4 * t + 2]] - b[tf[4 * t + 3]];
-    atomic_max_abs(&acc->divb_max, d);
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {0.0};
+    if (t < n_tets) v[0] = b[tf[4 * t]] - b[tf[4 * t + 1]] + b[tf[4 * t + 2]] - b[tf[4 * t + 3]];
+    unsigned long long* const out[1] = {&acc->divb_max};
+    block_max_abs<1>(v, out);
 }
 
 __global__ __launch_bounds__(kBlock) void k_dot(int64_t n, RowGrid rg, const double* __restrict__ a,

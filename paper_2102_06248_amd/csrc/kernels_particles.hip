@@ -753,16 +753,43 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PArrays<T> in, PArrays<T> ou
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rho(PArrays<T> p, int64_t n, const int32_t* __restrict__ tets,
                                                  double qw, double* __restrict__ rho) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int t = p.tet[i];
-    if (t < 0) return;
-    const double l1 = (double)p.l1[i], l2 = (double)p.l2[i], l3 = (double)p.l3[i];
-    const double l0 = 1.0 - l1 - l2 - l3;
-    atomic_add_f64(rho + tets[4 * t + 0], qw * l0);
-    atomic_add_f64(rho + tets[4 * t + 1], qw * l1);
-    atomic_add_f64(rho + tets[4 * t + 2], qw * l2);
-    atomic_add_f64(rho + tets[4 * t + 3], qw * l3);
+    // qw lambda_k summed over runs of lanes in the same tet (particles are kept sorted by
+    // tet, and a step moves few of them out of their run), then four atomics per run
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int key = -1;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < n) {
+        key = p.tet[i];
+        if (key >= 0) {
+            const double l1 = (double)p.l1[i], l2 = (double)p.l2[i], l3 = (double)p.l3[i];
+            v[0] = qw * (1.0 - l1 - l2 - l3);
+            v[1] = qw * l1;
+            v[2] = qw * l2;
+            v[3] = qw * l3;
+        }
+    }
+    const int prev_key = __shfl_up(key, 1);   // every lane takes part in the shuffle
+    int f = (lane == 0) || (key != prev_key);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        double o[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o[c] = __shfl_up(v[c], off);
+        const int fo = __shfl_up(f, off);
+        if (lane >= off) {
+            if (!f) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[c] += o[c];
+            }
+            f |= fo;
+        }
+    }
+    const int next_key = __shfl_down(key, 1);
+    if (key >= 0 && (lane == 63 || next_key != key)) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) atomic_add_f64(rho + tets[4 * key + c], v[c]);
+    }
 }
 
 }  // namespace
