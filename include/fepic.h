@@ -74,7 +74,8 @@ enum { FEPIC_WS_PREV = 0, FEPIC_WS_EXTRAP1 = 1, FEPIC_WS_EXTRAP2 = 2, FEPIC_WS_M
  * nodal vector fields into edge unknowns ((r_b - r_a) . (v_a + v_b) / 2), both on interior
  * edges and nodes.  The coarse levels add the same two corrections, again with one Jacobi
  * step, for piecewise-constant nodal fields on aggregates of 8, 64 (always) and 512,
- * 4096 (aux_far_levels) interior nodes consecutive in Morton order of their positions.
+ * 4096, 32768 (aux_far_levels) interior nodes consecutive in Morton order of their
+ * positions.
  * Either preconditioner converges to the same tolerance; the auxiliary spaces need
  * several times fewer iterations once dt is well beyond the explicit limit. */
 enum { FEPIC_PC_JACOBI = 0, FEPIC_PC_AUX = 1 };
@@ -103,9 +104,10 @@ typedef struct {
     int diagnostics;   /* 1: charge continuity, Gauss and div b residuals every step      */
     int timing;        /* 1: per-phase HIP-event times in fepic_step_stats                */
     int preconditioner;/* FEPIC_PC_* (default FEPIC_PC_AUX)                               */
-    int aux_far_levels;/* FEPIC_PC_AUX aggregate levels beyond 64 nodes (512, 4096 nodes):
-                          -1 (default) from dt: with tau^2 = mean beta dt^2 S_jj / M_jj,
-                          the level of 2^k nodes when tau >= 2 * 2^(k/3); or 0, 1, 2       */
+    int aux_far_levels;/* FEPIC_PC_AUX aggregate levels beyond 64 nodes (512, 4096, 32768
+                          nodes): -1 (default) from dt: with tau^2 = mean beta dt^2
+                          S_jj / M_jj, the level of 2^k nodes when tau >= 2 * 2^(k/3)
+                          and there are at least 16 such aggregates; or 0 to 3           */
     int walk;          /* FEPIC_WALK_* (default FEPIC_WALK_AUTO)                          */
 } fepic_options;
 

@@ -293,7 +293,7 @@ void particle_phase(fepic_ctx* c, double dt, bool do_sort) {
 void ensure_operator(fepic_ctx* c, double dt, double beta) {
     const double cA = beta * dt * dt;
     c->aux.n_far = c->opt.aux_far_levels >= 0 ? std::min(c->opt.aux_far_levels, kAuxFarLevels)
-                                              : aux_far_auto(cA * c->s_over_m);
+                                              : aux_far_auto(cA * c->s_over_m, c->aux.n_aux);
     if (c->A_scale == cA && c->A_valid) return;
     launch_scale_A(c->stream, c->mesh.mat, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_A, c->d_dinv, c->d_bedge, cA);
     launch_aux_scale(c->stream, c->aux, c->d_sp, c->d_col, c->d_A);
@@ -769,7 +769,7 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
     if (!(o.cg_tol > 0) || o.cg_max_iters < 1 || o.crossing_cap < 1 || o.sort_period < 0) return FEPIC_E_ARG;
     if (o.warm_start < FEPIC_WS_PREV || o.warm_start > FEPIC_WS_MLP) return FEPIC_E_ARG;
     if (o.preconditioner != FEPIC_PC_JACOBI && o.preconditioner != FEPIC_PC_AUX) return FEPIC_E_ARG;
-    if (o.aux_far_levels < -1 || o.aux_far_levels > 2) return FEPIC_E_ARG;
+    if (o.aux_far_levels < -1 || o.aux_far_levels > kAuxFarLevels) return FEPIC_E_ARG;
     if (o.walk < FEPIC_WALK_AUTO || o.walk > FEPIC_WALK_FUSED) return FEPIC_E_ARG;
     if (o.cg_check_every < 1) o.cg_check_every = 8;
     fepic_ctx* c = new fepic_ctx();

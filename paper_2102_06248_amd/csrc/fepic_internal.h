@@ -111,15 +111,18 @@ struct alignas(8) EdgeVec {
 // Padding entry of the auxiliary space's node incidence lists (no edge).
 constexpr int32_t kAuxPad = INT32_MIN;
 // log2 of the aggregate sizes of the auxiliary space's levels beyond one node slice.
-constexpr int kAuxFarLevels = 2;
-__host__ __device__ constexpr int aux_far_log(int L) { return L == 0 ? 9 : 12; }
+constexpr int kAuxFarLevels = 3;
+__host__ __device__ constexpr int aux_far_log(int L) { return 9 + 3 * L; }   // 512, 4096, 32768 nodes
 inline int64_t aux_far_count(int64_t n_aux, int L) { return (n_aux + (1ll << aux_far_log(L)) - 1) >> aux_far_log(L); }
 // Far levels chosen from tau^2 = mean over interior rows of beta dt^2 S_jj / M_jj (how many
 // cells a wave crosses in a step, squared): the level of 2^k nodes (about 2^(k/3) cells
-// across) is used when tau >= 2 * 2^(k/3).
-inline int aux_far_auto(double tau2) {
+// across) is used when tau >= 2 * 2^(k/3) and the mesh holds at least 16 such aggregates
+// (fewer, nearly global ones add cost and no convergence).
+inline int aux_far_auto(double tau2, int64_t n_aux) {
     int n = 0;
-    while (n < kAuxFarLevels && tau2 >= 4.0 * std::exp2(2.0 * aux_far_log(n) / 3.0)) ++n;
+    while (n < kAuxFarLevels && tau2 >= 4.0 * std::exp2(2.0 * aux_far_log(n) / 3.0) &&
+           n_aux >= (int64_t)16 << aux_far_log(n))
+        ++n;
     return n;
 }
 
@@ -141,8 +144,8 @@ struct AuxSpace {
     // residual's sums per aggregate are accumulated with atomics (far_acc: a 64-byte line
     // per aggregate and component, the sum in its first double; zeroed by the product
     // kernel of each iteration) and applied by the update kernel
-    double4* far_scale[2] = {nullptr, nullptr};
-    double4* far_acc[2] = {nullptr, nullptr};   // [8 * count] double4
+    double4* far_scale[kAuxFarLevels] = {};
+    double4* far_acc[kAuxFarLevels] = {};       // [8 * count] double4
     int n_far = 0;                              // far levels in use (0 .. kAuxFarLevels)
     double4* Y = nullptr;         // [n_aux + 1] nodal corrections of the residual, all levels;
                                   // Y[n_aux] = 0

@@ -595,8 +595,10 @@ __global__ __launch_bounds__(kBlock) void k_aux_coarse(AuxSpace g, const int64_t
 #pragma unroll
     for (int L = 0; L < kAuxFarLevels; ++L) {
         if (real) {
+            static_assert(kAuxFarLevels == 3, "one coarse_terms instance per far level");
             if (L == 0) coarse_terms<aux_far_log(0)>(g, sp, col, A, n, v);
-            else coarse_terms<aux_far_log(1)>(g, sp, col, A, n, v);
+            else if (L == 1) coarse_terms<aux_far_log(1)>(g, sp, col, A, n, v);
+            else coarse_terms<aux_far_log(2)>(g, sp, col, A, n, v);
         } else {
             v[0] = v[1] = v[2] = v[3] = 0.0;
         }
@@ -893,19 +895,29 @@ __device__ __forceinline__ void u_part(UPart& P, const AuxSpace& g, const double
     const int2 en = g.ends[row];
     P.ya = g.Y[en.x];
     P.yb = g.Y[en.y];
+    // far levels: an edge's two ends mostly share their aggregate, whose correction is then
+    // loaded once and added at both ends (the same sums as two loads)
 #pragma unroll
     for (int L = 0; L < kAuxFarLevels; ++L) {
         if (L >= g.n_far) break;
-        if (en.x < g.n_aux) {
-            const int64_t a = (int64_t)en.x >> aux_far_log(L);
+        const int64_t a = en.x < g.n_aux ? ((int64_t)en.x >> aux_far_log(L)) : -1;
+        const int64_t b = en.y < g.n_aux ? ((int64_t)en.y >> aux_far_log(L)) : -1;
+        if (a >= 0) {
             const double4 d = g.far_scale[L][a];
-            P.ya.x += *far_line(g, L, a, 0) * d.x;
-            P.ya.y += *far_line(g, L, a, 1) * d.y;
-            P.ya.z += *far_line(g, L, a, 2) * d.z;
-            P.ya.w += *far_line(g, L, a, 3) * d.w;
+            const double4 v = make_double4(*far_line(g, L, a, 0) * d.x, *far_line(g, L, a, 1) * d.y,
+                                           *far_line(g, L, a, 2) * d.z, *far_line(g, L, a, 3) * d.w);
+            P.ya.x += v.x;
+            P.ya.y += v.y;
+            P.ya.z += v.z;
+            P.ya.w += v.w;
+            if (b == a) {
+                P.yb.x += v.x;
+                P.yb.y += v.y;
+                P.yb.z += v.z;
+                P.yb.w += v.w;
+            }
         }
-        if (en.y < g.n_aux) {
-            const int64_t b = (int64_t)en.y >> aux_far_log(L);
+        if (b >= 0 && b != a) {
             const double4 d = g.far_scale[L][b];
             P.yb.x += *far_line(g, L, b, 0) * d.x;
             P.yb.y += *far_line(g, L, b, 1) * d.y;

@@ -223,7 +223,8 @@ def test_newmark_solve_vs_oracle(F, mode):
 
 
 @pytest.mark.parametrize("pc,n,cfl_ratio,far", [("jacobi", 7, 4.0, -1), ("jacobi", 16, 20.0, -1), ("aux", 7, 4.0, -1),
-                                                ("aux", 16, 8.0, -1), ("aux", 16, 20.0, -1), ("aux", 16, 20.0, 1)])
+                                                ("aux", 16, 8.0, -1), ("aux", 22, 20.0, -1), ("aux", 16, 20.0, 1),
+                                                ("aux", 16, 40.0, 3)])
 def test_preconditioned_cg_vs_oracle_pcg(F, pc, n, cfl_ratio, far):
     """One field-only step with each preconditioner: the library's iteration count matches
     the oracle's PCG with the same preconditioner (for the auxiliary space: the same
@@ -255,9 +256,12 @@ def test_preconditioned_cg_vs_oracle_pcg(F, pc, n, cfl_ratio, far):
         eg, _, _ = F.fepic_get_fields(L.ctx)
     if pc == "aux":
         tau2 = np.mean(0.25 * dt * dt * osim.Si.diagonal() / osim.Mi.diagonal())
-        rule = int(tau2 >= 4 * 2.0 ** 6) + int(tau2 >= 4 * 2.0 ** 8)
+        n_aux = len(m.interior_nodes)
+        rule = 0
+        while rule < 3 and tau2 >= 4 * 2.0 ** (2 * (9 + 3 * rule) / 3) and n_aux >= 16 * 2 ** (9 + 3 * rule):
+            rule += 1
         assert st.pc_far_levels == (rule if far < 0 else far)
-        levels = (8, 64, 512, 4096)[:2 + st.pc_far_levels]
+        levels = (8, 64, 512, 4096, 32768)[:2 + st.pc_far_levels]
         x_o, it_o, _ = auxspace.pcg(A, rhs, e[ie], auxspace.aux_space_preconditioner(A, m, levels=levels)[0], tol=1e-10)
     else:
         assert st.pc_far_levels == -1
