@@ -362,13 +362,14 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
         }
         // Iterations are launched in batches; after each batch the host reads the device's
         // convergence flag and sizes the next batch from the recent contraction of ||r||
-        // (never more than doubling what has been launched).  The first batch is most of
-        // the previous solve's count: counts vary little from step to step, and launches
-        // after convergence change nothing.
+        // (never more than doubling what has been launched).  The first batch is the
+        // previous solve's count plus two: counts vary little from step to step, and
+        // launches after convergence return at once, which costs less than another round
+        // trip to the host.
         int launched = 0, last_done = -1;
         double last_rr = 0.0;
         const int budget = maxit - total;
-        int todo = (restart == 0 && c->last_cg_iters > 0) ? std::max(batch, (int)(0.9 * c->last_cg_iters)) : batch;
+        int todo = (restart == 0 && c->last_cg_iters > 0) ? std::max(batch, c->last_cg_iters + 2) : batch;
         for (;;) {
             // the launch after the budget only checks (and is discarded on failure)
             todo = std::min(todo, budget + 1 - launched);
