@@ -440,16 +440,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
 // PCG with the nodal auxiliary-space preconditioner of Hiptmair and Xu (2007), additive,
 // one Jacobi step in each space:  B r = D^-1 r + G D_G^-1 G^T r + Pi D_Pi^-1 Pi^T r,
 // D = diag A, D_G = diag G^T A G, D_Pi = diag Pi^T A Pi, G the discrete gradient and Pi the
-// vector nodal interpolation on interior edges and nodes.  The slow components of
+// vector nodal interpolation on interior edges and nodes, plus the same two corrections
+// for piecewise-constant nodal fields on aggregates of 8, 64 (within a node slice) and
+// 512, 4096, 32768 (far levels) Morton-consecutive nodes.  The slow components of
 // Jacobi-PCG on the Newmark system are gradients (the kernel of S) and smooth curl
-// fields; the two nodal spaces reach both.  Plain (Hestenes-Stiefel) recurrences; an
+// fields; the nodal spaces reach both.  Plain (Hestenes-Stiefel) recurrences; an
 // iteration is three kernels, because z = B r needs the nodal sums of the new residual
 // before any edge can form it:
 //   k_pcg_q(i):      beta = g_i / g_{i-1};  p = z + beta p;  q = A p (the neighbours' p
 //                    formed on the fly from their gathered (z, p) pair);  dot (p, q)
 //   k_pcg_nodes(i):  alpha = g_i / (p, q);  per interior node, G^T r' and Pi^T r' over its
-//                    edges, r' = r - alpha q, scaled by D_G^-1 and D_Pi^-1
-//   k_pcg_update(i): x += alpha p;  r = r';  z = D^-1 r + G y + Pi v;  dots (r, z), (r, r)
+//                    edges, r' = r - alpha q, scaled by D_G^-1 and D_Pi^-1, plus the
+//                    aggregate levels of the node's slice; far-level sums by atomics
+//   k_pcg_update(i): p again (same operands, same bits);  x += alpha p;  r = r';
+//                    z = D^-1 r + G y + Pi v (all levels);  dots (r, z), (r, r)
 // Every kernel issues its loads before it sums the previous kernel's slots.  Reductions
 // use the iteration slots in four rotating buffers: reduction k goes to buffer k mod 4;
 // iteration i adds (p, q) as reduction 2i and (r, z), (r, r) as reduction 2i + 1; the
