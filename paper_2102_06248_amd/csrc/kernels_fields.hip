@@ -769,7 +769,7 @@ __device__ __forceinline__ void node_part(double P[8], const AuxSpace& g, const 
     const int64_t k0 = g.sp[sl] + lane, k1 = g.sp[sl + 1];
 #pragma unroll
     for (int v = 0; v < 8; ++v) P[v] = 0.0;
-    constexpr int U = 2;
+    constexpr int U = 4;   // slots per thread in flight together (about all of a node's share)
     for (int64_t k = k0 + 64 * j; k < k1; k += U * kNodePhases * 64) {
         int32_t c[U];
 #pragma unroll
