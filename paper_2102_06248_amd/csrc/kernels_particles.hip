@@ -307,25 +307,26 @@ __device__ __forceinline__ void walk_rest(PArrays<T>& out, int64_t i, int t, int
 // lanes that share a tet (the particles are sorted by tet); in the fused form the run sums
 // and walk pieces go through the workgroup's LDS table, flushed with one FP64 atomic per
 // edge, in the queue form each run adds its six sums with FP64 atomics.
-template <typename T, bool kFused>
-__global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, int64_t n,
+template <typename T, bool kFused, int kPB>
+__global__ __launch_bounds__(kPB) void k_push(PArrays<T> in, PArrays<T> out, int64_t n,
                                                   const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
                                                   PushParams pp, PushCounters* __restrict__ cnt,
                                                   const int32_t* __restrict__ n_live, CrossQueue<T> cq) {
     // the LDS table of the fused form (the queue form leaves it to k_cross: its 24 KB
     // would cost the first kernel occupancy)
-    constexpr int kBits = log2_const(8 * kBlock);
+    static_assert(kFused || kPB == kBlock, "the queue form fills regions of kBlock slots");
+    constexpr int kBits = log2_const(8 * kPB);
     constexpr int kSlots = kFused ? (1 << kBits) : 1;
     __shared__ int s_key[kSlots];
     __shared__ double s_val[kSlots];
     if (kFused) {
-        for (int k = threadIdx.x; k < kSlots; k += kBlock) {
+        for (int k = threadIdx.x; k < kSlots; k += kPB) {
             s_key[k] = -1;
             s_val[k] = 0.0;
         }
         __syncthreads();
     }
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x;
     const int lane = threadIdx.x & 63;
     if (n_live) n = min(n, (int64_t)*n_live);
     int t0 = -1;
@@ -454,10 +455,10 @@ __global__ __launch_bounds__(kBlock) void k_push(PArrays<T> in, PArrays<T> out, 
         unsigned int nc = 0, na = 0, ncap = 0;
         if (cross) walk_rest<T, kBits>(out, i, tn, q, ln, frac, dx, blk, dg, pp, s_key, s_val, nc, na, ncap);
         __syncthreads();
-        flush_table<kSlots, kBlock>(s_key, s_val, dg);
+        flush_table<kSlots, kPB>(s_key, s_val, dg);
         const unsigned int c1 = (cross || status == 2) ? 1u : 0u;
         const unsigned int sc = cross ? nc : c1;
-        add_counters(sc, sc, (status == 1) + na, (status == 2) + ncap, cnt);
+        add_counters<kPB>(sc, sc, (status == 1) + na, (status == 2) + ncap, cnt);
         return;
     }
     // compact the crossing lanes of the workgroup into its queue region
@@ -890,8 +891,10 @@ void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double*
                        tet_edges, tet_faces);
 }
 
-// Crossings per particle (last step) above which the particle step is one kernel.
+// Crossings per particle (last step) above which the particle step is one kernel, and that
+// kernel's workgroup size.
 constexpr double kFuseShare = 0.5;
+constexpr int kFusedBlock = 256;
 
 template <typename T>
 void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const TetBlock<T>* blk, double* dg,
@@ -902,10 +905,12 @@ void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const 
     if (walk == FEPIC_WALK_FUSED || (walk == FEPIC_WALK_AUTO && cross_share > kFuseShare)) {
         // most paths cross: finishing them in place costs less idle lanes than the queue
         // costs bytes (64 B written and read back per crossing particle)
-        hipLaunchKernelGGL((k_push<T, true>), dim3(n_wg), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live, cq);
+        hipLaunchKernelGGL((k_push<T, true, kFusedBlock>), dim3((unsigned)grid_1d(n, kFusedBlock)), dim3(kFusedBlock), 0,
+                           s, in, out, n, blk, dg, pp, cnt, n_live, cq);
         return;
     }
-    hipLaunchKernelGGL((k_push<T, false>), dim3(n_wg), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live, cq);
+    hipLaunchKernelGGL((k_push<T, false, kBlock>), dim3(n_wg), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live,
+                       cq);
     // one k_cross workgroup per k_push workgroup, sized for its expected queue length
     if (cross_share <= 0.25)
         hipLaunchKernelGGL((k_cross<T, 64>), dim3(n_wg), dim3(64), 0, s, out, cq, blk, dg, pp, cnt);
