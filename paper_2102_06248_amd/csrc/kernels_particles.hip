@@ -192,9 +192,19 @@ __device__ __forceinline__ void add_counters(unsigned int sc, unsigned int mc, u
 // goes to global memory directly.
 constexpr int kProbe = 16;
 
-// The six edge currents of one piece: the first probe of all six keys is issued at once
-// (independent compare-and-swaps), so one LDS round trip serves the common case; keys
-// whose first slot holds another edge continue with lds_add's probing.
+// Kernels that walk paths keep their registers within what 6 waves per SIMD allow in FP32
+// (80 VGPRs; the fused push needs 81 unconstrained, and 6 workgroups of it fit one CU's
+// LDS): the exit searches and LDS round trips of a walk are latency bound, so the extra
+// wave pays more than the registers it costs.  The FP64 forms (validation precision) hold
+// 5, where they do not spill.
+template <typename T>
+constexpr int walk_waves() { return sizeof(T) == 4 ? 6 : 5; }
+
+// The six edge currents of one piece: the first probe of all six keys is issued at once,
+// so one LDS round trip serves the common case; keys whose first slot holds another edge
+// probe on.  A slot's key is read before it is claimed: a slot, once claimed, keeps its
+// key, and lanes of a wave that add to the same edges then share one broadcast read
+// instead of serialising on compare-and-swaps of one address.
 template <int kBits>
 __device__ __forceinline__ void lds_add6(int* s_key, double* s_val, double* __restrict__ dg, const int32_t* e,
                                          const double v[6]) {
@@ -206,7 +216,11 @@ __device__ __forceinline__ void lds_add6(int* s_key, double* s_val, double* __re
         h[c] = ((unsigned int)key[c] * 2654435761u) >> (32 - kBits);
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) got[c] = (v[c] != 0.0) ? atomicCAS(s_key + h[c], -1, key[c]) : key[c];
+    for (int c = 0; c < 6; ++c)
+        got[c] = (v[c] != 0.0) ? __hip_atomic_load(s_key + h[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : key[c];
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        if (got[c] == -1) got[c] = atomicCAS(s_key + h[c], -1, key[c]);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         if (v[c] == 0.0) continue;
@@ -217,7 +231,8 @@ __device__ __forceinline__ void lds_add6(int* s_key, double* s_val, double* __re
             unsigned int hh = (h[c] + 1) & ((1u << kBits) - 1u);
             bool placed = false;
             for (int p = 1; p < kProbe && !placed; ++p) {
-                const int k = atomicCAS(s_key + hh, -1, key[c]);
+                int k = __hip_atomic_load(s_key + hh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (k == -1) k = atomicCAS(s_key + hh, -1, key[c]);
                 if (k == -1 || k == key[c]) {
                     __hip_atomic_fetch_add(s_val + hh, v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     placed = true;
@@ -308,7 +323,7 @@ __device__ __forceinline__ void walk_rest(PArrays<T>& out, int64_t i, int t, int
 // and walk pieces go through the workgroup's LDS table, flushed with one FP64 atomic per
 // edge, in the queue form each run adds its six sums with FP64 atomics.
 template <typename T, bool kFused, int kPB>
-__global__ __launch_bounds__(kPB) void k_push(PArrays<T> in, PArrays<T> out, int64_t n,
+__global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? walk_waves<T>() : 1, 8))) void k_push(PArrays<T> in, PArrays<T> out, int64_t n,
                                                   const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
                                                   PushParams pp, PushCounters* __restrict__ cnt,
                                                   const int32_t* __restrict__ n_live, CrossQueue<T> cq) {
@@ -502,7 +517,7 @@ __global__ __launch_bounds__(kPB) void k_push(PArrays<T> in, PArrays<T> out, int
 // table of 8 kB slots, then added to global memory once per edge.  kB is chosen from the
 // expected share of crossing particles, so most threads have one particle.
 template <typename T, int kB>
-__global__ __launch_bounds__(kB) void k_cross(PArrays<T> out, CrossQueue<T> cq, const TetBlock<T>* __restrict__ blk,
+__global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(walk_waves<T>(), 8))) void k_cross(PArrays<T> out, CrossQueue<T> cq, const TetBlock<T>* __restrict__ blk,
                                               double* __restrict__ dg, PushParams pp,
                                               PushCounters* __restrict__ cnt) {
     constexpr int kBits = log2_const(8 * kB);
