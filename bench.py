@@ -32,7 +32,8 @@ METRIC = "particle-steps/s (gather+push+deposit) + Newmark step time at CG resid
 HBM_PEAK_GBS = 8000.0
 FAMILIES = ["push", "stage", "sort", "rhs", "cg_iter", "faraday"]
 KERNEL_NAMES = {"push": "k_push+k_cross", "stage": "k_stage", "sort": "k_hist/k_scan/k_scatter", "rhs": "k_rhs",
-                "cg_iter": "k_pcg_q+k_pcg_nodes+k_pcg_update", "faraday": "k_faraday"}
+                "cg_iter": "k_pcg_q<double>+k_pcg_nodes<double>+k_pcg_update<double>", "faraday": "k_faraday"}
+MIXED_ITER_KERNEL = "k_pcg_q<float>+k_pcg_nodes<float>+k_pcg_update<float>"
 JACOBI_ITER_KERNEL = "k_cg_iter"
 KERNEL_SOURCES = {"push": "kernels_particles.hip", "stage": "kernels_particles.hip", "sort": "kernels_particles.hip",
                   "rhs": "kernels_fields.hip", "cg_iter": "kernels_fields.hip", "faraday": "kernels_fields.hip"}
@@ -42,14 +43,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(fam, geo, st, pc="aux"):
+def algorithmic_bytes(fam, geo, st, pc="aux", solve="fp64"):
     """Bytes the method must move per launch (each HBM word once), by kernel family.  A
     "cg_iter" launch is one PCG iteration: one kernel with Jacobi, three with the nodal
-    auxiliary-space preconditioner."""
+    auxiliary-space preconditioner (in FP32 for the inner solves of the mixed form)."""
     n_rows, nnz, ne, nf, nt = geo["n_rows"], geo["nnz"], geo["n_edges"], geo["n_faces"], geo["n_tets"]
     npart, occ, cross = st["particles"], st["occupied_tets"], st["crossings"]
     if fam == "cg_iter" and pc == "jacobi":   # A values + columns once; per row R, W, S, P and x read
         return 12 * nnz + 80 * n_rows          # and written
+    if fam == "cg_iter" and solve == "mixed":
+        # the same words in FP32 (values 4 B, (z, p) pairs 8 B, diagonals and Y 16 B per
+        # node), column ids, incidences, FP16 edge vectors and ends as before:
+        # q 8 nnz + 12 per row; nodes 16 per row, 32 per node; update 40 read + 16 written
+        # per row, 16 per node
+        return 8 * nnz + (12 + 16 + 56) * n_rows + 8 * geo["n_int_edges"] + 48 * geo["n_aux"]
     if fam == "cg_iter":
         # q = A p: A values + columns, (z, p) read, q written: 12 nnz + 24 per row;
         # nodes: one 4 B incidence per interior edge end, r, q and the FP16 edge vector per
@@ -76,15 +83,19 @@ def source_hash(fam):
     return hashlib.sha1(open(p, "rb").read()).hexdigest()[:12]
 
 
-def profile_key(fam, pc):
+def profile_key(fam, pc, solve="fp64"):
     """Name stem of a family's counter summary under profiles/."""
-    return "cg_iter_jacobi" if (fam == "cg_iter" and pc == "jacobi") else fam
+    if fam == "cg_iter" and pc == "jacobi":
+        return "cg_iter_jacobi"
+    if fam == "cg_iter" and solve == "mixed":
+        return "cg_iter_mixed"
+    return fam
 
 
-def traffic_from_profile(fam, workload, launches_bytes_per, pc="aux"):
+def traffic_from_profile(fam, workload, launches_bytes_per, pc="aux", solve="fp64"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
     on the current kernel source; None otherwise."""
-    p = os.path.join(ROOT, "profiles", f"{profile_key(fam, pc)}_{workload}_counters.json")
+    p = os.path.join(ROOT, "profiles", f"{profile_key(fam, pc, solve)}_{workload}_counters.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -157,6 +168,11 @@ def main():
                     help="re-sort particles by tet every this many steps (default: the workload's)")
     ap.add_argument("--walk", default="auto", choices=["auto", "queue", "fused"],
                     help="crossing paths: chosen from the last step's crossings, queue + second kernel, or in place")
+    ap.add_argument("--solve", default=None, choices=["fp64", "mixed"],
+                    help="Newmark solve arithmetic: FP64 PCG, or FP64 residuals around FP32 inner PCG "
+                         "(auxiliary-space preconditioner only); default: the workload's")
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="--solve mixed: residual reduction of one FP32 pass (default: the workload's)")
     ap.add_argument("--preconditioner", default="aux", choices=["aux", "jacobi"],
                     help="Newmark PCG preconditioner: nodal auxiliary space (default) or Jacobi")
     ap.add_argument("--inject", type=int, default=1, help="inject the beam's per-step batch (c2)")
@@ -190,10 +206,16 @@ def main():
           "mlp": F.FEPIC_WS_PREV}[args.warm_start]
     precision = {"auto": wl["precision"], "fp32": 0, "fp64": 1}[args.precision]
     pc = args.preconditioner
+    solve = args.solve or (wl.get("solve", "fp64") if pc == "aux" else "fp64")
+    if solve == "mixed" and pc != "aux":
+        raise SystemExit("--solve mixed needs --preconditioner aux")
+    inner_tol = args.inner_tol or wl.get("inner_tol")
     sort_period = args.sort_period if args.sort_period is not None else wl.get("sort_period", 1)
     sim = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=precision, warm_start=ws,
                        sort_period=sort_period, timing=1, diagnostics=1 if args.diagnostics else 0,
                        preconditioner=F.FEPIC_PC_AUX if pc == "aux" else F.FEPIC_PC_JACOBI,
+                       solve_precision=F.FEPIC_SOLVE_MIXED if solve == "mixed" else F.FEPIC_SOLVE_FP64,
+                       **({"mixed_inner_tol": inner_tol} if (solve == "mixed" and inner_tol) else {}),
                        walk={"auto": F.FEPIC_WALK_AUTO, "queue": F.FEPIC_WALK_QUEUE, "fused": F.FEPIC_WALK_FUSED}[args.walk])
     ctx = sim.ctx
     species = []
@@ -289,7 +311,7 @@ def main():
     ms_tot, nl = fam_time[dominant]
     mean_particles = psteps / args.steps
     wst = {"particles": mean_particles, "occupied_tets": occ, "crossings": cross / args.steps}
-    per_launch_bytes = algorithmic_bytes(dominant, geo, wst, pc)
+    per_launch_bytes = algorithmic_bytes(dominant, geo, wst, pc, solve)
     work_share = 1.0
     if dominant == "push":
         per_launch_bytes = algorithmic_bytes(dominant, geo, wst) / len(species)
@@ -299,12 +321,13 @@ def main():
         work_share = min(1.0, sum(cg_iters) / nl)
     avg_s = ms_tot / nl / 1e3
     achieved = per_launch_bytes * work_share / avg_s / 1e9
-    traffic = traffic_from_profile(dominant, wl["name"], per_launch_bytes, pc)
+    traffic = traffic_from_profile(dominant, wl["name"], per_launch_bytes, pc, solve)
     if traffic is not None:
         traffic = int(traffic * work_share)   # counters are per working launch (median)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": JACOBI_ITER_KERNEL if (dominant == "cg_iter" and pc == "jacobi") else KERNEL_NAMES[dominant],
+                "kernel": (JACOBI_ITER_KERNEL if pc == "jacobi" else MIXED_ITER_KERNEL if solve == "mixed"
+                           else KERNEL_NAMES[dominant]) if dominant == "cg_iter" else KERNEL_NAMES[dominant],
                 "avg_launch_us": round(avg_s * 1e6, 3), "launches": nl,
                 "working_launch_share": round(work_share, 4),
                 "algorithmic_bytes_per_launch": int(per_launch_bytes * work_share)}
@@ -340,14 +363,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "tets": len(wl["tets"]), "particles": n_total,
                    "mean_live_particles": round(mean_particles), "dt": wl["dt"], "beta": wl["beta"],
-                   "gamma": wl["gamma"], "cg_tol": 1e-10, "preconditioner": pc, "walk": args.walk,
+                   "gamma": wl["gamma"], "cg_tol": 1e-10, "preconditioner": pc, "solve": solve,
+                   "mixed_inner_tol": (inner_tol or 1e-4) if solve == "mixed" else None, "walk": args.walk,
                    "warm_start": args.warm_start,
                    "sort_period": sort_period, "inject_per_step": int(wl.get("inject_per_step") or 0) if inject else 0,
                    "inject_from": args.inject_from if inject else None,
-                   "precision": ("fp32 push / fp64 deposit+solve" if precision == 0 else "all fp64"),
+                   "precision": ("fp32 push / fp64 deposit" if precision == 0 else "all fp64 particles")
+                   + (" / fp64 residuals around fp32 inner solves" if solve == "mixed" else " / fp64 solve"),
                    "diagnostics_in_timed_steps": bool(args.diagnostics), "parallelism": "single GPU"},
         "newmark_ms_per_step": round(float(np.mean(newmark_ms)), 4),
         "cg_iters_mean": round(float(np.mean(cg_iters)), 2),
+        "cg_passes_mean": round(float(np.mean([st.cg_passes for st in stats])), 2),
         "push": push_info,
         "crossings_per_particle_step": round(cross / psteps, 4),
         "kernel_breakdown": breakdown,

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define FEPIC_ABI_VERSION 3
+#define FEPIC_ABI_VERSION 4
 
 enum {
     FEPIC_OK = 0,
@@ -80,6 +80,17 @@ enum { FEPIC_WS_PREV = 0, FEPIC_WS_EXTRAP1 = 1, FEPIC_WS_EXTRAP2 = 2, FEPIC_WS_M
  * several times fewer iterations once dt is well beyond the explicit limit. */
 enum { FEPIC_PC_JACOBI = 0, FEPIC_PC_AUX = 1 };
 
+/* Arithmetic of the Newmark solve (Sec. III-A; the paper fixes the tolerance, not how it
+ * is met).  FEPIC_SOLVE_FP64: PCG in FP64.  FEPIC_SOLVE_MIXED (needs FEPIC_PC_AUX):
+ * iterative refinement: the residual r = b - A x in FP64, then the same PCG in FP32 (A,
+ * the preconditioner's diagonals and the iteration vectors rounded to FP32; dot products
+ * and step lengths in FP64) on A d = r from d = 0 until its residual has fallen by
+ * mixed_inner_tol, or as far as cg_tol needs, then x += d in FP64; repeated until the FP64
+ * residual meets cg_tol (at most 8 passes).  The stopping rule, and so the guaranteed
+ * accuracy, is the FP64 solve's; an FP32 iteration moves about 40 % fewer bytes, at the
+ * price of a few more iterations in all (each pass restarts the Krylov space). */
+enum { FEPIC_SOLVE_FP64 = 0, FEPIC_SOLVE_MIXED = 1 };
+
 /* How the particle step finishes paths that cross a face (Sec. III-C, Alg. 1): in a second
  * kernel from a compacted queue of the crossing particles (FEPIC_WALK_QUEUE), or in place
  * in the first kernel (FEPIC_WALK_FUSED: no queue traffic, idle lanes while others walk).
@@ -109,6 +120,9 @@ typedef struct {
                           S_jj / M_jj, the level of 2^k nodes when tau >= 2 * 2^(k/3)
                           and there are at least 16 such aggregates; or 0 to 3           */
     int walk;          /* FEPIC_WALK_* (default FEPIC_WALK_AUTO)                          */
+    int solve_precision;   /* FEPIC_SOLVE_* (default FEPIC_SOLVE_FP64)                    */
+    double mixed_inner_tol;/* FEPIC_SOLVE_MIXED: residual reduction of one FP32 pass, in
+                              (0, 1) (default 1e-4)                                       */
 } fepic_options;
 
 typedef struct {
@@ -133,6 +147,9 @@ typedef struct {
     double kinetic_energy;        /* sum over live particles of w m c^2 (gamma - 1), J    */
     int pc_far_levels;            /* aggregate levels beyond 64 nodes the solve used (-1:  */
                                   /* Jacobi preconditioner or no solve)                   */
+    int cg_passes;                /* FP64 residual passes of a FEPIC_SOLVE_MIXED solve     */
+                                  /* (cg_iters counts the FP32 iterations of all of them); */
+                                  /* 0 for an FP64 solve                                  */
 } fepic_step_stats;
 
 /* ---------------------------------------------------------------- lifecycle */
@@ -152,8 +169,12 @@ int fepic_destroy(fepic_ctx* ctx);
 int fepic_set_allocator(fepic_ctx* ctx, void* (*alloc)(size_t bytes, void* user), void (*free_)(void* ptr, void* user),
                         void* user);
 /* Selects the preconditioner of later Newmark solves (FEPIC_PC_*; FEPIC_E_ARG for any
- * other value).  Results agree to the solver tolerance either way. */
+ * other value, and for FEPIC_PC_JACOBI while the solve is FEPIC_SOLVE_MIXED).  Results
+ * agree to the solver tolerance either way. */
 int fepic_set_preconditioner(fepic_ctx* ctx, int pc);
+/* Selects the arithmetic of later Newmark solves (FEPIC_SOLVE_*; FEPIC_E_ARG for any other
+ * value, and for FEPIC_SOLVE_MIXED with the Jacobi preconditioner). */
+int fepic_set_solve_precision(fepic_ctx* ctx, int solve_precision);
 /* Runs all later device work of this context on the given hipStream_t (NULL = the
  * context's own stream).  The caller keeps the stream alive while the context uses it. */
 int fepic_set_stream(fepic_ctx* ctx, void* hip_stream);

@@ -37,6 +37,16 @@ B is symmetric positive definite (a sum of an SPD matrix and symmetric positive
 semi-definite ones), so PCG with it converges to the same solution as any other PCG; it
 only changes how many iterations that takes.  The stopping rule is the one of
 ``newmark.pcg_jacobi``: ||r||_2 <= tol ||b||_2 on the updated residual.
+
+Mixed precision (``pcg_refined``): classical iterative refinement (Wilkinson; for CG
+inner solves see e.g. Carson and Higham, SIAM J. Sci. Comput. 40 (2018) A817).  The
+residual r = b - A x is formed in FP64; the correction d solves A d = r approximately
+with the same PCG run in FP32 (A, the preconditioner's inverse diagonals and all
+vectors rounded to FP32; inner products and the step lengths alpha, beta in FP64) from
+d = 0, until its updated residual is at most max(inner_tol, tol ||b|| / (2 ||r||)) ||r||;
+then x += d in FP64, and again until the FP64 residual meets tol ||b||.  Each pass gains
+a factor of about inner_tol as long as that exceeds what FP32 can resolve, and the
+result satisfies the same stopping rule as the FP64 PCG.
 """
 from __future__ import annotations
 
@@ -90,10 +100,12 @@ def aggregation_matrix(n, size):
     return sp.csr_matrix((np.ones(n), (k, k // size)), shape=(n, (n + size - 1) // size))
 
 
-def aux_space_preconditioner(A, mesh, edges=None, nodes=None, levels=()):
+def aux_space_preconditioner(A, mesh, edges=None, nodes=None, levels=(), dtype=np.float64):
     """The additive preconditioner B as a function r -> B r on the unknowns `edges`
     (default: interior edges, the rows of A) with nodal spaces on `nodes` (default:
     interior nodes, taken in Morton order) and aggregation levels of the given sizes.
+    With dtype float32, B r is computed in FP32 from the FP32 roundings of the matrices
+    and of the inverse diagonals (the diagonals themselves are formed in FP64).
     Returns (apply, G, Pi, dG, dPi) with the fine-level matrices and diagonals."""
     edges = mesh.interior_edges if edges is None else edges
     nodes = morton_order(mesh, mesh.interior_nodes if nodes is None else nodes)
@@ -115,6 +127,19 @@ def aux_space_preconditioner(A, mesh, edges=None, nodes=None, levels=()):
             z = z + Q @ ((Q.T @ r) / d)
         return z
 
+    if np.dtype(dtype) == np.float32:
+        f = np.float32
+        dinv = (1.0 / dA).astype(f)
+        terms = [(Q.astype(f).tocsr(), (1.0 / d).astype(f)) for Q, d in [(G, dG), (Pi, dPi)] + coarse]
+
+        def apply32(r):
+            r = np.asarray(r, dtype=f)
+            z = dinv * r
+            for Q, di in terms:
+                z = z + Q @ (di * (Q.T @ r))
+            return z
+
+        return apply32, G, Pi, dG, dPi
     return apply, G, Pi, dG, dPi
 
 
@@ -144,3 +169,53 @@ def pcg(A, b, x0, apply_B, tol=1e-10, maxit=10000):
             p = z + (rz_new / rz) * p
             rz = rz_new
     return x, it, np.linalg.norm(b - A @ x) / bnorm
+
+
+def _pcg_fp32(A32, b32, bnorm, apply_B32, tol, maxit):
+    """The PCG of ``pcg`` from x = 0 with FP32 vectors, FP64 inner products and step
+    lengths (rounded to FP32 where they scale a vector); stops when the updated residual
+    satisfies ||r||_2 <= tol * bnorm.  Returns (x, iterations)."""
+    f = np.float32
+    x = np.zeros_like(b32)
+    r = b32.copy()
+    it = 0
+    if np.linalg.norm(r.astype(np.float64)) > tol * bnorm:
+        z = apply_B32(r)
+        p = z.copy()
+        rz = float(r.astype(np.float64) @ z.astype(np.float64))
+        while it < maxit:
+            q = A32 @ p
+            alpha = rz / float(p.astype(np.float64) @ q.astype(np.float64))
+            x = x + f(alpha) * p
+            r = r - f(alpha) * q
+            it += 1
+            if np.linalg.norm(r.astype(np.float64)) <= tol * bnorm:
+                break
+            z = apply_B32(r)
+            rz_new = float(r.astype(np.float64) @ z.astype(np.float64))
+            p = z + f(rz_new / rz) * p
+            rz = rz_new
+    return x, it
+
+
+def pcg_refined(A, b, x0, apply_B32, tol=1e-10, inner_tol=1e-4, max_passes=8, maxit=10000):
+    """Mixed-precision iterative refinement around an FP32 PCG (module docstring).
+    apply_B32 is the FP32 preconditioner (``aux_space_preconditioner(..., dtype=float32)``).
+    Returns (x, total inner iterations, passes, true relative residual)."""
+    bnorm = np.linalg.norm(b)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    if bnorm == 0.0:
+        return np.zeros_like(x), 0, 0, 0.0
+    A32 = A.astype(np.float32).tocsr()
+    total = passes = 0
+    while True:
+        r = b - A @ x
+        rn = np.linalg.norm(r)
+        if rn <= tol * bnorm or passes >= max_passes or total >= maxit:
+            break
+        tol_in = max(inner_tol, 0.5 * tol * bnorm / rn)
+        d, it = _pcg_fp32(A32, r.astype(np.float32), rn, apply_B32, tol_in, maxit - total)
+        x += d.astype(np.float64)
+        total += it
+        passes += 1
+    return x, total, passes, rn / bnorm

@@ -299,6 +299,40 @@ void ensure_operator(fepic_ctx* c, double dt, double beta) {
     launch_aux_scale(c->stream, c->aux, c->d_sp, c->d_col, c->d_A);
     c->A_scale = cA;
     c->A_valid = true;
+    c->A32_valid = false;
+}
+
+// The FP32 state of the mixed-precision solve: allocated on first use, the operator's
+// copies refreshed whenever A changed.
+int ensure_operator_f32(fepic_ctx* c) {
+    const int64_t ne = c->mesh.n_edges, nnz = c->mesh.mat.slice_ptr.back(), na = c->aux.n_aux;
+    if (!c->d_A32) {
+        AuxSpace& g = c->aux;
+        c->d_A32 = dalloc<float>(c, nnz);
+        c->d_dinv32 = dalloc<float>(c, ne);
+        c->d_x32 = dalloc<float>(c, ne);
+        c->d_rq32 = dalloc<float>(c, 2 * ne);
+        for (float2*& p : c->d_zp32) p = dalloc<float2>(c, ne);
+        g.scale_f = dalloc<float4>(c, na);
+        g.scale8_f = dalloc<float4>(c, (na + 7) / 8);
+        g.scale64_f = dalloc<float4>(c, (na + 63) / 64);
+        g.Y_f = dalloc<float4>(c, na + 1);
+        bool ok = c->d_A32 && c->d_dinv32 && c->d_x32 && c->d_rq32 && c->d_zp32[0] && c->d_zp32[1] && g.scale_f &&
+                  g.scale8_f && g.scale64_f && g.Y_f;
+        for (int L = 0; L < kAuxFarLevels; ++L) {
+            g.far_scale_f[L] = dalloc<float4>(c, aux_far_count(na, L));
+            ok = ok && g.far_scale_f[L];
+        }
+        if (!ok) return fail(c, FEPIC_E_OOM, "device allocation failed");
+        HIPCHK(c, hipMemsetAsync(g.Y_f, 0, sizeof(float4) * (na + 1), c->stream));   // entry n_aux stays zero
+        HIPCHK(c, hipMemsetAsync(c->d_rq32, 0, sizeof(float) * 2 * ne, c->stream));
+        for (float2* p : c->d_zp32) HIPCHK(c, hipMemsetAsync(p, 0, sizeof(float2) * ne, c->stream));
+    }
+    if (!c->A32_valid) {
+        launch_operator_f32(c->stream, nnz, c->d_A, c->d_A32, ne, c->d_dinv, c->d_dinv32, c->aux);
+        c->A32_valid = true;
+    }
+    return FEPIC_OK;
 }
 
 constexpr int kMaxRestarts = 3;
@@ -333,6 +367,11 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
     CgVec* const V[2] = {c->d_cgv[0], c->d_cgv[1]};
     double2* const ZP[2] = {c->d_zp[0], c->d_zp[1]};
     const bool aux = c->opt.preconditioner == FEPIC_PC_AUX;
+    const bool mixed = aux && c->opt.solve_precision == FEPIC_SOLVE_MIXED;
+    if (mixed) {
+        int rc = ensure_operator_f32(c);
+        if (rc != FEPIC_OK) return rc;
+    }
     auto cg_init = [&]() {
         if (aux)
             launch_pcg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, c->aux, ZP[0],
@@ -341,48 +380,35 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
             launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, V[0], c->d_partial,
                            c->d_sc, c->opt.cg_tol);
     };
+    auto true_resid = [&]() -> int {
+        launch_cg_resid(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_rhs, c->d_x, c->d_rt, c->d_partial, c->d_sc);
+        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return FEPIC_OK;
+    };
     const int maxit = c->opt.cg_max_iters;
     const int batch = std::max(1, c->opt.cg_check_every);
     int total = 0;
     double rr0_first = -1.0;
     c->cg_restarts = 0;
-    for (int restart = 0;; ++restart) {
-        cg_init();
-        if (restart == 0 && mode == FEPIC_WS_MLP) {
-            // guard: a start worse than x0 = 0 (or non-finite) falls back to e^n
-            if (aux) launch_pcg_rr0(c->stream, c->d_partial, c->d_sc);
-            else launch_cg_rr0(c->stream, ne, c->d_partial, c->d_sc);
-            HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            if (!(std::isfinite(c->h_sc->rr0)) || c->h_sc->rr0 > c->h_sc->bb) {
-                c->mlp_fallbacks++;
-                launch_warm(c->stream, FEPIC_WS_PREV, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
-                cg_init();
-            }
-        }
-        // Iterations are launched in batches; after each batch the host reads the device's
-        // convergence flag and sizes the next batch from the recent contraction of ||r||
-        // (never more than doubling what has been launched).  The first batch is the
-        // previous solve's count plus two: counts vary little from step to step, and
-        // launches after convergence return at once, which costs less than another round
-        // trip to the host.
+    c->cg_passes = 0;
+    // Iterations are launched in batches; after each batch the host reads the device's
+    // convergence flag and sizes the next batch from the recent contraction of ||r||
+    // (never more than doubling what has been launched).  The first batch is the last
+    // solve's count (of the same pass) plus two: counts vary little from step to step, and
+    // launches after convergence return at once, which costs less than another round trip
+    // to the host.  iter(i) launches iteration i.
+    auto iterate = [&](int first, auto&& iter) -> int {
         int launched = 0, last_done = -1;
         double last_rr = 0.0;
         const int budget = maxit - total;
-        int todo = (restart == 0 && c->last_cg_iters > 0) ? std::max(batch, c->last_cg_iters + 2) : batch;
+        int todo = first;
         for (;;) {
             // the launch after the budget only checks (and is discarded on failure)
             todo = std::min(todo, budget + 1 - launched);
             hipEvent_t* ev = timer_pair(c, FAM_CG_ITER, todo);
             if (ev) (void)hipEventRecord(ev[0], c->stream);
-            for (int k = 0; k < todo; ++k) {
-                if (aux)
-                    launch_pcg_iter(c->stream, launched + k, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, c->aux,
-                                    ZP, c->d_rq, c->d_partial, c->d_sc);
-                else
-                    launch_cg_iter(c->stream, launched + k, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, V,
-                                   c->d_partial, c->d_sc);
-            }
+            for (int k = 0; k < todo; ++k) iter(launched + k);
             if (ev) (void)hipEventRecord(ev[1], c->stream);
             launched += todo;
             HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
@@ -404,17 +430,88 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
             last_done = done;
             last_rr = h.rr;
         }
-        if (restart == 0) rr0_first = c->h_sc->rr0;
-        total += c->h_sc->iters;
-        // The stopping rule is on the true residual.  If the recurrences drifted from it, or
-        // broke down (converged == 2: a non-positive or non-finite step), restart from the
-        // current iterate, up to kMaxRestarts times within the iteration budget.
-        launch_cg_resid(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_rhs, c->d_x, c->d_rt, c->d_partial, c->d_sc);
-        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        const CgScalars& h = *c->h_sc;
-        if (h.rr_true <= h.tol2_bb || restart >= kMaxRestarts || total >= maxit || h.converged == 0) break;
-        c->cg_restarts++;
+        return FEPIC_OK;
+    };
+    if (mixed) {
+        // Iterative refinement: the FP64 residual of x, an FP32 PCG for the correction
+        // from zero, x += d in FP64.  The inner solves overwrite the device's ||b||^2 and
+        // tolerance; the outer ones are kept here.
+        launch_pcg_rhs_norm(c->stream, ne, c->d_partial, c->d_sc, c->opt.cg_tol);
+        float2* const ZP32[2] = {c->d_zp32[0], c->d_zp32[1]};
+        constexpr int kMaxPasses = 8;
+        double bb = 0.0, tol2 = 0.0;
+        for (int pass = 0;; ++pass) {
+            int rc = true_resid();
+            if (rc != FEPIC_OK) return rc;
+            const CgScalars h = *c->h_sc;
+            if (pass == 0) {
+                bb = h.bb;
+                tol2 = h.tol2_bb;
+                if (mode == FEPIC_WS_MLP && (!std::isfinite(h.rr_true) || h.rr_true > bb)) {
+                    // guard: a start worse than x0 = 0 (or non-finite) falls back to e^n
+                    c->mlp_fallbacks++;
+                    mode = FEPIC_WS_PREV;
+                    launch_warm(c->stream, FEPIC_WS_PREV, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
+                    --pass;
+                    continue;
+                }
+                rr0_first = h.rr_true;
+            }
+            if (!(h.rr_true > tol2) || !std::isfinite(h.rr_true) || pass >= kMaxPasses || total >= maxit) break;
+            // the pass ends when its own residual has fallen by mixed_inner_tol, or below half
+            // the outer target
+            const double tol_in = std::max(c->opt.mixed_inner_tol, 0.5 * std::sqrt(tol2 / h.rr_true));
+            launch_pcg_init_f32(c->stream, ne, c->d_sp, c->d_col, c->d_A32, c->d_dinv32, c->d_rt, c->d_x32, c->aux,
+                                ZP32[0], c->d_rq32, c->d_partial, c->d_sc, tol_in);
+            const int first = c->last_pass_iters[pass] > 0 ? std::max(batch, c->last_pass_iters[pass] + 2) : batch;
+            rc = iterate(first, [&](int i) {
+                launch_pcg_iter_f32(c->stream, i, ne, c->d_sp, c->d_col, c->d_A32, c->d_dinv32, c->d_x32, c->aux,
+                                    ZP32, c->d_rq32, c->d_partial, c->d_sc);
+            });
+            if (rc != FEPIC_OK) return rc;
+            c->last_pass_iters[pass] = c->h_sc->iters;
+            total += c->h_sc->iters;
+            c->cg_passes = pass + 1;
+            launch_add_f32(c->stream, c->d_x, c->d_x32, ne);
+        }
+        c->h_sc->bb = bb;
+        c->h_sc->tol2_bb = tol2;
+    } else {
+        for (int restart = 0;; ++restart) {
+            cg_init();
+            if (restart == 0 && mode == FEPIC_WS_MLP) {
+                // guard: a start worse than x0 = 0 (or non-finite) falls back to e^n
+                if (aux) launch_pcg_rr0(c->stream, c->d_partial, c->d_sc);
+                else launch_cg_rr0(c->stream, ne, c->d_partial, c->d_sc);
+                HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+                if (!(std::isfinite(c->h_sc->rr0)) || c->h_sc->rr0 > c->h_sc->bb) {
+                    c->mlp_fallbacks++;
+                    launch_warm(c->stream, FEPIC_WS_PREV, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
+                    cg_init();
+                }
+            }
+            const int first = (restart == 0 && c->last_cg_iters > 0) ? std::max(batch, c->last_cg_iters + 2) : batch;
+            int rc = iterate(first, [&](int i) {
+                if (aux)
+                    launch_pcg_iter(c->stream, i, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, c->aux, ZP,
+                                    c->d_rq, c->d_partial, c->d_sc);
+                else
+                    launch_cg_iter(c->stream, i, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, V, c->d_partial,
+                                   c->d_sc);
+            });
+            if (rc != FEPIC_OK) return rc;
+            if (restart == 0) rr0_first = c->h_sc->rr0;
+            total += c->h_sc->iters;
+            // The stopping rule is on the true residual.  If the recurrences drifted from it,
+            // or broke down (converged == 2: a non-positive or non-finite step), restart from
+            // the current iterate, up to kMaxRestarts times within the iteration budget.
+            rc = true_resid();
+            if (rc != FEPIC_OK) return rc;
+            const CgScalars& h = *c->h_sc;
+            if (h.rr_true <= h.tol2_bb || restart >= kMaxRestarts || total >= maxit || h.converged == 0) break;
+            c->cg_restarts++;
+        }
     }
     c->h_sc->iters = total;
     c->h_sc->rr0 = rr0_first;
@@ -555,6 +652,7 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
         st.cg_rel_resid = sc.bb > 0 ? std::sqrt(sc.rr_true / sc.bb) : 0.0;
         st.cg_rel_resid0 = sc.bb > 0 ? std::sqrt(sc.rr0 / sc.bb) : 0.0;
         st.pc_far_levels = c->opt.preconditioner == FEPIC_PC_AUX ? c->aux.n_far : -1;
+        st.cg_passes = c->cg_passes;
     }
     fill_phase_times(c, &st, solve);
     // failure: leave the state as it was before the call (the sort is a pure reorder)
@@ -740,6 +838,8 @@ void fepic_default_options(fepic_options* o) {
     o->preconditioner = FEPIC_PC_AUX;
     o->aux_far_levels = -1;
     o->walk = FEPIC_WALK_AUTO;
+    o->solve_precision = FEPIC_SOLVE_FP64;
+    o->mixed_inner_tol = 1e-4;
 }
 
 const char* fepic_error_string(int code) {
@@ -772,6 +872,9 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
     if (o.preconditioner != FEPIC_PC_JACOBI && o.preconditioner != FEPIC_PC_AUX) return FEPIC_E_ARG;
     if (o.aux_far_levels < -1 || o.aux_far_levels > kAuxFarLevels) return FEPIC_E_ARG;
     if (o.walk < FEPIC_WALK_AUTO || o.walk > FEPIC_WALK_FUSED) return FEPIC_E_ARG;
+    if (o.solve_precision != FEPIC_SOLVE_FP64 && o.solve_precision != FEPIC_SOLVE_MIXED) return FEPIC_E_ARG;
+    if (o.solve_precision == FEPIC_SOLVE_MIXED && o.preconditioner != FEPIC_PC_AUX) return FEPIC_E_ARG;
+    if (!(o.mixed_inner_tol > 0.0 && o.mixed_inner_tol < 1.0)) return FEPIC_E_ARG;
     if (o.cg_check_every < 1) o.cg_check_every = 8;
     fepic_ctx* c = new fepic_ctx();
     c->opt = o;
@@ -837,8 +940,22 @@ int fepic_set_allocator(fepic_ctx* c, void* (*alloc)(size_t bytes, void* user), 
 
 int fepic_set_preconditioner(fepic_ctx* c, int pc) {
     if (!c || (pc != FEPIC_PC_JACOBI && pc != FEPIC_PC_AUX)) return FEPIC_E_ARG;
+    if (pc == FEPIC_PC_JACOBI && c->opt.solve_precision == FEPIC_SOLVE_MIXED)
+        return fail(c, FEPIC_E_ARG, "the mixed-precision solve needs the auxiliary-space preconditioner");
     if (c->opt.preconditioner != pc) c->last_cg_iters = 0;   // batch sizing starts afresh
     c->opt.preconditioner = pc;
+    return FEPIC_OK;
+}
+
+int fepic_set_solve_precision(fepic_ctx* c, int sp) {
+    if (!c || (sp != FEPIC_SOLVE_FP64 && sp != FEPIC_SOLVE_MIXED)) return FEPIC_E_ARG;
+    if (sp == FEPIC_SOLVE_MIXED && c->opt.preconditioner != FEPIC_PC_AUX)
+        return fail(c, FEPIC_E_ARG, "the mixed-precision solve needs the auxiliary-space preconditioner");
+    if (c->opt.solve_precision != sp) {
+        c->last_cg_iters = 0;
+        for (int& n : c->last_pass_iters) n = 0;
+    }
+    c->opt.solve_precision = sp;
     return FEPIC_OK;
 }
 

@@ -79,6 +79,13 @@ struct fepic_ctx {
     // auxiliary-space PCG: (z, p) pairs double buffered, r and q (n_edges each), nodal arrays
     double2* d_zp[2] = {nullptr, nullptr};
     double2* d_rq = nullptr;
+    // FP32 inner solves of the mixed-precision form (allocated on first use): A and D^-1,
+    // the correction d, r and q, (z, p) pairs; valid for the operator of A_scale
+    float *d_A32 = nullptr, *d_dinv32 = nullptr, *d_x32 = nullptr, *d_rq32 = nullptr;
+    float2* d_zp32[2] = {nullptr, nullptr};
+    bool A32_valid = false;
+    int last_pass_iters[8] = {};   // iterations of each pass of the last mixed solve
+    int cg_passes = 0;             // passes of the last mixed solve
     fepic::AuxSpace aux;
     double* d_partial = nullptr;
     fepic::CgScalars* d_sc = nullptr;

@@ -149,6 +149,12 @@ struct AuxSpace {
     int n_far = 0;                              // far levels in use (0 .. kAuxFarLevels)
     double4* Y = nullptr;         // [n_aux + 1] nodal corrections of the residual, all levels;
                                   // Y[n_aux] = 0
+    // FP32 copies for the inner solves of the mixed-precision form (null until first used)
+    float4* scale_f = nullptr;
+    float4* scale8_f = nullptr;
+    float4* scale64_f = nullptr;
+    float4* far_scale_f[kAuxFarLevels] = {};
+    float4* Y_f = nullptr;        // [n_aux + 1], Y_f[n_aux] = 0
 };
 
 // Device-side diagnostics accumulators (max-abs values stored as ordered bit patterns).
@@ -222,6 +228,16 @@ void launch_pcg_init(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, co
 void launch_pcg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
                      const double* A, const double* dinv, double* x, const AuxSpace& g, double2* const zp[2],
                      double2* rq, double* partial, CgScalars* sc);
+void launch_pcg_init_f32(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
+                         const float* A32, const float* dinv32, const double* r_true, float* d, const AuxSpace& g,
+                         float2* zp0, float* rq, double* partial, CgScalars* sc, double tol);
+void launch_pcg_iter_f32(hipStream_t s, int i, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
+                         const float* A32, const float* dinv32, float* d, const AuxSpace& g, float2* const zp[2],
+                         float* rq, double* partial, CgScalars* sc);
+void launch_operator_f32(hipStream_t s, int64_t nnz, const double* A, float* A32, int64_t n_rows, const double* dinv,
+                         float* dinv32, const AuxSpace& g);
+void launch_add_f32(hipStream_t s, double* x, const float* d, int64_t n);
+void launch_pcg_rhs_norm(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc, double tol);
 void launch_pcg_rr0(hipStream_t s, double* partial, CgScalars* sc);
 void launch_cg_resid(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
                      const double* A, const double* b, double* x, double* r_true, double* partial,

@@ -633,16 +633,63 @@ __device__ __forceinline__ double* far_line(const AuxSpace& g, int L, int64_t a,
     return reinterpret_cast<double*>(g.far_acc[L]) + 8 * (4 * a + comp);
 }
 
-// ||b||^2 from the right-hand side's partials; r = b - A x, q = 0; clears the four
-// reduction buffers and the far levels' accumulators.
+// Storage of the iteration: FP64, or FP32 for the inner solves of the mixed-precision
+// form (scalars and dot products stay FP64 either way).
+template <typename S>
+struct Vec;
+template <>
+struct Vec<double> {
+    using t2 = double2;
+    using t3 = double3;
+    using t4 = double4;
+    static __device__ __forceinline__ double2 two(double a, double b) { return make_double2(a, b); }
+    static __device__ __forceinline__ double4 four(double a, double b, double c, double d) {
+        return make_double4(a, b, c, d);
+    }
+};
+template <>
+struct Vec<float> {
+    using t2 = float2;
+    using t3 = float3;
+    using t4 = float4;
+    static __device__ __forceinline__ float2 two(float a, float b) { return make_float2(a, b); }
+    static __device__ __forceinline__ float4 four(float a, float b, float c, float d) {
+        return make_float4(a, b, c, d);
+    }
+};
+
+// The FP64 or the FP32 copy of an auxiliary-space array.
+template <typename S, typename D, typename F>
+__device__ __forceinline__ auto pick(D d, F f) {
+    if constexpr (sizeof(S) == 8)
+        return d;
+    else
+        return f;
+}
+
+template <typename S>
+__device__ __forceinline__ typename Vec<S>::t3 edge_vec_t(const AuxSpace& g, int64_t e) {
+    const EdgeVec t = g.th[e];
+    typename Vec<S>::t3 v;
+    v.x = (S)(float)t.x;
+    v.y = (S)(float)t.y;
+    v.z = (S)(float)t.z;
+    return v;
+}
+
+// ||b||^2 from the partials of the kernel that summed it (the right-hand side's, or the
+// true residual's for an inner solve); r = b - A x, or with zero_x r = b and x = 0 (the
+// inner solves start from zero); q = 0; clears the four reduction buffers and the far
+// levels' accumulators.
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
-                                                      const int32_t* __restrict__ col, const double* __restrict__ A,
-                                                      const double* __restrict__ b, const double* __restrict__ x,
-                                                      double* __restrict__ R, double* __restrict__ Q,
-                                                      const double* __restrict__ part_rhs,
-                                                      double* cg_slots, CgScalars* sc, double tol, AuxSpace g) {
+                                                      const int32_t* __restrict__ col, const S* __restrict__ A,
+                                                      const double* __restrict__ b, S* __restrict__ x, bool zero_x,
+                                                      S* __restrict__ R, S* __restrict__ Q,
+                                                      const double* __restrict__ part_b, double* cg_slots,
+                                                      CgScalars* sc, double tol, AuxSpace g) {
     double bb[1];
-    read_partials<1>(part_rhs, gridDim.x, bb);
+    read_partials<1>(part_b, gridDim.x, bb);
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) {
             sc->bb = bb[0];
@@ -655,39 +702,51 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(int64_t n_rows, RowGrid rg,
     for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
         const int64_t row = lb * kBlock + threadIdx.x;
         if (((row >> 6) << 6) >= n_rows) continue;
-        const double ax = sell_row(sp, col, A, row, [&](int c) { return x[c]; });
-        if (row < n_rows) {
-            R[row] = b[row] - ax;
-            Q[row] = 0.0;
+        if (zero_x) {
+            if (row < n_rows) {
+                R[row] = (S)b[row];
+                Q[row] = S(0);
+                x[row] = S(0);
+            }
+            continue;
+        }
+        if constexpr (sizeof(S) == 8) {
+            const double ax = sell_row(sp, col, A, row, [&](int c) { return x[c]; });
+            if (row < n_rows) {
+                R[row] = b[row] - ax;
+                Q[row] = 0.0;
+            }
         }
     }
 }
 
 // Row j of A p split by the iteration's scalar: sum_k A_jk z_k and sum_k A_jk p_k over
 // the stored entries, so the gathers are issued before beta is known; own (z, p).
+template <typename S>
 struct QPart {
-    double sZ, sP;
-    double2 own;
+    S sZ, sP;
+    typename Vec<S>::t2 own;
 };
 
-__device__ __forceinline__ void q_part(QPart& P, const int64_t* __restrict__ sp, const int32_t* __restrict__ col,
-                                       const double* __restrict__ A, const double2* __restrict__ ZP, int64_t row,
-                                       bool real) {
+template <typename S>
+__device__ __forceinline__ void q_part(QPart<S>& P, const int64_t* __restrict__ sp, const int32_t* __restrict__ col,
+                                       const S* __restrict__ A, const typename Vec<S>::t2* __restrict__ ZP,
+                                       int64_t row, bool real) {
     const int64_t sl = row >> 6;
     const int lane = (int)(row & 63);
     const int64_t k1 = sp[sl + 1];
     int64_t k = sp[sl] + lane;
     P.own = ZP[real ? row : 0];
-    double z0 = 0.0, p0 = 0.0, z1 = 0.0, p1 = 0.0;
+    S z0 = S(0), p0 = S(0), z1 = S(0), p1 = S(0);
     for (; k + (kUnroll - 1) * 64 < k1; k += kUnroll * 64) {
         int c[kUnroll];
-        double a[kUnroll];
+        S a[kUnroll];
 #pragma unroll
         for (int q = 0; q < kUnroll; ++q) {
             c[q] = col[k + 64 * q];
             a[q] = A[k + 64 * q];
         }
-        double2 zp[kUnroll];
+        typename Vec<S>::t2 zp[kUnroll];
 #pragma unroll
         for (int q = 0; q < kUnroll; ++q) zp[q] = ZP[c[q]];
 #pragma unroll
@@ -699,8 +758,8 @@ __device__ __forceinline__ void q_part(QPart& P, const int64_t* __restrict__ sp,
         }
     }
     for (; k < k1; k += 64) {
-        const double a = A[k];
-        const double2 zp = ZP[col[k]];
+        const S a = A[k];
+        const typename Vec<S>::t2 zp = ZP[col[k]];
         z0 += a * zp.x;
         p0 += a * zp.y;
     }
@@ -711,19 +770,20 @@ __device__ __forceinline__ void q_part(QPart& P, const int64_t* __restrict__ sp,
 // The convergence test of iterate i (its (r, r) from reduction 2i - 1), beta, the new
 // direction p = z + beta p and q = A p (only q is stored: the update kernel forms the same
 // p from the same operands); (p, q) into reduction 2i.
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_pcg_q(int64_t n_rows, RowGrid rg, int i, const int64_t* __restrict__ sp,
-                                                   const int32_t* __restrict__ col, const double* __restrict__ A,
-                                                   const double2* __restrict__ ZP, double* __restrict__ Q,
+                                                   const int32_t* __restrict__ col, const S* __restrict__ A,
+                                                   const typename Vec<S>::t2* __restrict__ ZP, S* __restrict__ Q,
                                                    double* __restrict__ cg_slots, CgScalars* sc, AuxSpace aux) {
     const int conv = sc->converged;
     double t[2];
     slot_load<2>(red_buf(cg_slots, 2 * i - 1), t);
     int64_t lb = rg_first(rg);
     const int64_t le = rg_end(rg);
-    QPart P;
+    QPart<S> P;
     int64_t row = lb * kBlock + threadIdx.x;
     bool active = lb < le && ((row >> 6) << 6) < n_rows;
-    if (active) q_part(P, sp, col, A, ZP, row, row < n_rows);
+    if (active) q_part<S>(P, sp, col, A, ZP, row, row < n_rows);
     if (conv) return;
     block_sum_all<2>(t);
     const double g = t[0], rr = t[1];
@@ -740,18 +800,19 @@ __global__ __launch_bounds__(kBlock) void k_pcg_q(int64_t n_rows, RowGrid rg, in
     }
     if (done || bad) return;
     if (blockIdx.x == 0) clear_far(aux);   // read by the previous update, added to by the next node pass
+    const S bs = (S)beta;
     double v[1] = {0.0};
     while (lb < le) {
         if (active && row < n_rows) {
-            const double p = P.own.x + beta * P.own.y;
-            const double q = P.sZ + beta * P.sP;
+            const S p = P.own.x + bs * P.own.y;
+            const S q = P.sZ + bs * P.sP;
             Q[row] = q;
-            v[0] += p * q;
+            v[0] += (double)p * (double)q;
         }
         lb += rg.g;
         row = lb * kBlock + threadIdx.x;
         active = lb < le && ((row >> 6) << 6) < n_rows;
-        if (active) q_part(P, sp, col, A, ZP, row, row < n_rows);
+        if (active) q_part<S>(P, sp, col, A, ZP, row, row < n_rows);
     }
     block_sum_all<1>(v);
     slot_add<1>(red_buf(cg_slots, 2 * i), v);
@@ -763,12 +824,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_q(int64_t n_rows, RowGrid rg, in
 // the four partial sums meet in LDS.  Padding entries read edge 0 and count zero.
 constexpr int kNodePhases = kBlock / 64;
 
-__device__ __forceinline__ void node_part(double P[8], const AuxSpace& g, const double* __restrict__ R,
-                                          const double* __restrict__ Q, int64_t sl,
-                                          int lane, int j) {
+template <typename S>
+__device__ __forceinline__ void node_part(S P[8], const AuxSpace& g, const S* __restrict__ R,
+                                          const S* __restrict__ Q, int64_t sl, int lane, int j) {
     const int64_t k0 = g.sp[sl] + lane, k1 = g.sp[sl + 1];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) P[v] = 0.0;
+    for (int v = 0; v < 8; ++v) P[v] = S(0);
     constexpr int U = 4;   // slots per thread in flight together (about all of a node's share)
     for (int64_t k = k0 + 64 * j; k < k1; k += U * kNodePhases * 64) {
         int32_t c[U];
@@ -777,39 +838,40 @@ __device__ __forceinline__ void node_part(double P[8], const AuxSpace& g, const 
             const int64_t kk = k + (int64_t)q * kNodePhases * 64;
             c[q] = kk < k1 ? g.inc[kk] : kAuxPad;
         }
-        double rv[U], qv[U];
-        double3 th[U];
-        double s[U];
+        S rv[U], qv[U];
+        typename Vec<S>::t3 th[U];
+        S s[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const bool ok = c[q] != kAuxPad;
             const int32_t e = ok ? (c[q] >= 0 ? c[q] : ~c[q]) : 0;
-            s[q] = ok ? (c[q] >= 0 ? 1.0 : -1.0) : 0.0;
+            s[q] = ok ? (c[q] >= 0 ? S(1) : S(-1)) : S(0);
             rv[q] = R[e];
             qv[q] = Q[e];
-            th[q] = edge_vec(g, e);
+            th[q] = edge_vec_t<S>(g, e);
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            const double r = s[q] != 0.0 ? rv[q] : 0.0, qq = s[q] != 0.0 ? qv[q] : 0.0;
+            const S r = s[q] != S(0) ? rv[q] : S(0), qq = s[q] != S(0) ? qv[q] : S(0);
             P[0] += s[q] * r;
             P[1] += s[q] * qq;
-            P[2] += (double)th[q].x * r;
-            P[3] += (double)th[q].y * r;
-            P[4] += (double)th[q].z * r;
-            P[5] += (double)th[q].x * qq;
-            P[6] += (double)th[q].y * qq;
-            P[7] += (double)th[q].z * qq;
+            P[2] += th[q].x * r;
+            P[3] += th[q].y * r;
+            P[4] += th[q].z * r;
+            P[5] += th[q].x * qq;
+            P[6] += th[q].y * qq;
+            P[7] += th[q].z * qq;
         }
     }
 }
 
 // alpha from reduction 2i (i = -1: the start, alpha = 0); Y = (D_G^-1 G^T r', D_Pi^-1 Pi^T r').
 // rg runs over slices of 64 nodes.
-__global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpace g, const double* __restrict__ R,
-                                                       const double* __restrict__ Q,
-                                                       double* __restrict__ cg_slots, CgScalars* sc) {
-    __shared__ double part[8][kNodePhases][64];
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpace g, const S* __restrict__ R,
+                                                       const S* __restrict__ Q, double* __restrict__ cg_slots,
+                                                       CgScalars* sc) {
+    __shared__ S part[8][kNodePhases][64];
     const int conv = sc->converged;
     double t[1] = {0.0};
     if (i >= 0) slot_load<1>(red_buf(cg_slots, 2 * i), t);
@@ -817,8 +879,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
     const int nl = threadIdx.x >> 2, comp = threadIdx.x & 3;   // output: node of the slice, component
     int64_t sl = rg_first(rg);
     const int64_t le = rg_end(rg);
-    double P[8];
-    if (sl < le) node_part(P, g, R, Q, sl, lane, j);
+    S P[8];
+    if (sl < le) node_part<S>(P, g, R, Q, sl, lane, j);
     if (conv) return;
     double alpha = 0.0;
     if (i >= 0) {
@@ -830,11 +892,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
         }
     }
     if (blockIdx.x == 0) clear_buf(red_buf(cg_slots, 2 * i + 1));
-    const double* scale = reinterpret_cast<const double*>(g.scale);
-    const double* scale8 = reinterpret_cast<const double*>(g.scale8);
-    const double* scale64 = reinterpret_cast<const double*>(g.scale64);
-    double* Y = reinterpret_cast<double*>(g.Y);
-    __shared__ double wsum[kNodePhases][4];
+    const S as = (S)alpha;
+    const S* scale = reinterpret_cast<const S*>(pick<S>(g.scale, g.scale_f));
+    const S* scale8 = reinterpret_cast<const S*>(pick<S>(g.scale8, g.scale8_f));
+    const S* scale64 = reinterpret_cast<const S*>(pick<S>(g.scale64, g.scale64_f));
+    S* Y = reinterpret_cast<S*>(pick<S>(g.Y, g.Y_f));
+    __shared__ S wsum[kNodePhases][4];
     // component comp of P^T r' at node nl: (sum of value va) - alpha (sum of value vb)
     const int va = comp == 0 ? 0 : 1 + comp, vb = comp == 0 ? 1 : 4 + comp;
     while (sl < le) {
@@ -842,23 +905,23 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
         for (int v = 0; v < 8; ++v) part[v][j][lane] = P[v];
         __syncthreads();
         const int64_t node = sl * 64 + nl;
-        double a = 0.0, b = 0.0;
+        S a = S(0), b = S(0);
 #pragma unroll
         for (int q = 0; q < kNodePhases; ++q) {
             a += part[va][q][nl];
             b += part[vb][q][nl];
         }
-        const double u = a - alpha * b;   // zero for the padding nodes of the last slice
+        const S u = a - as * b;   // zero for the padding nodes of the last slice
         // the aggregate of 8 nodes: lanes 4 nl + comp with the same comp and nl >> 3
-        double s8 = u;
+        S s8 = u;
         s8 += __shfl_xor(s8, 4);
         s8 += __shfl_xor(s8, 8);
         s8 += __shfl_xor(s8, 16);
         // the aggregate of 64 nodes (the slice): the wave's two groups, then the four waves
-        double s16 = s8 + __shfl_xor(s8, 32);
+        S s16 = s8 + __shfl_xor(s8, 32);
         if (lane < 4) wsum[j][lane] = s16;
         __syncthreads();
-        double s64 = 0.0;
+        S s64 = S(0);
 #pragma unroll
         for (int q = 0; q < kNodePhases; ++q) s64 += wsum[q][comp];
         if (node < g.n_aux)
@@ -870,46 +933,51 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
         if (threadIdx.x < 4) {   // comp = threadIdx.x
 #pragma unroll
             for (int L = 0; L < kAuxFarLevels; ++L)
-                if (L < g.n_far) unsafeAtomicAdd(far_line(g, L, (sl * 64) >> aux_far_log(L), comp), s64);
+                if (L < g.n_far) unsafeAtomicAdd(far_line(g, L, (sl * 64) >> aux_far_log(L), comp), (double)s64);
         }
         __syncthreads();
         sl += rg.g;
-        if (sl < le) node_part(P, g, R, Q, sl, lane, j);
+        if (sl < le) node_part<S>(P, g, R, Q, sl, lane, j);
     }
 }
 
 // A row's own values for the update.
+template <typename S>
 struct UPart {
-    double r, q;
-    double2 zp;
-    double x, dinv;
-    double3 th;
-    double4 ya, yb;
+    S r, q;
+    typename Vec<S>::t2 zp;
+    S x, dinv;
+    typename Vec<S>::t3 th;
+    typename Vec<S>::t4 ya, yb;
 };
 
-__device__ __forceinline__ void u_part(UPart& P, const AuxSpace& g, const double* __restrict__ dinv,
-                                       const double* __restrict__ x, const double2* __restrict__ ZP,
-                                       const double* __restrict__ R, const double* __restrict__ Q, int64_t row) {
+template <typename S>
+__device__ __forceinline__ void u_part(UPart<S>& P, const AuxSpace& g, const S* __restrict__ dinv,
+                                       const S* __restrict__ x, const typename Vec<S>::t2* __restrict__ ZP,
+                                       const S* __restrict__ R, const S* __restrict__ Q, int64_t row) {
     P.r = R[row];
     P.q = Q[row];
     P.zp = ZP[row];
     P.x = x[row];
     P.dinv = dinv[row];
-    P.th = edge_vec(g, row);
+    P.th = edge_vec_t<S>(g, row);
     const int2 en = g.ends[row];
-    P.ya = g.Y[en.x];
-    P.yb = g.Y[en.y];
+    const typename Vec<S>::t4* Y = pick<S>(g.Y, g.Y_f);
+    P.ya = Y[en.x];
+    P.yb = Y[en.y];
     // far levels: an edge's two ends mostly share their aggregate, whose correction is then
     // loaded once and added at both ends (the same sums as two loads)
 #pragma unroll
     for (int L = 0; L < kAuxFarLevels; ++L) {
         if (L >= g.n_far) break;
+        const typename Vec<S>::t4* fs = pick<S>(g.far_scale[L], g.far_scale_f[L]);
         const int64_t a = en.x < g.n_aux ? ((int64_t)en.x >> aux_far_log(L)) : -1;
         const int64_t b = en.y < g.n_aux ? ((int64_t)en.y >> aux_far_log(L)) : -1;
         if (a >= 0) {
-            const double4 d = g.far_scale[L][a];
-            const double4 v = make_double4(*far_line(g, L, a, 0) * d.x, *far_line(g, L, a, 1) * d.y,
-                                           *far_line(g, L, a, 2) * d.z, *far_line(g, L, a, 3) * d.w);
+            const typename Vec<S>::t4 d = fs[a];
+            const typename Vec<S>::t4 v =
+                Vec<S>::four((S)*far_line(g, L, a, 0) * d.x, (S)*far_line(g, L, a, 1) * d.y,
+                             (S)*far_line(g, L, a, 2) * d.z, (S)*far_line(g, L, a, 3) * d.w);
             P.ya.x += v.x;
             P.ya.y += v.y;
             P.ya.z += v.z;
@@ -922,11 +990,11 @@ __device__ __forceinline__ void u_part(UPart& P, const AuxSpace& g, const double
             }
         }
         if (b >= 0 && b != a) {
-            const double4 d = g.far_scale[L][b];
-            P.yb.x += *far_line(g, L, b, 0) * d.x;
-            P.yb.y += *far_line(g, L, b, 1) * d.y;
-            P.yb.z += *far_line(g, L, b, 2) * d.z;
-            P.yb.w += *far_line(g, L, b, 3) * d.w;
+            const typename Vec<S>::t4 d = fs[b];
+            P.yb.x += (S)*far_line(g, L, b, 0) * d.x;
+            P.yb.y += (S)*far_line(g, L, b, 1) * d.y;
+            P.yb.z += (S)*far_line(g, L, b, 2) * d.z;
+            P.yb.w += (S)*far_line(g, L, b, 3) * d.w;
         }
     }
 }
@@ -934,20 +1002,22 @@ __device__ __forceinline__ void u_part(UPart& P, const AuxSpace& g, const double
 // x += alpha p with p = z + beta p from the pair k_pcg_q(i) read (not at the start),
 // r' = r - alpha q, z' = D^-1 r' + G y + Pi v; the pair (z', p) into the other buffer;
 // (r', z') and (r', r') into reduction 2i + 1.
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n_rows, RowGrid rg, int i, AuxSpace g,
-                                                        const double* __restrict__ dinv, double* __restrict__ x,
-                                                        const double2* __restrict__ ZP, double2* __restrict__ ZPn,
-                                                        double* __restrict__ R, const double* __restrict__ Q,
-                                                        double* __restrict__ cg_slots, CgScalars* sc) {
+                                                        const S* __restrict__ dinv, S* __restrict__ x,
+                                                        const typename Vec<S>::t2* __restrict__ ZP,
+                                                        typename Vec<S>::t2* __restrict__ ZPn, S* __restrict__ R,
+                                                        const S* __restrict__ Q, double* __restrict__ cg_slots,
+                                                        CgScalars* sc) {
     const int conv = sc->converged;
     double t[1] = {0.0};
     if (i >= 0) slot_load<1>(red_buf(cg_slots, 2 * i), t);
     int64_t lb = rg_first(rg);
     const int64_t le = rg_end(rg);
-    UPart P;
+    UPart<S> P;
     int64_t row = lb * kBlock + threadIdx.x;
     bool active = lb < le && row < n_rows;
-    if (active) u_part(P, g, dinv, x, ZP, R, Q, row);
+    if (active) u_part<S>(P, g, dinv, x, ZP, R, Q, row);
     if (conv) return;
     double alpha = 0.0;
     if (i >= 0) {
@@ -958,26 +1028,50 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n_rows, RowGrid r
     // beta of this iteration, from the same operands as in k_pcg_q (the same bits)
     const double beta = (i <= 0) ? 0.0 : sc->gam[i & 1] / sc->gam[(i - 1) & 1];
     if (blockIdx.x == 0) clear_buf(red_buf(cg_slots, 2 * i + 2));
+    const S as = (S)alpha, bs = (S)beta;
     double v[2] = {0.0, 0.0};
     while (lb < le) {
         if (active) {
-            const double r = P.r - alpha * P.q;
-            const double p = i >= 0 ? P.zp.x + beta * P.zp.y : 0.0;
-            if (i >= 0) x[row] = P.x + alpha * p;
-            const double z = P.dinv * r + (P.yb.x - P.ya.x) + (double)P.th.x * (P.ya.y + P.yb.y) +
-                             (double)P.th.y * (P.ya.z + P.yb.z) + (double)P.th.z * (P.ya.w + P.yb.w);
+            const S r = P.r - as * P.q;
+            const S p = i >= 0 ? P.zp.x + bs * P.zp.y : S(0);
+            if (i >= 0) x[row] = P.x + as * p;
+            const S z = P.dinv * r + (P.yb.x - P.ya.x) + P.th.x * (P.ya.y + P.yb.y) + P.th.y * (P.ya.z + P.yb.z) +
+                        P.th.z * (P.ya.w + P.yb.w);
             R[row] = r;
-            ZPn[row] = make_double2(z, p);
-            v[0] += r * z;
-            v[1] += r * r;
+            ZPn[row] = Vec<S>::two(z, p);
+            v[0] += (double)r * (double)z;
+            v[1] += (double)r * (double)r;
         }
         lb += rg.g;
         row = lb * kBlock + threadIdx.x;
         active = lb < le && row < n_rows;
-        if (active) u_part(P, g, dinv, x, ZP, R, Q, row);
+        if (active) u_part<S>(P, g, dinv, x, ZP, R, Q, row);
     }
     block_sum_all<2>(v);
     slot_add<2>(red_buf(cg_slots, 2 * i + 1), v);
+}
+
+// ||b||^2 and the tolerance from the right-hand side's partials (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_rhs_norm(const double* __restrict__ part_b, int n_src, CgScalars* sc,
+                                                      double tol) {
+    double bb[1];
+    read_partials<1>(part_b, n_src, bb);
+    if (threadIdx.x == 0) {
+        sc->bb = bb[0];
+        sc->tol2_bb = tol * tol * bb[0];
+        sc->converged = 0;
+    }
+}
+
+// FP32 copy of n values; x += d (FP64 from FP32).
+__global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_add_f32(double* __restrict__ x, const float* __restrict__ d, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] += (double)d[i];
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero_if_b_zero(double* x, int64_t n, const CgScalars* sc) {
@@ -1255,21 +1349,44 @@ void launch_aux_scale(hipStream_t s, const AuxSpace& g, const int64_t* sp, const
     }
 }
 
+namespace {
+template <typename S>
+void pcg_start(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const S* A, const S* dinv,
+               const double* b, S* x, bool zero_x, const AuxSpace& g, typename Vec<S>::t2* zp0, S* R, S* Q,
+               const double* part_b, double* slots, CgScalars* sc, double tol) {
+    const RowGrid rg = row_grid(n_rows);
+    hipLaunchKernelGGL(k_pcg_init<S>, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, b, x, zero_x, R, Q,
+                       part_b, slots, sc, tol, g);
+    const RowGrid ng = node_grid(g.n_aux);
+    hipLaunchKernelGGL(k_pcg_nodes<S>, dim3(ng.grid), dim3(kBlock), 0, s, ng, -1, g, (const S*)R, (const S*)Q, slots,
+                       sc);
+    const RowGrid ug = row_grid_full(n_rows);
+    hipLaunchKernelGGL(k_pcg_update<S>, dim3(ug.grid), dim3(kBlock), 0, s, n_rows, ug, -1, g, dinv, x,
+                       (const typename Vec<S>::t2*)zp0, zp0, R, (const S*)Q, slots, sc);
+}
+
+template <typename S>
+void pcg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int32_t* col, const S* A, const S* dinv,
+              S* x, const AuxSpace& g, typename Vec<S>::t2* const zp[2], S* R, S* Q, double* slots, CgScalars* sc) {
+    const RowGrid rg = row_grid_full(n_rows);
+    const RowGrid ng = node_grid(g.n_aux);
+    const int a = i & 1, b = 1 - a;
+    hipLaunchKernelGGL(k_pcg_q<S>, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A,
+                       (const typename Vec<S>::t2*)zp[a], Q, slots, sc, g);
+    hipLaunchKernelGGL(k_pcg_nodes<S>, dim3(ng.grid), dim3(kBlock), 0, s, ng, i, g, (const S*)R, (const S*)Q, slots,
+                       sc);
+    hipLaunchKernelGGL(k_pcg_update<S>, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, g, dinv, x,
+                       (const typename Vec<S>::t2*)zp[a], zp[b], R, (const S*)Q, slots, sc);
+}
+}  // namespace
+
 // The start: r = b - A x, then z = B r and the dots (r, z), (r, r) as reduction -1.
 void launch_pcg_init(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
                      const double* dinv, const double* b, const double* x, const AuxSpace& g, double2* zp0,
                      double2* rq, double* partial, CgScalars* sc, double tol) {
-    const RowGrid rg = row_grid(n_rows);
-    double* slots = partial + SLOT_CG * kSlot;
     double* R = reinterpret_cast<double*>(rq);
-    double* Q = R + n_rows;
-    hipLaunchKernelGGL(k_pcg_init, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, b, x, R, Q,
-                       partial + SLOT_RHS * kSlot, slots, sc, tol, g);
-    const RowGrid ng = node_grid(g.n_aux);
-    hipLaunchKernelGGL(k_pcg_nodes, dim3(ng.grid), dim3(kBlock), 0, s, ng, -1, g, R, Q, slots, sc);
-    const RowGrid ug = row_grid_full(n_rows);
-    hipLaunchKernelGGL(k_pcg_update, dim3(ug.grid), dim3(kBlock), 0, s, n_rows, ug, -1, g, dinv, const_cast<double*>(x),
-                       zp0, zp0, R, Q, slots, sc);
+    pcg_start<double>(s, n_rows, sp, col, A, dinv, b, const_cast<double*>(x), false, g, zp0, R, R + n_rows,
+                      partial + SLOT_RHS * kSlot, partial + SLOT_CG * kSlot, sc, tol);
 }
 
 // Iteration i: (z, p) pairs read from buffer i & 1, the new pair written to (i + 1) & 1;
@@ -1277,16 +1394,49 @@ void launch_pcg_init(hipStream_t s, int64_t n_rows, const int64_t* sp, const int
 void launch_pcg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
                      const double* dinv, double* x, const AuxSpace& g, double2* const zp[2], double2* rq,
                      double* partial, CgScalars* sc) {
-    const RowGrid rg = row_grid_full(n_rows);
-    const RowGrid ng = node_grid(g.n_aux);
-    double* slots = partial + SLOT_CG * kSlot;
-    const int a = i & 1, b = 1 - a;
     double* R = reinterpret_cast<double*>(rq);
-    double* Q = R + n_rows;
-    hipLaunchKernelGGL(k_pcg_q, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, zp[a], Q, slots, sc, g);
-    hipLaunchKernelGGL(k_pcg_nodes, dim3(ng.grid), dim3(kBlock), 0, s, ng, i, g, R, Q, slots, sc);
-    hipLaunchKernelGGL(k_pcg_update, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, g, dinv, x, zp[a], zp[b], R, Q,
-                       slots, sc);
+    pcg_iter<double>(s, i, n_rows, sp, col, A, dinv, x, g, zp, R, R + n_rows, partial + SLOT_CG * kSlot, sc);
+}
+
+// The inner solve of the mixed-precision form: A d = r in FP32 from d = 0, r the FP64
+// true residual that launch_cg_resid left in r_true (its norm from that kernel's partials).
+void launch_pcg_init_f32(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const float* A32,
+                         const float* dinv32, const double* r_true, float* d, const AuxSpace& g, float2* zp0,
+                         float* rq, double* partial, CgScalars* sc, double tol) {
+    pcg_start<float>(s, n_rows, sp, col, A32, dinv32, r_true, d, true, g, zp0, rq, rq + n_rows,
+                     partial + SLOT_RESID * kSlot, partial + SLOT_CG * kSlot, sc, tol);
+}
+
+void launch_pcg_iter_f32(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int32_t* col,
+                         const float* A32, const float* dinv32, float* d, const AuxSpace& g, float2* const zp[2],
+                         float* rq, double* partial, CgScalars* sc) {
+    pcg_iter<float>(s, i, n_rows, sp, col, A32, dinv32, d, g, zp, rq, rq + n_rows, partial + SLOT_CG * kSlot, sc);
+}
+
+// FP32 copies of the operator for the inner solves: A (all nnz stored slots), D^-1, and the
+// auxiliary space's inverse diagonals at every level.
+void launch_operator_f32(hipStream_t s, int64_t nnz, const double* A, float* A32, int64_t n_rows, const double* dinv,
+                         float* dinv32, const AuxSpace& g) {
+    auto cvt = [&](const void* a, void* b, int64_t n) {
+        if (n > 0)
+            hipLaunchKernelGGL(k_to_f32, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s,
+                               reinterpret_cast<const double*>(a), reinterpret_cast<float*>(b), n);
+    };
+    cvt(A, A32, nnz);
+    cvt(dinv, dinv32, n_rows);
+    cvt(g.scale, g.scale_f, 4 * g.n_aux);
+    cvt(g.scale8, g.scale8_f, 4 * ((g.n_aux + 7) / 8));
+    cvt(g.scale64, g.scale64_f, 4 * ((g.n_aux + 63) / 64));
+    for (int L = 0; L < kAuxFarLevels; ++L) cvt(g.far_scale[L], g.far_scale_f[L], 4 * aux_far_count(g.n_aux, L));
+}
+
+void launch_pcg_rhs_norm(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc, double tol) {
+    hipLaunchKernelGGL(k_rhs_norm, dim3(1), dim3(kBlock), 0, s, partial + SLOT_RHS * kSlot, (int)row_grid(n_rows).grid,
+                       sc, tol);
+}
+
+void launch_add_f32(hipStream_t s, double* x, const float* d, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_add_f32, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, x, d, n);
 }
 
 void launch_pcg_rr0(hipStream_t s, double* partial, CgScalars* sc) {

@@ -15,12 +15,13 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfepic.so")
 
-ABI_VERSION = 3   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
+ABI_VERSION = 4   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
 FEPIC_OK = 0
 FEPIC_FP32_PUSH_FP64_ACC, FEPIC_ALL_FP64 = 0, 1
 FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP = 0, 1, 2, 3
 FEPIC_PC_JACOBI, FEPIC_PC_AUX = 0, 1
 FEPIC_WALK_AUTO, FEPIC_WALK_QUEUE, FEPIC_WALK_FUSED = 0, 1, 2
+FEPIC_SOLVE_FP64, FEPIC_SOLVE_MIXED = 0, 1
 FEPIC_E_CG_NOT_CONVERGED = -6
 FEPIC_E_CROSSING_CAP = -7
 FEPIC_MLP_N_PARAMS = 4545
@@ -34,7 +35,7 @@ class fepic_options(ctypes.Structure):
                 ("cg_max_iters", ctypes.c_int), ("cg_check_every", ctypes.c_int), ("sort_period", ctypes.c_int),
                 ("crossing_cap", ctypes.c_int), ("warm_start", ctypes.c_int), ("diagnostics", ctypes.c_int),
                 ("timing", ctypes.c_int), ("preconditioner", ctypes.c_int), ("aux_far_levels", ctypes.c_int),
-                ("walk", ctypes.c_int)]
+                ("walk", ctypes.c_int), ("solve_precision", ctypes.c_int), ("mixed_inner_tol", ctypes.c_double)]
 
 
 class fepic_step_stats(ctypes.Structure):
@@ -48,7 +49,7 @@ class fepic_step_stats(ctypes.Structure):
                 ("ms_rhs", ctypes.c_float), ("ms_warm", ctypes.c_float), ("ms_cg", ctypes.c_float),
                 ("ms_faraday", ctypes.c_float), ("ms_diag", ctypes.c_float),
                 ("magnetic_energy", ctypes.c_double), ("kinetic_energy", ctypes.c_double),
-                ("pc_far_levels", ctypes.c_int)]
+                ("pc_far_levels", ctypes.c_int), ("cg_passes", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -113,6 +114,7 @@ _SIGS = {
     "fepic_ws_set_weights": [_P, _P, _I64],
     "fepic_set_warm_start": [_P, _INT],
     "fepic_set_preconditioner": [_P, _INT],
+    "fepic_set_solve_precision": [_P, _INT],
     "fepic_mlp_forward": [_P, _I64, _P, _P],
     "fepic_mlp_grad": [_P, _I64, _P, _P, _P, ctypes.POINTER(_D)],
     "fepic_save": [_P, ctypes.c_char_p],
@@ -430,6 +432,10 @@ def fepic_set_warm_start(ctx, mode):
 
 def fepic_set_preconditioner(ctx, pc):
     _check(ctx, lib().fepic_set_preconditioner(ctx, int(pc)))
+
+
+def fepic_set_solve_precision(ctx, solve_precision):
+    _check(ctx, lib().fepic_set_solve_precision(ctx, int(solve_precision)))
 
 
 def fepic_mlp_forward(ctx, X):

@@ -37,7 +37,9 @@ def c2_beam(n_particles=1_000_000, seed=0, n_rings=12, n_layers=78):
     filling z in [0, 0.5) (the steady state of a 0.25 A beam injected at z = 0), 1 keV drift
     along z with a 1 eV Gaussian thermal spread; dt = 1e-10 s; weight from the injection
     rate of 3,750 macro-particles per step carrying 0.25 A.  The beam drifts as a whole,
-    so particles sorted by tet stay nearly sorted: re-sorting every 4th step is enough."""
+    so particles sorted by tet stay nearly sorted: re-sorting every 4th step is enough.
+    Newmark solve: FP64 residuals around FP32 inner solves that each reduce the residual
+    by 1e-5 (two passes per step)."""
     xyz, tets = inputs.prism_cylinder(0.05, 0.5, n_rings, n_layers)
     dt = 1e-10
     per_step = 3750
@@ -45,7 +47,7 @@ def c2_beam(n_particles=1_000_000, seed=0, n_rings=12, n_layers=78):
     x, u = inputs.beam_particles(n_particles, 0.01, 0.0, 0.5, 1000.0, 1.0, M_E, seed)
     return dict(name="c2_beam", xyz=xyz, tets=tets, B0=None,
                 species=[dict(q=-E_CHARGE, m=M_E, w=w, x=x, u=u)], dt=dt, beta=0.25, gamma=0.5,
-                inject_per_step=per_step, precision=0, sort_period=4)
+                inject_per_step=per_step, precision=0, sort_period=4, solve="mixed", inner_tol=1e-5)
 
 
 def c2_injection_batch(step, seed=0, per_step=3750):
@@ -57,7 +59,8 @@ def c3_plasma(n_pairs=8_000_000, n_cells=55, seed=0):
     """Neutral plasma ball: Kuhn mesh of [-4, 4]^3 cm (55^3 cubes, 998,250 tets), electrons
     and protons (mass ratio 1836) co-located in pairs from a Gaussian of width 1 cm
     truncated at 3.9 sigma, Te = 1 eV, Ti = 0.1 eV; peak density 2.5e13 m^-3 sets the
-    weight; dt = 0.05 / omega_pe."""
+    weight; dt = 0.05 / omega_pe.  Newmark solve: FP64 residuals around FP32 inner solves
+    that each reduce the residual by 3e-4 (deeper FP32 passes converge more slowly here)."""
     xyz, tets = inputs.kuhn_cube(n_cells, lo=(-0.04,) * 3, hi=(0.04,) * 3)
     m_p = inputs.PROTON_ELECTRON_MASS_RATIO * M_E
     x, ue, ui = inputs.gaussian_ball_pairs(n_pairs, 0.01, 3.9, 1.0, 0.1, M_E, m_p, seed)
@@ -68,7 +71,7 @@ def c3_plasma(n_pairs=8_000_000, n_cells=55, seed=0):
     wpe = math.sqrt(n0 * E_CHARGE ** 2 / (eps0 * M_E))
     return dict(name="c3_plasma", xyz=xyz, tets=tets, B0=None,
                 species=[dict(q=-E_CHARGE, m=M_E, w=w, x=x, u=ue), dict(q=E_CHARGE, m=m_p, w=w, x=x, u=ui)],
-                dt=0.05 / wpe, beta=0.25, gamma=0.5, precision=0)
+                dt=0.05 / wpe, beta=0.25, gamma=0.5, precision=0, solve="mixed", inner_tol=3e-4)
 
 
 def c5_plasma(n_pairs=64_000_000, n_cells=110, seed=0):

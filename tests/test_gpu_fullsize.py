@@ -2,8 +2,8 @@
 macro-particles, 3,750 injected per step, dt = 1e-10 s) in the launch configuration the
 benchmark times (FP32 push / FP64 deposit, the workload's sort period of 4 steps, so one
 step from sorted and one from unsorted particles, crossing paths finished in the first
-kernel, auxiliary-space PCG, warm start from e^n), against the FP64 oracle fed the same
-seeded inputs.
+kernel, auxiliary-space PCG with the workload's mixed-precision solve, warm start from
+e^n), against the FP64 oracle fed the same seeded inputs.
 
 The oracle finishes a whole step of this size in seconds, so every particle, every edge
 and face DoF is compared, with the tolerances of the small parity tests (positions within
@@ -30,6 +30,13 @@ def F():
     return require_lib()
 
 
+def _solve_opts(F, wl):
+    """The workload's Newmark solve settings, as the benchmark runs them."""
+    if wl.get("solve") == "mixed":
+        return {"solve_precision": F.FEPIC_SOLVE_MIXED, "mixed_inner_tol": wl["inner_tol"]}
+    return {"solve_precision": F.FEPIC_SOLVE_FP64}
+
+
 def test_beam_full_size_two_steps(F):
     announce("full-size beam: 202,176 tets, 1M particles, 2 steps with injection")
     wl = workloads.c2_beam()
@@ -46,7 +53,7 @@ def test_beam_full_size_two_steps(F):
     osim.init_electrostatic(tol=1e-13)
 
     L = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=wl["precision"], warm_start=F.FEPIC_WS_PREV,
-                     sort_period=wl["sort_period"])
+                     sort_period=wl["sort_period"], **_solve_opts(F, wl))
     try:
         s = F.fepic_add_species(L.ctx, sp["q"], sp["m"], sp["w"])
         assert F.fepic_upload_particles(L.ctx, s, sp["x"], sp["u"], ids=ids) == 0
@@ -70,7 +77,7 @@ def test_beam_full_size_two_steps(F):
 
             st = F.fepic_step(L.ctx, dt, beta, gamma)
             ost = osim.step(dt, beta, gamma)
-            print(f"\n[full] step {k}: lib cg {st.cg_iters} iters, {st.n_particles} particles, {st.n_crossings} "
+            print(f"\n[full] step {k}: lib cg {st.cg_iters} iters ({st.cg_passes} passes), {st.n_particles} particles, {st.n_crossings} "
                   f"crossings; oracle cg {ost['cg_iters']}, {ost['n_particles']}, {ost['n_crossings']}")
 
             e, _, b = F.fepic_get_fields(L.ctx)
@@ -115,7 +122,7 @@ def test_plasma_full_size_sampled(F):
     # the first step has no crossing history: take the queue form the plasma's 15 % share
     # of crossing particles selects from the second step on
     L = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=wl["precision"], warm_start=F.FEPIC_WS_PREV,
-                     sort_period=1, walk=F.FEPIC_WALK_QUEUE)
+                     sort_period=1, walk=F.FEPIC_WALK_QUEUE, **_solve_opts(F, wl))
     try:
         sps, sos = [], []
         for sp in wl["species"]:

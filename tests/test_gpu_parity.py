@@ -278,6 +278,50 @@ def test_preconditioned_cg_vs_oracle_pcg(F, pc, n, cfl_ratio, far):
     assert np.abs(eg[m.boundary_edge]).max() == 0.0
 
 
+@pytest.mark.parametrize("n,cfl_ratio,far", [(7, 4.0, -1), (16, 8.0, -1), (22, 20.0, -1), (16, 40.0, 3)])
+def test_mixed_precision_solve_vs_oracle(F, n, cfl_ratio, far):
+    """The mixed-precision solve (FP64 residuals, FP32 inner PCG from zero): the true FP64
+    residual meets 1e-10, the fields are as close to the direct solve as the FP64 PCG's,
+    and the passes and the total of inner iterations agree with the oracle's refinement
+    with the same levels and inner tolerance (FP32 sums in another order move a few
+    iterations)."""
+    from oracle import auxspace, newmark
+    import scipy.sparse.linalg as spla
+    announce(f"mixed-precision PCG on a {n}^3 Kuhn mesh, dt = {cfl_ratio} x the explicit limit, far levels {far}")
+    xyz, tets, h = jittered_kuhn(n, seed=11)
+    osim = OracleSim(xyz, tets)
+    m = osim.mesh
+    rng = np.random.default_rng(8)
+    e = rng.normal(size=m.n_edges)
+    ep = e + 0.05 * rng.normal(size=m.n_edges)
+    e[m.boundary_edge] = ep[m.boundary_edge] = 0.0
+    hmin = np.linalg.norm(m.xyz[m.edges[:, 1]] - m.xyz[m.edges[:, 0]], axis=1).min()
+    dt = cfl_ratio * hmin / C_LIGHT
+    ie = osim.ie
+    A, B1, B2 = osim.operators(dt, 0.25, 0.5)
+    rhs = newmark.newmark_rhs(B1, B2, e[ie], ep[ie], np.zeros(len(ie)))
+    with _lib_sim(F, xyz, tets, precision=0, preconditioner=F.FEPIC_PC_AUX, cg_check_every=4, aux_far_levels=far,
+                  solve_precision=F.FEPIC_SOLVE_MIXED) as L:
+        F.fepic_set_fields(L.ctx, e=e, e_prev=ep)
+        st = F.fepic_step(L.ctx, dt, 0.25, 0.5)
+        eg, _, _ = F.fepic_get_fields(L.ctx)
+    levels = (8, 64, 512, 4096, 32768)[:2 + st.pc_far_levels]
+    apply32 = auxspace.aux_space_preconditioner(A, m, levels=levels, dtype=np.float32)[0]
+    _, it_m, passes_m, res_m = auxspace.pcg_refined(A, rhs, e[ie], apply32, tol=1e-10, inner_tol=1e-4)
+    apply64 = auxspace.aux_space_preconditioner(A, m, levels=levels)[0]
+    x_o, it_o, _ = auxspace.pcg(A, rhs, e[ie], apply64, tol=1e-10)
+    x_direct = spla.spsolve(A.tocsc(), rhs)
+    err_o = np.linalg.norm(x_o - x_direct)
+    print(f"\n[mixed] n={n} levels {levels}: library {st.cg_iters} iterations in {st.cg_passes} passes, "
+          f"oracle refinement {it_m} in {passes_m}, oracle FP64 PCG {it_o}")
+    assert res_m <= 1e-10
+    assert st.cg_rel_resid <= 1e-10
+    assert abs(st.cg_passes - passes_m) <= 1 and st.cg_passes >= 1
+    assert abs(st.cg_iters - it_m) <= max(4, 0.1 * it_m)
+    assert np.linalg.norm(eg[ie] - x_direct) <= 10 * err_o + 1e-12 * np.linalg.norm(x_direct)
+    assert np.abs(eg[m.boundary_edge]).max() == 0.0
+
+
 def test_general_beta_gamma(F):
     announce("Newmark beta=0.3 gamma=0.6")
     xyz, tets, h = jittered_kuhn(5, seed=10)

@@ -108,3 +108,26 @@ def test_bench_byte_model_and_profile_bookkeeping(tmp_path, monkeypatch):
     (src_dir / "kernels_fields.hip").write_text("kernel v2")
     assert bench.traffic_from_profile("cg_iter", "c2_beam", 0) is None
     assert bench.traffic_from_profile("cg_iter", "c3_plasma", 0) is None
+
+
+def test_solve_precision_options(F):
+    """The mixed-precision solve is an option of the auxiliary-space preconditioner only;
+    its inner tolerance lies in (0, 1); the setters keep the pair consistent."""
+    o = F.fepic_default_options()
+    assert o.solve_precision == F.FEPIC_SOLVE_FP64 and o.mixed_inner_tol == 1e-4
+    for bad in ({"solve_precision": F.FEPIC_SOLVE_MIXED, "preconditioner": F.FEPIC_PC_JACOBI},
+                {"solve_precision": 2}, {"solve_precision": F.FEPIC_SOLVE_MIXED, "mixed_inner_tol": 1.0},
+                {"solve_precision": F.FEPIC_SOLVE_MIXED, "mixed_inner_tol": 0.0}):
+        with pytest.raises(F.FepicError) as ei:
+            F.fepic_create(device=-1, **bad)
+        assert F.ERROR_NAMES[ei.value.code] == "FEPIC_E_ARG"
+    ctx = F.fepic_create(device=-1, solve_precision=F.FEPIC_SOLVE_MIXED)
+    try:
+        with pytest.raises(F.FepicError):
+            F.fepic_set_preconditioner(ctx, F.FEPIC_PC_JACOBI)
+        F.fepic_set_solve_precision(ctx, F.FEPIC_SOLVE_FP64)
+        F.fepic_set_preconditioner(ctx, F.FEPIC_PC_JACOBI)
+        with pytest.raises(F.FepicError):
+            F.fepic_set_solve_precision(ctx, F.FEPIC_SOLVE_MIXED)
+    finally:
+        F.fepic_destroy(ctx)

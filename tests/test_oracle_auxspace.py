@@ -164,3 +164,41 @@ def test_multilevel_preconditioner(mesh, levels):
     assert res <= 1e-10 and np.linalg.norm(xs - x_direct) <= 1e-8 * np.linalg.norm(x_direct)
     assert it < it1
     print(f"levels {levels}: {it} iterations, one level {it1}")
+
+
+def test_fp32_preconditioner_is_the_rounded_fp64_one(mesh):
+    A = _newmark_A(mesh, 20.0)
+    apply64 = auxspace.aux_space_preconditioner(A, mesh, levels=(8, 64))[0]
+    apply32 = auxspace.aux_space_preconditioner(A, mesh, levels=(8, 64), dtype=np.float32)[0]
+    r = np.random.default_rng(10).normal(size=A.shape[0])
+    z64, z32 = apply64(r), apply32(r.astype(np.float32))
+    assert z32.dtype == np.float32
+    assert np.linalg.norm(z32 - z64) <= 1e-5 * np.linalg.norm(z64)
+
+
+@pytest.mark.parametrize("cfl_ratio", [5.0, 20.0])
+def test_refined_pcg_meets_the_fp64_tolerance(mesh, cfl_ratio):
+    """FP32 inner solves with FP64 residuals reach the FP64 stopping rule and the direct
+    solve's solution, in a few more iterations than the FP64 PCG; the same refinement
+    with its residual formed in FP32 (a planted mistake) stalls far above the tolerance."""
+    A = _newmark_A(mesh, cfl_ratio)
+    rng = np.random.default_rng(9)
+    b = rng.normal(size=A.shape[0])
+    x_direct = spla.spsolve(A.tocsc(), b)
+    levels = (8, 64)
+    apply32 = auxspace.aux_space_preconditioner(A, mesh, levels=levels, dtype=np.float32)[0]
+    x, it, passes, res = auxspace.pcg_refined(A, b, np.zeros_like(b), apply32, tol=1e-10, inner_tol=1e-4)
+    assert res <= 1e-10 and np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - x_direct) <= 1e-8 * np.linalg.norm(x_direct)
+    assert passes >= 2          # FP32 alone does not resolve 1e-10: refinement took place
+    apply64 = auxspace.aux_space_preconditioner(A, mesh, levels=levels)[0]
+    _, it64, _ = auxspace.pcg(A, b, np.zeros_like(b), apply64, tol=1e-10)
+    assert it <= 1.3 * it64 + 5
+    print(f"cfl ratio {cfl_ratio}: refined {it} iterations in {passes} passes, FP64 PCG {it64}")
+    # planted mistake: residuals in FP32
+    A32, b32, x32 = A.astype(np.float32), b.astype(np.float32), np.zeros(len(b), dtype=np.float32)
+    for _ in range(8):
+        r32 = b32 - A32 @ x32
+        d, _ = auxspace._pcg_fp32(A32, r32, np.linalg.norm(r32.astype(np.float64)), apply32, 1e-4, 10000)
+        x32 = x32 + d
+    assert np.linalg.norm(b - A @ x32.astype(np.float64)) > 1e-9 * np.linalg.norm(b)
