@@ -77,8 +77,9 @@ def c3_plasma(n_pairs=8_000_000, n_cells=55, seed=0):
 def c5_plasma(n_pairs=64_000_000, n_cells=110, seed=0):
     """The plasma ball of c3_plasma refined twice over: Kuhn mesh 110^3 of the same 8 cm cube
     (7,986,000 tets), 64M electron/proton pairs (the same plasma, 8x more macro-particles
-    of 1/8 the weight), the same dt."""
-    return c3_plasma(n_pairs=n_pairs, n_cells=n_cells, seed=seed) | {"name": "c5_plasma"}
+    of 1/8 the weight), the same dt; FP32 passes of the Newmark solve reduce the residual
+    by 1e-3 each (shallower still than the 998k-tet ball's)."""
+    return c3_plasma(n_pairs=n_pairs, n_cells=n_cells, seed=seed) | {"name": "c5_plasma", "inner_tol": 1e-3}
 
 
 WORKLOADS = {"c2_beam": c2_beam, "c3_plasma": c3_plasma, "c5_plasma": c5_plasma}
