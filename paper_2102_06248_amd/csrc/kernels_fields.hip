@@ -1001,8 +1001,10 @@ __device__ __forceinline__ void u_part(UPart<S>& P, const AuxSpace& g, const S* 
 
 // x += alpha p with p = z + beta p from the pair k_pcg_q(i) read (not at the start),
 // r' = r - alpha q, z' = D^-1 r' + G y + Pi v; the pair (z', p) into the other buffer;
-// (r', z') and (r', r') into reduction 2i + 1.
-template <typename S>
+// (r', z') and (r', r') into reduction 2i + 1.  Each workgroup takes one block of kR
+// consecutive groups of kBlock rows (the grid covers all rows), and each thread issues the
+// loads of its kR rows together: the FP32 form, whose rows carry fewer bytes, takes two.
+template <typename S, int kR>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n_rows, RowGrid rg, int i, AuxSpace g,
                                                         const S* __restrict__ dinv, S* __restrict__ x,
                                                         const typename Vec<S>::t2* __restrict__ ZP,
@@ -1012,12 +1014,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n_rows, RowGrid r
     const int conv = sc->converged;
     double t[1] = {0.0};
     if (i >= 0) slot_load<1>(red_buf(cg_slots, 2 * i), t);
-    int64_t lb = rg_first(rg);
+    const int64_t lb = rg_first(rg);
     const int64_t le = rg_end(rg);
-    UPart<S> P;
-    int64_t row = lb * kBlock + threadIdx.x;
-    bool active = lb < le && row < n_rows;
-    if (active) u_part<S>(P, g, dinv, x, ZP, R, Q, row);
+    UPart<S> P[kR];
+    bool act[kR];
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+        const int64_t row = (lb * kR + k) * kBlock + threadIdx.x;
+        act[k] = lb < le && row < n_rows;
+        if (act[k]) u_part<S>(P[k], g, dinv, x, ZP, R, Q, row);
+    }
     if (conv) return;
     double alpha = 0.0;
     if (i >= 0) {
@@ -1030,26 +1036,28 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n_rows, RowGrid r
     if (blockIdx.x == 0) clear_buf(red_buf(cg_slots, 2 * i + 2));
     const S as = (S)alpha, bs = (S)beta;
     double v[2] = {0.0, 0.0};
-    while (lb < le) {
-        if (active) {
-            const S r = P.r - as * P.q;
-            const S p = i >= 0 ? P.zp.x + bs * P.zp.y : S(0);
-            if (i >= 0) x[row] = P.x + as * p;
-            const S z = P.dinv * r + (P.yb.x - P.ya.x) + P.th.x * (P.ya.y + P.yb.y) + P.th.y * (P.ya.z + P.yb.z) +
-                        P.th.z * (P.ya.w + P.yb.w);
-            R[row] = r;
-            ZPn[row] = Vec<S>::two(z, p);
-            v[0] += (double)r * (double)z;
-            v[1] += (double)r * (double)r;
-        }
-        lb += rg.g;
-        row = lb * kBlock + threadIdx.x;
-        active = lb < le && row < n_rows;
-        if (active) u_part<S>(P, g, dinv, x, ZP, R, Q, row);
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+        if (!act[k]) continue;
+        const int64_t row = (lb * kR + k) * kBlock + threadIdx.x;
+        const UPart<S>& U = P[k];
+        const S r = U.r - as * U.q;
+        const S p = i >= 0 ? U.zp.x + bs * U.zp.y : S(0);
+        if (i >= 0) x[row] = U.x + as * p;
+        const S z = U.dinv * r + (U.yb.x - U.ya.x) + U.th.x * (U.ya.y + U.yb.y) + U.th.y * (U.ya.z + U.yb.z) +
+                    U.th.z * (U.ya.w + U.yb.w);
+        R[row] = r;
+        ZPn[row] = Vec<S>::two(z, p);
+        v[0] += (double)r * (double)z;
+        v[1] += (double)r * (double)r;
     }
     block_sum_all<2>(v);
     slot_add<2>(red_buf(cg_slots, 2 * i + 1), v);
 }
+
+// Rows per thread of the update kernel.
+template <typename S>
+constexpr int update_rows() { return sizeof(S) == 4 ? 2 : 1; }
 
 // ||b||^2 and the tolerance from the right-hand side's partials (one workgroup).
 __global__ __launch_bounds__(kBlock) void k_rhs_norm(const double* __restrict__ part_b, int n_src, CgScalars* sc,
@@ -1360,8 +1368,9 @@ void pcg_start(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* 
     const RowGrid ng = node_grid(g.n_aux);
     hipLaunchKernelGGL(k_pcg_nodes<S>, dim3(ng.grid), dim3(kBlock), 0, s, ng, -1, g, (const S*)R, (const S*)Q, slots,
                        sc);
-    const RowGrid ug = row_grid_full(n_rows);
-    hipLaunchKernelGGL(k_pcg_update<S>, dim3(ug.grid), dim3(kBlock), 0, s, n_rows, ug, -1, g, dinv, x,
+    constexpr int kR = update_rows<S>();
+    const RowGrid ug = row_grid_full((n_rows + kR - 1) / kR);
+    hipLaunchKernelGGL((k_pcg_update<S, kR>), dim3(ug.grid), dim3(kBlock), 0, s, n_rows, ug, -1, g, dinv, x,
                        (const typename Vec<S>::t2*)zp0, zp0, R, (const S*)Q, slots, sc);
 }
 
@@ -1375,7 +1384,9 @@ void pcg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int
                        (const typename Vec<S>::t2*)zp[a], Q, slots, sc, g);
     hipLaunchKernelGGL(k_pcg_nodes<S>, dim3(ng.grid), dim3(kBlock), 0, s, ng, i, g, (const S*)R, (const S*)Q, slots,
                        sc);
-    hipLaunchKernelGGL(k_pcg_update<S>, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, g, dinv, x,
+    constexpr int kR = update_rows<S>();
+    const RowGrid ug = row_grid_full((n_rows + kR - 1) / kR);
+    hipLaunchKernelGGL((k_pcg_update<S, kR>), dim3(ug.grid), dim3(kBlock), 0, s, n_rows, ug, i, g, dinv, x,
                        (const typename Vec<S>::t2*)zp[a], zp[b], R, (const S*)Q, slots, sc);
 }
 }  // namespace
