@@ -282,11 +282,12 @@ def main():
     for fam in FAMILIES:
         F.fepic_kernel_timing(ctx, fam, 1 + args.steps * (1200 if fam.startswith("cg") else 4))
 
+    n_start = sum(F.fepic_num_particles(ctx, s) for s in species)   # live particles before the first timed step
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     psteps, cg_iters, cross, newmark_ms, push_ms, stats = 0, [], 0, [], [], []
     for k in range(args.steps):
-        n_before = sum(F.fepic_num_particles(ctx, s) for s in species) if k == 0 else stats[-1].n_particles
+        n_before = n_start if k == 0 else stats[-1].n_particles
         if inject:
             n_before += len(batches[n_train + args.warmup + k][0])
         st = one_step(n_train + args.warmup + k)

@@ -1093,11 +1093,12 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
     if (c->d_cnt_slots) HIPCHK(c, hipMemset(c->d_cnt_slots, 0, sizeof(PushCounters) * kCntSlots));
     c->d_acc = dalloc<DiagAcc>(c, 1);
     c->d_dotc = dalloc<unsigned int>(c, 1);
+    c->d_live = dalloc<double>(c, 1);
     c->d_count = dalloc<int32_t>(c, nt);
     c->d_offset = dalloc<int32_t>(c, nt);
     c->d_bsums = dalloc<int32_t>(c, nt / 1024 + 2);
     if (!c->d_A || !c->d_dinv || !c->d_partial || !c->d_sc || !c->d_cnt || !c->d_cnt_slots || !c->d_acc || !c->d_count ||
-        !c->d_offset || !c->d_bsums || !c->d_dotc)
+        !c->d_offset || !c->d_bsums || !c->d_dotc || !c->d_live)
         return fail(c, FEPIC_E_OOM, "device allocation failed");
     HIPCHK(c, hipMemset(c->d_sc, 0, sizeof(CgScalars)));
     HIPCHK(c, hipMemset(c->d_dotc, 0, sizeof(unsigned int)));
@@ -1360,12 +1361,16 @@ int fepic_num_particles(fepic_ctx* c, int species, int64_t* n) {
     if (species < 0 || species >= (int)c->species.size() || !n) return FEPIC_E_ARG;
     int rc = sync_counts(c);
     if (rc) return rc;
-    // count live entries (dead ones stay until the next sort)
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // count live entries on the device (dead ones stay until the next sort)
     Species& s = c->species[species];
-    std::vector<int32_t> tet(s.n);
-    if (s.n) HIPCHK(c, hipMemcpy(tet.data(), s.buf[s.cur][0], sizeof(int32_t) * s.n, hipMemcpyDeviceToHost));
-    *n = std::count_if(tet.begin(), tet.end(), [](int32_t t) { return t >= 0; });
+    double live = 0.0;
+    if (s.n) {
+        launch_fill(c->stream, c->d_live, 1, 0.0);
+        launch_count_live(c->stream, (const int32_t*)s.buf[s.cur][0], s.n, c->d_live);
+        HIPCHK(c, hipMemcpyAsync(&live, c->d_live, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *n = (int64_t)live;
     return FEPIC_OK;
 }
 

@@ -66,6 +66,7 @@ struct fepic_ctx {
     double *d_M = nullptr, *d_S = nullptr, *d_A = nullptr, *d_dinv = nullptr;
     int32_t *d_cell_start = nullptr, *d_cell_tets = nullptr, *d_grid_n = nullptr;
     double* d_grid = nullptr;  // lo[3], inv_h[3]
+    double* d_live = nullptr;   // one double: live-particle count of fepic_num_particles
     double A_scale = -1.0;
     double s_over_m = 0.0;   // mean of S_jj / M_jj over interior rows (chooses the far levels)
     bool A_valid = false;

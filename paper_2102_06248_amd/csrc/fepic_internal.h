@@ -198,6 +198,7 @@ void launch_magnetic(hipStream_t s, int64_t n_tets, const double* b, const doubl
                      double* out);
 template <typename T>
 void launch_kinetic(hipStream_t s, PArrays<T> p, int64_t n, double wmc2, double* out);
+void launch_count_live(hipStream_t s, const int32_t* tet, int64_t n, double* out);
 
 // Field kernels (kernels_fields.hip).
 void launch_fill(hipStream_t s, double* x, int64_t n, double v);

@@ -879,7 +879,22 @@ __global__ __launch_bounds__(kBlock) void k_kinetic(PArrays<T> p, int64_t n, dou
     block_add(acc, out);
 }
 
+// Live particles (tet >= 0; absorbed ones stay until the next sort), summed into *out
+// (exact in FP64 for any count that fits device memory).
+__global__ __launch_bounds__(kBlock) void k_count_live(const int32_t* __restrict__ tet, int64_t n, double* out) {
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        acc += tet[i] >= 0 ? 1.0 : 0.0;
+    block_add(acc, out);
+}
+
 // ------------------------------------------------------------------------- launchers
+void launch_count_live(hipStream_t s, const int32_t* tet, int64_t n, double* out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_count_live, dim3((unsigned)std::min<int64_t>(1024, grid_1d(n, kBlock))), dim3(kBlock), 0, s,
+                       tet, n, out);
+}
+
 void launch_magnetic(hipStream_t s, int64_t n_tets, const double* b, const double* grad64, const int32_t* tet_faces,
                      double* out) {
     if (n_tets <= 0) return;

@@ -63,6 +63,9 @@ def test_particle_step_vs_oracle(F, precision, n, walk):
         st = F.fepic_push_particles(L.ctx, dt)
         gp = F.fepic_get_particles(L.ctx, sp)
         dg_gpu, _ = F.fepic_get_current(L.ctx)
+        # the live count (absorbed particles stay in the arrays until the next sort)
+        n_live = F.fepic_num_particles(L.ctx, sp)
+    assert n_live == len(gp["id"]) == n - st.n_absorbed
     ost = osim.step(dt, solve=False)
     op = osim.particles(s)
     tol = (1e-10, 1e-10) if precision == 1 else (1e-5, 1e-5)
