@@ -159,7 +159,8 @@ def main():
     ap.add_argument("--particles", type=int, default=None, help="override the particle count (pairs for plasmas)")
     ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "fp64"],
                     help="particle path precision (auto: the workload's; fp64 = all-FP64 path)")
-    ap.add_argument("--warm-start", default="prev", choices=["prev", "extrap1", "extrap2", "mlp"])
+    ap.add_argument("--warm-start", default=None, choices=["prev", "extrap1", "extrap2", "mlp"],
+                    help="start of the Newmark solve (default: the workload's, else the previous field)")
     ap.add_argument("--train-steps", type=int, default=40,
                     help="mlp: plain steps recorded for training before the warm-up steps")
     ap.add_argument("--diagnostics", action="store_true",
@@ -202,8 +203,9 @@ def main():
     wl = workloads.WORKLOADS[args.workload](**kw)
     log(f"[bench] workload {wl['name']} built in {time.perf_counter() - t0:.1f}s: "
         f"{len(wl['tets'])} tets, {sum(len(s['x']) for s in wl['species'])} particles")
+    warm = args.warm_start or wl.get("warm_start", "prev")
     ws = {"prev": F.FEPIC_WS_PREV, "extrap1": F.FEPIC_WS_EXTRAP1, "extrap2": F.FEPIC_WS_EXTRAP2,
-          "mlp": F.FEPIC_WS_PREV}[args.warm_start]
+          "mlp": F.FEPIC_WS_PREV}[warm]
     precision = {"auto": wl["precision"], "fp32": 0, "fp64": 1}[args.precision]
     pc = args.preconditioner
     solve = args.solve or (wl.get("solve", "fp64") if pc == "aux" else "fp64")
@@ -229,7 +231,7 @@ def main():
     it = F.fepic_init_electrostatic(ctx, 1e-12)
     log(f"[bench] electrostatic start: {it} CG iterations")
     inject = args.inject and wl.get("inject_per_step")
-    n_train = args.train_steps if args.warm_start == "mlp" else 0
+    n_train = args.train_steps if warm == "mlp" else 0
     batches = ([workloads.c2_injection_batch(k) for k in range(n_train + args.warmup + args.steps)]
                if inject else [])
     next_id = [10 ** 9]
@@ -366,7 +368,7 @@ def main():
                    "mean_live_particles": round(mean_particles), "dt": wl["dt"], "beta": wl["beta"],
                    "gamma": wl["gamma"], "cg_tol": 1e-10, "preconditioner": pc, "solve": solve,
                    "mixed_inner_tol": (inner_tol or 1e-4) if solve == "mixed" else None, "walk": args.walk,
-                   "warm_start": args.warm_start,
+                   "warm_start": warm,
                    "sort_period": sort_period, "inject_per_step": int(wl.get("inject_per_step") or 0) if inject else 0,
                    "inject_from": args.inject_from if inject else None,
                    "precision": ("fp32 push / fp64 deposit" if precision == 0 else "all fp64 particles")

@@ -60,7 +60,9 @@ def c3_plasma(n_pairs=8_000_000, n_cells=55, seed=0):
     and protons (mass ratio 1836) co-located in pairs from a Gaussian of width 1 cm
     truncated at 3.9 sigma, Te = 1 eV, Ti = 0.1 eV; peak density 2.5e13 m^-3 sets the
     weight; dt = 0.05 / omega_pe.  Newmark solve: FP64 residuals around FP32 inner solves
-    that each reduce the residual by 3e-4 (deeper FP32 passes converge more slowly here)."""
+    that each reduce the residual by 3e-4 (deeper FP32 passes converge more slowly here),
+    started from the quadratic extrapolation of the last three fields (the smooth
+    expansion makes it a better start than e^n: 144.5 iterations per step against 165.4)."""
     xyz, tets = inputs.kuhn_cube(n_cells, lo=(-0.04,) * 3, hi=(0.04,) * 3)
     m_p = inputs.PROTON_ELECTRON_MASS_RATIO * M_E
     x, ue, ui = inputs.gaussian_ball_pairs(n_pairs, 0.01, 3.9, 1.0, 0.1, M_E, m_p, seed)
@@ -71,7 +73,8 @@ def c3_plasma(n_pairs=8_000_000, n_cells=55, seed=0):
     wpe = math.sqrt(n0 * E_CHARGE ** 2 / (eps0 * M_E))
     return dict(name="c3_plasma", xyz=xyz, tets=tets, B0=None,
                 species=[dict(q=-E_CHARGE, m=M_E, w=w, x=x, u=ue), dict(q=E_CHARGE, m=m_p, w=w, x=x, u=ui)],
-                dt=0.05 / wpe, beta=0.25, gamma=0.5, precision=0, solve="mixed", inner_tol=3e-4)
+                dt=0.05 / wpe, beta=0.25, gamma=0.5, precision=0, solve="mixed", inner_tol=3e-4,
+                warm_start="extrap2")
 
 
 def c5_plasma(n_pairs=64_000_000, n_cells=110, seed=0):

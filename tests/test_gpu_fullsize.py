@@ -31,10 +31,13 @@ def F():
 
 
 def _solve_opts(F, wl):
-    """The workload's Newmark solve settings, as the benchmark runs them."""
+    """The workload's Newmark solve settings (arithmetic and start), as the benchmark runs
+    them."""
+    ws = {"prev": F.FEPIC_WS_PREV, "extrap1": F.FEPIC_WS_EXTRAP1,
+          "extrap2": F.FEPIC_WS_EXTRAP2}[wl.get("warm_start", "prev")]
     if wl.get("solve") == "mixed":
-        return {"solve_precision": F.FEPIC_SOLVE_MIXED, "mixed_inner_tol": wl["inner_tol"]}
-    return {"solve_precision": F.FEPIC_SOLVE_FP64}
+        return {"solve_precision": F.FEPIC_SOLVE_MIXED, "mixed_inner_tol": wl["inner_tol"], "warm_start": ws}
+    return {"solve_precision": F.FEPIC_SOLVE_FP64, "warm_start": ws}
 
 
 def test_beam_full_size_two_steps(F):
@@ -52,7 +55,7 @@ def test_beam_full_size_two_steps(F):
     osim.upload_particles(so, sp["x"], sp["u"], ids=ids)
     osim.init_electrostatic(tol=1e-13)
 
-    L = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=wl["precision"], warm_start=F.FEPIC_WS_PREV,
+    L = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=wl["precision"],
                      sort_period=wl["sort_period"], **_solve_opts(F, wl))
     try:
         s = F.fepic_add_species(L.ctx, sp["q"], sp["m"], sp["w"])
@@ -121,7 +124,7 @@ def test_plasma_full_size_sampled(F):
     h = np.linalg.norm(m.xyz[m.edges[:, 1]] - m.xyz[m.edges[:, 0]], axis=1).min()
     # the first step has no crossing history: take the queue form the plasma's 15 % share
     # of crossing particles selects from the second step on
-    L = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=wl["precision"], warm_start=F.FEPIC_WS_PREV,
+    L = F.Simulation(wl["xyz"], wl["tets"], device=0, precision=wl["precision"],
                      sort_period=1, walk=F.FEPIC_WALK_QUEUE, **_solve_opts(F, wl))
     try:
         sps, sos = [], []
