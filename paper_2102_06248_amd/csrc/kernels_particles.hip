@@ -648,26 +648,37 @@ __global__ __launch_bounds__(kBlock) void k_zero_i32(int32_t* p, int64_t n) {
     if (i < n) p[i] = 0;
 }
 
-// Runs of equal keys in a wave (the particles are nearly sorted by tet between sorts):
-// for each lane the first lane of its run and the run's length, from a ballot of the
-// run starts.
-__device__ __forceinline__ void key_run(int key, int lane, int& start, int& len) {
-    const int prev = __shfl_up(key, 1);
-    const unsigned long long starts = __ballot(lane == 0 || key != prev);
-    const unsigned long long upto = (2ull << lane) - 1ull;   // lanes 0..lane (all for 63)
-    start = 63 - __clzll(starts & upto);
-    const unsigned long long after = starts & ~upto;
-    len = (after ? __ffsll((long long)after) - 1 : 64) - start;
+// Lanes of a wave grouped by key, in any order: for each lane with key >= 0 its group's
+// leader (lowest lane), its rank among the group's lanes and the group's size; one pass
+// per distinct key.  Between sorts the particles stay nearly sorted, but those that
+// crossed a face break the runs of equal tets, so grouping by key needs about half the
+// atomics that one per run would.
+__device__ __forceinline__ void key_groups(int key, int lane, int& leader, int& rank, int& size) {
+    unsigned long long todo = __ballot(key >= 0);
+    leader = lane;
+    rank = 0;
+    size = 0;
+    while (todo) {
+        const int l = __ffsll((long long)todo) - 1;
+        const int k = __shfl(key, l);
+        const unsigned long long m = __ballot(key == k) & todo;
+        if (key == k) {
+            leader = l;
+            rank = __popcll(m & ((1ull << lane) - 1ull));
+            size = __popcll(m);
+        }
+        todo &= ~m;
+    }
 }
 
-// count[t] += number of particles in t; one atomic per run of equal tets in a wave.
+// count[t] += number of particles in t; one atomic per distinct tet in a wave.
 __global__ __launch_bounds__(kBlock) void k_hist(const int32_t* __restrict__ tet, int64_t n, int32_t* count) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int t = i < n ? tet[i] : -1;
-    int start, len;
-    key_run(t, lane, start, len);
-    if (t >= 0 && lane == start) atomicAdd(count + t, len);
+    int leader, rank, size;
+    key_groups(t, lane, leader, rank, size);
+    if (t >= 0 && lane == leader) atomicAdd(count + t, size);
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads = 4 waves).
@@ -741,20 +752,23 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(int32_t* __restrict__ out, 
         if (base + k < n) out[base + k] += add;
 }
 
+// Each live particle to its place in its tet's range (offset[t], the exclusive scan of the
+// counts, advanced as places are taken): the lanes of a wave in one tet take consecutive
+// places, in lane order, reserved by one atomic; absorbed particles (t < 0) are dropped.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scatter(PArrays<T> in, PArrays<T> out, int64_t n,
                                                      int32_t* __restrict__ offset) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int t = i < n ? in.tet[i] : -1;
-    int start, len;
-    key_run(t, lane, start, len);
-    // the run's first lane reserves len places in t's range; lanes keep their order
+    int leader, rank, size;
+    key_groups(t, lane, leader, rank, size);
+    // the group's leader reserves its places in t's range; lanes keep their order
     int base = 0;
-    if (t >= 0 && lane == start) base = atomicAdd(offset + t, len);
-    base = __shfl(base, start);
+    if (t >= 0 && lane == leader) base = atomicAdd(offset + t, size);
+    base = __shfl(base, leader);
     if (t < 0) return;
-    const int pos = base + (lane - start);
+    const int pos = base + rank;
     out.tet[pos] = t;
     out.l1[pos] = in.l1[i];
     out.l2[pos] = in.l2[i];
