@@ -117,6 +117,18 @@ def test_training_and_warm_start_gain(F):
     assert np.linalg.norm(e1 - e2) <= 1e-6 * np.linalg.norm(e1)
     # the trained network does not make the solve worse than starting from e^n
     assert np.mean(it_mlp) <= 1.1 * np.mean(it_plain)
+    # the same continuation with the mixed-precision solve (the network's start passes the
+    # same guard before the first FP32 pass)
+    for sim in (plain, learned):
+        F.fepic_set_solve_precision(sim.ctx, F.FEPIC_SOLVE_MIXED)
+    for _ in range(5):
+        a = F.fepic_step(plain.ctx, dt)
+        b = F.fepic_step(learned.ctx, dt)
+        assert a.cg_rel_resid <= 1e-10 and b.cg_rel_resid <= 1e-10
+        assert a.cg_passes >= 1 and b.cg_passes >= 1
+    e1, _, _ = F.fepic_get_fields(plain.ctx)
+    e2, _, _ = F.fepic_get_fields(learned.ctx)
+    assert np.linalg.norm(e1 - e2) <= 1e-6 * np.linalg.norm(e1)
     plain.close()
     learned.close()
 
