@@ -780,11 +780,40 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PArrays<T> in, PArrays<T> ou
 }
 
 // ------------------------------------------------------------------------- charge
+// One value into the workgroup's LDS table under key (linear probing, the key read before
+// the slot is claimed); to global memory directly if no slot is found within kProbe.
+template <int kBits>
+__device__ __forceinline__ void lds_add1(int* s_key, double* s_val, double* __restrict__ out, int key, double v) {
+    if (v == 0.0) return;
+    unsigned int h = ((unsigned int)key * 2654435761u) >> (32 - kBits);
+    for (int p = 0; p < kProbe; ++p) {
+        int k = __hip_atomic_load(s_key + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == -1) k = atomicCAS(s_key + h, -1, key);
+        if (k == -1 || k == key) {
+            __hip_atomic_fetch_add(s_val + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
+        h = (h + 1) & ((1u << kBits) - 1u);
+    }
+    atomic_add_f64(out + key, v);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rho(PArrays<T> p, int64_t n, const int32_t* __restrict__ tets,
                                                  double qw, double* __restrict__ rho) {
     // qw lambda_k summed over runs of lanes in the same tet (particles are kept sorted by
-    // tet, and a step moves few of them out of their run), then four atomics per run
+    // tet, and a step moves few of them out of their run), then per node in the
+    // workgroup's LDS table (neighbouring tets share most of their nodes), flushed with one
+    // FP64 atomic per distinct node
+    constexpr int kBits = log2_const(4 * kBlock);
+    constexpr int kSlots = 1 << kBits;
+    __shared__ int s_key[kSlots];
+    __shared__ double s_val[kSlots];
+    for (int k = threadIdx.x; k < kSlots; k += kBlock) {
+        s_key[k] = -1;
+        s_val[k] = 0.0;
+    }
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     int key = -1;
@@ -818,8 +847,10 @@ __global__ __launch_bounds__(kBlock) void k_rho(PArrays<T> p, int64_t n, const i
     const int next_key = __shfl_down(key, 1);
     if (key >= 0 && (lane == 63 || next_key != key)) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) atomic_add_f64(rho + tets[4 * key + c], v[c]);
+        for (int c = 0; c < 4; ++c) lds_add1<kBits>(s_key, s_val, rho, tets[4 * key + c], v[c]);
     }
+    __syncthreads();
+    flush_table<kSlots, kBlock>(s_key, s_val, rho);
 }
 
 }  // namespace
