@@ -414,6 +414,35 @@ def test_sort_period_and_many_waves(F):
         assert st.n_crossings > 0
 
 
+def test_sort_groups_of_equal_tets(F):
+    """The counting sort groups the lanes of a wave by tet: every particle in one tet, two
+    tets alternating lane by lane (groups that are not runs), and 200 tets in turn (64
+    distinct tets in every wave).  The result is sorted by tet, keeps every particle in the
+    tet it was placed in, and a step at rest in zero fields re-sorts it unchanged."""
+    announce("sort: one tet, alternating tets, 64 distinct tets per wave")
+    xyz, tets, h = jittered_kuhn(5, seed=13)
+    m = OracleSim(xyz, tets).mesh
+    cent = xyz[tets].mean(axis=1)
+    n = 64 * 20 + 11
+    k = np.arange(n)
+    patterns = {"one tet": np.full(n, 17), "alternating": np.where(k % 2 == 0, 3, 140),
+                "200 in turn": (k % 200) * 3 % len(tets)}
+    for name, sel in patterns.items():
+        x = cent[sel]
+        want = m.locate(x)
+        assert np.all(want >= 0)
+        with _lib_sim(F, xyz, tets, sort_period=1) as L:
+            sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 1.0)
+            assert F.fepic_upload_particles(L.ctx, sp, x, np.zeros((n, 3)), ids=k) == 0
+            for step in range(2):
+                g = F.fepic_get_particles(L.ctx, sp)
+                assert len(g["id"]) == n, name
+                assert np.all(np.diff(g["tet"]) >= 0), name
+                assert np.array_equal(np.sort(g["id"]), k), name
+                assert np.array_equal(g["tet"], want[g["id"]]), name
+                F.fepic_push_particles(L.ctx, 1e-15)
+
+
 def test_caller_allocator_matches_default(F):
     """Device memory from torch's caching allocator through fepic_set_allocator gives the
     same results as hipMalloc, and every allocation is returned when the context closes."""
