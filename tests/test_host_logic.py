@@ -94,6 +94,12 @@ def test_bench_byte_model_and_profile_bookkeeping(tmp_path, monkeypatch):
     st = {"particles": 1000, "occupied_tets": 40, "crossings": 300}
     assert bench.algorithmic_bytes("cg_iter", geo, st, "jacobi") == 12 * 1500 + 80 * 100
     assert bench.algorithmic_bytes("cg_iter", geo, st, "aux") == 12 * 1500 + 144 * 100 + 8 * 70 + 96 * 12
+    # FP32 inner iterations of the mixed-precision solve: 4 B values and vectors, the same
+    # column ids, incidences, FP16 edge vectors and ends
+    assert bench.algorithmic_bytes("cg_iter", geo, st, "aux", "mixed") == 8 * 1500 + 84 * 100 + 8 * 70 + 48 * 12
+    assert bench.profile_key("cg_iter", "aux", "mixed") == "cg_iter_mixed"
+    assert bench.profile_key("cg_iter", "jacobi") == "cg_iter_jacobi"
+    assert bench.profile_key("push", "aux", "mixed") == "push"
     assert bench.algorithmic_bytes("push", geo, st) == 56 * 1000 + 224 * 340
     # counter summaries are used only while the kernel source is unchanged
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
@@ -105,6 +111,7 @@ def test_bench_byte_model_and_profile_bookkeeping(tmp_path, monkeypatch):
     (tmp_path / "profiles" / "cg_iter_c2_beam_counters.json").write_text(json.dumps(rec))
     assert bench.traffic_from_profile("cg_iter", "c2_beam", 0) == 123456
     assert bench.traffic_from_profile("cg_iter", "c2_beam", 0, "jacobi") is None   # its own summary
+    assert bench.traffic_from_profile("cg_iter", "c2_beam", 0, "aux", "mixed") is None
     (src_dir / "kernels_fields.hip").write_text("kernel v2")
     assert bench.traffic_from_profile("cg_iter", "c2_beam", 0) is None
     assert bench.traffic_from_profile("cg_iter", "c3_plasma", 0) is None
