@@ -150,6 +150,75 @@ def cpu_baseline(wl, n_sample=None, n_steps=12):
             "newmark_cg_iters_mean": float(np.mean(iters)), "seconds": round(t_all, 2)}
 
 
+def ab_bytes_per_particle_step(k):
+    """Algorithmic HBM bytes of one Adams-Bashforth-k particle step: the particle state read
+    and written (tet 4 B, three barycentric coordinates and the velocity in FP64: 52 B each
+    way), the history it needs (positions r^n..r^{n+1-k}, velocities v^{n-1}..v^{n+1-k},
+    accelerations a^{n-1}..a^{n+1-k}: 3 (3k - 2) doubles) and the three new levels it must
+    keep (r^{n+1}, v^{n+1}, a^n: 9 doubles)."""
+    return 2 * 52 + 8 * 3 * (3 * k - 2) + 8 * 9
+
+
+def ab_bench(args, F, torch, sim, wl, species):
+    """Particle-only Adams-Bashforth pushes of every species in the workload's initial
+    fields (electrostatic start, fields frozen), as fepic_push_particles_ab runs them.
+    Prints one JSON line; the roofline is the AB kernel's, HIP-event timed."""
+    ctx = sim.ctx
+    k_ord, dt = args.ab_order, wl["dt"]
+    warmup = max(args.warmup, k_ord)              # the history reaches the full order first
+    for k in range(warmup):
+        for s in species:
+            st = F.fepic_push_particles_ab(ctx, s, dt, k_ord)
+        log(f"[bench] ab warmup {k}: {st.n_particles} particles, {st.n_crossings} crossings")
+    sizes = F.fepic_get_topology_sizes(ctx)
+    F.fepic_kernel_timing(ctx, "push", 1 + args.steps * 4 * len(species))
+    n_live = [F.fepic_num_particles(ctx, s) for s in species]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psteps, cross = 0, 0
+    for k in range(args.steps):
+        for j, s in enumerate(species):
+            st = F.fepic_push_particles_ab(ctx, s, dt, k_ord)
+            psteps += n_live[j]
+            n_live[j] = st.n_particles
+            cross += st.n_crossings
+        log(f"[bench] ab step {k}: {sum(n_live)} particles, {st.n_crossings} crossings (last species)")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms, nl = F.fepic_kernel_time(ctx, "push")
+    kernel_s = ms / 1e3
+    if args.copy_calibration:
+        a = torch.empty(256 * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    per_ps = ab_bytes_per_particle_step(k_ord)
+    # per launch: the particles' bytes, one staged record per tet (128 B) and the current
+    # vector written once
+    total_bytes = psteps * per_ps + nl * (128 * len(wl["tets"]) + 8 * sizes["n_edges"])
+    achieved = total_bytes / kernel_s / 1e9
+    out = {
+        "metric": "particle-steps/s (Adams-Bashforth gather+push+curved walk+deposit, fields frozen)",
+        "value": psteps / elapsed, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["name"], "tets": len(wl["tets"]), "particles": sum(len(s["x"]) for s in wl["species"]),
+                   "mean_live_particles": round(psteps / args.steps), "dt": dt, "ab_order": k_ord,
+                   "fields": "electrostatic start, frozen", "parallelism": "single GPU"},
+        "kernel_particle_steps_per_s": psteps / kernel_s,
+        "crossings_per_particle_step": round(cross / psteps, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_push_ab",
+                     "avg_launch_us": round(kernel_s / nl * 1e6, 3), "launches": nl,
+                     "algorithmic_bytes_per_particle_step": per_ps,
+                     "algorithmic_bytes_per_launch": int(total_bytes / nl)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +250,9 @@ def main():
                     help="device: batches staged in HBM before the timed region; host: copied per step")
     ap.add_argument("--cpu-sample", type=int, default=None, help="limit the oracle's particle count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pusher", default="boris", choices=["boris", "ab"],
+                    help="ab: time particle-only Adams-Bashforth pushes instead of whole steps")
+    ap.add_argument("--ab-order", type=int, default=4, help="order of the Adams-Bashforth pusher (1..5)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -207,6 +279,8 @@ def main():
     ws = {"prev": F.FEPIC_WS_PREV, "extrap1": F.FEPIC_WS_EXTRAP1, "extrap2": F.FEPIC_WS_EXTRAP2,
           "mlp": F.FEPIC_WS_PREV}[warm]
     precision = {"auto": wl["precision"], "fp32": 0, "fp64": 1}[args.precision]
+    if args.pusher == "ab":
+        precision = 1                      # the Adams-Bashforth kernel is FP64 only
     pc = args.preconditioner
     solve = args.solve or (wl.get("solve", "fp64") if pc == "aux" else "fp64")
     if solve == "mixed" and pc != "aux":
@@ -230,6 +304,9 @@ def main():
         F.fepic_set_uniform_B(ctx, wl["B0"])
     it = F.fepic_init_electrostatic(ctx, 1e-12)
     log(f"[bench] electrostatic start: {it} CG iterations")
+    if args.pusher == "ab":
+        ab_bench(args, F, torch, sim, wl, species)
+        return
     inject = args.inject and wl.get("inject_per_step")
     n_train = args.train_steps if warm == "mlp" else 0
     batches = ([workloads.c2_injection_batch(k) for k in range(n_train + args.warmup + args.steps)]

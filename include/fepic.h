@@ -258,6 +258,23 @@ int fepic_step(fepic_ctx* ctx, double dt, double beta, double gamma, fepic_step_
 /* Particle half only (fields frozen): stage, gather, push, track, deposit; commits the
  * particles and dG^{n+1} (the field history is left as is).  out may be NULL. */
 int fepic_push_particles(fepic_ctx* ctx, double dt, fepic_step_stats* out);
+/* The paper's own pusher for one species, fields frozen (Sec. III-B, III-C, Alg. 1 and 2):
+ * one Adams-Bashforth step of the given order (1..5) of the non-relativistic equations
+ * dv/dt = (q/m)(E + v x B), dr/dt = v, with u read and written as the velocity v at t_n;
+ * the path over the step is the Lagrange polynomial through r^{n+1} and the last `order`
+ * positions, followed cell by cell (exits bracketed by Gauss-Legendre points, then
+ * bisected to 1e-15 of the step; wall faces absorb), and each piece's Whitney-1 path
+ * integral, by (order + 1)-point Gauss-Legendre quadrature (exact), is added to dG^{n+1}.
+ * Each particle slot keeps its last positions, velocities and accelerations; a history
+ * starts from the current state at the first call and after any upload, injection, step
+ * or checkpoint load, and the order grows from 1 as levels accumulate.  Commits the
+ * particles and dG^{n+1} like fepic_push_particles, in place (no sort).  Needs
+ * FEPIC_ALL_FP64 (FEPIC_E_STATE otherwise); FEPIC_E_ARG for a bad species, order or dt.
+ * Particles whose path exceeds the crossing cap are dropped, the step is still committed,
+ * and FEPIC_E_CROSSING_CAP is returned.  out->n_particles is the species' live count after
+ * the step.  The kernel is timed as the "push" family (fepic_kernel_timing).  out may be
+ * NULL. */
+int fepic_push_particles_ab(fepic_ctx* ctx, int species, double dt, int order, fepic_step_stats* out);
 
 /* ---------------------------------------------------------------- read-out
  * Host copies; sizes from fepic_get_topology_sizes.  Any output may be NULL. */

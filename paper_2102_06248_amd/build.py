@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfepic.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["host_mesh.cpp", "kernels_particles.hip", "kernels_fields.hip", "kernels_mlp.hip", "capi.hip",
-           "mlp_host.hip"]
+SOURCES = ["host_mesh.cpp", "kernels_particles.hip", "kernels_fields.hip", "kernels_mlp.hip", "kernels_ab.hip",
+           "capi.hip", "mlp_host.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",

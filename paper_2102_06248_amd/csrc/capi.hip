@@ -609,8 +609,65 @@ int run_diagnostics(fepic_ctx* c, fepic_step_stats* st, bool have_step, bool hav
     return FEPIC_OK;
 }
 
+// Any other change of the particle slots (upload, injection, a Boris step and its sort, a
+// checkpoint load) leaves the Adams-Bashforth histories stale: the next AB step restarts
+// them from the current state (order 1 first).
+void ab_history_stale(fepic_ctx* c) {
+    for (auto& s : c->species) s.ab_valid = false;
+}
+
+// Adams-Bashforth coefficients of orders 1..kAbMax: the integrals over s in [0, 1] of the
+// Lagrange basis on the nodes s = 0, -1, ..., -(m - 1); Gauss-Legendre rules of 2..kAbMax+1
+// points (Newton on the Legendre polynomial from the usual cosine guesses).
+void ab_tables(AbParams& ap) {
+    for (int m = 1; m <= kAbMax; ++m)
+        for (int j = 0; j < kAbMax; ++j) {
+            if (j >= m) {
+                ap.beta[m - 1][j] = 0.0;
+                continue;
+            }
+            long double poly[kAbMax + 1] = {1.0L};   // coefficients, lowest degree first
+            long double den = 1.0L;
+            int deg = 0;
+            for (int q = 0; q < m; ++q) {
+                if (q == j) continue;
+                const long double node = -(long double)q;
+                for (int i = deg + 1; i >= 1; --i) poly[i] = poly[i - 1] - node * poly[i];
+                poly[0] = -node * poly[0];
+                ++deg;
+                den *= (-(long double)j) - node;
+            }
+            long double integral = 0.0L;
+            for (int i = 0; i <= deg; ++i) integral += poly[i] / (i + 1);
+            ap.beta[m - 1][j] = (double)(integral / den);
+        }
+    for (int n = 0; n < kAbMax + 2; ++n)
+        for (int q = 0; q < kAbMax + 2; ++q) ap.gl_x[n][q] = ap.gl_w[n][q] = 0.0;
+    for (int n = 1; n < kAbMax + 2; ++n) {
+        for (int q = 0; q < n; ++q) {
+            long double x = std::cos(3.14159265358979323846L * (q + 0.75L) / (n + 0.5L)), dp = 1.0L;
+            for (int it = 0; it < 100; ++it) {
+                long double p0 = 1.0L, p1 = x;
+                for (int k = 2; k <= n; ++k) {
+                    const long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = n * (x * p1 - p0) / (x * x - 1.0L);
+                const long double dx = p1 / dp;
+                x -= dx;
+                if (std::fabs((double)dx) < 1e-19) break;
+            }
+            // ascending order of nodes
+            ap.gl_x[n][n - 1 - q] = (double)x;
+            ap.gl_w[n][n - 1 - q] = (double)(2.0L / ((1.0L - x * x) * dp * dp));
+        }
+    }
+}
+
 int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats* out, bool solve) {
     NEED_DEV(c);
+    ab_history_stale(c);
     if (!(dt > 0) || !std::isfinite(dt) || !std::isfinite(beta) || !std::isfinite(gamma))
         return fail(c, FEPIC_E_ARG, "bad step parameters");
     fepic_step_stats st;
@@ -1246,6 +1303,7 @@ static int check_upload(fepic_ctx* c, int species, int64_t n, const double* x, c
 int fepic_upload_particles(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
                            const double* u, int64_t* n_rejected) {
     NEED_DEV(c);
+    ab_history_stale(c);
     if (n_rejected) *n_rejected = 0;
     int rc = check_upload(c, species, n, x, u);
     if (rc || n == 0) return rc;
@@ -1273,6 +1331,7 @@ int fepic_upload_particles(fepic_ctx* c, int species, int64_t n, const int64_t* 
 int fepic_upload_particles_device(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
                                   const double* u, int64_t* n_rejected) {
     NEED_DEV(c);
+    ab_history_stale(c);
     if (n_rejected) *n_rejected = 0;
     int rc = check_upload(c, species, n, x, u);
     if (rc || n == 0) return rc;
@@ -1285,6 +1344,7 @@ static int inject_located(fepic_ctx* c, Species& s, int64_t n, const int64_t* di
 int fepic_inject_particles(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
                            const double* u) {
     NEED_DEV(c);
+    ab_history_stale(c);
     if (species < 0 || species >= (int)c->species.size() || n < 0 || (n > 0 && (!x || !u)))
         return fail(c, FEPIC_E_ARG, "bad injection arguments");
     if (n == 0) return FEPIC_OK;
@@ -1345,6 +1405,7 @@ static int inject_located(fepic_ctx* c, Species& s, int64_t n, const int64_t* di
 int fepic_inject_particles_device(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
                                   const double* u) {
     NEED_DEV(c);
+    ab_history_stale(c);
     if (species < 0 || species >= (int)c->species.size() || n < 0 || (n > 0 && (!x || !u)))
         return fail(c, FEPIC_E_ARG, "bad injection arguments");
     if (n == 0) return FEPIC_OK;
@@ -1431,6 +1492,74 @@ int fepic_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_st
 }
 
 int fepic_push_particles(fepic_ctx* c, double dt, fepic_step_stats* out) { return do_step(c, dt, 0.25, 0.5, out, false); }
+
+int fepic_push_particles_ab(fepic_ctx* c, int species, double dt, int order, fepic_step_stats* out) {
+    NEED_DEV(c);
+    if (species < 0 || species >= (int)c->species.size() || order < 1 || order > kAbMax || !(dt > 0) ||
+        !std::isfinite(dt))
+        return FEPIC_E_ARG;
+    if (c->opt.precision != FEPIC_ALL_FP64)
+        return fail(c, FEPIC_E_STATE, "the Adams-Bashforth pusher needs the all-FP64 particle path");
+    int rc = sync_counts(c);
+    if (rc != FEPIC_OK) return rc;
+    Species& s = c->species[species];
+    if (s.abh_cap < s.n || !s.d_abh) {
+        double* h = dalloc<double>(c, std::max<int64_t>(s.n, 1) * kAbStride);
+        if (!h) return fail(c, FEPIC_E_OOM, "device allocation failed");
+        if (s.d_abh) dfree(c, s.d_abh);
+        s.d_abh = h;
+        s.abh_cap = std::max<int64_t>(s.n, 1);
+        s.ab_valid = false;
+    }
+    const TetBlock<double>* blk = (const TetBlock<double>*)c->d_blk;
+    launch_stage<double>(c->stream, c->mesh.n_tets, (TetBlock<double>*)c->d_blk, c->d_e, c->d_b, c->d_grad64,
+                         c->d_tet_edges, c->d_tet_faces);
+    if (!s.ab_valid) {
+        launch_ab_init(c->stream, parr<double>(s, s.cur), s.n, blk, c->d_r0, s.d_abh);
+        s.ab_valid = true;
+    }
+    launch_fill(c->stream, c->d_dgn, c->mesh.n_edges, 0.0);
+    AbParams ap;
+    ab_tables(ap);
+    ap.dt = dt;
+    ap.qm = s.q / s.m;
+    ap.qw = s.q * s.w;
+    ap.k = order;
+    ap.cap = c->opt.crossing_cap;
+    hipEvent_t* ev = timer_pair(c, FAM_PUSH);   // timed as the "push" family
+    if (ev) (void)hipEventRecord(ev[0], c->stream);
+    launch_push_ab(c->stream, parr<double>(s, s.cur), s.n, blk, c->d_r0, s.d_abh, c->d_dgn, ap, c->d_cnt_slots);
+    if (ev) (void)hipEventRecord(ev[1], c->stream);
+    launch_cnt_finish(c->stream, c->d_cnt_slots, c->d_cnt);
+    HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(PushCounters), hipMemcpyDeviceToHost, c->stream));
+    // the species' live count after the step (absorbed slots stay until the next sort)
+    double live = 0.0;
+    launch_fill(c->stream, c->d_live, 1, 0.0);
+    launch_count_live(c->stream, (const int32_t*)s.buf[s.cur][0], s.n, c->d_live);
+    HIPCHK(c, hipMemcpyAsync(&live, c->d_live, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    // commit the deposit as a particle-only step does: dG = this step's current, G += dG
+    std::swap(c->d_dg, c->d_dgn);
+    launch_axpby(c->stream, c->d_G, c->d_G, 1.0, c->d_dg, 1.0, c->mesh.n_edges);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    c->step_count++;
+    c->time += dt;
+    c->rho_valid = false;
+    fepic_step_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.gauss_drift_check_rel = st.cont_resid_rel = st.gauss_resid_rel = -1.0;
+    st.pc_far_levels = -1;
+    st.n_crossings = (int64_t)c->h_cnt->n_crossings;
+    st.n_absorbed = c->h_cnt->n_absorbed;
+    st.n_cap_exceeded = (int)c->h_cnt->n_cap;
+    st.n_particles = (int64_t)live;
+    st.step = c->step_count;
+    st.t = c->time;
+    if (out) *out = st;
+    if (st.n_cap_exceeded)
+        return fail(c, FEPIC_E_CROSSING_CAP, "a particle path exceeded the crossing cap; those particles were dropped");
+    return FEPIC_OK;
+}
 
 // Device edge vector -> caller's array in canonical edge order.
 static int edge_out(fepic_ctx* c, const double* d, double* out) {
@@ -1533,6 +1662,7 @@ int fepic_save(fepic_ctx* c, const char* path) {
 
 int fepic_load(fepic_ctx* c, const char* path) {
     NEED_DEV(c);
+    ab_history_stale(c);
     if (!path) return FEPIC_E_ARG;
     int rc = sync_counts(c);
     if (rc) return rc;

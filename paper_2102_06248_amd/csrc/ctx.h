@@ -34,6 +34,11 @@ struct Species {
     int idcur = 0;
     int32_t* d_nlive = nullptr;
     int32_t* h_nlive = nullptr;
+    // Adams-Bashforth history (fepic_push_particles_ab): kAbStride doubles per slot, valid
+    // while the slots hold the same particles
+    double* d_abh = nullptr;
+    int64_t abh_cap = 0;
+    bool ab_valid = false;
     bool sorted_pending = false;  // d_nlive holds a count not yet read back
 };
 

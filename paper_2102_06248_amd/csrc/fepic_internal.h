@@ -72,6 +72,20 @@ struct PushParams {
 // (workgroup b -> slot b mod kCntSlots); launch_cnt_finish folds them into one.
 constexpr int kCntSlots = 256;
 
+// Adams-Bashforth pusher (all-FP64): orders 1..kAbMax, a history record of kAbStride
+// doubles per particle slot (r^{n-j}, v^{n-j} for j < 5, a^{n-1-j} for j < 4, levels held).
+constexpr int kAbMax = 5;
+constexpr int kAbStride = 48;
+constexpr double kAbInsideEps = 1e-13;   // a point is in a tet when its smallest lambda >= -eps
+constexpr double kAbBisectTol = 1e-15;   // width of the final crossing bracket, in steps
+struct AbParams {
+    double dt, qm, qw;
+    int k, cap;
+    double beta[kAbMax][kAbMax];          // beta[m - 1][j]: the order-m coefficients
+    double gl_x[kAbMax + 2][kAbMax + 2];  // row n: the n Gauss-Legendre nodes on [-1, 1]
+    double gl_w[kAbMax + 2][kAbMax + 2];  // and weights
+};
+
 struct PushCounters {
     unsigned long long n_crossings;
     unsigned int max_crossings;
@@ -199,6 +213,10 @@ void launch_magnetic(hipStream_t s, int64_t n_tets, const double* b, const doubl
 template <typename T>
 void launch_kinetic(hipStream_t s, PArrays<T> p, int64_t n, double wmc2, double* out);
 void launch_count_live(hipStream_t s, const int32_t* tet, int64_t n, double* out);
+void launch_ab_init(hipStream_t s, PArrays<double> p, int64_t n, const TetBlock<double>* blk, const double* r0,
+                    double* hist);
+void launch_push_ab(hipStream_t s, PArrays<double> p, int64_t n, const TetBlock<double>* blk, const double* r0,
+                    double* hist, double* dg, const AbParams& ap, PushCounters* slots);
 
 // Field kernels (kernels_fields.hip).
 void launch_fill(hipStream_t s, double* x, int64_t n, double v);

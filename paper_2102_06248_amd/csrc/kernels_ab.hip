@@ -1,0 +1,285 @@
+// kernels_ab.hip - the paper's Adams-Bashforth-k particle pusher (Sec. III-B) with its
+// Lagrange-polynomial path, followed cell by cell (Sec. III-C, Alg. 1 and Alg. 2), and the
+// Whitney-1 path integral of each curved piece by Gauss-Legendre quadrature.  All-FP64.
+//
+// One thread per particle.  The particle's past positions, velocities and accelerations
+// live in a per-particle history record; the step:
+//   a^n = (q/m)(E + v x B) from the staged tet record at the particle's barycentric point;
+//   order m = min(k, levels of history + 1);
+//   v^{n+1} = v^n + dt sum_j beta_j a^{n-j},  r^{n+1} = r^n + dt sum_j beta_j v^{n-j};
+//   path r(s), s in [0, 1]: the Lagrange polynomial through r^{n+1} (s = 1), r^n (s = 0),
+//   r^{n-1} (s = -1), ..., r^{n+1-m};
+//   walk: in the current tet, the first of the remaining interval's m + 1 Gauss-Legendre
+//   points (or its end) found outside brackets the exit with the last point inside, and
+//   bisection narrows the bracket to 1e-15 of the step; the exit face is the most negative
+//   barycentric coordinate at the bracket's outer end; a wall face absorbs the particle;
+//   deposit: each piece adds q w int W_ab(r(s)) . r'(s) ds over its interval with m + 1
+//   Gauss-Legendre points (exact: the integrand has degree 2m - 1), six FP64 atomics.
+// Barycentric coordinates of a point x in tet t: lambda_k = grad lambda_k . (x - r_0(t)) for
+// k = 1..3 (r_0 = the tet's local vertex 0), lambda_0 = 1 - the others.
+#include "fepic_internal.h"
+
+namespace fepic {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int LE_A[6] = {0, 0, 0, 1, 1, 2};   // local edges (a, b), a < b
+constexpr int LE_B[6] = {1, 2, 3, 2, 3, 3};
+
+__device__ __forceinline__ void lam_at(const TetBlock<double>* bp, const double* r0, const double x[3],
+                                       double lam[4]) {
+    const double d0 = x[0] - r0[0], d1 = x[1] - r0[1], d2 = x[2] - r0[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lam[k + 1] = bp->gl[3 * k] * d0 + bp->gl[3 * k + 1] * d1 + bp->gl[3 * k + 2] * d2;
+    lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
+}
+
+__device__ __forceinline__ double min4(const double l[4]) { return fmin(fmin(l[0], l[1]), fmin(l[2], l[3])); }
+
+// r(s) and r'(s) of the Lagrange polynomial through P[j] at s_j = 1 - j, j = 0..np-1.
+__device__ __forceinline__ void path_at(const double P[][3], int np, double s, double r[3], double dr[3]) {
+    r[0] = r[1] = r[2] = 0.0;
+    dr[0] = dr[1] = dr[2] = 0.0;
+    for (int j = 0; j < np; ++j) {
+        const double sj = 1.0 - j;
+        double l = 1.0, dl = 0.0;
+        for (int m = 0; m < np; ++m) {
+            if (m == j) continue;
+            l *= (s - (1.0 - m)) / (sj - (1.0 - m));
+        }
+        for (int i = 0; i < np; ++i) {
+            if (i == j) continue;
+            double term = 1.0 / (sj - (1.0 - i));
+            for (int m = 0; m < np; ++m) {
+                if (m == j || m == i) continue;
+                term *= (s - (1.0 - m)) / (sj - (1.0 - m));
+            }
+            dl += term;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            r[d] += l * P[j][d];
+            dr[d] += dl * P[j][d];
+        }
+    }
+}
+
+__device__ __forceinline__ bool inside_at(const TetBlock<double>* bp, const double* r0, const double P[][3], int np,
+                                          double s) {
+    double r[3], dr[3], lam[4];
+    path_at(P, np, s, r, dr);
+    lam_at(bp, r0, r, lam);
+    return min4(lam) >= -kAbInsideEps;
+}
+
+// The piece [sa, sb] of the path in tet t: q w int W . r' ds into dg (ng-point Gauss-Legendre).
+__device__ __forceinline__ void deposit_piece(const TetBlock<double>* bp, const double* r0, const double P[][3],
+                                              int np, double sa, double sb, const AbParams& ap, int ng,
+                                              double* __restrict__ dg) {
+    const double half = 0.5 * (sb - sa);
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < ng; ++q) {
+        const double s = sa + half * (ap.gl_x[ng][q] + 1.0);
+        double r[3], dr[3], lam[4], dl[4];
+        path_at(P, np, s, r, dr);
+        lam_at(bp, r0, r, lam);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dl[k + 1] = bp->gl[3 * k] * dr[0] + bp->gl[3 * k + 1] * dr[1] + bp->gl[3 * k + 2] * dr[2];
+        dl[0] = -(dl[1] + dl[2] + dl[3]);
+        const double w = ap.gl_w[ng][q];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += w * (lam[LE_A[c]] * dl[LE_B[c]] - lam[LE_B[c]] * dl[LE_A[c]]);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) unsafeAtomicAdd(dg + bp->edge[c], ap.qw * half * acc[c]);
+}
+
+// History record of one particle (kAbStride doubles): r^{n-j} at 3j (j < 5), v^{n-j} at
+// 15 + 3j (j < 5), a^{n-1-j} at 30 + 3j (j < 4), and at 45 the number of past levels held.
+__global__ __launch_bounds__(kBlock) void k_push_ab(PArrays<double> p, int64_t n, const TetBlock<double>* __restrict__ blk,
+                                                     const double* __restrict__ r0s, double* __restrict__ hist,
+                                                     double* __restrict__ dg, AbParams ap,
+                                                     PushCounters* __restrict__ slots) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    unsigned int nc = 0, na = 0, ncap = 0;
+    if (i < n && p.tet[i] >= 0) {
+        double* H = hist + i * kAbStride;
+        int t = p.tet[i];
+        const TetBlock<double>* bp = blk + t;
+        // gather at the particle's barycentric point
+        const double l1 = p.l1[i], l2 = p.l2[i], l3 = p.l3[i];
+        const double lam[4] = {1.0 - l1 - l2 - l3, l1, l2, l3};
+        double g[4][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            g[1][d] = bp->gl[d];
+            g[2][d] = bp->gl[3 + d];
+            g[3][d] = bp->gl[6 + d];
+            g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+        }
+        double E[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const int a = LE_A[c], b = LE_B[c];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) E[d] += bp->e[c] * (lam[a] * g[b][d] - lam[b] * g[a][d]);
+        }
+        const double v[3] = {p.u0[i], p.u1[i], p.u2[i]};
+        const double acc[3] = {ap.qm * (E[0] + v[1] * bp->B[2] - v[2] * bp->B[1]),
+                               ap.qm * (E[1] + v[2] * bp->B[0] - v[0] * bp->B[2]),
+                               ap.qm * (E[2] + v[0] * bp->B[1] - v[1] * bp->B[0])};
+        const int held = (int)H[45];
+        const int m = min(ap.k, held + 1);
+        const double* beta = ap.beta[m - 1];
+        double vn[3], rn[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double dv = beta[0] * acc[d], dr = beta[0] * v[d];
+            for (int j = 1; j < m; ++j) {
+                dv += beta[j] * H[30 + 3 * (j - 1) + d];
+                dr += beta[j] * H[15 + 3 * j + d];
+            }
+            vn[d] = v[d] + ap.dt * dv;
+            rn[d] = H[d] + ap.dt * dr;
+        }
+        // the path's points: r^{n+1}, r^n, ..., r^{n+1-m}
+        double P[kAbMax + 1][3];
+        const int np = m + 1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) P[0][d] = rn[d];
+        for (int j = 1; j < np; ++j)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) P[j][d] = H[3 * (j - 1) + d];
+        const int ng = m + 1;
+        double sa = 0.0;
+        bool alive = true;
+        for (;;) {
+            const double* r0 = r0s + 3 * t;
+            double out = -1.0;
+            for (int q = 0; q <= ng; ++q) {
+                const double s = q < ng ? sa + (1.0 - sa) * 0.5 * (ap.gl_x[ng][q] + 1.0) : 1.0;
+                if (!inside_at(bp, r0, P, np, s)) {
+                    out = s;
+                    break;
+                }
+            }
+            if (out < 0.0) {
+                deposit_piece(bp, r0, P, np, sa, 1.0, ap, ng, dg);
+                break;
+            }
+            double lo = sa, hi = out;
+            for (int it = 0; it < 64 && hi - lo > kAbBisectTol; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (inside_at(bp, r0, P, np, mid)) lo = mid;
+                else hi = mid;
+            }
+            const double sx = 0.5 * (lo + hi);
+            deposit_piece(bp, r0, P, np, sa, sx, ap, ng, dg);
+            double r[3], dr[3], lo4[4];
+            path_at(P, np, hi, r, dr);
+            lam_at(bp, r0, r, lo4);
+            int kf = 0;
+#pragma unroll
+            for (int k = 1; k < 4; ++k)
+                if (lo4[k] < lo4[kf]) kf = k;
+            const int nb = bp->nbr[kf];
+            if (nb < 0) {
+                ++na;
+                alive = false;
+                break;
+            }
+            if (++nc > (unsigned)ap.cap) {
+                ++ncap;
+                alive = false;
+                break;
+            }
+            t = nb >> 2;
+            bp = blk + t;
+            sa = sx;
+        }
+        if (!alive) {
+            p.tet[i] = -1;
+        } else {
+            double lf[4];
+            lam_at(bp, r0s + 3 * t, rn, lf);
+            p.tet[i] = t;
+            p.l1[i] = lf[1];
+            p.l2[i] = lf[2];
+            p.l3[i] = lf[3];
+            p.u0[i] = vn[0];
+            p.u1[i] = vn[1];
+            p.u2[i] = vn[2];
+            // shift the history by one level
+            for (int j = kAbMax - 1; j >= 1; --j)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    H[3 * j + d] = H[3 * (j - 1) + d];
+                    H[15 + 3 * j + d] = H[15 + 3 * (j - 1) + d];
+                }
+            for (int j = kAbMax - 2; j >= 1; --j)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) H[30 + 3 * j + d] = H[30 + 3 * (j - 1) + d];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                H[d] = rn[d];
+                H[15 + d] = vn[d];
+                H[30 + d] = acc[d];
+            }
+            H[45] = (double)min(held + 1, kAbMax - 1);
+        }
+    }
+    // counters: per wave, then one add per wave into the workgroup's slot
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        nc += __shfl_xor(nc, off);
+        na += __shfl_xor(na, off);
+        ncap += __shfl_xor(ncap, off);
+    }
+    if ((threadIdx.x & 63) == 0 && (nc | na | ncap)) {
+        PushCounters* s = slots + (blockIdx.x & (kCntSlots - 1));
+        atomicAdd(&s->n_crossings, (unsigned long long)nc);
+        atomicAdd(&s->n_absorbed, na);
+        atomicAdd(&s->n_cap, ncap);
+    }
+}
+
+// History from the current state: r^n = r_0 + G^-1 (lambda_1, lambda_2, lambda_3) with G the
+// rows grad lambda_1..3 of the particle's tet; v^n = u; no past levels.
+__global__ __launch_bounds__(kBlock) void k_ab_init(PArrays<double> p, int64_t n, const TetBlock<double>* __restrict__ blk,
+                                                     const double* __restrict__ r0s, double* __restrict__ hist) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double* H = hist + i * kAbStride;
+    H[45] = 0.0;
+    const int t = p.tet[i];
+    if (t < 0) return;
+    const double* G = blk[t].gl;
+    const double* r0 = r0s + 3 * t;
+    const double a = G[0], b = G[1], c = G[2], d = G[3], e = G[4], f = G[5], g = G[6], h = G[7], k = G[8];
+    const double det = a * (e * k - f * h) - b * (d * k - f * g) + c * (d * h - e * g);
+    const double inv[9] = {(e * k - f * h) / det, (c * h - b * k) / det, (b * f - c * e) / det,
+                           (f * g - d * k) / det, (a * k - c * g) / det, (c * d - a * f) / det,
+                           (d * h - e * g) / det, (b * g - a * h) / det, (a * e - b * d) / det};
+    const double l[3] = {p.l1[i], p.l2[i], p.l3[i]};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) H[r] = r0[r] + inv[3 * r] * l[0] + inv[3 * r + 1] * l[1] + inv[3 * r + 2] * l[2];
+    H[15] = p.u0[i];
+    H[16] = p.u1[i];
+    H[17] = p.u2[i];
+}
+
+}  // namespace
+
+void launch_ab_init(hipStream_t s, PArrays<double> p, int64_t n, const TetBlock<double>* blk, const double* r0,
+                    double* hist) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_ab_init, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, p, n, blk, r0, hist);
+}
+
+void launch_push_ab(hipStream_t s, PArrays<double> p, int64_t n, const TetBlock<double>* blk, const double* r0,
+                    double* hist, double* dg, const AbParams& ap, PushCounters* slots) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_push_ab, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, p, n, blk, r0, hist, dg, ap, slots);
+}
+
+}  // namespace fepic

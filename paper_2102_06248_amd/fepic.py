@@ -101,6 +101,7 @@ _SIGS = {
     "fepic_get_particles": [_P, _INT, _I64, _PI64, _P, _P, _P, _P, _P],
     "fepic_step": [_P, _D, _D, _D, ctypes.POINTER(fepic_step_stats)],
     "fepic_push_particles": [_P, _D, ctypes.POINTER(fepic_step_stats)],
+    "fepic_push_particles_ab": [_P, _INT, _D, _INT, ctypes.POINTER(fepic_step_stats)],
     "fepic_get_fields": [_P, _P, _P, _P],
     "fepic_get_current": [_P, _P, _P],
     "fepic_get_rho": [_P, _P],
@@ -354,6 +355,12 @@ def fepic_step(ctx, dt, beta=0.25, gamma=0.5, check=True):
 def fepic_push_particles(ctx, dt):
     st = fepic_step_stats()
     _check(ctx, lib().fepic_push_particles(ctx, dt, ctypes.byref(st)))
+    return st
+
+
+def fepic_push_particles_ab(ctx, species, dt, order):
+    st = fepic_step_stats()
+    _check(ctx, lib().fepic_push_particles_ab(ctx, int(species), float(dt), int(order), ctypes.byref(st)))
     return st
 
 
