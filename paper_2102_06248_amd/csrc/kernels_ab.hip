@@ -36,52 +36,78 @@ __device__ __forceinline__ void lam_at(const TetBlock<double>* bp, const double*
 
 __device__ __forceinline__ double min4(const double l[4]) { return fmin(fmin(l[0], l[1]), fmin(l[2], l[3])); }
 
-// r(s) and r'(s) of the Lagrange polynomial through P[j] at s_j = 1 - j, j = 0..np-1.
-__device__ __forceinline__ void path_at(const double P[][3], int np, double s, double r[3], double dr[3]) {
-    r[0] = r[1] = r[2] = 0.0;
-    dr[0] = dr[1] = dr[2] = 0.0;
-    for (int j = 0; j < np; ++j) {
-        const double sj = 1.0 - j;
-        double l = 1.0, dl = 0.0;
-        for (int m = 0; m < np; ++m) {
-            if (m == j) continue;
-            l *= (s - (1.0 - m)) / (sj - (1.0 - m));
-        }
-        for (int i = 0; i < np; ++i) {
-            if (i == j) continue;
-            double term = 1.0 / (sj - (1.0 - i));
-            for (int m = 0; m < np; ++m) {
-                if (m == j || m == i) continue;
-                term *= (s - (1.0 - m)) / (sj - (1.0 - m));
-            }
-            dl += term;
-        }
+// The path of one step in Newton form on its nodes s_j = 1 - j (j = 0..M): r(s) =
+// sum_k c_k prod_{i<k} (s - s_i), with c_k the divided differences of the points P[j] at
+// s_j.  The nodes are unit-spaced, so each level of the table divides by -k.  Built once
+// per particle and step; every evaluation is then a nested product, without divisions.
+template <int M>
+struct NewtonPath {
+    double c[M + 1][3];
+    __device__ __forceinline__ explicit NewtonPath(const double P[M + 1][3]) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            r[d] += l * P[j][d];
-            dr[d] += dl * P[j][d];
+        for (int j = 0; j <= M; ++j)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) c[j][d] = P[j][d];
+#pragma unroll
+        for (int k = 1; k <= M; ++k) {
+            const double inv = -1.0 / (double)k;
+#pragma unroll
+            for (int j = M; j >= k; --j)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) c[j][d] = (c[j][d] - c[j - 1][d]) * inv;
         }
     }
-}
+    __device__ __forceinline__ void at(double s, double r[3]) const {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) r[d] = c[M][d];
+#pragma unroll
+        for (int k = M - 1; k >= 0; --k) {
+            const double f = s - (1.0 - k);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) r[d] = r[d] * f + c[k][d];
+        }
+    }
+    __device__ __forceinline__ void at(double s, double r[3], double dr[3]) const {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            r[d] = c[M][d];
+            dr[d] = 0.0;
+        }
+#pragma unroll
+        for (int k = M - 1; k >= 0; --k) {
+            const double f = s - (1.0 - k);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                dr[d] = dr[d] * f + r[d];
+                r[d] = r[d] * f + c[k][d];
+            }
+        }
+    }
+};
 
-__device__ __forceinline__ bool inside_at(const TetBlock<double>* bp, const double* r0, const double P[][3], int np,
+template <int M>
+__device__ __forceinline__ bool inside_at(const TetBlock<double>* bp, const double* r0, const NewtonPath<M>& path,
                                           double s) {
-    double r[3], dr[3], lam[4];
-    path_at(P, np, s, r, dr);
+    double r[3], lam[4];
+    path.at(s, r);
     lam_at(bp, r0, r, lam);
     return min4(lam) >= -kAbInsideEps;
 }
 
-// The piece [sa, sb] of the path in tet t: q w int W . r' ds into dg (ng-point Gauss-Legendre).
-__device__ __forceinline__ void deposit_piece(const TetBlock<double>* bp, const double* r0, const double P[][3],
-                                              int np, double sa, double sb, const AbParams& ap, int ng,
+// The piece [sa, sb] of the path in tet t: q w int W . r' ds into dg, with M + 1
+// Gauss-Legendre points.
+template <int M>
+__device__ __forceinline__ void deposit_piece(const TetBlock<double>* bp, const double* r0,
+                                              const NewtonPath<M>& path, double sa, double sb, const AbParams& ap,
                                               double* __restrict__ dg) {
+    constexpr int ng = M + 1;
     const double half = 0.5 * (sb - sa);
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
     for (int q = 0; q < ng; ++q) {
         const double s = sa + half * (ap.gl_x[ng][q] + 1.0);
         double r[3], dr[3], lam[4], dl[4];
-        path_at(P, np, s, r, dr);
+        path.at(s, r, dr);
         lam_at(bp, r0, r, lam);
 #pragma unroll
         for (int k = 0; k < 3; ++k) dl[k + 1] = bp->gl[3 * k] * dr[0] + bp->gl[3 * k + 1] * dr[1] + bp->gl[3 * k + 2] * dr[2];
@@ -92,6 +118,80 @@ __device__ __forceinline__ void deposit_piece(const TetBlock<double>* bp, const 
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) unsafeAtomicAdd(dg + bp->edge[c], ap.qw * half * acc[c]);
+}
+
+// Walks the order-M path of one step from tet t (Alg. 1 and 2) and deposits every piece.
+// Returns the final tet, or -1 when a wall absorbed the particle or it passed the crossing
+// cap (counted in na / ncap); nc counts the faces crossed.
+template <int M>
+__device__ __forceinline__ int walk_path(const TetBlock<double>* __restrict__ blk, const double* __restrict__ r0s, int t,
+                                      const double P[M + 1][3], const AbParams& ap, double* __restrict__ dg,
+                                      unsigned int& nc, unsigned int& na, unsigned int& ncap) {
+    constexpr int ng = M + 1;
+    const NewtonPath<M> path(P);
+    const TetBlock<double>* bp = blk + t;
+    double sa = 0.0;
+    unsigned int crossed = 0;
+    for (;;) {
+        const double* r0 = r0s + 3 * t;
+        double out = -1.0;
+#pragma unroll 1
+        for (int q = 0; q <= ng; ++q) {
+            const double s = q < ng ? sa + (1.0 - sa) * 0.5 * (ap.gl_x[ng][q] + 1.0) : 1.0;
+            if (!inside_at(bp, r0, path, s)) {
+                out = s;
+                break;
+            }
+        }
+        if (out < 0.0) {
+            deposit_piece(bp, r0, path, sa, 1.0, ap, dg);
+            nc += crossed;
+            return t;
+        }
+        double lo = sa, hi = out;
+        for (int it = 0; it < 64 && hi - lo > kAbBisectTol; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (inside_at(bp, r0, path, mid)) lo = mid;
+            else hi = mid;
+        }
+        const double sx = 0.5 * (lo + hi);
+        deposit_piece(bp, r0, path, sa, sx, ap, dg);
+        double r[3], lo4[4];
+        path.at(hi, r);
+        lam_at(bp, r0, r, lo4);
+        int kf = 0;
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            if (lo4[k] < lo4[kf]) kf = k;
+        const int nb = bp->nbr[kf];
+        if (nb < 0) {
+            nc += crossed;
+            ++na;
+            return -1;
+        }
+        if (++crossed > (unsigned)ap.cap) {
+            nc += crossed;
+            ++ncap;
+            return -1;
+        }
+        t = nb >> 2;
+        bp = blk + t;
+        sa = sx;
+    }
+}
+
+template <int M>
+__device__ __forceinline__ int walk_m(const TetBlock<double>* __restrict__ blk, const double* __restrict__ r0s, int t,
+                                      const double rn[3], const double* H, const AbParams& ap, double* __restrict__ dg,
+                                      unsigned int& nc, unsigned int& na, unsigned int& ncap) {
+    double P[M + 1][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) P[0][d] = rn[d];
+#pragma unroll
+    for (int j = 1; j <= M; ++j)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) P[j][d] = H[3 * (j - 1) + d];
+    return walk_path<M>(blk, r0s, t, P, ap, dg, nc, na, ncap);
 }
 
 // History record of one particle (kAbStride doubles): r^{n-j} at 3j (j < 5), v^{n-j} at
@@ -142,61 +242,16 @@ __global__ __launch_bounds__(kBlock) void k_push_ab(PArrays<double> p, int64_t n
             vn[d] = v[d] + ap.dt * dv;
             rn[d] = H[d] + ap.dt * dr;
         }
-        // the path's points: r^{n+1}, r^n, ..., r^{n+1-m}
-        double P[kAbMax + 1][3];
-        const int np = m + 1;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) P[0][d] = rn[d];
-        for (int j = 1; j < np; ++j)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) P[j][d] = H[3 * (j - 1) + d];
-        const int ng = m + 1;
-        double sa = 0.0;
-        bool alive = true;
-        for (;;) {
-            const double* r0 = r0s + 3 * t;
-            double out = -1.0;
-            for (int q = 0; q <= ng; ++q) {
-                const double s = q < ng ? sa + (1.0 - sa) * 0.5 * (ap.gl_x[ng][q] + 1.0) : 1.0;
-                if (!inside_at(bp, r0, P, np, s)) {
-                    out = s;
-                    break;
-                }
-            }
-            if (out < 0.0) {
-                deposit_piece(bp, r0, P, np, sa, 1.0, ap, ng, dg);
-                break;
-            }
-            double lo = sa, hi = out;
-            for (int it = 0; it < 64 && hi - lo > kAbBisectTol; ++it) {
-                const double mid = 0.5 * (lo + hi);
-                if (inside_at(bp, r0, P, np, mid)) lo = mid;
-                else hi = mid;
-            }
-            const double sx = 0.5 * (lo + hi);
-            deposit_piece(bp, r0, P, np, sa, sx, ap, ng, dg);
-            double r[3], dr[3], lo4[4];
-            path_at(P, np, hi, r, dr);
-            lam_at(bp, r0, r, lo4);
-            int kf = 0;
-#pragma unroll
-            for (int k = 1; k < 4; ++k)
-                if (lo4[k] < lo4[kf]) kf = k;
-            const int nb = bp->nbr[kf];
-            if (nb < 0) {
-                ++na;
-                alive = false;
-                break;
-            }
-            if (++nc > (unsigned)ap.cap) {
-                ++ncap;
-                alive = false;
-                break;
-            }
-            t = nb >> 2;
-            bp = blk + t;
-            sa = sx;
+        // the path through r^{n+1}, r^n, ..., r^{n+1-m}, walked with the order in use
+        switch (m) {
+            case 1: t = walk_m<1>(blk, r0s, t, rn, H, ap, dg, nc, na, ncap); break;
+            case 2: t = walk_m<2>(blk, r0s, t, rn, H, ap, dg, nc, na, ncap); break;
+            case 3: t = walk_m<3>(blk, r0s, t, rn, H, ap, dg, nc, na, ncap); break;
+            case 4: t = walk_m<4>(blk, r0s, t, rn, H, ap, dg, nc, na, ncap); break;
+            default: t = walk_m<5>(blk, r0s, t, rn, H, ap, dg, nc, na, ncap); break;
         }
+        const bool alive = t >= 0;
+        bp = alive ? blk + t : bp;
         if (!alive) {
             p.tet[i] = -1;
         } else {
