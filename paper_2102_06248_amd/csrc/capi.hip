@@ -1515,7 +1515,7 @@ int fepic_push_particles_ab(fepic_ctx* c, int species, double dt, int order, fep
     launch_stage<double>(c->stream, c->mesh.n_tets, (TetBlock<double>*)c->d_blk, c->d_e, c->d_b, c->d_grad64,
                          c->d_tet_edges, c->d_tet_faces);
     if (!s.ab_valid) {
-        launch_ab_init(c->stream, parr<double>(s, s.cur), s.n, blk, c->d_r0, s.d_abh);
+        launch_ab_init(c->stream, parr<double>(s, s.cur), s.n, blk, c->d_r0, s.d_abh, s.abh_cap);
         s.ab_valid = true;
     }
     launch_fill(c->stream, c->d_dgn, c->mesh.n_edges, 0.0);
@@ -1528,7 +1528,8 @@ int fepic_push_particles_ab(fepic_ctx* c, int species, double dt, int order, fep
     ap.cap = c->opt.crossing_cap;
     hipEvent_t* ev = timer_pair(c, FAM_PUSH);   // timed as the "push" family
     if (ev) (void)hipEventRecord(ev[0], c->stream);
-    launch_push_ab(c->stream, parr<double>(s, s.cur), s.n, blk, c->d_r0, s.d_abh, c->d_dgn, ap, c->d_cnt_slots);
+    launch_push_ab(c->stream, parr<double>(s, s.cur), s.n, blk, c->d_r0, s.d_abh, s.abh_cap, c->d_dgn, ap,
+                   c->d_cnt_slots);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
     launch_cnt_finish(c->stream, c->d_cnt_slots, c->d_cnt);
     HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(PushCounters), hipMemcpyDeviceToHost, c->stream));

@@ -72,8 +72,9 @@ struct PushParams {
 // (workgroup b -> slot b mod kCntSlots); launch_cnt_finish folds them into one.
 constexpr int kCntSlots = 256;
 
-// Adams-Bashforth pusher (all-FP64): orders 1..kAbMax, a history record of kAbStride
-// doubles per particle slot (r^{n-j}, v^{n-j} for j < 5, a^{n-1-j} for j < 4, levels held).
+// Adams-Bashforth pusher (all-FP64): orders 1..kAbMax, a history of kAbStride doubles per
+// particle slot (r^{n-j}, v^{n-j} for j < 5, a^{n-1-j} for j < 4, levels held), stored
+// component-major: component c of slot i at c * capacity + i.
 constexpr int kAbMax = 5;
 constexpr int kAbStride = 48;
 constexpr double kAbInsideEps = 1e-13;   // a point is in a tet when its smallest lambda >= -eps
@@ -214,9 +215,9 @@ template <typename T>
 void launch_kinetic(hipStream_t s, PArrays<T> p, int64_t n, double wmc2, double* out);
 void launch_count_live(hipStream_t s, const int32_t* tet, int64_t n, double* out);
 void launch_ab_init(hipStream_t s, PArrays<double> p, int64_t n, const TetBlock<double>* blk, const double* r0,
-                    double* hist);
+                    double* hist, int64_t hstride);
 void launch_push_ab(hipStream_t s, PArrays<double> p, int64_t n, const TetBlock<double>* blk, const double* r0,
-                    double* hist, double* dg, const AbParams& ap, PushCounters* slots);
+                    double* hist, int64_t hstride, double* dg, const AbParams& ap, PushCounters* slots);
 
 // Field kernels (kernels_fields.hip).
 void launch_fill(hipStream_t s, double* x, int64_t n, double v);

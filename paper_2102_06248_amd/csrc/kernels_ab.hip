@@ -3,7 +3,7 @@
 // Whitney-1 path integral of each curved piece by Gauss-Legendre quadrature.  All-FP64.
 //
 // One thread per particle.  The particle's past positions, velocities and accelerations
-// live in a per-particle history record; the step:
+// live in a per-particle history (structure of arrays); the step:
 //   a^n = (q/m)(E + v x B) from the staged tet record at the particle's barycentric point;
 //   order m = min(k, levels of history + 1);
 //   v^{n+1} = v^n + dt sum_j beta_j a^{n-j},  r^{n+1} = r^n + dt sum_j beta_j v^{n-j};
@@ -14,7 +14,8 @@
 //   bisection narrows the bracket to 1e-15 of the step; the exit face is the most negative
 //   barycentric coordinate at the bracket's outer end; a wall face absorbs the particle;
 //   deposit: each piece adds q w int W_ab(r(s)) . r'(s) ds over its interval with m + 1
-//   Gauss-Legendre points (exact: the integrand has degree 2m - 1), six FP64 atomics.
+//   Gauss-Legendre points (exact: the integrand has degree 2m - 1), six adds into the
+//   workgroup's LDS edge table, flushed to dG at the end.
 // Barycentric coordinates of a point x in tet t: lambda_k = grad lambda_k . (x - r_0(t)) for
 // k = 1..3 (r_0 = the tet's local vertex 0), lambda_0 = 1 - the others.
 #include "fepic_internal.h"
@@ -25,6 +26,35 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int LE_A[6] = {0, 0, 0, 1, 1, 2};   // local edges (a, b), a < b
 constexpr int LE_B[6] = {1, 2, 3, 2, 3, 3};
+
+// Per-workgroup table of edge currents in LDS (open addressing from a multiplicative hash,
+// linear probing).  A slot's key is read before it is claimed, so lanes adding to an edge
+// that is already there share one broadcast read; a value that finds no slot within
+// kProbe probes goes straight to the global vector.  Particles arrive sorted by tet, so a
+// workgroup's pieces touch few edges and most adds stay in LDS; the table is flushed with
+// one FP64 atomic per occupied slot.
+constexpr int kTableBits = 10;
+constexpr int kTableSlots = 1 << kTableBits;
+constexpr int kProbe = 8;
+
+struct EdgeTable {
+    int* key;
+    double* val;
+    double* dg;
+    __device__ __forceinline__ void add(int e, double v) const {
+        unsigned int h = ((unsigned int)e * 2654435761u) >> (32 - kTableBits);
+        for (int p = 0; p < kProbe; ++p) {
+            int k = __hip_atomic_load(key + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (k == -1) k = atomicCAS(key + h, -1, e);
+            if (k == -1 || k == e) {
+                __hip_atomic_fetch_add(val + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return;
+            }
+            h = (h + 1) & (kTableSlots - 1);
+        }
+        unsafeAtomicAdd(dg + e, v);
+    }
+};
 
 __device__ __forceinline__ void lam_at(const TetBlock<double>* bp, const double* r0, const double x[3],
                                        double lam[4]) {
@@ -94,12 +124,12 @@ __device__ __forceinline__ bool inside_at(const TetBlock<double>* bp, const doub
     return min4(lam) >= -kAbInsideEps;
 }
 
-// The piece [sa, sb] of the path in tet t: q w int W . r' ds into dg, with M + 1
+// The piece [sa, sb] of the path in tet t: q w int W . r' ds into the table, with M + 1
 // Gauss-Legendre points.
 template <int M>
 __device__ __forceinline__ void deposit_piece(const TetBlock<double>* bp, const double* r0,
                                               const NewtonPath<M>& path, double sa, double sb, const AbParams& ap,
-                                              double* __restrict__ dg) {
+                                              const EdgeTable& tab) {
     constexpr int ng = M + 1;
     const double half = 0.5 * (sb - sa);
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -117,7 +147,7 @@ __device__ __forceinline__ void deposit_piece(const TetBlock<double>* bp, const 
         for (int c = 0; c < 6; ++c) acc[c] += w * (lam[LE_A[c]] * dl[LE_B[c]] - lam[LE_B[c]] * dl[LE_A[c]]);
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) unsafeAtomicAdd(dg + bp->edge[c], ap.qw * half * acc[c]);
+    for (int c = 0; c < 6; ++c) tab.add(bp->edge[c], ap.qw * half * acc[c]);
 }
 
 // Walks the order-M path of one step from tet t (Alg. 1 and 2) and deposits every piece.
@@ -125,7 +155,7 @@ __device__ __forceinline__ void deposit_piece(const TetBlock<double>* bp, const 
 // cap (counted in na / ncap); nc counts the faces crossed.
 template <int M>
 __device__ __forceinline__ int walk_path(const TetBlock<double>* __restrict__ blk, const double* __restrict__ r0s, int t,
-                                      const double P[M + 1][3], const AbParams& ap, double* __restrict__ dg,
+                                      const double P[M + 1][3], const AbParams& ap, const EdgeTable& tab,
                                       unsigned int& nc, unsigned int& na, unsigned int& ncap) {
     constexpr int ng = M + 1;
     const NewtonPath<M> path(P);
@@ -144,7 +174,7 @@ __device__ __forceinline__ int walk_path(const TetBlock<double>* __restrict__ bl
             }
         }
         if (out < 0.0) {
-            deposit_piece(bp, r0, path, sa, 1.0, ap, dg);
+            deposit_piece(bp, r0, path, sa, 1.0, ap, tab);
             nc += crossed;
             return t;
         }
@@ -155,7 +185,7 @@ __device__ __forceinline__ int walk_path(const TetBlock<double>* __restrict__ bl
             else hi = mid;
         }
         const double sx = 0.5 * (lo + hi);
-        deposit_piece(bp, r0, path, sa, sx, ap, dg);
+        deposit_piece(bp, r0, path, sa, sx, ap, tab);
         double r[3], lo4[4];
         path.at(hi, r);
         lam_at(bp, r0, r, lo4);
@@ -180,9 +210,17 @@ __device__ __forceinline__ int walk_path(const TetBlock<double>* __restrict__ bl
     }
 }
 
+// One particle's history in the structure-of-arrays store: component c of particle i at
+// hist[c * stride + i], so a wave's loads of one component are contiguous.
+struct HistRef {
+    double* base;
+    int64_t stride;
+    __device__ __forceinline__ double& operator[](int c) const { return base[c * stride]; }
+};
+
 template <int M>
 __device__ __forceinline__ int walk_m(const TetBlock<double>* __restrict__ blk, const double* __restrict__ r0s, int t,
-                                      const double rn[3], const double* H, const AbParams& ap, double* __restrict__ dg,
+                                      const double rn[3], const HistRef& H, const AbParams& ap, const EdgeTable& tab,
                                       unsigned int& nc, unsigned int& na, unsigned int& ncap) {
     double P[M + 1][3];
 #pragma unroll
@@ -191,19 +229,27 @@ __device__ __forceinline__ int walk_m(const TetBlock<double>* __restrict__ blk, 
     for (int j = 1; j <= M; ++j)
 #pragma unroll
         for (int d = 0; d < 3; ++d) P[j][d] = H[3 * (j - 1) + d];
-    return walk_path<M>(blk, r0s, t, P, ap, dg, nc, na, ncap);
+    return walk_path<M>(blk, r0s, t, P, ap, tab, nc, na, ncap);
 }
 
-// History record of one particle (kAbStride doubles): r^{n-j} at 3j (j < 5), v^{n-j} at
+// History of one particle (kAbStride components): r^{n-j} at 3j (j < 5), v^{n-j} at
 // 15 + 3j (j < 5), a^{n-1-j} at 30 + 3j (j < 4), and at 45 the number of past levels held.
 __global__ __launch_bounds__(kBlock) void k_push_ab(PArrays<double> p, int64_t n, const TetBlock<double>* __restrict__ blk,
                                                      const double* __restrict__ r0s, double* __restrict__ hist,
-                                                     double* __restrict__ dg, AbParams ap,
+                                                     int64_t hstride, double* __restrict__ dg, AbParams ap,
                                                      PushCounters* __restrict__ slots) {
+    __shared__ int s_key[kTableSlots];
+    __shared__ double s_val[kTableSlots];
+    for (int k = threadIdx.x; k < kTableSlots; k += kBlock) {
+        s_key[k] = -1;
+        s_val[k] = 0.0;
+    }
+    __syncthreads();
+    const EdgeTable tab{s_key, s_val, dg};
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     unsigned int nc = 0, na = 0, ncap = 0;
     if (i < n && p.tet[i] >= 0) {
-        double* H = hist + i * kAbStride;
+        const HistRef H{hist + i, hstride};
         int t = p.tet[i];
         const TetBlock<double>* bp = blk + t;
         // gather at the particle's barycentric point
@@ -244,11 +290,11 @@ __global__ __launch_bounds__(kBlock) void k_push_ab(PArrays<double> p, int64_t n
         }
         // the path through r^{n+1}, r^n, ..., r^{n+1-m}, walked with the order in use
         switch (m) {
-            case 1: t = walk_m<1>(blk, r0s, t, rn, H, ap, dg, nc, na, ncap); break;
-            case 2: t = walk_m<2>(blk, r0s, t, rn, H, ap, dg, nc, na, ncap); break;
-            case 3: t = walk_m<3>(blk, r0s, t, rn, H, ap, dg, nc, na, ncap); break;
-            case 4: t = walk_m<4>(blk, r0s, t, rn, H, ap, dg, nc, na, ncap); break;
-            default: t = walk_m<5>(blk, r0s, t, rn, H, ap, dg, nc, na, ncap); break;
+            case 1: t = walk_m<1>(blk, r0s, t, rn, H, ap, tab, nc, na, ncap); break;
+            case 2: t = walk_m<2>(blk, r0s, t, rn, H, ap, tab, nc, na, ncap); break;
+            case 3: t = walk_m<3>(blk, r0s, t, rn, H, ap, tab, nc, na, ncap); break;
+            case 4: t = walk_m<4>(blk, r0s, t, rn, H, ap, tab, nc, na, ncap); break;
+            default: t = walk_m<5>(blk, r0s, t, rn, H, ap, tab, nc, na, ncap); break;
         }
         const bool alive = t >= 0;
         bp = alive ? blk + t : bp;
@@ -283,6 +329,9 @@ __global__ __launch_bounds__(kBlock) void k_push_ab(PArrays<double> p, int64_t n
             H[45] = (double)min(held + 1, kAbMax - 1);
         }
     }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kTableSlots; k += kBlock)
+        if (s_key[k] >= 0) unsafeAtomicAdd(dg + s_key[k], s_val[k]);
     // counters: per wave, then one add per wave into the workgroup's slot
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -301,10 +350,11 @@ __global__ __launch_bounds__(kBlock) void k_push_ab(PArrays<double> p, int64_t n
 // History from the current state: r^n = r_0 + G^-1 (lambda_1, lambda_2, lambda_3) with G the
 // rows grad lambda_1..3 of the particle's tet; v^n = u; no past levels.
 __global__ __launch_bounds__(kBlock) void k_ab_init(PArrays<double> p, int64_t n, const TetBlock<double>* __restrict__ blk,
-                                                     const double* __restrict__ r0s, double* __restrict__ hist) {
+                                                     const double* __restrict__ r0s, double* __restrict__ hist,
+                                                     int64_t hstride) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    double* H = hist + i * kAbStride;
+    const HistRef H{hist + i, hstride};
     H[45] = 0.0;
     const int t = p.tet[i];
     if (t < 0) return;
@@ -326,15 +376,16 @@ __global__ __launch_bounds__(kBlock) void k_ab_init(PArrays<double> p, int64_t n
 }  // namespace
 
 void launch_ab_init(hipStream_t s, PArrays<double> p, int64_t n, const TetBlock<double>* blk, const double* r0,
-                    double* hist) {
+                    double* hist, int64_t hstride) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_ab_init, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, p, n, blk, r0, hist);
+    hipLaunchKernelGGL(k_ab_init, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, p, n, blk, r0, hist, hstride);
 }
 
 void launch_push_ab(hipStream_t s, PArrays<double> p, int64_t n, const TetBlock<double>* blk, const double* r0,
-                    double* hist, double* dg, const AbParams& ap, PushCounters* slots) {
+                    double* hist, int64_t hstride, double* dg, const AbParams& ap, PushCounters* slots) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_push_ab, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, p, n, blk, r0, hist, dg, ap, slots);
+    hipLaunchKernelGGL(k_push_ab, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, p, n, blk, r0, hist, hstride, dg, ap,
+                       slots);
 }
 
 }  // namespace fepic
