@@ -73,7 +73,7 @@ struct PushParams {
 constexpr int kCntSlots = 256;
 
 // Adams-Bashforth pusher (all-FP64): orders 1..kAbMax, a history of kAbStride doubles per
-// particle slot (r^{n-j}, v^{n-j} for j < 5, a^{n-1-j} for j < 4, levels held), stored
+// particle slot (rings of 5 levels of r, v and a, the levels held, the rings' head), stored
 // component-major: component c of slot i at c * capacity + i.
 constexpr int kAbMax = 5;
 constexpr int kAbStride = 48;

@@ -218,22 +218,31 @@ struct HistRef {
     __device__ __forceinline__ double& operator[](int c) const { return base[c * stride]; }
 };
 
+// Slot of level j in a ring of kAbMax levels whose newest level sits at `head`.
+__device__ __forceinline__ int ring(int head, int j) {
+    const int s = head + j;
+    return s >= kAbMax ? s - kAbMax : s;
+}
+
 template <int M>
 __device__ __forceinline__ int walk_m(const TetBlock<double>* __restrict__ blk, const double* __restrict__ r0s, int t,
-                                      const double rn[3], const HistRef& H, const AbParams& ap, const EdgeTable& tab,
-                                      unsigned int& nc, unsigned int& na, unsigned int& ncap) {
+                                      const double rn[3], const HistRef& H, int head, const AbParams& ap,
+                                      const EdgeTable& tab, unsigned int& nc, unsigned int& na, unsigned int& ncap) {
     double P[M + 1][3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) P[0][d] = rn[d];
 #pragma unroll
     for (int j = 1; j <= M; ++j)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) P[j][d] = H[3 * (j - 1) + d];
+        for (int d = 0; d < 3; ++d) P[j][d] = H[3 * ring(head, j - 1) + d];
     return walk_path<M>(blk, r0s, t, P, ap, tab, nc, na, ncap);
 }
 
-// History of one particle (kAbStride components): r^{n-j} at 3j (j < 5), v^{n-j} at
-// 15 + 3j (j < 5), a^{n-1-j} at 30 + 3j (j < 4), and at 45 the number of past levels held.
+// History of one particle (kAbStride components): three rings of kAbMax levels that share
+// one head h (component 46): r^{n-j} at 3 ring(h, j), v^{n-j} at 15 + 3 ring(h, j) and
+// a^{n-1-j} at 30 + 3 ring(h, j), and at 45 the number of past levels held.  A step writes
+// its new level into the slot before the head, which holds the level no longer needed, and
+// moves the head there: nothing is shifted.
 __global__ __launch_bounds__(kBlock) void k_push_ab(PArrays<double> p, int64_t n, const TetBlock<double>* __restrict__ blk,
                                                      const double* __restrict__ r0s, double* __restrict__ hist,
                                                      int64_t hstride, double* __restrict__ dg, AbParams ap,
@@ -275,6 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_push_ab(PArrays<double> p, int64_t n
                                ap.qm * (E[1] + v[2] * bp->B[0] - v[0] * bp->B[2]),
                                ap.qm * (E[2] + v[0] * bp->B[1] - v[1] * bp->B[0])};
         const int held = (int)H[45];
+        const int head = (int)H[46];
         const int m = min(ap.k, held + 1);
         const double* beta = ap.beta[m - 1];
         double vn[3], rn[3];
@@ -282,19 +292,19 @@ __global__ __launch_bounds__(kBlock) void k_push_ab(PArrays<double> p, int64_t n
         for (int d = 0; d < 3; ++d) {
             double dv = beta[0] * acc[d], dr = beta[0] * v[d];
             for (int j = 1; j < m; ++j) {
-                dv += beta[j] * H[30 + 3 * (j - 1) + d];
-                dr += beta[j] * H[15 + 3 * j + d];
+                dv += beta[j] * H[30 + 3 * ring(head, j - 1) + d];
+                dr += beta[j] * H[15 + 3 * ring(head, j) + d];
             }
             vn[d] = v[d] + ap.dt * dv;
-            rn[d] = H[d] + ap.dt * dr;
+            rn[d] = H[3 * head + d] + ap.dt * dr;
         }
         // the path through r^{n+1}, r^n, ..., r^{n+1-m}, walked with the order in use
         switch (m) {
-            case 1: t = walk_m<1>(blk, r0s, t, rn, H, ap, tab, nc, na, ncap); break;
-            case 2: t = walk_m<2>(blk, r0s, t, rn, H, ap, tab, nc, na, ncap); break;
-            case 3: t = walk_m<3>(blk, r0s, t, rn, H, ap, tab, nc, na, ncap); break;
-            case 4: t = walk_m<4>(blk, r0s, t, rn, H, ap, tab, nc, na, ncap); break;
-            default: t = walk_m<5>(blk, r0s, t, rn, H, ap, tab, nc, na, ncap); break;
+            case 1: t = walk_m<1>(blk, r0s, t, rn, H, head, ap, tab, nc, na, ncap); break;
+            case 2: t = walk_m<2>(blk, r0s, t, rn, H, head, ap, tab, nc, na, ncap); break;
+            case 3: t = walk_m<3>(blk, r0s, t, rn, H, head, ap, tab, nc, na, ncap); break;
+            case 4: t = walk_m<4>(blk, r0s, t, rn, H, head, ap, tab, nc, na, ncap); break;
+            default: t = walk_m<5>(blk, r0s, t, rn, H, head, ap, tab, nc, na, ncap); break;
         }
         const bool alive = t >= 0;
         bp = alive ? blk + t : bp;
@@ -310,23 +320,16 @@ __global__ __launch_bounds__(kBlock) void k_push_ab(PArrays<double> p, int64_t n
             p.u0[i] = vn[0];
             p.u1[i] = vn[1];
             p.u2[i] = vn[2];
-            // shift the history by one level
-            for (int j = kAbMax - 1; j >= 1; --j)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    H[3 * j + d] = H[3 * (j - 1) + d];
-                    H[15 + 3 * j + d] = H[15 + 3 * (j - 1) + d];
-                }
-            for (int j = kAbMax - 2; j >= 1; --j)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) H[30 + 3 * j + d] = H[30 + 3 * (j - 1) + d];
+            // the new level goes into the slot before the head
+            const int nh = ring(head, kAbMax - 1);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                H[d] = rn[d];
-                H[15 + d] = vn[d];
-                H[30 + d] = acc[d];
+                H[3 * nh + d] = rn[d];
+                H[15 + 3 * nh + d] = vn[d];
+                H[30 + 3 * nh + d] = acc[d];
             }
             H[45] = (double)min(held + 1, kAbMax - 1);
+            H[46] = (double)nh;
         }
     }
     __syncthreads();
@@ -356,6 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_ab_init(PArrays<double> p, int64_t n
     if (i >= n) return;
     const HistRef H{hist + i, hstride};
     H[45] = 0.0;
+    H[46] = 0.0;
     const int t = p.tet[i];
     if (t < 0) return;
     const double* G = blk[t].gl;
