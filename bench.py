@@ -198,6 +198,14 @@ def ab_bench(args, F, torch, sim, wl, species):
     # vector written once
     total_bytes = psteps * per_ps + nl * (128 * len(wl["tets"]) + 8 * sizes["n_edges"])
     achieved = total_bytes / kernel_s / 1e9
+    # HBM bytes per launch from the committed counter summary, if taken on this kernel source
+    traffic = None
+    cpath = os.path.join(ROOT, "profiles", f"push_ab{k_ord}_{wl['name']}_counters.json")
+    if os.path.exists(cpath):
+        cd = json.load(open(cpath))
+        src = os.path.join(ROOT, "paper_2102_06248_amd", "csrc", cd["source"])
+        if cd.get("source_sha1") == hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]:
+            traffic = cd["hbm_bytes_per_launch"]
     out = {
         "metric": "particle-steps/s (Adams-Bashforth gather+push+curved walk+deposit, fields frozen)",
         "value": psteps / elapsed, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -209,7 +217,7 @@ def ab_bench(args, F, torch, sim, wl, species):
         "kernel_particle_steps_per_s": psteps / kernel_s,
         "crossings_per_particle_step": round(cross / psteps, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_push_ab",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_push_ab",
                      "avg_launch_us": round(kernel_s / nl * 1e6, 3), "launches": nl,
                      "algorithmic_bytes_per_particle_step": per_ps,
                      "algorithmic_bytes_per_launch": int(total_bytes / nl)},
