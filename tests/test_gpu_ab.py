@@ -1,6 +1,6 @@
 """GPU parity of the Adams-Bashforth pusher (fepic_push_particles_ab) against the oracle's
 (oracle/ab.py): the same seeded particles in the same seeded fields, stepped with orders 1
-to 4 for enough steps that the history reaches the full order.  Every step compares every
+to 5 for enough steps that the history reaches the full order.  Every step compares every
 particle's position and velocity, the absorbed set, and the deposited current on every
 edge, and checks charge continuity D^T dG = rho^{n+1} - rho^n on the library's own state.
 """
@@ -64,7 +64,7 @@ def ab_max():
     return 5
 
 
-@pytest.mark.parametrize("order", [1, 2, 3, 4])
+@pytest.mark.parametrize("order", [1, 2, 3, 4, 5])
 def test_ab_push_vs_oracle(F, order):
     announce(f"Adams-Bashforth pusher, order {order}")
     xyz, tets, h = jittered_kuhn(5, seed=21)
@@ -106,3 +106,24 @@ def test_ab_push_vs_oracle(F, order):
             rho_prev, G_prev = rho, G
         assert total_cross > n
         print(f"\n[ab] order {order}: {n_steps} steps, {total_cross} crossings, {len(ref[-1][0])} of {n} left")
+
+
+def test_ab_push_rejects_bad_calls(F):
+    """Order outside 1..5, a non-positive dt or an unknown species is FEPIC_E_ARG; the
+    pusher needs the all-FP64 particle path (FEPIC_E_STATE otherwise); nothing is pushed."""
+    announce("Adams-Bashforth pusher: argument and state errors")
+    xyz, tets, _ = jittered_kuhn(3, seed=5)
+    x = np.full((4, 3), 0.5) + 0.01 * np.arange(12).reshape(4, 3)
+    v = np.zeros((4, 3))
+    for precision, bad in [(F.FEPIC_ALL_FP64, [(0, 0, 1e-9), (0, 6, 1e-9), (0, 2, 0.0), (0, 2, -1e-9), (3, 2, 1e-9)]),
+                           (F.FEPIC_FP32_PUSH_FP64_ACC, [(0, 2, 1e-9)])]:
+        with F.Simulation(xyz, tets, device=0, precision=precision) as L:
+            sp = F.fepic_add_species(L.ctx, -1.0, 1.0, 1.0)
+            F.fepic_upload_particles(L.ctx, sp, x, v, ids=np.arange(4))
+            want = "FEPIC_E_ARG" if precision == F.FEPIC_ALL_FP64 else "FEPIC_E_STATE"
+            for species, order, dt in bad:
+                with pytest.raises(F.FepicError) as ei:
+                    F.fepic_push_particles_ab(L.ctx, species, dt, order)
+                assert F.ERROR_NAMES[ei.value.code] == want
+            gp = F.fepic_get_particles(L.ctx, sp)
+            assert np.allclose(np.sort(gp["x"], axis=0), np.sort(x, axis=0), atol=1e-12)
