@@ -138,3 +138,18 @@ def test_solve_precision_options(F):
             F.fepic_set_solve_precision(ctx, F.FEPIC_SOLVE_MIXED)
     finally:
         F.fepic_destroy(ctx)
+
+
+def test_ab_byte_model():
+    """Adams-Bashforth-k bytes per particle-step: the particle state both ways (tet, three
+    barycentric coordinates, velocity: 52 B each), the k positions, k - 1 velocities and
+    k - 1 accelerations the step reads, and the three new levels it writes."""
+    import bench
+    for k in range(1, 6):
+        reads = 8 * 3 * (k + (k - 1) + (k - 1))
+        assert bench.ab_bytes_per_particle_step(k) == 2 * 52 + reads + 8 * 9
+    assert bench.ab_bytes_per_particle_step(4) == 416
+    assert bench.ab_bytes_per_particle_step(2) == 272
+    # the committed counter summary names the kernel source it was taken on
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "..", "profiles", "push_ab4_c3_plasma_counters.json")))
+    assert d["source"] == "kernels_ab.hip" and len(d["source_sha1"]) == 12 and d["hbm_bytes_per_launch"] > 0
