@@ -26,6 +26,25 @@ LOCAL_EDGES = np.array([(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)], dtype=n
 LOCAL_FACES = np.array([(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)], dtype=np.int64)
 
 
+def _unique_rows(rows, n_nodes):
+    """Unique rows of non-negative ids below n_nodes in lexicographic order, and each
+    input row's index among them.  A row (a, b[, c]) is the base-n_nodes number
+    a n^2 + b n + c, whose numeric order is the rows' lexicographic order, so a 1-D unique
+    of these numbers gives the same result as a unique over rows, faster."""
+    rows = np.asarray(rows, dtype=np.int64)
+    if float(n_nodes) ** rows.shape[1] >= 2.0 ** 62:
+        return np.unique(rows, axis=0, return_inverse=True)
+    key = rows[:, 0].copy()
+    for j in range(1, rows.shape[1]):
+        key = key * n_nodes + rows[:, j]
+    u, inv = np.unique(key, return_inverse=True)
+    out = np.empty((len(u), rows.shape[1]), dtype=np.int64)
+    for j in range(rows.shape[1] - 1, -1, -1):
+        out[:, j] = u % n_nodes
+        u = u // n_nodes
+    return out, inv.reshape(-1)
+
+
 class Mesh:
     def __init__(self, xyz, tets):
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
@@ -36,13 +55,13 @@ class Mesh:
 
         # ---- edges
         inst = self.tets[:, LOCAL_EDGES].reshape(-1, 2)
-        self.edges, inv = np.unique(inst, axis=0, return_inverse=True)
+        self.edges, inv = _unique_rows(inst, self.n_nodes)
         self.tet_edges = inv.reshape(nt, 6).astype(np.int64)
         self.n_edges = self.edges.shape[0]
 
         # ---- faces
         inst = self.tets[:, LOCAL_FACES].reshape(-1, 3)
-        self.faces, inv = np.unique(inst, axis=0, return_inverse=True)
+        self.faces, inv = _unique_rows(inst, self.n_nodes)
         inv = inv.reshape(-1)
         self.tet_faces = inv.reshape(nt, 4).astype(np.int64)
         self.n_faces = self.faces.shape[0]

@@ -1,7 +1,10 @@
 // Field-side kernels for gfx950: Newmark right-hand side, PCG on a sliced-ELLPACK matrix
 // (slice height 64 = one wavefront, coalesced column loads) with the nodal auxiliary-space
-// preconditioner or with Jacobi, Faraday update and the conservation diagnostics.  All
-// arithmetic FP64.
+// preconditioner or with Jacobi, Faraday update and the conservation diagnostics.  Field
+// vectors, residuals, dot products and the diagnostics are FP64; the PCG kernels are
+// templated on their storage type, and the FP32 instances (matrix values, inverse
+// diagonals and iteration vectors rounded to FP32, dot products and step lengths still
+// FP64) run the inner passes of the mixed-precision solve.
 //
 // Grids are XCD-contiguous: the hardware hands workgroup b to XCD b % 8, so workgroup b
 // walks the row blocks of the b % 8-th eighth of the rows, giving each XCD's L2 one
