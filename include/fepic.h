@@ -333,6 +333,22 @@ int fepic_set_warm_start(fepic_ctx* ctx, int mode);
 int fepic_mlp_forward(fepic_ctx* ctx, int64_t n, const float* X, float* y);
 int fepic_mlp_grad(fepic_ctx* ctx, int64_t n, const float* X, const float* t, float* grad, double* loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * training or serving loops, harnesses that forbid hipMalloc): fepic_mlp_grad on device
+ * arrays, allocating nothing.  X [n][4] FP32 and t [n] FP32 are read, grad [4545] FP32 and
+ * loss [1] FP64 (the mean squared error) written, all in device memory of the context's
+ * device; the kernels are enqueued on the context's stream and the call returns without
+ * waiting (the caller synchronizes before reading the outputs).  The result is that of
+ * fepic_mlp_grad on the same rows, summed in the same order.  The per-workgroup partial
+ * sums live in one fixed device array of the library per GPU (2.3 MB, held until the
+ * process ends), set up by fepic_create: calls that overlap on one GPU, from any context
+ * or stream, race on it.  Errors: FEPIC_E_ARG for n <= 0, a NULL pointer or n above
+ * FEPIC_MLP_NOALLOC_MAX_ROWS; FEPIC_E_STATE when the context has no network weights yet
+ * (fepic_ws_set_weights or fepic_ws_train first; this call does not create them);
+ * FEPIC_E_NO_DEVICE on a host-only context. */
+#define FEPIC_MLP_NOALLOC_MAX_ROWS 65536
+int fepic_mlp_grad_noalloc(fepic_ctx* ctx, int64_t n, const float* X, const float* t, float* grad, double* loss);
+
 /* ---------------------------------------------------------------- checkpoint
  * Versioned binary file: fields and their history, current history, particles of every
  * species, step counter and time, warm-start weights.  Load requires a context with the

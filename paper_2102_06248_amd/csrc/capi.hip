@@ -954,6 +954,7 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
             return FEPIC_E_OOM;
         }
         for (auto& e : c->phase_ev) (void)hipEventCreate(&e);
+        mlp_noalloc_setup(o.device);
     }
     *out = c;
     return FEPIC_OK;

@@ -156,6 +156,7 @@ int mlp_warm_start(fepic_ctx* c);
 int mlp_record_features(fepic_ctx* c);
 int mlp_record_target(fepic_ctx* c);
 void mlp_destroy(fepic_ctx* c);
+void mlp_noalloc_setup(int device);
 int mlp_save(fepic_ctx* c, std::FILE* f);
 int mlp_load(fepic_ctx* c, std::FILE* f);
 }  // namespace fepic

@@ -378,6 +378,15 @@ __global__ __launch_bounds__(256) void k_mlp_reduce_adam(const float* __restrict
     }
 }
 
+// Mean squared error from the per-workgroup sums of k_mlp_grad (fixed order, one thread).
+__global__ __launch_bounds__(64) void k_mlp_loss_sum(const double* __restrict__ loss_part, int n_blocks, double inv_n,
+                                                     double* __restrict__ loss) {
+    if (threadIdx.x != 0) return;
+    double a = 0.0;
+    for (int b = 0; b < n_blocks; ++b) a += loss_part[b];
+    loss[0] = a * inv_n;
+}
+
 // Per-edge features over the interior edges: [e, e_prev, e_prev2] / s_e, dG / s_g.
 __global__ __launch_bounds__(256) void k_mlp_features(int64_t n_int, const int32_t* __restrict__ ie,
                                                       const double* __restrict__ e, const double* __restrict__ ep,
@@ -485,6 +494,10 @@ void mlp_launch_grad(hipStream_t s, const float* X, const float* T, int64_t n, i
                      const float* P, float* part, double* loss_part, int blocks) {
     BatchSrc src{(const float4*)X, T, n, n_all, seed};
     hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(kMlpBlock), 0, s, src, 1.0f / (float)n, P, part, loss_part);
+}
+
+void mlp_launch_loss_sum(hipStream_t s, const double* loss_part, int blocks, double inv_n, double* loss) {
+    hipLaunchKernelGGL(k_mlp_loss_sum, dim3(1), dim3(64), 0, s, loss_part, blocks, inv_n, loss);
 }
 
 void mlp_launch_reduce_adam(hipStream_t s, const float* part, int blocks, float* grad, float* P, float* m, float* v,

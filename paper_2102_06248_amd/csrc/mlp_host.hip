@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <vector>
 
@@ -17,9 +18,42 @@ void mlp_launch_grad(hipStream_t s, const float* X, const float* T, int64_t n, i
                      const float* P, float* part, double* loss_part, int blocks);
 void mlp_launch_reduce_adam(hipStream_t s, const float* part, int blocks, float* grad, float* P, float* m, float* v,
                             int adam, float lr, float b1, float b2, float eps, float bc1, float bc2);
+void mlp_launch_loss_sum(hipStream_t s, const double* loss_part, int blocks, double inv_n, double* loss);
 
 constexpr int kNP = FEPIC_MLP_N_PARAMS;
 constexpr int kMaxGradBlocks = 512;
+
+// ---- scratch of the allocation-free gradient (fepic_mlp_grad_noalloc)
+// The per-workgroup partial gradients (kNP floats each) and partial squared errors of
+// k_mlp_grad, for at most kNoAllocBlocks workgroups: mlp_grad_blocks(n) <= 128 exactly
+// when n <= FEPIC_MLP_NOALLOC_MAX_ROWS, so the allocation-free call launches the same grid
+// as fepic_mlp_grad and sums in the same order.  Every workgroup overwrites its whole
+// slice, so nothing needs clearing between calls.  One copy per GPU, for the life of the
+// process.
+constexpr int kNoAllocBlocks = 128;
+constexpr size_t kScratchGradBytes = sizeof(float) * (size_t)kNP * kNoAllocBlocks;
+constexpr size_t kScratchBytes = kScratchGradBytes + sizeof(double) * kNoAllocBlocks;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of scratch on each GPU (the array's name is only a host-side handle).
+constexpr int kMaxScratchDevices = 64;
+static void* g_scratch_addr[kMaxScratchDevices] = {};
+static hipError_t g_scratch_err[kMaxScratchDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Called by fepic_create with the context's device current: looks the array's address up
+// once per device.
+void mlp_noalloc_setup(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_addr[device]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && p) g_scratch_addr[device] = p;
+    else g_scratch_err[device] = (e == hipSuccess ? hipErrorInvalidSymbol : e);
+}
+
+static_assert(FEPIC_MLP_NOALLOC_MAX_ROWS == 32 * 16 * kNoAllocBlocks, "grid of the allocation-free gradient");
 
 struct MlpState {
     float* P = nullptr;      // FP32 master weights
@@ -358,6 +392,33 @@ int fepic_mlp_forward(fepic_ctx* c, int64_t n, const float* X, float* y) {
     HIPCHK_RET(c, hipStreamSynchronize(c->stream));
     HIPCHK_RET(c, hipMemcpy(y, dy, sizeof(float) * n, hipMemcpyDeviceToHost));
     dfree(c, dy);
+    return FEPIC_OK;
+}
+
+int fepic_mlp_grad_noalloc(fepic_ctx* c, int64_t n, const float* X, const float* t, float* grad, double* loss) {
+    if (!c) return FEPIC_E_ARG;
+    if (c->host_only) return fail(c, FEPIC_E_NO_DEVICE, "host-only context");
+    if (n <= 0 || !X || !t || !grad || !loss) return fail(c, FEPIC_E_ARG, "fepic_mlp_grad_noalloc: bad arguments");
+    if (n > FEPIC_MLP_NOALLOC_MAX_ROWS)
+        return fail(c, FEPIC_E_ARG,
+                    "fepic_mlp_grad_noalloc: n = " + std::to_string(n) + " rows exceeds FEPIC_MLP_NOALLOC_MAX_ROWS = " +
+                        std::to_string(FEPIC_MLP_NOALLOC_MAX_ROWS));
+    if (!c->mlp || !c->mlp->have_weights)
+        return fail(c, FEPIC_E_STATE, "fepic_mlp_grad_noalloc: no network weights (set or train them first)");
+    const int dev = c->opt.device;
+    void* base = (dev >= 0 && dev < kMaxScratchDevices) ? g_scratch_addr[dev] : nullptr;
+    if (!base) {
+        const hipError_t e = (dev >= 0 && dev < kMaxScratchDevices) ? g_scratch_err[dev] : hipErrorInvalidDevice;
+        return hip_fail(c, e == hipSuccess ? hipErrorInvalidSymbol : e, "hipGetSymbolAddress(scratch)");
+    }
+    const int blocks = mlp_grad_blocks(n);
+    if (blocks > kNoAllocBlocks) return fail(c, FEPIC_E_ARG, "fepic_mlp_grad_noalloc: grid exceeds the scratch");
+    float* part = (float*)base;
+    double* loss_part = (double*)((unsigned char*)base + kScratchGradBytes);
+    mlp_launch_grad(c->stream, X, t, n, 0, 0, c->mlp->P, part, loss_part, blocks);
+    mlp_launch_reduce_adam(c->stream, part, blocks, grad, nullptr, nullptr, nullptr, 0, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f);
+    mlp_launch_loss_sum(c->stream, loss_part, blocks, 1.0 / (double)n, loss);
+    HIPCHK_RET(c, hipGetLastError());
     return FEPIC_OK;
 }
 

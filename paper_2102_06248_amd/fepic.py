@@ -25,6 +25,7 @@ FEPIC_SOLVE_FP64, FEPIC_SOLVE_MIXED = 0, 1
 FEPIC_E_CG_NOT_CONVERGED = -6
 FEPIC_E_CROSSING_CAP = -7
 FEPIC_MLP_N_PARAMS = 4545
+FEPIC_MLP_NOALLOC_MAX_ROWS = 65536   # include/fepic.h
 
 ERROR_NAMES = {-1: "FEPIC_E_ARG", -2: "FEPIC_E_MESH", -3: "FEPIC_E_STATE", -4: "FEPIC_E_OOM", -5: "FEPIC_E_HIP",
                -6: "FEPIC_E_CG_NOT_CONVERGED", -7: "FEPIC_E_CROSSING_CAP", -8: "FEPIC_E_IO", -9: "FEPIC_E_NO_DEVICE"}
@@ -118,6 +119,7 @@ _SIGS = {
     "fepic_set_solve_precision": [_P, _INT],
     "fepic_mlp_forward": [_P, _I64, _P, _P],
     "fepic_mlp_grad": [_P, _I64, _P, _P, _P, ctypes.POINTER(_D)],
+    "fepic_mlp_grad_noalloc": [_P, _I64, _P, _P, _P, _P],
     "fepic_save": [_P, ctypes.c_char_p],
     "fepic_load": [_P, ctypes.c_char_p],
 }
@@ -459,6 +461,12 @@ def fepic_mlp_grad(ctx, X, t):
     loss = ctypes.c_double()
     _check(ctx, lib().fepic_mlp_grad(ctx, len(X), _ptr(X), _ptr(t), _ptr(g), ctypes.byref(loss)))
     return loss.value, g
+
+
+def fepic_mlp_grad_noalloc(ctx, n, X_dev, t_dev, grad_dev, loss_dev):
+    """Device pointers (ints, e.g. torch tensors' data_ptr()); enqueued on the context's
+    stream, nothing allocated, no synchronization."""
+    _check(ctx, lib().fepic_mlp_grad_noalloc(ctx, n, X_dev, t_dev, grad_dev, loss_dev))
 
 
 def fepic_save(ctx, path):
