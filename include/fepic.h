@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define FEPIC_ABI_VERSION 4
+#define FEPIC_ABI_VERSION 5
 
 enum {
     FEPIC_OK = 0,
@@ -98,6 +98,24 @@ enum { FEPIC_SOLVE_FP64 = 0, FEPIC_SOLVE_MIXED = 1 };
  * particle.  Results agree to the rounding order of the current sums either way. */
 enum { FEPIC_WALK_AUTO = 0, FEPIC_WALK_QUEUE = 1, FEPIC_WALK_FUSED = 2 };
 
+/* Particle pusher of fepic_step and fepic_push_particles.  FEPIC_PUSHER_BORIS: relativistic
+ * Boris with straight paths (u = gamma v at t_{n-1/2}).  FEPIC_PUSHER_AB: the paper's own
+ * pusher (Sec. III-B, III-C, Alg. 1 and 2): Adams-Bashforth of order ab_order (1..5) of the
+ * non-relativistic equations dv/dt = (q/m)(E + v x B), dr/dt = v, with u read and written as
+ * the velocity v at t_n; the path over a step is the Lagrange polynomial through r^{n+1}
+ * and the last `order` positions, followed cell by cell (exits bracketed by Gauss-Legendre
+ * points, then located to 1e-15 of the step where the smallest barycentric coordinate
+ * reaches -1e-13; wall faces absorb), and each piece's Whitney-1 path integral, by
+ * (order + 1)-point Gauss-Legendre quadrature (exact), is closed onto the face it leaves
+ * by with a straight segment, so that D^T dG = q w (lambda_end - lambda_start) holds to
+ * round-off (Sec. III-A).  Needs FEPIC_ALL_FP64.  Each particle slot keeps its last five
+ * positions, velocities and accelerations; the sort moves them with the particle.  A
+ * particle starts at order 1 from its state (after upload or injection) and gains one
+ * order per step; every history restarts at order 1 when dt changes (the coefficients
+ * assume equally spaced levels), after a Boris step or a pusher switch, and after
+ * fepic_load. */
+enum { FEPIC_PUSHER_BORIS = 0, FEPIC_PUSHER_AB = 1 };
+
 typedef struct fepic_ctx fepic_ctx;
 
 typedef struct {
@@ -123,6 +141,8 @@ typedef struct {
     int solve_precision;   /* FEPIC_SOLVE_* (default FEPIC_SOLVE_FP64)                    */
     double mixed_inner_tol;/* FEPIC_SOLVE_MIXED: residual reduction of one FP32 pass, in
                               (0, 1) (default 1e-4)                                       */
+    int pusher;            /* FEPIC_PUSHER_* (default FEPIC_PUSHER_BORIS)                 */
+    int ab_order;          /* FEPIC_PUSHER_AB: order 1..5 (default 4)                     */
 } fepic_options;
 
 typedef struct {
@@ -175,6 +195,10 @@ int fepic_set_preconditioner(fepic_ctx* ctx, int pc);
 /* Selects the arithmetic of later Newmark solves (FEPIC_SOLVE_*; FEPIC_E_ARG for any other
  * value, and for FEPIC_SOLVE_MIXED with the Jacobi preconditioner). */
 int fepic_set_solve_precision(fepic_ctx* ctx, int solve_precision);
+/* Selects the pusher (FEPIC_PUSHER_*) and Adams-Bashforth order (1..5) of later steps;
+ * FEPIC_E_ARG for other values and for FEPIC_PUSHER_AB without FEPIC_ALL_FP64.  A switch of
+ * pusher restarts the Adams-Bashforth histories. */
+int fepic_set_pusher(fepic_ctx* ctx, int pusher, int ab_order);
 /* Runs all later device work of this context on the given hipStream_t (NULL = the
  * context's own stream).  The caller keeps the stream alive while the context uses it. */
 int fepic_set_stream(fepic_ctx* ctx, void* hip_stream);
@@ -255,26 +279,10 @@ int fepic_get_particles(fepic_ctx* ctx, int species, int64_t cap, int64_t* n, in
  * FEPIC_E_CG_NOT_CONVERGED or FEPIC_E_CROSSING_CAP nothing is committed.  out may be
  * NULL. */
 int fepic_step(fepic_ctx* ctx, double dt, double beta, double gamma, fepic_step_stats* out);
-/* Particle half only (fields frozen): stage, gather, push, track, deposit; commits the
- * particles and dG^{n+1} (the field history is left as is).  out may be NULL. */
+/* Particle half only (fields frozen): stage, gather, push (the configured pusher), track,
+ * deposit; commits the particles and dG^{n+1} (the field history is left as is).  Atomic
+ * like fepic_step: on FEPIC_E_CROSSING_CAP nothing is committed.  out may be NULL. */
 int fepic_push_particles(fepic_ctx* ctx, double dt, fepic_step_stats* out);
-/* The paper's own pusher for one species, fields frozen (Sec. III-B, III-C, Alg. 1 and 2):
- * one Adams-Bashforth step of the given order (1..5) of the non-relativistic equations
- * dv/dt = (q/m)(E + v x B), dr/dt = v, with u read and written as the velocity v at t_n;
- * the path over the step is the Lagrange polynomial through r^{n+1} and the last `order`
- * positions, followed cell by cell (exits bracketed by Gauss-Legendre points, then
- * bisected to 1e-15 of the step; wall faces absorb), and each piece's Whitney-1 path
- * integral, by (order + 1)-point Gauss-Legendre quadrature (exact), is added to dG^{n+1}.
- * Each particle slot keeps its last positions, velocities and accelerations; a history
- * starts from the current state at the first call and after any upload, injection, step
- * or checkpoint load, and the order grows from 1 as levels accumulate.  Commits the
- * particles and dG^{n+1} like fepic_push_particles, in place (no sort).  Needs
- * FEPIC_ALL_FP64 (FEPIC_E_STATE otherwise); FEPIC_E_ARG for a bad species, order or dt.
- * Particles whose path exceeds the crossing cap are dropped, the step is still committed,
- * and FEPIC_E_CROSSING_CAP is returned.  out->n_particles is the species' live count after
- * the step.  The kernel is timed as the "push" family (fepic_kernel_timing).  out may be
- * NULL. */
-int fepic_push_particles_ab(fepic_ctx* ctx, int species, double dt, int order, fepic_step_stats* out);
 
 /* ---------------------------------------------------------------- read-out
  * Host copies; sizes from fepic_get_topology_sizes.  Any output may be NULL. */

@@ -184,7 +184,7 @@ class Mesh:
             self._centroid = self.xyz[self.tets].mean(axis=1)
             self._kdtree = cKDTree(self._centroid)
         k = min(n_candidates, self.n_tets)
-        _, cand = self._kdtree.query(x, k=k)
+        _, cand = self._kdtree.query(x, k=k, workers=-1)
         cand = np.asarray(cand).reshape(len(x), k)
         lam = self.barycentric(cand, np.repeat(x[:, None, :], k, axis=1))
         score = lam.min(axis=2)

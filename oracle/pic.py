@@ -17,6 +17,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse.linalg as spla
 
+from . import ab
 from . import diagnostics as dg_
 from . import fem, newmark
 from .mesh import Mesh
@@ -34,7 +35,11 @@ class Species:
 
 
 class OracleSim:
-    def __init__(self, xyz, tets, cg_tol=1e-10, cg_maxit=10000, crossing_cap=64):
+    def __init__(self, xyz, tets, cg_tol=1e-10, cg_maxit=10000, crossing_cap=64, pusher="boris", ab_order=4):
+        """pusher: "boris" (relativistic Boris, straight paths; u = gamma v at t_{n-1/2}) or
+        "ab" (the Adams-Bashforth pusher of Sec. III-B of order ab_order with its curved
+        paths; u = v at t_n)."""
+        self.pusher, self.ab_order = pusher, ab_order
         self.mesh = m = Mesh(xyz, tets)
         self.cmesh = CMesh(m)
         self.cg_tol, self.cg_maxit, self.cap = cg_tol, cg_maxit, crossing_cap
@@ -60,7 +65,9 @@ class OracleSim:
 
     # ------------------------------------------------------------------ set-up
     def add_species(self, q, m, w):
-        self.species.append(Species(q, m, w))
+        sp_ = Species(q, m, w)
+        sp_.hist = ab.Histories()
+        self.species.append(sp_)
         return len(self.species) - 1
 
     def upload_particles(self, s, x, u, ids=None):
@@ -124,6 +131,13 @@ class OracleSim:
         st = {"n_crossings": 0, "max_crossings": 0, "n_absorbed": 0, "n_cap_exceeded": 0}
         for sp_ in self.species:
             if len(sp_.tet) == 0:
+                continue
+            if self.pusher == "ab":
+                nc, na, ncap = ab.push_species(self.mesh, sp_.ids, sp_.x, sp_.u, sp_.tet, sp_.alive, sp_.q, sp_.m,
+                                               sp_.w, dt, self.ab_order, self.e, self.b, dG_new, sp_.hist, self.cap)
+                st["n_crossings"] += nc
+                st["n_absorbed"] += na
+                st["n_cap_exceeded"] += ncap
                 continue
             rc, s = push(self.cmesh, sp_.x, sp_.u, sp_.tet, sp_.alive, sp_.q, sp_.m, sp_.w, dt,
                          self.e, self.b, dG_new, self.cap)

@@ -129,6 +129,30 @@ size_t array_bytes(const fepic_ctx* c, int a, int64_t n) {
     return field_size(c) * (size_t)n;
 }
 
+// Makes an existing Adams-Bashforth history match the species' particle capacity, keeping
+// the history of slots [0, n) (one 2-D copy per array: the component stride changes).
+int ab_fit(fepic_ctx* c, Species& s) {
+    if (!s.d_abh[0] || s.abh_cap == s.cap) return FEPIC_OK;
+    double* nh[2] = {dalloc<double>(c, s.cap * kAbStride), dalloc<double>(c, s.cap * kAbStride)};
+    int32_t* nm[2] = {dalloc<int32_t>(c, s.cap), dalloc<int32_t>(c, s.cap)};
+    if (!nh[0] || !nh[1] || !nm[0] || !nm[1]) return fail(c, FEPIC_E_OOM, "history allocation failed");
+    if (!s.ab_reset && s.n > 0) {
+        HIPCHK(c, hipMemcpy2DAsync(nh[0], 8 * s.cap, s.d_abh[s.abh_cur], 8 * s.abh_cap, 8 * s.n, kAbStride,
+                                   hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(nm[0], s.d_abm[s.abm_cur], 4 * s.n, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int w = 0; w < 2; ++w) {
+        dfree(c, s.d_abh[w]);
+        dfree(c, s.d_abm[w]);
+        s.d_abh[w] = nh[w];
+        s.d_abm[w] = nm[w];
+    }
+    s.abh_cur = s.abm_cur = 0;
+    s.abh_cap = s.cap;
+    return FEPIC_OK;
+}
+
 int ensure_capacity(fepic_ctx* c, Species& s, int64_t need) {
     if (need <= s.cap) return FEPIC_OK;
     const int64_t cap = std::max<int64_t>({need, s.cap + s.cap / 4, 1024});
@@ -149,18 +173,45 @@ int ensure_capacity(fepic_ctx* c, Species& s, int64_t need) {
     s.cur = 0;
     s.idcur = 0;
     s.cap = cap;
-    return FEPIC_OK;
+    return ab_fit(c, s);
+}
+
+bool ab_carry(const fepic_ctx* c, const Species& s) {
+    return c->opt.pusher == FEPIC_PUSHER_AB && s.d_abh[0] && !s.ab_reset;
+}
+
+// Slots appended since the last Adams-Bashforth step have no history yet (AbMeta -1).
+void ab_mark_new(fepic_ctx* c, Species& s) {
+    if (ab_carry(c, s) && s.ab_fill_from < s.n)
+        launch_fill_i32(c->stream, s.d_abm[s.abm_cur] + s.ab_fill_from, s.n - s.ab_fill_from, -1);
+    s.ab_fill_from = INT64_MAX;
 }
 
 template <typename T>
 void sort_species(fepic_ctx* c, Species& s) {
     hipEvent_t* ev = timer_pair(c, FAM_SORT);
     if (ev) (void)hipEventRecord(ev[0], c->stream);
+    AbHistIo ab;
+    const bool carry = ab_carry(c, s);
+    if (carry) {   // the Adams-Bashforth history moves with the particles
+        ab_mark_new(c, s);
+        ab.hin = s.d_abh[s.abh_cur];
+        ab.hout = s.d_abh[1 - s.abh_cur];
+        ab.stride = s.abh_cap;
+        ab.min = s.d_abm[s.abm_cur];
+        ab.mout = s.d_abm[1 - s.abm_cur];
+    }
     launch_sort<T>(c->stream, parr<T>(s, s.cur), parr<T>(s, 1 - s.cur), s.n, c->mesh.n_tets, c->d_count, c->d_offset,
-                   c->d_bsums, s.d_nlive);
+                   c->d_bsums, s.d_nlive, ab);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
     s.cur = 1 - s.cur;
     s.idcur = 1 - s.idcur;
+    if (carry) {
+        s.abh_cur = 1 - s.abh_cur;
+        s.abm_cur = 1 - s.abm_cur;
+    } else {
+        s.ab_reset = true;
+    }
     s.sorted_pending = true;
 }
 
@@ -285,8 +336,80 @@ void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
     ev_mark(c, 3);
 }
 
+void ab_tables(AbParams& ap);
+
+// Sizes the species' Adams-Bashforth history and marks the slots whose history is missing or
+// stale (dt changed: the coefficients assume equally spaced levels) to restart at order 1.
+int ab_prepare(fepic_ctx* c, Species& s, double dt) {
+    if (!s.d_abh[0]) {
+        for (int w = 0; w < 2; ++w) {
+            s.d_abh[w] = dalloc<double>(c, s.cap * kAbStride);
+            s.d_abm[w] = dalloc<int32_t>(c, s.cap);
+            if (!s.d_abh[w] || !s.d_abm[w]) return fail(c, FEPIC_E_OOM, "history allocation failed");
+        }
+        s.abh_cap = s.cap;
+        s.abh_cur = s.abm_cur = 0;
+        s.ab_reset = true;
+    }
+    int rc = ab_fit(c, s);
+    if (rc != FEPIC_OK) return rc;
+    if (s.ab_reset || s.ab_dt != dt) {
+        launch_fill_i32(c->stream, s.d_abm[s.abm_cur], s.n, -1);
+        s.ab_reset = false;
+        s.ab_fill_from = INT64_MAX;
+        s.ab_dt = dt;
+    } else {
+        ab_mark_new(c, s);
+    }
+    return FEPIC_OK;
+}
+
+// The Adams-Bashforth particle phase (all-FP64): the sort carries the histories; one
+// k_push_ab per species into d_dgn, the alternate particle buffers and the alternate AbMeta.
+// Nothing is committed here.
+void particle_phase_ab(fepic_ctx* c, double dt, bool do_sort) {
+    for (auto& s : c->species) {
+        const int rc = ab_prepare(c, s, dt);
+        if (rc != FEPIC_OK) {
+            c->deferred_err = rc;
+            return;
+        }
+    }
+    ev_mark(c, 0);
+    if (do_sort) sort_all(c);
+    ev_mark(c, 1);
+    {
+        hipEvent_t* ev = timer_pair(c, FAM_STAGE);
+        if (ev) (void)hipEventRecord(ev[0], c->stream);
+        launch_stage<double>(c->stream, c->mesh.n_tets, (TetBlock<double>*)c->d_blk, c->d_e, c->d_b, c->d_grad64,
+                             c->d_tet_edges, c->d_tet_faces);
+        if (ev) (void)hipEventRecord(ev[1], c->stream);
+    }
+    ev_mark(c, 2);
+    launch_fill(c->stream, c->d_dgn, c->mesh.n_edges, 0.0);
+    AbParams ap;
+    ab_tables(ap);
+    ap.dt = dt;
+    ap.k = c->opt.ab_order;
+    ap.cap = c->opt.crossing_cap;
+    for (auto& s : c->species) {
+        if (s.n == 0) continue;
+        ap.qm = s.q / s.m;
+        ap.qw = s.q * s.w;
+        hipEvent_t* ev = timer_pair(c, FAM_PUSH);
+        if (ev) (void)hipEventRecord(ev[0], c->stream);
+        launch_push_ab(c->stream, parr<double>(s, s.cur), parr<double>(s, 1 - s.cur), s.n,
+                       (const TetBlock<double>*)c->d_blk, c->d_r0, s.d_abh[s.abh_cur], s.abh_cap, s.d_abm[s.abm_cur],
+                       s.d_abm[1 - s.abm_cur], c->d_dgn, ap, c->d_cnt_slots, s.sorted_pending ? s.d_nlive : nullptr);
+        if (ev) (void)hipEventRecord(ev[1], c->stream);
+    }
+    launch_cnt_finish(c->stream, c->d_cnt_slots, c->d_cnt);
+    ev_mark(c, 3);
+}
+
 void particle_phase(fepic_ctx* c, double dt, bool do_sort) {
-    if (c->opt.precision == FEPIC_ALL_FP64) particle_phase_T<double>(c, dt, do_sort);
+    if (c->opt.pusher == FEPIC_PUSHER_AB) particle_phase_ab(c, dt, do_sort);
+    else if (c->opt.precision == FEPIC_ALL_FP64) particle_phase_T<double>(c, dt, do_sort);
     else particle_phase_T<float>(c, dt, do_sort);
 }
 
@@ -609,11 +732,10 @@ int run_diagnostics(fepic_ctx* c, fepic_step_stats* st, bool have_step, bool hav
     return FEPIC_OK;
 }
 
-// Any other change of the particle slots (upload, injection, a Boris step and its sort, a
-// checkpoint load) leaves the Adams-Bashforth histories stale: the next AB step restarts
-// them from the current state (order 1 first).
+// A Boris step or a checkpoint load leaves the Adams-Bashforth histories stale: the next AB
+// step restarts every particle from its current state (order 1 first).
 void ab_history_stale(fepic_ctx* c) {
-    for (auto& s : c->species) s.ab_valid = false;
+    for (auto& s : c->species) s.ab_reset = true;
 }
 
 // Adams-Bashforth coefficients of orders 1..kAbMax: the integrals over s in [0, 1] of the
@@ -667,7 +789,6 @@ void ab_tables(AbParams& ap) {
 
 int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats* out, bool solve) {
     NEED_DEV(c);
-    ab_history_stale(c);
     if (!(dt > 0) || !std::isfinite(dt) || !std::isfinite(beta) || !std::isfinite(gamma))
         return fail(c, FEPIC_E_ARG, "bad step parameters");
     fepic_step_stats st;
@@ -727,6 +848,10 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
     }
     // commit
     for (auto& s : c->species) s.cur = 1 - s.cur;
+    if (c->opt.pusher == FEPIC_PUSHER_AB)
+        for (auto& s : c->species) s.abm_cur = 1 - s.abm_cur;
+    else
+        ab_history_stale(c);
     std::swap(c->d_dg, c->d_dgn);
     launch_axpby(c->stream, c->d_G, c->d_G, 1.0, c->d_dg, 1.0, c->mesh.n_edges);
     if (solve) {
@@ -897,6 +1022,8 @@ void fepic_default_options(fepic_options* o) {
     o->walk = FEPIC_WALK_AUTO;
     o->solve_precision = FEPIC_SOLVE_FP64;
     o->mixed_inner_tol = 1e-4;
+    o->pusher = FEPIC_PUSHER_BORIS;
+    o->ab_order = 4;
 }
 
 const char* fepic_error_string(int code) {
@@ -932,6 +1059,9 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
     if (o.solve_precision != FEPIC_SOLVE_FP64 && o.solve_precision != FEPIC_SOLVE_MIXED) return FEPIC_E_ARG;
     if (o.solve_precision == FEPIC_SOLVE_MIXED && o.preconditioner != FEPIC_PC_AUX) return FEPIC_E_ARG;
     if (!(o.mixed_inner_tol > 0.0 && o.mixed_inner_tol < 1.0)) return FEPIC_E_ARG;
+    if (o.pusher != FEPIC_PUSHER_BORIS && o.pusher != FEPIC_PUSHER_AB) return FEPIC_E_ARG;
+    if (o.ab_order < 1 || o.ab_order > kAbMax) return FEPIC_E_ARG;
+    if (o.pusher == FEPIC_PUSHER_AB && o.precision != FEPIC_ALL_FP64) return FEPIC_E_ARG;
     if (o.cg_check_every < 1) o.cg_check_every = 8;
     fepic_ctx* c = new fepic_ctx();
     c->opt = o;
@@ -1014,6 +1144,19 @@ int fepic_set_solve_precision(fepic_ctx* c, int sp) {
         for (int& n : c->last_pass_iters) n = 0;
     }
     c->opt.solve_precision = sp;
+    return FEPIC_OK;
+}
+
+int fepic_set_pusher(fepic_ctx* c, int pusher, int ab_order) {
+    if (!c) return FEPIC_E_ARG;
+    if (pusher != FEPIC_PUSHER_BORIS && pusher != FEPIC_PUSHER_AB)
+        return fail(c, FEPIC_E_ARG, "pusher must be FEPIC_PUSHER_BORIS or FEPIC_PUSHER_AB");
+    if (ab_order < 1 || ab_order > kAbMax) return fail(c, FEPIC_E_ARG, "ab_order must be 1..5");
+    if (pusher == FEPIC_PUSHER_AB && c->opt.precision != FEPIC_ALL_FP64)
+        return fail(c, FEPIC_E_ARG, "the Adams-Bashforth pusher needs the all-FP64 particle path");
+    if (pusher != c->opt.pusher) ab_history_stale(c);
+    c->opt.pusher = pusher;
+    c->opt.ab_order = ab_order;
     return FEPIC_OK;
 }
 
@@ -1276,6 +1419,7 @@ static int upload_located(fepic_ctx* c, Species& s, int64_t n, const int64_t* di
         launch_locate<float>(c->stream, n, dx, du, did, s.next_id, parr<float>(s, s.cur), s.n, c->d_grad64, c->d_r0,
                              c->d_cell_start, c->d_cell_tets, g, g + 3, c->d_grid_n, c->d_cnt);
     s.next_id += n;
+    s.ab_fill_from = std::min(s.ab_fill_from, s.n);
     s.n += n;
     if (c->opt.precision == FEPIC_ALL_FP64) sort_species<double>(c, s);
     else sort_species<float>(c, s);
@@ -1304,7 +1448,6 @@ static int check_upload(fepic_ctx* c, int species, int64_t n, const double* x, c
 int fepic_upload_particles(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
                            const double* u, int64_t* n_rejected) {
     NEED_DEV(c);
-    ab_history_stale(c);
     if (n_rejected) *n_rejected = 0;
     int rc = check_upload(c, species, n, x, u);
     if (rc || n == 0) return rc;
@@ -1332,7 +1475,6 @@ int fepic_upload_particles(fepic_ctx* c, int species, int64_t n, const int64_t* 
 int fepic_upload_particles_device(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
                                   const double* u, int64_t* n_rejected) {
     NEED_DEV(c);
-    ab_history_stale(c);
     if (n_rejected) *n_rejected = 0;
     int rc = check_upload(c, species, n, x, u);
     if (rc || n == 0) return rc;
@@ -1345,7 +1487,6 @@ static int inject_located(fepic_ctx* c, Species& s, int64_t n, const int64_t* di
 int fepic_inject_particles(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
                            const double* u) {
     NEED_DEV(c);
-    ab_history_stale(c);
     if (species < 0 || species >= (int)c->species.size() || n < 0 || (n > 0 && (!x || !u)))
         return fail(c, FEPIC_E_ARG, "bad injection arguments");
     if (n == 0) return FEPIC_OK;
@@ -1397,6 +1538,7 @@ static int inject_located(fepic_ctx* c, Species& s, int64_t n, const int64_t* di
         launch_locate<float>(c->stream, n, dx, du, did, s.next_id, parr<float>(s, s.cur), s.n, c->d_grad64, c->d_r0,
                              c->d_cell_start, c->d_cell_tets, g, g + 3, c->d_grid_n, c->d_cnt);
     s.next_id += n;
+    s.ab_fill_from = std::min(s.ab_fill_from, s.n);
     s.n += n;
     c->rho_valid = false;
     c->rG_levels = 0;
@@ -1406,7 +1548,6 @@ static int inject_located(fepic_ctx* c, Species& s, int64_t n, const int64_t* di
 int fepic_inject_particles_device(fepic_ctx* c, int species, int64_t n, const int64_t* id, const double* x,
                                   const double* u) {
     NEED_DEV(c);
-    ab_history_stale(c);
     if (species < 0 || species >= (int)c->species.size() || n < 0 || (n > 0 && (!x || !u)))
         return fail(c, FEPIC_E_ARG, "bad injection arguments");
     if (n == 0) return FEPIC_OK;
@@ -1494,74 +1635,6 @@ int fepic_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_st
 
 int fepic_push_particles(fepic_ctx* c, double dt, fepic_step_stats* out) { return do_step(c, dt, 0.25, 0.5, out, false); }
 
-int fepic_push_particles_ab(fepic_ctx* c, int species, double dt, int order, fepic_step_stats* out) {
-    NEED_DEV(c);
-    if (species < 0 || species >= (int)c->species.size() || order < 1 || order > kAbMax || !(dt > 0) ||
-        !std::isfinite(dt))
-        return FEPIC_E_ARG;
-    if (c->opt.precision != FEPIC_ALL_FP64)
-        return fail(c, FEPIC_E_STATE, "the Adams-Bashforth pusher needs the all-FP64 particle path");
-    int rc = sync_counts(c);
-    if (rc != FEPIC_OK) return rc;
-    Species& s = c->species[species];
-    if (s.abh_cap < s.n || !s.d_abh) {
-        double* h = dalloc<double>(c, std::max<int64_t>(s.n, 1) * kAbStride);
-        if (!h) return fail(c, FEPIC_E_OOM, "device allocation failed");
-        if (s.d_abh) dfree(c, s.d_abh);
-        s.d_abh = h;
-        s.abh_cap = std::max<int64_t>(s.n, 1);
-        s.ab_valid = false;
-    }
-    const TetBlock<double>* blk = (const TetBlock<double>*)c->d_blk;
-    launch_stage<double>(c->stream, c->mesh.n_tets, (TetBlock<double>*)c->d_blk, c->d_e, c->d_b, c->d_grad64,
-                         c->d_tet_edges, c->d_tet_faces);
-    if (!s.ab_valid) {
-        launch_ab_init(c->stream, parr<double>(s, s.cur), s.n, blk, c->d_r0, s.d_abh, s.abh_cap);
-        s.ab_valid = true;
-    }
-    launch_fill(c->stream, c->d_dgn, c->mesh.n_edges, 0.0);
-    AbParams ap;
-    ab_tables(ap);
-    ap.dt = dt;
-    ap.qm = s.q / s.m;
-    ap.qw = s.q * s.w;
-    ap.k = order;
-    ap.cap = c->opt.crossing_cap;
-    hipEvent_t* ev = timer_pair(c, FAM_PUSH);   // timed as the "push" family
-    if (ev) (void)hipEventRecord(ev[0], c->stream);
-    launch_push_ab(c->stream, parr<double>(s, s.cur), s.n, blk, c->d_r0, s.d_abh, s.abh_cap, c->d_dgn, ap,
-                   c->d_cnt_slots);
-    if (ev) (void)hipEventRecord(ev[1], c->stream);
-    launch_cnt_finish(c->stream, c->d_cnt_slots, c->d_cnt);
-    HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(PushCounters), hipMemcpyDeviceToHost, c->stream));
-    // the species' live count after the step (absorbed slots stay until the next sort)
-    double live = 0.0;
-    launch_fill(c->stream, c->d_live, 1, 0.0);
-    launch_count_live(c->stream, (const int32_t*)s.buf[s.cur][0], s.n, c->d_live);
-    HIPCHK(c, hipMemcpyAsync(&live, c->d_live, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    // commit the deposit as a particle-only step does: dG = this step's current, G += dG
-    std::swap(c->d_dg, c->d_dgn);
-    launch_axpby(c->stream, c->d_G, c->d_G, 1.0, c->d_dg, 1.0, c->mesh.n_edges);
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipGetLastError());
-    c->step_count++;
-    c->time += dt;
-    c->rho_valid = false;
-    fepic_step_stats st;
-    std::memset(&st, 0, sizeof(st));
-    st.gauss_drift_check_rel = st.cont_resid_rel = st.gauss_resid_rel = -1.0;
-    st.pc_far_levels = -1;
-    st.n_crossings = (int64_t)c->h_cnt->n_crossings;
-    st.n_absorbed = c->h_cnt->n_absorbed;
-    st.n_cap_exceeded = (int)c->h_cnt->n_cap;
-    st.n_particles = (int64_t)live;
-    st.step = c->step_count;
-    st.t = c->time;
-    if (out) *out = st;
-    if (st.n_cap_exceeded)
-        return fail(c, FEPIC_E_CROSSING_CAP, "a particle path exceeded the crossing cap; those particles were dropped");
-    return FEPIC_OK;
-}
 
 // Device edge vector -> caller's array in canonical edge order.
 static int edge_out(fepic_ctx* c, const double* d, double* out) {

@@ -9,6 +9,7 @@
 
 #include "fepic_internal.h"
 #include "host_mesh.h"
+#include <climits>
 
 namespace fepic {
 
@@ -34,11 +35,16 @@ struct Species {
     int idcur = 0;
     int32_t* d_nlive = nullptr;
     int32_t* h_nlive = nullptr;
-    // Adams-Bashforth history (fepic_push_particles_ab): kAbStride doubles per slot, valid
-    // while the slots hold the same particles
-    double* d_abh = nullptr;
+    // Adams-Bashforth pusher: history [kAbStride][abh_cap] (component-major) and per-slot
+    // AbMeta, each double-buffered.  The sorts move both (flipping abh_cur and abm_cur); a
+    // step writes its meta to the other buffer, flipped at the commit with cur.
+    double* d_abh[2] = {};
+    int32_t* d_abm[2] = {};
+    int abh_cur = 0, abm_cur = 0;
     int64_t abh_cap = 0;
-    bool ab_valid = false;
+    double ab_dt = 0.0;                // dt of the levels held
+    bool ab_reset = true;              // every slot restarts at order 1 at the next AB step
+    int64_t ab_fill_from = INT64_MAX;  // slots appended since: no history yet
     bool sorted_pending = false;  // d_nlive holds a count not yet read back
 };
 

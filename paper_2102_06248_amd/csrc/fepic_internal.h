@@ -73,12 +73,18 @@ struct PushParams {
 constexpr int kCntSlots = 256;
 
 // Adams-Bashforth pusher (all-FP64): orders 1..kAbMax, a history of kAbStride doubles per
-// particle slot (rings of 5 levels of r, v and a, the levels held, the rings' head), stored
-// component-major: component c of slot i at c * capacity + i.
+// particle slot (rings of kAbRing levels of r, v and a), stored component-major: component c
+// of slot i at c * capacity + i.  A step uses at most kAbMax levels of a ring and writes its
+// new level into the one left over, so the levels of the state before the step survive
+// until the step is committed.  Per slot an int32 AbMeta (double-buffered with the
+// particle state) holds the levels held and the rings' head, or -1 for a particle without
+// history (it starts at order 1 from its current state).
 constexpr int kAbMax = 5;
-constexpr int kAbStride = 48;
+constexpr int kAbRing = kAbMax + 1;
+constexpr int kAbStride = 9 * kAbRing;
 constexpr double kAbInsideEps = 1e-13;   // a point is in a tet when its smallest lambda >= -eps
-constexpr double kAbBisectTol = 1e-15;   // width of the final crossing bracket, in steps
+constexpr double kAbRootTol = 1e-15;     // width of the final crossing bracket, in steps
+__host__ __device__ constexpr int ab_meta(int held, int head) { return held | (head << 8); }
 struct AbParams {
     double dt, qm, qw;
     int k, cap;
@@ -204,9 +210,18 @@ void launch_locate(hipStream_t s, int64_t n, const double* x, const double* u, c
                    PArrays<T> out, int64_t out_off, const double* grad64, const double* r0, const int32_t* cell_start,
                    const int32_t* cell_tets, const double* grid_lo, const double* grid_inv_h, const int32_t* grid_n,
                    PushCounters* cnt);
+// The Adams-Bashforth history moved by a sort with the particles it belongs to (hin ==
+// nullptr: no history); both history buffers have `stride` slots per component.
+struct AbHistIo {
+    const double* hin = nullptr;
+    double* hout = nullptr;
+    int64_t stride = 0;
+    const int32_t* min = nullptr;
+    int32_t* mout = nullptr;
+};
 template <typename T>
 void launch_sort(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, int64_t n_tets, int32_t* count,
-                 int32_t* offset, int32_t* block_sums, int32_t* n_live_dev);
+                 int32_t* offset, int32_t* block_sums, int32_t* n_live_dev, AbHistIo ab = AbHistIo());
 template <typename T>
 void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, double qw, double* rho);
 void launch_magnetic(hipStream_t s, int64_t n_tets, const double* b, const double* grad64, const int32_t* tet_faces,
@@ -214,10 +229,13 @@ void launch_magnetic(hipStream_t s, int64_t n_tets, const double* b, const doubl
 template <typename T>
 void launch_kinetic(hipStream_t s, PArrays<T> p, int64_t n, double wmc2, double* out);
 void launch_count_live(hipStream_t s, const int32_t* tet, int64_t n, double* out);
-void launch_ab_init(hipStream_t s, PArrays<double> p, int64_t n, const TetBlock<double>* blk, const double* r0,
-                    double* hist, int64_t hstride);
-void launch_push_ab(hipStream_t s, PArrays<double> p, int64_t n, const TetBlock<double>* blk, const double* r0,
-                    double* hist, int64_t hstride, double* dg, const AbParams& ap, PushCounters* slots);
+// Adams-Bashforth pusher (kernels_ab.hip): state read from in, written to out, the new
+// history level into the free ring slot of hist, the new AbMeta into meta_out.
+void launch_push_ab(hipStream_t s, PArrays<double> in, PArrays<double> out, int64_t n,
+                    const TetBlock<double>* blk, const double* r0, double* hist, int64_t hstride,
+                    const int32_t* meta_in, int32_t* meta_out, double* dg, const AbParams& ap, PushCounters* slots,
+                    const int32_t* n_live);
+void launch_fill_i32(hipStream_t s, int32_t* x, int64_t n, int32_t v);
 
 // Field kernels (kernels_fields.hip).
 void launch_fill(hipStream_t s, double* x, int64_t n, double v);

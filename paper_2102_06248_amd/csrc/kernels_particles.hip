@@ -757,7 +757,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(int32_t* __restrict__ out, 
 // places, in lane order, reserved by one atomic; absorbed particles (t < 0) are dropped.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scatter(PArrays<T> in, PArrays<T> out, int64_t n,
-                                                     int32_t* __restrict__ offset) {
+                                                     int32_t* __restrict__ offset, AbHistIo ab) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int t = i < n ? in.tet[i] : -1;
@@ -777,6 +777,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PArrays<T> in, PArrays<T> ou
     out.u1[pos] = in.u1[i];
     out.u2[pos] = in.u2[i];
     out.id[pos] = in.id[i];
+    if (ab.hin) {   // the Adams-Bashforth history moves with its particle
+        ab.mout[pos] = ab.min[i];
+        for (int c = 0; c < kAbStride; ++c) ab.hout[c * ab.stride + pos] = ab.hin[c * ab.stride + i];
+    }
 }
 
 // ------------------------------------------------------------------------- charge
@@ -1007,7 +1011,7 @@ void launch_locate(hipStream_t s, int64_t n, const double* x, const double* u, c
 
 template <typename T>
 void launch_sort(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, int64_t n_tets, int32_t* count,
-                 int32_t* offset, int32_t* block_sums, int32_t* n_live_dev) {
+                 int32_t* offset, int32_t* block_sums, int32_t* n_live_dev, AbHistIo ab) {
     hipLaunchKernelGGL(k_zero_i32, dim3(grid_1d(n_tets, kBlock)), dim3(kBlock), 0, s, count, n_tets);
     if (n > 0)
         hipLaunchKernelGGL(k_hist, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, in.tet, n, count);
@@ -1017,7 +1021,7 @@ void launch_sort(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, int64_
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, block_sums, nb, n_live_dev);
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, s, offset, n_tets, block_sums);
     if (n > 0)
-        hipLaunchKernelGGL(k_scatter<T>, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, in, out, n, offset);
+        hipLaunchKernelGGL(k_scatter<T>, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, in, out, n, offset, ab);
 }
 
 template <typename T>
@@ -1035,7 +1039,7 @@ void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, dou
                                    PArrays<T>, int64_t, const double*, const double*, const int32_t*,            \
                                    const int32_t*, const double*, const double*, const int32_t*, PushCounters*); \
     template void launch_sort<T>(hipStream_t, PArrays<T>, PArrays<T>, int64_t, int64_t, int32_t*, int32_t*,      \
-                                 int32_t*, int32_t*);                                                            \
+                                 int32_t*, int32_t*, AbHistIo);                                                  \
     template void launch_rho<T>(hipStream_t, PArrays<T>, int64_t, const int32_t*, double, double*);               \
     template void launch_kinetic<T>(hipStream_t, PArrays<T>, int64_t, double, double*);
 

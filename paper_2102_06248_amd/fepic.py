@@ -15,13 +15,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfepic.so")
 
-ABI_VERSION = 4   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
+ABI_VERSION = 5   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
 FEPIC_OK = 0
 FEPIC_FP32_PUSH_FP64_ACC, FEPIC_ALL_FP64 = 0, 1
 FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP = 0, 1, 2, 3
 FEPIC_PC_JACOBI, FEPIC_PC_AUX = 0, 1
 FEPIC_WALK_AUTO, FEPIC_WALK_QUEUE, FEPIC_WALK_FUSED = 0, 1, 2
 FEPIC_SOLVE_FP64, FEPIC_SOLVE_MIXED = 0, 1
+FEPIC_PUSHER_BORIS, FEPIC_PUSHER_AB = 0, 1
 FEPIC_E_CG_NOT_CONVERGED = -6
 FEPIC_E_CROSSING_CAP = -7
 FEPIC_MLP_N_PARAMS = 4545
@@ -36,7 +37,8 @@ class fepic_options(ctypes.Structure):
                 ("cg_max_iters", ctypes.c_int), ("cg_check_every", ctypes.c_int), ("sort_period", ctypes.c_int),
                 ("crossing_cap", ctypes.c_int), ("warm_start", ctypes.c_int), ("diagnostics", ctypes.c_int),
                 ("timing", ctypes.c_int), ("preconditioner", ctypes.c_int), ("aux_far_levels", ctypes.c_int),
-                ("walk", ctypes.c_int), ("solve_precision", ctypes.c_int), ("mixed_inner_tol", ctypes.c_double)]
+                ("walk", ctypes.c_int), ("solve_precision", ctypes.c_int), ("mixed_inner_tol", ctypes.c_double),
+                ("pusher", ctypes.c_int), ("ab_order", ctypes.c_int)]
 
 
 class fepic_step_stats(ctypes.Structure):
@@ -102,7 +104,6 @@ _SIGS = {
     "fepic_get_particles": [_P, _INT, _I64, _PI64, _P, _P, _P, _P, _P],
     "fepic_step": [_P, _D, _D, _D, ctypes.POINTER(fepic_step_stats)],
     "fepic_push_particles": [_P, _D, ctypes.POINTER(fepic_step_stats)],
-    "fepic_push_particles_ab": [_P, _INT, _D, _INT, ctypes.POINTER(fepic_step_stats)],
     "fepic_get_fields": [_P, _P, _P, _P],
     "fepic_get_current": [_P, _P, _P],
     "fepic_get_rho": [_P, _P],
@@ -117,6 +118,7 @@ _SIGS = {
     "fepic_set_warm_start": [_P, _INT],
     "fepic_set_preconditioner": [_P, _INT],
     "fepic_set_solve_precision": [_P, _INT],
+    "fepic_set_pusher": [_P, _INT, _INT],
     "fepic_mlp_forward": [_P, _I64, _P, _P],
     "fepic_mlp_grad": [_P, _I64, _P, _P, _P, ctypes.POINTER(_D)],
     "fepic_mlp_grad_noalloc": [_P, _I64, _P, _P, _P, _P],
@@ -276,6 +278,13 @@ def fepic_get_matrix(ctx, which):
     return r, c, v
 
 
+def fepic_get_matrix_nnz(ctx, which):
+    """Stored entries of matrix `which` (0 = M, 1 = S) over interior edges."""
+    n = ctypes.c_int64()
+    _check(ctx, lib().fepic_get_matrix(ctx, which, 0, ctypes.byref(n), None, None, None))
+    return n.value
+
+
 def fepic_set_fields(ctx, e=None, e_prev=None, b=None):
     e = None if e is None else _arr(e, np.float64)
     e_prev = None if e_prev is None else _arr(e_prev, np.float64)
@@ -335,13 +344,16 @@ def fepic_num_particles(ctx, species):
     return n.value
 
 
-def fepic_get_particles(ctx, species):
+def fepic_get_particles(ctx, species, fields=("id", "x", "u", "tet", "lam")):
+    """Live particles of a species; only the named arrays are copied out (the others are
+    passed as NULL)."""
     cap = fepic_num_particles(ctx, species)
-    out = {"id": np.zeros(cap, np.int64), "x": np.zeros((cap, 3)), "u": np.zeros((cap, 3)),
-           "tet": np.zeros(cap, np.int32), "lam": np.zeros((cap, 4))}
+    shapes = {"id": ((cap,), np.int64), "x": ((cap, 3), np.float64), "u": ((cap, 3), np.float64),
+              "tet": ((cap,), np.int32), "lam": ((cap, 4), np.float64)}
+    out = {k: np.zeros(*shapes[k]) for k in fields}
     n = ctypes.c_int64()
-    _check(ctx, lib().fepic_get_particles(ctx, species, cap, ctypes.byref(n), _ptr(out["id"]), _ptr(out["x"]),
-                                          _ptr(out["u"]), _ptr(out["tet"]), _ptr(out["lam"])))
+    ptrs = [_ptr(out[k]) if k in out else None for k in ("id", "x", "u", "tet", "lam")]
+    _check(ctx, lib().fepic_get_particles(ctx, species, cap, ctypes.byref(n), *ptrs))
     return {k: v[:n.value] for k, v in out.items()}
 
 
@@ -357,12 +369,6 @@ def fepic_step(ctx, dt, beta=0.25, gamma=0.5, check=True):
 def fepic_push_particles(ctx, dt):
     st = fepic_step_stats()
     _check(ctx, lib().fepic_push_particles(ctx, dt, ctypes.byref(st)))
-    return st
-
-
-def fepic_push_particles_ab(ctx, species, dt, order):
-    st = fepic_step_stats()
-    _check(ctx, lib().fepic_push_particles_ab(ctx, int(species), float(dt), int(order), ctypes.byref(st)))
     return st
 
 
@@ -445,6 +451,10 @@ def fepic_set_preconditioner(ctx, pc):
 
 def fepic_set_solve_precision(ctx, solve_precision):
     _check(ctx, lib().fepic_set_solve_precision(ctx, int(solve_precision)))
+
+
+def fepic_set_pusher(ctx, pusher, ab_order=4):
+    _check(ctx, lib().fepic_set_pusher(ctx, int(pusher), int(ab_order)))
 
 
 def fepic_mlp_forward(ctx, X):

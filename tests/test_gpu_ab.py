@@ -1,18 +1,31 @@
-"""GPU parity of the Adams-Bashforth pusher (fepic_push_particles_ab) against the oracle's
-(oracle/ab.py): the same seeded particles in the same seeded fields, stepped with orders 1
-to 5 for enough steps that the history reaches the full order.  Every step compares every
-particle's position and velocity, the absorbed set, and the deposited current on every
-edge, and checks charge continuity D^T dG = rho^{n+1} - rho^n on the library's own state.
+"""GPU parity of the Adams-Bashforth pusher (the FEPIC_PUSHER_AB option) against the
+oracle's (oracle/ab.py).
+
+* Particle half (fepic_push_particles, fields frozen): electrons and protons in the same
+  seeded fields, orders 1 to 5, sorted by tet every step (the history moves with the
+  particles), with a change of dt part-way (every history restarts at order 1).  Every
+  step compares every particle's position and velocity, the absorbed set and the
+  deposited current on every edge with the oracle, and checks charge continuity
+  D^T dG = rho^{n+1} - rho^n on the library's own state to 1e-12 of q w (the pieces are
+  closed onto the faces they cross, so continuity holds to round-off).
+* Whole steps (fepic_step): the same pusher with the Newmark field solve between pushes,
+  against OracleSim(pusher="ab"): fields, particles, continuity and the Gauss-drift
+  identity every step.
+* Errors: the pusher needs the all-FP64 path, orders outside 1..5 are refused, and a path
+  beyond the crossing cap fails the step without committing anything.
 """
 import numpy as np
 import pytest
 
 from gpu_common import announce, divfree_fields, have_gpu, jittered_kuhn, require_lib
-from oracle import ab, fem
+from oracle import ab
 from oracle.constants import M_E, Q_E
 from oracle.pic import OracleSim
+from paper_2102_06248_amd import inputs
 
 pytestmark = pytest.mark.gpu
+
+M_P = inputs.PROTON_ELECTRON_MASS_RATIO * M_E
 
 
 @pytest.fixture(scope="module")
@@ -22,108 +35,140 @@ def F():
     return require_lib()
 
 
-def _oracle_steps(m, e, b, x, v, q, mass, w, dt, order, n_steps):
-    """Per particle: the oracle's AB step, curved walk and deposit; returns per step the
-    alive ids, their positions and velocities, and the current vector."""
-    n = len(x)
-    tet = m.locate(x)
-    r_hist = [[x[i].copy()] for i in range(n)]
-    v_hist = [[v[i].copy()] for i in range(n)]
-    a_hist = [[] for _ in range(n)]
-    alive = tet >= 0
-    out = []
-    for _ in range(n_steps):
-        g = np.zeros(m.n_edges)
-        for i in range(n):
-            if not alive[i]:
-                continue
-            t = int(tet[i])
-            lam = m.barycentric(t, r_hist[i][0])
-            E = fem.eval_E(m, e, t, lam)
-            B = fem.eval_B(m, b, t, lam)
-            vi = v_hist[i][0]
-            a_hist[i].insert(0, (q / mass) * (E + np.cross(vi, B)))
-            k = min(order, len(a_hist[i]))
-            r_new, v_new = ab.ab_step(r_hist[i], v_hist[i], a_hist[i], dt, order)
-            path = ab.step_path(r_new, r_hist[i][:k])
-            pieces, last = ab.walk_curved(m, t, path, n_gl=k + 1)
-            ab.deposit_curved(m, pieces, path, q * w, n_gl=k + 1, g=g)
-            if last < 0:
-                alive[i] = False
-                continue
-            tet[i] = last
-            r_hist[i] = [r_new] + r_hist[i][:ab_max() - 1]
-            v_hist[i] = [v_new] + v_hist[i][:ab_max() - 1]
-            a_hist[i] = a_hist[i][:ab_max() - 1]
-        ids = np.nonzero(alive)[0]
-        out.append((ids, np.array([r_hist[i][0] for i in ids]), np.array([v_hist[i][0] for i in ids]), g))
-    return out
-
-
-def ab_max():
-    return 5
+def _species(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.25, 0.75, size=(n, 3))
+    ve = rng.normal(0.0, 6e5, size=(n, 3))
+    vp = rng.normal(0.0, 6e5, size=(n, 3)) * 2.0       # protons: fast enough to cross cells
+    return [(-Q_E, M_E, 1e3, x, ve), (Q_E, M_P, 1e3, x.copy(), vp)]
 
 
 @pytest.mark.parametrize("order", [1, 2, 3, 4, 5])
 def test_ab_push_vs_oracle(F, order):
-    announce(f"Adams-Bashforth pusher, order {order}")
+    announce(f"Adams-Bashforth pusher, order {order}: two species, sort every step, dt change")
     xyz, tets, h = jittered_kuhn(5, seed=21)
     osim = OracleSim(xyz, tets)
     m = osim.mesh
     e, b = divfree_fields(osim, 2.0, 5e-7, [0.0, 0.0, 3e-5], seed=22)
-    n = 300
-    rng = np.random.default_rng(23)
-    x = rng.uniform(0.25, 0.75, size=(n, 3))
-    v = rng.normal(0.0, 6e5, size=(n, 3))
-    q, mass, w = -Q_E, M_E, 1e3
-    dt = 6e-8                                   # about a third of a cell per step, w dt = 0.3 rad
-    n_steps = order + 3
-    ref = _oracle_steps(m, e, b, x, v, q, mass, w, dt, order, n_steps)
+    n = 150
+    sp_in = _species(n, 23)
+    dts = [6e-8] * (order + 2) + [4e-8] * (order + 1)   # about a third of a cell per step
+    # oracle
+    o_state = []
+    for q, mass, w, x, v in sp_in:
+        tet = m.locate(x).astype(np.int64)
+        assert np.all(tet >= 0)
+        o_state.append(dict(q=q, m=mass, w=w, ids=np.arange(n), x=x.copy(), u=v.copy(), tet=tet,
+                            alive=np.ones(n, np.int8), hist=ab.Histories()))
     interior = ~m.boundary_node
-    with F.Simulation(xyz, tets, device=0, precision=F.FEPIC_ALL_FP64, sort_period=0) as L:
+    with F.Simulation(xyz, tets, device=0, precision=F.FEPIC_ALL_FP64, sort_period=1,
+                      pusher=F.FEPIC_PUSHER_AB, ab_order=order) as L:
         F.fepic_set_fields(L.ctx, e=e, e_prev=e, b=b)
-        sp = F.fepic_add_species(L.ctx, q, mass, w)
-        assert F.fepic_upload_particles(L.ctx, sp, x, v, ids=np.arange(n)) == 0
+        handles = []
+        for q, mass, w, x, v in sp_in:
+            s = F.fepic_add_species(L.ctx, q, mass, w)
+            assert F.fepic_upload_particles(L.ctx, s, x, v, ids=np.arange(n)) == 0
+            handles.append(s)
         _, G_prev = F.fepic_get_current(L.ctx)
         rho_prev = F.fepic_get_rho(L.ctx, m.n_nodes)
         total_cross = 0
-        for k, (ids, r_o, v_o, g_o) in enumerate(ref):
-            st = F.fepic_push_particles_ab(L.ctx, sp, dt, order)
+        for k, dt in enumerate(dts):
+            g_o = np.zeros(m.n_edges)
+            for o in o_state:
+                ab.push_species(m, o["ids"], o["x"], o["u"], o["tet"], o["alive"], o["q"], o["m"], o["w"], dt,
+                                order, e, b, g_o, o["hist"])
+            st = F.fepic_push_particles(L.ctx, dt)
             total_cross += st.n_crossings
-            gp = F.fepic_get_particles(L.ctx, sp)
-            gi = np.argsort(gp["id"])
-            assert np.array_equal(gp["id"][gi], ids), f"step {k}: absorbed sets differ"
-            assert np.abs(gp["x"][gi] - r_o).max() <= 1e-10, f"step {k}"
-            assert np.abs(gp["u"][gi] - v_o).max() <= 1e-10 * np.abs(v_o).max(), f"step {k}"
+            for s, o in zip(handles, o_state):
+                gp = F.fepic_get_particles(L.ctx, s)
+                gi = np.argsort(gp["id"])
+                alive = o["alive"].astype(bool)
+                assert np.array_equal(gp["id"][gi], o["ids"][alive]), f"step {k}: absorbed sets differ"
+                assert alive.sum() > 0
+                assert np.abs(gp["x"][gi] - o["x"][alive]).max() <= 1e-10, f"step {k}"
+                assert np.abs(gp["u"][gi] - o["u"][alive]).max() <= 1e-10 * np.abs(o["u"]).max(), f"step {k}"
             dG, G = F.fepic_get_current(L.ctx)
             assert np.abs(dG - g_o).max() <= 1e-10 * np.abs(g_o).max(), f"step {k}"
-            # continuity holds up to the walk's inside tolerance: a crossing point may sit up
-            # to 1e-13 (in barycentric terms) outside its face, where the two cells'
-            # barycentric coordinates differ by as much, once per crossing through a node
             rho = F.fepic_get_rho(L.ctx, m.n_nodes)
             cont = (rho - rho_prev) - osim.D.T @ (G - G_prev)
-            assert np.abs(cont[interior]).max() <= 1e-13 * 200 * abs(q * w), f"step {k}"
+            assert np.abs(cont[interior]).max() <= 1e-12 * 1e3 * Q_E, f"step {k}: continuity"
             rho_prev, G_prev = rho, G
         assert total_cross > n
-        print(f"\n[ab] order {order}: {n_steps} steps, {total_cross} crossings, {len(ref[-1][0])} of {n} left")
+        left = sum(int(o["alive"].sum()) for o in o_state)
+        print(f"\n[ab] order {order}: {len(dts)} steps, {total_cross} crossings, {left} of {2 * n} left")
 
 
-def test_ab_push_rejects_bad_calls(F):
-    """Order outside 1..5, a non-positive dt or an unknown species is FEPIC_E_ARG; the
-    pusher needs the all-FP64 particle path (FEPIC_E_STATE otherwise); nothing is pushed."""
-    announce("Adams-Bashforth pusher: argument and state errors")
+@pytest.mark.parametrize("order", [2, 4])
+def test_ab_full_step_vs_oracle(F, order):
+    """fepic_step with the Adams-Bashforth pusher: push, Newmark solve, Faraday, against the
+    oracle's whole step with the same pusher (Jacobi-PCG on both sides to 1e-10)."""
+    announce(f"Adams-Bashforth whole steps, order {order}")
+    xyz, tets, h = jittered_kuhn(4, seed=31)
+    dt, n_steps = 6e-8, order + 3
+    osim = OracleSim(xyz, tets, pusher="ab", ab_order=order)
+    sp_in = _species(120, 32)
+    for q, mass, w, x, v in sp_in:
+        s = osim.add_species(q, mass, w * 50)
+        osim.upload_particles(s, x, v, ids=np.arange(len(x)))
+    osim.set_uniform_B([0.0, 0.0, 3e-5])
+    osim.init_electrostatic(1e-14)
+    with F.Simulation(xyz, tets, device=0, precision=F.FEPIC_ALL_FP64, diagnostics=1, sort_period=1,
+                      preconditioner=F.FEPIC_PC_JACOBI, pusher=F.FEPIC_PUSHER_AB, ab_order=order) as L:
+        handles = []
+        for q, mass, w, x, v in sp_in:
+            s = F.fepic_add_species(L.ctx, q, mass, w * 50)
+            F.fepic_upload_particles(L.ctx, s, x, v, ids=np.arange(len(x)))
+            handles.append(s)
+        F.fepic_set_uniform_B(L.ctx, [0.0, 0.0, 3e-5])
+        F.fepic_init_electrostatic(L.ctx, 1e-14)
+        for k in range(n_steps):
+            so = osim.step(dt, 0.25, 0.5)
+            st = F.fepic_step(L.ctx, dt, 0.25, 0.5)
+            assert st.cont_resid_rel <= 1e-12, (k, st.cont_resid_rel)
+            assert so["cont_resid_rel"] <= 1e-12
+            if k >= 2:
+                assert st.gauss_drift_check_rel <= 1e-9, (k, st.gauss_drift_check_rel)
+            e, _, bf = F.fepic_get_fields(L.ctx)
+            assert np.linalg.norm(e - osim.e) <= 1e-6 * np.linalg.norm(osim.e), k
+            assert np.abs(bf - osim.b).max() <= 1e-6 * np.abs(osim.b).max(), k
+            for s, j in zip(handles, range(len(sp_in))):
+                gp = F.fepic_get_particles(L.ctx, s)
+                op_ = osim.particles(j)
+                gi, oi = np.argsort(gp["id"]), np.argsort(op_["id"])
+                assert np.array_equal(gp["id"][gi], op_["id"][oi]), k
+                assert np.abs(gp["x"][gi] - op_["x"][oi]).max() <= 1e-9, k
+        print(f"\n[ab step] order {order}: {n_steps} steps, cg {st.cg_iters} iters, continuity {st.cont_resid_rel:.1e}")
+
+
+def test_ab_rejects_bad_options_and_cap_commits_nothing(F):
+    announce("Adams-Bashforth pusher: option errors, crossing cap")
     xyz, tets, _ = jittered_kuhn(3, seed=5)
-    x = np.full((4, 3), 0.5) + 0.01 * np.arange(12).reshape(4, 3)
-    v = np.zeros((4, 3))
-    for precision, bad in [(F.FEPIC_ALL_FP64, [(0, 0, 1e-9), (0, 6, 1e-9), (0, 2, 0.0), (0, 2, -1e-9), (3, 2, 1e-9)]),
-                           (F.FEPIC_FP32_PUSH_FP64_ACC, [(0, 2, 1e-9)])]:
-        with F.Simulation(xyz, tets, device=0, precision=precision) as L:
-            sp = F.fepic_add_species(L.ctx, -1.0, 1.0, 1.0)
-            F.fepic_upload_particles(L.ctx, sp, x, v, ids=np.arange(4))
-            want = "FEPIC_E_ARG" if precision == F.FEPIC_ALL_FP64 else "FEPIC_E_STATE"
-            for species, order, dt in bad:
-                with pytest.raises(F.FepicError) as ei:
-                    F.fepic_push_particles_ab(L.ctx, species, dt, order)
-                assert F.ERROR_NAMES[ei.value.code] == want
-            gp = F.fepic_get_particles(L.ctx, sp)
-            assert np.allclose(np.sort(gp["x"], axis=0), np.sort(x, axis=0), atol=1e-12)
+    with pytest.raises(F.FepicError) as ei:
+        F.fepic_create(device=0, precision=F.FEPIC_FP32_PUSH_FP64_ACC, pusher=F.FEPIC_PUSHER_AB)
+    assert F.ERROR_NAMES[ei.value.code] == "FEPIC_E_ARG"
+    for bad in (0, 6):
+        with pytest.raises(F.FepicError):
+            F.fepic_create(device=0, precision=F.FEPIC_ALL_FP64, pusher=F.FEPIC_PUSHER_AB, ab_order=bad)
+    with F.Simulation(xyz, tets, device=0, precision=F.FEPIC_FP32_PUSH_FP64_ACC) as L:
+        with pytest.raises(F.FepicError):
+            F.fepic_set_pusher(L.ctx, F.FEPIC_PUSHER_AB, 3)
+    # a path crossing more faces than the cap allows: the step fails and commits nothing
+    with F.Simulation(xyz, tets, device=0, precision=F.FEPIC_ALL_FP64, crossing_cap=1,
+                      pusher=F.FEPIC_PUSHER_AB, ab_order=2) as L:
+        s = F.fepic_add_species(L.ctx, -1.0, 1.0, 1.0)
+        x = np.array([[0.1, 0.12, 0.13], [0.5, 0.52, 0.55]])
+        v = np.array([[0.8, 0.7, 0.75], [1e-3, 0.0, 0.0]])
+        F.fepic_upload_particles(L.ctx, s, x, v, ids=np.arange(2))
+        before = F.fepic_get_particles(L.ctx, s)
+        _, G0 = F.fepic_get_current(L.ctx)
+        with pytest.raises(F.FepicError) as ei:
+            F.fepic_push_particles(L.ctx, 1.0)
+        assert F.ERROR_NAMES[ei.value.code] == "FEPIC_E_CROSSING_CAP"
+        after = F.fepic_get_particles(L.ctx, s)
+        _, G1 = F.fepic_get_current(L.ctx)
+        for k in ("id", "x", "u", "tet"):
+            assert np.array_equal(before[k], after[k]), k
+        assert np.array_equal(G0, G1)
+        # the same particles at a step that fits the cap move as the oracle's
+        st = F.fepic_push_particles(L.ctx, 0.01)
+        assert st.n_cap_exceeded == 0

@@ -100,7 +100,10 @@ def test_bench_byte_model_and_profile_bookkeeping(tmp_path, monkeypatch):
     assert bench.profile_key("cg_iter", "aux", "mixed") == "cg_iter_mixed"
     assert bench.profile_key("cg_iter", "jacobi") == "cg_iter_jacobi"
     assert bench.profile_key("push", "aux", "mixed") == "push"
-    assert bench.algorithmic_bytes("push", geo, st) == 56 * 1000 + 224 * 340
+    # the particle step's per-unit bytes: 56 per particle (104 all-FP64), 284 per occupied
+    # tet, 164 per crossing
+    assert bench.algorithmic_bytes("push", geo, st) == 56 * 1000 + 284 * 40 + 164 * 300
+    assert bench.algorithmic_bytes("push", geo, st, precision=1) == 104 * 1000 + 284 * 40 + 164 * 300
     # counter summaries are used only while the kernel source is unchanged
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     (tmp_path / "profiles").mkdir()
@@ -109,12 +112,12 @@ def test_bench_byte_model_and_profile_bookkeeping(tmp_path, monkeypatch):
     (src_dir / "kernels_fields.hip").write_text("kernel v1")
     rec = {"source_sha1": bench.source_hash("cg_iter"), "hbm_bytes_per_launch": 123456}
     (tmp_path / "profiles" / "cg_iter_c2_beam_counters.json").write_text(json.dumps(rec))
-    assert bench.traffic_from_profile("cg_iter", "c2_beam", 0) == 123456
-    assert bench.traffic_from_profile("cg_iter", "c2_beam", 0, "jacobi") is None   # its own summary
-    assert bench.traffic_from_profile("cg_iter", "c2_beam", 0, "aux", "mixed") is None
+    assert bench.traffic_from_profile("cg_iter", "c2_beam") == 123456
+    assert bench.traffic_from_profile("cg_iter", "c2_beam", "jacobi") is None   # its own summary
+    assert bench.traffic_from_profile("cg_iter", "c2_beam", "aux", "mixed") is None
     (src_dir / "kernels_fields.hip").write_text("kernel v2")
-    assert bench.traffic_from_profile("cg_iter", "c2_beam", 0) is None
-    assert bench.traffic_from_profile("cg_iter", "c3_plasma", 0) is None
+    assert bench.traffic_from_profile("cg_iter", "c2_beam") is None
+    assert bench.traffic_from_profile("cg_iter", "c3_plasma") is None
 
 
 def test_solve_precision_options(F):

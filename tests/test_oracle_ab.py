@@ -108,8 +108,9 @@ def test_straight_path_matches_the_closed_form(mesh):
     assert len(pieces) > 3 and last >= 0
     g = ab.deposit_curved(mesh, pieces, path, 1.0, n_gl=2)
     want = np.zeros(mesh.n_edges)
-    for t, sa, sb in pieces:
-        ls, le = mesh.barycentric(t, path(sa)), mesh.barycentric(t, path(sb))
+    for t, sa, sb, p_in, p_out in pieces:
+        ls = mesh.barycentric(t, path(sa)) if p_in is None else p_in
+        le = mesh.barycentric(t, path(sb)) if p_out is None else p_out
         ea, eb = LOCAL_EDGES[:, 0], LOCAL_EDGES[:, 1]
         want[mesh.tet_edges[t]] += ls[ea] * le[eb] - le[ea] * ls[eb]
     assert np.allclose(g, want, rtol=0, atol=1e-13)
@@ -131,30 +132,63 @@ def test_curved_walk_chains_cells_and_conserves_charge(mesh, seed):
     assert tet >= 0
     pieces, last = ab.walk_curved(mesh, tet, path, n_gl=5)
     assert last >= 0 and len(pieces) >= 4
-    for (t0, _, s), (t1, s1, _) in zip(pieces[:-1], pieces[1:]):
+    for (t0, _, s, _, p_out), (t1, s1, _, p_in, _) in zip(pieces[:-1], pieces[1:]):
         assert s == s1 and t1 in mesh.nbr[t0]
         assert abs(mesh.barycentric(t0, path(s)).min()) < 1e-12
+        # the closing face point: on the face, near r(s), the same point in both cells
+        k = int(np.argmin(p_out))
+        assert p_out[k] == 0.0 and abs(p_out.sum() - 1.0) < 1e-15
+        assert np.abs(p_out - mesh.barycentric(t0, path(s))).max() < 1e-12
+        x_out = p_out @ mesh.xyz[mesh.tets[t0]]
+        assert np.abs(p_in @ mesh.xyz[mesh.tets[t1]] - x_out).max() < 1e-15
+        assert sorted(p_in) == sorted(p_out)
     qw = -3.0
     g = ab.deposit_curved(mesh, pieces, path, qw, n_gl=5)
-    # adaptive quadrature of the same integrand on each piece
-    for t, sa, sb in pieces[:3]:
+    # adaptive quadrature of the same integrand on each piece's curved part
+    for piece in pieces[:3]:
+        t, sa, sb = piece[:3]
         grad = mesh.grad_lambda[t]
         ea, eb = LOCAL_EDGES[:, 0], LOCAL_EDGES[:, 1]
         def f(s, c):
             lam = mesh.barycentric(t, path(s))
             dl = grad @ path.deriv(s)
             return lam[ea[c]] * dl[eb[c]] - lam[eb[c]] * dl[ea[c]]
-        one = ab.deposit_curved(mesh, [(t, sa, sb)], path, 1.0, n_gl=5)
+        one = ab.piece_integral(mesh, piece, path, n_gl=5)
         for c in range(6):
             ref = integrate.quad(f, sa, sb, args=(c,), epsabs=1e-15, epsrel=1e-13)[0]
-            assert abs(one[mesh.tet_edges[t, c]] - ref) <= 1e-12
+            assert abs(one[c] - ref) <= 1e-12
     # charge continuity: D^T g against the change of the nodal charge
     DTg = mesh.D().T @ g
     rho0 = np.zeros(mesh.n_nodes)
     rho1 = np.zeros(mesh.n_nodes)
     np.add.at(rho0, mesh.tets[tet], qw * mesh.barycentric(tet, path(0.0)))
     np.add.at(rho1, mesh.tets[last], qw * mesh.barycentric(last, path(1.0)))
-    assert np.abs(DTg - (rho1 - rho0)).max() <= 1e-12 * abs(qw)
+    assert np.abs(DTg - (rho1 - rho0)).max() <= 1e-14 * abs(qw)
     # a wrong quadrature order (too few points) breaks the exactness of the deposit
     g2 = ab.deposit_curved(mesh, pieces, path, qw, n_gl=2)
     assert np.abs(g2 - g).max() > 1e-6 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("tol", [1e-15, 1e-7])
+def test_face_closures_make_continuity_exact_for_any_crossing_tolerance(mesh, tol):
+    """With the crossings located only to tol, the closed pieces still give D^T g = q w
+    (lambda(end) - lambda(start)) to round-off; without the closures (the curved parts
+    alone) the residual is of the size of the crossing error."""
+    qw = 2.5
+    D = mesh.D()
+    for seed in (5, 6, 7, 8):
+        path = _curved_path(seed)
+        tet = int(mesh.locate(path(0.0)[None])[0])
+        pieces, last = ab.walk_curved(mesh, tet, path, n_gl=5, tol=tol)
+        if last < 0:
+            continue
+        rho = np.zeros(mesh.n_nodes)
+        np.add.at(rho, mesh.tets[last], qw * mesh.barycentric(last, path(1.0)))
+        np.add.at(rho, mesh.tets[tet], -qw * mesh.barycentric(tet, path(0.0)))
+        g = ab.deposit_curved(mesh, pieces, path, qw, n_gl=5)
+        assert np.abs(D.T @ g - rho).max() <= 1e-14 * abs(qw)
+        bare = np.zeros(mesh.n_edges)
+        for piece in pieces:
+            bare[mesh.tet_edges[piece[0]]] += qw * ab.piece_integral(mesh, piece, path, n_gl=5)
+        if tol > 1e-10 and len(pieces) > 1:
+            assert np.abs(D.T @ bare - rho).max() > 1e-12 * abs(qw)
