@@ -292,6 +292,12 @@ int fepic_get_fields(fepic_ctx* ctx, double* e, double* e_prev, double* b);
 int fepic_get_current(fepic_ctx* ctx, double* dG, double* G);
 /* rho: [n_nodes] nodal charge sum_p q w lambda_k(x_p) of the live particles. */
 int fepic_get_rho(fepic_ctx* ctx, double* rho);
+/* on != 0: each later Newmark solve keeps a copy of its start vector x0 (after the warm
+ * start: e^n, an extrapolation, or the learned prediction with its line step), for
+ * inspection; fepic_get_warm_start copies the last one out ([n_edges], canonical order;
+ * FEPIC_E_STATE before any). */
+int fepic_keep_warm_start(fepic_ctx* ctx, int on);
+int fepic_get_warm_start(fepic_ctx* ctx, double* x0);
 /* Recomputes the residuals of fepic_step_stats for the current state on demand. */
 int fepic_diagnostics(fepic_ctx* ctx, fepic_step_stats* out);
 
@@ -340,6 +346,12 @@ int fepic_set_warm_start(fepic_ctx* ctx, int mode);
  * error against t [n] -> grad [4545] and *loss, computed by the device kernels. */
 int fepic_mlp_forward(fepic_ctx* ctx, int64_t n, const float* X, float* y);
 int fepic_mlp_grad(fepic_ctx* ctx, int64_t n, const float* X, const float* t, float* grad, double* loss);
+
+/* One Adam update (Kingma and Ba) of the network's FP32 master weights with the given
+ * gradient grad [4545] (host), by the device kernel training uses; the moment estimates
+ * and step counter are the context's (they restart with fepic_ws_set_weights).  A test
+ * entry: training feeds the kernel minibatch gradients itself. */
+int fepic_mlp_adam_step(fepic_ctx* ctx, const float* grad, double lr, double beta1, double beta2, double eps);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * training or serving loops, harnesses that forbid hipMalloc): fepic_mlp_grad on device

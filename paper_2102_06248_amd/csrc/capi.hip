@@ -486,6 +486,14 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
         int rc = mlp_record_features(c);
         if (rc != FEPIC_OK) return rc;
     }
+    if (c->keep_start && !c->d_x0keep && !(c->d_x0keep = dalloc<double>(c, ne)))
+        return fail(c, FEPIC_E_OOM, "allocation failed");
+    // the start the solve uses (after the learned start's guard), kept on request
+    auto keep_x0 = [&]() -> int {
+        if (c->keep_start)
+            HIPCHK(c, hipMemcpyAsync(c->d_x0keep, c->d_x, sizeof(double) * ne, hipMemcpyDeviceToDevice, c->stream));
+        return FEPIC_OK;
+    };
     ev_mark(c, 6);
     CgVec* const V[2] = {c->d_cgv[0], c->d_cgv[1]};
     double2* const ZP[2] = {c->d_zp[0], c->d_zp[1]};
@@ -579,6 +587,7 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
                     continue;
                 }
                 rr0_first = h.rr_true;
+                if ((rc = keep_x0()) != FEPIC_OK) return rc;
             }
             if (!(h.rr_true > tol2) || !std::isfinite(h.rr_true) || pass >= kMaxPasses || total >= maxit) break;
             // the pass ends when its own residual has fallen by mixed_inner_tol, or below half
@@ -613,6 +622,10 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
                     launch_warm(c->stream, FEPIC_WS_PREV, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
                     cg_init();
                 }
+            }
+            if (restart == 0) {
+                const int rk = keep_x0();
+                if (rk != FEPIC_OK) return rk;
             }
             const int first = (restart == 0 && c->last_cg_iters > 0) ? std::max(batch, c->last_cg_iters + 2) : batch;
             int rc = iterate(first, [&](int i) {
@@ -1653,6 +1666,20 @@ int fepic_get_fields(fepic_ctx* c, double* e, double* e_prev, double* b) {
     if (e_prev && (rc = edge_out(c, c->d_ep, e_prev))) return rc;
     if (b) HIPCHK(c, hipMemcpy(b, c->d_b, 8 * c->mesh.n_faces, hipMemcpyDeviceToHost));
     return FEPIC_OK;
+}
+
+int fepic_keep_warm_start(fepic_ctx* c, int on) {
+    NEED_DEV(c);
+    c->keep_start = on != 0;
+    return FEPIC_OK;
+}
+
+int fepic_get_warm_start(fepic_ctx* c, double* x0) {
+    NEED_DEV(c);
+    if (!x0) return fail(c, FEPIC_E_ARG, "null output");
+    if (!c->d_x0keep) return fail(c, FEPIC_E_STATE, "no start kept (fepic_keep_warm_start, then a step)");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return edge_out(c, c->d_x0keep, x0);
 }
 
 int fepic_get_current(fepic_ctx* c, double* dG, double* G) {

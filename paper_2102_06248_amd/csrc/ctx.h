@@ -142,6 +142,9 @@ struct fepic_ctx {
     int cg_restarts = 0;
     bool recording = false;
     int64_t mlp_fallbacks = 0;
+    // copy of the last Newmark solve's start vector (fepic_keep_warm_start)
+    bool keep_start = false;
+    double* d_x0keep = nullptr;
 };
 
 #define HIPCHK_RET(c, expr)                                          \

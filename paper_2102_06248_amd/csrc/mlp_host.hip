@@ -325,7 +325,9 @@ int fepic_ws_train(fepic_ctx* c, const fepic_train_opts* o, fepic_train_stats* o
             s->adam_t++;
             const uint64_t seed = o->seed * 0x9E3779B97F4A7C15ull + (uint64_t)s->adam_t * 0xBF58476D1CE4E5B9ull;
             mlp_launch_grad(c->stream, Xtr, Ttr, batch, n_tr, seed, s->P, s->part, s->loss_part, blocks);
-            const float bc1 = 1.f - std::pow(b1, (float)s->adam_t), bc2 = 1.f - std::pow(b2, (float)s->adam_t);
+            // bias corrections in FP64: 1 - b^t cancels badly in FP32 for b near 1
+            const float bc1 = (float)(1.0 - std::pow((double)b1, (double)s->adam_t)),
+                        bc2 = (float)(1.0 - std::pow((double)b2, (double)s->adam_t));
             mlp_launch_reduce_adam(c->stream, s->part, blocks, nullptr, s->P, s->m, s->v, 1, (float)o->lr, b1, b2, eps,
                                    bc1, bc2);
             ++steps;
@@ -392,6 +394,25 @@ int fepic_mlp_forward(fepic_ctx* c, int64_t n, const float* X, float* y) {
     HIPCHK_RET(c, hipStreamSynchronize(c->stream));
     HIPCHK_RET(c, hipMemcpy(y, dy, sizeof(float) * n, hipMemcpyDeviceToHost));
     dfree(c, dy);
+    return FEPIC_OK;
+}
+
+int fepic_mlp_adam_step(fepic_ctx* c, const float* grad, double lr, double beta1, double beta2, double eps) {
+    if (!c || !grad || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return c ? fail(c, FEPIC_E_ARG, "fepic_mlp_adam_step: bad arguments") : FEPIC_E_ARG;
+    int rc = ensure_mlp(c);
+    if (rc) return rc;
+    MlpState* s = c->mlp;
+    if (!s->have_weights) return fail(c, FEPIC_E_STATE, "no weights");
+    // the gradient as the single "partial sum" of the reduce-and-update kernel training uses
+    HIPCHK_RET(c, hipMemcpyAsync(s->part, grad, sizeof(float) * kNP, hipMemcpyHostToDevice, c->stream));
+    s->adam_t++;
+    const float b1 = (float)beta1, b2 = (float)beta2;
+    const float bc1 = (float)(1.0 - std::pow((double)b1, (double)s->adam_t)),
+                bc2 = (float)(1.0 - std::pow((double)b2, (double)s->adam_t));
+    mlp_launch_reduce_adam(c->stream, s->part, 1, nullptr, s->P, s->m, s->v, 1, (float)lr, b1, b2, (float)eps, bc1,
+                           bc2);
+    HIPCHK_RET(c, hipStreamSynchronize(c->stream));
     return FEPIC_OK;
 }
 

@@ -122,6 +122,9 @@ _SIGS = {
     "fepic_mlp_forward": [_P, _I64, _P, _P],
     "fepic_mlp_grad": [_P, _I64, _P, _P, _P, ctypes.POINTER(_D)],
     "fepic_mlp_grad_noalloc": [_P, _I64, _P, _P, _P, _P],
+    "fepic_mlp_adam_step": [_P, _P, _D, _D, _D, _D],
+    "fepic_keep_warm_start": [_P, _INT],
+    "fepic_get_warm_start": [_P, _P],
     "fepic_save": [_P, ctypes.c_char_p],
     "fepic_load": [_P, ctypes.c_char_p],
 }
@@ -393,6 +396,22 @@ def fepic_get_rho(ctx, n_nodes):
     rho = np.zeros(n_nodes)
     _check(ctx, lib().fepic_get_rho(ctx, _ptr(rho)))
     return rho
+
+
+def fepic_keep_warm_start(ctx, on=True):
+    _check(ctx, lib().fepic_keep_warm_start(ctx, int(bool(on))))
+
+
+def fepic_get_warm_start(ctx):
+    x0 = np.zeros(fepic_get_topology_sizes(ctx)["n_edges"])
+    _check(ctx, lib().fepic_get_warm_start(ctx, _ptr(x0)))
+    return x0
+
+
+def fepic_mlp_adam_step(ctx, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    g = _arr(grad, np.float32)
+    assert len(g) == FEPIC_MLP_N_PARAMS
+    _check(ctx, lib().fepic_mlp_adam_step(ctx, _ptr(g), lr, beta1, beta2, eps))
 
 
 def fepic_diagnostics(ctx):

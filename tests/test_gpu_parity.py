@@ -75,10 +75,30 @@ def test_particle_step_vs_oracle(F, precision, n, walk):
     assert st.n_crossings == pytest.approx(ost["n_crossings"], rel=0.01, abs=3)
     assert st.n_absorbed == pytest.approx(ost["n_absorbed"], abs=max(1, n // 2000))
     dg_orc = osim.dG
-    scale = np.abs(dg_orc).max()
     dtol = 1e-10 if precision == 1 else 1e-5
-    if nodd == 0:
-        assert np.max(np.abs(dg_gpu - dg_orc)) <= dtol * scale
+    if nodd:
+        # a few particles were absorbed on one side only (FP32 rounding at a wall): push the
+        # particles both sides agree on again, on both sides, and compare their current
+        alive_g = set(gp["id"].tolist())
+        alive_o = set(op["id"].tolist())
+        keep = np.array(sorted(set(range(n)) - (alive_g ^ alive_o)))
+        osim = OracleSim(xyz, tets)
+        s = osim.add_species(-Q_E, M_E, 1e3)
+        osim.upload_particles(s, x[keep], u[keep], ids=keep)
+        osim.e, osim.b = e.copy(), b.copy()
+        osim.step(dt, solve=False)
+        dg_orc = osim.dG
+        with _lib_sim(F, xyz, tets, precision=precision, walk=mode) as L:
+            F.fepic_set_fields(L.ctx, e=e, e_prev=e, b=b)
+            sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 1e3)
+            F.fepic_upload_particles(L.ctx, sp, x[keep], u[keep], ids=keep)
+            F.fepic_push_particles(L.ctx, dt)
+            dg_gpu, _ = F.fepic_get_current(L.ctx)
+            gp2 = F.fepic_get_particles(L.ctx, sp)
+        _, nodd2 = compare_particles(gp2, osim.particles(s), h, *tol)
+        assert nodd2 == 0
+    scale = np.abs(dg_orc).max()
+    assert np.max(np.abs(dg_gpu - dg_orc)) <= dtol * scale
     # particles come back sorted by tet (the sort runs at upload)
     assert np.all(np.diff(g0["tet"]) >= 0)
 
@@ -123,15 +143,13 @@ def test_c1_single_electron_2000_steps_fp64(F):
     rL = gam * M_E * v0 / (Q_E * B0)
     c = np.full(3, 5 / 12)
     x0, u0 = [c + [rL, 0, 0]], [[0, gam * v0, 0]]
-    # Both solves stop at 1e-13: the library's preconditioner differs from the oracle's
-    # Jacobi, so each step's solution differs within the stopping tolerance, and over 2000
-    # steps a 1e-10 tolerance adds up to a few 1e-6 of this small field.
-    osim = OracleSim(xyz, tets, cg_tol=1e-13)
+    # Like for like with the oracle: Jacobi-PCG to ||r|| <= 1e-10 ||b|| on both sides.
+    osim = OracleSim(xyz, tets, cg_tol=1e-10)
     osim.set_uniform_B([0, 0, B0])
     s = osim.add_species(-Q_E, M_E, 1.0)
     osim.upload_particles(s, x0, u0)
     osim.init_electrostatic()
-    with _lib_sim(F, xyz, tets, precision=1, diagnostics=1, cg_tol=1e-13) as L:
+    with _lib_sim(F, xyz, tets, precision=1, diagnostics=1, cg_tol=1e-10, preconditioner=F.FEPIC_PC_JACOBI) as L:
         F.fepic_set_uniform_B(L.ctx, [0, 0, B0])
         sp = F.fepic_add_species(L.ctx, -Q_E, M_E, 1.0)
         F.fepic_upload_particles(L.ctx, sp, x0, u0)
@@ -139,11 +157,12 @@ def test_c1_single_electron_2000_steps_fp64(F):
         e0, _, _ = F.fepic_get_fields(L.ctx)
         assert np.allclose(e0, osim.e, rtol=0, atol=1e-9 * np.abs(osim.e).max())
         worst = 0.0
-        cont, drift, ncross = 0.0, 0.0, 0
+        cont, drift, ncross, it_diff = 0.0, 0.0, 0, 0
         for n in range(2000):
             st = F.fepic_step(L.ctx, dt, 0.25, 0.5)
             ost = osim.step(dt, 0.25, 0.5)
             ncross += st.n_crossings
+            it_diff = max(it_diff, abs(st.cg_iters - ost["cg_iters"]))
             cont = max(cont, st.cont_resid_rel)
             if st.gauss_drift_check_rel >= 0:
                 drift = max(drift, st.gauss_drift_check_rel)
@@ -153,6 +172,7 @@ def test_c1_single_electron_2000_steps_fp64(F):
         e, _, b = F.fepic_get_fields(L.ctx)
     assert worst < 1e-7
     assert ncross > 200
+    assert it_diff <= 1        # the same Jacobi-PCG on both sides: the same iteration counts
     assert cont < 1e-12
     assert drift < 1e-12
     assert np.linalg.norm(e - osim.e) <= 1e-6 * np.linalg.norm(osim.e)
