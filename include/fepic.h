@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define FEPIC_ABI_VERSION 5
+#define FEPIC_ABI_VERSION 6
 
 enum {
     FEPIC_OK = 0,
@@ -170,6 +170,7 @@ typedef struct {
     int cg_passes;                /* FP64 residual passes of a FEPIC_SOLVE_MIXED solve     */
                                   /* (cg_iters counts the FP32 iterations of all of them); */
                                   /* 0 for an FP64 solve                                  */
+    int64_t n_injected;           /* particles the injectors added in this step            */
 } fepic_step_stats;
 
 /* ---------------------------------------------------------------- lifecycle */
@@ -238,6 +239,31 @@ int fepic_init_electrostatic(fepic_ctx* ctx, double tol, int* iters);
  * A species has charge q (C), mass m (kg) and macro-particle weight w (physical particles
  * per macro-particle, Sec. II-A point shapes). */
 int fepic_add_species(fepic_ctx* ctx, double q, double m, double w, int* species_out);
+/* Seeded disk source of a species (a beam entering through a wall, Sec. IV-B): every later
+ * step (fepic_step, fepic_push_particles) first adds per_step particles drawn on the
+ * device, uniformly on the disk of the given radius around center in the plane normal to
+ * normal (a wall of the mesh, for the particles to start inside it), with velocity
+ * v = v0 n + sigma (N1, N2, N3): drift v0 from kinetic_eV (relativistic), N standard
+ * normals per Cartesian component, sigma = sqrt(thermal_eV e / m); u is stored as gamma v
+ * (Boris) or v (Adams-Bashforth).  Draws come from the counter-based generator
+ * Philox4x32-10 (Salmon et al., SC 2011): particle j of the k-th injection of species s
+ * uses the blocks of counter (j, k mod 2^32, k div 2^32, 4 s + b), b = 0..2, under the key
+ * (seed mod 2^32, seed div 2^32); the twelve words give six uniforms
+ * ((w_2i >> 5) 2^26 + (w_2i+1 >> 6) + 1/2) 2^-53: radius R sqrt(u0), angle 2 pi u1,
+ * Box-Muller normals from (u2, u3) and (u4, u5); the plane's basis is e1 = unit(n x a),
+ * e2 = n x e1, a = the x axis unless |n_x| >= 0.9, then the y axis.  The particles are
+ * located after the step's sort and pushed with the others a full step; ids continue the
+ * species' default ids.  A step that fails commits none of them and does not count the
+ * injection (k advances only with committed steps).  spec == NULL switches the source off;
+ * setting one restarts k at 0.  FEPIC_E_ARG for a bad species or non-finite, negative or
+ * degenerate parameters. */
+typedef struct {
+    double center[3], normal[3], radius;   /* m                                       */
+    double kinetic_eV, thermal_eV;         /* drift energy along normal, temperature  */
+    int64_t per_step;                      /* particles per step (< 2^30)             */
+    uint64_t seed;
+} fepic_injector;
+int fepic_set_injector(fepic_ctx* ctx, int species, const fepic_injector* spec);
 /* Appends n particles: id [n] (caller-chosen, kept through sorting; NULL = running
  * index), x [n][3] Cartesian positions at t_n, u [n][3] = gamma v at t_{n-1/2} (m/s).
  * Each is located in its tet on the device; points outside the mesh or with non-finite

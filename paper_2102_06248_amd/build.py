@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfepic.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["host_mesh.cpp", "kernels_particles.hip", "kernels_fields.hip", "kernels_mlp.hip", "kernels_ab.hip",
+SOURCES = ["host_mesh.cpp", "kernels_particles.hip", "kernels_fields.hip", "kernels_mlp.hip", "kernels_ab.hip", "kernels_inject.hip",
            "capi.hip", "mlp_host.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -121,6 +121,21 @@ PArrays<T> parr(Species& s, int which) {
     return p;
 }
 
+// The arrays of parr() from slot `off` on.
+template <typename T>
+PArrays<T> parr_off(Species& s, int which, int64_t off) {
+    PArrays<T> p = parr<T>(s, which);
+    p.tet += off;
+    p.l1 += off;
+    p.l2 += off;
+    p.l3 += off;
+    p.u0 += off;
+    p.u1 += off;
+    p.u2 += off;
+    p.id += off;
+    return p;
+}
+
 size_t field_size(const fepic_ctx* c) { return c->opt.precision == FEPIC_ALL_FP64 ? 8 : 4; }
 
 size_t array_bytes(const fepic_ctx* c, int a, int64_t n) {
@@ -298,12 +313,78 @@ CrossQueue<T> cqueue(fepic_ctx* c) {
     return q;
 }
 
+// The injectors' particles of this step, drawn on the device and appended after the sort
+// (the push moves them with the rest, their charge joins rho^n when diagnostics run);
+// inject_undo drops them again when the step is not committed.
+template <typename T>
+int inject_phase(fepic_ctx* c) {
+    bool any = false;
+    for (const auto& s : c->species) any = any || (s.inj_on && s.inj.per_step > 0);
+    if (!any) return FEPIC_OK;
+    int rc = sync_counts(c);
+    if (rc != FEPIC_OK) return rc;
+    for (auto& s : c->species) {
+        s.inj_undo_n = -1;
+        if (!s.inj_on || s.inj.per_step <= 0) continue;
+        const int64_t m = s.inj.per_step;
+        if (s.n + m >= ((int64_t)1 << 31)) return fail(c, FEPIC_E_ARG, "too many particles for one species");
+        if ((rc = ensure_capacity(c, s, s.n + m)) != FEPIC_OK) return rc;
+        if (c->inj_cap < m) {
+            dfree(c, c->d_inj);
+            c->d_inj = dalloc<double>(c, 6 * m);
+            if (!c->d_inj) return fail(c, FEPIC_E_OOM, "injection staging allocation failed");
+            c->inj_cap = m;
+        }
+        InjectorSpec sp = s.inj;
+        sp.relativistic_u = c->opt.pusher == FEPIC_PUSHER_AB ? 0 : 1;
+        launch_inject_disk(c->stream, sp, s.inj_k, c->d_inj, c->d_inj + 3 * m);
+        const double* g = c->d_grid;
+        launch_locate<T>(c->stream, m, c->d_inj, c->d_inj + 3 * m, nullptr, s.next_id, parr<T>(s, s.cur), s.n,
+                         c->d_grad64, c->d_r0, c->d_cell_start, c->d_cell_tets, g, g + 3, c->d_grid_n, c->d_cnt);
+        if (c->opt.diagnostics && c->rho_valid)
+            launch_rho<T>(c->stream, parr_off<T>(s, s.cur, s.n), m, c->d_tets, s.q * s.w, c->d_rho);
+        s.inj_undo_n = s.n;
+        s.ab_fill_from = std::min(s.ab_fill_from, s.n);
+        s.next_id += m;
+        s.n += m;
+    }
+    return FEPIC_OK;
+}
+
+void inject_undo(fepic_ctx* c) {
+    for (auto& s : c->species)
+        if (s.inj_undo_n >= 0) {
+            s.n = s.inj_undo_n;
+            s.next_id -= s.inj.per_step;
+            s.inj_undo_n = -1;
+            c->rho_valid = false;
+        }
+}
+
+int64_t inject_commit(fepic_ctx* c) {
+    int64_t n = 0;
+    for (auto& s : c->species)
+        if (s.inj_undo_n >= 0) {
+            n += s.inj.per_step;
+            s.inj_k++;
+            s.inj_undo_n = -1;
+        }
+    return n;
+}
+
 // Particle half: optional sort, staging, gather/push/track/deposit into d_dgn and the
 // alternate particle buffers.  Nothing is committed here.
 template <typename T>
 void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
     ev_mark(c, 0);
     if (do_sort) sort_all(c);
+    {
+        const int rc = inject_phase<T>(c);
+        if (rc != FEPIC_OK) {
+            c->deferred_err = rc;
+            return;
+        }
+    }
     ev_mark(c, 1);
     {
         hipEvent_t* ev = timer_pair(c, FAM_STAGE);
@@ -377,6 +458,19 @@ void particle_phase_ab(fepic_ctx* c, double dt, bool do_sort) {
     }
     ev_mark(c, 0);
     if (do_sort) sort_all(c);
+    {
+        int rc = inject_phase<double>(c);
+        if (rc == FEPIC_OK)
+            for (auto& s : c->species) {   // injected slots start at order 1
+                rc = ab_fit(c, s);
+                if (rc != FEPIC_OK) break;
+                ab_mark_new(c, s);
+            }
+        if (rc != FEPIC_OK) {
+            c->deferred_err = rc;
+            return;
+        }
+    }
     ev_mark(c, 1);
     {
         hipEvent_t* ev = timer_pair(c, FAM_STAGE);
@@ -813,6 +907,14 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
         c->rho_valid = true;
     }
     const bool do_sort = (c->opt.sort_period > 0) && (c->step_count % c->opt.sort_period == 0);
+    // particles injected by this step are dropped again on any failure below
+    struct InjectGuard {
+        fepic_ctx* c;
+        bool committed = false;
+        ~InjectGuard() {
+            if (!committed) inject_undo(c);
+        }
+    } guard{c};
     particle_phase(c, dt, do_sort);
     if (c->deferred_err) {
         int rc = c->deferred_err;
@@ -860,6 +962,8 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
         if (rc != FEPIC_OK) return rc;
     }
     // commit
+    guard.committed = true;
+    st.n_injected = inject_commit(c);
     for (auto& s : c->species) s.cur = 1 - s.cur;
     if (c->opt.pusher == FEPIC_PUSHER_AB)
         for (auto& s : c->species) s.abm_cur = 1 - s.abm_cur;
@@ -1416,6 +1520,46 @@ int fepic_add_species(fepic_ctx* c, double q, double m, double w, int* out) {
         return fail(c, FEPIC_E_OOM, "allocation failed");
     c->species.push_back(s);
     if (out) *out = (int)c->species.size() - 1;
+    return FEPIC_OK;
+}
+
+int fepic_set_injector(fepic_ctx* c, int species, const fepic_injector* spec) {
+    NEED_DEV(c);
+    if (species < 0 || species >= (int)c->species.size()) return fail(c, FEPIC_E_ARG, "bad species");
+    Species& s = c->species[species];
+    if (!spec) {
+        s.inj_on = false;
+        return FEPIC_OK;
+    }
+    const double nn = std::sqrt(spec->normal[0] * spec->normal[0] + spec->normal[1] * spec->normal[1] +
+                                spec->normal[2] * spec->normal[2]);
+    bool ok = std::isfinite(nn) && nn > 0 && spec->radius > 0 && std::isfinite(spec->radius) &&
+              spec->kinetic_eV >= 0 && std::isfinite(spec->kinetic_eV) && spec->thermal_eV >= 0 &&
+              std::isfinite(spec->thermal_eV) && spec->per_step >= 0 && spec->per_step < ((int64_t)1 << 30);
+    for (int d = 0; d < 3; ++d) ok = ok && std::isfinite(spec->center[d]);
+    if (!ok) return fail(c, FEPIC_E_ARG, "bad injector parameters");
+    InjectorSpec& sp = s.inj;
+    for (int d = 0; d < 3; ++d) {
+        sp.c[d] = spec->center[d];
+        sp.n[d] = spec->normal[d] / nn;
+    }
+    // in-plane basis: e1 = unit(n x a), a the x axis unless n is within 26 degrees of it
+    const double a[3] = {std::fabs(sp.n[0]) < 0.9 ? 1.0 : 0.0, std::fabs(sp.n[0]) < 0.9 ? 0.0 : 1.0, 0.0};
+    double e1[3] = {sp.n[1] * a[2] - sp.n[2] * a[1], sp.n[2] * a[0] - sp.n[0] * a[2], sp.n[0] * a[1] - sp.n[1] * a[0]};
+    const double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (int d = 0; d < 3; ++d) sp.e1[d] = e1[d] / l1;
+    sp.e2[0] = sp.n[1] * sp.e1[2] - sp.n[2] * sp.e1[1];
+    sp.e2[1] = sp.n[2] * sp.e1[0] - sp.n[0] * sp.e1[2];
+    sp.e2[2] = sp.n[0] * sp.e1[1] - sp.n[1] * sp.e1[0];
+    sp.radius = spec->radius;
+    const double g0 = 1.0 + spec->kinetic_eV * kQe / (s.m * kC * kC);
+    sp.v0 = kC * std::sqrt(1.0 - 1.0 / (g0 * g0));
+    sp.sigma = std::sqrt(spec->thermal_eV * kQe / s.m);
+    sp.per_step = spec->per_step;
+    sp.seed = spec->seed;
+    sp.species = species;
+    s.inj_on = true;
+    s.inj_k = 0;
     return FEPIC_OK;
 }
 

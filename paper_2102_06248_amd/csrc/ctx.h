@@ -46,6 +46,12 @@ struct Species {
     bool ab_reset = true;              // every slot restarts at order 1 at the next AB step
     int64_t ab_fill_from = INT64_MAX;  // slots appended since: no history yet
     bool sorted_pending = false;  // d_nlive holds a count not yet read back
+    // seeded disk source (fepic_set_injector): inj_k counts committed injections; a step
+    // that is not committed drops the particles it appended (inj_undo_n = count before)
+    bool inj_on = false;
+    InjectorSpec inj{};
+    int64_t inj_k = 0;
+    int64_t inj_undo_n = -1;
 };
 
 struct MlpState;
@@ -142,6 +148,9 @@ struct fepic_ctx {
     int cg_restarts = 0;
     bool recording = false;
     int64_t mlp_fallbacks = 0;
+    // staging of the injectors' draws (x, u per particle)
+    double* d_inj = nullptr;
+    int64_t inj_cap = 0;
     // copy of the last Newmark solve's start vector (fepic_keep_warm_start)
     bool keep_start = false;
     double* d_x0keep = nullptr;

@@ -16,6 +16,7 @@ namespace fepic {
 constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kMu0 = 1.25663706212e-6;
 constexpr double kC = 299792458.0;
+constexpr double kQe = 1.602176634e-19;   // elementary charge (exact); eV -> J
 
 // Sliced-ELLPACK slice height: one 64-lane wavefront per slice of 64 consecutive rows,
 // each of the slice's columns stored contiguously so a wave's loads coalesce.
@@ -210,6 +211,17 @@ void launch_locate(hipStream_t s, int64_t n, const double* x, const double* u, c
                    PArrays<T> out, int64_t out_off, const double* grad64, const double* r0, const int32_t* cell_start,
                    const int32_t* cell_tets, const double* grid_lo, const double* grid_inv_h, const int32_t* grid_n,
                    PushCounters* cnt);
+// Seeded disk source (fepic_set_injector, kernels_inject.hip): centre, unit normal, the
+// in-plane basis e1 = unit(n x a), e2 = n x e1, radius, drift speed, thermal spread.
+struct InjectorSpec {
+    double c[3], n[3], e1[3], e2[3];
+    double radius, v0, sigma;
+    int64_t per_step;
+    uint64_t seed;
+    int species;
+    int relativistic_u;   // store gamma v (Boris) rather than v (Adams-Bashforth)
+};
+void launch_inject_disk(hipStream_t s, const InjectorSpec& spec, int64_t k, double* x, double* u);
 // The Adams-Bashforth history moved by a sort with the particles it belongs to (hin ==
 // nullptr: no history); both history buffers have `stride` slots per component.
 struct AbHistIo {

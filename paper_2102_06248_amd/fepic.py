@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfepic.so")
 
-ABI_VERSION = 5   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
+ABI_VERSION = 6   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
 FEPIC_OK = 0
 FEPIC_FP32_PUSH_FP64_ACC, FEPIC_ALL_FP64 = 0, 1
 FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP = 0, 1, 2, 3
@@ -52,10 +52,16 @@ class fepic_step_stats(ctypes.Structure):
                 ("ms_rhs", ctypes.c_float), ("ms_warm", ctypes.c_float), ("ms_cg", ctypes.c_float),
                 ("ms_faraday", ctypes.c_float), ("ms_diag", ctypes.c_float),
                 ("magnetic_energy", ctypes.c_double), ("kinetic_energy", ctypes.c_double),
-                ("pc_far_levels", ctypes.c_int), ("cg_passes", ctypes.c_int)]
+                ("pc_far_levels", ctypes.c_int), ("cg_passes", ctypes.c_int), ("n_injected", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class fepic_injector(ctypes.Structure):
+    _fields_ = [("center", ctypes.c_double * 3), ("normal", ctypes.c_double * 3), ("radius", ctypes.c_double),
+                ("kinetic_eV", ctypes.c_double), ("thermal_eV", ctypes.c_double), ("per_step", ctypes.c_int64),
+                ("seed", ctypes.c_uint64)]
 
 
 class fepic_train_opts(ctypes.Structure):
@@ -97,6 +103,7 @@ _SIGS = {
     "fepic_init_electrostatic": [_P, _D, ctypes.POINTER(_INT)],
     "fepic_add_species": [_P, _D, _D, _D, ctypes.POINTER(_INT)],
     "fepic_upload_particles": [_P, _INT, _I64, _P, _P, _P, _PI64],
+    "fepic_set_injector": [_P, _INT, ctypes.POINTER(fepic_injector)],
     "fepic_inject_particles": [_P, _INT, _I64, _P, _P, _P],
     "fepic_inject_particles_device": [_P, _INT, _I64, _P, _P, _P],
     "fepic_upload_particles_device": [_P, _INT, _I64, _P, _P, _P, _PI64],
@@ -339,6 +346,17 @@ def fepic_inject_particles_device(ctx, species, n, x_ptr, u_ptr, id_ptr=None):
     """x_ptr, u_ptr: device addresses of [n][3] float64 arrays (e.g. tensor.data_ptr());
     id_ptr: device address of [n] int64 ids, or None."""
     _check(ctx, lib().fepic_inject_particles_device(ctx, species, n, id_ptr, x_ptr, u_ptr))
+
+
+def fepic_set_injector(ctx, species, center=None, normal=None, radius=None, kinetic_eV=0.0, thermal_eV=0.0,
+                       per_step=0, seed=0, off=False):
+    """Seeded disk source of a species (off=True removes it)."""
+    if off:
+        _check(ctx, lib().fepic_set_injector(ctx, int(species), None))
+        return
+    spec = fepic_injector((ctypes.c_double * 3)(*center), (ctypes.c_double * 3)(*normal), float(radius),
+                          float(kinetic_eV), float(thermal_eV), int(per_step), int(seed))
+    _check(ctx, lib().fepic_set_injector(ctx, int(species), ctypes.byref(spec)))
 
 
 def fepic_num_particles(ctx, species):
