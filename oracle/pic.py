@@ -19,7 +19,7 @@ import scipy.sparse.linalg as spla
 
 from . import ab
 from . import diagnostics as dg_
-from . import fem, newmark
+from . import fem, mfem, newmark
 from .mesh import Mesh
 from .particles import CMesh, push
 
@@ -35,11 +35,14 @@ class Species:
 
 
 class OracleSim:
-    def __init__(self, xyz, tets, cg_tol=1e-10, cg_maxit=10000, crossing_cap=64, pusher="boris", ab_order=4):
+    def __init__(self, xyz, tets, cg_tol=1e-10, cg_maxit=10000, crossing_cap=64, pusher="boris", ab_order=4,
+                 field_solver="wave"):
         """pusher: "boris" (relativistic Boris, straight paths; u = gamma v at t_{n-1/2}) or
         "ab" (the Adams-Bashforth pusher of Sec. III-B of order ab_order with its curved
-        paths; u = v at t_n)."""
-        self.pusher, self.ab_order = pusher, ab_order
+        paths; u = v at t_n).  field_solver: "wave" (the Newmark wave equation for e, b by
+        Faraday), "nm_mfem" or "bd_mfem" (the mixed system, oracle/mfem.py)."""
+        assert field_solver in ("wave", "nm_mfem", "bd_mfem")
+        self.pusher, self.ab_order, self.field_solver = pusher, ab_order, field_solver
         self.mesh = m = Mesh(xyz, tets)
         self.cmesh = CMesh(m)
         self.cg_tol, self.cg_maxit, self.cap = cg_tol, cg_maxit, crossing_cap
@@ -54,7 +57,11 @@ class OracleSim:
         self.e_prev = np.zeros(ne)
         self.e_prev2 = np.zeros(ne)
         self.b = np.zeros(nf)
+        self.b_prev = np.zeros(nf)
         self.dG = np.zeros(ne)
+        if field_solver != "wave":
+            self.Mf = fem.face_mass_matrix(m)
+            self.CtMf = (self.C.T @ self.Mf).tocsr()
         self.G = np.zeros(ne)
         self.species = []
         self.t = 0.0
@@ -88,6 +95,7 @@ class OracleSim:
 
     def set_uniform_B(self, B0):
         self.b = self.mesh.face_dofs_of_uniform_field(B0)
+        self.b_prev = self.b.copy()
 
     def charge(self):
         rho = np.zeros(self.mesh.n_nodes)
@@ -159,7 +167,15 @@ class OracleSim:
             src = (dG_new - self.dG)[ie]
         else:
             src = source_override(dG_new, self.dG)
-        rhs = newmark.newmark_rhs(B1, B2, self.e[ie], self.e_prev[ie], src)
+        if self.field_solver == "wave":
+            rhs = newmark.newmark_rhs(B1, B2, self.e[ie], self.e_prev[ie], src)
+        elif self.field_solver == "nm_mfem":
+            A = newmark.newmark_operators(self.Mi, self.Si, dt, 0.25, 0.5)[0]
+            rhs = mfem.nm_rhs(self.M, self.S, self.CtMf, dt, self.e, self.e_prev, self.b, self.b_prev, dG_new,
+                              self.dG)[ie]
+        else:
+            A = newmark.newmark_operators(self.Mi, self.Si, dt, 1.0, 0.5)[0]
+            rhs = mfem.bd_rhs(self.M, self.CtMf, dt, self.e, self.b, dG_new)[ie]
         e_new = np.zeros_like(self.e)
         if solve:
             start = self.e[ie] if x0 is None else x0
@@ -171,11 +187,16 @@ class OracleSim:
             it, res = 0, 0.0
             e_new[:] = self.e
             r_cg = np.zeros_like(self.e)
-        b_new = newmark.faraday(self.C, self.b, e_new, self.e, dt, gamma)
+        if self.field_solver == "wave":
+            b_new = newmark.faraday(self.C, self.b, e_new, self.e, dt, gamma)
+        elif self.field_solver == "nm_mfem":
+            b_new = mfem.nm_faraday(self.C, dt, self.b_prev, e_new, self.e, self.e_prev)
+        else:
+            b_new = mfem.bd_faraday(self.C, dt, self.b, e_new)
 
         # commit
         self.e_prev2, self.e_prev, self.e = self.e_prev, self.e, e_new
-        self.b = b_new
+        self.b_prev, self.b = self.b, b_new
         self.dG = dG_new
         self.G = self.G + dG_new
         self.t += dt
@@ -192,7 +213,10 @@ class OracleSim:
         scale = max(np.max(np.abs(self.rho[ni])) if len(ni) else 0.0, qw)
         drift = None
         if len(self._rG) == 3:
-            d2 = self._rG[2] - 2 * self._rG[1] + self._rG[0]
+            # the Gauss residual's recurrence follows the solver's stencil: wave (1, -2, 1),
+            # NM-MFEM (1, 0, -1), BD-MFEM (1, -1, 0), newest first
+            c0, c1, c2 = {"wave": (1, -2, 1), "nm_mfem": (-1, 0, 1), "bd_mfem": (0, -1, 1)}[self.field_solver]
+            d2 = c0 * self._rG[0] + c1 * self._rG[1] + c2 * self._rG[2]
             drift = float(np.max(np.abs(d2 - (self.D.T @ r_cg)[ni])) / scale) if len(ni) else 0.0
         st.update(cg_iters=it, cg_rel_resid=res, cont_resid_rel=float(np.max(np.abs(r_cont)) / scale) if len(ni) else 0.0,
                   gauss_resid_rel=float(np.max(np.abs(r_g)) / scale) if len(ni) else 0.0,
