@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define FEPIC_ABI_VERSION 6
+#define FEPIC_ABI_VERSION 7
 
 enum {
     FEPIC_OK = 0,
@@ -116,6 +116,23 @@ enum { FEPIC_WALK_AUTO = 0, FEPIC_WALK_QUEUE = 1, FEPIC_WALK_FUSED = 2 };
  * fepic_load. */
 enum { FEPIC_PUSHER_BORIS = 0, FEPIC_PUSHER_AB = 1 };
 
+/* Field update of fepic_step (Sec. II-B; the source is the time-integrated current G in
+ * every case, Sec. III-A, so continuity and Gauss hold whichever is used).
+ * FEPIC_FIELD_WAVE: the Newmark(beta, gamma) wave equation for e (step's beta, gamma),
+ * b by Faraday b^{n+1} = b^n - dt C (gamma e^{n+1} + (1 - gamma) e^n).
+ * FEPIC_FIELD_NM_MFEM: the mixed system (b on faces, e on edges: d_t b + C e = 0,
+ * M d_t e - C^T Mf b = -j, Mf the Whitney-2 mass [*mu0^-1]) with the three-level Newmark
+ * recurrence at beta = 1/4, gamma = 1/2 and the e-row source -1/2 (G^{n+1} - G^{n-1});
+ * b^{n+1} eliminated, e^{n+1} solves (M + dt^2/4 S) e^{n+1} = M e^{n-1}
+ * + dt C^T Mf (b^n + b^{n-1}) - dt^2 S (e^n / 2 + e^{n-1} / 4) - (G^{n+1} - G^{n-1}), then
+ * b^{n+1} = b^{n-1} - dt C (e^n + (e^{n+1} + e^{n-1}) / 2).
+ * FEPIC_FIELD_BD_MFEM: the same system with backward differences (backward Euler):
+ * (M + dt^2 S) e^{n+1} = M e^n + dt C^T Mf b^n - (G^{n+1} - G^n), b^{n+1} = b^n - dt C e^{n+1}.
+ * The mixed updates ignore the step's beta and gamma.  The Gauss-drift check follows each
+ * update's recurrence: r^{n+1} - 2 r^n + r^{n-1}, r^{n+1} - r^{n-1} or r^{n+1} - r^n equals
+ * D^T r_cg. */
+enum { FEPIC_FIELD_WAVE = 0, FEPIC_FIELD_NM_MFEM = 1, FEPIC_FIELD_BD_MFEM = 2 };
+
 typedef struct fepic_ctx fepic_ctx;
 
 typedef struct {
@@ -143,6 +160,7 @@ typedef struct {
                               (0, 1) (default 1e-4)                                       */
     int pusher;            /* FEPIC_PUSHER_* (default FEPIC_PUSHER_BORIS)                 */
     int ab_order;          /* FEPIC_PUSHER_AB: order 1..5 (default 4)                     */
+    int field_solver;      /* FEPIC_FIELD_* (default FEPIC_FIELD_WAVE)                    */
 } fepic_options;
 
 typedef struct {
@@ -196,6 +214,8 @@ int fepic_set_preconditioner(fepic_ctx* ctx, int pc);
 /* Selects the arithmetic of later Newmark solves (FEPIC_SOLVE_*; FEPIC_E_ARG for any other
  * value, and for FEPIC_SOLVE_MIXED with the Jacobi preconditioner). */
 int fepic_set_solve_precision(fepic_ctx* ctx, int solve_precision);
+/* Selects the field update of later steps (FEPIC_FIELD_*; FEPIC_E_ARG otherwise). */
+int fepic_set_field_solver(fepic_ctx* ctx, int solver);
 /* Selects the pusher (FEPIC_PUSHER_*) and Adams-Bashforth order (1..5) of later steps;
  * FEPIC_E_ARG for other values and for FEPIC_PUSHER_AB without FEPIC_ALL_FP64.  A switch of
  * pusher restarts the Adams-Bashforth histories. */

@@ -552,19 +552,154 @@ int ensure_operator_f32(fepic_ctx* c) {
     return FEPIC_OK;
 }
 
+// SELL-64 layout of variable-length rows: slice s of 64 rows has the width of its longest
+// row; entry k of row r sits at sp[s] + 64 k + (r mod 64); shorter rows are padded with
+// `pad` (column) and zero values.
+template <typename V>
+void sell_pack(const std::vector<int64_t>& row_ptr, const std::vector<int32_t>& cols, const std::vector<V>& vals,
+               bool pad_self, int32_t pad, std::vector<int64_t>& sp, std::vector<int32_t>& out_col,
+               std::vector<V>& out_val) {
+    const int64_t n = (int64_t)row_ptr.size() - 1, ns = (n + kSell - 1) / kSell;
+    sp.assign(ns + 1, 0);
+    for (int64_t sl = 0; sl < ns; ++sl) {
+        int64_t w = 0;
+        for (int64_t r = sl * kSell; r < std::min(n, (sl + 1) * kSell); ++r) w = std::max(w, row_ptr[r + 1] - row_ptr[r]);
+        sp[sl + 1] = sp[sl] + w * kSell;
+    }
+    out_col.assign(sp[ns], pad);
+    out_val.assign(sp[ns], V(0));
+    for (int64_t sl = 0; sl < ns; ++sl)
+        for (int64_t l = 0; l < kSell; ++l) {
+            const int64_t r = sl * kSell + l;
+            const int64_t w = (sp[sl + 1] - sp[sl]) / kSell;
+            for (int64_t k = 0; k < w; ++k) {
+                const int64_t at = sp[sl] + k * kSell + l;
+                if (r < n && row_ptr[r] + k < row_ptr[r + 1]) {
+                    out_col[at] = cols[row_ptr[r] + k];
+                    out_val[at] = vals[row_ptr[r] + k];
+                } else if (pad_self) {
+                    out_col[at] = (int32_t)std::min<int64_t>(r, n - 1);
+                }
+            }
+        }
+}
+
+// The operators of the mixed (b, e) updates, built once on the host: the Whitney-2 mass
+// Mf = [*mu0^-1] over faces, element by element from the field's vertex values (the
+// field of face (i, j, l) is 2 grad l_j x grad l_l at vertex i, and so on, zero at the
+// opposite vertex; int lambda_v lambda_w = V (1 + delta_vw) / 20), and each edge's list of
+// incident faces with the sign of C (face (i, j, k): +(i, j), +(j, k), -(i, k)).
+int ensure_mfem(fepic_ctx* c) {
+    if (c->mfem_ready) return FEPIC_OK;
+    const HostMesh& m = c->mesh;
+    const int64_t nt = m.n_tets, nf = m.n_faces, ne = m.n_edges;
+    constexpr int kLFv[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    std::vector<int8_t> cnt(nf, 0);
+    std::vector<int32_t> cc(7 * nf, -1);
+    std::vector<double> cv(7 * nf, 0.0);
+    auto add = [&](int64_t f, int32_t g, double v) {
+        for (int k = 0; k < cnt[f]; ++k)
+            if (cc[7 * f + k] == g) {
+                cv[7 * f + k] += v;
+                return;
+            }
+        cc[7 * f + cnt[f]] = g;
+        cv[7 * f + cnt[f]] = v;
+        ++cnt[f];
+    };
+    for (int64_t t = 0; t < nt; ++t) {
+        double g[4][3];
+        for (int k = 1; k < 4; ++k)
+            for (int d = 0; d < 3; ++d) g[k][d] = m.grad[9 * t + 3 * (k - 1) + d];
+        for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+        double w[4][4][3] = {};   // w[face][vertex]
+        auto cr = [](const double* a, const double* b, double* o) {
+            o[0] = 2.0 * (a[1] * b[2] - a[2] * b[1]);
+            o[1] = 2.0 * (a[2] * b[0] - a[0] * b[2]);
+            o[2] = 2.0 * (a[0] * b[1] - a[1] * b[0]);
+        };
+        for (int k = 0; k < 4; ++k) {
+            const int i = kLFv[k][0], j = kLFv[k][1], l = kLFv[k][2];
+            cr(g[j], g[l], w[k][i]);
+            cr(g[l], g[i], w[k][j]);
+            cr(g[i], g[j], w[k][l]);
+        }
+        const double f0 = m.vol[t] / (20.0 * kMu0);
+        for (int k = 0; k < 4; ++k)
+            for (int l = 0; l < 4; ++l) {
+                double sv = 0.0, sk[3] = {0, 0, 0}, sl[3] = {0, 0, 0};
+                for (int v = 0; v < 4; ++v)
+                    for (int d = 0; d < 3; ++d) {
+                        sv += w[k][v][d] * w[l][v][d];
+                        sk[d] += w[k][v][d];
+                        sl[d] += w[l][v][d];
+                    }
+                add(m.tet_faces[4 * t + k], m.tet_faces[4 * t + l], f0 * (sv + sk[0] * sl[0] + sk[1] * sl[1] + sk[2] * sl[2]));
+            }
+    }
+    std::vector<int64_t> rp(nf + 1, 0);
+    for (int64_t f = 0; f < nf; ++f) rp[f + 1] = rp[f] + cnt[f];
+    std::vector<int32_t> cols(rp[nf]);
+    std::vector<double> vals(rp[nf]);
+    for (int64_t f = 0; f < nf; ++f)
+        for (int k = 0; k < cnt[f]; ++k) {
+            cols[rp[f] + k] = cc[7 * f + k];
+            vals[rp[f] + k] = cv[7 * f + k];
+        }
+    std::vector<int64_t> msp, esp;
+    std::vector<int32_t> mcol, einc;
+    std::vector<double> mval;
+    sell_pack(rp, cols, vals, true, 0, msp, mcol, mval);
+    // edge rows (device order): incident faces with the sign of C
+    std::vector<int64_t> erp(ne + 1, 0);
+    for (int64_t f = 0; f < nf; ++f)
+        for (int j = 0; j < 3; ++j) ++erp[m.dev_face_edges[3 * f + j] + 1];
+    for (int64_t e = 0; e < ne; ++e) erp[e + 1] += erp[e];
+    std::vector<int32_t> ecode(erp[ne]);
+    std::vector<int64_t> fill(erp.begin(), erp.end() - 1);
+    for (int64_t f = 0; f < nf; ++f)
+        for (int j = 0; j < 3; ++j) ecode[fill[m.dev_face_edges[3 * f + j]]++] = (int32_t)((f << 1) | (j == 2 ? 1 : 0));
+    std::vector<int32_t> dummy_val(erp[ne], 0), dummy_out;
+    sell_pack(erp, ecode, dummy_val, false, -1, esp, einc, dummy_out);
+    int rc;
+    if ((rc = upload(c, &c->d_mf_sp, msp)) || (rc = upload(c, &c->d_mf_col, mcol)) ||
+        (rc = upload(c, &c->d_mf_val, mval)) || (rc = upload(c, &c->d_ef_sp, esp)) || (rc = upload(c, &c->d_ef_inc, einc)))
+        return rc;
+    c->d_h = dalloc<double>(c, nf);
+    if (!c->d_h) return fail(c, FEPIC_E_OOM, "device allocation failed");
+    c->mfem_ready = true;
+    return FEPIC_OK;
+}
+
 constexpr int kMaxRestarts = 3;
 
 // Field half: RHS, warm start, PCG, true residual, Faraday into d_bn.  Returns the
 // iteration count via the host scalars (stream synchronized at return).
 int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
     const int64_t ne = c->mesh.n_edges;
-    ensure_operator(c, dt, beta);
+    const int fs = c->opt.field_solver;
+    if (fs != FEPIC_FIELD_WAVE) {
+        const int rc = ensure_mfem(c);
+        if (rc != FEPIC_OK) return rc;
+    }
+    // the mixed updates solve with the wave operator's form: M + dt^2/4 S (NM), M + dt^2 S (BD)
+    ensure_operator(c, dt, fs == FEPIC_FIELD_NM_MFEM ? 0.25 : fs == FEPIC_FIELD_BD_MFEM ? 1.0 : beta);
     ev_mark(c, 4);
     {
         hipEvent_t* ev = timer_pair(c, FAM_RHS);
         if (ev) (void)hipEventRecord(ev[0], c->stream);
-        launch_rhs(c->stream, ne, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_e, c->d_ep, c->d_dgn, c->d_dg, c->d_bedge,
-                   dt * dt, 0.5 - 2.0 * beta + gamma, 0.5 + beta - gamma, c->d_rhs, c->d_partial);
+        const int64_t nf = c->mesh.n_faces;
+        if (fs == FEPIC_FIELD_NM_MFEM)
+            launch_mfem_rhs(c->stream, ne, nf, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_e, c->d_ep, c->d_dgn, c->d_dg,
+                            c->d_bedge, c->d_mf_sp, c->d_mf_col, c->d_mf_val, c->d_b, 1.0, c->d_bp, 1.0, c->d_ef_sp,
+                            c->d_ef_inc, c->d_h, dt, 0.0, 1.0, -0.5, -0.25, 1.0, 1.0, c->d_rhs, c->d_partial);
+        else if (fs == FEPIC_FIELD_BD_MFEM)
+            launch_mfem_rhs(c->stream, ne, nf, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_e, c->d_ep, c->d_dgn, c->d_dg,
+                            c->d_bedge, c->d_mf_sp, c->d_mf_col, c->d_mf_val, c->d_b, 1.0, c->d_bp, 0.0, c->d_ef_sp,
+                            c->d_ef_inc, c->d_h, dt, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0, c->d_rhs, c->d_partial);
+        else
+            launch_rhs(c->stream, ne, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_e, c->d_ep, c->d_dgn, c->d_dg,
+                       c->d_bedge, dt * dt, 0.5 - 2.0 * beta + gamma, 0.5 + beta - gamma, c->d_rhs, c->d_partial);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
     ev_mark(c, 5);
@@ -752,7 +887,14 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
     {
         hipEvent_t* ev = timer_pair(c, FAM_FARADAY);
         if (ev) (void)hipEventRecord(ev[0], c->stream);
-        launch_faraday(c->stream, c->mesh.n_faces, c->d_face_edges, c->d_b, c->d_x, c->d_e, dt, gamma, c->d_bn);
+        if (fs == FEPIC_FIELD_NM_MFEM)
+            launch_mfem_faraday(c->stream, c->mesh.n_faces, c->d_face_edges, c->d_bp, c->d_e, c->d_ep, c->d_x, dt,
+                                1.0, 0.5, 0.5, c->d_bn);
+        else if (fs == FEPIC_FIELD_BD_MFEM)
+            launch_mfem_faraday(c->stream, c->mesh.n_faces, c->d_face_edges, c->d_b, c->d_e, c->d_ep, c->d_x, dt,
+                                0.0, 0.0, 1.0, c->d_bn);
+        else
+            launch_faraday(c->stream, c->mesh.n_faces, c->d_face_edges, c->d_b, c->d_x, c->d_e, dt, gamma, c->d_bn);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
     ev_mark(c, 8);
@@ -798,8 +940,12 @@ int run_diagnostics(fepic_ctx* c, fepic_step_stats* st, bool have_step, bool hav
     double* rG_new = c->d_rG[c->rG_head];
     const double* rG1 = c->d_rG[(c->rG_head + 2) % 3];
     const double* rG2 = c->d_rG[(c->rG_head + 1) % 3];
+    // the Gauss residual's recurrence follows the field update's stencil (r^{n+1} + c1 r^n +
+    // c2 r^{n-1} = D^T r_cg): wave (-2, 1), NM-MFEM (0, -1), BD-MFEM (-1, 0)
+    const double gc1 = c->opt.field_solver == FEPIC_FIELD_WAVE ? -2.0 : c->opt.field_solver == FEPIC_FIELD_BD_MFEM ? -1.0 : 0.0;
+    const double gc2 = c->opt.field_solver == FEPIC_FIELD_BD_MFEM ? 0.0 : c->opt.field_solver == FEPIC_FIELD_NM_MFEM ? -1.0 : 1.0;
     launch_diag_nodes(s, nn, c->d_inode, c->d_rho_new, c->rho_valid ? c->d_rho : c->d_rho_new, c->d_n1, c->d_n2, rG1,
-                      rG2, c->d_n3, have_hist, rG_new, c->d_acc);
+                      rG2, c->d_n3, have_hist, gc1, gc2, rG_new, c->d_acc);
     launch_divb(s, c->mesh.n_tets, c->d_tet_faces, c->d_b, c->d_acc);
     launch_dot(s, ne, c->d_e, c->d_Me, c->d_partial, &c->d_acc->energy);
     launch_magnetic(s, c->mesh.n_tets, c->d_b, c->d_grad64, c->d_tet_faces, &c->d_acc->magnetic);
@@ -977,7 +1123,10 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
         c->d_ep = c->d_e;
         c->d_e = c->d_x;
         c->d_x = old_ep2;
-        std::swap(c->d_b, c->d_bn);
+        double* old_bp = c->d_bp;   // b^{n-1} <- b^n <- b^{n+1}
+        c->d_bp = c->d_b;
+        c->d_b = c->d_bn;
+        c->d_bn = old_bp;
     }
     c->step_count++;
     c->time += dt;
@@ -1141,6 +1290,7 @@ void fepic_default_options(fepic_options* o) {
     o->mixed_inner_tol = 1e-4;
     o->pusher = FEPIC_PUSHER_BORIS;
     o->ab_order = 4;
+    o->field_solver = FEPIC_FIELD_WAVE;
 }
 
 const char* fepic_error_string(int code) {
@@ -1179,6 +1329,7 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
     if (o.pusher != FEPIC_PUSHER_BORIS && o.pusher != FEPIC_PUSHER_AB) return FEPIC_E_ARG;
     if (o.ab_order < 1 || o.ab_order > kAbMax) return FEPIC_E_ARG;
     if (o.pusher == FEPIC_PUSHER_AB && o.precision != FEPIC_ALL_FP64) return FEPIC_E_ARG;
+    if (o.field_solver < FEPIC_FIELD_WAVE || o.field_solver > FEPIC_FIELD_BD_MFEM) return FEPIC_E_ARG;
     if (o.cg_check_every < 1) o.cg_check_every = 8;
     fepic_ctx* c = new fepic_ctx();
     c->opt = o;
@@ -1261,6 +1412,14 @@ int fepic_set_solve_precision(fepic_ctx* c, int sp) {
         for (int& n : c->last_pass_iters) n = 0;
     }
     c->opt.solve_precision = sp;
+    return FEPIC_OK;
+}
+
+int fepic_set_field_solver(fepic_ctx* c, int solver) {
+    if (!c) return FEPIC_E_ARG;
+    if (solver < FEPIC_FIELD_WAVE || solver > FEPIC_FIELD_BD_MFEM) return fail(c, FEPIC_E_ARG, "bad field solver");
+    if (solver != c->opt.field_solver) c->rG_levels = 0;   // the Gauss recurrence changes with it
+    c->opt.field_solver = solver;
     return FEPIC_OK;
 }
 
@@ -1392,7 +1551,7 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
         HIPCHK(c, hipMemset(c->d_rq, 0, sizeof(double2) * ne));
         for (double2* p : c->d_zp) HIPCHK(c, hipMemset(p, 0, sizeof(double2) * ne));
     }
-    double** fv[] = {&c->d_b, &c->d_bn};
+    double** fv[] = {&c->d_b, &c->d_bn, &c->d_bp};
     for (double** p : fv) {
         *p = dalloc<double>(c, nf);
         if (!*p) return fail(c, FEPIC_E_OOM, "device allocation failed");
@@ -1493,7 +1652,10 @@ int fepic_set_fields(fepic_ctx* c, const double* e, const double* e_prev, const 
     if (e && (rc = put_e(c->d_e, e))) return rc;
     if (e_prev && (rc = put_e(c->d_ep, e_prev))) return rc;
     if (e_prev && (rc = put_e(c->d_ep2, e_prev))) return rc;
-    if (b) HIPCHK(c, hipMemcpy(c->d_b, b, sizeof(double) * m.n_faces, hipMemcpyHostToDevice));
+    if (b) {
+        HIPCHK(c, hipMemcpy(c->d_b, b, sizeof(double) * m.n_faces, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->d_bp, b, sizeof(double) * m.n_faces, hipMemcpyHostToDevice));
+    }
     c->rG_levels = 0;
     return FEPIC_OK;
 }
@@ -1875,7 +2037,7 @@ int fepic_save(fepic_ctx* c, const char* path) {
     const HostMesh& m = c->mesh;
     bool ok = true;
     auto W = [&](const void* p, size_t n) { ok = ok && std::fwrite(p, 1, n, f) == n; };
-    W("FEPICCK1", 8);
+    W("FEPICCK2", 8);
     const int64_t hdr[6] = {m.n_nodes, m.n_tets, m.n_edges, m.n_faces, (int64_t)c->species.size(),
                             c->opt.precision};
     W(hdr, sizeof(hdr));
@@ -1888,6 +2050,7 @@ int fepic_save(fepic_ctx* c, const char* path) {
     };
     for (const double* d : {c->d_e, c->d_ep, c->d_ep2, c->d_dg, c->d_G}) dump(d, m.n_edges);
     dump(c->d_b, m.n_faces);
+    dump(c->d_bp, m.n_faces);
     for (auto& s : c->species) {
         W(&s.q, 8);
         W(&s.m, 8);
@@ -1922,7 +2085,7 @@ int fepic_load(fepic_ctx* c, const char* path) {
     R(magic, 8);
     int64_t hdr[6];
     R(hdr, sizeof(hdr));
-    if (!ok || std::memcmp(magic, "FEPICCK1", 8) || hdr[0] != m.n_nodes || hdr[1] != m.n_tets ||
+    if (!ok || std::memcmp(magic, "FEPICCK2", 8) || hdr[0] != m.n_nodes || hdr[1] != m.n_tets ||
         hdr[2] != m.n_edges || hdr[3] != m.n_faces || hdr[4] != (int64_t)c->species.size() ||
         hdr[5] != c->opt.precision) {
         std::fclose(f);
@@ -1937,6 +2100,7 @@ int fepic_load(fepic_ctx* c, const char* path) {
     };
     for (double* d : {c->d_e, c->d_ep, c->d_ep2, c->d_dg, c->d_G}) fill(d, m.n_edges);
     fill(c->d_b, m.n_faces);
+    fill(c->d_bp, m.n_faces);
     for (auto& s : c->species) {
         double q, mm, w;
         int64_t n, next_id;

@@ -92,6 +92,13 @@ struct fepic_ctx {
     double *d_e = nullptr, *d_ep = nullptr, *d_ep2 = nullptr, *d_x = nullptr;
     double *d_dg = nullptr, *d_dgn = nullptr, *d_G = nullptr;
     double *d_b = nullptr, *d_bn = nullptr;
+    double* d_bp = nullptr;   // b^{n-1} (the three-level mixed update needs it)
+    // mixed (b, e) updates: Whitney-2 mass over faces and each edge's incident faces, both
+    // SELL-64 (built on first use), and a face work vector
+    bool mfem_ready = false;
+    int64_t *d_mf_sp = nullptr, *d_ef_sp = nullptr;
+    int32_t *d_mf_col = nullptr, *d_ef_inc = nullptr;
+    double *d_mf_val = nullptr, *d_h = nullptr;
     double *d_rhs = nullptr, *d_rt = nullptr, *d_Me = nullptr;
     fepic::CgVec* d_cgv[2] = {nullptr, nullptr};   // Jacobi-PCG state, double buffered
     // auxiliary-space PCG: (z, p) pairs double buffered, r and q (n_edges each), nodal arrays

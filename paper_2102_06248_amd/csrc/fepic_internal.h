@@ -297,7 +297,19 @@ void launch_faraday(hipStream_t s, int64_t n_faces, const int32_t* face_edges, c
 void launch_DT(hipStream_t s, int64_t n_edges, const int32_t* edges, const double* v, double* out_nodes);
 void launch_diag_nodes(hipStream_t s, int64_t n_nodes, const uint8_t* interior_node, const double* rho_new,
                        const double* rho_old, const double* dtdg, const double* dtMe, const double* rG1,
-                       const double* rG2, const double* dtrcg, int have_hist, double* rG_out, DiagAcc* acc);
+                       const double* rG2, const double* dtrcg, int have_hist, double c1, double c2, double* rG_out,
+                       DiagAcc* acc);
+// Mixed (b, e) field updates: face-mass product then the eliminated right-hand side (see
+// kernels_fields.hip), and the face flux update.
+void launch_mfem_rhs(hipStream_t s, int64_t n_rows, int64_t n_faces, const int64_t* sp, const int32_t* col,
+                     const double* M, const double* S, const double* e, const double* ep, const double* dg_new,
+                     const double* dg_old, const uint8_t* bmask, const int64_t* fsp, const int32_t* fcol,
+                     const double* fval, const double* b1, double cb1, const double* b2, double cb2,
+                     const int64_t* esp, const int32_t* einc, double* h, double dt, double a0, double a1, double s0,
+                     double s1, double g0, double g1, double* bvec, double* partial);
+void launch_mfem_faraday(hipStream_t s, int64_t n_faces, const int32_t* face_edges, const double* b_base,
+                         const double* e_n, const double* e_nm1, const double* e_np1, double dt, double cn, double cm,
+                         double cp, double* b_new);
 void launch_divb(hipStream_t s, int64_t n_tets, const int32_t* tet_faces, const double* b, DiagAcc* acc);
 void launch_dot(hipStream_t s, int64_t n, const double* a, const double* b, double* partial, double* out);
 size_t partial_buffer_doubles();

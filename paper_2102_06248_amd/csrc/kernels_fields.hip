@@ -209,6 +209,91 @@ __global__ __launch_bounds__(kBlock) void k_rhs(int64_t n_rows, RowGrid rg, cons
     write_partials<1>(bb, partial);
 }
 
+// The mixed (b, e) updates (FEPIC_FIELD_NM_MFEM, FEPIC_FIELD_BD_MFEM) with b^{n+1}
+// eliminated: h = Mf (c1 b^n + c2 b^{n-1}) on face rows (Whitney-2 mass, SELL-64), then on
+// edge rows
+//   rhs = M (a0 e^n + a1 e^{n-1}) + dt^2 S (s0 e^n + s1 e^{n-1}) + dt sum_f C_fe h_f
+//         - (g0 dG^{n+1} + g1 dG^n),
+// C_fe from each edge's list of faces ((f << 1) | 1 for -1; -1 pads); wall rows 0.  The
+// partials of ||rhs||^2 go where k_rhs puts them, for the solve that follows.
+__global__ __launch_bounds__(kBlock) void k_face_spmv(int64_t n_faces, const int64_t* __restrict__ sp,
+                                                       const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                       const double* __restrict__ b1, double c1,
+                                                       const double* __restrict__ b2, double c2,
+                                                       double* __restrict__ h) {
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (((r >> 6) << 6) >= n_faces) return;
+    const int64_t sl = r >> 6;
+    const int lane = (int)(r & 63);
+    double acc = 0.0;
+    for (int64_t k = sp[sl] + lane; k < sp[sl + 1]; k += 64) {
+        const int c = col[k];
+        acc += val[k] * (c1 * b1[c] + c2 * b2[c]);
+    }
+    if (r < n_faces) h[r] = acc;
+}
+
+struct MfemCoef {
+    double a0, a1, s0, s1, g0, g1;
+};
+
+__global__ __launch_bounds__(kBlock) void k_mfem_rhs(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
+                                                      const int32_t* __restrict__ col, const double* __restrict__ M,
+                                                      const double* __restrict__ S, const double* __restrict__ e,
+                                                      const double* __restrict__ ep, const double* __restrict__ dgn,
+                                                      const double* __restrict__ dgo, const uint8_t* __restrict__ bmask,
+                                                      const int64_t* __restrict__ esp, const int32_t* __restrict__ einc,
+                                                      const double* __restrict__ h, double dt, MfemCoef k,
+                                                      double* __restrict__ bvec, double* __restrict__ partial) {
+    double bb[1] = {0.0};
+    for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
+        const int64_t r = lb * kBlock + threadIdx.x;
+        if (((r >> 6) << 6) >= n_rows) continue;
+        const int64_t s = r >> 6;
+        const int lane = (int)(r & 63);
+        double am = 0.0, as = 0.0, ac = 0.0;
+        for (int64_t q = sp[s] + lane; q < sp[s + 1]; q += 64) {
+            const int c = col[q];
+            const double ec = e[c], epc = ep[c];
+            am += M[q] * (k.a0 * ec + k.a1 * epc);
+            as += S[q] * (k.s0 * ec + k.s1 * epc);
+        }
+        for (int64_t q = esp[s] + lane; q < esp[s + 1]; q += 64) {
+            const int code = einc[q];
+            if (code < 0) continue;
+            const double hf = h[code >> 1];
+            ac += (code & 1) ? -hf : hf;
+        }
+        if (r < n_rows) {
+            double v = am + dt * dt * as + dt * ac - (k.g0 * dgn[r] + k.g1 * dgo[r]);
+            if (bmask[r]) v = 0.0;
+            bvec[r] = v;
+            bb[0] += v * v;
+        }
+    }
+    write_partials<1>(bb, partial);
+}
+
+// b^{n+1} = b_base - dt C (cn e^n + cm e^{n-1} + cp e^{n+1}) (NM: b_base = b^{n-1},
+// coefficients 1, 1/2, 1/2; BD: b_base = b^n, 0, 0, 1).
+__global__ __launch_bounds__(kBlock) void k_mfem_faraday(int64_t n_faces, const int32_t* __restrict__ fe,
+                                                          const double* __restrict__ b_base,
+                                                          const double* __restrict__ e_n,
+                                                          const double* __restrict__ e_nm1,
+                                                          const double* __restrict__ e_np1, double dt, double cn,
+                                                          double cm, double cp, double* __restrict__ b_new) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f >= n_faces) return;
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int a = fe[3 * f + j];
+        const double ea = cn * e_n[a] + cm * e_nm1[a] + cp * e_np1[a];
+        v += j == 2 ? -ea : ea;
+    }
+    b_new[f] = b_base[f] - dt * v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_warm(int mode, int64_t n, const double* __restrict__ e,
                                                   const double* __restrict__ ep, const double* __restrict__ ep2,
                                                   double* __restrict__ x) {
@@ -1177,7 +1262,8 @@ __global__ __launch_bounds__(kBlock) void k_diag_nodes(int64_t n_nodes, const ui
                                                         const double* __restrict__ dtMe,
                                                         const double* __restrict__ rG1, const double* __restrict__ rG2,
                                                         const double* __restrict__ dtrcg, int have_hist,
-                                                        double* __restrict__ rG_out, DiagAcc* acc) {
+                                                        double c1, double c2, double* __restrict__ rG_out,
+                                                        DiagAcc* acc) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double v[4] = {0.0, 0.0, 0.0, 0.0};   // continuity, Gauss, rho, drift
     if (k < n_nodes) {
@@ -1190,7 +1276,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_nodes(int64_t n_nodes, const ui
             v[0] = rc;
             v[1] = rg;
             v[2] = rho_new[k];
-            if (have_hist) v[3] = (rg - 2.0 * rG1[k] + rG2[k]) - dtrcg[k];
+            if (have_hist) v[3] = (rg + c1 * rG1[k] + c2 * rG2[k]) - dtrcg[k];
         }
     }
     unsigned long long* const out[4] = {&acc->cont_max, &acc->gauss_max, &acc->rho_max, &acc->drift_max};
@@ -1289,6 +1375,27 @@ void launch_rhs(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t*
     const RowGrid rg = row_grid(n_rows);
     hipLaunchKernelGGL(k_rhs, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, M, S, e, ep, dg_new, dg_old,
                        bmask, dt2, c1, c2, b, partial + SLOT_RHS * kSlot);
+}
+
+void launch_mfem_rhs(hipStream_t s, int64_t n_rows, int64_t n_faces, const int64_t* sp, const int32_t* col,
+                     const double* M, const double* S, const double* e, const double* ep, const double* dg_new,
+                     const double* dg_old, const uint8_t* bmask, const int64_t* fsp, const int32_t* fcol,
+                     const double* fval, const double* b1, double cb1, const double* b2, double cb2,
+                     const int64_t* esp, const int32_t* einc, double* h, double dt, double a0, double a1, double s0,
+                     double s1, double g0, double g1, double* bvec, double* partial) {
+    hipLaunchKernelGGL(k_face_spmv, dim3(grid_1d((n_faces + 63) / 64 * 64, kBlock)), dim3(kBlock), 0, s, n_faces, fsp,
+                       fcol, fval, b1, cb1, b2, cb2, h);
+    const RowGrid rg = row_grid(n_rows);
+    const MfemCoef k{a0, a1, s0, s1, g0, g1};
+    hipLaunchKernelGGL(k_mfem_rhs, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, M, S, e, ep, dg_new, dg_old,
+                       bmask, esp, einc, h, dt, k, bvec, partial + SLOT_RHS * kSlot);
+}
+
+void launch_mfem_faraday(hipStream_t s, int64_t n_faces, const int32_t* face_edges, const double* b_base,
+                         const double* e_n, const double* e_nm1, const double* e_np1, double dt, double cn, double cm,
+                         double cp, double* b_new) {
+    hipLaunchKernelGGL(k_mfem_faraday, dim3(grid_1d(n_faces, kBlock)), dim3(kBlock), 0, s, n_faces, face_edges, b_base,
+                       e_n, e_nm1, e_np1, dt, cn, cm, cp, b_new);
 }
 
 void launch_warm(hipStream_t s, int mode, int64_t n, const double* e, const double* ep, const double* ep2, double* x) {
@@ -1487,9 +1594,10 @@ void launch_DT(hipStream_t s, int64_t n_edges, const int32_t* edges, const doubl
 
 void launch_diag_nodes(hipStream_t s, int64_t n_nodes, const uint8_t* interior_node, const double* rho_new,
                        const double* rho_old, const double* dtdg, const double* dtMe, const double* rG1,
-                       const double* rG2, const double* dtrcg, int have_hist, double* rG_out, DiagAcc* acc) {
+                       const double* rG2, const double* dtrcg, int have_hist, double c1, double c2, double* rG_out,
+                       DiagAcc* acc) {
     hipLaunchKernelGGL(k_diag_nodes, dim3(grid_1d(n_nodes, kBlock)), dim3(kBlock), 0, s, n_nodes, interior_node,
-                       rho_new, rho_old, dtdg, dtMe, rG1, rG2, dtrcg, have_hist, rG_out, acc);
+                       rho_new, rho_old, dtdg, dtMe, rG1, rG2, dtrcg, have_hist, c1, c2, rG_out, acc);
 }
 
 void launch_divb(hipStream_t s, int64_t n_tets, const int32_t* tet_faces, const double* b, DiagAcc* acc) {

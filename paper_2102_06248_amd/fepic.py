@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfepic.so")
 
-ABI_VERSION = 6   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
+ABI_VERSION = 7   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
 FEPIC_OK = 0
 FEPIC_FP32_PUSH_FP64_ACC, FEPIC_ALL_FP64 = 0, 1
 FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP = 0, 1, 2, 3
@@ -23,6 +23,7 @@ FEPIC_PC_JACOBI, FEPIC_PC_AUX = 0, 1
 FEPIC_WALK_AUTO, FEPIC_WALK_QUEUE, FEPIC_WALK_FUSED = 0, 1, 2
 FEPIC_SOLVE_FP64, FEPIC_SOLVE_MIXED = 0, 1
 FEPIC_PUSHER_BORIS, FEPIC_PUSHER_AB = 0, 1
+FEPIC_FIELD_WAVE, FEPIC_FIELD_NM_MFEM, FEPIC_FIELD_BD_MFEM = 0, 1, 2
 FEPIC_E_CG_NOT_CONVERGED = -6
 FEPIC_E_CROSSING_CAP = -7
 FEPIC_MLP_N_PARAMS = 4545
@@ -38,7 +39,7 @@ class fepic_options(ctypes.Structure):
                 ("crossing_cap", ctypes.c_int), ("warm_start", ctypes.c_int), ("diagnostics", ctypes.c_int),
                 ("timing", ctypes.c_int), ("preconditioner", ctypes.c_int), ("aux_far_levels", ctypes.c_int),
                 ("walk", ctypes.c_int), ("solve_precision", ctypes.c_int), ("mixed_inner_tol", ctypes.c_double),
-                ("pusher", ctypes.c_int), ("ab_order", ctypes.c_int)]
+                ("pusher", ctypes.c_int), ("ab_order", ctypes.c_int), ("field_solver", ctypes.c_int)]
 
 
 class fepic_step_stats(ctypes.Structure):
@@ -126,6 +127,7 @@ _SIGS = {
     "fepic_set_preconditioner": [_P, _INT],
     "fepic_set_solve_precision": [_P, _INT],
     "fepic_set_pusher": [_P, _INT, _INT],
+    "fepic_set_field_solver": [_P, _INT],
     "fepic_mlp_forward": [_P, _I64, _P, _P],
     "fepic_mlp_grad": [_P, _I64, _P, _P, _P, ctypes.POINTER(_D)],
     "fepic_mlp_grad_noalloc": [_P, _I64, _P, _P, _P, _P],
@@ -488,6 +490,10 @@ def fepic_set_preconditioner(ctx, pc):
 
 def fepic_set_solve_precision(ctx, solve_precision):
     _check(ctx, lib().fepic_set_solve_precision(ctx, int(solve_precision)))
+
+
+def fepic_set_field_solver(ctx, solver):
+    _check(ctx, lib().fepic_set_field_solver(ctx, int(solver)))
 
 
 def fepic_set_pusher(ctx, pusher, ab_order=4):
