@@ -12,6 +12,9 @@ that is exact for the integrand's polynomial degree:
   [*eps]_ij   = < W1_i, eps0 W1_j >            (edge mass M; degree 2 -> 4-point rule)
   [*mu^-1]_ij = < W2_i, mu0^-1 W2_j >          (face mass; degree 2 -> 4-point rule)
   [*S]        = [curl]^T [*mu^-1] [curl]       (curl-curl; assembled from curl W1 directly)
+and the boundary matrix of the surface impedance matrix (Sec. II-A), without its mu^-1:
+  K_ij = int over the absorbing faces of (n x W1_i) . (n x W1_j) dS
+(degree 2 on each triangle; a 16-point collapsed Gauss rule).
 """
 from __future__ import annotations
 
@@ -121,3 +124,52 @@ def eval_E(mesh, e, t, lam):
 def eval_B(mesh, b, t, lam):
     W = whitney2(lam, mesh.grad_lambda[t])
     return np.einsum("...i,...id->...d", b[mesh.tet_faces[t]], W)
+
+
+# Collapsed (Duffy) 4 x 4 Gauss-Legendre rule on the reference triangle {s, t >= 0,
+# s + t <= 1}: exact for polynomials of degree <= 6 there.
+def _triangle_rule():
+    g, w = np.polynomial.legendre.leggauss(4)
+    g, w = 0.5 * (g + 1.0), 0.5 * w
+    pts, wts = [], []
+    for a, wa in zip(g, w):
+        for b, wb in zip(g, w):
+            pts.append((a, b * (1.0 - a)))
+            wts.append(wa * wb * (1.0 - a))
+    return np.array(pts), np.array(wts)
+
+
+TRI_PTS, TRI_W = _triangle_rule()       # weights sum to 1/2, the reference area
+
+
+def boundary_matrix(mesh, faces):
+    """K over all edges for the wall faces `faces` (boolean mask or ids): on each face, at
+    every quadrature point, the six Whitney-1 functions of the face's tet, crossed with the
+    face's unit normal and dotted pairwise.  The tangential trace of an edge function off
+    the face vanishes, so only the face's own three edges carry weight."""
+    fm = np.zeros(mesh.n_faces, dtype=bool)
+    fm[np.asarray(faces)] = True
+    rows, cols, vals = [], [], []
+    for f in np.nonzero(fm)[0]:
+        t = mesh.face_tets[f, 0]
+        k = int(np.nonzero(mesh.tet_faces[t] == f)[0][0])
+        verts = LOCAL_FACES[k]
+        p = mesh.xyz[mesh.faces[f]]
+        N = np.cross(p[1] - p[0], p[2] - p[0])
+        jac = np.linalg.norm(N)                     # twice the area
+        n = N / jac
+        lam = np.zeros((len(TRI_W), 4))
+        lam[:, verts[0]] = 1.0 - TRI_PTS[:, 0] - TRI_PTS[:, 1]
+        lam[:, verts[1]] = TRI_PTS[:, 0]
+        lam[:, verts[2]] = TRI_PTS[:, 1]
+        W = whitney1(lam, mesh.grad_lambda[t][None])          # [q, 6, 3]
+        nW = np.cross(n, W)
+        Ke = jac * np.einsum("q,qid,qjd->ij", TRI_W, nW, nW)
+        ge = mesh.tet_edges[t]
+        rows.append(np.repeat(ge, 6))
+        cols.append(np.tile(ge, 6))
+        vals.append(Ke.ravel())
+    if not rows:
+        return sp.csr_matrix((mesh.n_edges, mesh.n_edges))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(mesh.n_edges, mesh.n_edges))

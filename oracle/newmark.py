@@ -16,6 +16,18 @@ case, with misprinted coefficients):
 Boundary (PEC, eq. (dirichlet) with Psi_D = 0): tangential E vanishes, so boundary edge
 unknowns are 0 and the system is solved on interior edges only.
 
+First-order absorbing faces (eq. (impedanceBC) with Psi_I = 0, differentiated in time and
+combined with Faraday's law, Sec. II-A): the boundary term of the weak curl-curl form
+becomes a damping term C d_t e, C = Y K with Y = 1 / (mu0 c) the admittance of free space
+and K the boundary matrix (oracle/fem.py), and the edges on those faces become unknowns.
+The Newmark recurrence of M e'' + C e' + S e = f (velocity term weighted by gamma):
+  (M + gamma dt C + beta dt^2 S) e^{n+1} = (2M - (1 - 2 gamma) dt C - (1/2 - 2 beta + gamma)
+        dt^2 S) e^n + (-M + (1 - gamma) dt C - (1/2 + beta - gamma) dt^2 S) e^{n-1} - ...
+At beta = 1/4, gamma = 1/2 and with no source the energy E^{n+1/2} = 1/2 |e^{n+1} - e^n|_M^2
+/ dt^2 + 1/2 |(e^{n+1} + e^n) / 2|_S^2 drops by exactly (e^{n+1} - e^{n-1})^T C (e^{n+1} -
+e^{n-1}) / (4 dt) per step.  D^T C vanishes on interior nodes (an edge on a wall face has
+both ends on the wall), so the Gauss identities there are untouched.
+
 Faraday (eq. (faraday)) advances the face fluxes: b^{n+1} = b^n - dt C (gamma e^{n+1} +
 (1 - gamma) e^n); for gamma = 1/2 this is the trapezoid rule.  D2 C = 0 keeps D2 b fixed.
 """
@@ -25,12 +37,23 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def newmark_operators(M, S, dt, beta, gamma):
-    """(A, B1, B2) with A e^{n+1} = B1 e^n + B2 e^{n-1} - Delta^2 G."""
-    A = (M + (beta * dt * dt) * S).tocsr()
-    B1 = (2.0 * M - ((0.5 - 2.0 * beta + gamma) * dt * dt) * S).tocsr()
-    B2 = (-M - ((0.5 + beta - gamma) * dt * dt) * S).tocsr()
-    return A, B1, B2
+def newmark_operators(M, S, dt, beta, gamma, Cd=None):
+    """(A, B1, B2) with A e^{n+1} = B1 e^n + B2 e^{n-1} - Delta^2 G; Cd the damping matrix
+    of absorbing faces (None: PEC only)."""
+    A = M + (beta * dt * dt) * S
+    B1 = 2.0 * M - ((0.5 - 2.0 * beta + gamma) * dt * dt) * S
+    B2 = -M - ((0.5 + beta - gamma) * dt * dt) * S
+    if Cd is not None:
+        A = A + (gamma * dt) * Cd
+        B1 = B1 - ((1.0 - 2.0 * gamma) * dt) * Cd
+        B2 = B2 + ((1.0 - gamma) * dt) * Cd
+    return A.tocsr(), B1.tocsr(), B2.tocsr()
+
+
+def damped_energy(M, S, e_np1, e_n, dt):
+    """E^{n+1/2} = 1/2 |e^{n+1} - e^n|_M^2 / dt^2 + 1/2 |(e^{n+1} + e^n) / 2|_S^2."""
+    d, a = e_np1 - e_n, 0.5 * (e_np1 + e_n)
+    return 0.5 * float(d @ (M @ d)) / (dt * dt) + 0.5 * float(a @ (S @ a))
 
 
 def restrict(Mat, idx):

@@ -20,6 +20,7 @@ import scipy.sparse.linalg as spla
 from . import ab
 from . import diagnostics as dg_
 from . import fem, mfem, newmark
+from .constants import C_LIGHT, MU0
 from .mesh import Mesh
 from .particles import CMesh, push
 
@@ -36,12 +37,15 @@ class Species:
 
 class OracleSim:
     def __init__(self, xyz, tets, cg_tol=1e-10, cg_maxit=10000, crossing_cap=64, pusher="boris", ab_order=4,
-                 field_solver="wave"):
+                 field_solver="wave", abc_faces=None):
         """pusher: "boris" (relativistic Boris, straight paths; u = gamma v at t_{n-1/2}) or
         "ab" (the Adams-Bashforth pusher of Sec. III-B of order ab_order with its curved
         paths; u = v at t_n).  field_solver: "wave" (the Newmark wave equation for e, b by
-        Faraday), "nm_mfem" or "bd_mfem" (the mixed system, oracle/mfem.py)."""
+        Faraday), "nm_mfem" or "bd_mfem" (the mixed system, oracle/mfem.py).
+        abc_faces: wall faces that absorb (first-order condition, oracle/newmark.py), as
+        face ids or "all"; the others stay PEC (wave update only)."""
         assert field_solver in ("wave", "nm_mfem", "bd_mfem")
+        assert abc_faces is None or field_solver == "wave"
         self.pusher, self.ab_order, self.field_solver = pusher, ab_order, field_solver
         self.mesh = m = Mesh(xyz, tets)
         self.cmesh = CMesh(m)
@@ -50,6 +54,17 @@ class OracleSim:
         self.S = fem.curlcurl_matrix(m)
         self.D, self.C, self.D2 = m.D(), m.C(), m.D2()
         self.ie, self.inode = m.interior_edges, m.interior_nodes
+        self.Kd = None
+        if abc_faces is not None:
+            abc = m.boundary_face.copy() if isinstance(abc_faces, str) and abc_faces == "all" else \
+                np.isin(np.arange(m.n_faces), np.asarray(abc_faces))
+            assert not np.any(abc & ~m.boundary_face), "absorbing faces must be wall faces"
+            pec = m.boundary_face & ~abc
+            fixed = np.zeros(m.n_edges, dtype=bool)
+            fixed[m.face_edges[pec].ravel()] = True
+            self.ie = np.nonzero(~fixed)[0]                  # the unknown edges
+            self.K = fem.boundary_matrix(m, abc)
+            self.Kd = newmark.restrict(self.K / (MU0 * C_LIGHT), self.ie)
         self.Mi = newmark.restrict(self.M, self.ie)
         self.Si = newmark.restrict(self.S, self.ie)
         ne, nf = m.n_edges, m.n_faces
@@ -129,7 +144,7 @@ class OracleSim:
     def operators(self, dt, beta, gamma):
         key = (dt, beta, gamma)
         if key != self._ops_key:
-            self._ops = newmark.newmark_operators(self.Mi, self.Si, dt, beta, gamma)
+            self._ops = newmark.newmark_operators(self.Mi, self.Si, dt, beta, gamma, self.Kd)
             self._ops_key = key
         return self._ops
 
