@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define FEPIC_ABI_VERSION 7
+#define FEPIC_ABI_VERSION 8
 
 enum {
     FEPIC_OK = 0,
@@ -161,6 +161,18 @@ typedef struct {
     int pusher;            /* FEPIC_PUSHER_* (default FEPIC_PUSHER_BORIS)                 */
     int ab_order;          /* FEPIC_PUSHER_AB: order 1..5 (default 4)                     */
     int field_solver;      /* FEPIC_FIELD_* (default FEPIC_FIELD_WAVE)                    */
+    int deterministic;     /* 1: bitwise reproducible steps.  Current and charge are summed
+                              as 128-bit fixed-point integers (order-independent; each term
+                              truncated to 2^-64 of the power of two above the largest
+                              |q w|), the particle step always walks in place, and the PCG
+                              dots use one workgroup per partial slot.  Needs
+                              FEPIC_PC_JACOBI, FEPIC_SOLVE_FP64 and a warm start other than
+                              FEPIC_WS_MLP (FEPIC_E_ARG at create; the setters refuse to
+                              leave them with FEPIC_E_STATE).  The state after a step
+                              (fields, charge, current, each particle by id) and the
+                              integer step stats repeat bit for bit; the floating-point
+                              conservation and energy diagnostics are still summed in any
+                              order.  Default 0.                                           */
 } fepic_options;
 
 typedef struct {
@@ -208,8 +220,9 @@ int fepic_destroy(fepic_ctx* ctx);
 int fepic_set_allocator(fepic_ctx* ctx, void* (*alloc)(size_t bytes, void* user), void (*free_)(void* ptr, void* user),
                         void* user);
 /* Selects the preconditioner of later Newmark solves (FEPIC_PC_*; FEPIC_E_ARG for any
- * other value, and for FEPIC_PC_JACOBI while the solve is FEPIC_SOLVE_MIXED).  Results
- * agree to the solver tolerance either way. */
+ * other value, and for FEPIC_PC_JACOBI while the solve is FEPIC_SOLVE_MIXED;
+ * FEPIC_E_STATE for FEPIC_PC_AUX with absorbing faces or in the deterministic mode).
+ * Results agree to the solver tolerance either way. */
 int fepic_set_preconditioner(fepic_ctx* ctx, int pc);
 /* Selects the arithmetic of later Newmark solves (FEPIC_SOLVE_*; FEPIC_E_ARG for any other
  * value, and for FEPIC_SOLVE_MIXED with the Jacobi preconditioner). */
@@ -241,13 +254,33 @@ int fepic_get_topology_sizes(fepic_ctx* ctx, int64_t* n_edges, int64_t* n_faces,
  * face k, -1 on the wall). */
 int fepic_get_topology(fepic_ctx* ctx, int32_t* tets_sorted, int32_t* edges, int32_t* faces, int32_t* tet_edges,
                        int32_t* tet_faces, int32_t* nbr);
-/* Assembled matrix which = 0 (M) or 1 (S) restricted to interior edges, as COO over
- * global edge ids.  With row == NULL only *nnz is returned.  cap = capacity of the arrays. */
+/* Assembled matrix which = 0 (M), 1 (S) or 2 (K, the boundary matrix of the absorbing
+ * faces; FEPIC_E_STATE before fepic_set_absorbing_faces) restricted to the unknown edges
+ * (all but those on a PEC wall face), as COO over global edge ids.  With row == NULL only
+ * *nnz is returned.  cap = capacity of the arrays. */
 int fepic_get_matrix(fepic_ctx* ctx, int which, int64_t cap, int64_t* nnz, int64_t* row, int64_t* col, double* val);
 
+/* First-order absorbing boundary (Sec. II-A, eq. (impedanceBC) with Psi_I = 0 and Y the
+ * admittance of free space 1 / (mu0 c); the surface impedance matrix of Sec. II-A):
+ * marks wall faces as absorbing instead of PEC.  faces: n canonical face ids (as
+ * fepic_get_topology numbers them), each a wall face; NULL = every wall face (n ignored).
+ * The tangential field on absorbing faces becomes unknown: edges on them join the solve,
+ * and the wave-equation update gains the damping matrix C = Y K, K_ij = the integral over
+ * the absorbing faces of (n x W_i) . (n x W_j), in the Newmark recurrence
+ *   (M + gamma dt C + beta dt^2 S) e^{n+1} = (2M - (1 - 2 gamma) dt C - (1/2 - 2 beta
+ *   + gamma) dt^2 S) e^n - (M - (1 - gamma) dt C + (1/2 + beta - gamma) dt^2 S) e^{n-1}
+ *   - (G^{n+1} - 2 G^n + G^{n-1}).
+ * Particles still leave the domain through any wall face.  Only before the first step and
+ * once per context; only with FEPIC_FIELD_WAVE, FEPIC_PC_JACOBI and FEPIC_SOLVE_FP64
+ * (FEPIC_E_STATE otherwise; later requests for another field update or preconditioner are
+ * refused the same way); FEPIC_E_ARG for an id that is not a wall face.  Fields set
+ * before the call keep their values.  Works on a host-only context too (assembly only).
+ * Checkpoints do not record the absorbing faces: restore into a context set up alike. */
+int fepic_set_absorbing_faces(fepic_ctx* ctx, int64_t n, const int32_t* faces);
+
 /* ---------------------------------------------------------------- fields
- * e, e_prev: [n_edges] edge unknowns at t_n and t_{n-1} (boundary entries ignored, held
- * at 0); b: [n_faces] face fluxes at t_n.  Any may be NULL (left unchanged). */
+ * e, e_prev: [n_edges] edge unknowns at t_n and t_{n-1} (entries of edges on PEC wall
+ * faces ignored, held at 0); b: [n_faces] face fluxes at t_n.  Any may be NULL (left unchanged). */
 int fepic_set_fields(fepic_ctx* ctx, const double* e, const double* e_prev, const double* b);
 /* b_f = B0 . (area vector of f): the exact Whitney-2 interpolant of a uniform field. */
 int fepic_set_uniform_B(fepic_ctx* ctx, const double B0[3]);
@@ -380,8 +413,11 @@ typedef struct {
     int64_t n_train_rows, n_val_rows, n_steps;
     float ms_total;
 } fepic_train_stats;
-/* on != 0: each later fepic_step appends (features, target) of its interior edges to a
- * device buffer holding up to max_snapshots steps (oldest dropped first). */
+/* on = k >= 1: each later fepic_step appends (features, target) of one interior edge in k
+ * (rows r0, r0 + k, ... with r0 = snapshot count mod k, so successive snapshots sample
+ * different edges; k = 1 records every interior edge) to a device buffer holding up to
+ * max_snapshots steps (oldest dropped first); a new k or max_snapshots starts the buffer
+ * afresh.  on = 0 stops recording.  FEPIC_E_ARG for k above the interior edge count. */
 int fepic_ws_record(fepic_ctx* ctx, int on, int64_t max_snapshots);
 int fepic_ws_num_snapshots(fepic_ctx* ctx, int64_t* n);
 int fepic_ws_train(fepic_ctx* ctx, const fepic_train_opts* opts, fepic_train_stats* out);

@@ -259,10 +259,35 @@ int sync_counts(fepic_ctx* c) {
     return FEPIC_OK;
 }
 
+// Deterministic mode: the accumulators (2 words per edge or node, cleared), and the unit of
+// the fixed-point sums: the power of two at or above the largest |q w| (a piece's current
+// on an edge and a particle's charge on a node are at most |q w|).
+unsigned long long* fix_buffer(fepic_ctx* c) {
+    if (!c->opt.deterministic) return nullptr;
+    if (!c->d_fix) {
+        const int64_t n = 2 * std::max(c->mesh.n_edges, c->mesh.n_nodes);
+        c->d_fix = dalloc<unsigned long long>(c, n);
+        if (!c->d_fix) return nullptr;
+        launch_fill(c->stream, reinterpret_cast<double*>(c->d_fix), n, 0.0);   // all-zero bits
+    }
+    return c->d_fix;
+}
+
+double fix_scale(const fepic_ctx* c) {
+    double q = 0.0;
+    for (const auto& s : c->species) q = std::max(q, std::fabs(s.q * s.w));
+    if (!(q > 0.0)) return 1.0;
+    return std::ldexp(1.0, std::ilogb(q) + 1);
+}
+
 template <typename T>
 void compute_rho_T(fepic_ctx* c, double* rho) {
-    launch_fill(c->stream, rho, c->mesh.n_nodes, 0.0);
-    for (auto& s : c->species) launch_rho<T>(c->stream, parr<T>(s, s.cur), s.n, c->d_tets, s.q * s.w, rho);
+    unsigned long long* fix = fix_buffer(c);
+    const double scale = fix_scale(c);
+    if (!fix) launch_fill(c->stream, rho, c->mesh.n_nodes, 0.0);
+    for (auto& s : c->species)
+        launch_rho<T>(c->stream, parr<T>(s, s.cur), s.n, c->d_tets, s.q * s.w, rho, fix, 1.0 / scale);
+    if (fix) launch_fix_out(c->stream, fix, c->mesh.n_nodes, scale, rho);
 }
 
 void compute_rho(fepic_ctx* c, double* rho) {
@@ -399,6 +424,12 @@ void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
         c->deferred_err = FEPIC_E_OOM;
         return;
     }
+    unsigned long long* fix = fix_buffer(c);
+    if (c->opt.deterministic && !fix) {
+        c->deferred_err = FEPIC_E_OOM;
+        return;
+    }
+    const double scale = fix_scale(c);
     for (auto& s : c->species) {
         if (s.n == 0) continue;
         PushParams pp;
@@ -406,6 +437,8 @@ void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
         pp.qm_half_dt = s.q * dt / (2.0 * s.m);
         pp.qw = s.q * s.w;
         pp.cap = c->opt.crossing_cap;
+        pp.fix = fix;
+        pp.fix_inv = 1.0 / scale;
         hipEvent_t* ev = timer_pair(c, FAM_PUSH);
         if (ev) (void)hipEventRecord(ev[0], c->stream);
         launch_push<T>(c->stream, parr<T>(s, s.cur), parr<T>(s, 1 - s.cur), s.n, (const TetBlock<T>*)c->d_blk,
@@ -413,6 +446,7 @@ void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
                        c->cross_share, c->opt.walk);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
+    if (fix) launch_fix_out(c->stream, fix, c->mesh.n_edges, scale, c->d_dgn);
     launch_cnt_finish(c->stream, c->d_cnt_slots, c->d_cnt);
     ev_mark(c, 3);
 }
@@ -486,6 +520,14 @@ void particle_phase_ab(fepic_ctx* c, double dt, bool do_sort) {
     ap.dt = dt;
     ap.k = c->opt.ab_order;
     ap.cap = c->opt.crossing_cap;
+    unsigned long long* fix = fix_buffer(c);
+    if (c->opt.deterministic && !fix) {
+        c->deferred_err = FEPIC_E_OOM;
+        return;
+    }
+    const double scale = fix_scale(c);
+    ap.fix = fix;
+    ap.fix_inv = 1.0 / scale;
     for (auto& s : c->species) {
         if (s.n == 0) continue;
         ap.qm = s.q / s.m;
@@ -497,6 +539,7 @@ void particle_phase_ab(fepic_ctx* c, double dt, bool do_sort) {
                        s.d_abm[1 - s.abm_cur], c->d_dgn, ap, c->d_cnt_slots, s.sorted_pending ? s.d_nlive : nullptr);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
+    if (fix) launch_fix_out(c->stream, fix, c->mesh.n_edges, scale, c->d_dgn);
     launch_cnt_finish(c->stream, c->d_cnt_slots, c->d_cnt);
     ev_mark(c, 3);
 }
@@ -507,14 +550,20 @@ void particle_phase(fepic_ctx* c, double dt, bool do_sort) {
     else particle_phase_T<float>(c, dt, do_sort);
 }
 
-void ensure_operator(fepic_ctx* c, double dt, double beta) {
-    const double cA = beta * dt * dt;
+// Admittance of free space, 1 / (mu0 c): the first-order absorbing condition's damping
+// matrix is this times the boundary matrix K.
+constexpr double kY0 = 1.0 / (kMu0 * kC);
+
+void ensure_operator(fepic_ctx* c, double dt, double beta, double gamma = 0.5) {
+    const double cA = beta * dt * dt, cK = c->abc_on ? gamma * dt * kY0 : 0.0;
     c->aux.n_far = c->opt.aux_far_levels >= 0 ? std::min(c->opt.aux_far_levels, kAuxFarLevels)
                                               : aux_far_auto(cA * c->s_over_m, c->aux.n_aux);
-    if (c->A_scale == cA && c->A_valid) return;
-    launch_scale_A(c->stream, c->mesh.mat, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_A, c->d_dinv, c->d_bedge, cA);
+    if (c->A_scale == cA && c->A_scale_K == cK && c->A_valid) return;
+    launch_scale_A(c->stream, c->mesh.mat, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_A, c->d_dinv, c->d_bedge, cA,
+                   c->abc_on ? c->d_K : nullptr, cK);
     launch_aux_scale(c->stream, c->aux, c->d_sp, c->d_col, c->d_A);
     c->A_scale = cA;
+    c->A_scale_K = cK;
     c->A_valid = true;
     c->A32_valid = false;
 }
@@ -683,7 +732,7 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
         if (rc != FEPIC_OK) return rc;
     }
     // the mixed updates solve with the wave operator's form: M + dt^2/4 S (NM), M + dt^2 S (BD)
-    ensure_operator(c, dt, fs == FEPIC_FIELD_NM_MFEM ? 0.25 : fs == FEPIC_FIELD_BD_MFEM ? 1.0 : beta);
+    ensure_operator(c, dt, fs == FEPIC_FIELD_NM_MFEM ? 0.25 : fs == FEPIC_FIELD_BD_MFEM ? 1.0 : beta, gamma);
     ev_mark(c, 4);
     {
         hipEvent_t* ev = timer_pair(c, FAM_RHS);
@@ -699,7 +748,9 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
                             c->d_ef_inc, c->d_h, dt, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0, c->d_rhs, c->d_partial);
         else
             launch_rhs(c->stream, ne, c->d_sp, c->d_col, c->d_M, c->d_S, c->d_e, c->d_ep, c->d_dgn, c->d_dg,
-                       c->d_bedge, dt * dt, 0.5 - 2.0 * beta + gamma, 0.5 + beta - gamma, c->d_rhs, c->d_partial);
+                       c->d_bedge, dt * dt, 0.5 - 2.0 * beta + gamma, 0.5 + beta - gamma,
+                       c->abc_on ? c->d_K : nullptr, -(1.0 - 2.0 * gamma) * dt * kY0, (1.0 - gamma) * dt * kY0,
+                       c->d_rhs, c->d_partial);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
     ev_mark(c, 5);
@@ -738,7 +789,7 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
                             c->d_rq, c->d_partial, c->d_sc, c->opt.cg_tol);
         else
             launch_cg_init(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_rhs, c->d_x, V[0], c->d_partial,
-                           c->d_sc, c->opt.cg_tol);
+                           c->d_sc, c->opt.cg_tol, c->opt.deterministic != 0);
     };
     auto true_resid = [&]() -> int {
         launch_cg_resid(c->stream, ne, c->d_sp, c->d_col, c->d_A, c->d_rhs, c->d_x, c->d_rt, c->d_partial, c->d_sc);
@@ -863,7 +914,7 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
                                     c->d_rq, c->d_partial, c->d_sc);
                 else
                     launch_cg_iter(c->stream, i, ne, c->d_sp, c->d_col, c->d_A, c->d_dinv, c->d_x, V, c->d_partial,
-                                   c->d_sc);
+                                   c->d_sc, c->opt.deterministic != 0);
             });
             if (rc != FEPIC_OK) return rc;
             if (restart == 0) rr0_first = c->h_sc->rr0;
@@ -1291,6 +1342,7 @@ void fepic_default_options(fepic_options* o) {
     o->pusher = FEPIC_PUSHER_BORIS;
     o->ab_order = 4;
     o->field_solver = FEPIC_FIELD_WAVE;
+    o->deterministic = 0;
 }
 
 const char* fepic_error_string(int code) {
@@ -1330,6 +1382,10 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
     if (o.ab_order < 1 || o.ab_order > kAbMax) return FEPIC_E_ARG;
     if (o.pusher == FEPIC_PUSHER_AB && o.precision != FEPIC_ALL_FP64) return FEPIC_E_ARG;
     if (o.field_solver < FEPIC_FIELD_WAVE || o.field_solver > FEPIC_FIELD_BD_MFEM) return FEPIC_E_ARG;
+    if (o.deterministic != 0 && o.deterministic != 1) return FEPIC_E_ARG;
+    if (o.deterministic && (o.preconditioner != FEPIC_PC_JACOBI || o.solve_precision != FEPIC_SOLVE_FP64 ||
+                            o.warm_start == FEPIC_WS_MLP))
+        return FEPIC_E_ARG;
     if (o.cg_check_every < 1) o.cg_check_every = 8;
     fepic_ctx* c = new fepic_ctx();
     c->opt = o;
@@ -1398,6 +1454,10 @@ int fepic_set_preconditioner(fepic_ctx* c, int pc) {
     if (!c || (pc != FEPIC_PC_JACOBI && pc != FEPIC_PC_AUX)) return FEPIC_E_ARG;
     if (pc == FEPIC_PC_JACOBI && c->opt.solve_precision == FEPIC_SOLVE_MIXED)
         return fail(c, FEPIC_E_ARG, "the mixed-precision solve needs the auxiliary-space preconditioner");
+    if (pc == FEPIC_PC_AUX && c->abc_on)
+        return fail(c, FEPIC_E_STATE, "absorbing faces need the Jacobi preconditioner");
+    if (pc == FEPIC_PC_AUX && c->opt.deterministic)
+        return fail(c, FEPIC_E_STATE, "the deterministic mode needs the Jacobi preconditioner");
     if (c->opt.preconditioner != pc) c->last_cg_iters = 0;   // batch sizing starts afresh
     c->opt.preconditioner = pc;
     return FEPIC_OK;
@@ -1418,8 +1478,77 @@ int fepic_set_solve_precision(fepic_ctx* c, int sp) {
 int fepic_set_field_solver(fepic_ctx* c, int solver) {
     if (!c) return FEPIC_E_ARG;
     if (solver < FEPIC_FIELD_WAVE || solver > FEPIC_FIELD_BD_MFEM) return fail(c, FEPIC_E_ARG, "bad field solver");
+    if (solver != FEPIC_FIELD_WAVE && c->abc_on)
+        return fail(c, FEPIC_E_STATE, "absorbing faces work with the wave-equation update only");
     if (solver != c->opt.field_solver) c->rG_levels = 0;   // the Gauss recurrence changes with it
     c->opt.field_solver = solver;
+    return FEPIC_OK;
+}
+
+int fepic_set_absorbing_faces(fepic_ctx* c, int64_t n, const int32_t* faces) {
+    if (!c) return FEPIC_E_ARG;
+    if (!c->have_mesh) return fail(c, FEPIC_E_STATE, "no mesh uploaded");
+    if (c->abc_on) return fail(c, FEPIC_E_STATE, "absorbing faces already set");
+    if (c->step_count > 0) return fail(c, FEPIC_E_STATE, "absorbing faces are set before the first step");
+    if (c->opt.field_solver != FEPIC_FIELD_WAVE)
+        return fail(c, FEPIC_E_STATE, "absorbing faces work with the wave-equation update only");
+    if (c->opt.preconditioner != FEPIC_PC_JACOBI || c->opt.solve_precision != FEPIC_SOLVE_FP64)
+        return fail(c, FEPIC_E_STATE, "absorbing faces need the Jacobi preconditioner and the FP64 solve");
+    HostMesh& m = c->mesh;
+    // a face is on the wall when its tet instance has no neighbour across it
+    std::vector<uint8_t> wall(m.n_faces, 0);
+    for (int64_t j = 0; j < 4 * m.n_tets; ++j)
+        if (m.nbr[j] < 0) wall[m.tet_faces[j]] = 1;
+    std::vector<uint8_t> abc(m.n_faces, 0);
+    if (!faces) {
+        abc = wall;
+    } else {
+        if (n <= 0) return fail(c, FEPIC_E_ARG, "no faces given");
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t f = faces[i];
+            if (f < 0 || f >= m.n_faces || !wall[f])
+                return fail(c, FEPIC_E_ARG, "face " + std::to_string(f) + " is not a wall face");
+            abc[f] = 1;
+        }
+    }
+    // fixed edges: those on a PEC (non-absorbing) wall face
+    std::vector<uint8_t> fixed(m.n_edges, 0);
+    for (int64_t f = 0; f < m.n_faces; ++f)
+        if (wall[f] && !abc[f])
+            for (int j = 0; j < 3; ++j) fixed[m.dev_face_edges[3 * f + j]] = 1;
+    HostMesh trial = m;   // assemble aside: on failure the context keeps its PEC matrices
+    int rc = assemble_edge_matrices(trial, fixed, abc, c->err);
+    if (rc != FEPIC_OK) return rc;
+    if (!c->host_only) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        int64_t* sp = nullptr;
+        int32_t* col = nullptr;
+        uint8_t* fx = nullptr;
+        double *M = nullptr, *S = nullptr, *K = nullptr, *A = nullptr;
+        const int64_t nnz = trial.mat.slice_ptr.back();
+        if ((rc = upload(c, &sp, trial.mat.slice_ptr)) || (rc = upload(c, &col, trial.mat.col)) ||
+            (rc = upload(c, &M, trial.mat.M)) || (rc = upload(c, &S, trial.mat.S)) || (rc = upload(c, &K, trial.mat.K)) ||
+            (rc = upload(c, &fx, fixed)) || !(A = dalloc<double>(c, nnz))) {
+            for (void* p : {(void*)sp, (void*)col, (void*)M, (void*)S, (void*)K, (void*)fx}) dfree(c, p);
+            return rc ? rc : fail(c, FEPIC_E_OOM, "device allocation failed");
+        }
+        for (void* p : {(void*)c->d_sp, (void*)c->d_col, (void*)c->d_M, (void*)c->d_S, (void*)c->d_A,
+                        (void*)c->d_bedge})
+            dfree(c, p);
+        c->d_sp = sp;
+        c->d_col = col;
+        c->d_M = M;
+        c->d_S = S;
+        c->d_K = K;
+        c->d_A = A;
+        c->d_bedge = fx;
+        c->A_valid = false;
+        c->A32_valid = false;
+    }
+    m.mat = std::move(trial.mat);
+    m.dev_fixed = std::move(fixed);
+    m.abc_face = std::move(abc);
+    c->abc_on = true;
     return FEPIC_OK;
 }
 
@@ -1460,7 +1589,7 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
         for (int d = 0; d < 3; ++d) r0[3 * t + d] = m.xyz[3 * m.tets[4 * t] + d];
     if ((rc = upload(c, &c->d_tets, m.tets)) || (rc = upload(c, &c->d_edges, m.dev_edges)) ||
         (rc = upload(c, &c->d_tet_edges, m.dev_tet_edges)) || (rc = upload(c, &c->d_tet_faces, m.tet_faces)) ||
-        (rc = upload(c, &c->d_face_edges, m.dev_face_edges)) || (rc = upload(c, &c->d_bedge, m.dev_bedge)) ||
+        (rc = upload(c, &c->d_face_edges, m.dev_face_edges)) || (rc = upload(c, &c->d_bedge, m.dev_fixed)) ||
         (rc = upload(c, &c->d_inode, inode)) || (rc = upload(c, &c->d_grad64, m.grad)) ||
         (rc = upload(c, &c->d_r0, r0)) || (rc = upload(c, &c->d_sp, m.mat.slice_ptr)) ||
         (rc = upload(c, &c->d_col, m.mat.col)) || (rc = upload(c, &c->d_M, m.mat.M)) ||
@@ -1511,7 +1640,7 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
         double sum = 0.0;
         int64_t cnt = 0;
         for (int64_t r = 0; r < ne; ++r) {
-            if (m.dev_bedge[r]) continue;
+            if (m.dev_fixed[r]) continue;
             const int64_t k = m.mat.slice_ptr[r / kSell] + r % kSell;   // the diagonal slot
             if (m.mat.M[k] > 0) {
                 sum += m.mat.S[k] / m.mat.M[k];
@@ -1611,17 +1740,18 @@ int fepic_get_topology(fepic_ctx* c, int32_t* tets_sorted, int32_t* edges, int32
 }
 
 int fepic_get_matrix(fepic_ctx* c, int which, int64_t cap, int64_t* nnz, int64_t* row, int64_t* col, double* val) {
-    if (!c || !nnz || (which != 0 && which != 1)) return FEPIC_E_ARG;
+    if (!c || !nnz || which < 0 || which > 2) return FEPIC_E_ARG;
     if (!c->have_mesh) return fail(c, FEPIC_E_STATE, "no mesh uploaded");
     const HostMesh& m = c->mesh;
     const SellMatrix& A = m.mat;
-    const std::vector<double>& v = which == 0 ? A.M : A.S;
+    if (which == 2 && A.K.empty()) return fail(c, FEPIC_E_STATE, "no absorbing faces set");
+    const std::vector<double>& v = which == 0 ? A.M : which == 1 ? A.S : A.K;
     int64_t n = 0;
     for (int64_t s = 0; s < A.n_slices; ++s) {
         const int64_t w = (A.slice_ptr[s + 1] - A.slice_ptr[s]) / kSell;
         for (int l = 0; l < kSell; ++l) {
             const int64_t r = s * kSell + l;
-            if (r >= A.n_rows || m.dev_bedge[r]) continue;
+            if (r >= A.n_rows || m.dev_fixed[r]) continue;
             for (int64_t k = 0; k < w; ++k) {
                 const int64_t p = A.slice_ptr[s] + k * kSell + l;
                 if (k > 0 && A.col[p] == r) continue;  // padding
@@ -1643,7 +1773,7 @@ int fepic_set_fields(fepic_ctx* c, const double* e, const double* e_prev, const 
     const HostMesh& m = c->mesh;
     auto put_e = [&](double* dst, const double* src) -> int {
         std::vector<double> v(m.n_edges);
-        for (int64_t i = 0; i < m.n_edges; ++i) v[m.eperm[i]] = m.bedge[i] ? 0.0 : src[i];
+        for (int64_t i = 0; i < m.n_edges; ++i) v[m.eperm[i]] = m.dev_fixed[m.eperm[i]] ? 0.0 : src[i];
         HIPCHK(c, hipMemcpy(dst, v.data(), sizeof(double) * m.n_edges, hipMemcpyHostToDevice));
         return FEPIC_OK;
     };

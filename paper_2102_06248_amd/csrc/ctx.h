@@ -84,7 +84,13 @@ struct fepic_ctx {
     int32_t *d_cell_start = nullptr, *d_cell_tets = nullptr, *d_grid_n = nullptr;
     double* d_grid = nullptr;  // lo[3], inv_h[3]
     double* d_live = nullptr;   // one double: live-particle count of fepic_num_particles
-    double A_scale = -1.0;
+    double A_scale = -1.0, A_scale_K = 0.0;
+    // deterministic mode: fixed-point accumulators, two words per edge or node (kept
+    // cleared between uses), allocated on first use
+    unsigned long long* d_fix = nullptr;
+    // first-order absorbing faces: their boundary matrix K in the pattern of M and S
+    double* d_K = nullptr;
+    bool abc_on = false;
     double s_over_m = 0.0;   // mean of S_jj / M_jj over interior rows (chooses the far levels)
     bool A_valid = false;
 

@@ -67,6 +67,10 @@ struct PushParams {
     double qm_half_dt;   // q dt / (2 m)
     double qw;           // q w (deposit scale)
     int cap;             // crossing cap
+    // deterministic mode: currents go to fixed-point accumulators (fixed_point.h) in units
+    // of 1 / fix_inv instead of the FP64 vector; nullptr otherwise
+    unsigned long long* fix = nullptr;
+    double fix_inv = 0.0;
 };
 
 // The particle kernel adds its per-workgroup counts into kCntSlots copies of the counters
@@ -89,6 +93,8 @@ __host__ __device__ constexpr int ab_meta(int held, int head) { return held | (h
 struct AbParams {
     double dt, qm, qw;
     int k, cap;
+    unsigned long long* fix = nullptr;    // deterministic mode, as in PushParams
+    double fix_inv = 0.0;
     double beta[kAbMax][kAbMax];          // beta[m - 1][j]: the order-m coefficients
     double gl_x[kAbMax + 2][kAbMax + 2];  // row n: the n Gauss-Legendre nodes on [-1, 1]
     double gl_w[kAbMax + 2][kAbMax + 2];  // and weights
@@ -194,6 +200,7 @@ struct SellMatrix {
     std::vector<int64_t> slice_ptr;  // [n_slices + 1], element offsets
     std::vector<int32_t> col;        // padded entries point at the row itself, value 0
     std::vector<double> M, S;        // edge mass and curl-curl values
+    std::vector<double> K;           // boundary matrix of absorbing faces (empty: none)
 };
 
 // ----------------------------------------------------------------------------- launchers
@@ -234,8 +241,13 @@ struct AbHistIo {
 template <typename T>
 void launch_sort(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, int64_t n_tets, int32_t* count,
                  int32_t* offset, int32_t* block_sums, int32_t* n_live_dev, AbHistIo ab = AbHistIo());
+// rho += q w lambda per particle (FP64 atomics), or with fix into fixed-point accumulators
+// in units of 1 / fix_inv (deterministic mode; rho untouched).
 template <typename T>
-void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, double qw, double* rho);
+void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, double qw, double* rho,
+                unsigned long long* fix = nullptr, double fix_inv = 0.0);
+// out[i] = accumulator i times scale, and the accumulators cleared (fixed_point.h).
+void launch_fix_out(hipStream_t s, unsigned long long* acc, int64_t n, double scale, double* out);
 void launch_magnetic(hipStream_t s, int64_t n_tets, const double* b, const double* grad64, const int32_t* tet_faces,
                      double* out);
 template <typename T>
@@ -253,19 +265,23 @@ void launch_fill_i32(hipStream_t s, int32_t* x, int64_t n, int32_t v);
 void launch_fill(hipStream_t s, double* x, int64_t n, double v);
 void launch_axpby(hipStream_t s, double* y, const double* a, double alpha, const double* b, double beta, int64_t n);
 void launch_scale_A(hipStream_t s, const SellMatrix& shape, const int64_t* slice_ptr, const int32_t* col,
-                    const double* M, const double* S, double* A, double* dinv, const uint8_t* bmask, double c);
+                    const double* M, const double* S, double* A, double* dinv, const uint8_t* bmask, double c,
+                    const double* K = nullptr, double cK = 0.0);
 void launch_sell_spmv(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
                       const double* val, const double* x, double* y);
 void launch_rhs(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* M,
                 const double* S, const double* e, const double* ep, const double* dg_new, const double* dg_old,
-                const uint8_t* bmask, double dt2, double c1, double c2, double* b, double* partial);
+                const uint8_t* bmask, double dt2, double c1, double c2, const double* K, double k1, double k2,
+                double* b, double* partial);
 void launch_warm(hipStream_t s, int mode, int64_t n, const double* e, const double* ep, const double* ep2, double* x);
 void launch_cg_init(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col, const double* A,
                     const double* dinv, const double* b, const double* x, CgVec* v, double* partial, CgScalars* sc,
-                    double tol);
+                    double tol, bool det = false);
+// det: at most one workgroup per dot slot, so every slot takes a single add and the dots
+// do not depend on the order of the workgroups (deterministic mode).
 void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* slice_ptr, const int32_t* col,
                     const double* A, const double* dinv, double* x, CgVec* const v[2], double* partial,
-                    CgScalars* sc);
+                    CgScalars* sc, bool det = false);
 void launch_cg_rr0(hipStream_t s, int64_t n_rows, double* partial, CgScalars* sc);
 // PCG with the nodal auxiliary-space preconditioner: per row z = B r with the previous
 // search direction p (zp, double buffered), and r and q = A p as two arrays of n_rows
@@ -318,14 +334,17 @@ void launch_line_start(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, 
 
 // Learned warm start (kernels_mlp.hip).
 void mlp_launch_rms(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e, const double* dg,
-                    double* scales);
+                    double* part, double* scales);
 void mlp_launch_features(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e,
                          const double* ep, const double* ep2, const double* dg, const double* scales, float* X);
 void mlp_launch_forward(hipStream_t s, int64_t n, const float* X, const float* params_f32, float* y);
 void mlp_launch_direction(hipStream_t s, int64_t n_int, const int32_t* int_edges, const float* y,
                           const double* scales, double* d);
-void mlp_launch_target(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e_new,
-                       const double* e, const double* scales, float* t);
+// Training targets of interior edges r0, r0 + stride, ... (n rows); the same rows of a
+// feature array [rows][4] picked into dst.
+void mlp_launch_target(hipStream_t s, int64_t n, int64_t r0, int64_t stride, const int32_t* int_edges,
+                       const double* e_new, const double* e, const double* scales, float* t);
+void mlp_launch_pick(hipStream_t s, const float* X, int64_t r0, int64_t stride, int64_t n, float* dst);
 
 int grid_1d(int64_t n, int block);
 

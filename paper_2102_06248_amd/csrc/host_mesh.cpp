@@ -125,6 +125,177 @@ void build_aux_space(HostMesh& m) {
     }
 }
 
+// The edge matrices over the unknown edges (those not in `fixed`, device order) in SELL-64:
+// M = [*eps0] and S = [curl]^T [*mu0^-1] [curl] element by element in closed form, rows of
+// fixed edges reduced to a unit diagonal; with absorbing faces (abc_face, canonical face
+// ids) also their boundary matrix K in the same pattern.
+int assemble_edge_matrices(HostMesh& m, const std::vector<uint8_t>& fixed, const std::vector<uint8_t>& abc_face,
+                           std::string& err) {
+    const std::vector<int32_t>& TE = m.dev_tet_edges;
+    const std::vector<uint8_t>& BE = fixed;
+    const int64_t n_tets = m.n_tets;
+
+    // ---- assembly pattern (device order): row e couples to the interior edges of every
+    // tet holding e
+    const int64_t ne = m.n_edges;
+    std::vector<int64_t> et_start(ne + 1, 0);
+    for (int64_t j = 0; j < 6 * n_tets; ++j) et_start[TE[j] + 1]++;
+    for (int64_t e = 0; e < ne; ++e) et_start[e + 1] += et_start[e];
+    std::vector<int32_t> et(6 * n_tets);
+    {
+        std::vector<int64_t> pos(et_start.begin(), et_start.end() - 1);
+        for (int64_t j = 0; j < 6 * n_tets; ++j) et[pos[TE[j]]++] = (int32_t)(j / 6);
+    }
+    SellMatrix& A = m.mat;
+    A.n_rows = ne;
+    A.n_slices = (ne + kSell - 1) / kSell;
+    std::vector<int32_t> rlen(A.n_slices * kSell, 0);
+    std::vector<int64_t> rstart(ne + 1, 0);
+    std::vector<int32_t> rcols;
+    rcols.reserve(ne * 17);
+    std::vector<int32_t> tmp;
+    for (int64_t e = 0; e < ne; ++e) {
+        rstart[e] = (int64_t)rcols.size();
+        rcols.push_back((int32_t)e);  // diagonal first
+        if (!BE[e]) {
+            tmp.clear();
+            for (int64_t j = et_start[e]; j < et_start[e + 1]; ++j) {
+                const int t = et[j];
+                for (int i = 0; i < 6; ++i) {
+                    const int32_t c = TE[6 * t + i];
+                    if (c != e && !BE[c]) tmp.push_back(c);
+                }
+            }
+            std::sort(tmp.begin(), tmp.end());
+            tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+            rcols.insert(rcols.end(), tmp.begin(), tmp.end());
+        }
+        rlen[e] = (int32_t)(rcols.size() - rstart[e]);
+    }
+    rstart[ne] = (int64_t)rcols.size();
+    A.slice_ptr.assign(A.n_slices + 1, 0);
+    for (int64_t s = 0; s < A.n_slices; ++s) {
+        int32_t w = 0;
+        for (int l = 0; l < kSell; ++l) w = std::max(w, rlen[s * kSell + l]);
+        A.slice_ptr[s + 1] = A.slice_ptr[s] + (int64_t)w * kSell;
+    }
+    const int64_t total = A.slice_ptr[A.n_slices];
+    A.col.assign(total, 0);
+    A.M.assign(total, 0.0);
+    A.S.assign(total, 0.0);
+    for (int64_t s = 0; s < A.n_slices; ++s) {
+        const int64_t w = (A.slice_ptr[s + 1] - A.slice_ptr[s]) / kSell;
+        for (int l = 0; l < kSell; ++l) {
+            const int64_t r = s * kSell + l;
+            for (int64_t k = 0; k < w; ++k) {
+                int32_t c = 0;
+                if (r < ne) c = (k < rlen[r]) ? rcols[rstart[r] + k] : (int32_t)r;
+                A.col[A.slice_ptr[s] + k * kSell + l] = c;
+            }
+        }
+    }
+    auto slot = [&](int64_t r, int32_t c) -> int64_t {
+        const int64_t s = r / kSell, l = r % kSell;
+        if (c == r) return A.slice_ptr[s] + l;
+        // columns after the diagonal are ascending
+        int64_t lo = 1, hi = rlen[r] - 1;
+        while (lo <= hi) {
+            const int64_t mid = (lo + hi) / 2;
+            const int32_t v = rcols[rstart[r] + mid];
+            if (v == c) return A.slice_ptr[s] + mid * kSell + l;
+            if (v < c) lo = mid + 1; else hi = mid - 1;
+        }
+        return -1;
+    };
+    // element matrices, closed form:
+    //   M_(ab)(cd) = eps0 V/20 [(1+d_ac) g_b.g_d - (1+d_ad) g_b.g_c - (1+d_bc) g_a.g_d + (1+d_bd) g_a.g_c]
+    //   S_(ab)(cd) = 4 V / mu0 (g_a x g_b) . (g_c x g_d)
+    for (int64_t t = 0; t < n_tets; ++t) {
+        double g[4][3];
+        for (int k = 1; k < 4; ++k)
+            for (int d = 0; d < 3; ++d) g[k][d] = m.grad[9 * t + 3 * (k - 1) + d];
+        for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+        double gg[4][4], cr[6][3];
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) gg[a][b] = dot(g[a], g[b]);
+        for (int i = 0; i < 6; ++i) cross(g[kLE[i][0]], g[kLE[i][1]], cr[i]);
+        const double V = m.vol[t];
+        const double mc = kEps0 * V / 20.0, sc = 4.0 * V / kMu0;
+        for (int i = 0; i < 6; ++i) {
+            const int32_t ei = TE[6 * t + i];
+            if (BE[ei]) continue;
+            const int a = kLE[i][0], b = kLE[i][1];
+            for (int j = 0; j < 6; ++j) {
+                const int32_t ej = TE[6 * t + j];
+                if (BE[ej]) continue;
+                const int c = kLE[j][0], d = kLE[j][1];
+                const double Mv = mc * ((1 + (a == c)) * gg[b][d] - (1 + (a == d)) * gg[b][c] -
+                                        (1 + (b == c)) * gg[a][d] + (1 + (b == d)) * gg[a][c]);
+                const double Sv = sc * dot(cr[i], cr[j]);
+                const int64_t p = slot(ei, ej);
+                if (p < 0) {
+                    err = "internal: assembly pattern miss";
+                    return FEPIC_E_MESH;
+                }
+                A.M[p] += Mv;
+                A.S[p] += Sv;
+            }
+        }
+    }
+    // absorbing faces: K = int over the face of (n x W_a) . (n x W_b), the tangential traces
+    // being the triangle's own Whitney functions mu_a grad mu_b - mu_b grad mu_a, with
+    // int mu_i mu_j = A (1 + delta_ij) / 12 and surface gradients grad mu_i = N x (edge
+    // opposite i, taken around the triangle) / |N|^2, N = (p1 - p0) x (p2 - p0)
+    A.K.clear();
+    if (!abc_face.empty()) {
+        A.K.assign(total, 0.0);
+        constexpr int kTE[3][2] = {{0, 1}, {1, 2}, {0, 2}};   // face_edges order: (i,j), (j,k), (i,k)
+        for (int64_t f = 0; f < m.n_faces; ++f) {
+            if (!abc_face[f]) continue;
+            const double* p[3] = {&m.xyz[3 * m.faces[3 * f]], &m.xyz[3 * m.faces[3 * f + 1]],
+                                  &m.xyz[3 * m.faces[3 * f + 2]]};
+            double u[3], v[3], N[3];
+            for (int d = 0; d < 3; ++d) {
+                u[d] = p[1][d] - p[0][d];
+                v[d] = p[2][d] - p[0][d];
+            }
+            cross(u, v, N);
+            const double n2 = dot(N, N), area = 0.5 * std::sqrt(n2);
+            double gm[3][3];
+            for (int i = 0; i < 3; ++i) {
+                const double* a = p[(i + 1) % 3];
+                const double* b = p[(i + 2) % 3];
+                double ed[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, t[3];
+                cross(N, ed, t);
+                for (int d = 0; d < 3; ++d) gm[i][d] = t[d] / n2;
+            }
+            const double kc = area / 12.0;
+            for (int i = 0; i < 3; ++i) {
+                const int32_t ei = m.dev_face_edges[3 * f + i];
+                if (BE[ei]) continue;
+                const int a = kTE[i][0], b = kTE[i][1];
+                for (int j = 0; j < 3; ++j) {
+                    const int32_t ej = m.dev_face_edges[3 * f + j];
+                    if (BE[ej]) continue;
+                    const int cc = kTE[j][0], d = kTE[j][1];
+                    const double Kv = kc * ((1 + (a == cc)) * dot(gm[b], gm[d]) - (1 + (a == d)) * dot(gm[b], gm[cc]) -
+                                            (1 + (b == cc)) * dot(gm[a], gm[d]) + (1 + (b == d)) * dot(gm[a], gm[cc]));
+                    const int64_t q = slot(ei, ej);
+                    if (q < 0) {
+                        err = "internal: boundary pattern miss";
+                        return FEPIC_E_MESH;
+                    }
+                    A.K[q] += Kv;
+                }
+            }
+        }
+    }
+    // fixed rows: keep a unit mass on the diagonal (identity rows after scaling)
+    for (int64_t e = 0; e < ne; ++e)
+        if (BE[e]) A.M[slot(e, (int32_t)e)] = 1.0;
+    return FEPIC_OK;
+}
+
 int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets_in,
                     std::string& err) {
     if (n_nodes <= 0 || n_tets <= 0 || !xyz || !tets_in) {
@@ -345,119 +516,12 @@ int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_t
         for (int64_t d = 0; d < ne0; ++d)
             if (!m.dev_bedge[d]) m.dev_int_edges.push_back((int32_t)d);
     }
-    const std::vector<int32_t>& TE = m.dev_tet_edges;
-    const std::vector<uint8_t>& BE = m.dev_bedge;
-
-    // ---- assembly pattern (device order): row e couples to the interior edges of every
-    // tet holding e
-    const int64_t ne = m.n_edges;
-    std::vector<int64_t> et_start(ne + 1, 0);
-    for (int64_t j = 0; j < 6 * n_tets; ++j) et_start[TE[j] + 1]++;
-    for (int64_t e = 0; e < ne; ++e) et_start[e + 1] += et_start[e];
-    std::vector<int32_t> et(6 * n_tets);
     {
-        std::vector<int64_t> pos(et_start.begin(), et_start.end() - 1);
-        for (int64_t j = 0; j < 6 * n_tets; ++j) et[pos[TE[j]]++] = (int32_t)(j / 6);
+        m.dev_fixed = m.dev_bedge;
+        m.abc_face.clear();
+        const int rc = assemble_edge_matrices(m, m.dev_fixed, m.abc_face, err);
+        if (rc != FEPIC_OK) return rc;
     }
-    SellMatrix& A = m.mat;
-    A.n_rows = ne;
-    A.n_slices = (ne + kSell - 1) / kSell;
-    std::vector<int32_t> rlen(A.n_slices * kSell, 0);
-    std::vector<int64_t> rstart(ne + 1, 0);
-    std::vector<int32_t> rcols;
-    rcols.reserve(ne * 17);
-    std::vector<int32_t> tmp;
-    for (int64_t e = 0; e < ne; ++e) {
-        rstart[e] = (int64_t)rcols.size();
-        rcols.push_back((int32_t)e);  // diagonal first
-        if (!BE[e]) {
-            tmp.clear();
-            for (int64_t j = et_start[e]; j < et_start[e + 1]; ++j) {
-                const int t = et[j];
-                for (int i = 0; i < 6; ++i) {
-                    const int32_t c = TE[6 * t + i];
-                    if (c != e && !BE[c]) tmp.push_back(c);
-                }
-            }
-            std::sort(tmp.begin(), tmp.end());
-            tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-            rcols.insert(rcols.end(), tmp.begin(), tmp.end());
-        }
-        rlen[e] = (int32_t)(rcols.size() - rstart[e]);
-    }
-    rstart[ne] = (int64_t)rcols.size();
-    A.slice_ptr.assign(A.n_slices + 1, 0);
-    for (int64_t s = 0; s < A.n_slices; ++s) {
-        int32_t w = 0;
-        for (int l = 0; l < kSell; ++l) w = std::max(w, rlen[s * kSell + l]);
-        A.slice_ptr[s + 1] = A.slice_ptr[s] + (int64_t)w * kSell;
-    }
-    const int64_t total = A.slice_ptr[A.n_slices];
-    A.col.assign(total, 0);
-    A.M.assign(total, 0.0);
-    A.S.assign(total, 0.0);
-    for (int64_t s = 0; s < A.n_slices; ++s) {
-        const int64_t w = (A.slice_ptr[s + 1] - A.slice_ptr[s]) / kSell;
-        for (int l = 0; l < kSell; ++l) {
-            const int64_t r = s * kSell + l;
-            for (int64_t k = 0; k < w; ++k) {
-                int32_t c = 0;
-                if (r < ne) c = (k < rlen[r]) ? rcols[rstart[r] + k] : (int32_t)r;
-                A.col[A.slice_ptr[s] + k * kSell + l] = c;
-            }
-        }
-    }
-    auto slot = [&](int64_t r, int32_t c) -> int64_t {
-        const int64_t s = r / kSell, l = r % kSell;
-        if (c == r) return A.slice_ptr[s] + l;
-        // columns after the diagonal are ascending
-        int64_t lo = 1, hi = rlen[r] - 1;
-        while (lo <= hi) {
-            const int64_t mid = (lo + hi) / 2;
-            const int32_t v = rcols[rstart[r] + mid];
-            if (v == c) return A.slice_ptr[s] + mid * kSell + l;
-            if (v < c) lo = mid + 1; else hi = mid - 1;
-        }
-        return -1;
-    };
-    // element matrices, closed form:
-    //   M_(ab)(cd) = eps0 V/20 [(1+d_ac) g_b.g_d - (1+d_ad) g_b.g_c - (1+d_bc) g_a.g_d + (1+d_bd) g_a.g_c]
-    //   S_(ab)(cd) = 4 V / mu0 (g_a x g_b) . (g_c x g_d)
-    for (int64_t t = 0; t < n_tets; ++t) {
-        double g[4][3];
-        for (int k = 1; k < 4; ++k)
-            for (int d = 0; d < 3; ++d) g[k][d] = m.grad[9 * t + 3 * (k - 1) + d];
-        for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
-        double gg[4][4], cr[6][3];
-        for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b) gg[a][b] = dot(g[a], g[b]);
-        for (int i = 0; i < 6; ++i) cross(g[kLE[i][0]], g[kLE[i][1]], cr[i]);
-        const double V = m.vol[t];
-        const double mc = kEps0 * V / 20.0, sc = 4.0 * V / kMu0;
-        for (int i = 0; i < 6; ++i) {
-            const int32_t ei = TE[6 * t + i];
-            if (BE[ei]) continue;
-            const int a = kLE[i][0], b = kLE[i][1];
-            for (int j = 0; j < 6; ++j) {
-                const int32_t ej = TE[6 * t + j];
-                if (BE[ej]) continue;
-                const int c = kLE[j][0], d = kLE[j][1];
-                const double Mv = mc * ((1 + (a == c)) * gg[b][d] - (1 + (a == d)) * gg[b][c] -
-                                        (1 + (b == c)) * gg[a][d] + (1 + (b == d)) * gg[a][c]);
-                const double Sv = sc * dot(cr[i], cr[j]);
-                const int64_t p = slot(ei, ej);
-                if (p < 0) {
-                    err = "internal: assembly pattern miss";
-                    return FEPIC_E_MESH;
-                }
-                A.M[p] += Mv;
-                A.S[p] += Sv;
-            }
-        }
-    }
-    // boundary rows: keep a unit mass on the diagonal (identity rows after scaling)
-    for (int64_t e = 0; e < ne; ++e)
-        if (BE[e]) A.M[slot(e, (int32_t)e)] = 1.0;
 
     build_aux_space(m);
 

@@ -34,6 +34,9 @@ struct HostMesh {
     std::vector<int32_t> dev_tet_edges;   // [n_tets][6] device edge ids
     std::vector<int32_t> dev_face_edges;  // [n_faces][3] device edge ids
     std::vector<uint8_t> dev_bedge;       // wall flag, device order
+    std::vector<uint8_t> dev_fixed;       // fixed (PEC) edges, device order: the wall edges
+                                          // not on an absorbing face
+    std::vector<uint8_t> abc_face;        // [n_faces] absorbing wall faces (empty: none)
     std::vector<int32_t> dev_int_edges;   // interior edges, device ids ascending
     std::vector<double> grad;         // [n_tets][9] grad lambda_1..3
     std::vector<double> vol;          // [n_tets]
@@ -58,6 +61,11 @@ struct HostMesh {
 // Returns FEPIC_OK or FEPIC_E_MESH/FEPIC_E_ARG with a message in err.
 int build_host_mesh(HostMesh& m, int64_t n_nodes, const double* xyz, int64_t n_tets, const int32_t* tets,
                     std::string& err);
+
+// The edge matrices over the unknown edges (not `fixed`, device order), and with absorbing
+// faces (abc_face per canonical face, or empty) their boundary matrix K; see host_mesh.cpp.
+int assemble_edge_matrices(HostMesh& m, const std::vector<uint8_t>& fixed, const std::vector<uint8_t>& abc_face,
+                           std::string& err);
 
 // Face area vectors 1/2 (r_j - r_i) x (r_k - r_i).
 void face_area_vectors(const HostMesh& m, std::vector<double>& out);

@@ -28,6 +28,7 @@
 // Barycentric coordinates of a point x in tet t: lambda_k = grad lambda_k . (x - r_0(t)) for
 // k = 1..3 (r_0 = the tet's local vertex 0), lambda_0 = 1 - the others.
 #include "fepic_internal.h"
+#include "fixed_point.h"
 
 namespace fepic {
 namespace {
@@ -50,7 +51,13 @@ struct EdgeTable {
     int* key;
     double* val;
     double* dg;
+    unsigned long long* fix;   // deterministic mode: straight to the fixed-point accumulators
+    double fix_inv;
     __device__ __forceinline__ void add(int e, double v) const {
+        if (fix) {
+            fix_add(fix, e, v, fix_inv);
+            return;
+        }
         unsigned int h = ((unsigned int)e * 2654435761u) >> (32 - kTableBits);
         for (int p = 0; p < kProbe; ++p) {
             int k = __hip_atomic_load(key + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -332,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_push_ab(PArrays<double> in, PArrays<
         s_val[k] = 0.0;
     }
     __syncthreads();
-    const EdgeTable tab{s_key, s_val, dg};
+    const EdgeTable tab{s_key, s_val, dg, ap.fix, ap.fix_inv};
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     unsigned int nc = 0, na = 0, ncap = 0;
     // after a sort in the same step only the first *n_live slots hold particles

@@ -32,11 +32,11 @@ struct RowGrid {
     unsigned grid;   // 8 * g
 };
 
-inline RowGrid row_grid(int64_t n_rows) {
+inline RowGrid row_grid(int64_t n_rows, int max_grid = kMaxGrid) {
     RowGrid r;
     r.nb = (n_rows + kBlock - 1) / kBlock;
     r.per = (r.nb + 7) / 8;
-    r.g = (int)std::min<int64_t>(r.per, kMaxGrid / 8);
+    r.g = (int)std::min<int64_t>(r.per, max_grid / 8);
     if (r.g < 1) r.g = 1;
     r.grid = 8u * (unsigned)r.g;
     return r;
@@ -144,13 +144,13 @@ __global__ __launch_bounds__(kBlock) void k_axpby(double* y, const double* a, do
     if (i < n) y[i] = alpha * a[i] + beta * b[i];
 }
 
-// A = M + c S; boundary rows (PEC) become identity rows.  The diagonal is slot 0 of every
-// row (the host orders it first), so dinv = 1 / A(slot 0).
+// A = M + c S (+ cK K with absorbing faces); fixed (PEC) rows become identity rows.  The
+// diagonal is slot 0 of every row (the host orders it first), so dinv = 1 / A(slot 0).
 __global__ __launch_bounds__(kBlock) void k_scale_A(int64_t n_rows, const int64_t* __restrict__ sp,
                                                      const int32_t* __restrict__ col, const double* __restrict__ M,
                                                      const double* __restrict__ S, double* __restrict__ A,
                                                      double* __restrict__ dinv, const uint8_t* __restrict__ bmask,
-                                                     double c) {
+                                                     double c, const double* __restrict__ K, double cK) {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t s = r >> 6;
     const int lane = (int)(r & 63);
@@ -160,6 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_scale_A(int64_t n_rows, const int64_
     const bool bnd = real && bmask[r];
     for (int64_t k = b + lane; k < e; k += 64) {
         double a = M[k] + c * S[k];
+        if (K) a += cK * K[k];
         if (bnd) a = (k == b + lane) ? 1.0 : 0.0;
         if (!real) a = 0.0;
         A[k] = a;
@@ -176,14 +177,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n_rows, const int64_t* 
     if (r < n_rows) y[r] = v;
 }
 
-// b = M (2 e - ep) - dt^2 S (c1 e + c2 ep) - (dg_new - dg_old), zero on boundary rows;
-// partials of ||b||^2.
+// b = M (2 e - ep) - dt^2 S (c1 e + c2 ep) - (dg_new - dg_old), zero on fixed rows;
+// partials of ||b||^2.  With absorbing faces (kAbc) also + K (kc1 e + kc2 ep), the damping
+// terms of the Newmark recurrence.
+template <bool kAbc>
 __global__ __launch_bounds__(kBlock) void k_rhs(int64_t n_rows, RowGrid rg, const int64_t* __restrict__ sp,
                                                  const int32_t* __restrict__ col, const double* __restrict__ M,
                                                  const double* __restrict__ S, const double* __restrict__ e,
                                                  const double* __restrict__ ep, const double* __restrict__ dgn,
                                                  const double* __restrict__ dgo, const uint8_t* __restrict__ bmask,
-                                                 double dt2, double c1, double c2, double* __restrict__ bvec,
+                                                 double dt2, double c1, double c2, const double* __restrict__ K,
+                                                 double kc1, double kc2, double* __restrict__ bvec,
                                                  double* __restrict__ partial) {
     double bb[1] = {0.0};
     for (int64_t lb = rg_first(rg), le = rg_end(rg); lb < le; lb += rg.g) {
@@ -192,15 +196,17 @@ __global__ __launch_bounds__(kBlock) void k_rhs(int64_t n_rows, RowGrid rg, cons
         const int64_t s = r >> 6;
         const int lane = (int)(r & 63);
         const int64_t k0 = sp[s], k1 = sp[s + 1];
-        double am = 0.0, as = 0.0;
+        double am = 0.0, as = 0.0, ak = 0.0;
         for (int64_t k = k0 + lane; k < k1; k += 64) {
             const int c = col[k];
             const double ec = e[c], epc = ep[c];
             am += M[k] * (2.0 * ec - epc);
             as += S[k] * (c1 * ec + c2 * epc);
+            if constexpr (kAbc) ak += K[k] * (kc1 * ec + kc2 * epc);
         }
         if (r < n_rows) {
             double v = am - dt2 * as - (dgn[r] - dgo[r]);
+            if constexpr (kAbc) v += ak;
             if (bmask[r]) v = 0.0;
             bvec[r] = v;
             bb[0] += v * v;
@@ -342,10 +348,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_a(int64_t n_rows, RowGrid rg
                                                        const int32_t* __restrict__ col, const double* __restrict__ A,
                                                        const double* __restrict__ dinv, const double* __restrict__ b,
                                                        const double* __restrict__ x, CgVec* __restrict__ V,
-                                                       const double* __restrict__ part_rhs, double* cg_slots,
-                                                       CgScalars* sc, double tol) {
+                                                       const double* __restrict__ part_rhs, int n_rhs_wg,
+                                                       double* cg_slots, CgScalars* sc, double tol) {
     double bb[1];
-    read_partials<1>(part_rhs, gridDim.x, bb);
+    read_partials<1>(part_rhs, n_rhs_wg, bb);
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) {
             sc->bb = bb[0];
@@ -1358,10 +1364,11 @@ void launch_axpby(hipStream_t s, double* y, const double* a, double alpha, const
 }
 
 void launch_scale_A(hipStream_t s, const SellMatrix& shape, const int64_t* sp, const int32_t* col, const double* M,
-                    const double* S, double* A, double* dinv, const uint8_t* bmask, double c) {
+                    const double* S, double* A, double* dinv, const uint8_t* bmask, double c, const double* K,
+                    double cK) {
     const int64_t rows = shape.n_slices * kSell;
     hipLaunchKernelGGL(k_scale_A, dim3(grid_1d(rows, kBlock)), dim3(kBlock), 0, s, shape.n_rows, sp, col, M, S, A,
-                       dinv, bmask, c);
+                       dinv, bmask, c, K, cK);
 }
 
 void launch_sell_spmv(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* val,
@@ -1371,10 +1378,15 @@ void launch_sell_spmv(hipStream_t s, int64_t n_rows, const int64_t* sp, const in
 
 void launch_rhs(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* M,
                 const double* S, const double* e, const double* ep, const double* dg_new, const double* dg_old,
-                const uint8_t* bmask, double dt2, double c1, double c2, double* b, double* partial) {
+                const uint8_t* bmask, double dt2, double c1, double c2, const double* K, double k1, double k2,
+                double* b, double* partial) {
     const RowGrid rg = row_grid(n_rows);
-    hipLaunchKernelGGL(k_rhs, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, M, S, e, ep, dg_new, dg_old,
-                       bmask, dt2, c1, c2, b, partial + SLOT_RHS * kSlot);
+    if (K)
+        hipLaunchKernelGGL(k_rhs<true>, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, M, S, e, ep, dg_new,
+                           dg_old, bmask, dt2, c1, c2, K, k1, k2, b, partial + SLOT_RHS * kSlot);
+    else
+        hipLaunchKernelGGL(k_rhs<false>, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, M, S, e, ep, dg_new,
+                           dg_old, bmask, dt2, c1, c2, K, k1, k2, b, partial + SLOT_RHS * kSlot);
 }
 
 void launch_mfem_rhs(hipStream_t s, int64_t n_rows, int64_t n_faces, const int64_t* sp, const int32_t* col,
@@ -1404,10 +1416,10 @@ void launch_warm(hipStream_t s, int mode, int64_t n, const double* e, const doub
 
 void launch_cg_init(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
                     const double* dinv, const double* b, const double* x, CgVec* v, double* partial, CgScalars* sc,
-                    double tol) {
-    const RowGrid rg = row_grid(n_rows);
+                    double tol, bool det) {
+    const RowGrid rg = row_grid(n_rows, det ? kCgSlots : kMaxGrid);
     hipLaunchKernelGGL(k_cg_init_a, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, dinv, b, x, v,
-                       partial + SLOT_RHS * kSlot, partial + SLOT_CG * kSlot, sc, tol);
+                       partial + SLOT_RHS * kSlot, (int)row_grid(n_rows).grid, partial + SLOT_CG * kSlot, sc, tol);
     hipLaunchKernelGGL(k_cg_init_b, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, sp, col, A, dinv, v,
                        partial + SLOT_CG * kSlot);
 }
@@ -1425,8 +1437,8 @@ inline RowGrid row_grid_full(int64_t n_rows) {
 
 // Iteration i reads the interleaved state from buffer i & 1 and writes buffer (i + 1) & 1.
 void launch_cg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int32_t* col, const double* A,
-                    const double* dinv, double* x, CgVec* const v[2], double* partial, CgScalars* sc) {
-    const RowGrid rg = row_grid_full(n_rows);
+                    const double* dinv, double* x, CgVec* const v[2], double* partial, CgScalars* sc, bool det) {
+    const RowGrid rg = det ? row_grid(n_rows, kCgSlots) : row_grid_full(n_rows);
     const int a = i & 1, b = 1 - a;
     hipLaunchKernelGGL(k_cg_iter, dim3(rg.grid), dim3(kBlock), 0, s, n_rows, rg, i, sp, col, A, dinv, x, v[a], v[b],
                        partial + SLOT_CG * kSlot, sc);

@@ -11,6 +11,8 @@
 //   D (16 x 16):  rows 4 g + i (i = 0..3), column l % 16
 // Only the pairing of A's and B's k entries within a lane matters for the sum, and both
 // operands are always built with the same k order.
+#include <algorithm>
+
 #include "fepic_internal.h"
 
 namespace fepic {
@@ -399,17 +401,40 @@ __global__ __launch_bounds__(256) void k_mlp_features(int64_t n_int, const int32
     X[j] = make_float4((float)(e[k] * se), (float)(ep[k] * se), (float)(ep2[k] * se), (float)(dg[k] * sg));
 }
 
-// s_e = RMS of e over interior edges, s_g = RMS of dG (1 where zero).
-__global__ __launch_bounds__(256) void k_mlp_rms(int64_t n_int, const int32_t* __restrict__ ie,
-                                                 const double* __restrict__ e, const double* __restrict__ dg,
-                                                 double* __restrict__ scales) {
+// s_e = RMS of e over interior edges, s_g = RMS of dG (1 where zero): per-workgroup sums
+// of squares (grid-stride), then one workgroup adds them in a fixed order.
+constexpr int kRmsBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_mlp_rms_part(int64_t n_int, const int32_t* __restrict__ ie,
+                                                      const double* __restrict__ e, const double* __restrict__ dg,
+                                                      double* __restrict__ part) {
     __shared__ double s[2][4];
     double a = 0.0, b = 0.0;
-    for (int64_t j = threadIdx.x; j < n_int; j += 256) {
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n_int; j += (int64_t)gridDim.x * 256) {
         const int k = ie[j];
         a += e[k] * e[k];
         b += dg[k] * dg[k];
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s[0][threadIdx.x >> 6] = a;
+        s[1][threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = (s[0][0] + s[0][1]) + (s[0][2] + s[0][3]);
+        part[kRmsBlocks + blockIdx.x] = (s[1][0] + s[1][1]) + (s[1][2] + s[1][3]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_rms_fin(int64_t n_int, int nb, const double* __restrict__ part,
+                                                     double* __restrict__ scales) {
+    __shared__ double s[2][4];
+    double a = threadIdx.x < nb ? part[threadIdx.x] : 0.0;
+    double b = threadIdx.x < nb ? part[kRmsBlocks + threadIdx.x] : 0.0;
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_xor(a, off);
         b += __shfl_xor(b, off);
@@ -428,6 +453,14 @@ __global__ __launch_bounds__(256) void k_mlp_rms(int64_t n_int, const int32_t* _
     }
 }
 
+// Rows r0, r0 + stride, ... (n of them) of X [rows][4] into dst: the subsample of edges a
+// snapshot records.
+__global__ __launch_bounds__(256) void k_mlp_pick(const float4* __restrict__ X, int64_t r0, int64_t stride, int64_t n,
+                                                  float4* __restrict__ dst) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < n) dst[j] = X[r0 + j * stride];
+}
+
 // Predicted increment as an edge vector: d[ie] = s_e y (d is zero elsewhere).
 __global__ __launch_bounds__(256) void k_mlp_direction(int64_t n_int, const int32_t* __restrict__ ie,
                                                        const float* __restrict__ y, const double* __restrict__ scales,
@@ -437,13 +470,14 @@ __global__ __launch_bounds__(256) void k_mlp_direction(int64_t n_int, const int3
     d[ie[j]] = scales[0] * (double)y[j];
 }
 
-// Training target: (e^{n+1} - e^n) / s_e on interior edges.
-__global__ __launch_bounds__(256) void k_mlp_target(int64_t n_int, const int32_t* __restrict__ ie,
-                                                    const double* __restrict__ e_new, const double* __restrict__ e,
-                                                    const double* __restrict__ scales, float* __restrict__ t) {
+// Training target: (e^{n+1} - e^n) / s_e on interior edges r0, r0 + stride, ... (n rows).
+__global__ __launch_bounds__(256) void k_mlp_target(int64_t n, int64_t r0, int64_t stride,
+                                                    const int32_t* __restrict__ ie, const double* __restrict__ e_new,
+                                                    const double* __restrict__ e, const double* __restrict__ scales,
+                                                    float* __restrict__ t) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n_int) return;
-    const int k = ie[j];
+    if (j >= n) return;
+    const int k = ie[r0 + j * stride];
     t[j] = (float)((e_new[k] - e[k]) / scales[0]);
 }
 
@@ -459,8 +493,10 @@ int mlp_grad_blocks(int64_t n) {
 }
 
 void mlp_launch_rms(hipStream_t s, int64_t n_int, const int32_t* ie, const double* e, const double* dg,
-                    double* scales) {
-    hipLaunchKernelGGL(k_mlp_rms, dim3(1), dim3(256), 0, s, n_int, ie, e, dg, scales);
+                    double* part, double* scales) {
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kRmsBlocks, (n_int + 1023) / 1024));
+    hipLaunchKernelGGL(k_mlp_rms_part, dim3(nb), dim3(256), 0, s, n_int, ie, e, dg, part);
+    hipLaunchKernelGGL(k_mlp_rms_fin, dim3(1), dim3(256), 0, s, n_int, nb, part, scales);
 }
 
 void mlp_launch_features(hipStream_t s, int64_t n_int, const int32_t* ie, const double* e, const double* ep,
@@ -484,10 +520,16 @@ void mlp_launch_direction(hipStream_t s, int64_t n_int, const int32_t* ie, const
     hipLaunchKernelGGL(k_mlp_direction, dim3(grid_1d(n_int, 256)), dim3(256), 0, s, n_int, ie, y, scales, d);
 }
 
-void mlp_launch_target(hipStream_t s, int64_t n_int, const int32_t* ie, const double* e_new, const double* e,
-                       const double* scales, float* t) {
-    if (n_int <= 0) return;
-    hipLaunchKernelGGL(k_mlp_target, dim3(grid_1d(n_int, 256)), dim3(256), 0, s, n_int, ie, e_new, e, scales, t);
+void mlp_launch_target(hipStream_t s, int64_t n, int64_t r0, int64_t stride, const int32_t* ie, const double* e_new,
+                       const double* e, const double* scales, float* t) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_mlp_target, dim3(grid_1d(n, 256)), dim3(256), 0, s, n, r0, stride, ie, e_new, e, scales, t);
+}
+
+void mlp_launch_pick(hipStream_t s, const float* X, int64_t r0, int64_t stride, int64_t n, float* dst) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_mlp_pick, dim3(grid_1d(n, 256)), dim3(256), 0, s, (const float4*)X, r0, stride, n,
+                       (float4*)dst);
 }
 
 void mlp_launch_grad(hipStream_t s, const float* X, const float* T, int64_t n, int64_t n_all, uint64_t seed,

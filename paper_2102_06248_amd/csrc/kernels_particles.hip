@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "fepic_internal.h"
+#include "fixed_point.h"
 
 namespace fepic {
 
@@ -246,6 +247,12 @@ __device__ __forceinline__ void lds_add6(int* s_key, double* s_val, double* __re
 
 constexpr int log2_const(int v) { return v <= 1 ? 0 : 1 + log2_const(v / 2); }
 
+// The six edge currents of one piece into the deterministic mode's accumulators.
+__device__ __forceinline__ void fix_add6(const PushParams& pp, const int32_t* e, const double v[6]) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) fix_add(pp.fix, e[c], v[c], pp.fix_inv);
+}
+
 // One FP64 atomic per occupied slot of the table (after a barrier).
 template <int kSlots, int kB>
 __device__ __forceinline__ void flush_table(const int* s_key, const double* s_val, double* __restrict__ dg) {
@@ -258,7 +265,7 @@ __device__ __forceinline__ void flush_table(const int* s_key, const double* s_va
 // displacement dx, tet by tet up to the end point or a wall, each piece's current into the
 // workgroup's LDS table.  nc counts the particle's crossings (1 on entry); na and ncap
 // count an absorption and a stop at the crossing cap.
-template <typename T, int kBits>
+template <typename T, int kBits, bool kDet = false>
 __device__ __forceinline__ void walk_rest(PArrays<T>& out, int64_t i, int t, int entry, double ls[4], double frac,
                                           const T dx[3], const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
                                           const PushParams& pp, int* s_key, double* s_val, unsigned int& nc,
@@ -278,7 +285,8 @@ __device__ __forceinline__ void walk_rest(PArrays<T>& out, int64_t i, int t, int
             T rr[3];
             end_point(ls, dl, rr, le);
             piece_current(pp.qw, ls, le, cur);
-            lds_add6<kBits>(s_key, s_val, dg, bp->edge, cur);
+            if constexpr (kDet) fix_add6(pp, bp->edge, cur);
+            else lds_add6<kBits>(s_key, s_val, dg, bp->edge, cur);
             out.tet[i] = t;
             out.l1[i] = rr[0];
             out.l2[i] = rr[1];
@@ -288,7 +296,8 @@ __device__ __forceinline__ void walk_rest(PArrays<T>& out, int64_t i, int t, int
 #pragma unroll
         for (int k = 0; k < 4; ++k) le[k] = (k == kb) ? 0.0 : ls[k] + best * dl[k];
         piece_current(pp.qw, ls, le, cur);
-        lds_add6<kBits>(s_key, s_val, dg, bp->edge, cur);
+        if constexpr (kDet) fix_add6(pp, bp->edge, cur);
+        else lds_add6<kBits>(s_key, s_val, dg, bp->edge, cur);
         const int nb = bp->nbr[kb];
         if (nb < 0) {
             ++na;
@@ -321,8 +330,9 @@ __device__ __forceinline__ void walk_rest(PArrays<T>& out, int64_t i, int t, int
 // k_cross, their u and id being final here.  First-piece currents are summed over runs of
 // lanes that share a tet (the particles are sorted by tet); in the fused form the run sums
 // and walk pieces go through the workgroup's LDS table, flushed with one FP64 atomic per
-// edge, in the queue form each run adds its six sums with FP64 atomics.
-template <typename T, bool kFused, int kPB>
+// edge, in the queue form each run adds its six sums with FP64 atomics.  kDet (fused form
+// only): every lane adds its own pieces to the fixed-point accumulators, no table.
+template <typename T, bool kFused, int kPB, bool kDet = false>
 __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? walk_waves<T>() : 1, 8))) void k_push(PArrays<T> in, PArrays<T> out, int64_t n,
                                                   const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
                                                   PushParams pp, PushCounters* __restrict__ cnt,
@@ -330,11 +340,12 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? wa
     // the LDS table of the fused form (the queue form leaves it to k_cross: its 24 KB
     // would cost the first kernel occupancy)
     static_assert(kFused || kPB == kBlock, "the queue form fills regions of kBlock slots");
+    static_assert(kFused || !kDet, "the deterministic form walks in place");
     constexpr int kBits = log2_const(8 * kPB);
-    constexpr int kSlots = kFused ? (1 << kBits) : 1;
+    constexpr int kSlots = (kFused && !kDet) ? (1 << kBits) : 1;
     __shared__ int s_key[kSlots];
     __shared__ double s_val[kSlots];
-    if (kFused) {
+    if (kFused && !kDet) {
         for (int k = threadIdx.x; k < kSlots; k += kPB) {
             s_key[k] = -1;
             s_val[k] = 0.0;
@@ -434,8 +445,11 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? wa
 
     // first-piece currents: one sum per run of lanes sharing a tet, added by the run's last
     // lane (fused form: into the workgroup's LDS table, where runs of neighbouring tets and
-    // the walks share edges; queue form: six FP64 atomics)
-    {
+    // the walks share edges; queue form: six FP64 atomics); deterministic form: each lane's
+    // own, exactly
+    if constexpr (kDet) {
+        if (t0 >= 0) fix_add6(pp, blk[t0].edge, first);
+    } else {
         const int key = t0;
         const int prev_key = __shfl_up(key, 1);
         int f = (lane == 0) || (key != prev_key);
@@ -468,9 +482,11 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? wa
     if (kFused) {
         // the rest of every crossing path here, currents through the LDS table
         unsigned int nc = 0, na = 0, ncap = 0;
-        if (cross) walk_rest<T, kBits>(out, i, tn, q, ln, frac, dx, blk, dg, pp, s_key, s_val, nc, na, ncap);
-        __syncthreads();
-        flush_table<kSlots, kPB>(s_key, s_val, dg);
+        if (cross) walk_rest<T, kBits, kDet>(out, i, tn, q, ln, frac, dx, blk, dg, pp, s_key, s_val, nc, na, ncap);
+        if constexpr (!kDet) {
+            __syncthreads();
+            flush_table<kSlots, kPB>(s_key, s_val, dg);
+        }
         const unsigned int c1 = (cross || status == 2) ? 1u : 0u;
         const unsigned int sc = cross ? nc : c1;
         add_counters<kPB>(sc, sc, (status == 1) + na, (status == 2) + ncap, cnt);
@@ -857,6 +873,30 @@ __global__ __launch_bounds__(kBlock) void k_rho(PArrays<T> p, int64_t n, const i
     flush_table<kSlots, kBlock>(s_key, s_val, rho);
 }
 
+// Deterministic form: q w lambda_k of every particle into the fixed-point accumulators.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rho_fix(PArrays<T> p, int64_t n, const int32_t* __restrict__ tets,
+                                                     double qw, unsigned long long* __restrict__ fix, double fix_inv) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int t = p.tet[i];
+    if (t < 0) return;
+    const double l1 = (double)p.l1[i], l2 = (double)p.l2[i], l3 = (double)p.l3[i];
+    fix_add(fix, tets[4 * t], qw * (1.0 - l1 - l2 - l3), fix_inv);
+    fix_add(fix, tets[4 * t + 1], qw * l1, fix_inv);
+    fix_add(fix, tets[4 * t + 2], qw * l2, fix_inv);
+    fix_add(fix, tets[4 * t + 3], qw * l3, fix_inv);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fix_out(unsigned long long* __restrict__ acc, int64_t n, double scale,
+                                                     double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    out[i] = fix_value(acc[2 * i], acc[2 * i + 1], scale);
+    acc[2 * i] = 0ull;
+    acc[2 * i + 1] = 0ull;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------- energies
@@ -995,6 +1035,11 @@ void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const 
                  int walk) {
     if (n <= 0) return;
     const unsigned n_wg = (unsigned)grid_1d(n, kBlock);
+    if (pp.fix) {
+        hipLaunchKernelGGL((k_push<T, true, kFusedBlock, true>), dim3((unsigned)grid_1d(n, kFusedBlock)),
+                           dim3(kFusedBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live, cq);
+        return;
+    }
     if (walk == FEPIC_WALK_FUSED || (walk == FEPIC_WALK_AUTO && cross_share > kFuseShare)) {
         // most paths cross: finishing them in place costs less idle lanes than the queue
         // costs bytes (64 B written and read back per crossing particle)
@@ -1039,9 +1084,18 @@ void launch_sort(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, int64_
 }
 
 template <typename T>
-void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, double qw, double* rho) {
+void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, double qw, double* rho,
+                unsigned long long* fix, double fix_inv) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_rho<T>, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, p, n, tets, qw, rho);
+    if (fix)
+        hipLaunchKernelGGL(k_rho_fix<T>, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, p, n, tets, qw, fix, fix_inv);
+    else
+        hipLaunchKernelGGL(k_rho<T>, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, p, n, tets, qw, rho);
+}
+
+void launch_fix_out(hipStream_t s, unsigned long long* acc, int64_t n, double scale, double* out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fix_out, dim3(grid_1d(n, kBlock)), dim3(kBlock), 0, s, acc, n, scale, out);
 }
 
 #define FEPIC_INSTANTIATE(T)                                                                                      \
@@ -1054,7 +1108,8 @@ void launch_rho(hipStream_t s, PArrays<T> p, int64_t n, const int32_t* tets, dou
                                    const int32_t*, const double*, const double*, const int32_t*, PushCounters*); \
     template void launch_sort<T>(hipStream_t, PArrays<T>, PArrays<T>, int64_t, int64_t, int32_t*, int32_t*,      \
                                  int32_t*, int32_t*, AbHistIo);                                                  \
-    template void launch_rho<T>(hipStream_t, PArrays<T>, int64_t, const int32_t*, double, double*);               \
+    template void launch_rho<T>(hipStream_t, PArrays<T>, int64_t, const int32_t*, double, double*,                 \
+                                unsigned long long*, double);                                                     \
     template void launch_kinetic<T>(hipStream_t, PArrays<T>, int64_t, double, double*);
 
 FEPIC_INSTANTIATE(float)

@@ -65,10 +65,12 @@ struct MlpState {
     double* scales = nullptr;  // s_e, s_g of the current step
     float* Xcur = nullptr;   // features of the current step [n_int][4]
     float* ycur = nullptr;
-    // recording ring
-    float* Xrec = nullptr;   // [cap][n_int][4]
-    float* Trec = nullptr;   // [cap][n_int]
+    // recording ring: each snapshot keeps rows r0, r0 + stride, ... of the interior edges
+    // (n_rec of them), r0 cycling through 0..stride-1 over the snapshots taken
+    float* Xrec = nullptr;   // [cap][n_rec][4]
+    float* Trec = nullptr;   // [cap][n_rec]
     int64_t cap = 0, count = 0, head = 0;
+    int64_t stride = 1, n_rec = 0, taken = 0;
     int64_t adam_t = 0;
     bool have_weights = false;
     // scratch for host batches
@@ -122,7 +124,7 @@ static int init_weights(fepic_ctx* c, uint64_t seed) {
 static void features_into(fepic_ctx* c, float* dst) {
     MlpState* s = c->mlp;
     const int64_t ni = c->mesh.n_int_edges;
-    mlp_launch_rms(c->stream, ni, c->d_int_edges, c->d_e, c->d_dgn, s->scales);
+    mlp_launch_rms(c->stream, ni, c->d_int_edges, c->d_e, c->d_dgn, s->loss_part, s->scales);
     mlp_launch_features(c->stream, ni, c->d_int_edges, c->d_e, c->d_ep, c->d_ep2, c->d_dgn, s->scales, dst);
 }
 
@@ -151,20 +153,18 @@ int mlp_record_features(fepic_ctx* c) {
     if (rc) return rc;
     MlpState* s = c->mlp;
     if (s->cap == 0) return FEPIC_OK;
-    const int64_t ni = c->mesh.n_int_edges;
-    float* dst = s->Xrec + (size_t)s->head * ni * 4;
-    if (c->opt.warm_start == FEPIC_WS_MLP && c->mlp_ready)
-        HIPCHK_RET(c, hipMemcpyAsync(dst, s->Xcur, sizeof(float) * 4 * ni, hipMemcpyDeviceToDevice, c->stream));
-    else
-        features_into(c, dst);
+    float* dst = s->Xrec + (size_t)s->head * s->n_rec * 4;
+    if (!(c->opt.warm_start == FEPIC_WS_MLP && c->mlp_ready)) features_into(c, s->Xcur);
+    mlp_launch_pick(c->stream, s->Xcur, s->taken % s->stride, s->stride, s->n_rec, dst);
     return FEPIC_OK;
 }
 
 int mlp_record_target(fepic_ctx* c) {
     MlpState* s = c->mlp;
     if (!s || s->cap == 0) return FEPIC_OK;
-    const int64_t ni = c->mesh.n_int_edges;
-    mlp_launch_target(c->stream, ni, c->d_int_edges, c->d_x, c->d_e, s->scales, s->Trec + (size_t)s->head * ni);
+    mlp_launch_target(c->stream, s->n_rec, s->taken % s->stride, s->stride, c->d_int_edges, c->d_x, c->d_e, s->scales,
+                      s->Trec + (size_t)s->head * s->n_rec);
+    s->taken++;
     s->head = (s->head + 1) % s->cap;
     s->count = std::min(s->count + 1, s->cap);
     return FEPIC_OK;
@@ -254,22 +254,26 @@ using namespace fepic;
 extern "C" {
 
 int fepic_ws_record(fepic_ctx* c, int on, int64_t max_snapshots) {
-    if (!c) return FEPIC_E_ARG;
+    if (!c || on < 0) return FEPIC_E_ARG;
     int rc = ensure_mlp(c);
     if (rc) return rc;
     MlpState* s = c->mlp;
-    if (on && max_snapshots > 0 && max_snapshots != s->cap) {
-        const int64_t ni = c->mesh.n_int_edges;
+    const int64_t ni = c->mesh.n_int_edges;
+    if (on > ni) return fail(c, FEPIC_E_ARG, "row stride above the number of interior edges");
+    if (on && max_snapshots > 0 && (max_snapshots != s->cap || on != s->stride)) {
+        const int64_t n_rec = ni / on;
         dfree(c, s->Xrec);
         dfree(c, s->Trec);
-        s->Xrec = (float*)dmalloc(c, sizeof(float) * 4 * ni * max_snapshots);
-        s->Trec = (float*)dmalloc(c, sizeof(float) * ni * max_snapshots);
+        s->Xrec = (float*)dmalloc(c, sizeof(float) * 4 * n_rec * max_snapshots);
+        s->Trec = (float*)dmalloc(c, sizeof(float) * n_rec * max_snapshots);
         if (!s->Xrec || !s->Trec) {
             s->cap = 0;
             return fail(c, FEPIC_E_OOM, "recording buffer allocation failed");
         }
         s->cap = max_snapshots;
-        s->count = s->head = 0;
+        s->stride = on;
+        s->n_rec = n_rec;
+        s->count = s->head = s->taken = 0;
     }
     if (on && s->cap == 0) return fail(c, FEPIC_E_ARG, "recording needs max_snapshots > 0");
     c->recording = on != 0;
@@ -287,7 +291,7 @@ int fepic_ws_train(fepic_ctx* c, const fepic_train_opts* o, fepic_train_stats* o
     int rc = ensure_mlp(c);
     if (rc) return rc;
     MlpState* s = c->mlp;
-    const int64_t ni = c->mesh.n_int_edges;
+    const int64_t ni = s->n_rec;   // rows per snapshot
     if (s->count < 1 || ni == 0) return fail(c, FEPIC_E_STATE, "no recorded snapshots");
     if (o->epochs < 1 || o->batch < 64 || !(o->lr > 0)) return fail(c, FEPIC_E_ARG, "bad training options");
     const auto t0 = std::chrono::steady_clock::now();
@@ -377,6 +381,8 @@ int fepic_ws_set_weights(fepic_ctx* c, const float* w, int64_t n) {
 
 int fepic_set_warm_start(fepic_ctx* c, int mode) {
     if (!c || mode < FEPIC_WS_PREV || mode > FEPIC_WS_MLP) return FEPIC_E_ARG;
+    if (mode == FEPIC_WS_MLP && c->opt.deterministic)
+        return fail(c, FEPIC_E_STATE, "the deterministic mode does not take the learned start");
     c->opt.warm_start = mode;
     return FEPIC_OK;
 }

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfepic.so")
 
-ABI_VERSION = 7   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
+ABI_VERSION = 8   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
 FEPIC_OK = 0
 FEPIC_FP32_PUSH_FP64_ACC, FEPIC_ALL_FP64 = 0, 1
 FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP = 0, 1, 2, 3
@@ -39,7 +39,8 @@ class fepic_options(ctypes.Structure):
                 ("crossing_cap", ctypes.c_int), ("warm_start", ctypes.c_int), ("diagnostics", ctypes.c_int),
                 ("timing", ctypes.c_int), ("preconditioner", ctypes.c_int), ("aux_far_levels", ctypes.c_int),
                 ("walk", ctypes.c_int), ("solve_precision", ctypes.c_int), ("mixed_inner_tol", ctypes.c_double),
-                ("pusher", ctypes.c_int), ("ab_order", ctypes.c_int), ("field_solver", ctypes.c_int)]
+                ("pusher", ctypes.c_int), ("ab_order", ctypes.c_int), ("field_solver", ctypes.c_int),
+                ("deterministic", ctypes.c_int)]
 
 
 class fepic_step_stats(ctypes.Structure):
@@ -128,6 +129,7 @@ _SIGS = {
     "fepic_set_solve_precision": [_P, _INT],
     "fepic_set_pusher": [_P, _INT, _INT],
     "fepic_set_field_solver": [_P, _INT],
+    "fepic_set_absorbing_faces": [_P, _I64, _P],
     "fepic_mlp_forward": [_P, _I64, _P, _P],
     "fepic_mlp_grad": [_P, _I64, _P, _P, _P, ctypes.POINTER(_D)],
     "fepic_mlp_grad_noalloc": [_P, _I64, _P, _P, _P, _P],
@@ -291,7 +293,7 @@ def fepic_get_matrix(ctx, which):
 
 
 def fepic_get_matrix_nnz(ctx, which):
-    """Stored entries of matrix `which` (0 = M, 1 = S) over interior edges."""
+    """Stored entries of matrix `which` (0 = M, 1 = S, 2 = K) over the unknown edges."""
     n = ctypes.c_int64()
     _check(ctx, lib().fepic_get_matrix(ctx, which, 0, ctypes.byref(n), None, None, None))
     return n.value
@@ -494,6 +496,15 @@ def fepic_set_solve_precision(ctx, solve_precision):
 
 def fepic_set_field_solver(ctx, solver):
     _check(ctx, lib().fepic_set_field_solver(ctx, int(solver)))
+
+
+def fepic_set_absorbing_faces(ctx, faces=None):
+    """Absorbing wall faces (canonical ids); None = every wall face."""
+    if faces is None:
+        _check(ctx, lib().fepic_set_absorbing_faces(ctx, 0, None))
+        return
+    f = np.ascontiguousarray(faces, dtype=np.int32)
+    _check(ctx, lib().fepic_set_absorbing_faces(ctx, len(f), _ptr(f)))
 
 
 def fepic_set_pusher(ctx, pusher, ab_order=4):

@@ -147,3 +147,66 @@ def test_call_order_is_checked(F):
         assert ei.value.code == -3
     finally:
         F.fepic_destroy(ctx)
+
+
+def test_absorbing_faces_assembly_matches_oracle(F):
+    """fepic_set_absorbing_faces on a host-only context: the library's closed-form boundary
+    matrix (surface gradients of the triangle's own barycentrics) against the oracle's
+    quadrature of the tet's Whitney functions, and M, S re-assembled over the new unknown
+    edges (those not on a PEC face)."""
+    xyz, tets = inputs.kuhn_cube(3)
+    xyz = inputs.jitter_nodes(xyz, inputs.kuhn_interior_nodes(3), 1 / 3, 0.1, seed=3)
+    m = Mesh(xyz, tets)
+    sel = np.nonzero(m.boundary_face)[0][::2]
+    pec = m.boundary_face.copy()
+    pec[sel] = False
+    fixed = np.zeros(m.n_edges, dtype=bool)
+    fixed[m.face_edges[pec].ravel()] = True
+    free = np.nonzero(~fixed)[0]
+    ctx = F.fepic_create(device=-1, preconditioner=F.FEPIC_PC_JACOBI)
+    try:
+        F.fepic_upload_mesh(ctx, xyz, tets)
+        with pytest.raises(F.FepicError) as ei:
+            F.fepic_get_matrix(ctx, 2)
+        assert ei.value.code == -3
+        F.fepic_set_absorbing_faces(ctx, sel)
+        for which, ref in ((0, fem.mass_matrix(m)), (1, fem.curlcurl_matrix(m)), (2, fem.boundary_matrix(m, sel))):
+            r, c, v = F.fepic_get_matrix(ctx, which)
+            assert not np.any(fixed[r])
+            A = sp.csr_matrix((v, (r, c)), shape=(m.n_edges, m.n_edges))
+            R = ref.tocsr()[free][:, free]
+            assert abs(R - A[free][:, free]).max() <= 1e-12 * abs(R).max(), which
+        with pytest.raises(F.FepicError) as ei:
+            F.fepic_set_absorbing_faces(ctx, sel)                 # once per context
+        assert ei.value.code == -3
+        with pytest.raises(F.FepicError):
+            F.fepic_set_preconditioner(ctx, F.FEPIC_PC_AUX)
+        with pytest.raises(F.FepicError):
+            F.fepic_set_field_solver(ctx, F.FEPIC_FIELD_NM_MFEM)
+    finally:
+        F.fepic_destroy(ctx)
+
+
+def test_absorbing_faces_argument_checks(F):
+    xyz, tets = inputs.kuhn_cube(2)
+    m = Mesh(xyz, tets)
+    interior_face = int(np.nonzero(~m.boundary_face)[0][0])
+    ctx = F.fepic_create(device=-1)                                # default: auxiliary-space PC
+    try:
+        F.fepic_upload_mesh(ctx, xyz, tets)
+        with pytest.raises(F.FepicError) as ei:
+            F.fepic_set_absorbing_faces(ctx)
+        assert ei.value.code == -3
+        F.fepic_set_preconditioner(ctx, F.FEPIC_PC_JACOBI)
+        for bad in ([interior_face], [-1], [m.n_faces]):
+            with pytest.raises(F.FepicError) as ei:
+                F.fepic_set_absorbing_faces(ctx, bad)
+            assert ei.value.code == -1
+        # a refused call leaves the PEC matrices in place
+        r, _, _ = F.fepic_get_matrix(ctx, 0)
+        assert not np.any(m.boundary_edge[r])
+        F.fepic_set_absorbing_faces(ctx)                            # every wall face
+        r, _, v = F.fepic_get_matrix(ctx, 2)          # stored in the pattern of M and S
+        assert set(np.unique(r[v != 0.0]).tolist()) == set(np.nonzero(m.boundary_edge)[0].tolist())
+    finally:
+        F.fepic_destroy(ctx)
