@@ -156,3 +156,24 @@ def test_ab_byte_model():
     # the committed counter summary names the kernel source it was taken on
     d = json.load(open(os.path.join(os.path.dirname(__file__), "..", "profiles", "push_ab4_c3_plasma_counters.json")))
     assert d["source"] == "kernels_ab.hip" and len(d["source_sha1"]) == 12 and d["hbm_bytes_per_launch"] > 0
+
+
+def test_deterministic_option_checks(F):
+    """The deterministic mode takes the Jacobi preconditioner, the FP64 solve and a warm
+    start other than the learned one; the setters refuse to leave them."""
+    assert F.fepic_default_options().deterministic == 0
+    for bad in ({"deterministic": 1}, {"deterministic": 2, "preconditioner": F.FEPIC_PC_JACOBI},
+                {"deterministic": 1, "preconditioner": F.FEPIC_PC_JACOBI, "warm_start": F.FEPIC_WS_MLP}):
+        with pytest.raises(F.FepicError) as ei:
+            F.fepic_create(device=-1, **bad)
+        assert F.ERROR_NAMES[ei.value.code] == "FEPIC_E_ARG"
+    ctx = F.fepic_create(device=-1, deterministic=1, preconditioner=F.FEPIC_PC_JACOBI)
+    try:
+        for call in (lambda: F.fepic_set_preconditioner(ctx, F.FEPIC_PC_AUX),
+                     lambda: F.fepic_set_warm_start(ctx, F.FEPIC_WS_MLP),
+                     lambda: F.fepic_set_solve_precision(ctx, F.FEPIC_SOLVE_MIXED)):
+            with pytest.raises(F.FepicError):
+                call()
+        F.fepic_set_warm_start(ctx, F.FEPIC_WS_EXTRAP1)
+    finally:
+        F.fepic_destroy(ctx)
