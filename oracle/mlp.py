@@ -4,8 +4,11 @@ Not from the paper (which has no learned part): a 3-layer perceptron 4 -> 64 -> 
 with ReLU, applied to every interior edge independently.  Inputs per edge:
   [e^n / s_e, e^{n-1} / s_e, e^{n-2} / s_e, dG^{n+1} / s_g],
 s_e = RMS of e^n over interior edges and s_g = RMS of dG^{n+1} (each replaced by 1 when
-zero).  The output y predicts the normalised increment, so the warm start is
-x0 = e^n + s_e * y.  Loss: mean squared error of y against (e^{n+1} - e^n) / s_e.
+zero).  The output y predicts the shape of the increment: the warm start is
+x0 = e^n + theta s_e y with theta the energy-optimal step along s_e y, so the
+prediction's scale is free.  Loss: mean squared error of y against the step's
+increment e^{n+1} - e^n divided by its own RMS over the recorded edges (1 when zero;
+s_e would vanish with e^n at a neutral start).
 
 Parameter order and shapes (also the flat layout): W1 [64,4], b1 [64], W2 [64,64],
 b2 [64], W3 [1,64], b3 [1].

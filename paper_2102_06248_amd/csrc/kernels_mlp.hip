@@ -470,15 +470,43 @@ __global__ __launch_bounds__(256) void k_mlp_direction(int64_t n_int, const int3
     d[ie[j]] = scales[0] * (double)y[j];
 }
 
-// Training target: (e^{n+1} - e^n) / s_e on interior edges r0, r0 + stride, ... (n rows).
+// Training target, first pass: the increments e^{n+1} - e^n on interior edges r0,
+// r0 + stride, ... (n rows) into d (FP64) and per-workgroup sums of their squares.
 __global__ __launch_bounds__(256) void k_mlp_target(int64_t n, int64_t r0, int64_t stride,
                                                     const int32_t* __restrict__ ie, const double* __restrict__ e_new,
-                                                    const double* __restrict__ e, const double* __restrict__ scales,
-                                                    float* __restrict__ t) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const int k = ie[r0 + j * stride];
-    t[j] = (float)((e_new[k] - e[k]) / scales[0]);
+                                                    const double* __restrict__ e, double* __restrict__ d,
+                                                    double* __restrict__ part) {
+    __shared__ double s[4];
+    double a = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+        const int k = ie[r0 + j * stride];
+        const double v = e_new[k] - e[k];
+        d[j] = v;
+        a += v * v;
+    }
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// Second pass: t = d / RMS(d) (1 where zero): each snapshot's increments in units of their
+// own RMS.  The start uses the prediction only as a direction (its step length comes from
+// the line step), so the scale is free, and this one stays finite where e^n vanishes (a
+// neutral start), unlike the RMS of e^n.
+__global__ __launch_bounds__(256) void k_mlp_target_scale(int64_t n, int nb, const double* __restrict__ part,
+                                                          const double* __restrict__ d, float* __restrict__ t) {
+    __shared__ double s_inv;
+    if (threadIdx.x == 0) {
+        double a = 0.0;
+        for (int b = 0; b < nb; ++b) a += part[b];
+        const double r = n ? sqrt(a / (double)n) : 0.0;
+        s_inv = r > 0.0 ? 1.0 / r : 1.0;
+    }
+    __syncthreads();
+    const double inv = s_inv;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256)
+        t[j] = (float)(d[j] * inv);
 }
 
 }  // namespace
@@ -521,9 +549,11 @@ void mlp_launch_direction(hipStream_t s, int64_t n_int, const int32_t* ie, const
 }
 
 void mlp_launch_target(hipStream_t s, int64_t n, int64_t r0, int64_t stride, const int32_t* ie, const double* e_new,
-                       const double* e, const double* scales, float* t) {
+                       const double* e, double* work, double* part, float* t) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_mlp_target, dim3(grid_1d(n, 256)), dim3(256), 0, s, n, r0, stride, ie, e_new, e, scales, t);
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kRmsBlocks, (n + 1023) / 1024));
+    hipLaunchKernelGGL(k_mlp_target, dim3(nb), dim3(256), 0, s, n, r0, stride, ie, e_new, e, work, part);
+    hipLaunchKernelGGL(k_mlp_target_scale, dim3(nb), dim3(256), 0, s, n, nb, part, work, t);
 }
 
 void mlp_launch_pick(hipStream_t s, const float* X, int64_t r0, int64_t stride, int64_t n, float* dst) {

@@ -162,8 +162,9 @@ int mlp_record_features(fepic_ctx* c) {
 int mlp_record_target(fepic_ctx* c) {
     MlpState* s = c->mlp;
     if (!s || s->cap == 0) return FEPIC_OK;
-    mlp_launch_target(c->stream, s->n_rec, s->taken % s->stride, s->stride, c->d_int_edges, c->d_x, c->d_e, s->scales,
-                      s->Trec + (size_t)s->head * s->n_rec);
+    // work: d_Me is free after the solve (the diagnostics recompute it); n_rec <= n_edges
+    mlp_launch_target(c->stream, s->n_rec, s->taken % s->stride, s->stride, c->d_int_edges, c->d_x, c->d_e, c->d_Me,
+                      s->loss_part, s->Trec + (size_t)s->head * s->n_rec);
     s->taken++;
     s->head = (s->head + 1) % s->cap;
     s->count = std::min(s->count + 1, s->cap);
