@@ -63,8 +63,14 @@ enum {
 enum { FEPIC_FP32_PUSH_FP64_ACC = 0, FEPIC_ALL_FP64 = 1 };
 
 /* Warm start of the Newmark solve: previous field, linear or quadratic extrapolation in
- * time, or the per-edge learned predictor (fepic_ws_*). */
-enum { FEPIC_WS_PREV = 0, FEPIC_WS_EXTRAP1 = 1, FEPIC_WS_EXTRAP2 = 2, FEPIC_WS_MLP = 3 };
+ * time, or the per-edge learned predictor (fepic_ws_*) of the increment, s_d y (s_d the
+ * RMS of e^n - e^{n-1} over interior edges): FEPIC_WS_MLP takes the energy-norm-optimal
+ * step along it, x0 = e^n + theta s_d y (never worse than e^n in the A-norm; falls back to e^n when
+ * the start's residual exceeds ||b|| or is not finite); FEPIC_WS_MLP_DIRECT takes the
+ * prediction as it is, x0 = e^n + s_d y, as the extrapolations take theirs (falls back to
+ * e^n when the start's residual is not finite or exceeds 1e4 ||b||).  Both need trained
+ * or set weights; until then they start from e^n. */
+enum { FEPIC_WS_PREV = 0, FEPIC_WS_EXTRAP1 = 1, FEPIC_WS_EXTRAP2 = 2, FEPIC_WS_MLP = 3, FEPIC_WS_MLP_DIRECT = 4 };
 
 /* Preconditioner of the Newmark solve.  FEPIC_PC_JACOBI: diag(A)^-1.  FEPIC_PC_AUX: the
  * nodal auxiliary-space preconditioner (Hiptmair and Xu, SIAM J. Numer. Anal. 45, 2007),
@@ -167,7 +173,7 @@ typedef struct {
                               |q w|), the particle step always walks in place, and the PCG
                               dots use one workgroup per partial slot.  Needs
                               FEPIC_PC_JACOBI, FEPIC_SOLVE_FP64 and a warm start other than
-                              FEPIC_WS_MLP (FEPIC_E_ARG at create; the setters refuse to
+                              the learned ones (FEPIC_E_ARG at create; the setters refuse to
                               leave them with FEPIC_E_STATE).  The state after a step
                               (fields, charge, current, each particle by id) and the
                               integer step stats repeat bit for bit; the floating-point
@@ -394,8 +400,10 @@ int fepic_kernel_time(fepic_ctx* ctx, const char* family, double* total_ms, int6
 
 /* ---------------------------------------------------------------- learned warm start
  * Per-edge network 4 -> 64 -> 64 -> 1 (ReLU), BF16 matrix-core arithmetic with FP32
- * accumulation.  Inputs per interior edge: [e^n, e^{n-1}, e^{n-2}] / s_e and dG^{n+1} / s_g
- * with s_e, s_g the RMS over interior edges (1 if zero); prediction x0 = e^n + s_e y.
+ * accumulation.  Inputs per interior edge: e^n / s_e, (e^n - e^{n-1}) / s_d,
+ * (e^{n-1} - e^{n-2}) / s_d (differences formed in FP64) and dG^{n+1} / s_g, with s_e,
+ * s_d, s_g the RMS over interior edges (1 if zero); the output predicts the increment in
+ * units of s_d (see FEPIC_WS_MLP and FEPIC_WS_MLP_DIRECT).
  * Flat FP32 weight layout: W1[64][4], b1[64], W2[64][64], b2[64], W3[1][64], b3[1]
  * (4545 values).  The PCG always runs to cg_tol from whatever start, so the network only
  * changes the iteration count, never the accuracy; a non-finite prediction or one whose
@@ -413,11 +421,14 @@ typedef struct {
     int64_t n_train_rows, n_val_rows, n_steps;
     float ms_total;
 } fepic_train_stats;
-/* on = k >= 1: each later fepic_step appends (features, target) of one interior edge in k
+/* on = k >= 1: each later fepic_step appends (features, target (e^{n+1} - e^n) / s_d) of
+ * one interior edge in k
  * (rows r0, r0 + k, ... with r0 = snapshot count mod k, so successive snapshots sample
  * different edges; k = 1 records every interior edge) to a device buffer holding up to
  * max_snapshots steps (oldest dropped first); a new k or max_snapshots starts the buffer
- * afresh.  on = 0 stops recording.  FEPIC_E_ARG for k above the interior edge count. */
+ * afresh.  A step whose increment's RMS exceeds 10 s_d (the history near zero, as after a
+ * neutral start) is not recorded.  on = 0 stops recording.  FEPIC_E_ARG for k above the interior
+ * edge count. */
 int fepic_ws_record(fepic_ctx* ctx, int on, int64_t max_snapshots);
 int fepic_ws_num_snapshots(fepic_ctx* ctx, int64_t* n);
 int fepic_ws_train(fepic_ctx* ctx, const fepic_train_opts* opts, fepic_train_stats* out);

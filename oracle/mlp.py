@@ -2,13 +2,16 @@
 
 Not from the paper (which has no learned part): a 3-layer perceptron 4 -> 64 -> 64 -> 1
 with ReLU, applied to every interior edge independently.  Inputs per edge:
-  [e^n / s_e, e^{n-1} / s_e, e^{n-2} / s_e, dG^{n+1} / s_g],
-s_e = RMS of e^n over interior edges and s_g = RMS of dG^{n+1} (each replaced by 1 when
-zero).  The output y predicts the shape of the increment: the warm start is
-x0 = e^n + theta s_e y with theta the energy-optimal step along s_e y, so the
-prediction's scale is free.  Loss: mean squared error of y against the step's
-increment e^{n+1} - e^n divided by its own RMS over the recorded edges (1 when zero;
-s_e would vanish with e^n at a neutral start).
+  [e^n / s_e, (e^n - e^{n-1}) / s_d, (e^{n-1} - e^{n-2}) / s_d, dG^{n+1} / s_g],
+s_e = RMS of e^n, s_d = RMS of e^n - e^{n-1} and s_g = RMS of dG^{n+1} over interior
+edges (each replaced by 1 when zero).  The differences are formed in FP64 before the
+inputs are rounded to BF16: successive fields differ by a few per cent, which BF16's
+0.4 % rounding of the raw fields would turn into rough per-edge noise.  The output y
+predicts the increment in units of s_d: the warm start is x0 = e^n + theta s_d y with
+theta the energy-optimal step along s_d y (line-step form) or x0 = e^n + s_d y (direct
+form).  Loss: mean squared error of y against (e^{n+1} - e^n) / s_d; a step where that
+target's RMS exceeds 10 (the history near zero, as after a neutral start) is not used
+for training.
 
 Parameter order and shapes (also the flat layout): W1 [64,4], b1 [64], W2 [64,64],
 b2 [64], W3 [1,64], b3 [1].
@@ -55,10 +58,11 @@ def rms_or_one(v):
 
 
 def features(e_n, e_nm1, e_nm2, dG_new):
-    s_e = rms_or_one(e_n)
-    s_g = rms_or_one(dG_new)
-    X = np.stack([e_n / s_e, e_nm1 / s_e, e_nm2 / s_e, dG_new / s_g], axis=1)
-    return X, s_e, s_g
+    """Inputs [n, 4], the increments' unit s_d and s_g."""
+    d1, d2 = e_n - e_nm1, e_nm1 - e_nm2
+    s_e, s_d, s_g = rms_or_one(e_n), rms_or_one(d1), rms_or_one(dG_new)
+    X = np.stack([e_n / s_e, d1 / s_d, d2 / s_d, dG_new / s_g], axis=1)
+    return X, s_d, s_g
 
 
 def forward(p, X):

@@ -722,6 +722,16 @@ int ensure_mfem(fepic_ctx* c) {
 
 constexpr int kMaxRestarts = 3;
 
+// The learned start's guard on its squared residual rr0 against ||b||^2: with the line
+// step (never worse than e^n in the A-norm) a start worse than x0 = 0 means broken
+// weights; the direct prediction is judged like an extrapolation, which may raise the
+// residual, so only a non-finite or absurd one (above 1e4 ||b||) is refused.
+bool mlp_start_rejected(int mode, double rr0, double bb) {
+    if (mode == FEPIC_WS_MLP) return !std::isfinite(rr0) || rr0 > bb;
+    if (mode == FEPIC_WS_MLP_DIRECT) return !std::isfinite(rr0) || rr0 > 1e8 * bb;
+    return false;
+}
+
 // Field half: RHS, warm start, PCG, true residual, Faraday into d_bn.  Returns the
 // iteration count via the host scalars (stream synchronized at return).
 int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
@@ -755,9 +765,10 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
     }
     ev_mark(c, 5);
     int mode = c->opt.warm_start;
-    if (mode == FEPIC_WS_MLP && !c->mlp_ready) mode = FEPIC_WS_PREV;
-    if (mode == FEPIC_WS_MLP) {
-        int rc = mlp_warm_start(c);
+    const bool learned = mode == FEPIC_WS_MLP || mode == FEPIC_WS_MLP_DIRECT;
+    if (learned && !c->mlp_ready) mode = FEPIC_WS_PREV;
+    if (mode == FEPIC_WS_MLP || mode == FEPIC_WS_MLP_DIRECT) {
+        int rc = mlp_warm_start(c, mode == FEPIC_WS_MLP_DIRECT);
         if (rc != FEPIC_OK) return rc;
     } else {
         launch_warm(c->stream, mode, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
@@ -858,8 +869,8 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
             if (pass == 0) {
                 bb = h.bb;
                 tol2 = h.tol2_bb;
-                if (mode == FEPIC_WS_MLP && (!std::isfinite(h.rr_true) || h.rr_true > bb)) {
-                    // guard: a start worse than x0 = 0 (or non-finite) falls back to e^n
+                if (mlp_start_rejected(mode, h.rr_true, bb)) {
+                    // guard: a non-finite or implausible start falls back to e^n
                     c->mlp_fallbacks++;
                     mode = FEPIC_WS_PREV;
                     launch_warm(c->stream, FEPIC_WS_PREV, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
@@ -891,13 +902,13 @@ int field_phase(fepic_ctx* c, double dt, double beta, double gamma) {
     } else {
         for (int restart = 0;; ++restart) {
             cg_init();
-            if (restart == 0 && mode == FEPIC_WS_MLP) {
-                // guard: a start worse than x0 = 0 (or non-finite) falls back to e^n
+            if (restart == 0 && (mode == FEPIC_WS_MLP || mode == FEPIC_WS_MLP_DIRECT)) {
+                // guard: a non-finite or implausible start falls back to e^n
                 if (aux) launch_pcg_rr0(c->stream, c->d_partial, c->d_sc);
                 else launch_cg_rr0(c->stream, ne, c->d_partial, c->d_sc);
                 HIPCHK(c, hipMemcpyAsync(c->h_sc, c->d_sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
                 HIPCHK(c, hipStreamSynchronize(c->stream));
-                if (!(std::isfinite(c->h_sc->rr0)) || c->h_sc->rr0 > c->h_sc->bb) {
+                if (mlp_start_rejected(mode, c->h_sc->rr0, c->h_sc->bb)) {
                     c->mlp_fallbacks++;
                     launch_warm(c->stream, FEPIC_WS_PREV, ne, c->d_e, c->d_ep, c->d_ep2, c->d_x);
                     cg_init();
@@ -1371,7 +1382,7 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
     if (opts) o = *opts;
     if (o.precision != FEPIC_FP32_PUSH_FP64_ACC && o.precision != FEPIC_ALL_FP64) return FEPIC_E_ARG;
     if (!(o.cg_tol > 0) || o.cg_max_iters < 1 || o.crossing_cap < 1 || o.sort_period < 0) return FEPIC_E_ARG;
-    if (o.warm_start < FEPIC_WS_PREV || o.warm_start > FEPIC_WS_MLP) return FEPIC_E_ARG;
+    if (o.warm_start < FEPIC_WS_PREV || o.warm_start > FEPIC_WS_MLP_DIRECT) return FEPIC_E_ARG;
     if (o.preconditioner != FEPIC_PC_JACOBI && o.preconditioner != FEPIC_PC_AUX) return FEPIC_E_ARG;
     if (o.aux_far_levels < -1 || o.aux_far_levels > kAuxFarLevels) return FEPIC_E_ARG;
     if (o.walk < FEPIC_WALK_AUTO || o.walk > FEPIC_WALK_FUSED) return FEPIC_E_ARG;
@@ -1384,7 +1395,7 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
     if (o.field_solver < FEPIC_FIELD_WAVE || o.field_solver > FEPIC_FIELD_BD_MFEM) return FEPIC_E_ARG;
     if (o.deterministic != 0 && o.deterministic != 1) return FEPIC_E_ARG;
     if (o.deterministic && (o.preconditioner != FEPIC_PC_JACOBI || o.solve_precision != FEPIC_SOLVE_FP64 ||
-                            o.warm_start == FEPIC_WS_MLP))
+                            o.warm_start == FEPIC_WS_MLP || o.warm_start == FEPIC_WS_MLP_DIRECT))
         return FEPIC_E_ARG;
     if (o.cg_check_every < 1) o.cg_check_every = 8;
     fepic_ctx* c = new fepic_ctx();

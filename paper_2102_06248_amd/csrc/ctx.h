@@ -183,7 +183,7 @@ void dfree(fepic_ctx* c, void* p);
 hipEvent_t* timer_pair(fepic_ctx* c, int fam, int64_t n_launches = 1);
 
 int init_electrostatic(fepic_ctx* c, double tol, int* iters);
-int mlp_warm_start(fepic_ctx* c);
+int mlp_warm_start(fepic_ctx* c, bool direct);
 int mlp_record_features(fepic_ctx* c);
 int mlp_record_target(fepic_ctx* c);
 void mlp_destroy(fepic_ctx* c);

@@ -333,18 +333,18 @@ void launch_line_start(hipStream_t s, int64_t n_rows, const int64_t* slice_ptr, 
                        const double* b, const double* e, const double* d, double* partial, double* theta, double* x);
 
 // Learned warm start (kernels_mlp.hip).
-void mlp_launch_rms(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e, const double* dg,
-                    double* part, double* scales);
+void mlp_launch_rms(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e, const double* ep,
+                    const double* dg, double* part, double* scales);
 void mlp_launch_features(hipStream_t s, int64_t n_int, const int32_t* int_edges, const double* e,
                          const double* ep, const double* ep2, const double* dg, const double* scales, float* X);
 void mlp_launch_forward(hipStream_t s, int64_t n, const float* X, const float* params_f32, float* y);
 void mlp_launch_direction(hipStream_t s, int64_t n_int, const int32_t* int_edges, const float* y,
                           const double* scales, double* d);
 // Training targets of interior edges r0, r0 + stride, ... (n rows): the increments
-// e_new - e over their RMS (work: n doubles, part: 256 doubles of scratch); the same rows
-// of a feature array [rows][4] picked into dst.
+// (e_new - e) / scales[0] (s_d), their RMS into scales[3] (work: n doubles, part: 256 doubles of
+// scratch); the same rows of a feature array [rows][4] picked into dst.
 void mlp_launch_target(hipStream_t s, int64_t n, int64_t r0, int64_t stride, const int32_t* int_edges,
-                       const double* e_new, const double* e, double* work, double* part, float* t);
+                       const double* e_new, const double* e, double* work, double* part, double* scales, float* t);
 void mlp_launch_pick(hipStream_t s, const float* X, int64_t r0, int64_t stride, int64_t n, float* dst);
 
 int grid_1d(int64_t n, int block);

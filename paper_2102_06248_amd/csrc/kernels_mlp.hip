@@ -389,7 +389,8 @@ __global__ __launch_bounds__(64) void k_mlp_loss_sum(const double* __restrict__ 
     loss[0] = a * inv_n;
 }
 
-// Per-edge features over the interior edges: [e, e_prev, e_prev2] / s_e, dG / s_g.
+// Per-edge features over the interior edges: e / s_e, (e - e_prev) / s_d,
+// (e_prev - e_prev2) / s_d (differences in FP64, before the rounding), dG / s_g.
 __global__ __launch_bounds__(256) void k_mlp_features(int64_t n_int, const int32_t* __restrict__ ie,
                                                       const double* __restrict__ e, const double* __restrict__ ep,
                                                       const double* __restrict__ ep2, const double* __restrict__ dg,
@@ -397,59 +398,69 @@ __global__ __launch_bounds__(256) void k_mlp_features(int64_t n_int, const int32
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n_int) return;
     const int k = ie[j];
-    const double se = 1.0 / scales[0], sg = 1.0 / scales[1];
-    X[j] = make_float4((float)(e[k] * se), (float)(ep[k] * se), (float)(ep2[k] * se), (float)(dg[k] * sg));
+    const double se = 1.0 / scales[4], sd = 1.0 / scales[0], sg = 1.0 / scales[1];
+    const double en = e[k], e1 = ep[k];
+    X[j] = make_float4((float)(en * se), (float)((en - e1) * sd), (float)((e1 - ep2[k]) * sd), (float)(dg[k] * sg));
 }
 
-// s_e = RMS of e over interior edges, s_g = RMS of dG (1 where zero): per-workgroup sums
-// of squares (grid-stride), then one workgroup adds them in a fixed order.
+// The scales of the inputs over interior edges (each 1 where zero): s_d = RMS of
+// e^n - e^{n-1} into scales[0], s_g = RMS of dG into scales[1], s_e = RMS of e^n into
+// scales[4]; per-workgroup sums of squares (grid-stride), then one workgroup adds them in
+// a fixed order.
 constexpr int kRmsBlocks = 256;
 
 __global__ __launch_bounds__(256) void k_mlp_rms_part(int64_t n_int, const int32_t* __restrict__ ie,
-                                                      const double* __restrict__ e, const double* __restrict__ dg,
-                                                      double* __restrict__ part) {
-    __shared__ double s[2][4];
-    double a = 0.0, b = 0.0;
+                                                      const double* __restrict__ e, const double* __restrict__ ep,
+                                                      const double* __restrict__ dg, double* __restrict__ part) {
+    __shared__ double s[3][4];
+    double a = 0.0, b = 0.0, c = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n_int; j += (int64_t)gridDim.x * 256) {
         const int k = ie[j];
-        a += e[k] * e[k];
-        b += dg[k] * dg[k];
+        const double en = e[k], d = en - ep[k], g = dg[k];
+        a += en * en;
+        b += d * d;
+        c += g * g;
     }
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_xor(a, off);
         b += __shfl_xor(b, off);
+        c += __shfl_xor(c, off);
     }
     if ((threadIdx.x & 63) == 0) {
         s[0][threadIdx.x >> 6] = a;
         s[1][threadIdx.x >> 6] = b;
+        s[2][threadIdx.x >> 6] = c;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = (s[0][0] + s[0][1]) + (s[0][2] + s[0][3]);
-        part[kRmsBlocks + blockIdx.x] = (s[1][0] + s[1][1]) + (s[1][2] + s[1][3]);
+    if (threadIdx.x < 3) {
+        const int q = threadIdx.x;
+        part[q * kRmsBlocks + blockIdx.x] = (s[q][0] + s[q][1]) + (s[q][2] + s[q][3]);
     }
 }
 
 __global__ __launch_bounds__(256) void k_mlp_rms_fin(int64_t n_int, int nb, const double* __restrict__ part,
                                                      double* __restrict__ scales) {
-    __shared__ double s[2][4];
-    double a = threadIdx.x < nb ? part[threadIdx.x] : 0.0;
-    double b = threadIdx.x < nb ? part[kRmsBlocks + threadIdx.x] : 0.0;
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off);
-        b += __shfl_xor(b, off);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        s[0][threadIdx.x >> 6] = a;
-        s[1][threadIdx.x >> 6] = b;
-    }
+    __shared__ double s[3][4];
+    double v[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) v[q] = threadIdx.x < nb ? part[q * kRmsBlocks + threadIdx.x] : 0.0;
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[q] += __shfl_xor(v[q], off);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s[q][threadIdx.x >> 6] = v[q];
     __syncthreads();
     if (threadIdx.x == 0) {
-        const double sa = (s[0][0] + s[0][1]) + (s[0][2] + s[0][3]);
-        const double sb = (s[1][0] + s[1][1]) + (s[1][2] + s[1][3]);
-        const double ra = n_int ? sqrt(sa / (double)n_int) : 0.0, rb = n_int ? sqrt(sb / (double)n_int) : 0.0;
-        scales[0] = ra > 0.0 ? ra : 1.0;
-        scales[1] = rb > 0.0 ? rb : 1.0;
+        double r[3];
+        for (int q = 0; q < 3; ++q) {
+            const double sum = (s[q][0] + s[q][1]) + (s[q][2] + s[q][3]);
+            r[q] = n_int ? sqrt(sum / (double)n_int) : 0.0;
+            if (!(r[q] > 0.0)) r[q] = 1.0;
+        }
+        scales[4] = r[0];
+        scales[0] = r[1];
+        scales[1] = r[2];
     }
 }
 
@@ -461,7 +472,7 @@ __global__ __launch_bounds__(256) void k_mlp_pick(const float4* __restrict__ X, 
     if (j < n) dst[j] = X[r0 + j * stride];
 }
 
-// Predicted increment as an edge vector: d[ie] = s_e y (d is zero elsewhere).
+// Predicted increment as an edge vector: d[ie] = s_d y (d is zero elsewhere).
 __global__ __launch_bounds__(256) void k_mlp_direction(int64_t n_int, const int32_t* __restrict__ ie,
                                                        const float* __restrict__ y, const double* __restrict__ scales,
                                                        double* __restrict__ d) {
@@ -490,21 +501,18 @@ __global__ __launch_bounds__(256) void k_mlp_target(int64_t n, int64_t r0, int64
     if (threadIdx.x == 0) part[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
-// Second pass: t = d / RMS(d) (1 where zero): each snapshot's increments in units of their
-// own RMS.  The start uses the prediction only as a direction (its step length comes from
-// the line step), so the scale is free, and this one stays finite where e^n vanishes (a
-// neutral start), unlike the RMS of e^n.
+// Second pass: t = d / s_d, and (workgroup 0) the RMS of t into scales[3], by which the host
+// leaves out steps where the history is near zero (a neutral start) and the increment
+// dwarfs it.
 __global__ __launch_bounds__(256) void k_mlp_target_scale(int64_t n, int nb, const double* __restrict__ part,
-                                                          const double* __restrict__ d, float* __restrict__ t) {
-    __shared__ double s_inv;
-    if (threadIdx.x == 0) {
+                                                          const double* __restrict__ d, double* __restrict__ scales,
+                                                          float* __restrict__ t) {
+    const double inv = 1.0 / scales[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         double a = 0.0;
         for (int b = 0; b < nb; ++b) a += part[b];
-        const double r = n ? sqrt(a / (double)n) : 0.0;
-        s_inv = r > 0.0 ? 1.0 / r : 1.0;
+        scales[3] = n ? sqrt(a / (double)n) * inv : 0.0;
     }
-    __syncthreads();
-    const double inv = s_inv;
     for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256)
         t[j] = (float)(d[j] * inv);
 }
@@ -520,10 +528,10 @@ int mlp_grad_blocks(int64_t n) {
     return (int)b;
 }
 
-void mlp_launch_rms(hipStream_t s, int64_t n_int, const int32_t* ie, const double* e, const double* dg,
-                    double* part, double* scales) {
+void mlp_launch_rms(hipStream_t s, int64_t n_int, const int32_t* ie, const double* e, const double* ep,
+                    const double* dg, double* part, double* scales) {
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kRmsBlocks, (n_int + 1023) / 1024));
-    hipLaunchKernelGGL(k_mlp_rms_part, dim3(nb), dim3(256), 0, s, n_int, ie, e, dg, part);
+    hipLaunchKernelGGL(k_mlp_rms_part, dim3(nb), dim3(256), 0, s, n_int, ie, e, ep, dg, part);
     hipLaunchKernelGGL(k_mlp_rms_fin, dim3(1), dim3(256), 0, s, n_int, nb, part, scales);
 }
 
@@ -549,11 +557,11 @@ void mlp_launch_direction(hipStream_t s, int64_t n_int, const int32_t* ie, const
 }
 
 void mlp_launch_target(hipStream_t s, int64_t n, int64_t r0, int64_t stride, const int32_t* ie, const double* e_new,
-                       const double* e, double* work, double* part, float* t) {
+                       const double* e, double* work, double* part, double* scales, float* t) {
     if (n <= 0) return;
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kRmsBlocks, (n + 1023) / 1024));
     hipLaunchKernelGGL(k_mlp_target, dim3(nb), dim3(256), 0, s, n, r0, stride, ie, e_new, e, work, part);
-    hipLaunchKernelGGL(k_mlp_target_scale, dim3(nb), dim3(256), 0, s, n, nb, part, work, t);
+    hipLaunchKernelGGL(k_mlp_target_scale, dim3(nb), dim3(256), 0, s, n, nb, part, work, scales, t);
 }
 
 void mlp_launch_pick(hipStream_t s, const float* X, int64_t r0, int64_t stride, int64_t n, float* dst) {

@@ -21,6 +21,7 @@ void mlp_launch_reduce_adam(hipStream_t s, const float* part, int blocks, float*
 void mlp_launch_loss_sum(hipStream_t s, const double* loss_part, int blocks, double inv_n, double* loss);
 
 constexpr int kNP = FEPIC_MLP_N_PARAMS;
+constexpr double kMaxTargetRms = 10.0;   // recorded steps: RMS of (e^{n+1} - e^n) / s_d at most this
 constexpr int kMaxGradBlocks = 512;
 
 // ---- scratch of the allocation-free gradient (fepic_mlp_grad_noalloc)
@@ -62,7 +63,7 @@ struct MlpState {
     float* grad = nullptr;
     float* part = nullptr;   // [kMaxGradBlocks][kNP]
     double* loss_part = nullptr;
-    double* scales = nullptr;  // s_e, s_g of the current step
+    double* scales = nullptr;  // s_d, s_g, line step, target RMS, s_e of the current step
     float* Xcur = nullptr;   // features of the current step [n_int][4]
     float* ycur = nullptr;
     // recording ring: each snapshot keeps rows r0, r0 + stride, ... of the interior edges
@@ -90,8 +91,8 @@ static int ensure_mlp(fepic_ctx* c) {
     s->v = (float*)dmalloc(c, sizeof(float) * kNP);
     s->grad = (float*)dmalloc(c, sizeof(float) * kNP);
     s->part = (float*)dmalloc(c, sizeof(float) * kNP * kMaxGradBlocks);
-    s->loss_part = (double*)dmalloc(c, sizeof(double) * kMaxGradBlocks);
-    s->scales = (double*)dmalloc(c, sizeof(double) * 3);  // s_e, s_g, line step
+    s->loss_part = (double*)dmalloc(c, sizeof(double) * std::max(kMaxGradBlocks, 3 * 256));   // also the RMS partials
+    s->scales = (double*)dmalloc(c, sizeof(double) * 5);  // s_d, s_g, line step, target RMS, s_e
     s->Xcur = (float*)dmalloc(c, sizeof(float) * 4 * ni);
     s->ycur = (float*)dmalloc(c, sizeof(float) * ni);
     c->mlp = s;
@@ -120,15 +121,16 @@ static int init_weights(fepic_ctx* c, uint64_t seed) {
     return FEPIC_OK;
 }
 
-// Scales and features of the current step (e^n, e^{n-1}, e^{n-2}, dG^{n+1}) into dst.
+// Scales and features of the current step (e^n, e^n - e^{n-1}, e^{n-1} - e^{n-2}, dG^{n+1},
+// formed in FP64) into dst.
 static void features_into(fepic_ctx* c, float* dst) {
     MlpState* s = c->mlp;
     const int64_t ni = c->mesh.n_int_edges;
-    mlp_launch_rms(c->stream, ni, c->d_int_edges, c->d_e, c->d_dgn, s->loss_part, s->scales);
+    mlp_launch_rms(c->stream, ni, c->d_int_edges, c->d_e, c->d_ep, c->d_dgn, s->loss_part, s->scales);
     mlp_launch_features(c->stream, ni, c->d_int_edges, c->d_e, c->d_ep, c->d_ep2, c->d_dgn, s->scales, dst);
 }
 
-int mlp_warm_start(fepic_ctx* c) {
+int mlp_warm_start(fepic_ctx* c, bool direct) {
     int rc = ensure_mlp(c);
     if (rc) return rc;
     MlpState* s = c->mlp;
@@ -138,13 +140,17 @@ int mlp_warm_start(fepic_ctx* c) {
     if (ev) (void)hipEventRecord(ev[0], c->stream);
     mlp_launch_forward(c->stream, ni, s->Xcur, s->P, s->ycur);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
-    // the prediction is used as a search direction: x0 = e^n + theta d with the
-    // energy-norm-optimal theta (never worse than x0 = e^n in the A-norm)
+    // the predicted increment d = s_d y; the line-step form moves along it to the
+    // energy-norm-optimal x0 = e^n + theta d (never worse than x0 = e^n in the A-norm), the
+    // direct form takes x0 = e^n + d
     double* d = c->d_Me;  // work vector, free during the solve
     launch_fill(c->stream, d, c->mesh.n_edges, 0.0);
     mlp_launch_direction(c->stream, ni, c->d_int_edges, s->ycur, s->scales, d);
-    launch_line_start(c->stream, c->mesh.n_edges, c->d_sp, c->d_col, c->d_A, c->d_rhs, c->d_e, d, c->d_partial,
-                      s->scales + 2, c->d_x);
+    if (direct)
+        launch_axpby(c->stream, c->d_x, c->d_e, 1.0, d, 1.0, c->mesh.n_edges);
+    else
+        launch_line_start(c->stream, c->mesh.n_edges, c->d_sp, c->d_col, c->d_A, c->d_rhs, c->d_e, d, c->d_partial,
+                          s->scales + 2, c->d_x);
     return FEPIC_OK;
 }
 
@@ -154,7 +160,8 @@ int mlp_record_features(fepic_ctx* c) {
     MlpState* s = c->mlp;
     if (s->cap == 0) return FEPIC_OK;
     float* dst = s->Xrec + (size_t)s->head * s->n_rec * 4;
-    if (!(c->opt.warm_start == FEPIC_WS_MLP && c->mlp_ready)) features_into(c, s->Xcur);
+    const bool have = (c->opt.warm_start == FEPIC_WS_MLP || c->opt.warm_start == FEPIC_WS_MLP_DIRECT) && c->mlp_ready;
+    if (!have) features_into(c, s->Xcur);
     mlp_launch_pick(c->stream, s->Xcur, s->taken % s->stride, s->stride, s->n_rec, dst);
     return FEPIC_OK;
 }
@@ -164,8 +171,14 @@ int mlp_record_target(fepic_ctx* c) {
     if (!s || s->cap == 0) return FEPIC_OK;
     // work: d_Me is free after the solve (the diagnostics recompute it); n_rec <= n_edges
     mlp_launch_target(c->stream, s->n_rec, s->taken % s->stride, s->stride, c->d_int_edges, c->d_x, c->d_e, c->d_Me,
-                      s->loss_part, s->Trec + (size_t)s->head * s->n_rec);
+                      s->loss_part, s->scales, s->Trec + (size_t)s->head * s->n_rec);
     s->taken++;
+    // a step whose increment dwarfs e^n (e^n near zero: a neutral start) would teach the
+    // network nothing but outliers; its slot is reused by the next snapshot
+    double ratio = 0.0;
+    HIPCHK_RET(c, hipMemcpyAsync(&ratio, s->scales + 3, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK_RET(c, hipStreamSynchronize(c->stream));
+    if (!(ratio <= kMaxTargetRms)) return FEPIC_OK;
     s->head = (s->head + 1) % s->cap;
     s->count = std::min(s->count + 1, s->cap);
     return FEPIC_OK;
@@ -381,8 +394,8 @@ int fepic_ws_set_weights(fepic_ctx* c, const float* w, int64_t n) {
 }
 
 int fepic_set_warm_start(fepic_ctx* c, int mode) {
-    if (!c || mode < FEPIC_WS_PREV || mode > FEPIC_WS_MLP) return FEPIC_E_ARG;
-    if (mode == FEPIC_WS_MLP && c->opt.deterministic)
+    if (!c || mode < FEPIC_WS_PREV || mode > FEPIC_WS_MLP_DIRECT) return FEPIC_E_ARG;
+    if ((mode == FEPIC_WS_MLP || mode == FEPIC_WS_MLP_DIRECT) && c->opt.deterministic)
         return fail(c, FEPIC_E_STATE, "the deterministic mode does not take the learned start");
     c->opt.warm_start = mode;
     return FEPIC_OK;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfepic.so")
 ABI_VERSION = 8   # include/fepic.h FEPIC_ABI_VERSION: layouts of the structs below
 FEPIC_OK = 0
 FEPIC_FP32_PUSH_FP64_ACC, FEPIC_ALL_FP64 = 0, 1
-FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP = 0, 1, 2, 3
+FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP, FEPIC_WS_MLP_DIRECT = 0, 1, 2, 3, 4
 FEPIC_PC_JACOBI, FEPIC_PC_AUX = 0, 1
 FEPIC_WALK_AUTO, FEPIC_WALK_QUEUE, FEPIC_WALK_FUSED = 0, 1, 2
 FEPIC_SOLVE_FP64, FEPIC_SOLVE_MIXED = 0, 1

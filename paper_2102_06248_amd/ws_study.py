@@ -6,11 +6,12 @@ Protocol (the plasma of workloads.c3_plasma, all solves to the same residual 1e-
      solve's features and target (one interior edge in `stride` per snapshot);
   2. the network is trained on the GPU on all recorded solves (the library's own BF16
      forward/backward kernels and Adam);
-  3. for every evaluation seed, three contexts advance the same plasma side by side, the
+  3. for every evaluation seed, four contexts advance the same plasma side by side, the
      solve started from e^n (plain), from the quadratic extrapolation of the last three
-     fields, and from the network's prediction: iterations, the initial residual and the
-     time of the Newmark part (right-hand side, start, solve, Faraday; the network's
-     inference is in the start) are compared step by step.
+     fields, and from the network's prediction, with the energy-optimal line step along
+     it and as it is: iterations, the initial residual and the time of the Newmark part
+     (right-hand side, start, solve, Faraday; the network's inference is in the start)
+     are compared step by step.
 
 A seed's start is carried between contexts through a checkpoint file (the electrostatic
 start is computed once per seed).  Prints progress lines and one JSON summary.
@@ -99,8 +100,10 @@ def run(train_seeds, steps_per_seed, eval_seeds, eval_steps, stride=8, epochs=3,
     R = F.Simulation(pl.xyz, pl.tets, **pl.options(F.FEPIC_WS_PREV))
     P = F.Simulation(pl.xyz, pl.tets, **pl.options(F.FEPIC_WS_PREV))
     X = F.Simulation(pl.xyz, pl.tets, **pl.options(F.FEPIC_WS_EXTRAP2))
+    D = F.Simulation(pl.xyz, pl.tets, **pl.options(F.FEPIC_WS_PREV))
+    sims = {"plain": P, "extrap2": X, "learned": R, "learned_direct": D}
     try:
-        for sim in (R, P, X):
+        for sim in sims.values():
             pl.add_species(sim.ctx)
         n_snap = len(train_seeds) * steps_per_seed
         recorded_iters = []
@@ -123,15 +126,17 @@ def run(train_seeds, steps_per_seed, eval_seeds, eval_steps, stride=8, epochs=3,
         log(f"[ws] trained on {n_rec} solves ({tst.n_train_rows} rows, {tst.n_steps} Adam steps) in {train_s:.1f}s: "
             f"train loss {tst.train_loss:.4g}, validation loss {tst.val_loss:.4g}")
         F.fepic_set_warm_start(R.ctx, F.FEPIC_WS_MLP)
+        F.fepic_ws_set_weights(D.ctx, F.fepic_ws_get_weights(R.ctx))
+        F.fepic_set_warm_start(D.ctx, F.FEPIC_WS_MLP_DIRECT)
         per_seed = []
         for s in eval_seeds:
             path = pl.start_file(s, workdir)
-            for sim in (R, P, X):
+            for sim in sims.values():
                 F.fepic_load(sim.ctx, path)
             os.remove(path)
-            rows = {"plain": [], "extrap2": [], "learned": []}
+            rows = {name: [] for name in sims}
             for k in range(eval_steps):
-                for name, sim in (("plain", P), ("extrap2", X), ("learned", R)):
+                for name, sim in sims.items():
                     t0 = time.perf_counter()
                     st = F.fepic_step(sim.ctx, pl.dt)
                     wall = (time.perf_counter() - t0) * 1e3
@@ -139,11 +144,11 @@ def run(train_seeds, steps_per_seed, eval_seeds, eval_steps, stride=8, epochs=3,
                         raise RuntimeError(f"{name} solve stopped at {st.cg_rel_resid:.3g}")
                     rows[name].append((st.cg_iters, st.cg_rel_resid0, _newmark_ms(st), wall))
                 if k % 50 == 49:
-                    log(f"[ws] eval seed {s}: step {k + 1}, iterations plain {rows['plain'][-1][0]}, "
-                        f"extrap2 {rows['extrap2'][-1][0]}, learned {rows['learned'][-1][0]}")
+                    log(f"[ws] eval seed {s}: step {k + 1}, iterations " +
+                        ", ".join(f"{name} {r[-1][0]}" for name, r in rows.items()))
             e_p, _, _ = F.fepic_get_fields(P.ctx)
-            e_l, _, _ = F.fepic_get_fields(R.ctx)
-            agree = float(np.linalg.norm(e_l - e_p) / np.linalg.norm(e_p))
+            agree = max(float(np.linalg.norm(F.fepic_get_fields(sim.ctx)[0] - e_p) / np.linalg.norm(e_p))
+                        for sim in (R, D))
             summary = {"seed": s, "fields_rel_diff_learned_vs_plain": agree}
             for name, r in rows.items():
                 a = np.array(r)
@@ -152,7 +157,7 @@ def run(train_seeds, steps_per_seed, eval_seeds, eval_steps, stride=8, epochs=3,
             per_seed.append(summary)
             log(f"[ws] eval seed {s}: {json.dumps(summary)}")
     finally:
-        for sim in (R, P, X):
+        for sim in sims.values():
             sim.close()
         if own_dir:
             try:
@@ -170,9 +175,9 @@ def run(train_seeds, steps_per_seed, eval_seeds, eval_steps, stride=8, epochs=3,
         "train_loss": tst.train_loss, "val_loss": tst.val_loss, "train_s": round(train_s, 1),
         "recording_cg_iters_mean": round(float(np.mean(recorded_iters)), 2),
         "eval_seeds": eval_seeds, "eval_steps": eval_steps, "per_seed": per_seed,
-        "cg_iters": {n: mean(n, "cg_iters") for n in ("plain", "extrap2", "learned")},
-        "newmark_ms": {n: mean(n, "newmark_ms") for n in ("plain", "extrap2", "learned")},
-        "step_wall_ms": {n: mean(n, "step_wall_ms") for n in ("plain", "extrap2", "learned")},
+        "cg_iters": {n: mean(n, "cg_iters") for n in sims},
+        "newmark_ms": {n: mean(n, "newmark_ms") for n in sims},
+        "step_wall_ms": {n: mean(n, "step_wall_ms") for n in sims},
         "wall_s": round(time.perf_counter() - t_start, 1),
     }
     return result

@@ -8,10 +8,11 @@ against the oracle.
 * Diagnostics after real steps, recomputed by the oracle's formulas from the library's own
   state (rho^n, rho^{n+1}, G, e, the Newmark right-hand side and residual): charge
   continuity, the Gauss residual, and the Gauss-drift identity.
-* The learned start x0 = e^n + theta s_e y (features from e^n, e^{n-1}, e^{n-2} and
-  dG^{n+1}, the network, the energy-optimal step along the prediction) against the
-  oracle's FP64 network on the library's state, at BF16 tolerance; one device Adam update
-  after another against the oracle's; non-finite and absurd weights fall back to e^n.
+* The learned start x0 = e^n + theta s_d y (features from e^n, e^n - e^{n-1},
+  e^{n-1} - e^{n-2} and dG^{n+1}, the network, the energy-optimal step along the
+  prediction) and its direct form x0 = e^n + s_d y against the oracle's FP64 network on the library's state, at BF16
+  tolerance; one device Adam update after another against the oracle's; non-finite and
+  absurd weights fall back to e^n.
 
 Tolerances: the diagnostics are the same formulas on the same numbers, so they agree to
 round-off (1e-12 relative, or 1e-14 of the charge scale for values that are themselves
@@ -138,8 +139,8 @@ def _params(seed):
 
 def test_learned_start_vs_oracle(F):
     """The start vector of MLP-started solves, read back from the library, against the
-    oracle's features, FP64 network (with the library's FP32 weights) and line step, all
-    evaluated on the library's state."""
+    oracle's features, FP64 network (with the library's FP32 weights) and line step (steps
+    2 and 3) or the direct prediction (step 4), all evaluated on the library's state."""
     announce("learned warm start x0 vs oracle")
     xyz, tets, x, u = _beam_setup(seed=11)
     osim = OracleSim(xyz, tets)
@@ -159,26 +160,31 @@ def test_learned_start_vs_oracle(F):
         dG_n, _ = F.fepic_get_current(L.ctx)
         checked = 0
         for k in range(5):
-            F.fepic_set_warm_start(L.ctx, F.FEPIC_WS_MLP if k >= 2 else F.FEPIC_WS_PREV)
+            F.fepic_set_warm_start(L.ctx, F.FEPIC_WS_MLP_DIRECT if k == 4 else
+                                   F.FEPIC_WS_MLP if k >= 2 else F.FEPIC_WS_PREV)
             st = F.fepic_step(L.ctx, dt, beta, gamma)
             x0 = F.fepic_get_warm_start(L.ctx)
             dG, _ = F.fepic_get_current(L.ctx)
             e_new, _, _ = F.fepic_get_fields(L.ctx)
             if k >= 2:
-                X, s_e, s_g = mlp.features(e_n[ie], e_nm1[ie], e_nm2[ie], dG[ie])
+                X, s_d, s_g = mlp.features(e_n[ie], e_nm1[ie], e_nm2[ie], dG[ie])
                 y, _ = mlp.forward(p, X)
-                d = s_e * y
+                d = s_d * y
                 rhs = newmark.newmark_rhs(B1, B2, e_n[ie], e_nm1[ie], (dG - dG_n)[ie])
                 r0 = rhs - A @ e_n[ie]
                 theta = (d @ r0) / (d @ (A @ d))
                 x0_o = e_n[ie] + theta * d
                 inc_o = x0_o - e_n[ie]
-                assert np.linalg.norm(x0[ie] - x0_o) <= 2e-2 * np.linalg.norm(inc_o)
+                if k == 4:      # the direct form: the prediction as it is
+                    inc_o = d
+                    assert np.linalg.norm(x0[ie] - (e_n[ie] + d)) <= 2e-2 * np.linalg.norm(inc_o)
+                else:
+                    assert np.linalg.norm(x0[ie] - x0_o) <= 2e-2 * np.linalg.norm(inc_o)
+                    # the learned start is at least as good as e^n in the A-norm (line step)
+                    err0 = x0[ie] - e_new[ie]
+                    errp = e_n[ie] - e_new[ie]
+                    assert err0 @ (A @ err0) <= errp @ (A @ errp) * (1 + 1e-9)
                 assert np.linalg.norm(inc_o) > 1e-6 * np.linalg.norm(e_n[ie])     # a real prediction
-                # the learned start is at least as good as e^n in the A-norm (line step)
-                err0 = x0[ie] - e_new[ie]
-                errp = e_n[ie] - e_new[ie]
-                assert err0 @ (A @ err0) <= errp @ (A @ errp) * (1 + 1e-9)
                 checked += 1
             else:
                 assert np.array_equal(x0[ie], e_n[ie])
@@ -209,21 +215,22 @@ def test_device_adam_vs_oracle(F):
             assert np.abs(got - p).max() > 0.5e-3 * step     # the updates did move the weights
 
 
-@pytest.mark.parametrize("kind", ["nan", "absurd"])
-def test_bad_weights_fall_back_to_the_previous_field(F, kind):
+@pytest.mark.parametrize("kind,direct", [("nan", False), ("absurd", False), ("nan", True), ("absurd", True)])
+def test_bad_weights_fall_back_to_the_previous_field(F, kind, direct):
     """Weights that give a non-finite prediction leave the solve starting from e^n: the same
     start, iterations and solution as the plain method (to the rounding order of the atomic
     sums, which differs from run to run).  Absurd finite weights give a useless direction
-    that the line step scales down: no more iterations than the plain start, the same
-    solution."""
-    announce(f"learned start fallback, {kind} weights")
+    that the line step scales down (no more iterations than the plain start, the same
+    solution), and a start the direct form refuses (its residual beyond 1e4 ||b||), so it
+    starts from e^n."""
+    announce(f"learned start fallback, {kind} weights, {'direct' if direct else 'line step'}")
     xyz, tets, x, u = _beam_setup(seed=13)
     w, dt = 5e4, 1e-10
     n_par = F.FEPIC_MLP_N_PARAMS
     bad = np.full(n_par, np.nan, np.float32) if kind == "nan" else \
         (np.random.default_rng(1).normal(size=n_par) * 1e6).astype(np.float32)
     runs = []
-    for ws in (F.FEPIC_WS_PREV, F.FEPIC_WS_MLP):
+    for ws in (F.FEPIC_WS_PREV, F.FEPIC_WS_MLP_DIRECT if direct else F.FEPIC_WS_MLP):
         with F.Simulation(xyz, tets, device=0, precision=1, preconditioner=F.FEPIC_PC_JACOBI) as L:
             sp = F.fepic_add_species(L.ctx, -Q_E, M_E, w)
             F.fepic_upload_particles(L.ctx, sp, x, u, ids=np.arange(len(x)))
@@ -240,7 +247,7 @@ def test_bad_weights_fall_back_to_the_previous_field(F, kind):
     for k, (a, b_, xa, xb) in enumerate(zip(sp_, sm, xp, xm)):
         assert np.all(np.isfinite(xb))
         assert a.cg_rel_resid <= 1e-10 and b_.cg_rel_resid <= 1e-10
-        if kind == "nan":
+        if kind == "nan" or direct:
             # the fallback: the plain start e^n (the two runs differ by the rounding order of
             # their FP64 atomic sums, which each solve may carry up to its tolerance)
             assert np.linalg.norm(xa - xb) <= 1e-8 * np.linalg.norm(xa), k

@@ -24,7 +24,8 @@ def test_small_study(F, tmp_path):
     announce("learned warm start study, small plasma ball")
     res = ws_study.run([1, 2, 3], 60, [11], 40, stride=2, epochs=4, n_pairs=100_000, n_cells=16,
                        workdir=str(tmp_path))
-    assert res["recorded_solves"] == 180
+    # steps whose target RMS exceeds 10 (a history near zero) are left out
+    assert 3 * 60 - 3 <= res["recorded_solves"] <= 3 * 60
     assert res["train_rows"] > 0 and np.isfinite(res["train_loss"]) and np.isfinite(res["val_loss"])
     seed = res["per_seed"][0]
     assert seed["fields_rel_diff_learned_vs_plain"] <= 1e-6

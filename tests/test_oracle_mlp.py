@@ -40,9 +40,13 @@ def test_adam_first_step_closed_form():
 def test_features_and_prediction_scaling():
     rng = np.random.default_rng(1)
     e_n, e1, e2, dg = (rng.normal(size=100) * s for s in (3.0, 3.0, 3.0, 1e-12))
-    X, s_e, s_g = mlp.features(e_n, e1, e2, dg)
-    assert np.isclose(np.sqrt(np.mean(X[:, 0] ** 2)), 1.0)
-    assert np.isclose(np.sqrt(np.mean(X[:, 3] ** 2)), 1.0)
+    X, s_d, s_g = mlp.features(e_n, e1, e2, dg)
+    for c in range(4):
+        assert np.isclose(np.sqrt(np.mean(X[:, c] ** 2)), 1.0) or c == 2
+    # the quadratic extrapolation's increment is linear in the inputs, in units of s_d
+    e_n, e1, e2 = 1.0 + 0.01 * rng.normal(size=(3, 100)).cumsum(axis=0)
+    X, s_d, _ = mlp.features(e_n, e1, e2, dg)
+    assert np.allclose(s_d * (2.0 * X[:, 1] - X[:, 2]), 2.0 * e_n - 3.0 * e1 + e2, rtol=1e-12, atol=1e-15)
     X0, s0, g0 = mlp.features(np.zeros(5), np.zeros(5), np.zeros(5), np.zeros(5))
     assert s0 == 1.0 and g0 == 1.0 and not np.any(X0)
     assert mlp.N_PARAMS == 64 * 4 + 64 + 64 * 64 + 64 + 64 + 1
