@@ -247,6 +247,43 @@ __device__ __forceinline__ void lds_add6(int* s_key, double* s_val, double* __re
 
 constexpr int log2_const(int v) { return v <= 1 ? 0 : 1 + log2_const(v / 2); }
 
+// Segmented inclusive sums across the wave of N doubles, a segment starting at every lane
+// with f != 0 (lane 0 always starts one): after it, the last lane of each segment holds the
+// segment's sum.  Steps of the Hillis-Steele scan by DPP moves: row shifts by 1, 2, 4 and 8
+// inside each row of 16 lanes, then the rows' running sums carried across by broadcasting
+// lane 15 (into rows 1 and 3) and lane 31 (into rows 2 and 3).  Lanes without a source
+// receive zeros, which neither add nor end a segment.  VALU moves, where shuffles would
+// be LDS permutes.  Every lane of the wave must take part.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xf, true);
+}
+
+template <int N, int kCtrl, int kRowMask>
+__device__ __forceinline__ void seg_step(double v[N], int& f) {
+    double o[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c)
+        o[c] = __hiloint2double(dpp_i32<kCtrl, kRowMask>(__double2hiint(v[c])),
+                                dpp_i32<kCtrl, kRowMask>(__double2loint(v[c])));
+    const int fo = dpp_i32<kCtrl, kRowMask>(f);
+    if (!f) {
+#pragma unroll
+        for (int c = 0; c < N; ++c) v[c] += o[c];
+    }
+    f |= fo;
+}
+
+template <int N>
+__device__ __forceinline__ void seg_sum_wave(double v[N], int f) {
+    seg_step<N, 0x111, 0xf>(v, f);   // row_shr:1
+    seg_step<N, 0x112, 0xf>(v, f);   // row_shr:2
+    seg_step<N, 0x114, 0xf>(v, f);   // row_shr:4
+    seg_step<N, 0x118, 0xf>(v, f);   // row_shr:8
+    seg_step<N, 0x142, 0xa>(v, f);   // row_bcast:15
+    seg_step<N, 0x143, 0xc>(v, f);   // row_bcast:31
+}
+
 // The six edge currents of one piece into the deterministic mode's accumulators.
 __device__ __forceinline__ void fix_add6(const PushParams& pp, const int32_t* e, const double v[6]) {
 #pragma unroll
@@ -341,11 +378,12 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? wa
     // would cost the first kernel occupancy)
     static_assert(kFused || kPB == kBlock, "the queue form fills regions of kBlock slots");
     static_assert(kFused || !kDet, "the deterministic form walks in place");
+    constexpr bool kTable = kFused && !kDet;
     constexpr int kBits = log2_const(8 * kPB);
-    constexpr int kSlots = (kFused && !kDet) ? (1 << kBits) : 1;
+    constexpr int kSlots = kTable ? (1 << kBits) : 1;
     __shared__ int s_key[kSlots];
     __shared__ double s_val[kSlots];
-    if (kFused && !kDet) {
+    if (kTable) {
         for (int k = threadIdx.x; k < kSlots; k += kPB) {
             s_key[k] = -1;
             s_val[k] = 0.0;
@@ -452,24 +490,10 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? wa
     } else {
         const int key = t0;
         const int prev_key = __shfl_up(key, 1);
-        int f = (lane == 0) || (key != prev_key);
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            double o[6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) o[c] = __shfl_up(first[c], off);
-            const int fo = __shfl_up(f, off);
-            if (lane >= off) {
-                if (!f) {
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) first[c] += o[c];
-                }
-                f |= fo;
-            }
-        }
+        seg_sum_wave<6>(first, (lane == 0) || (key != prev_key));
         const int next_key = __shfl_down(key, 1);
         if (key >= 0 && (lane == 63 || next_key != key)) {
-            if (kFused) {
+            if (kTable) {
                 lds_add6<kBits>(s_key, s_val, dg, blk[key].edge, first);
             } else {
                 const TetBlock<T>* bk = blk + key;
@@ -849,21 +873,7 @@ __global__ __launch_bounds__(kBlock) void k_rho(PArrays<T> p, int64_t n, const i
         }
     }
     const int prev_key = __shfl_up(key, 1);   // every lane takes part in the shuffle
-    int f = (lane == 0) || (key != prev_key);
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        double o[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) o[c] = __shfl_up(v[c], off);
-        const int fo = __shfl_up(f, off);
-        if (lane >= off) {
-            if (!f) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) v[c] += o[c];
-            }
-            f |= fo;
-        }
-    }
+    seg_sum_wave<4>(v, (lane == 0) || (key != prev_key));
     const int next_key = __shfl_down(key, 1);
     if (key >= 0 && (lane == 63 || next_key != key)) {
 #pragma unroll
