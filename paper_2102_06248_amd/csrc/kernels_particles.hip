@@ -23,12 +23,21 @@ constexpr int kBlock = 256;
 constexpr int LE_A[6] = {0, 0, 0, 1, 1, 2};
 constexpr int LE_B[6] = {1, 2, 3, 2, 3, 3};
 
+// a / sqrt(x) and a / x: for FP32 particles by the hardware's reciprocal square root and
+// reciprocal (about 1 ulp, no range scaling or refinement steps), for FP64 ones correctly
+// rounded
 template <typename T>
-__device__ __forceinline__ T tsqrt(T x);
+__device__ __forceinline__ T div_sqrt(T a, T x);
 template <>
-__device__ __forceinline__ float tsqrt<float>(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ float div_sqrt<float>(float a, float x) { return a * __builtin_amdgcn_rsqf(x); }
 template <>
-__device__ __forceinline__ double tsqrt<double>(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ double div_sqrt<double>(double a, double x) { return a / __builtin_sqrt(x); }
+template <typename T>
+__device__ __forceinline__ T tdiv(T a, T x);
+template <>
+__device__ __forceinline__ float tdiv<float>(float a, float x) { return a * __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double tdiv<double>(double a, double x) { return a / x; }
 
 __device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
 
@@ -101,20 +110,24 @@ __device__ __forceinline__ double pick4(int idx, const double v[4]) {
 // First exit of a straight piece from barycentric point ls along dl (d lambda over the
 // rest of the step): the smallest ls_k / (-dl_k) over faces with dl_k < 0, other than the
 // entry face; kb = -1 if the piece ends inside (t* >= 1).  Ties go to the smallest k.
+// The candidates are compared as fractions with positive denominators, by cross products
+// against the best so far (bn / bd, starting at 1 / 1), and only the winner's quotient is
+// divided out: one FP64 division per exit instead of one per candidate face.
 __device__ __forceinline__ void exit_search(const double ls[4], const double dl[4], int entry, double& best,
                                             int& kb) {
-    best = 1.0;
+    double bn = 1.0, bd = 1.0;
     kb = -1;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (k != entry && dl[k] < 0.0) {
-            const double tk = ls[k] / (-dl[k]);
-            if (tk < best) {
-                best = tk;
-                kb = k;
-            }
+        const double d = -dl[k];
+        if (k != entry && d > 0.0 && ls[k] * bd < bn * d) {
+            bn = ls[k];
+            bd = d;
+            kb = k;
         }
     }
+    best = 1.0;
+    if (kb >= 0) best = bn / bd;
 }
 
 // Barycentric coordinates in the neighbour across the face opposite local kb, whose far
@@ -393,18 +406,28 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? wa
     const int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x;
     const int lane = threadIdx.x & 63;
     if (n_live) n = min(n, (int64_t)*n_live);
+    // the particle's own words are loaded together with its tet index (one memory round
+    // trip before the tet record's), whether or not the particle is live
     int t0 = -1;
-    if (i < n) t0 = in.tet[i];
+    T l1 = T(0), l2 = T(0), l3 = T(0), u[3] = {T(0), T(0), T(0)};
+    if (i < n) {
+        t0 = in.tet[i];
+        l1 = in.l1[i];
+        l2 = in.l2[i];
+        l3 = in.l3[i];
+        u[0] = in.u0[i];
+        u[1] = in.u1[i];
+        u[2] = in.u2[i];
+    }
     double first[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int status = 0;       // 1 absorbed, 2 crossing cap
     bool cross = false;   // continues in k_cross
     double ln[4] = {0.0, 0.0, 0.0, 0.0}, frac = 0.0;
     T dx[3] = {T(0), T(0), T(0)};
     int tn = 0, q = 0;
+    int o_tet = -1;       // the slot's tet after this kernel
     if (t0 >= 0) {
         const TetBlock<T>* bp = blk + t0;
-        const T l1 = in.l1[i], l2 = in.l2[i], l3 = in.l3[i];
-        T u[3] = {in.u0[i], in.u1[i], in.u2[i]};
         T g[4][3];
         load_grads(bp, g);
         // gather: E = sum over edges e_ab (lambda_a grad l_b - lambda_b grad l_a)
@@ -422,16 +445,15 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? wa
         const T h = (T)pp.qm_half_dt;
         const T ic2 = (T)(1.0 / (kC * kC));
         T um[3] = {u[0] + h * E[0], u[1] + h * E[1], u[2] + h * E[2]};
-        const T gm = tsqrt<T>(T(1) + (um[0] * um[0] + um[1] * um[1] + um[2] * um[2]) * ic2);
-        const T hg = h / gm;
+        const T hg = div_sqrt<T>(h, T(1) + (um[0] * um[0] + um[1] * um[1] + um[2] * um[2]) * ic2);
         const T tv[3] = {hg * Bv[0], hg * Bv[1], hg * Bv[2]};
-        const T s2 = T(2) / (T(1) + tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
+        const T s2 = tdiv<T>(T(2), T(1) + tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
         const T up[3] = {um[0] + (um[1] * tv[2] - um[2] * tv[1]), um[1] + (um[2] * tv[0] - um[0] * tv[2]),
                          um[2] + (um[0] * tv[1] - um[1] * tv[0])};
         u[0] = um[0] + s2 * (up[1] * tv[2] - up[2] * tv[1]) + h * E[0];
         u[1] = um[1] + s2 * (up[2] * tv[0] - up[0] * tv[2]) + h * E[1];
         u[2] = um[2] + s2 * (up[0] * tv[1] - up[1] * tv[0]) + h * E[2];
-        const T ginv = T(1) / tsqrt<T>(T(1) + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic2);
+        const T ginv = div_sqrt<T>(T(1), T(1) + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic2);
         const T dtt = (T)pp.dt;
         dx[0] = dtt * u[0] * ginv;
         dx[1] = dtt * u[1] * ginv;
@@ -449,10 +471,10 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? wa
             T r[3];
             end_point(ls, dl, r, le);
             piece_current(pp.qw, ls, le, first);
-            out.tet[i] = t0;
-            out.l1[i] = r[0];
-            out.l2[i] = r[1];
-            out.l3[i] = r[2];
+            o_tet = t0;
+            l1 = r[0];
+            l2 = r[1];
+            l3 = r[2];
         } else {
 #pragma unroll
             for (int k = 0; k < 4; ++k) le[k] = (k == kb) ? 0.0 : ls[k] + best * dl[k];
@@ -460,25 +482,30 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? wa
             const int nb = bp->nbr[kb];
             if (nb < 0) {           // wall: absorbed after depositing up to it
                 status = 1;
-                out.tet[i] = -1;
             } else if (pp.cap < 1) {
                 status = 2;
-                out.tet[i] = -1;
             } else {
                 cross = true;
                 tn = nb >> 2;
                 q = nb & 3;
                 enter_neighbour(le, kb, q, ln);
                 frac = 1.0 - best;
+                o_tet = tn;
             }
         }
-        if (status == 0) {
-            out.u0[i] = u[0];
-            out.u1[i] = u[1];
-            out.u2[i] = u[2];   // the slot (and its id) is kept: ids are not copied
-        }
-    } else if (i < n) {
-        out.tet[i] = -1;
+    }
+    // every lane writes all six words of its slot and its tet, so that each store covers
+    // whole cache lines: a path that goes on into another tet has its end written later (in
+    // k_cross, or by the walk below); an absorbed or dead particle's words other than its
+    // tet (-1) are never read.  The slot's id is kept: ids are not copied.
+    if (i < n) {
+        out.tet[i] = o_tet;
+        out.l1[i] = l1;
+        out.l2[i] = l2;
+        out.l3[i] = l3;
+        out.u0[i] = u[0];
+        out.u1[i] = u[1];
+        out.u2[i] = u[2];
     }
 
     // first-piece currents: one sum per run of lanes sharing a tet, added by the run's last
@@ -516,18 +543,26 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? wa
         add_counters<kPB>(sc, sc, (status == 1) + na, (status == 2) + ncap, cnt);
         return;
     }
-    // compact the crossing lanes of the workgroup into its queue region
+    // compact the crossing lanes of the workgroup into its queue region; the counters here
+    // are flags (a path crossed, was absorbed, stopped at the cap), counted by ballots and
+    // summed over the workgroup's waves in the same LDS exchange as the queue offsets
     {
-        __shared__ int s_wc[kBlock / 64];
+        __shared__ int s_wc[kBlock / 64][3];
         const int w = threadIdx.x >> 6;
         const unsigned long long m = __ballot(cross);
-        if (lane == 0) s_wc[w] = (int)__popcll(m);
+        const unsigned long long m_abs = __ballot(status == 1);
+        const unsigned long long m_cap = __ballot(status == 2);
+        if (lane == 0) {
+            s_wc[w][0] = (int)__popcll(m);
+            s_wc[w][1] = (int)__popcll(m_abs);
+            s_wc[w][2] = (int)__popcll(m_cap);
+        }
         __syncthreads();
         int base = 0, total = 0;
 #pragma unroll
         for (int k = 0; k < kBlock / 64; ++k) {
-            base += (k < w) ? s_wc[k] : 0;
-            total += s_wc[k];
+            base += (k < w) ? s_wc[k][0] : 0;
+            total += s_wc[k][0];
         }
         if (cross) {
             const int64_t slot =
@@ -544,10 +579,25 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFused ? wa
             cq.tet[slot] = tn;
             cq.entry[slot] = q;
         }
-        if (threadIdx.x == 0) cq.wg_count[blockIdx.x] = total;
+        if (threadIdx.x == 0) {
+            cq.wg_count[blockIdx.x] = total;
+            unsigned int ta = 0, tp = 0;
+#pragma unroll
+            for (int k = 0; k < kBlock / 64; ++k) {
+                ta += s_wc[k][1];
+                tp += s_wc[k][2];
+            }
+            // a refused crossing (the cap) counts as a crossing, as in k_cross
+            const unsigned int tc = (unsigned int)total + tp;
+            PushCounters* slot = cnt + (blockIdx.x & (kCntSlots - 1));
+            if (tc) {
+                atomicAdd(&slot->n_crossings, (unsigned long long)tc);
+                atomicMax(&slot->max_crossings, 1u);
+            }
+            if (ta) atomicAdd(&slot->n_absorbed, ta);
+            if (tp) atomicAdd(&slot->n_cap, tp);
+        }
     }
-    const unsigned int c1 = (cross || status == 2) ? 1u : 0u;   // a refused crossing counts, as in k_cross
-    add_counters(c1, c1, status == 1, status == 2, cnt);
 }
 
 
@@ -564,11 +614,14 @@ __global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(walk_waves<T
     constexpr int kSlots = 1 << kBits;
     __shared__ int s_key[kSlots];
     __shared__ double s_val[kSlots];
+    // an empty queue region (no path of the first kernel's workgroup crossed a face) has
+    // nothing to walk, deposit or count: the whole workgroup leaves before the table
+    const int total = cq.wg_count[blockIdx.x];
+    if (total == 0) return;
     for (int k = threadIdx.x; k < kSlots; k += kB) {
         s_key[k] = -1;
         s_val[k] = 0.0;
     }
-    const int total = cq.wg_count[blockIdx.x];
     __syncthreads();
     unsigned int sc = 0, mc = 0, na = 0, ncap = 0;
     for (int j = threadIdx.x; j < total; j += kB) {
