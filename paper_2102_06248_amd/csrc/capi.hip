@@ -443,8 +443,16 @@ void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
         if (ev) (void)hipEventRecord(ev[0], c->stream);
         launch_push<T>(c->stream, parr<T>(s, s.cur), parr<T>(s, 1 - s.cur), s.n, (const TetBlock<T>*)c->d_blk,
                        c->d_dgn, pp, c->d_cnt_slots, s.sorted_pending ? s.d_nlive : nullptr, cqueue<T>(c),
-                       c->cross_share, c->opt.walk);
+                       c->cross_share, s.own_share, c->opt.walk);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
+        s.n_pushed = s.n;
+        launch_cnt_crossings(c->stream, c->d_cnt_slots, s.d_xcum);
+        const hipError_t xe = hipMemcpyAsync(s.h_xcum, s.d_xcum, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                             c->stream);
+        if (xe != hipSuccess) {
+            c->deferred_err = hip_fail(c, xe, "hipMemcpyAsync(crossing count)");
+            return;
+        }
     }
     if (fix) launch_fix_out(c->stream, fix, c->mesh.n_edges, scale, c->d_dgn);
     launch_cnt_finish(c->stream, c->d_cnt_slots, c->d_cnt);
@@ -1143,6 +1151,16 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
         int64_t n_all = 0;
         for (const auto& sp : c->species) n_all += sp.n;
         c->cross_share = n_all > 0 ? (double)st.n_crossings / (double)n_all : 1.0;
+        // each species' own share (the species of the Boris step count their crossings in
+        // turn; a species without particles keeps its last share)
+        unsigned long long prev = 0;
+        for (auto& sp : c->species) {
+            if (sp.n_pushed <= 0) continue;
+            const unsigned long long cum = *sp.h_xcum;
+            sp.own_share = cum >= prev ? (double)(cum - prev) / (double)sp.n_pushed : 1.0;
+            prev = cum;
+            sp.n_pushed = 0;
+        }
     }
     st.max_crossings = (int)c->h_cnt->max_crossings;
     st.n_absorbed = c->h_cnt->n_absorbed;
@@ -1433,6 +1451,7 @@ int fepic_destroy(fepic_ctx* c) {
         for (void* p : c->allocs) release(c, p);
         for (auto& s : c->species) {
             if (s.h_nlive) (void)hipHostFree(s.h_nlive);
+            if (s.h_xcum) (void)hipHostFree(s.h_xcum);
         }
         for (auto& t : c->timers)
             for (auto e : t.ev) (void)hipEventDestroy(e);
@@ -1819,8 +1838,11 @@ int fepic_add_species(fepic_ctx* c, double q, double m, double w, int* out) {
     s.m = m;
     s.w = w;
     s.d_nlive = dalloc<int32_t>(c, 1);
-    if (!s.d_nlive || hipHostMalloc((void**)&s.h_nlive, sizeof(int32_t)) != hipSuccess)
+    s.d_xcum = dalloc<unsigned long long>(c, 1);
+    if (!s.d_nlive || !s.d_xcum || hipHostMalloc((void**)&s.h_nlive, sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc((void**)&s.h_xcum, sizeof(unsigned long long)) != hipSuccess)
         return fail(c, FEPIC_E_OOM, "allocation failed");
+    *s.h_xcum = 0;
     c->species.push_back(s);
     if (out) *out = (int)c->species.size() - 1;
     return FEPIC_OK;

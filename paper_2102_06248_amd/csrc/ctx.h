@@ -35,6 +35,13 @@ struct Species {
     int idcur = 0;
     int32_t* d_nlive = nullptr;
     int32_t* h_nlive = nullptr;
+    // face crossings of the step so far, counted after this species' particle kernels (its
+    // own crossings are the difference to the previous species'), and the species' own
+    // crossings per particle at its last committed step
+    unsigned long long* d_xcum = nullptr;
+    unsigned long long* h_xcum = nullptr;
+    int64_t n_pushed = 0;
+    double own_share = 1.0;
     // Adams-Bashforth pusher: history [kAbStride][abh_cap] (component-major) and per-slot
     // AbMeta, each double-buffered.  The sorts move both (flipping abh_cur and abm_cur); a
     // step writes its meta to the other buffer, flipped at the commit with cur.

@@ -211,8 +211,10 @@ void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double*
 template <typename T>
 void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const TetBlock<T>* blk, double* dg,
                  PushParams pp, PushCounters* cnt, const int32_t* n_live, CrossQueue<T> cq, double cross_share,
-                 int walk);
+                 double own_share, int walk);
 void launch_cnt_finish(hipStream_t s, PushCounters* slots, PushCounters* out);
+// The face crossings the slots hold so far (summed over the slots) into *out.
+void launch_cnt_crossings(hipStream_t s, const PushCounters* slots, unsigned long long* out);
 template <typename T>
 void launch_locate(hipStream_t s, int64_t n, const double* x, const double* u, const int64_t* id, int64_t id_base,
                    PArrays<T> out, int64_t out_off, const double* grad64, const double* r0, const int32_t* cell_start,

@@ -640,6 +640,82 @@ __global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(walk_waves<T
     add_counters<kB>(sc, mc, na, ncap, cnt);
 }
 
+// The same walks for a species whose paths rarely cross a face (most queue regions empty):
+// a resident grid of one-wave workgroups, each taking a contiguous run of regions, reads
+// 64 regions' counts at once and walks only the regions that hold a path (a dispatch per
+// region would cost more than the walks).  The table is flushed and cleared after each
+// region, as in k_cross.
+template <typename T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(walk_waves<T>(), 8))) void k_cross_sparse(
+    PArrays<T> out, CrossQueue<T> cq, int64_t n_regions, const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
+    PushParams pp, PushCounters* __restrict__ cnt) {
+    constexpr int kB = 64;
+    constexpr int kBits = log2_const(8 * kB);
+    constexpr int kSlots = 1 << kBits;
+    __shared__ int s_key[kSlots];
+    __shared__ double s_val[kSlots];
+    for (int k = threadIdx.x; k < kSlots; k += kB) {
+        s_key[k] = -1;
+        s_val[k] = 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x;
+    const int64_t per = (n_regions + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(n_regions, r0 + per);
+    unsigned int sc = 0, mc = 0, na = 0, ncap = 0;
+    for (int64_t base = r0; base < r1; base += kB) {
+        const int own = (base + lane < r1) ? cq.wg_count[base + lane] : 0;
+        unsigned long long todo = __ballot(own > 0);
+        while (todo) {
+            const int l = __ffsll((long long)todo) - 1;
+            todo &= todo - 1ull;
+            const int64_t b = base + l;
+            const int total = __shfl(own, l);
+            for (int j = lane; j < total; j += kB) {
+                const int64_t slot = b * kBlock + j;
+                const int64_t i = cq.idx[slot];
+                double ls[4] = {cq.l0[slot], cq.l1[slot], cq.l2[slot], cq.l3[slot]};
+                const T dx[3] = {cq.dx0[slot], cq.dx1[slot], cq.dx2[slot]};
+                unsigned int nc = 0;
+                walk_rest<T, kBits>(out, i, cq.tet[slot], cq.entry[slot], ls, cq.frac[slot], dx, blk, dg, pp, s_key,
+                                    s_val, nc, na, ncap);
+                sc += nc - 1;
+                mc = max(mc, nc);
+            }
+            __syncthreads();
+            for (int k = lane; k < kSlots; k += kB) {
+                const int key = s_key[k];
+                if (key >= 0) {
+                    atomic_add_f64(dg + key, s_val[k]);
+                    s_key[k] = -1;
+                    s_val[k] = 0.0;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    add_counters<kB>(sc, mc, na, ncap, cnt);
+}
+
+// Resident one-wave workgroups of k_cross_sparse: what the walk's register budget keeps on
+// the 256 CUs (walk_waves waves on each of four SIMDs).
+template <typename T>
+constexpr unsigned sparse_grid() { return 256u * 4u * (unsigned)walk_waves<T>(); }
+
+// Face crossings counted so far in this step (the slots' running sum), into *out.
+__global__ __launch_bounds__(kCntSlots) void k_cnt_crossings(const PushCounters* __restrict__ slots,
+                                                             unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long s_c[kCntSlots];
+    const int t = threadIdx.x;
+    s_c[t] = slots[t].n_crossings;
+    __syncthreads();
+    for (int h = kCntSlots / 2; h > 0; h >>= 1) {
+        if (t < h) s_c[t] += s_c[t + h];
+        __syncthreads();
+    }
+    if (t == 0) *out = s_c[0];
+}
+
 // Folds the per-slot push counters into *out and clears the slots for the next step.
 __global__ __launch_bounds__(kCntSlots) void k_cnt_finish(PushCounters* __restrict__ slots,
                                                           PushCounters* __restrict__ out) {
@@ -1079,6 +1155,10 @@ void launch_cnt_finish(hipStream_t s, PushCounters* slots, PushCounters* out) {
     hipLaunchKernelGGL(k_cnt_finish, dim3(1), dim3(kCntSlots), 0, s, slots, out);
 }
 
+void launch_cnt_crossings(hipStream_t s, const PushCounters* slots, unsigned long long* out) {
+    hipLaunchKernelGGL(k_cnt_crossings, dim3(1), dim3(kCntSlots), 0, s, slots, out);
+}
+
 template <typename T>
 void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double* e, const double* b,
                   const double* grad64, const int32_t* tet_edges, const int32_t* tet_faces) {
@@ -1091,11 +1171,14 @@ void launch_stage(hipStream_t s, int64_t n_tets, TetBlock<T>* blk, const double*
 // kernel's workgroup size.
 constexpr double kFuseShare = 0.5;
 constexpr int kFusedBlock = 256;
+// A species' own crossings per particle (last step) below which its queue regions are
+// visited by k_cross_sparse: fewer than four crossing paths per region of 256 on average.
+constexpr double kSparseShare = 1.0 / 64.0;
 
 template <typename T>
 void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const TetBlock<T>* blk, double* dg,
                  PushParams pp, PushCounters* cnt, const int32_t* n_live, CrossQueue<T> cq, double cross_share,
-                 int walk) {
+                 double own_share, int walk) {
     if (n <= 0) return;
     const unsigned n_wg = (unsigned)grid_1d(n, kBlock);
     if (pp.fix) {
@@ -1112,8 +1195,13 @@ void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const 
     }
     hipLaunchKernelGGL((k_push<T, false, kBlock>), dim3(n_wg), dim3(kBlock), 0, s, in, out, n, blk, dg, pp, cnt, n_live,
                        cq);
-    // one k_cross workgroup per k_push workgroup, sized for its expected queue length
-    if (cross_share <= 0.25)
+    // a species whose paths rarely cross: resident one-wave workgroups visit the few
+    // non-empty queue regions; otherwise one k_cross workgroup per k_push workgroup, sized
+    // for its expected queue length
+    if (own_share < kSparseShare)
+        hipLaunchKernelGGL((k_cross_sparse<T>), dim3(std::min<unsigned>(n_wg, sparse_grid<T>())), dim3(64), 0, s, out,
+                           cq, (int64_t)n_wg, blk, dg, pp, cnt);
+    else if (cross_share <= 0.25)
         hipLaunchKernelGGL((k_cross<T, 64>), dim3(n_wg), dim3(64), 0, s, out, cq, blk, dg, pp, cnt);
     else if (cross_share <= 0.5)
         hipLaunchKernelGGL((k_cross<T, 128>), dim3(n_wg), dim3(128), 0, s, out, cq, blk, dg, pp, cnt);
@@ -1165,7 +1253,7 @@ void launch_fix_out(hipStream_t s, unsigned long long* acc, int64_t n, double sc
     template void launch_stage<T>(hipStream_t, int64_t, TetBlock<T>*, const double*, const double*,             \
                                   const double*, const int32_t*, const int32_t*);                                \
     template void launch_push<T>(hipStream_t, PArrays<T>, PArrays<T>, int64_t, const TetBlock<T>*, double*,      \
-                                 PushParams, PushCounters*, const int32_t*, CrossQueue<T>, double, int);         \
+                                 PushParams, PushCounters*, const int32_t*, CrossQueue<T>, double, double, int); \
     template void launch_locate<T>(hipStream_t, int64_t, const double*, const double*, const int64_t*, int64_t,  \
                                    PArrays<T>, int64_t, const double*, const double*, const int32_t*,            \
                                    const int32_t*, const double*, const double*, const int32_t*, PushCounters*); \
