@@ -641,10 +641,10 @@ __global__ __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(walk_waves<T
 }
 
 // The same walks for a species whose paths rarely cross a face (most queue regions empty):
-// a resident grid of one-wave workgroups, each taking a contiguous run of regions, reads
-// 64 regions' counts at once and walks only the regions that hold a path (a dispatch per
-// region would cost more than the walks).  The table is flushed and cleared after each
-// region, as in k_cross.
+// a resident grid of one-wave workgroups, each taking a contiguous run of regions 64 at a
+// time, one region per lane: a lane walks the paths of its region (none, mostly), so the
+// few paths of 64 regions are walked side by side.  All go through one LDS table per
+// workgroup, flushed at the end (a dispatch per region would cost more than the walks).
 template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(walk_waves<T>(), 8))) void k_cross_sparse(
     PArrays<T> out, CrossQueue<T> cq, int64_t n_regions, const TetBlock<T>* __restrict__ blk, double* __restrict__ dg,
@@ -664,36 +664,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(walk_waves<T
     const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(n_regions, r0 + per);
     unsigned int sc = 0, mc = 0, na = 0, ncap = 0;
     for (int64_t base = r0; base < r1; base += kB) {
-        const int own = (base + lane < r1) ? cq.wg_count[base + lane] : 0;
-        unsigned long long todo = __ballot(own > 0);
-        while (todo) {
-            const int l = __ffsll((long long)todo) - 1;
-            todo &= todo - 1ull;
-            const int64_t b = base + l;
-            const int total = __shfl(own, l);
-            for (int j = lane; j < total; j += kB) {
-                const int64_t slot = b * kBlock + j;
-                const int64_t i = cq.idx[slot];
-                double ls[4] = {cq.l0[slot], cq.l1[slot], cq.l2[slot], cq.l3[slot]};
-                const T dx[3] = {cq.dx0[slot], cq.dx1[slot], cq.dx2[slot]};
-                unsigned int nc = 0;
-                walk_rest<T, kBits>(out, i, cq.tet[slot], cq.entry[slot], ls, cq.frac[slot], dx, blk, dg, pp, s_key,
-                                    s_val, nc, na, ncap);
-                sc += nc - 1;
-                mc = max(mc, nc);
-            }
-            __syncthreads();
-            for (int k = lane; k < kSlots; k += kB) {
-                const int key = s_key[k];
-                if (key >= 0) {
-                    atomic_add_f64(dg + key, s_val[k]);
-                    s_key[k] = -1;
-                    s_val[k] = 0.0;
-                }
-            }
-            __syncthreads();
+        const int64_t b = base + lane;
+        const int total = b < r1 ? cq.wg_count[b] : 0;
+        for (int j = 0; j < total; ++j) {
+            const int64_t slot = b * kBlock + j;
+            const int64_t i = cq.idx[slot];
+            double ls[4] = {cq.l0[slot], cq.l1[slot], cq.l2[slot], cq.l3[slot]};
+            const T dx[3] = {cq.dx0[slot], cq.dx1[slot], cq.dx2[slot]};
+            unsigned int nc = 0;
+            walk_rest<T, kBits>(out, i, cq.tet[slot], cq.entry[slot], ls, cq.frac[slot], dx, blk, dg, pp, s_key, s_val,
+                                nc, na, ncap);
+            sc += nc - 1;
+            mc = max(mc, nc);
         }
     }
+    __syncthreads();
+    flush_table<kSlots, kB>(s_key, s_val, dg);
     add_counters<kB>(sc, mc, na, ncap, cnt);
 }
 
