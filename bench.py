@@ -541,7 +541,8 @@ def run_workload(args, F, torch, name, steps, warmup, with_cpu, with_fp64_solve)
                    "mean_live_particles": round(mean_particles), "dt": wl["dt"], "beta": wl["beta"],
                    "gamma": wl["gamma"], "cg_tol": 1e-10, "preconditioner": pc, "solve": solve,
                    "mixed_inner_tol": (inner_tol or 1e-4) if solve == "mixed" else None,
-                   "walk": args.walk if headline else "auto", "warm_start": warm, "sort_period": sort_period,
+                   "walk": args.walk if headline else "auto", "warm_start": warm,
+                   "sort_period": "auto" if sort_period == F.FEPIC_SORT_AUTO else sort_period,
                    "inject_per_step": int(wl.get("inject_per_step") or 0) if inject else 0,
                    "inject_from": args.inject_from if inject else None,
                    "precision": ("fp32 push / fp64 deposit" if precision == 0 else "all fp64 particles")
@@ -609,7 +610,8 @@ def main():
     ap.add_argument("--diagnostics", action="store_true",
                     help="run the conservation diagnostics every step (continuity, Gauss drift)")
     ap.add_argument("--sort-period", type=int, default=None,
-                    help="re-sort particles by tet every this many steps (default: the workload's)")
+                    help="re-sort particles by tet every this many steps; -1: each species when a 64th "
+                         "of it has left its tet (default: the workload's)")
     ap.add_argument("--walk", default="auto", choices=["auto", "queue", "fused"],
                     help="crossing paths: chosen from the last step's crossings, queue + second kernel, or in place")
     ap.add_argument("--solve", default=None, choices=["fp64", "mixed"],

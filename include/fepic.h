@@ -104,6 +104,9 @@ enum { FEPIC_SOLVE_FP64 = 0, FEPIC_SOLVE_MIXED = 1 };
  * particle.  Results agree to the rounding order of the current sums either way. */
 enum { FEPIC_WALK_AUTO = 0, FEPIC_WALK_QUEUE = 1, FEPIC_WALK_FUSED = 2 };
 
+/* fepic_options.sort_period: re-bin each species by its own need (see there) */
+enum { FEPIC_SORT_AUTO = -1 };
+
 /* Particle pusher of fepic_step and fepic_push_particles.  FEPIC_PUSHER_BORIS: relativistic
  * Boris with straight paths (u = gamma v at t_{n-1/2}).  FEPIC_PUSHER_AB: the paper's own
  * pusher (Sec. III-B, III-C, Alg. 1 and 2): Adams-Bashforth of order ab_order (1..5) of the
@@ -150,7 +153,10 @@ typedef struct {
     double cg_tol;     /* stop when ||b - A x||_2 <= cg_tol ||b||_2 (default 1e-10)      */
     int cg_max_iters;  /* default 10000                                                  */
     int cg_check_every;/* iterations between convergence reads on the host (default 8)   */
-    int sort_period;   /* re-bin particles by tet every this many steps (default 1)      */
+    int sort_period;   /* re-bin particles by tet every this many steps (default 1; 0:
+                          never); FEPIC_SORT_AUTO: each species when its particles that
+                          left their tet or the mesh since its last re-binning reach 1/64
+                          of it, or particles were added to it                        */
     int crossing_cap;  /* faces one path may cross in one step (default 64)              */
     int warm_start;    /* FEPIC_WS_* (default FEPIC_WS_PREV)                             */
     int diagnostics;   /* 1: charge continuity, Gauss and div b residuals every step      */

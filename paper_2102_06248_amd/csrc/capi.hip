@@ -228,10 +228,19 @@ void sort_species(fepic_ctx* c, Species& s) {
         s.ab_reset = true;
     }
     s.sorted_pending = true;
+    s.moved = 0;
+    s.added = false;
 }
 
-void sort_all(fepic_ctx* c) {
+// Species that left the sorted order by at least this share of their particles (face
+// crossings and losses since the last re-binning) are re-binned under FEPIC_SORT_AUTO.
+constexpr int64_t kResortDivisor = 64;
+
+// The sorts of a step: every species, or under FEPIC_SORT_AUTO (and not for the
+// Adams-Bashforth pusher, whose step sorts every species) those that need it.
+void sort_all(fepic_ctx* c, bool every = false) {
     for (auto& s : c->species) {
+        if (!every && c->opt.sort_period == FEPIC_SORT_AUTO && !s.added && s.moved * kResortDivisor < s.n) continue;
         if (c->opt.precision == FEPIC_ALL_FP64) sort_species<double>(c, s);
         else sort_species<float>(c, s);
     }
@@ -372,6 +381,7 @@ int inject_phase(fepic_ctx* c) {
         s.ab_fill_from = std::min(s.ab_fill_from, s.n);
         s.next_id += m;
         s.n += m;
+        s.added = true;
     }
     return FEPIC_OK;
 }
@@ -447,8 +457,8 @@ void particle_phase_T(fepic_ctx* c, double dt, bool do_sort) {
         if (ev) (void)hipEventRecord(ev[1], c->stream);
         s.n_pushed = s.n;
         launch_cnt_crossings(c->stream, c->d_cnt_slots, s.d_xcum);
-        const hipError_t xe = hipMemcpyAsync(s.h_xcum, s.d_xcum, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                                             c->stream);
+        const hipError_t xe = hipMemcpyAsync(s.h_xcum, s.d_xcum, 2 * sizeof(unsigned long long),
+                                             hipMemcpyDeviceToHost, c->stream);
         if (xe != hipSuccess) {
             c->deferred_err = hip_fail(c, xe, "hipMemcpyAsync(crossing count)");
             return;
@@ -499,7 +509,7 @@ void particle_phase_ab(fepic_ctx* c, double dt, bool do_sort) {
         }
     }
     ev_mark(c, 0);
-    if (do_sort) sort_all(c);
+    if (do_sort) sort_all(c, true);
     {
         int rc = inject_phase<double>(c);
         if (rc == FEPIC_OK)
@@ -1122,7 +1132,8 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
         compute_rho(c, c->d_rho);
         c->rho_valid = true;
     }
-    const bool do_sort = (c->opt.sort_period > 0) && (c->step_count % c->opt.sort_period == 0);
+    const bool do_sort = c->opt.sort_period == FEPIC_SORT_AUTO ||
+                         ((c->opt.sort_period > 0) && (c->step_count % c->opt.sort_period == 0));
     // particles injected by this step are dropped again on any failure below
     struct InjectGuard {
         fepic_ctx* c;
@@ -1153,12 +1164,15 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
         c->cross_share = n_all > 0 ? (double)st.n_crossings / (double)n_all : 1.0;
         // each species' own share (the species of the Boris step count their crossings in
         // turn; a species without particles keeps its last share)
-        unsigned long long prev = 0;
+        unsigned long long prev = 0, prev_gone = 0;
         for (auto& sp : c->species) {
             if (sp.n_pushed <= 0) continue;
-            const unsigned long long cum = *sp.h_xcum;
-            sp.own_share = cum >= prev ? (double)(cum - prev) / (double)sp.n_pushed : 1.0;
+            const unsigned long long cum = sp.h_xcum[0], gone = sp.h_xcum[1];
+            const unsigned long long own = cum >= prev ? cum - prev : 0, own_gone = gone >= prev_gone ? gone - prev_gone : 0;
+            sp.own_share = (double)own / (double)sp.n_pushed;
+            sp.moved += (int64_t)(own + own_gone);
             prev = cum;
+            prev_gone = gone;
             sp.n_pushed = 0;
         }
     }
@@ -1399,7 +1413,9 @@ int fepic_create(const fepic_options* opts, fepic_ctx** out) {
     fepic_default_options(&o);
     if (opts) o = *opts;
     if (o.precision != FEPIC_FP32_PUSH_FP64_ACC && o.precision != FEPIC_ALL_FP64) return FEPIC_E_ARG;
-    if (!(o.cg_tol > 0) || o.cg_max_iters < 1 || o.crossing_cap < 1 || o.sort_period < 0) return FEPIC_E_ARG;
+    if (!(o.cg_tol > 0) || o.cg_max_iters < 1 || o.crossing_cap < 1 ||
+        (o.sort_period < 0 && o.sort_period != FEPIC_SORT_AUTO))
+        return FEPIC_E_ARG;
     if (o.warm_start < FEPIC_WS_PREV || o.warm_start > FEPIC_WS_MLP_DIRECT) return FEPIC_E_ARG;
     if (o.preconditioner != FEPIC_PC_JACOBI && o.preconditioner != FEPIC_PC_AUX) return FEPIC_E_ARG;
     if (o.aux_far_levels < -1 || o.aux_far_levels > kAuxFarLevels) return FEPIC_E_ARG;
@@ -1838,11 +1854,11 @@ int fepic_add_species(fepic_ctx* c, double q, double m, double w, int* out) {
     s.m = m;
     s.w = w;
     s.d_nlive = dalloc<int32_t>(c, 1);
-    s.d_xcum = dalloc<unsigned long long>(c, 1);
+    s.d_xcum = dalloc<unsigned long long>(c, 2);
     if (!s.d_nlive || !s.d_xcum || hipHostMalloc((void**)&s.h_nlive, sizeof(int32_t)) != hipSuccess ||
-        hipHostMalloc((void**)&s.h_xcum, sizeof(unsigned long long)) != hipSuccess)
+        hipHostMalloc((void**)&s.h_xcum, 2 * sizeof(unsigned long long)) != hipSuccess)
         return fail(c, FEPIC_E_OOM, "allocation failed");
-    *s.h_xcum = 0;
+    s.h_xcum[0] = s.h_xcum[1] = 0;
     c->species.push_back(s);
     if (out) *out = (int)c->species.size() - 1;
     return FEPIC_OK;
@@ -2022,6 +2038,7 @@ static int inject_located(fepic_ctx* c, Species& s, int64_t n, const int64_t* di
     s.next_id += n;
     s.ab_fill_from = std::min(s.ab_fill_from, s.n);
     s.n += n;
+    s.added = true;
     c->rho_valid = false;
     c->rG_levels = 0;
     return FEPIC_OK;

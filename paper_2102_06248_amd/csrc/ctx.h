@@ -38,10 +38,14 @@ struct Species {
     // face crossings of the step so far, counted after this species' particle kernels (its
     // own crossings are the difference to the previous species'), and the species' own
     // crossings per particle at its last committed step
-    unsigned long long* d_xcum = nullptr;
+    unsigned long long* d_xcum = nullptr;   // [2]: crossings, and absorptions + paths cut at the cap
     unsigned long long* h_xcum = nullptr;
     int64_t n_pushed = 0;
     double own_share = 1.0;
+    // FEPIC_SORT_AUTO: particles that left their tet or the mesh since the species' last
+    // re-binning (face crossings counted), and whether particles were added since
+    int64_t moved = 0;
+    bool added = false;
     // Adams-Bashforth pusher: history [kAbStride][abh_cap] (component-major) and per-slot
     // AbMeta, each double-buffered.  The sorts move both (flipping abh_cur and abm_cur); a
     // step writes its meta to the other buffer, flipped at the commit with cur.

@@ -213,7 +213,8 @@ void launch_push(hipStream_t s, PArrays<T> in, PArrays<T> out, int64_t n, const 
                  PushParams pp, PushCounters* cnt, const int32_t* n_live, CrossQueue<T> cq, double cross_share,
                  double own_share, int walk);
 void launch_cnt_finish(hipStream_t s, PushCounters* slots, PushCounters* out);
-// The face crossings the slots hold so far (summed over the slots) into *out.
+// The face crossings the slots hold so far (summed over the slots) into out[0], the
+// absorptions and paths stopped at the crossing cap into out[1].
 void launch_cnt_crossings(hipStream_t s, const PushCounters* slots, unsigned long long* out);
 template <typename T>
 void launch_locate(hipStream_t s, int64_t n, const double* x, const double* u, const int64_t* id, int64_t id_base,

@@ -688,18 +688,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(walk_waves<T
 template <typename T>
 constexpr unsigned sparse_grid() { return 256u * 4u * (unsigned)walk_waves<T>(); }
 
-// Face crossings counted so far in this step (the slots' running sum), into *out.
+// Face crossings counted so far in this step (the slots' running sum) into out[0], and the
+// absorptions plus paths stopped at the crossing cap into out[1].
 __global__ __launch_bounds__(kCntSlots) void k_cnt_crossings(const PushCounters* __restrict__ slots,
                                                              unsigned long long* __restrict__ out) {
-    __shared__ unsigned long long s_c[kCntSlots];
+    __shared__ unsigned long long s_c[kCntSlots], s_a[kCntSlots];
     const int t = threadIdx.x;
     s_c[t] = slots[t].n_crossings;
+    s_a[t] = (unsigned long long)slots[t].n_absorbed + slots[t].n_cap;
     __syncthreads();
     for (int h = kCntSlots / 2; h > 0; h >>= 1) {
-        if (t < h) s_c[t] += s_c[t + h];
+        if (t < h) {
+            s_c[t] += s_c[t + h];
+            s_a[t] += s_a[t + h];
+        }
         __syncthreads();
     }
-    if (t == 0) *out = s_c[0];
+    if (t == 0) {
+        out[0] = s_c[0];
+        out[1] = s_a[0];
+    }
 }
 
 // Folds the per-slot push counters into *out and clears the slots for the next step.

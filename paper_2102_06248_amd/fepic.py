@@ -21,6 +21,7 @@ FEPIC_FP32_PUSH_FP64_ACC, FEPIC_ALL_FP64 = 0, 1
 FEPIC_WS_PREV, FEPIC_WS_EXTRAP1, FEPIC_WS_EXTRAP2, FEPIC_WS_MLP, FEPIC_WS_MLP_DIRECT = 0, 1, 2, 3, 4
 FEPIC_PC_JACOBI, FEPIC_PC_AUX = 0, 1
 FEPIC_WALK_AUTO, FEPIC_WALK_QUEUE, FEPIC_WALK_FUSED = 0, 1, 2
+FEPIC_SORT_AUTO = -1
 FEPIC_SOLVE_FP64, FEPIC_SOLVE_MIXED = 0, 1
 FEPIC_PUSHER_BORIS, FEPIC_PUSHER_AB = 0, 1
 FEPIC_FIELD_WAVE, FEPIC_FIELD_NM_MFEM, FEPIC_FIELD_BD_MFEM = 0, 1, 2

@@ -62,7 +62,9 @@ def c3_plasma(n_pairs=8_000_000, n_cells=55, seed=0):
     weight; dt = 0.05 / omega_pe.  Newmark solve: FP64 residuals around FP32 inner solves
     that each reduce the residual by 3e-4 (deeper FP32 passes converge more slowly here),
     started from the quadratic extrapolation of the last three fields (the smooth
-    expansion makes it a better start than e^n: 144.5 iterations per step against 165.4)."""
+    expansion makes it a better start than e^n: 144.5 iterations per step against 165.4).
+    Each species is re-binned by tet when a 64th of it has left its tet since its last
+    re-binning (the electrons every step, the protons every few dozen steps)."""
     xyz, tets = inputs.kuhn_cube(n_cells, lo=(-0.04,) * 3, hi=(0.04,) * 3)
     m_p = inputs.PROTON_ELECTRON_MASS_RATIO * M_E
     x, ue, ui = inputs.gaussian_ball_pairs(n_pairs, 0.01, 3.9, 1.0, 0.1, M_E, m_p, seed)
@@ -74,7 +76,7 @@ def c3_plasma(n_pairs=8_000_000, n_cells=55, seed=0):
     return dict(name="c3_plasma", xyz=xyz, tets=tets, B0=None,
                 species=[dict(q=-E_CHARGE, m=M_E, w=w, x=x, u=ue), dict(q=E_CHARGE, m=m_p, w=w, x=x, u=ui)],
                 dt=0.05 / wpe, beta=0.25, gamma=0.5, precision=0, solve="mixed", inner_tol=3e-4,
-                warm_start="extrap2")
+                warm_start="extrap2", sort_period=-1)
 
 
 def c5_plasma(n_pairs=64_000_000, n_cells=110, seed=0):

@@ -142,6 +142,43 @@ def test_rarely_crossing_species_vs_oracle(F, precision):
     print(f"\n[rarely crossing p{precision}] {st.n_crossings} crossings of {n} particles in the last step")
 
 
+def test_automatic_sort_schedule(F):
+    """FEPIC_SORT_AUTO re-bins a species only when a 64th of its particles left their tet
+    since its last re-binning: over six pushes of a fast and a slow species the slow one is
+    re-binned less often than every step, and particles and current equal those of
+    re-binning every step (to rounding order)."""
+    announce("automatic sort schedule")
+    xyz, tets, h = jittered_kuhn(6)
+    osim = OracleSim(xyz, tets)
+    e, b = divfree_fields(osim, 50.0, 1e-4, [0.0, 0.0, 0.002], seed=3)
+    n = 20000
+    xf, uf = inputs.uniform_box_particles(n, [0.02] * 3, [0.98] * 3, 3e6, seed=5)
+    xs, us = inputs.uniform_box_particles(n, [0.02] * 3, [0.98] * 3, 2.5e4, seed=6)
+    dt = 2e-9
+    out = {}
+    for period in (F.FEPIC_SORT_AUTO, 1):
+        with _lib_sim(F, xyz, tets, precision=1, sort_period=period, timing=1) as L:
+            F.fepic_set_fields(L.ctx, e=e, e_prev=e, b=b)
+            sf = F.fepic_add_species(L.ctx, -Q_E, M_E, 1e3)
+            ss = F.fepic_add_species(L.ctx, -Q_E, M_E, 1e3)
+            F.fepic_upload_particles(L.ctx, sf, xf, uf, ids=np.arange(n))
+            F.fepic_upload_particles(L.ctx, ss, xs, us, ids=np.arange(n))
+            F.fepic_kernel_timing(L.ctx, "sort", 100)
+            for _ in range(6):
+                F.fepic_push_particles(L.ctx, dt)
+            _, n_sorts = F.fepic_kernel_time(L.ctx, "sort")
+            dG, G = F.fepic_get_current(L.ctx)
+            out[period] = (n_sorts, G, F.fepic_get_particles(L.ctx, sf), F.fepic_get_particles(L.ctx, ss))
+    n_auto, G_auto, pf_a, ps_a = out[F.FEPIC_SORT_AUTO]
+    n_every, G_every, pf_e, ps_e = out[1]
+    assert n_every == 12 and 1 <= n_auto < 12, (n_auto, n_every)
+    assert np.abs(G_auto - G_every).max() <= 1e-12 * np.abs(G_every).max()
+    for pa, pe in ((pf_a, pf_e), (ps_a, ps_e)):
+        ncommon, nodd = compare_particles(pa, pe, h, 1e-12, 1e-12)
+        assert nodd == 0 and ncommon == len(pe["id"])
+    print(f"\n[automatic sort] {n_auto} re-binnings in 6 steps of two species (12 when every step)")
+
+
 def test_gather_uniform_fields_exact(F):
     """A uniform E0 is reproduced exactly by the Whitney-1 interpolant, so one push from
     rest with B = 0 gives the closed-form Boris update u = (q dt / m) E0."""

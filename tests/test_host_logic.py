@@ -177,3 +177,13 @@ def test_deterministic_option_checks(F):
         F.fepic_set_warm_start(ctx, F.FEPIC_WS_EXTRAP1)
     finally:
         F.fepic_destroy(ctx)
+
+
+def test_sort_period_option_checks(F):
+    """sort_period: a period >= 0, or FEPIC_SORT_AUTO (each species by its own need);
+    other negative values are refused."""
+    for bad in (-2, -64):
+        with pytest.raises(F.FepicError):
+            F.fepic_create(device=-1, sort_period=bad)
+    for ok in (F.FEPIC_SORT_AUTO, 0, 1, 7):
+        F.fepic_destroy(F.fepic_create(device=-1, sort_period=ok))
