@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/s (gather+push+deposit) + Newmark step time at CG resid 1e-10"
 HBM_PEAK_GBS = 8000.0
 FAMILIES = ["push", "stage", "sort", "rhs", "cg_iter", "faraday"]
-KERNEL_NAMES = {"push": "k_push+k_cross", "stage": "k_stage", "sort": "k_hist/k_scan/k_scatter", "rhs": "k_rhs",
+KERNEL_NAMES = {"push": "k_push+k_cross|k_cross_sparse", "stage": "k_stage", "sort": "k_hist/k_scan/k_scatter", "rhs": "k_rhs",
                 "cg_iter": "k_pcg_q<double>+k_pcg_nodes<double>+k_pcg_update<double, 1>", "faraday": "k_faraday"}
 MIXED_ITER_KERNEL = "k_pcg_q<float>+k_pcg_nodes<float>+k_pcg_update<float, 2>"
 JACOBI_ITER_KERNEL = "k_cg_iter"
