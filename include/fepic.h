@@ -156,10 +156,9 @@ typedef struct {
     int sort_period;   /* re-bin particles by tet every this many steps (default 1; 0:
                           never); FEPIC_SORT_AUTO: each species when its particles that
                           left their tet or the mesh since its last re-binning reach 1/64
-                          of it, or particles were added to it (the Adams-Bashforth pusher
-                          re-bins every species every step; a run resumed from a checkpoint
-                          starts its count afresh, so it agrees with the uninterrupted run
-                          to rounding order, not bit for bit)                          */
+                          of it, or particles were added to it (a run resumed from a
+                          checkpoint starts its count afresh, so it agrees with the
+                          uninterrupted run to rounding order, not bit for bit)         */
     int crossing_cap;  /* faces one path may cross in one step (default 64)              */
     int warm_start;    /* FEPIC_WS_* (default FEPIC_WS_PREV)                             */
     int diagnostics;   /* 1: charge continuity, Gauss and div b residuals every step      */

@@ -236,11 +236,10 @@ void sort_species(fepic_ctx* c, Species& s) {
 // crossings and losses since the last re-binning) are re-binned under FEPIC_SORT_AUTO.
 constexpr int64_t kResortDivisor = 64;
 
-// The sorts of a step: every species, or under FEPIC_SORT_AUTO (and not for the
-// Adams-Bashforth pusher, whose step sorts every species) those that need it.
-void sort_all(fepic_ctx* c, bool every = false) {
+// The sorts of a step: every species, or under FEPIC_SORT_AUTO those that need it.
+void sort_all(fepic_ctx* c) {
     for (auto& s : c->species) {
-        if (!every && c->opt.sort_period == FEPIC_SORT_AUTO && !s.added && s.moved * kResortDivisor < s.n) continue;
+        if (c->opt.sort_period == FEPIC_SORT_AUTO && !s.added && s.moved * kResortDivisor < s.n) continue;
         if (c->opt.precision == FEPIC_ALL_FP64) sort_species<double>(c, s);
         else sort_species<float>(c, s);
     }
@@ -509,7 +508,7 @@ void particle_phase_ab(fepic_ctx* c, double dt, bool do_sort) {
         }
     }
     ev_mark(c, 0);
-    if (do_sort) sort_all(c, true);
+    if (do_sort) sort_all(c);
     {
         int rc = inject_phase<double>(c);
         if (rc == FEPIC_OK)
@@ -556,6 +555,14 @@ void particle_phase_ab(fepic_ctx* c, double dt, bool do_sort) {
                        (const TetBlock<double>*)c->d_blk, c->d_r0, s.d_abh[s.abh_cur], s.abh_cap, s.d_abm[s.abm_cur],
                        s.d_abm[1 - s.abm_cur], c->d_dgn, ap, c->d_cnt_slots, s.sorted_pending ? s.d_nlive : nullptr);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
+        s.n_pushed = s.n;
+        launch_cnt_crossings(c->stream, c->d_cnt_slots, s.d_xcum);
+        const hipError_t xe = hipMemcpyAsync(s.h_xcum, s.d_xcum, 2 * sizeof(unsigned long long),
+                                             hipMemcpyDeviceToHost, c->stream);
+        if (xe != hipSuccess) {
+            c->deferred_err = hip_fail(c, xe, "hipMemcpyAsync(crossing count)");
+            return;
+        }
     }
     if (fix) launch_fix_out(c->stream, fix, c->mesh.n_edges, scale, c->d_dgn);
     launch_cnt_finish(c->stream, c->d_cnt_slots, c->d_cnt);

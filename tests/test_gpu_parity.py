@@ -142,12 +142,14 @@ def test_rarely_crossing_species_vs_oracle(F, precision):
     print(f"\n[rarely crossing p{precision}] {st.n_crossings} crossings of {n} particles in the last step")
 
 
-def test_automatic_sort_schedule(F):
+@pytest.mark.parametrize("pusher", ["boris", "ab"])
+def test_automatic_sort_schedule(F, pusher):
     """FEPIC_SORT_AUTO re-bins a species only when a 64th of its particles left their tet
     since its last re-binning: over six pushes of a fast and a slow species the slow one is
     re-binned less often than every step, and particles and current equal those of
-    re-binning every step (to rounding order)."""
-    announce("automatic sort schedule")
+    re-binning every step (to rounding order).  With the Boris pusher and with the
+    Adams-Bashforth one, whose histories move with the particles when they are re-binned."""
+    announce(f"automatic sort schedule, {pusher}")
     xyz, tets, h = jittered_kuhn(6)
     osim = OracleSim(xyz, tets)
     e, b = divfree_fields(osim, 50.0, 1e-4, [0.0, 0.0, 0.002], seed=3)
@@ -157,7 +159,8 @@ def test_automatic_sort_schedule(F):
     dt = 2e-9
     out = {}
     for period in (F.FEPIC_SORT_AUTO, 1):
-        with _lib_sim(F, xyz, tets, precision=1, sort_period=period, timing=1) as L:
+        extra = dict(pusher=F.FEPIC_PUSHER_AB, ab_order=3) if pusher == "ab" else {}
+        with _lib_sim(F, xyz, tets, precision=1, sort_period=period, timing=1, **extra) as L:
             F.fepic_set_fields(L.ctx, e=e, e_prev=e, b=b)
             sf = F.fepic_add_species(L.ctx, -Q_E, M_E, 1e3)
             ss = F.fepic_add_species(L.ctx, -Q_E, M_E, 1e3)
@@ -176,7 +179,7 @@ def test_automatic_sort_schedule(F):
     for pa, pe in ((pf_a, pf_e), (ps_a, ps_e)):
         ncommon, nodd = compare_particles(pa, pe, h, 1e-12, 1e-12)
         assert nodd == 0 and ncommon == len(pe["id"])
-    print(f"\n[automatic sort] {n_auto} re-binnings in 6 steps of two species (12 when every step)")
+    print(f"\n[automatic sort, {pusher}] {n_auto} re-binnings in 6 steps of two species (12 when every step)")
 
 
 def test_gather_uniform_fields_exact(F):
