@@ -1169,8 +1169,10 @@ int do_step(fepic_ctx* c, double dt, double beta, double gamma, fepic_step_stats
         int64_t n_all = 0;
         for (const auto& sp : c->species) n_all += sp.n;
         c->cross_share = n_all > 0 ? (double)st.n_crossings / (double)n_all : 1.0;
-        // each species' own share (the species of the Boris step count their crossings in
-        // turn; a species without particles keeps its last share)
+        // each species' own crossings and losses: the running counts read after each
+        // species' kernels, differenced in push order (a species without particles keeps
+        // its last share); its crossings per particle choose its crossing-walk form at the
+        // next step, and crossings plus losses count towards its re-binning
         unsigned long long prev = 0, prev_gone = 0;
         for (auto& sp : c->species) {
             if (sp.n_pushed <= 0) continue;
