@@ -35,8 +35,9 @@ METRIC = "particle-steps/s (gather+push+deposit) + Newmark step time at CG resid
 HBM_PEAK_GBS = 8000.0
 FAMILIES = ["push", "stage", "sort", "rhs", "cg_iter", "faraday"]
 KERNEL_NAMES = {"push": "k_push+k_cross|k_cross_sparse", "stage": "k_stage", "sort": "k_hist/k_scan/k_scatter", "rhs": "k_rhs",
-                "cg_iter": "k_pcg_q<double>+k_pcg_nodes<double>+k_pcg_update<double, 1>", "faraday": "k_faraday"}
-MIXED_ITER_KERNEL = "k_pcg_q<float>+k_pcg_nodes<float>+k_pcg_update<float, 2>"
+                "cg_iter": "k_pcg_q<double>+k_pcg_nodes<double>+k_pcg_fold<double>+k_pcg_update<double, 1>",
+                "faraday": "k_faraday"}
+MIXED_ITER_KERNEL = "k_pcg_q<float>+k_pcg_nodes<float>+k_pcg_fold<float>+k_pcg_update<float, 2>"
 JACOBI_ITER_KERNEL = "k_cg_iter"
 KERNEL_SOURCES = {"push": "kernels_particles.hip", "stage": "kernels_particles.hip", "sort": "kernels_particles.hip",
                   "rhs": "kernels_fields.hip", "cg_iter": "kernels_fields.hip", "faraday": "kernels_fields.hip"}
@@ -66,25 +67,27 @@ def push_bytes(n_particles, occupied, crossings, precision=0):
 
 def algorithmic_bytes(fam, geo, st, pc="aux", solve="fp64", precision=0):
     """Bytes the method must move per launch (each HBM word once), by kernel family.  A
-    "cg_iter" launch is one PCG iteration: one kernel with Jacobi, three with the nodal
+    "cg_iter" launch is one PCG iteration: one kernel with Jacobi, four with the nodal
     auxiliary-space preconditioner (in FP32 for the inner solves of the mixed form)."""
     n_rows, nnz, ne, nf, nt = geo["n_rows"], geo["nnz"], geo["n_edges"], geo["n_faces"], geo["n_tets"]
+    fold = 1 if geo.get("far_levels", 0) > 0 else 0   # the far levels' per-node fold runs
     npart, occ, cross = st["particles"], st["occupied_tets"], st["crossings"]
     if fam == "cg_iter" and pc == "jacobi":   # A values + columns once; per row R, W, S, P and x read
         return 12 * nnz + 80 * n_rows          # and written
     if fam == "cg_iter" and solve == "mixed":
         # the same words in FP32 (values 4 B, (z, p) pairs 8 B, diagonals and Y 16 B per
         # node), column ids, incidences, FP16 edge vectors and ends as before:
-        # q 8 nnz + 12 per row; nodes 16 per row, 32 per node; update 40 read + 16 written
-        # per row, 16 per node
-        return 8 * nnz + (12 + 16 + 56) * n_rows + 8 * geo["n_int_edges"] + 48 * geo["n_aux"]
+        # q 8 nnz + 12 per row; nodes 16 per row, 32 per node; with far levels, their fold:
+        # Y read and written per node (32); update 40 read + 16 written per row, 16 per node
+        return 8 * nnz + (12 + 16 + 56) * n_rows + 8 * geo["n_int_edges"] + (48 + 32 * fold) * geo["n_aux"]
     if fam == "cg_iter":
         # q = A p: A values + columns, (z, p) read, q written: 12 nnz + 24 per row;
         # nodes: one 4 B incidence per interior edge end, r, q and the FP16 edge vector per
-        # row (24), scale read and Y written per node (64);
+        # row (24), scale read and Y written per node (64); with far levels, their fold: Y
+        # read and written per node (64);
         # update: r, q, z, p, x, 1/A_jj, edge vector, ends read (64) and r, z, p, x written
         # (32) per row, Y read per node (32)
-        return 12 * nnz + (24 + 24 + 96) * n_rows + 8 * geo["n_int_edges"] + 96 * geo["n_aux"]
+        return 12 * nnz + (24 + 24 + 96) * n_rows + 8 * geo["n_int_edges"] + (96 + 64 * fold) * geo["n_aux"]
     if fam == "rhs":          # M, S values + columns; e, e_prev, dG_new, dG_old read; b written
         return 20 * nnz + 40 * n_rows
     if fam == "push":         # all species of one step
@@ -438,8 +441,9 @@ def run_workload(args, F, torch, name, steps, warmup, with_cpu, with_fp64_solve)
         learned = {"train_steps": n_train, "plain_cg_iters_mean_while_recording": round(float(np.mean(plain_iters)), 2),
                    "train": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in tst.as_dict().items()}}
         log(f"[bench] trained the warm-start network on {n_train} solves: {learned['train']}")
+    warm_st = None    # the last warm-up step's statistics (None without warm-up steps)
     for k in range(warmup):
-        st = one_step(n_train + k)
+        st = warm_st = one_step(n_train + k)
         if k < 5 or k == warmup - 1:
             log(f"[bench] warmup {k}: cg {st.cg_iters} iters, {st.n_particles} particles, {st.n_crossings} crossings")
     # geometry of the work, for algorithmic bytes
@@ -447,7 +451,8 @@ def run_workload(args, F, torch, name, steps, warmup, with_cpu, with_fp64_solve)
     nnz_int = F.fepic_get_matrix_nnz(ctx, 0)
     geo = {"n_rows": sizes["n_edges"], "nnz": nnz_int + (sizes["n_edges"] - sizes["n_int_edges"]),
            "n_edges": sizes["n_edges"], "n_faces": sizes["n_faces"], "n_tets": len(wl["tets"]),
-           "n_int_edges": sizes["n_int_edges"], "n_aux": sizes["n_int_nodes"]}
+           "n_int_edges": sizes["n_int_edges"], "n_aux": sizes["n_int_nodes"],
+           "far_levels": max(0, int(warm_st.pc_far_levels)) if warm_st is not None else 0}
     occ = 0     # tets holding particles, counted per species (each species' launch reads them)
     for s in species:
         occ += len(np.unique(F.fepic_get_particles(ctx, s, fields=("tet",))["tet"]))

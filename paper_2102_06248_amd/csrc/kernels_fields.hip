@@ -539,13 +539,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
 // 512, 4096, 32768 (far levels) Morton-consecutive nodes.  The slow components of
 // Jacobi-PCG on the Newmark system are gradients (the kernel of S) and smooth curl
 // fields; the nodal spaces reach both.  Plain (Hestenes-Stiefel) recurrences; an
-// iteration is three kernels, because z = B r needs the nodal sums of the new residual
-// before any edge can form it:
+// iteration is three kernels (four with far levels), because z = B r needs the nodal sums
+// of the new residual before any edge can form it:
 //   k_pcg_q(i):      beta = g_i / g_{i-1};  p = z + beta p;  q = A p (the neighbours' p
 //                    formed on the fly from their gathered (z, p) pair);  dot (p, q)
 //   k_pcg_nodes(i):  alpha = g_i / (p, q);  per interior node, G^T r' and Pi^T r' over its
 //                    edges, r' = r - alpha q, scaled by D_G^-1 and D_Pi^-1, plus the
 //                    aggregate levels of the node's slice; far-level sums by atomics
+//   k_pcg_fold(i):   with far levels, each node's Y += its far aggregates' sums times
+//                    their scales (once per node, not at both ends of every edge)
 //   k_pcg_update(i): p again (same operands, same bits);  x += alpha p;  r = r';
 //                    z = D^-1 r + G y + Pi v (all levels);  dots (r, z), (r, r)
 // Every kernel issues its loads before it sums the previous kernel's slots.  Reductions
@@ -1057,40 +1059,32 @@ __device__ __forceinline__ void u_part(UPart<S>& P, const AuxSpace& g, const S* 
     P.th = edge_vec_t<S>(g, row);
     const int2 en = g.ends[row];
     const typename Vec<S>::t4* Y = pick<S>(g.Y, g.Y_f);
-    P.ya = Y[en.x];
+    P.ya = Y[en.x];   // the far levels' corrections are already folded in (k_pcg_fold)
     P.yb = Y[en.y];
-    // far levels: an edge's two ends mostly share their aggregate, whose correction is then
-    // loaded once and added at both ends (the same sums as two loads)
+}
+
+// The far levels' corrections folded into each node's Y once, after the node pass has
+// summed every far aggregate and before the update reads Y at both ends of every edge:
+// Y += (the aggregate's sum) * (its scale), level by level, the same products and sums the
+// update would otherwise form at each end of each edge.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_pcg_fold(AuxSpace g, const CgScalars* __restrict__ sc) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.n_aux || sc->converged) return;   // a stopped solve's node pass left Y as it was
+    typename Vec<S>::t4* Y = pick<S>(g.Y, g.Y_f);
+    typename Vec<S>::t4 y = Y[n];
 #pragma unroll
     for (int L = 0; L < kAuxFarLevels; ++L) {
         if (L >= g.n_far) break;
         const typename Vec<S>::t4* fs = pick<S>(g.far_scale[L], g.far_scale_f[L]);
-        const int64_t a = en.x < g.n_aux ? ((int64_t)en.x >> aux_far_log(L)) : -1;
-        const int64_t b = en.y < g.n_aux ? ((int64_t)en.y >> aux_far_log(L)) : -1;
-        if (a >= 0) {
-            const typename Vec<S>::t4 d = fs[a];
-            const typename Vec<S>::t4 v =
-                Vec<S>::four((S)*far_line(g, L, a, 0) * d.x, (S)*far_line(g, L, a, 1) * d.y,
-                             (S)*far_line(g, L, a, 2) * d.z, (S)*far_line(g, L, a, 3) * d.w);
-            P.ya.x += v.x;
-            P.ya.y += v.y;
-            P.ya.z += v.z;
-            P.ya.w += v.w;
-            if (b == a) {
-                P.yb.x += v.x;
-                P.yb.y += v.y;
-                P.yb.z += v.z;
-                P.yb.w += v.w;
-            }
-        }
-        if (b >= 0 && b != a) {
-            const typename Vec<S>::t4 d = fs[b];
-            P.yb.x += (S)*far_line(g, L, b, 0) * d.x;
-            P.yb.y += (S)*far_line(g, L, b, 1) * d.y;
-            P.yb.z += (S)*far_line(g, L, b, 2) * d.z;
-            P.yb.w += (S)*far_line(g, L, b, 3) * d.w;
-        }
+        const int64_t a = n >> aux_far_log(L);
+        const typename Vec<S>::t4 d = fs[a];
+        y.x += (S)*far_line(g, L, a, 0) * d.x;
+        y.y += (S)*far_line(g, L, a, 1) * d.y;
+        y.z += (S)*far_line(g, L, a, 2) * d.z;
+        y.w += (S)*far_line(g, L, a, 3) * d.w;
     }
+    Y[n] = y;
 }
 
 // x += alpha p with p = z + beta p from the pair k_pcg_q(i) read (not at the start),
@@ -1490,6 +1484,8 @@ void pcg_start(hipStream_t s, int64_t n_rows, const int64_t* sp, const int32_t* 
     const RowGrid ng = node_grid(g.n_aux);
     hipLaunchKernelGGL(k_pcg_nodes<S>, dim3(ng.grid), dim3(kBlock), 0, s, ng, -1, g, (const S*)R, (const S*)Q, slots,
                        sc);
+    if (g.n_far > 0)
+        hipLaunchKernelGGL(k_pcg_fold<S>, dim3(grid_1d(g.n_aux, kBlock)), dim3(kBlock), 0, s, g, sc);
     constexpr int kR = update_rows<S>();
     const RowGrid ug = row_grid_full((n_rows + kR - 1) / kR);
     hipLaunchKernelGGL((k_pcg_update<S, kR>), dim3(ug.grid), dim3(kBlock), 0, s, n_rows, ug, -1, g, dinv, x,
@@ -1506,6 +1502,8 @@ void pcg_iter(hipStream_t s, int i, int64_t n_rows, const int64_t* sp, const int
                        (const typename Vec<S>::t2*)zp[a], Q, slots, sc, g);
     hipLaunchKernelGGL(k_pcg_nodes<S>, dim3(ng.grid), dim3(kBlock), 0, s, ng, i, g, (const S*)R, (const S*)Q, slots,
                        sc);
+    if (g.n_far > 0)
+        hipLaunchKernelGGL(k_pcg_fold<S>, dim3(grid_1d(g.n_aux, kBlock)), dim3(kBlock), 0, s, g, sc);
     constexpr int kR = update_rows<S>();
     const RowGrid ug = row_grid_full((n_rows + kR - 1) / kR);
     hipLaunchKernelGGL((k_pcg_update<S, kR>), dim3(ug.grid), dim3(kBlock), 0, s, n_rows, ug, i, g, dinv, x,

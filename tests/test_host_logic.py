@@ -97,6 +97,10 @@ def test_bench_byte_model_and_profile_bookkeeping(tmp_path, monkeypatch):
     # FP32 inner iterations of the mixed-precision solve: 4 B values and vectors, the same
     # column ids, incidences, FP16 edge vectors and ends
     assert bench.algorithmic_bytes("cg_iter", geo, st, "aux", "mixed") == 8 * 1500 + 84 * 100 + 8 * 70 + 48 * 12
+    # with far levels, their fold reads and writes each node's Y once more
+    far = dict(geo, far_levels=2)
+    assert bench.algorithmic_bytes("cg_iter", far, st, "aux") == 12 * 1500 + 144 * 100 + 8 * 70 + 160 * 12
+    assert bench.algorithmic_bytes("cg_iter", far, st, "aux", "mixed") == 8 * 1500 + 84 * 100 + 8 * 70 + 80 * 12
     assert bench.profile_key("cg_iter", "aux", "mixed") == "cg_iter_mixed"
     assert bench.profile_key("cg_iter", "jacobi") == "cg_iter_jacobi"
     assert bench.profile_key("push", "aux", "mixed") == "push"
