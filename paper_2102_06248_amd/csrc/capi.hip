@@ -1719,12 +1719,13 @@ int fepic_upload_mesh(fepic_ctx* c, int64_t n_nodes, const double* xyz, int64_t 
         c->aux.scale64 = dalloc<double4>(c, (m.n_aux + 63) / 64);
         c->aux.Y = dalloc<double4>(c, m.n_aux + 1);
         for (int L = 0; L < kAuxFarLevels; ++L) {
-            const int64_t nf = aux_far_count(m.n_aux, L);
-            c->aux.far_scale[L] = dalloc<double4>(c, nf);
-            c->aux.far_acc[L] = dalloc<double4>(c, 8 * nf);
-            if (!c->aux.far_scale[L] || !c->aux.far_acc[L]) return fail(c, FEPIC_E_OOM, "device allocation failed");
-            HIPCHK(c, hipMemset(c->aux.far_acc[L], 0, sizeof(double4) * std::max<int64_t>(8 * nf, 1)));
+            c->aux.far_scale[L] = dalloc<double4>(c, aux_far_count(m.n_aux, L));
+            if (!c->aux.far_scale[L]) return fail(c, FEPIC_E_OOM, "device allocation failed");
         }
+        const int64_t nf0 = aux_far_count(m.n_aux, 0);
+        c->aux.far_acc = dalloc<double4>(c, 8 * nf0);
+        if (!c->aux.far_acc) return fail(c, FEPIC_E_OOM, "device allocation failed");
+        HIPCHK(c, hipMemset(c->aux.far_acc, 0, sizeof(double4) * std::max<int64_t>(8 * nf0, 1)));
         c->d_rq = dalloc<double2>(c, ne);
         for (double2*& p : c->d_zp) p = dalloc<double2>(c, ne);
         if (!c->aux.scale || !c->aux.scale8 || !c->aux.scale64 || !c->aux.Y || !c->d_rq || !c->d_zp[0] ||

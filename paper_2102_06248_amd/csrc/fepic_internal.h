@@ -169,11 +169,12 @@ struct AuxSpace {
     double4* scale8 = nullptr;    // [ceil(n_aux / 8)]
     double4* scale64 = nullptr;   // [ceil(n_aux / 64)]
     // levels of 2^aux_far_log(L) nodes, which span several workgroups of the node pass: the
-    // residual's sums per aggregate are accumulated with atomics (far_acc: a 64-byte line
-    // per aggregate and component, the sum in its first double; zeroed by the product
-    // kernel of each iteration) and applied by the update kernel
+    // residual's sums per aggregate of the finest far level are accumulated with atomics
+    // (far_acc: a 64-byte line per aggregate and component, the sum in its first double;
+    // zeroed by the product kernel of each iteration); the coarser levels' sums are formed
+    // from those, and all are folded into each node's Y once per iteration
     double4* far_scale[kAuxFarLevels] = {};
-    double4* far_acc[kAuxFarLevels] = {};       // [8 * count] double4
+    double4* far_acc = nullptr;                 // [8 * count of level 0] double4
     int n_far = 0;                              // far levels in use (0 .. kAuxFarLevels)
     double4* Y = nullptr;         // [n_aux + 1] nodal corrections of the residual, all levels;
                                   // Y[n_aux] = 0

@@ -545,9 +545,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(int64_t n_rows, RowGrid rg, 
 //                    formed on the fly from their gathered (z, p) pair);  dot (p, q)
 //   k_pcg_nodes(i):  alpha = g_i / (p, q);  per interior node, G^T r' and Pi^T r' over its
 //                    edges, r' = r - alpha q, scaled by D_G^-1 and D_Pi^-1, plus the
-//                    aggregate levels of the node's slice; far-level sums by atomics
-//   k_pcg_fold(i):   with far levels, each node's Y += its far aggregates' sums times
-//                    their scales (once per node, not at both ends of every edge)
+//                    aggregate levels of the node's slice; the finest far level's sums
+//                    by atomics
+//   k_pcg_fold(i):   with far levels, the coarser far levels' sums from the finest
+//                    level's, then each node's Y += its far aggregates' sums times their
+//                    scales (once per node, not at both ends of every edge)
 //   k_pcg_update(i): p again (same operands, same bits);  x += alpha p;  r = r';
 //                    z = D^-1 r + G y + Pi v (all levels);  dots (r, z), (r, r)
 // Every kernel issues its loads before it sums the previous kernel's slots.  Reductions
@@ -713,20 +715,19 @@ __global__ __launch_bounds__(kBlock) void k_invert_pos(double* v, int64_t n) {
     if (i < n) v[i] = v[i] > 0.0 ? 1.0 / v[i] : 0.0;
 }
 
-// Zeroes the far levels' accumulators (one workgroup).
+// Zeroes the finest far level's accumulators, the only ones the node pass adds into (one
+// workgroup).
 __device__ __forceinline__ void clear_far(const AuxSpace& g) {
-#pragma unroll
-    for (int L = 0; L < kAuxFarLevels; ++L) {
-        if (L >= g.n_far) break;
-        const int64_t nf = (g.n_aux + (1ll << aux_far_log(L)) - 1) >> aux_far_log(L);
-        double* a = reinterpret_cast<double*>(g.far_acc[L]);
-        for (int64_t k = threadIdx.x; k < 4 * nf; k += kBlock) a[8 * k] = 0.0;
-    }
+    if (g.n_far < 1) return;
+    const int64_t nf = (g.n_aux + (1ll << aux_far_log(0)) - 1) >> aux_far_log(0);
+    double* a = reinterpret_cast<double*>(g.far_acc);
+    for (int64_t k = threadIdx.x; k < 4 * nf; k += kBlock) a[8 * k] = 0.0;
 }
 
-// The accumulator of component comp of far-level L aggregate a: one 64-byte line each.
-__device__ __forceinline__ double* far_line(const AuxSpace& g, int L, int64_t a, int comp) {
-    return reinterpret_cast<double*>(g.far_acc[L]) + 8 * (4 * a + comp);
+// The accumulator of component comp of the finest far level's aggregate a: one 64-byte
+// line each.
+__device__ __forceinline__ double* far_line(const AuxSpace& g, int64_t a, int comp) {
+    return reinterpret_cast<double*>(g.far_acc) + 8 * (4 * a + comp);
 }
 
 // Storage of the iteration: FP64, or FP32 for the inner solves of the mixed-precision
@@ -975,8 +976,25 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
     const int nl = threadIdx.x >> 2, comp = threadIdx.x & 3;   // output: node of the slice, component
     int64_t sl = rg_first(rg);
     const int64_t le = rg_end(rg);
+    const S* scale = reinterpret_cast<const S*>(pick<S>(g.scale, g.scale_f));
+    const S* scale8 = reinterpret_cast<const S*>(pick<S>(g.scale8, g.scale8_f));
+    const S* scale64 = reinterpret_cast<const S*>(pick<S>(g.scale64, g.scale64_f));
+    // the output's three scales, loaded with the slice's incidences (they depend on nothing
+    // else, and would otherwise be a memory round trip of their own after the barrier)
+    S d1 = S(0), d8 = S(0), d64 = S(0);
+    auto load_scales = [&](int64_t s) {
+        const int64_t node = s * 64 + nl;
+        if (node < g.n_aux) {
+            d1 = scale[4 * node + comp];
+            d8 = scale8[4 * (node >> 3) + comp];
+            d64 = scale64[4 * s + comp];
+        }
+    };
     S P[8];
-    if (sl < le) node_part<S>(P, g, R, Q, sl, lane, j);
+    if (sl < le) {
+        load_scales(sl);
+        node_part<S>(P, g, R, Q, sl, lane, j);
+    }
     if (conv) return;
     double alpha = 0.0;
     if (i >= 0) {
@@ -989,9 +1007,6 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
     }
     if (blockIdx.x == 0) clear_buf(red_buf(cg_slots, 2 * i + 1));
     const S as = (S)alpha;
-    const S* scale = reinterpret_cast<const S*>(pick<S>(g.scale, g.scale_f));
-    const S* scale8 = reinterpret_cast<const S*>(pick<S>(g.scale8, g.scale8_f));
-    const S* scale64 = reinterpret_cast<const S*>(pick<S>(g.scale64, g.scale64_f));
     S* Y = reinterpret_cast<S*>(pick<S>(g.Y, g.Y_f));
     __shared__ S wsum[kNodePhases][4];
     // component comp of P^T r' at node nl: (sum of value va) - alpha (sum of value vb)
@@ -1020,20 +1035,18 @@ __global__ __launch_bounds__(kBlock) void k_pcg_nodes(RowGrid rg, int i, AuxSpac
         S s64 = S(0);
 #pragma unroll
         for (int q = 0; q < kNodePhases; ++q) s64 += wsum[q][comp];
-        if (node < g.n_aux)
-            Y[4 * node + comp] = u * scale[4 * node + comp] + s8 * scale8[4 * (node >> 3) + comp] +
-                                 s64 * scale64[4 * sl + comp];
-        // Far levels: the slice's sums added into its aggregates; each component of an
-        // aggregate has its own 64-byte line, so at most 2^(log - 6) workgroups add into one
-        // line.
-        if (threadIdx.x < 4) {   // comp = threadIdx.x
-#pragma unroll
-            for (int L = 0; L < kAuxFarLevels; ++L)
-                if (L < g.n_far) unsafeAtomicAdd(far_line(g, L, (sl * 64) >> aux_far_log(L), comp), (double)s64);
-        }
+        if (node < g.n_aux) Y[4 * node + comp] = u * d1 + s8 * d8 + s64 * d64;
+        // Far levels: the slice's sums added into its aggregate of the finest far level
+        // (each component of an aggregate has its own 64-byte line, so eight workgroups add
+        // into one line); the coarser far levels' sums are formed from those by the fold.
+        if (threadIdx.x < 4 && g.n_far > 0)   // comp = threadIdx.x
+            unsafeAtomicAdd(far_line(g, (sl * 64) >> aux_far_log(0), comp), (double)s64);
         __syncthreads();
         sl += rg.g;
-        if (sl < le) node_part<S>(P, g, R, Q, sl, lane, j);
+        if (sl < le) {
+            load_scales(sl);
+            node_part<S>(P, g, R, Q, sl, lane, j);
+        }
     }
 }
 
@@ -1064,13 +1077,42 @@ __device__ __forceinline__ void u_part(UPart<S>& P, const AuxSpace& g, const S* 
 }
 
 // The far levels' corrections folded into each node's Y once, after the node pass has
-// summed every far aggregate and before the update reads Y at both ends of every edge:
-// Y += (the aggregate's sum) * (its scale), level by level, the same products and sums the
-// update would otherwise form at each end of each edge.
+// summed the finest far level's aggregates and before the update reads Y at both ends of
+// every edge: Y += (the aggregate's sum) * (its scale), level by level.  The coarser
+// levels' sums are those of their eight (level 1) and 64 (level 2) finest aggregates: a
+// workgroup's 256 nodes lie in one aggregate of each far level, so thread t loads
+// component t & 3 of the (t >> 2)-th finest aggregate of its level-2 aggregate, groups of
+// eight are summed across lanes and the groups in LDS.
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_pcg_fold(AuxSpace g, const CgScalars* __restrict__ sc) {
-    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (n >= g.n_aux || sc->converged) return;   // a stopped solve's node pass left Y as it was
+    static_assert(kBlock == 256 && aux_far_log(0) >= 8 && aux_far_log(1) == aux_far_log(0) + 3 &&
+                      aux_far_log(2) == aux_far_log(0) + 6 && kAuxFarLevels == 3,
+                  "one workgroup's nodes in one aggregate per far level; 8 and 64 finest ones per coarser");
+    if (sc->converged) return;   // a stopped solve's node pass left Y as it was (uniform)
+    const int64_t n0 = (int64_t)blockIdx.x * kBlock, n = n0 + threadIdx.x;
+    double c1[4] = {0.0, 0.0, 0.0, 0.0}, c2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (g.n_far > 1) {
+        __shared__ double grp[8][4];
+        const int comp = threadIdx.x & 3, lane = threadIdx.x & 63;
+        const int64_t nf0 = (g.n_aux + (1ll << aux_far_log(0)) - 1) >> aux_far_log(0);
+        const int64_t a = ((n0 >> aux_far_log(2)) << 6) + (threadIdx.x >> 2);
+        double v = a < nf0 ? *far_line(g, a, comp) : 0.0;
+        v += __shfl_xor(v, 4);    // lanes 4k + comp: the eight consecutive k of one group
+        v += __shfl_xor(v, 8);
+        v += __shfl_xor(v, 16);
+        if ((lane & 28) == 0) grp[threadIdx.x >> 5][comp] = v;   // group (threadIdx.x >> 2) >> 3
+        __syncthreads();
+        const int q1 = (int)((n0 >> aux_far_log(1)) & 7);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            c1[c] = grp[q1][c];
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) t += grp[q][c];
+            c2[c] = t;
+        }
+    }
+    if (n >= g.n_aux) return;
     typename Vec<S>::t4* Y = pick<S>(g.Y, g.Y_f);
     typename Vec<S>::t4 y = Y[n];
 #pragma unroll
@@ -1079,10 +1121,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_fold(AuxSpace g, const CgScalars
         const typename Vec<S>::t4* fs = pick<S>(g.far_scale[L], g.far_scale_f[L]);
         const int64_t a = n >> aux_far_log(L);
         const typename Vec<S>::t4 d = fs[a];
-        y.x += (S)*far_line(g, L, a, 0) * d.x;
-        y.y += (S)*far_line(g, L, a, 1) * d.y;
-        y.z += (S)*far_line(g, L, a, 2) * d.z;
-        y.w += (S)*far_line(g, L, a, 3) * d.w;
+        double f[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) f[c] = L == 0 ? *far_line(g, a, c) : (L == 1 ? c1[c] : c2[c]);
+        y.x += (S)f[0] * d.x;
+        y.y += (S)f[1] * d.y;
+        y.z += (S)f[2] * d.z;
+        y.w += (S)f[3] * d.w;
     }
     Y[n] = y;
 }
